@@ -1,0 +1,231 @@
+"""Python binding of libba.so (argument marshalling only).
+
+Every function mirrors the C entry point of the same name in include/ba.h.
+Device arrays are torch tensors on the GPU (float64 / int32 / uint8, C
+contiguous); work is ordered on torch's current HIP stream unless a stream
+is given.  The library is required: importing this module on a machine
+without the built library raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libba.so")
+
+BA_OK, BA_ERR_INVALID_ARG, BA_ERR_STATE, BA_ERR_NOT_SPD, BA_ERR_NOT_CONVERGED, BA_ERR_OUT_OF_MEMORY, BA_ERR_DEVICE = range(7)
+BA_FP64, BA_MIXED = 0, 1
+BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED = 0, 1
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("n_pts", C.c_int32), ("n_obs", C.c_int64),
+                ("obs_cam", C.c_void_p), ("obs_pt", C.c_void_p), ("obs_uv", C.c_void_p),
+                ("cam_fixed", C.c_void_p), ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("stream", C.c_void_p), ("workspace_cap", C.c_size_t)]
+
+
+class PcgOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32), ("x0", C.c_void_p)]
+
+
+class PcgInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double), ("ms", C.c_double)]
+
+
+class LMState(C.Structure):
+    _fields_ = [("lam", C.c_double), ("nu", C.c_double), ("iter", C.c_int32), ("flags", C.c_int32)]
+
+
+class LMOpts(C.Structure):
+    _fields_ = [("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32), ("precond", C.c_int32)]
+
+
+class LMInfo(C.Structure):
+    _fields_ = [("cost", C.c_double), ("cost_new", C.c_double), ("rho", C.c_double),
+                ("model_decrease", C.c_double), ("pcg_relres", C.c_double),
+                ("pcg_iters", C.c_int32), ("pcg_status", C.c_int32), ("accepted", C.c_int32),
+                ("stop", C.c_int32), ("ms_linearize", C.c_double), ("ms_form_rcs", C.c_double),
+                ("ms_pcg", C.c_double), ("ms_back_substitute", C.c_double),
+                ("ms_evaluate", C.c_double), ("ms_total", C.c_double)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("n_cams", C.c_int32), ("n_pts", C.c_int32), ("n_rows", C.c_int32), ("precision", C.c_int32),
+                ("n_obs", C.c_int64), ("n_blk", C.c_int64), ("n_pairs", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+# exported symbol -> (restype, argtypes)
+_vp, _dp = C.c_void_p, C.POINTER(C.c_double)
+SIGNATURES = {
+    "ba_create": (C.c_int, [C.POINTER(ProblemDesc), C.POINTER(C.c_void_p)]),
+    "ba_destroy": (None, [_vp]),
+    "ba_linearize": (C.c_int, [_vp, _vp, _vp, _dp]),
+    "ba_form_rcs": (C.c_int, [_vp, C.c_double]),
+    "ba_pcg_solve": (C.c_int, [_vp, C.POINTER(PcgOpts), _vp, C.POINTER(PcgInfo)]),
+    "ba_back_substitute": (C.c_int, [_vp, _vp, _vp]),
+    "ba_lm_step": (C.c_int, [_vp, _vp, _vp, C.POINTER(LMState), C.POINTER(LMOpts), C.POINTER(LMInfo)]),
+    "ba_project": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
+    "ba_get_sizes": (C.c_int, [_vp, C.POINTER(Sizes)]),
+    "ba_get_pattern": (C.c_int, [_vp, _vp, _vp]),
+    "ba_get_rcs": (C.c_int, [_vp, _vp, _vp]),
+    "ba_get_jacobians": (C.c_int, [_vp, _vp, _vp]),
+    "ba_get_stage_ms": (C.c_int, [_vp, _dp]),
+    "ba_status_str": (C.c_char_p, [C.c_int]),
+    "ba_last_error": (C.c_char_p, [_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class BAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lib().ba_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+def _check(status, ctx=None, allow=()):
+    if status != BA_OK and status not in allow:
+        raise BAError(status, lib().ba_last_error(ctx).decode())
+    return status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_contiguous(), "tensor must be contiguous"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------------------
+def ba_create(n_cams, n_pts, obs_cam, obs_pt, obs_uv, cam_fixed=None, precision=BA_FP64,
+              stream=None, workspace_cap=0):
+    """obs_cam/obs_pt: int32 [n_obs]; obs_uv: float64 [2][n_obs]; cam_fixed: uint8 [n_cams] or None."""
+    import torch
+    assert obs_cam.dtype == torch.int32 and obs_pt.dtype == torch.int32 and obs_uv.dtype == torch.float64
+    d = ProblemDesc(n_cams=n_cams, n_pts=n_pts, n_obs=obs_cam.numel(), obs_cam=_ptr(obs_cam),
+                    obs_pt=_ptr(obs_pt), obs_uv=_ptr(obs_uv), cam_fixed=_ptr(cam_fixed),
+                    precision=precision, reserved=0, stream=_stream(stream), workspace_cap=workspace_cap)
+    h = C.c_void_p()
+    _check(lib().ba_create(C.byref(d), C.byref(h)))
+    return h
+
+
+def ba_destroy(ctx):
+    if ctx:
+        lib().ba_destroy(ctx)
+
+
+def ba_linearize(ctx, cams, pts, want_cost=True):
+    cost = C.c_double(0.0)
+    _check(lib().ba_linearize(ctx, _ptr(cams), _ptr(pts), C.byref(cost) if want_cost else None), ctx)
+    return cost.value if want_cost else None
+
+
+def ba_form_rcs(ctx, lam):
+    _check(lib().ba_form_rcs(ctx, float(lam)), ctx)
+
+
+def ba_pcg_solve(ctx, dxc, tol=1e-6, max_iter=1000, precond=BA_PRECOND_BLOCK_JACOBI, x0=None):
+    o = PcgOpts(tol=tol, max_iter=max_iter, precond=precond, x0=_ptr(x0))
+    info = PcgInfo()
+    st = _check(lib().ba_pcg_solve(ctx, C.byref(o), _ptr(dxc), C.byref(info)), ctx,
+                allow=(BA_ERR_NOT_CONVERGED,))
+    return dict(iters=info.iters, status=info.status, relres=info.relres, ms=info.ms, returned=st)
+
+
+def ba_back_substitute(ctx, dxc, dxp):
+    _check(lib().ba_back_substitute(ctx, _ptr(dxc), _ptr(dxp)), ctx)
+
+
+def ba_lm_step(ctx, cams, pts, state: LMState, pcg_tol=1e-6, pcg_max_iter=1000,
+               precond=BA_PRECOND_BLOCK_JACOBI):
+    o = LMOpts(pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter, precond=precond)
+    info = LMInfo()
+    _check(lib().ba_lm_step(ctx, _ptr(cams), _ptr(pts), C.byref(state), C.byref(o), C.byref(info)), ctx)
+    return {k: getattr(info, k) for k, _ in LMInfo._fields_}
+
+
+def ba_project(cams, pts, obs_cam, obs_pt, noise=None, out=None, stream=None):
+    import torch
+    n = obs_cam.numel()
+    uv = out if out is not None else torch.empty((2, n), dtype=torch.float64, device=cams.device)
+    _check(lib().ba_project(_ptr(cams), _ptr(pts), _ptr(obs_cam), _ptr(obs_pt), n, _ptr(noise),
+                            _ptr(uv), _stream(stream)))
+    return uv
+
+
+def ba_get_sizes(ctx):
+    s = Sizes()
+    _check(lib().ba_get_sizes(ctx, C.byref(s)), ctx)
+    return {k: getattr(s, k) for k, _ in Sizes._fields_}
+
+
+def ba_get_pattern(ctx):
+    s = ba_get_sizes(ctx)
+    rp = np.empty(s["n_rows"] + 1, np.int64)
+    ci = np.empty(max(s["n_blk"], 1), np.int32)
+    _check(lib().ba_get_pattern(ctx, _np_ptr(rp), _np_ptr(ci)), ctx)
+    return rp, ci[: s["n_blk"]]
+
+
+def ba_get_rcs(ctx):
+    s = ba_get_sizes(ctx)
+    blk = np.empty((max(s["n_blk"], 1), 9, 9))
+    rhs = np.empty((max(s["n_rows"], 1), 9))
+    _check(lib().ba_get_rcs(ctx, _np_ptr(blk), _np_ptr(rhs)), ctx)
+    return blk[: s["n_blk"]], rhs[: s["n_rows"]]
+
+
+def ba_get_jacobians(ctx):
+    """Returns (J [n_obs][24], e [n_obs][2]) in the caller's observation order."""
+    s = ba_get_sizes(ctx)
+    J = np.empty((s["n_obs"], 24))
+    e = np.empty((s["n_obs"], 2))
+    _check(lib().ba_get_jacobians(ctx, _np_ptr(J), _np_ptr(e)), ctx)
+    return J, e
+
+
+def ba_get_stage_ms(ctx):
+    ms = (C.c_double * 4)()
+    _check(lib().ba_get_stage_ms(ctx, ms), ctx)
+    return list(ms)
+
+
+def ba_status_str(status):
+    return lib().ba_status_str(status).decode()
+
+
+def ba_last_error(ctx=None):
+    return lib().ba_last_error(ctx).decode()
+
+
+def new_lm_state(lam=1e-4):
+    return LMState(lam=lam, nu=2.0, iter=0, flags=0)

@@ -1,0 +1,615 @@
+// C ABI of the bundle-adjustment library: context creation (validation and
+// the co-visibility pattern, built once), the per-stage entry points and one
+// LM iteration.  All device work goes to the context's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "ba_common.hpp"
+
+namespace ba {
+void launch_spmv(ba_ctx* c, const double* x, double* y);
+}
+
+namespace {
+
+using ba::kJStride;
+using ba::kMaxTrack;
+using ba::kWhatStride;
+using ba::Pcg;
+
+thread_local std::string g_create_error;
+
+struct ba_oom {
+    std::string what;
+};
+struct ba_invalid {
+    std::string what;
+};
+
+template <typename T>
+void dalloc(ba_ctx* c, T** p, size_t n) {
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    if (c->cap && c->bytes + bytes > c->cap)
+        throw ba_oom{"device workspace cap of " + std::to_string(c->cap) + " bytes exceeded"};
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        throw ba_oom{"hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    if (e != hipSuccess) throw ba_hip_error(e, "hipMalloc", __FILE__, __LINE__);
+    c->bytes += bytes;
+}
+
+template <typename T>
+void upload(ba_ctx* c, T** p, const std::vector<T>& h) {
+    dalloc(c, p, h.size());
+    if (!h.empty())
+        BA_HIP_CHECK(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+}
+
+void free_ctx(ba_ctx* c) {
+    if (!c) return;
+    void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->pt_ptr, c->chunk_ptr, c->cam_row,
+                    c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
+                    c->tr_ptr, c->tr_blk, c->J, c->e, c->What, c->g, c->ptL, c->blk, c->rhs, c->Minv,
+                    c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r, c->pcg.z,
+                    c->pcg.q, c->pcg.d[0], c->pcg.d[1], c->pcg.pA, c->pcg.pB[0], c->pcg.pB[1], c->pcg.state,
+                    c->pcg.scal};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->h_scal) (void)hipHostFree(c->h_scal);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+// Builds the internal observation order, the pattern and every index
+// structure on the host, then uploads them.
+void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t>& pt, const std::vector<double>& uv,
+           const std::vector<uint8_t>& fixed) {
+    const int64_t n = c->n_obs;
+    const int32_t nc = c->n_cams, np = c->n_pts;
+    for (int64_t k = 0; k < n; ++k) {
+        if (cam[k] < 0 || cam[k] >= nc) throw ba_invalid{"obs_cam[" + std::to_string(k) + "] out of range"};
+        if (pt[k] < 0 || pt[k] >= np) throw ba_invalid{"obs_pt[" + std::to_string(k) + "] out of range"};
+        if (!std::isfinite(uv[k]) || !std::isfinite(uv[n + k]))
+            throw ba_invalid{"obs_uv of observation " + std::to_string(k) + " is not finite"};
+    }
+    // (point, camera) order
+    std::vector<int32_t> ptr(np + 1, 0);
+    for (int64_t k = 0; k < n; ++k) ptr[pt[k] + 1]++;
+    for (int32_t p = 0; p < np; ++p) {
+        const int t = ptr[p + 1];
+        if (t < 2) throw ba_invalid{"point " + std::to_string(p) + " has " + std::to_string(t) + " observations (need >= 2)"};
+        if (t > kMaxTrack) throw ba_invalid{"point " + std::to_string(p) + " has more than 64 observations"};
+        ptr[p + 1] += ptr[p];
+    }
+    std::vector<int64_t> perm(n);
+    {
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t k = 0; k < n; ++k) perm[fill[pt[k]]++] = k;
+    }
+    for (int32_t p = 0; p < np; ++p) {
+        auto b = perm.begin() + ptr[p], e = perm.begin() + ptr[p + 1];
+        std::sort(b, e, [&](int64_t x, int64_t y) { return cam[x] < cam[y]; });
+        for (auto it = b + 1; it < e; ++it)
+            if (cam[*it] == cam[*(it - 1)])
+                throw ba_invalid{"duplicate observation of point " + std::to_string(p) + " by camera " + std::to_string(cam[*it])};
+    }
+    std::vector<int32_t> cam_row(nc);
+    int32_t nr = 0;
+    for (int32_t i = 0; i < nc; ++i) cam_row[i] = (!fixed.empty() && fixed[i]) ? -1 : nr++;
+    c->n_rows = nr;
+    std::vector<int32_t> ocam(n), opt(n), orow(n);
+    std::vector<double> ouv(2 * n);
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t s = perm[k];
+        ocam[k] = cam[s];
+        opt[k] = pt[s];
+        orow[k] = cam_row[cam[s]];
+        ouv[k] = uv[s];
+        ouv[n + k] = uv[n + s];
+    }
+    // point-aligned chunks of at most 64 observations
+    std::vector<int32_t> chunk{0};
+    for (int32_t p = 0; p < np; ++p)
+        if (ptr[p + 1] - chunk.back() > kMaxTrack) chunk.push_back(ptr[p]);
+    chunk.push_back((int32_t)n);
+    c->n_chunk = (int32_t)chunk.size() - 1;
+    // observation couples of every pair of free cameras sharing a point
+    int64_t ntr = 0;
+    for (int32_t p = 0; p < np; ++p) {
+        int64_t f = 0;
+        for (int32_t k = ptr[p]; k < ptr[p + 1]; ++k) f += orow[k] >= 0;
+        ntr += f * (f - 1) / 2;
+    }
+    if (ntr > INT32_MAX) throw ba_invalid{"too many camera-pair couples for 32-bit indices"};
+    std::vector<int32_t> ta(ntr), tb(ntr);
+    {
+        int64_t m = 0;
+        for (int32_t p = 0; p < np; ++p)
+            for (int32_t a = ptr[p]; a < ptr[p + 1]; ++a) {
+                if (orow[a] < 0) continue;
+                for (int32_t b = a + 1; b < ptr[p + 1]; ++b)
+                    if (orow[b] >= 0) { ta[m] = a; tb[m] = b; ++m; }
+            }
+    }
+    // stable two-pass counting sort by (row(a), row(b)); rows increase along
+    // a track because cameras do, so row(a) < row(b)
+    std::vector<int32_t> ta2(ntr), tb2(ntr);
+    {
+        std::vector<int64_t> cnt(nr + 1, 0);
+        for (int64_t m = 0; m < ntr; ++m) cnt[orow[tb[m]] + 1]++;
+        for (int32_t r = 0; r < nr; ++r) cnt[r + 1] += cnt[r];
+        for (int64_t m = 0; m < ntr; ++m) {
+            const int64_t d = cnt[orow[tb[m]]]++;
+            ta2[d] = ta[m]; tb2[d] = tb[m];
+        }
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (int64_t m = 0; m < ntr; ++m) cnt[orow[ta2[m]] + 1]++;
+        for (int32_t r = 0; r < nr; ++r) cnt[r + 1] += cnt[r];
+        for (int64_t m = 0; m < ntr; ++m) {
+            const int64_t d = cnt[orow[ta2[m]]]++;
+            ta[d] = ta2[m]; tb[d] = tb2[m];
+        }
+    }
+    std::vector<int32_t>().swap(ta2);
+    std::vector<int32_t>().swap(tb2);
+    // blocks: per row the diagonal first, then the off-diagonal segments
+    std::vector<int64_t> row_ptr(nr + 1, 0);
+    std::vector<int32_t> col_idx;
+    std::vector<int32_t> off_blk, pair_ptr, seg_row;
+    col_idx.reserve(nr * 8);
+    {
+        int64_t m = 0;
+        int64_t blk_id = 0;
+        for (int32_t r = 0; r < nr; ++r) {
+            row_ptr[r] = blk_id;
+            col_idx.push_back(r);
+            ++blk_id;
+            while (m < ntr && orow[ta[m]] == r) {
+                const int32_t s = orow[tb[m]];
+                off_blk.push_back((int32_t)blk_id);
+                pair_ptr.push_back((int32_t)m);
+                seg_row.push_back(r);
+                col_idx.push_back(s);
+                ++blk_id;
+                while (m < ntr && orow[ta[m]] == r && orow[tb[m]] == s) ++m;
+            }
+        }
+        row_ptr[nr] = blk_id;
+        pair_ptr.push_back((int32_t)ntr);
+    }
+    c->n_blk = (int64_t)col_idx.size();
+    c->n_offseg = (int32_t)off_blk.size();
+    c->n_pairs = ntr;
+    // observations of each RCS row
+    std::vector<int32_t> rowobs_ptr(nr + 1, 0), rowobs;
+    for (int64_t k = 0; k < n; ++k)
+        if (orow[k] >= 0) rowobs_ptr[orow[k] + 1]++;
+    for (int32_t r = 0; r < nr; ++r) rowobs_ptr[r + 1] += rowobs_ptr[r];
+    rowobs.resize(rowobs_ptr[nr]);
+    {
+        std::vector<int32_t> fill(rowobs_ptr.begin(), rowobs_ptr.end() - 1);
+        for (int64_t k = 0; k < n; ++k)
+            if (orow[k] >= 0) rowobs[fill[orow[k]]++] = (int32_t)k;
+    }
+    // transposed blocks: for column s, the blocks (r, s) with r < s, by r
+    std::vector<int32_t> tr_ptr(nr + 1, 0), tr;
+    for (int32_t sg = 0; sg < c->n_offseg; ++sg) tr_ptr[col_idx[off_blk[sg]] + 1]++;
+    for (int32_t r = 0; r < nr; ++r) tr_ptr[r + 1] += tr_ptr[r];
+    tr.resize(2 * (size_t)tr_ptr[nr]);
+    {
+        std::vector<int32_t> fill(tr_ptr.begin(), tr_ptr.end() - 1);
+        for (int32_t sg = 0; sg < c->n_offseg; ++sg) {
+            const int32_t s = col_idx[off_blk[sg]];
+            const int32_t d = fill[s]++;
+            tr[2 * d] = off_blk[sg];
+            tr[2 * d + 1] = seg_row[sg];
+        }
+    }
+    std::vector<int32_t> trip(2 * (size_t)ntr);
+    for (int64_t m = 0; m < ntr; ++m) { trip[2 * m] = ta[m]; trip[2 * m + 1] = tb[m]; }
+    std::vector<int32_t>().swap(ta);
+    std::vector<int32_t>().swap(tb);
+    std::vector<int32_t> row_ptr32(row_ptr.begin(), row_ptr.end());
+    // device copies
+    upload(c, &c->obs_cam, ocam);
+    upload(c, &c->obs_pt, opt);
+    upload(c, &c->obs_row, orow);
+    upload(c, &c->obs_uv, ouv);
+    upload(c, &c->pt_ptr, ptr);
+    upload(c, &c->chunk_ptr, chunk);
+    upload(c, &c->cam_row, cam_row);
+    upload(c, &c->row_ptr, row_ptr32);
+    upload(c, &c->col_idx, col_idx);
+    upload(c, &c->off_blk, off_blk);
+    upload(c, &c->pair_ptr, pair_ptr);
+    upload(c, &c->trip, trip);
+    upload(c, &c->rowobs_ptr, rowobs_ptr);
+    upload(c, &c->rowobs, rowobs);
+    upload(c, &c->tr_ptr, tr_ptr);
+    upload(c, &c->tr_blk, tr);
+    BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->h_row_ptr = std::move(row_ptr);
+    c->h_col_idx = std::move(col_idx);
+    c->h_perm = std::move(perm);
+    // workspace
+    const size_t es = c->precision == BA_MIXED ? sizeof(float) : sizeof(double);
+    dalloc(c, (char**)&c->J, (size_t)n * kJStride * es);
+    dalloc(c, &c->e, (size_t)n * 2);
+    dalloc(c, (char**)&c->What, (size_t)n * kWhatStride * es);
+    dalloc(c, &c->g, (size_t)n * 9);
+    dalloc(c, &c->ptL, (size_t)np * 9);
+    dalloc(c, &c->blk, (size_t)c->n_blk * 81);
+    dalloc(c, &c->rhs, (size_t)nr * 9);
+    dalloc(c, &c->Minv, (size_t)nr * 81);
+    dalloc(c, &c->dxc, (size_t)nr * 9);
+    dalloc(c, &c->dxp, (size_t)np * 3);
+    c->n_part = (int32_t)(3 * ((n + 255) / 256) + 8);
+    dalloc(c, &c->part, (size_t)c->n_part);
+    dalloc(c, &c->scal, 16);
+    dalloc(c, &c->flags, 8);
+    Pcg& P = c->pcg;
+    dalloc(c, &P.x, (size_t)nr * 9);
+    dalloc(c, &P.r, (size_t)nr * 9);
+    dalloc(c, &P.z, (size_t)nr * 9);
+    dalloc(c, &P.q, (size_t)nr * 9);
+    dalloc(c, &P.d[0], (size_t)nr * 9);
+    dalloc(c, &P.d[1], (size_t)nr * 9);
+    dalloc(c, &P.pA, (size_t)nr / 4 + 8);
+    dalloc(c, &P.pB[0], 2 * ((size_t)nr / 28 + 8));
+    dalloc(c, &P.pB[1], 2 * ((size_t)nr / 28 + 8));
+    dalloc(c, &P.state, 8);
+    dalloc(c, &P.scal, 8);
+    BA_HIP_CHECK(hipHostMalloc((void**)&c->h_scal, 32 * sizeof(double), hipHostMallocDefault));
+    BA_HIP_CHECK(hipHostMalloc((void**)&c->h_flags, 16 * sizeof(int), hipHostMallocDefault));
+    for (auto& e : c->ev) BA_HIP_CHECK(hipEventCreate(&e));
+}
+
+template <typename F>
+ba_status guarded(ba_ctx* c, F&& f) {
+    try {
+        return f();
+    } catch (const ba_oom& e) {
+        if (c) c->err = e.what;
+        return BA_ERR_OUT_OF_MEMORY;
+    } catch (const ba_invalid& e) {
+        if (c) c->err = e.what;
+        return BA_ERR_INVALID_ARG;
+    } catch (const ba_hip_error& e) {
+        if (c) c->err = e.what;
+        return BA_ERR_DEVICE;
+    } catch (const std::bad_alloc&) {
+        if (c) c->err = "host allocation failed";
+        return BA_ERR_OUT_OF_MEMORY;
+    } catch (...) {
+        if (c) c->err = "unexpected exception";
+        return BA_ERR_DEVICE;
+    }
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    return ms;
+}
+
+ba_status form_rcs_async(ba_ctx* c, double lambda) {
+    BA_HIP_CHECK(hipMemsetAsync(c->flags, 0, 8 * sizeof(int), c->stream));
+    BA_HIP_CHECK(hipEventRecord(c->ev[1], c->stream));
+    ba::launch_point(c, lambda);
+    BA_HIP_CHECK(hipEventRecord(c->ev[2], c->stream));
+    ba::launch_offdiag(c);
+    BA_HIP_CHECK(hipEventRecord(c->ev[3], c->stream));
+    ba::launch_diag(c, lambda);
+    BA_HIP_CHECK(hipEventRecord(c->ev[4], c->stream));
+    BA_HIP_CHECK(hipGetLastError());
+    c->have_rcs = true;
+    c->lambda = lambda;
+    return BA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ba_status_str(ba_status s) {
+    switch (s) {
+        case BA_OK: return "ok";
+        case BA_ERR_INVALID_ARG: return "invalid argument";
+        case BA_ERR_STATE: return "call out of order";
+        case BA_ERR_NOT_SPD: return "matrix not positive definite";
+        case BA_ERR_NOT_CONVERGED: return "PCG did not converge";
+        case BA_ERR_OUT_OF_MEMORY: return "out of memory";
+        case BA_ERR_DEVICE: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char* ba_last_error(const ba_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+
+ba_status ba_create(const ba_problem_desc* d, ba_ctx** out) {
+    if (out) *out = nullptr;
+    g_create_error.clear();
+    if (!d || !out) { g_create_error = "null descriptor or output"; return BA_ERR_INVALID_ARG; }
+    if (d->n_cams <= 0 || d->n_pts <= 0 || d->n_obs <= 0 || d->n_obs >= INT32_MAX) {
+        g_create_error = "sizes must satisfy n_cams > 0, n_pts > 0, 0 < n_obs < 2^31";
+        return BA_ERR_INVALID_ARG;
+    }
+    if (!d->obs_cam || !d->obs_pt || !d->obs_uv) { g_create_error = "null observation arrays"; return BA_ERR_INVALID_ARG; }
+    if (d->precision != BA_FP64 && d->precision != BA_MIXED) { g_create_error = "unknown precision"; return BA_ERR_INVALID_ARG; }
+    ba_ctx* c = new ba_ctx();
+    c->n_cams = d->n_cams;
+    c->n_pts = d->n_pts;
+    c->n_obs = d->n_obs;
+    c->precision = d->precision;
+    c->stream = (hipStream_t)d->stream;
+    c->cap = d->workspace_cap;
+    ba_status st = guarded(c, [&]() {
+        BA_HIP_CHECK(hipGetDevice(&c->device));
+        const int64_t n = c->n_obs;
+        std::vector<int32_t> cam(n), pt(n);
+        std::vector<double> uv(2 * n);
+        std::vector<uint8_t> fixed;
+        BA_HIP_CHECK(hipMemcpyAsync(cam.data(), d->obs_cam, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(pt.data(), d->obs_pt, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(uv.data(), d->obs_uv, 2 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (d->cam_fixed) {
+            fixed.resize(c->n_cams);
+            BA_HIP_CHECK(hipMemcpyAsync(fixed.data(), d->cam_fixed, c->n_cams, hipMemcpyDeviceToHost, c->stream));
+        }
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        build(c, cam, pt, uv, fixed);
+        return BA_OK;
+    });
+    if (st != BA_OK) {
+        g_create_error = c->err;
+        free_ctx(c);
+        return st;
+    }
+    *out = c;
+    return BA_OK;
+}
+
+void ba_destroy(ba_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_ctx(ctx);
+}
+
+ba_status ba_get_sizes(const ba_ctx* c, ba_sizes* o) {
+    if (!c || !o) return BA_ERR_INVALID_ARG;
+    o->n_cams = c->n_cams; o->n_pts = c->n_pts; o->n_rows = c->n_rows; o->precision = c->precision;
+    o->n_obs = c->n_obs; o->n_blk = c->n_blk; o->n_pairs = c->n_pairs; o->device_bytes = (int64_t)c->bytes;
+    return BA_OK;
+}
+
+ba_status ba_project(const double* cams, const double* pts, const int32_t* obs_cam, const int32_t* obs_pt, int64_t n_obs,
+                     const double* noise, double* uv, void* stream) {
+    if (n_obs < 0 || (n_obs > 0 && (!cams || !pts || !obs_cam || !obs_pt || !uv))) return BA_ERR_INVALID_ARG;
+    ba::launch_project(cams, pts, obs_cam, obs_pt, n_obs, noise, uv, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? BA_OK : BA_ERR_DEVICE;
+}
+
+ba_status ba_linearize(ba_ctx* c, const double* cams, const double* pts, double* cost_host) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!cams || !pts) { c->err = "null parameter arrays"; return BA_ERR_INVALID_ARG; }
+    return guarded(c, [&]() {
+        BA_HIP_CHECK(hipEventRecord(c->ev[0], c->stream));
+        ba::launch_linearize(c, cams, pts);
+        BA_HIP_CHECK(hipEventRecord(c->ev[5], c->stream));
+        BA_HIP_CHECK(hipGetLastError());
+        c->have_lin = true;
+        c->have_rcs = false;
+        if (cost_host) {
+            BA_HIP_CHECK(hipMemcpyAsync(c->h_scal, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+            *cost_host = c->h_scal[0];
+        }
+        return BA_OK;
+    });
+}
+
+ba_status ba_form_rcs(ba_ctx* c, double lambda) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!c->have_lin) { c->err = "ba_form_rcs needs a prior ba_linearize"; return BA_ERR_STATE; }
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) { c->err = "lambda must be finite and >= 0"; return BA_ERR_INVALID_ARG; }
+    return guarded(c, [&]() {
+        form_rcs_async(c, lambda);
+        BA_HIP_CHECK(hipMemcpyAsync(c->h_flags, c->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        if (c->h_flags[0]) { c->err = "a damped point block V* is not positive definite"; return BA_ERR_NOT_SPD; }
+        if (c->h_flags[1]) { c->err = "an RCS diagonal block is not positive definite"; return BA_ERR_NOT_SPD; }
+        return BA_OK;
+    });
+}
+
+ba_status ba_get_stage_ms(ba_ctx* c, double* ms) {
+    if (!c || !ms) return BA_ERR_INVALID_ARG;
+    return guarded(c, [&]() {
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        ms[0] = elapsed(c->ev[0], c->ev[5]);
+        ms[1] = elapsed(c->ev[1], c->ev[2]);
+        ms[2] = elapsed(c->ev[2], c->ev[3]);
+        ms[3] = elapsed(c->ev[3], c->ev[4]);
+        return BA_OK;
+    });
+}
+
+ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info* info) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!c->have_rcs) { c->err = "ba_pcg_solve needs a formed RCS"; return BA_ERR_STATE; }
+    if (!dxc) { c->err = "null dxc"; return BA_ERR_INVALID_ARG; }
+    const double tol = o ? o->tol : 1e-6;
+    const int max_iter = o ? o->max_iter : 1000;
+    const int pre = o ? o->precond : BA_PRECOND_BLOCK_JACOBI;
+    if (!(tol >= 0.0) || max_iter < 0) { c->err = "tol must be >= 0 and max_iter >= 0"; return BA_ERR_INVALID_ARG; }
+    if (pre == BA_PRECOND_LEARNED && !c->learned_ready) { c->err = "no learned preconditioner set"; return BA_ERR_STATE; }
+    if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI) { c->err = "unknown preconditioner"; return BA_ERR_INVALID_ARG; }
+    return guarded(c, [&]() {
+        int it = 0;
+        double rr = 0.0;
+        BA_HIP_CHECK(hipEventRecord(c->ev[6], c->stream));
+        ba_status s = BA_OK;
+        if (c->n_rows > 0)
+            s = ba::run_pcg(c, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, tol, max_iter, o ? o->x0 : nullptr,
+                            dxc, &it, &rr);
+        BA_HIP_CHECK(hipEventRecord(c->ev[7], c->stream));
+        BA_HIP_CHECK(hipEventSynchronize(c->ev[7]));
+        if (info) {
+            info->iters = it;
+            info->status = s;
+            info->relres = rr;
+            info->ms = elapsed(c->ev[6], c->ev[7]);
+        }
+        if (s == BA_ERR_NOT_SPD) c->err = "d^T S d <= 0 in PCG";
+        if (s == BA_ERR_NOT_CONVERGED) c->err = "PCG reached max_iter";
+        return s;
+    });
+}
+
+ba_status ba_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!c->have_rcs) { c->err = "ba_back_substitute needs a formed RCS"; return BA_ERR_STATE; }
+    if (!dxc || !dxp) { c->err = "null dxc or dxp"; return BA_ERR_INVALID_ARG; }
+    return guarded(c, [&]() {
+        ba::launch_back_substitute(c, dxc, dxp);
+        BA_HIP_CHECK(hipGetLastError());
+        return BA_OK;
+    });
+}
+
+ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, const ba_lm_opts* o, ba_lm_info* info) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!cams || !pts || !st) { c->err = "null parameters or state"; return BA_ERR_INVALID_ARG; }
+    if (!(st->lambda >= 0.0) || !std::isfinite(st->lambda) || !(st->nu >= 1.0)) {
+        c->err = "state needs lambda >= 0 and nu >= 1";
+        return BA_ERR_INVALID_ARG;
+    }
+    const double tol = o ? o->pcg_tol : 1e-6;
+    const int max_iter = o ? o->pcg_max_iter : 1000;
+    const int pre = o ? o->precond : BA_PRECOND_BLOCK_JACOBI;
+    if (pre == BA_PRECOND_LEARNED && !c->learned_ready) { c->err = "no learned preconditioner set"; return BA_ERR_STATE; }
+    return guarded(c, [&]() {
+        ba_lm_info I;
+        std::memset(&I, 0, sizeof I);
+        hipEvent_t* ev = c->ev;
+        BA_HIP_CHECK(hipEventRecord(ev[8], c->stream));
+        const bool relin = !(st->flags & 1) || !c->have_lin;
+        BA_HIP_CHECK(hipEventRecord(ev[0], c->stream));
+        if (relin) ba::launch_linearize(c, cams, pts);
+        BA_HIP_CHECK(hipEventRecord(ev[5], c->stream));
+        c->have_lin = true;
+        form_rcs_async(c, st->lambda);
+        int it = 0;
+        double rr = 0.0;
+        ba_status ps = BA_OK;
+        BA_HIP_CHECK(hipEventRecord(ev[6], c->stream));
+        if (c->n_rows > 0)
+            ps = ba::run_pcg(c, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, tol, max_iter, nullptr, c->dxc, &it, &rr);
+        else
+            BA_HIP_CHECK(hipMemsetAsync(c->dxc, 0, sizeof(double), c->stream));
+        BA_HIP_CHECK(hipEventRecord(ev[7], c->stream));
+        ba::launch_back_substitute(c, c->dxc, c->dxp);
+        BA_HIP_CHECK(hipEventRecord(ev[9], c->stream));
+        ba::launch_evaluate(c, cams, pts, c->dxc, c->dxp);
+        BA_HIP_CHECK(hipEventRecord(ev[10], c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(c->h_scal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(c->h_flags, c->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        BA_HIP_CHECK(hipGetLastError());
+        const double F = c->h_scal[0], Fn = c->h_scal[1], jdx2 = c->h_scal[2], dxl = c->h_scal[3];
+        const double L = dxl - 0.5 * jdx2;
+        I.cost = F;
+        I.cost_new = Fn;
+        I.model_decrease = L;
+        I.rho = (F - Fn) / L;
+        I.pcg_iters = it;
+        I.pcg_status = ps;
+        I.pcg_relres = rr;
+        const bool formed = !c->h_flags[0] && !c->h_flags[1];
+        if (!formed) I.pcg_status = BA_ERR_NOT_SPD;
+        const bool ok = formed && (ps == BA_OK || ps == BA_ERR_NOT_CONVERGED) && L > 0.0 && std::isfinite(Fn) && Fn < F;
+        if (ok) {
+            ba::launch_update(c, cams, pts, c->dxc, c->dxp);
+            const double t = 2.0 * I.rho - 1.0;
+            st->lambda *= std::max(1.0 / 3.0, 1.0 - t * t * t);
+            st->nu = 2.0;
+            st->flags &= ~1;
+            I.accepted = 1;
+            if (F - Fn < 1e-12 * F) I.stop = 1;
+        } else {
+            st->lambda *= st->nu;
+            st->nu *= 2.0;
+            st->flags |= 1;
+        }
+        st->iter += 1;
+        BA_HIP_CHECK(hipEventRecord(ev[11], c->stream));
+        BA_HIP_CHECK(hipEventSynchronize(ev[11]));
+        I.ms_linearize = elapsed(ev[0], ev[5]);
+        I.ms_form_rcs = elapsed(ev[1], ev[4]);
+        I.ms_pcg = elapsed(ev[6], ev[7]);
+        I.ms_back_substitute = elapsed(ev[7], ev[9]);
+        I.ms_evaluate = elapsed(ev[9], ev[10]);
+        I.ms_total = elapsed(ev[8], ev[11]);
+        if (info) *info = I;
+        return BA_OK;
+    });
+}
+
+ba_status ba_get_pattern(ba_ctx* c, int64_t* row_ptr, int32_t* col_idx) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (row_ptr) std::memcpy(row_ptr, c->h_row_ptr.data(), c->h_row_ptr.size() * sizeof(int64_t));
+    if (col_idx) std::memcpy(col_idx, c->h_col_idx.data(), c->h_col_idx.size() * sizeof(int32_t));
+    return BA_OK;
+}
+
+ba_status ba_get_rcs(ba_ctx* c, double* blk, double* rhs) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!c->have_rcs) { c->err = "no RCS formed"; return BA_ERR_STATE; }
+    return guarded(c, [&]() {
+        if (blk) BA_HIP_CHECK(hipMemcpyAsync(blk, c->blk, c->n_blk * 81 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (rhs) BA_HIP_CHECK(hipMemcpyAsync(rhs, c->rhs, (size_t)c->n_rows * 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        return BA_OK;
+    });
+}
+
+ba_status ba_get_jacobians(ba_ctx* c, double* J, double* e) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!c->have_lin) { c->err = "no linearization"; return BA_ERR_STATE; }
+    return guarded(c, [&]() {
+        const int64_t n = c->n_obs;
+        if (J) {
+            if (c->precision == BA_MIXED) {
+                std::vector<float> h((size_t)n * kJStride);
+                BA_HIP_CHECK(hipMemcpyAsync(h.data(), c->J, h.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+                BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+                for (int64_t k = 0; k < n; ++k)
+                    for (int i = 0; i < kJStride; ++i) J[c->h_perm[k] * kJStride + i] = h[k * kJStride + i];
+            } else {
+                std::vector<double> h((size_t)n * kJStride);
+                BA_HIP_CHECK(hipMemcpyAsync(h.data(), c->J, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+                BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+                for (int64_t k = 0; k < n; ++k)
+                    std::memcpy(J + c->h_perm[k] * kJStride, h.data() + k * kJStride, kJStride * sizeof(double));
+            }
+        }
+        if (e) {
+            std::vector<double> h((size_t)n * 2);
+            BA_HIP_CHECK(hipMemcpyAsync(h.data(), c->e, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+            for (int64_t k = 0; k < n; ++k) {
+                e[2 * c->h_perm[k]] = h[2 * k];
+                e[2 * c->h_perm[k] + 1] = h[2 * k + 1];
+            }
+        }
+        return BA_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,215 @@
+// Internal declarations of the MI355X bundle-adjustment library: context
+// layout, device math shared by the kernels, and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ba.h"
+
+namespace ba {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxTrack = 64;      // observations per point handled by one wave
+constexpr int kWhatStride = 32;    // padded length of the per-observation W-hat record
+constexpr int kJStride = 24;       // J_c (18) + J_p (6) per observation
+
+// ---------------------------------------------------------------------------
+// device math
+// ---------------------------------------------------------------------------
+
+// Coefficients of R(w) X = X + a (w x X) + b w x (w x X), with s = |w|^2,
+// a = sin(th)/th, b = (1 - cos th)/th^2 and their s-derivatives as = da/ds,
+// bs = db/ds.  Below th = 0.5 the Taylor series in s (truncated after the
+// s^7 term, error < 1e-17) avoids the cancellation of the closed forms.
+__device__ __forceinline__ void rot_coeffs(double s, double& a, double& b, double& as, double& bs) {
+    if (s < 0.25) {
+        a = 1.0 + s * (-1.0 / 6 + s * (1.0 / 120 + s * (-1.0 / 5040 + s * (1.0 / 362880 + s * (-1.0 / 39916800 + s * (1.0 / 6227020800.0 + s * (-1.0 / 1307674368000.0)))))));
+        b = 0.5 + s * (-1.0 / 24 + s * (1.0 / 720 + s * (-1.0 / 40320 + s * (1.0 / 3628800 + s * (-1.0 / 479001600 + s * (1.0 / 87178291200.0 + s * (-1.0 / 20922789888000.0)))))));
+        as = -1.0 / 6 + s * (2.0 / 120 + s * (-3.0 / 5040 + s * (4.0 / 362880 + s * (-5.0 / 39916800 + s * (6.0 / 6227020800.0 + s * (-7.0 / 1307674368000.0))))));
+        bs = -1.0 / 24 + s * (2.0 / 720 + s * (-3.0 / 40320 + s * (4.0 / 3628800 + s * (-5.0 / 479001600 + s * (6.0 / 87178291200.0 + s * (-7.0 / 20922789888000.0))))));
+    } else {
+        double th = sqrt(s);
+        double sn, cs;
+        sincos(th, &sn, &cs);
+        double sh = sin(0.5 * th);
+        double omc = 2.0 * sh * sh;   // 1 - cos th without cancellation
+        a = sn / th;
+        b = omc / s;
+        as = (th * cs - sn) / (2.0 * s * th);
+        bs = (th * sn - 2.0 * omc) / (2.0 * s * s);
+    }
+}
+
+// Predicted pixel of point X in camera c (9 params) and, if JAC, the
+// hand-derived Jacobian rows: Jc[r*9 + j] = d pix_r / d c_j,
+// Jp[r*3 + j] = d pix_r / d X_j.
+//   dP/dw = 2 as (w x X) w^T - a [X]x + 2 bs (w x (w x X)) w^T
+//           + b ((w.X) I + w X^T - 2 X w^T)
+//   dP/dX = R = I + a [w]x + b (w w^T - s I)
+template <bool JAC>
+__device__ __forceinline__ void project_point(const double* __restrict__ c, double X0, double X1, double X2,
+                                              double& pu, double& pv, double* Jc, double* Jp) {
+    const double w0 = c[0], w1 = c[1], w2 = c[2];
+    const double s = w0 * w0 + w1 * w1 + w2 * w2;
+    double a, b, as, bs;
+    rot_coeffs(s, a, b, as, bs);
+    const double cx0 = w1 * X2 - w2 * X1, cx1 = w2 * X0 - w0 * X2, cx2 = w0 * X1 - w1 * X0;
+    const double cc0 = w1 * cx2 - w2 * cx1, cc1 = w2 * cx0 - w0 * cx2, cc2 = w0 * cx1 - w1 * cx0;
+    const double P0 = X0 + a * cx0 + b * cc0 + c[3];
+    const double P1 = X1 + a * cx1 + b * cc1 + c[4];
+    const double P2 = X2 + a * cx2 + b * cc2 + c[5];
+    const double iz = 1.0 / P2;
+    const double x = P0 * iz, y = P1 * iz;
+    const double r2 = x * x + y * y;
+    const double f = c[6], k1 = c[7], k2 = c[8];
+    const double d = 1.0 + r2 * (k1 + k2 * r2);
+    pu = f * d * x;
+    pv = f * d * y;
+    if (!JAC) return;
+    const double dd = k1 + 2.0 * k2 * r2;
+    const double A00 = f * (d + 2.0 * x * x * dd), A01 = f * (2.0 * x * y * dd), A11 = f * (d + 2.0 * y * y * dd);
+    const double E00 = A00 * iz, E01 = A01 * iz, E02 = -(A00 * x + A01 * y) * iz;
+    const double E10 = A01 * iz, E11 = A11 * iz, E12 = -(A01 * x + A11 * y) * iz;
+    const double wX = w0 * X0 + w1 * X1 + w2 * X2;
+    const double g0 = 2.0 * (as * cx0 + bs * cc0), g1 = 2.0 * (as * cx1 + bs * cc1), g2 = 2.0 * (as * cx2 + bs * cc2);
+    const double M00 = g0 * w0 + b * (wX + w0 * X0 - 2.0 * X0 * w0);
+    const double M01 = g0 * w1 + a * X2 + b * (w0 * X1 - 2.0 * X0 * w1);
+    const double M02 = g0 * w2 - a * X1 + b * (w0 * X2 - 2.0 * X0 * w2);
+    const double M10 = g1 * w0 - a * X2 + b * (w1 * X0 - 2.0 * X1 * w0);
+    const double M11 = g1 * w1 + b * (wX + w1 * X1 - 2.0 * X1 * w1);
+    const double M12 = g1 * w2 + a * X0 + b * (w1 * X2 - 2.0 * X1 * w2);
+    const double M20 = g2 * w0 + a * X1 + b * (w2 * X0 - 2.0 * X2 * w0);
+    const double M21 = g2 * w1 - a * X0 + b * (w2 * X1 - 2.0 * X2 * w1);
+    const double M22 = g2 * w2 + b * (wX + w2 * X2 - 2.0 * X2 * w2);
+    Jc[0] = E00 * M00 + E01 * M10 + E02 * M20;
+    Jc[1] = E00 * M01 + E01 * M11 + E02 * M21;
+    Jc[2] = E00 * M02 + E01 * M12 + E02 * M22;
+    Jc[3] = E00; Jc[4] = E01; Jc[5] = E02;
+    Jc[6] = d * x; Jc[7] = f * x * r2; Jc[8] = f * x * r2 * r2;
+    Jc[9] = E10 * M00 + E11 * M10 + E12 * M20;
+    Jc[10] = E10 * M01 + E11 * M11 + E12 * M21;
+    Jc[11] = E10 * M02 + E11 * M12 + E12 * M22;
+    Jc[12] = E10; Jc[13] = E11; Jc[14] = E12;
+    Jc[15] = d * y; Jc[16] = f * y * r2; Jc[17] = f * y * r2 * r2;
+    const double R00 = 1.0 + b * (w0 * w0 - s), R01 = -a * w2 + b * w0 * w1, R02 = a * w1 + b * w0 * w2;
+    const double R10 = a * w2 + b * w1 * w0, R11 = 1.0 + b * (w1 * w1 - s), R12 = -a * w0 + b * w1 * w2;
+    const double R20 = -a * w1 + b * w2 * w0, R21 = a * w0 + b * w2 * w1, R22 = 1.0 + b * (w2 * w2 - s);
+    Jp[0] = E00 * R00 + E01 * R10 + E02 * R20;
+    Jp[1] = E00 * R01 + E01 * R11 + E02 * R21;
+    Jp[2] = E00 * R02 + E01 * R12 + E02 * R22;
+    Jp[3] = E10 * R00 + E11 * R10 + E12 * R20;
+    Jp[4] = E10 * R01 + E11 * R11 + E12 * R21;
+    Jp[5] = E10 * R02 + E11 * R12 + E12 * R22;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Deterministic block sum (fixed shuffle tree, then fixed LDS order); the
+// result is valid in thread 0.
+template <int BS>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < BS / kWave; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct Pcg {
+    double *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr, *d[2] = {nullptr, nullptr};
+    double *pA = nullptr, *pB[2] = {nullptr, nullptr};
+    int* state = nullptr;      // [0] done, [1] iterations, [2] status
+    double* scal = nullptr;    // [0] r0^2, [1] final relres
+    int nA = 0, nB = 0;        // partial counts of the two kernels
+};
+
+}  // namespace ba
+
+struct ba_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int32_t n_cams = 0, n_pts = 0, n_rows = 0, precision = BA_FP64;
+    int64_t n_obs = 0, n_blk = 0, n_pairs = 0;
+    int32_t n_chunk = 0, n_offseg = 0;
+    size_t bytes = 0, cap = 0;
+    std::string err;
+    // host copies
+    std::vector<int64_t> h_row_ptr;
+    std::vector<int32_t> h_col_idx;
+    std::vector<int64_t> h_perm;       // internal observation -> caller index
+    // device: observations in internal (point, camera) order
+    int32_t *obs_cam = nullptr, *obs_pt = nullptr, *obs_row = nullptr;
+    double* obs_uv = nullptr;          // [2][n_obs]
+    int32_t* pt_ptr = nullptr;         // [n_pts+1]
+    int32_t* chunk_ptr = nullptr;      // [n_chunk+1] point-aligned chunks of <= 64 observations
+    int32_t* cam_row = nullptr;        // [n_cams] RCS row or -1
+    // pattern
+    int32_t *row_ptr = nullptr, *col_idx = nullptr;
+    int32_t *off_blk = nullptr, *pair_ptr = nullptr, *trip = nullptr;
+    int32_t *rowobs_ptr = nullptr, *rowobs = nullptr;
+    int32_t *tr_ptr = nullptr, *tr_blk = nullptr;
+    // linearization / formation
+    void* J = nullptr;                 // [n_obs][24] T
+    double* e = nullptr;               // [n_obs][2]
+    void* What = nullptr;              // [n_obs][32] T
+    double* g = nullptr;               // [n_obs][9]
+    double* ptL = nullptr;             // [n_pts][9]: Cholesky of V* (6), L^-1 l_p (3)
+    double *blk = nullptr, *rhs = nullptr, *Minv = nullptr, *Mlearn = nullptr;
+    // LM
+    double *dxc = nullptr, *dxp = nullptr, *part = nullptr, *scal = nullptr;
+    int* flags = nullptr;
+    double* h_scal = nullptr;          // pinned
+    int* h_flags = nullptr;            // pinned
+    int32_t n_part = 0;
+    ba::Pcg pcg;
+    hipEvent_t ev[16] = {};
+    bool have_lin = false, have_rcs = false, learned_ready = false;
+    double lambda = 0.0;
+    double stage_ms[4] = {0, 0, 0, 0};
+};
+
+namespace ba {
+
+// launchers (stream-ordered, no synchronisation)
+void launch_project(const double* cams, const double* pts, const int32_t* obs_cam, const int32_t* obs_pt,
+                    int64_t n_obs, const double* noise, double* uv, hipStream_t st);
+void launch_linearize(ba_ctx* c, const double* cams, const double* pts);      // -> J, e, scal[0] = F
+void launch_point(ba_ctx* c, double lambda);
+void launch_offdiag(ba_ctx* c);
+void launch_diag(ba_ctx* c, double lambda);
+void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp);
+void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const double* dxc, const double* dxp);
+void launch_update(ba_ctx* c, double* cams, double* pts, const double* dxc, const double* dxp);
+// PCG: returns status; fills iters/relres (synchronises)
+ba_status run_pcg(ba_ctx* c, const double* Mblocks, double tol, int max_iter, const double* x0,
+                  double* out, int* iters, double* relres);
+
+}  // namespace ba
+
+#define BA_HIP_CHECK(call)                                                     \
+    do {                                                                       \
+        hipError_t _e = (call);                                                \
+        if (_e != hipSuccess) throw ba_hip_error(_e, #call, __FILE__, __LINE__); \
+    } while (0)
+
+struct ba_hip_error {
+    hipError_t code;
+    std::string what;
+    ba_hip_error(hipError_t c, const char* call, const char* file, int line)
+        : code(c), what(std::string(call) + " failed: " + hipGetErrorString(c) + " at " + file + ":" + std::to_string(line)) {}
+};

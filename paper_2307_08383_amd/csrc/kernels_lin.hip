@@ -1,0 +1,203 @@
+// Per-observation kernels: projection, linearization (residual + Jacobian
+// blocks, Sec. 3.1), candidate-cost / model evaluation and the parameter
+// update of an accepted LM step.  One lane per observation, observations in
+// the context's (point, camera) order so that point reads stream.
+#include "ba_common.hpp"
+
+namespace ba {
+
+namespace {
+
+constexpr int BS = 256;
+
+template <typename T>
+__device__ __forceinline__ void store_rec24(T* dst, const double* Jc, const double* Jp);
+
+template <>
+__device__ __forceinline__ void store_rec24<double>(double* dst, const double* Jc, const double* Jp) {
+    double2* d2 = reinterpret_cast<double2*>(dst);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) d2[i] = make_double2(Jc[2 * i], Jc[2 * i + 1]);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) d2[9 + i] = make_double2(Jp[2 * i], Jp[2 * i + 1]);
+}
+
+template <>
+__device__ __forceinline__ void store_rec24<float>(float* dst, const double* Jc, const double* Jp) {
+    float4* d4 = reinterpret_cast<float4*>(dst);
+    float v[24];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) v[i] = (float)Jc[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[18 + i] = (float)Jp[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) d4[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_rec24(const T* src, double* v);
+
+template <>
+__device__ __forceinline__ void load_rec24<double>(const double* src, double* v) {
+    const double2* s2 = reinterpret_cast<const double2*>(src);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        double2 t = s2[i];
+        v[2 * i] = t.x;
+        v[2 * i + 1] = t.y;
+    }
+}
+
+template <>
+__device__ __forceinline__ void load_rec24<float>(const float* src, double* v) {
+    const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        float4 t = s4[i];
+        v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w;
+    }
+}
+
+__global__ __launch_bounds__(BS) void k_project(int64_t n, const double* __restrict__ cams, const double* __restrict__ pts,
+                                                const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_pt,
+                                                const double* __restrict__ noise, double* __restrict__ uv) {
+    const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (k >= n) return;
+    const double* X = pts + (int64_t)obs_pt[k] * 3;
+    double pu, pv;
+    project_point<false>(cams + (int64_t)obs_cam[k] * 9, X[0], X[1], X[2], pu, pv, nullptr, nullptr);
+    if (noise) { pu += noise[k]; pv += noise[n + k]; }
+    uv[k] = pu;
+    uv[n + k] = pv;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_linearize(int n, const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_pt,
+                                                  const double* __restrict__ uv, const double* __restrict__ cams,
+                                                  const double* __restrict__ pts, T* __restrict__ J, double* __restrict__ e,
+                                                  double* __restrict__ part) {
+    __shared__ double sh[BS / kWave];
+    const int k = blockIdx.x * BS + threadIdx.x;
+    double cost = 0.0;
+    if (k < n) {
+        const double* X = pts + (int64_t)obs_pt[k] * 3;
+        double pu, pv, Jc[18], Jp[6];
+        project_point<true>(cams + (int64_t)obs_cam[k] * 9, X[0], X[1], X[2], pu, pv, Jc, Jp);
+        const double eu = pu - uv[k], ev = pv - uv[n + k];
+        store_rec24<T>(J + (int64_t)k * kJStride, Jc, Jp);
+        reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
+        cost = 0.5 * (eu * eu + ev * ev);
+    }
+    const double s = block_sum<BS>(cost, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// F' at x + dx, and from the stored linearization |J dx|^2 and dx^T l with
+// l = -J^T e (the model terms of the gain ratio).
+template <typename T>
+__global__ __launch_bounds__(BS) void k_evaluate(int n, const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_pt,
+                                                 const int32_t* __restrict__ obs_row, const double* __restrict__ uv,
+                                                 const double* __restrict__ cams, const double* __restrict__ pts,
+                                                 const double* __restrict__ dxc, const double* __restrict__ dxp,
+                                                 const T* __restrict__ J, const double* __restrict__ e,
+                                                 double* __restrict__ part, int nb) {
+    __shared__ double sh[BS / kWave];
+    const int k = blockIdx.x * BS + threadIdx.x;
+    double cost = 0.0, jdx2 = 0.0, dxl = 0.0;
+    if (k < n) {
+        const int row = obs_row[k];
+        const int p = obs_pt[k];
+        const double* c0 = cams + (int64_t)obs_cam[k] * 9;
+        double c[9], dc[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            dc[i] = row >= 0 ? dxc[(int64_t)row * 9 + i] : 0.0;
+            c[i] = c0[i] + dc[i];
+        }
+        const double* X = pts + (int64_t)p * 3;
+        const double* dX = dxp + (int64_t)p * 3;
+        double pu, pv;
+        project_point<false>(c, X[0] + dX[0], X[1] + dX[1], X[2] + dX[2], pu, pv, nullptr, nullptr);
+        const double eu = pu - uv[k], ev = pv - uv[n + k];
+        cost = 0.5 * (eu * eu + ev * ev);
+        double v[24];
+        load_rec24<T>(J + (int64_t)k * kJStride, v);
+        double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) { g0 += v[i] * dc[i]; g1 += v[9 + i] * dc[i]; }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) { g0 += v[18 + i] * dX[i]; g1 += v[21 + i] * dX[i]; }
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        jdx2 = g0 * g0 + g1 * g1;
+        dxl = -(g0 * ek.x + g1 * ek.y);
+    }
+    const double s0 = block_sum<BS>(cost, sh);
+    const double s1 = block_sum<BS>(jdx2, sh);
+    const double s2 = block_sum<BS>(dxl, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0;
+        part[nb + blockIdx.x] = s1;
+        part[2 * nb + blockIdx.x] = s2;
+    }
+}
+
+// out[j] = sum of part[j*n .. j*n + n) in a fixed order (one block per j)
+__global__ __launch_bounds__(BS) void k_reduce(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double sh[BS / kWave];
+    const double* p = part + (int64_t)blockIdx.x * n;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += BS) s += p[i];
+    s = block_sum<BS>(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_update(int n_cams, int n_pts, const int32_t* __restrict__ cam_row,
+                                               double* __restrict__ cams, double* __restrict__ pts,
+                                               const double* __restrict__ dxc, const double* __restrict__ dxp) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i < (int64_t)n_cams * 9) {
+        const int c = (int)(i / 9), j = (int)(i % 9);
+        const int r = cam_row[c];
+        if (r >= 0) cams[i] += dxc[(int64_t)r * 9 + j];
+    }
+    if (i < (int64_t)n_pts * 3) pts[i] += dxp[i];
+}
+
+inline int nblk(int64_t n) { return (int)((n + BS - 1) / BS); }
+
+}  // namespace
+
+void launch_project(const double* cams, const double* pts, const int32_t* obs_cam, const int32_t* obs_pt,
+                    int64_t n_obs, const double* noise, double* uv, hipStream_t st) {
+    if (n_obs <= 0) return;
+    k_project<<<nblk(n_obs), BS, 0, st>>>(n_obs, cams, pts, obs_cam, obs_pt, noise, uv);
+}
+
+void launch_linearize(ba_ctx* c, const double* cams, const double* pts) {
+    const int n = (int)c->n_obs, nb = nblk(n);
+    if (c->precision == BA_MIXED)
+        k_linearize<float><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_uv, cams, pts,
+                                                     (float*)c->J, c->e, c->part);
+    else
+        k_linearize<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_uv, cams, pts,
+                                                      (double*)c->J, c->e, c->part);
+    k_reduce<<<1, BS, 0, c->stream>>>(c->part, nb, c->scal + 0);
+}
+
+void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const double* dxc, const double* dxp) {
+    const int n = (int)c->n_obs, nb = nblk(n);
+    if (c->precision == BA_MIXED)
+        k_evaluate<float><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts,
+                                                    dxc, dxp, (const float*)c->J, c->e, c->part, nb);
+    else
+        k_evaluate<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts,
+                                                     dxc, dxp, (const double*)c->J, c->e, c->part, nb);
+    k_reduce<<<3, BS, 0, c->stream>>>(c->part, nb, c->scal + 1);   // scal[1] F', [2] |J dx|^2, [3] dx^T l
+}
+
+void launch_update(ba_ctx* c, double* cams, double* pts, const double* dxc, const double* dxp) {
+    const int64_t n = std::max<int64_t>((int64_t)c->n_cams * 9, (int64_t)c->n_pts * 3);
+    k_update<<<nblk(n), BS, 0, c->stream>>>(c->n_cams, c->n_pts, c->cam_row, cams, pts, dxc, dxp);
+}
+
+}  // namespace ba

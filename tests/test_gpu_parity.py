@@ -1,0 +1,285 @@
+"""HIP path against the oracle on identical seeded inputs (needs a GPU).
+
+Bars: pattern bit-exact; Jacobians / residuals to ~1e-12; RCS blocks to
+1e-10 (FP64) and 1e-4 (mixed) in the floored per-block metric; PCG
+solution, back-substitution and LM trajectory; final cost to rel 1e-6."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2307_08383_amd import scenegen
+
+from conftest import small_scene
+from gpu_util import T, block_errors, create
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ba = pytest.importorskip("paper_2307_08383_amd.ba")
+
+
+def _mid_scene(seed=4, n_pts=20000):
+    # 10 x 8 grid: several tiles of every kernel plus ragged tails
+    return scenegen.aerial_grid_scene(seed=seed, nx=10, ny=8, n_pts=n_pts, with_stats=False)
+
+
+def _both(scene, uv=None, precision=0, lam=1e-4, params="init"):
+    uv = orc.observations(scene) if uv is None else uv
+    cams = scene.cams_init if params == "init" else scene.cams_true
+    pts = scene.pts_init if params == "init" else scene.pts_true
+    P = orc.Problem.from_scene(scene, uv)
+    F_ref = P.linearize(cams, pts)
+    P.form_rcs(lam)
+    ctx = create(scene, uv, precision)
+    F = ba.ba_linearize(ctx, T(cams, torch.float64), T(pts, torch.float64))
+    ba.ba_form_rcs(ctx, lam)
+    return P, F_ref, ctx, F
+
+
+@pytest.mark.parametrize("variant", ["plain", "fixed", "shuffled"])
+def test_pattern_bit_exact(variant):
+    s = scenegen.tiny_scene(seed=7, n_pts=300, with_stats=False)
+    uv = orc.observations(s)
+    if variant == "fixed":
+        s.cam_fixed[[2, 5, 11]] = 1
+    if variant == "shuffled":
+        s, perm = scenegen.shuffled(s)
+        uv = uv[:, perm]
+    P = orc.Problem.from_scene(s, uv)
+    ctx = create(s, uv)
+    try:
+        rp, ci = ba.ba_get_pattern(ctx)
+        rp_ref, ci_ref = P.pattern()
+        assert np.array_equal(rp, rp_ref) and np.array_equal(ci, ci_ref)
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_project_matches_oracle():
+    s = _mid_scene(n_pts=5000)
+    uv_ref = orc.observations(s)
+    uv = ba.ba_project(T(s.cams_true, torch.float64), T(s.pts_true, torch.float64),
+                       T(s.obs_cam, torch.int32), T(s.obs_pt, torch.int32), T(s.noise, torch.float64))
+    np.testing.assert_allclose(uv.cpu().numpy(), uv_ref, rtol=1e-13, atol=1e-10)
+
+
+@pytest.mark.parametrize("theta_mode", ["nadir", "small"])
+def test_linearize_parity(theta_mode):
+    s = small_scene(seed=11, n_pts=200)
+    if theta_mode == "small":
+        # rotations near zero (series branch of the closed-form Jacobian)
+        # (t keeps P_z = X_z + 10 > 0 once R is close to the identity)
+        s.cams_init[:, :3] *= 1e-3 / np.linalg.norm(s.cams_init[:, :3], axis=1, keepdims=True)
+    uv = orc.observations(s)
+    F_ref, e_ref, Jc, Jp = orc.linearize(s.cams_init, s.pts_init, s.obs_cam, s.obs_pt, uv)
+    ctx = create(s, uv)
+    try:
+        F = ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        J, e = ba.ba_get_jacobians(ctx)
+        J_ref = np.concatenate([Jc.reshape(-1, 18), Jp.reshape(-1, 6)], axis=1)
+        scale = np.abs(J_ref).max(axis=1, keepdims=True)
+        assert (np.abs(J - J_ref) / scale).max() <= 1e-11
+        np.testing.assert_allclose(e, e_ref, rtol=0, atol=1e-9)
+        assert abs(F - F_ref) <= 1e-11 * F_ref
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_zero_residual_noise_free():
+    s = _mid_scene(n_pts=4000)
+    uv = orc.project(s.cams_true, s.pts_true, s.obs_cam, s.obs_pt)
+    ctx = create(s, uv)
+    try:
+        F = ba.ba_linearize(ctx, T(s.cams_true, torch.float64), T(s.pts_true, torch.float64))
+        _, e = ba.ba_get_jacobians(ctx)
+        assert np.abs(e).max() < 1e-9 and F < 1e-18 * s.n_obs
+    finally:
+        ba.ba_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, 1e-4)])
+@pytest.mark.parametrize("scene_kind", ["tiny", "mid", "fixed"])
+def test_rcs_parity(precision, tol, scene_kind):
+    if scene_kind == "tiny":
+        s = scenegen.tiny_scene(seed=0, with_stats=False)
+    else:
+        s = _mid_scene()
+        if scene_kind == "fixed":
+            s.cam_fixed[[0, 9, 40, 79]] = 1
+    for lam in (1e-4, 0.5):
+        P, F_ref, ctx, F = _both(s, precision=precision, lam=lam)
+        try:
+            blk, rhs = ba.ba_get_rcs(ctx)
+            blk_ref, rhs_ref = P.rcs()
+            rp, ci = P.pattern()
+            errs, raw = block_errors(blk, blk_ref, rp, ci)
+            assert errs.max() <= tol, (errs.max(), np.quantile(errs, 0.999), raw.max())
+            rerr = np.linalg.norm(rhs - rhs_ref, axis=1) / np.maximum(np.linalg.norm(rhs_ref, axis=1), 1e-300)
+            assert rerr.max() <= (1e-9 if precision == 0 else 1e-4), rerr.max()
+            # diagonal blocks are exactly symmetric
+            for r in range(len(rp) - 1):
+                assert np.array_equal(blk[rp[r]], blk[rp[r]].T)
+            assert abs(F - F_ref) <= 1e-11 * F_ref
+        finally:
+            ba.ba_destroy(ctx)
+
+
+def test_rcs_deterministic():
+    s = _mid_scene(n_pts=8000)
+    P, _, ctx, _ = _both(s)
+    try:
+        a = ba.ba_get_rcs(ctx)
+        ba.ba_form_rcs(ctx, 1e-4)
+        b = ba.ba_get_rcs(ctx)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_pcg_and_back_substitution_parity():
+    s = _mid_scene(n_pts=10000)
+    P, _, ctx, _ = _both(s, lam=1e-3)
+    try:
+        n_rows = P.n_rows
+        dxc = torch.empty((n_rows, 9), dtype=torch.float64, device="cuda")
+        info = ba.ba_pcg_solve(ctx, dxc, tol=1e-12, max_iter=5000)
+        x_ref, oinfo = P.pcg(tol=1e-12, max_iter=5000)
+        x = dxc.cpu().numpy()
+        assert info["status"] == 0 and info["relres"] <= 1e-12
+        assert np.linalg.norm(x - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
+        assert abs(info["iters"] - oinfo["iters"]) <= max(3, 0.05 * oinfo["iters"])
+        # same tolerance as the LM path
+        info6 = ba.ba_pcg_solve(ctx, dxc, tol=1e-6)
+        _, oinfo6 = P.pcg(tol=1e-6)
+        assert abs(info6["iters"] - oinfo6["iters"]) <= 2 and info6["relres"] <= 1e-6
+        # back-substitution from the same dxc
+        dxc_t = T(x_ref, torch.float64)
+        dxp = torch.empty((s.n_pts, 3), dtype=torch.float64, device="cuda")
+        ba.ba_back_substitute(ctx, dxc_t, dxp)
+        dxp_ref = P.back_substitute(x_ref)
+        np.testing.assert_allclose(dxp.cpu().numpy(), dxp_ref, rtol=0, atol=1e-10 * np.abs(dxp_ref).max())
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_pcg_initial_guess_and_limits():
+    s = _mid_scene(n_pts=6000)
+    P, _, ctx, _ = _both(s, lam=1e-3)
+    try:
+        x_ref, _ = P.pcg(tol=1e-12, max_iter=5000)
+        dxc = torch.empty((P.n_rows, 9), dtype=torch.float64, device="cuda")
+        a = ba.ba_pcg_solve(ctx, dxc, tol=1e-8)
+        xa = dxc.cpu().numpy().copy()
+        # an explicit zero initial guess is the default start, bit for bit
+        b = ba.ba_pcg_solve(ctx, dxc, tol=1e-8, x0=torch.zeros_like(dxc))
+        assert a["iters"] == b["iters"] and np.array_equal(xa, dxc.cpu().numpy())
+        # warm start from a loose solution still reaches the solution
+        ba.ba_pcg_solve(ctx, dxc, tol=1e-3)
+        warm = dxc.clone()
+        c = ba.ba_pcg_solve(ctx, dxc, tol=1e-9, x0=warm)
+        assert c["status"] == 0
+        assert np.linalg.norm(dxc.cpu().numpy() - x_ref) <= 1e-6 * np.linalg.norm(x_ref)
+        info = ba.ba_pcg_solve(ctx, dxc, tol=1e-12, max_iter=3)
+        assert info["status"] == ba.BA_ERR_NOT_CONVERGED and info["iters"] == 3
+        info = ba.ba_pcg_solve(ctx, dxc, tol=1e-12, max_iter=0)
+        assert info["iters"] == 0
+    finally:
+        ba.ba_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lm_trajectory(precision):
+    s = scenegen.tiny_scene(seed=0, with_stats=False)
+    uv = orc.observations(s)
+    P = orc.Problem.from_scene(s, uv)
+    _, _, hist_ref = orc.lm_run(P, s.cams_init, s.pts_init, 10)
+    ctx = create(s, uv, precision)
+    try:
+        cams = T(s.cams_init, torch.float64)
+        pts = T(s.pts_init, torch.float64)
+        st = ba.new_lm_state(1e-4)
+        hist = []
+        for _ in range(10):
+            hist.append(ba.ba_lm_step(ctx, cams, pts, st))
+        tol = 1e-9 if precision == 0 else 1e-5
+        for h, r in zip(hist, hist_ref):
+            # decisions are compared while the step is far from a tie
+            if (r["cost"] - r["cost_new"]) > 1e-8 * r["cost"]:
+                assert h["accepted"] == r["accepted"]
+                assert abs(h["cost"] - r["cost"]) <= tol * r["cost"]
+        F_fin = min(h["cost_new"] if h["accepted"] else h["cost"] for h in hist)
+        F_ref_fin = min(h["cost_new"] if h["accepted"] else h["cost"] for h in hist_ref)
+        assert abs(F_fin - F_ref_fin) <= 1e-6 * F_ref_fin
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_lm_mid_scene_final_cost():
+    s = _mid_scene(n_pts=20000)
+    uv = orc.observations(s)
+    P = orc.Problem.from_scene(s, uv)
+    c_ref, p_ref, hist_ref = orc.lm_run(P, s.cams_init, s.pts_init, 8)
+    ctx = create(s, uv)
+    try:
+        cams = T(s.cams_init, torch.float64)
+        pts = T(s.pts_init, torch.float64)
+        st = ba.new_lm_state(1e-4)
+        for _ in range(8):
+            ba.ba_lm_step(ctx, cams, pts, st)
+        F = P.cost(cams.cpu().numpy(), pts.cpu().numpy())
+        F_ref = P.cost(c_ref, p_ref)
+        assert abs(F - F_ref) <= 1e-6 * F_ref
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_reject_keeps_parameters():
+    s = scenegen.tiny_scene(seed=2, noise_sigma=0.0, with_stats=False)
+    uv = orc.observations(s)
+    ctx = create(s, uv)
+    try:
+        cams = T(s.cams_true, torch.float64)
+        pts = T(s.pts_true, torch.float64)
+        st = ba.new_lm_state(1e-3)
+        info = ba.ba_lm_step(ctx, cams, pts, st)
+        assert info["accepted"] == 0 and st.flags & 1
+        assert np.array_equal(cams.cpu().numpy(), s.cams_true) and np.array_equal(pts.cpu().numpy(), s.pts_true)
+        assert st.lam == pytest.approx(2e-3) and st.nu == 4.0 and st.iter == 1
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_invalid_inputs():
+    s = small_scene(seed=1)
+    uv = orc.observations(s)
+    bad = s.obs_cam.copy(); bad[0] = s.n_cams
+    import dataclasses
+    with pytest.raises(ba.BAError) as ei:
+        create(dataclasses.replace(s, obs_cam=bad), uv)
+    assert ei.value.status == ba.BA_ERR_INVALID_ARG
+    uvn = uv.copy(); uvn[1, 3] = np.nan
+    with pytest.raises(ba.BAError):
+        create(s, uvn)
+    oc = np.concatenate([s.obs_cam, s.obs_cam[:1]]); op = np.concatenate([s.obs_pt, s.obs_pt[:1]])
+    with pytest.raises(ba.BAError):
+        create(dataclasses.replace(s, obs_cam=oc, obs_pt=op), np.concatenate([uv, uv[:, :1]], axis=1))
+    ctx = create(s, uv)
+    try:
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_form_rcs(ctx, 1e-3)
+        assert ei.value.status == ba.BA_ERR_STATE
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        with pytest.raises(ba.BAError):
+            ba.ba_form_rcs(ctx, -1.0)
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_workspace_cap_out_of_memory():
+    s = small_scene(seed=1)
+    uv = orc.observations(s)
+    from paper_2307_08383_amd import ba as b
+    with pytest.raises(b.BAError) as ei:
+        b.ba_create(s.n_cams, s.n_pts, T(s.obs_cam, torch.int32), T(s.obs_pt, torch.int32),
+                    T(uv, torch.float64), workspace_cap=4096)
+    assert ei.value.status == b.BA_ERR_OUT_OF_MEMORY
