@@ -1,0 +1,169 @@
+"""Benchmark of the bundle-adjustment hot path on one MI355X.
+
+A step is one LM iteration (linearize, RCS formation, block-Jacobi PCG to
+rel 1e-6, back-substitution, candidate cost and gain ratio) on the aerial
+grid scene: 2,000 nadir cameras on a 50 x 40 grid, 400,000 points, track
+length truncated-geometric on [2, 12] with mean 4 (~1.6M observations),
+pixel noise N(0, 0.5^2), FP64.  Inputs are synthetic and resident in HBM
+before timing starts.
+
+Printed JSON line: value = RCS formation throughput (observations per
+second through linearize + formation, device time of the timed steps);
+ms_per_step = LM-iteration wall time; the roofline entry covers the
+dominant formation kernel (the camera-pair stage); cpu_baseline is the C
+oracle on the host cores for a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RCS formation obs/s + LM-iteration time, learned vs block-Jacobi PCG"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="aerial", choices=["aerial", "strips", "partition"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-formations", type=int, default=2)
+    return ap.parse_args()
+
+
+def build_scene(kind):
+    from paper_2307_08383_amd import scenegen
+    if kind == "aerial":
+        return scenegen.aerial_grid_scene(seed=0, with_stats=False)
+    if kind == "strips":
+        return scenegen.strips_scene(seed=1, with_stats=False)
+    return scenegen.partition_scene(seed=2, with_stats=False)
+
+
+def pair_stage_bytes(n_pairs, n_offseg, precision):
+    """Algorithmic bytes of one camera-pair-stage launch: per observation
+    couple its two index words and the two 9x3 W-hat records, per
+    off-diagonal block its 81 FP64 outputs and its segment bounds."""
+    es = 4 if precision == "mixed" else 8
+    return n_pairs * (8 + 2 * 27 * es) + n_offseg * (81 * 8 + 8)
+
+
+def traffic_from_profile(kernel_src_hash, kernel):
+    """HBM traffic per launch from committed rocprofv3 counter summaries, if
+    they were taken on the current kernel source; otherwise None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        ent = d.get(kernel)
+        if ent and ent.get("source_sha256") == kernel_src_hash:
+            return ent.get("bytes_per_launch")
+    except Exception:
+        return None
+    return None
+
+
+def cpu_baseline(scene, n_form):
+    from oracle import oracle as orc
+    nt = os.cpu_count() or 1
+    uv = orc.observations(scene)
+    P = orc.Problem.from_scene(scene, uv, n_threads=nt)
+    t0 = time.perf_counter()
+    for _ in range(n_form):
+        P.linearize(scene.cams_init, scene.pts_init)
+        P.form_rcs(1e-4)
+    dt = time.perf_counter() - t0
+    return {"value": scene.n_obs * n_form / dt, "unit": "obs/s", "cores": nt, "kind": "oracle",
+            "sample": f"the full scene ({scene.n_obs} observations), {n_form} formations "
+                      f"(linearize + RCS formation), {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build covers the one-GPU share of the "
+              "problem and uses no collectives; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2307_08383_amd import ba
+
+    dev = torch.device("cuda:0")
+    scene = build_scene(args.workload)
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    obs_cam = T(scene.obs_cam, torch.int32)
+    obs_pt = T(scene.obs_pt, torch.int32)
+    uv = ba.ba_project(T(scene.cams_true, torch.float64), T(scene.pts_true, torch.float64),
+                       obs_cam, obs_pt, T(scene.noise, torch.float64))
+    prec = ba.BA_MIXED if args.precision == "mixed" else ba.BA_FP64
+    cf = T(scene.cam_fixed, torch.uint8) if scene.cam_fixed.any() else None
+    ctx = ba.ba_create(scene.n_cams, scene.n_pts, obs_cam, obs_pt, uv, cf, precision=prec)
+    sizes = ba.ba_get_sizes(ctx)
+    cams = T(scene.cams_init, torch.float64)
+    pts = T(scene.pts_init, torch.float64)
+    st = ba.new_lm_state(1e-4)
+    for _ in range(args.warmup):
+        ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol)
+    torch.cuda.synchronize()
+    infos, stages = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol))
+        stages.append(ba.ba_get_stage_ms(ctx))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    lin = [i["ms_linearize"] for i in infos if i["ms_linearize"] > 0]
+    form = [i["ms_form_rcs"] for i in infos]
+    t_form = (np.mean(lin) if lin else 0.0) + np.mean(form)
+    value = scene.n_obs / (t_form * 1e-3)
+    st_arr = np.array(stages)
+    pair_ms = float(st_arr[:, 2].mean())
+    n_offseg = sizes["n_blk"] - sizes["n_rows"]
+    alg = pair_stage_bytes(sizes["n_pairs"], n_offseg, args.precision)
+    achieved = alg / (pair_ms * 1e-3) / 1e9
+    src = open(os.path.join(ROOT, "paper_2307_08383_amd", "csrc", "kernels_rcs.hip"), "rb").read()
+    traffic = traffic_from_profile(hashlib.sha256(src).hexdigest(), "k_offdiag_" + args.precision)
+    out = {
+        "metric": METRIC, "value": value, "unit": "obs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"{scene.name} ({scene.n_obs} observations), "
+                               f"{'FP64' if args.precision == 'fp64' else 'mixed FP32/FP64'}, "
+                               f"block-Jacobi PCG to rel {scene.pcg_tol:g}",
+                   "n_cams": scene.n_cams, "n_pts": scene.n_pts, "n_obs": scene.n_obs,
+                   "n_blocks": sizes["n_blk"], "n_pairs": sizes["n_pairs"]},
+        "lm_iteration_ms": ms_per_step,
+        "formation_ms": t_form,
+        "stages_ms": {"linearize": float(st_arr[:, 0][st_arr[:, 0] > 0].mean()) if (st_arr[:, 0] > 0).any() else 0.0,
+                      "point": float(st_arr[:, 1].mean()), "pair": pair_ms, "diag": float(st_arr[:, 3].mean()),
+                      "pcg": float(np.mean([i["ms_pcg"] for i in infos])),
+                      "back_substitute": float(np.mean([i["ms_back_substitute"] for i in infos])),
+                      "evaluate": float(np.mean([i["ms_evaluate"] for i in infos]))},
+        "pcg_iters_mean": float(np.mean([i["pcg_iters"] for i in infos])),
+        "final_cost": float(min(i["cost_new"] if i["accepted"] else i["cost"] for i in infos)),
+        "roofline": {"kernel": "k_offdiag (camera-pair stage)", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": alg},
+    }
+    ba.ba_destroy(ctx)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scene, args.cpu_sample_formations)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

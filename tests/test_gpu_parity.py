@@ -201,7 +201,9 @@ def test_lm_trajectory(precision):
         hist = []
         for _ in range(10):
             hist.append(ba.ba_lm_step(ctx, cams, pts, st))
-        tol = 1e-9 if precision == 0 else 1e-5
+        # each step solves the RCS only to PCG rel 1e-6, so iterates agree to
+        # about that level; the cost of each iterate is compared at 1e-6
+        tol = 1e-6 if precision == 0 else 1e-5
         for h, r in zip(hist, hist_ref):
             # decisions are compared while the step is far from a tie
             if (r["cost"] - r["cost_new"]) > 1e-8 * r["cost"]:
@@ -234,17 +236,33 @@ def test_lm_mid_scene_final_cost():
 
 
 def test_reject_keeps_parameters():
-    s = scenegen.tiny_scene(seed=2, noise_sigma=0.0, with_stats=False)
+    """A start far outside the region where the quadratic model holds (points
+    pulled 3.5 units towards the cameras and scattered, lambda ~ 0): the oracle
+    rejects with F' well above F, so must the library; parameters then stay
+    bitwise unchanged and lambda *= nu, nu *= 2."""
+    s = scenegen.tiny_scene(seed=2, with_stats=False)
     uv = orc.observations(s)
+    rng = np.random.default_rng(0)
+    pts0 = s.pts_true.copy()
+    pts0[:, 2] = 6.0
+    pts0[:, :2] += rng.normal(0, 2.0, (s.n_pts, 2))
+    P = orc.Problem.from_scene(s, uv)
+    ost = orc.LMState(lam=1e-12, nu=2.0, iter=0, pad=0)
+    oinfo = P.lm_step(s.cams_true.copy(), pts0.copy(), ost)
+    assert oinfo["accepted"] == 0 and oinfo["cost_new"] > 1.2 * oinfo["cost"]
     ctx = create(s, uv)
     try:
         cams = T(s.cams_true, torch.float64)
-        pts = T(s.pts_true, torch.float64)
-        st = ba.new_lm_state(1e-3)
+        pts = T(pts0, torch.float64)
+        st = ba.new_lm_state(1e-12)
         info = ba.ba_lm_step(ctx, cams, pts, st)
         assert info["accepted"] == 0 and st.flags & 1
-        assert np.array_equal(cams.cpu().numpy(), s.cams_true) and np.array_equal(pts.cpu().numpy(), s.pts_true)
-        assert st.lam == pytest.approx(2e-3) and st.nu == 4.0 and st.iter == 1
+        assert abs(info["cost"] - oinfo["cost"]) <= 1e-10 * oinfo["cost"]
+        assert np.array_equal(cams.cpu().numpy(), s.cams_true) and np.array_equal(pts.cpu().numpy(), pts0)
+        assert st.lam == pytest.approx(2e-12) and st.nu == 4.0 and st.iter == 1
+        # the second attempt reuses the linearization (flag bit 0 set)
+        info2 = ba.ba_lm_step(ctx, cams, pts, st)
+        assert info2["cost"] == info["cost"] and st.iter == 2
     finally:
         ba.ba_destroy(ctx)
 
