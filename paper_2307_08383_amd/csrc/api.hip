@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <cstdlib>
 
 #include "ba_common.hpp"
 
@@ -14,9 +15,8 @@ void launch_spmv(ba_ctx* c, const double* x, double* y);
 
 namespace {
 
-using ba::kJStride;
 using ba::kMaxTrack;
-using ba::kWhatStride;
+using ba::kRec;
 using ba::Pcg;
 
 thread_local std::string g_create_error;
@@ -53,7 +53,7 @@ void free_ctx(ba_ctx* c) {
     if (!c) return;
     void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->pt_ptr, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
-                    c->tr_ptr, c->tr_blk, c->J, c->e, c->What, c->g, c->ptL, c->blk, c->rhs, c->Minv,
+                    c->sp_ptr, c->sp_ent, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
                     c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r, c->pcg.z,
                     c->pcg.q, c->pcg.d[0], c->pcg.d[1], c->pcg.pA, c->pcg.pB[0], c->pcg.pB[1], c->pcg.state,
                     c->pcg.scal};
@@ -63,6 +63,8 @@ void free_ctx(ba_ctx* c) {
     if (c->h_flags) (void)hipHostFree(c->h_flags);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& g : c->pcg_graphs) (void)hipGraphExecDestroy(g.exec);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
 }
 
@@ -186,29 +188,86 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     c->n_blk = (int64_t)col_idx.size();
     c->n_offseg = (int32_t)off_blk.size();
     c->n_pairs = ntr;
+    // inside each row, order the pair segments longest first so that lanes
+    // sharing a wavefront get similar amounts of work (the block each segment
+    // writes is unchanged)
+    {
+        const int32_t ns = c->n_offseg;
+        std::vector<int32_t> order(ns);
+        std::iota(order.begin(), order.end(), 0);
+        int32_t s0 = 0;
+        while (s0 < ns) {
+            int32_t s1 = s0;
+            while (s1 < ns && seg_row[s1] == seg_row[s0]) ++s1;
+            std::stable_sort(order.begin() + s0, order.begin() + s1, [&](int32_t x, int32_t y) {
+                return pair_ptr[x + 1] - pair_ptr[x] > pair_ptr[y + 1] - pair_ptr[y];
+            });
+            s0 = s1;
+        }
+        std::vector<int32_t> off2(ns), ptr2(ns + 1), row2(ns), ta2(ntr), tb2(ntr);
+        int64_t m = 0;
+        for (int32_t i = 0; i < ns; ++i) {
+            const int32_t sg = order[i];
+            off2[i] = off_blk[sg];
+            row2[i] = seg_row[sg];
+            ptr2[i] = (int32_t)m;
+            for (int32_t t = pair_ptr[sg]; t < pair_ptr[sg + 1]; ++t, ++m) { ta2[m] = ta[t]; tb2[m] = tb[t]; }
+        }
+        ptr2[ns] = (int32_t)m;
+        off_blk.swap(off2);
+        pair_ptr.swap(ptr2);
+        seg_row.swap(row2);
+        ta.swap(ta2);
+        tb.swap(tb2);
+    }
+    c->n_seg_wg = (c->n_offseg + 15) / 16;
     // observations of each RCS row
     std::vector<int32_t> rowobs_ptr(nr + 1, 0), rowobs;
     for (int64_t k = 0; k < n; ++k)
         if (orow[k] >= 0) rowobs_ptr[orow[k] + 1]++;
     for (int32_t r = 0; r < nr; ++r) rowobs_ptr[r + 1] += rowobs_ptr[r];
     rowobs.resize(rowobs_ptr[nr]);
+    std::vector<int32_t> rowobs_pt(rowobs_ptr[nr]);
     {
         std::vector<int32_t> fill(rowobs_ptr.begin(), rowobs_ptr.end() - 1);
         for (int64_t k = 0; k < n; ++k)
-            if (orow[k] >= 0) rowobs[fill[orow[k]]++] = (int32_t)k;
+            if (orow[k] >= 0) {
+                const int32_t d = fill[orow[k]]++;
+                rowobs[d] = (int32_t)k;
+                rowobs_pt[d] = opt[k];
+            }
     }
-    // transposed blocks: for column s, the blocks (r, s) with r < s, by r
-    std::vector<int32_t> tr_ptr(nr + 1, 0), tr;
-    for (int32_t sg = 0; sg < c->n_offseg; ++sg) tr_ptr[col_idx[off_blk[sg]] + 1]++;
-    for (int32_t r = 0; r < nr; ++r) tr_ptr[r + 1] += tr_ptr[r];
-    tr.resize(2 * (size_t)tr_ptr[nr]);
+    // product entries of each row: its upper blocks S_rs (vector row s), then
+    // the blocks (s, r), s < r, of its column, used transposed (vector row s)
+    std::vector<int32_t> sp_ptr(nr + 1, 0), sp_ent;
     {
+        std::vector<int32_t> trn(nr, 0);
+        for (int32_t sg = 0; sg < c->n_offseg; ++sg) trn[col_idx[off_blk[sg]]]++;
+        for (int32_t r = 0; r < nr; ++r) sp_ptr[r + 1] = sp_ptr[r] + (int32_t)(row_ptr[r + 1] - row_ptr[r]) + trn[r];
+        std::vector<int32_t> tr_ptr(nr + 1, 0);
+        for (int32_t r = 0; r < nr; ++r) tr_ptr[r + 1] = tr_ptr[r] + trn[r];
+        std::vector<int32_t> tr_blk(tr_ptr[nr]), tr_row(tr_ptr[nr]);
         std::vector<int32_t> fill(tr_ptr.begin(), tr_ptr.end() - 1);
-        for (int32_t sg = 0; sg < c->n_offseg; ++sg) {
+        for (int32_t sg = 0; sg < c->n_offseg; ++sg) {   // segments are in row order
             const int32_t s = col_idx[off_blk[sg]];
             const int32_t d = fill[s]++;
-            tr[2 * d] = off_blk[sg];
-            tr[2 * d + 1] = seg_row[sg];
+            tr_blk[d] = off_blk[sg];
+            tr_row[d] = seg_row[sg];
+        }
+        int32_t es = 1;
+        for (int32_t r = 0; r < nr; ++r) es = std::max(es, sp_ptr[r + 1] - sp_ptr[r]);
+        c->ent_stride = es;
+        sp_ent.assign(2 * (size_t)nr * es, -1);
+        for (int32_t r = 0; r < nr; ++r) {
+            int64_t d = (int64_t)r * es;
+            for (int64_t kb = row_ptr[r]; kb < row_ptr[r + 1]; ++kb, ++d) {
+                sp_ent[2 * d] = (int32_t)kb;
+                sp_ent[2 * d + 1] = col_idx[kb] << 1;
+            }
+            for (int32_t t = tr_ptr[r]; t < tr_ptr[r + 1]; ++t, ++d) {
+                sp_ent[2 * d] = tr_blk[t];
+                sp_ent[2 * d + 1] = (tr_row[t] << 1) | 1;
+            }
         }
     }
     std::vector<int32_t> trip(2 * (size_t)ntr);
@@ -231,18 +290,18 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->trip, trip);
     upload(c, &c->rowobs_ptr, rowobs_ptr);
     upload(c, &c->rowobs, rowobs);
-    upload(c, &c->tr_ptr, tr_ptr);
-    upload(c, &c->tr_blk, tr);
+    upload(c, &c->rowobs_pt, rowobs_pt);
+    upload(c, &c->sp_ptr, sp_ptr);
+    upload(c, &c->sp_ent, sp_ent);
     BA_HIP_CHECK(hipStreamSynchronize(c->stream));
     c->h_row_ptr = std::move(row_ptr);
     c->h_col_idx = std::move(col_idx);
     c->h_perm = std::move(perm);
     // workspace
     const size_t es = c->precision == BA_MIXED ? sizeof(float) : sizeof(double);
-    dalloc(c, (char**)&c->J, (size_t)n * kJStride * es);
+    dalloc(c, (char**)&c->R, (size_t)n * kRec * es);
+    dalloc(c, (char**)&c->Jp, (size_t)n * 6 * es);
     dalloc(c, &c->e, (size_t)n * 2);
-    dalloc(c, (char**)&c->What, (size_t)n * kWhatStride * es);
-    dalloc(c, &c->g, (size_t)n * 9);
     dalloc(c, &c->ptL, (size_t)np * 9);
     dalloc(c, &c->blk, (size_t)c->n_blk * 81);
     dalloc(c, &c->rhs, (size_t)nr * 9);
@@ -260,14 +319,16 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &P.q, (size_t)nr * 9);
     dalloc(c, &P.d[0], (size_t)nr * 9);
     dalloc(c, &P.d[1], (size_t)nr * 9);
-    dalloc(c, &P.pA, (size_t)nr / 4 + 8);
-    dalloc(c, &P.pB[0], 2 * ((size_t)nr / 28 + 8));
-    dalloc(c, &P.pB[1], 2 * ((size_t)nr / 28 + 8));
+    dalloc(c, &P.pA, (size_t)nr + 8);
+    dalloc(c, &P.pB[0], 8 * ((size_t)nr / 28 + 2));
+    dalloc(c, &P.pB[1], 8 * ((size_t)nr / 28 + 2));
     dalloc(c, &P.state, 8);
     dalloc(c, &P.scal, 8);
     BA_HIP_CHECK(hipHostMalloc((void**)&c->h_scal, 32 * sizeof(double), hipHostMallocDefault));
     BA_HIP_CHECK(hipHostMalloc((void**)&c->h_flags, 16 * sizeof(int), hipHostMallocDefault));
     for (auto& e : c->ev) BA_HIP_CHECK(hipEventCreate(&e));
+    BA_HIP_CHECK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
+    if (const char* g = std::getenv("BA_PCG_GRAPHS")) c->use_graphs = std::atoi(g) != 0;
 }
 
 template <typename F>
@@ -585,18 +646,17 @@ ba_status ba_get_jacobians(ba_ctx* c, double* J, double* e) {
     return guarded(c, [&]() {
         const int64_t n = c->n_obs;
         if (J) {
-            if (c->precision == BA_MIXED) {
-                std::vector<float> h((size_t)n * kJStride);
-                BA_HIP_CHECK(hipMemcpyAsync(h.data(), c->J, h.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
-                BA_HIP_CHECK(hipStreamSynchronize(c->stream));
-                for (int64_t k = 0; k < n; ++k)
-                    for (int i = 0; i < kJStride; ++i) J[c->h_perm[k] * kJStride + i] = h[k * kJStride + i];
-            } else {
-                std::vector<double> h((size_t)n * kJStride);
-                BA_HIP_CHECK(hipMemcpyAsync(h.data(), c->J, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-                BA_HIP_CHECK(hipStreamSynchronize(c->stream));
-                for (int64_t k = 0; k < n; ++k)
-                    std::memcpy(J + c->h_perm[k] * kJStride, h.data() + k * kJStride, kJStride * sizeof(double));
+            const size_t es = c->precision == BA_MIXED ? sizeof(float) : sizeof(double);
+            std::vector<char> hr((size_t)n * kRec * es), hp((size_t)n * 6 * es);
+            BA_HIP_CHECK(hipMemcpyAsync(hr.data(), c->R, hr.size(), hipMemcpyDeviceToHost, c->stream));
+            BA_HIP_CHECK(hipMemcpyAsync(hp.data(), c->Jp, hp.size(), hipMemcpyDeviceToHost, c->stream));
+            BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+            for (int64_t k = 0; k < n; ++k) {
+                double* out = J + c->h_perm[k] * 24;
+                for (int i = 0; i < 18; ++i)
+                    out[i] = es == 4 ? ((const float*)hr.data())[k * kRec + i] : ((const double*)hr.data())[k * kRec + i];
+                for (int i = 0; i < 6; ++i)
+                    out[18 + i] = es == 4 ? ((const float*)hp.data())[k * 6 + i] : ((const double*)hp.data())[k * 6 + i];
             }
         }
         if (e) {

@@ -14,8 +14,8 @@ namespace ba {
 
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxTrack = 64;      // observations per point handled by one wave
-constexpr int kWhatStride = 32;    // padded length of the per-observation W-hat record
-constexpr int kJStride = 24;       // J_c (18) + J_p (6) per observation
+constexpr int kPcgBatch = 16;      // PCG iterations per enqueued batch (one graph)
+constexpr int kRec = 24;           // per-observation record: J_c (18), then K = J_p L^-T (6)
 
 // ---------------------------------------------------------------------------
 // device math
@@ -106,6 +106,54 @@ __device__ __forceinline__ void project_point(const double* __restrict__ c, doub
     Jp[5] = E10 * R02 + E11 * R12 + E12 * R22;
 }
 
+// Typed record access (T = double, or float for the mixed-precision path).
+// Records start on 16-byte boundaries (24 values of 8 or 4 bytes); the K part
+// and the separate J_p rows are 8-byte aligned.
+__device__ __forceinline__ void load_jc(const double* __restrict__ r, double* v) {
+    const double2* p = reinterpret_cast<const double2*>(r);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { const double2 t = p[i]; v[2 * i] = t.x; v[2 * i + 1] = t.y; }
+}
+__device__ __forceinline__ void load_jc(const float* __restrict__ r, double* v) {
+    const float4* p = reinterpret_cast<const float4*>(r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { const float4 t = p[i]; v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w; }
+    const float2 t = reinterpret_cast<const float2*>(r)[8];
+    v[16] = t.x; v[17] = t.y;
+}
+__device__ __forceinline__ void store_jc(double* __restrict__ r, const double* v) {
+    double2* p = reinterpret_cast<double2*>(r);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) p[i] = make_double2(v[2 * i], v[2 * i + 1]);
+}
+__device__ __forceinline__ void store_jc(float* __restrict__ r, const double* v) {
+    float4* p = reinterpret_cast<float4*>(r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) p[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
+    reinterpret_cast<float2*>(r)[8] = make_float2((float)v[16], (float)v[17]);
+}
+// six values at an 8-byte aligned address (the K part of a record, J_p rows)
+__device__ __forceinline__ void load6(const double* __restrict__ r, double* v) {
+    const double2* p = reinterpret_cast<const double2*>(r);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { const double2 t = p[i]; v[2 * i] = t.x; v[2 * i + 1] = t.y; }
+}
+__device__ __forceinline__ void load6(const float* __restrict__ r, double* v) {
+    const float2* p = reinterpret_cast<const float2*>(r);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) { const float2 t = p[i]; v[2 * i] = t.x; v[2 * i + 1] = t.y; }
+}
+__device__ __forceinline__ void store6(double* __restrict__ r, const double* v) {
+    double2* p = reinterpret_cast<double2*>(r);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] = make_double2(v[2 * i], v[2 * i + 1]);
+}
+__device__ __forceinline__ void store6(float* __restrict__ r, const double* v) {
+    float2* p = reinterpret_cast<float2*>(r);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) p[i] = make_float2((float)v[2 * i], (float)v[2 * i + 1]);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -162,12 +210,14 @@ struct ba_ctx {
     int32_t *row_ptr = nullptr, *col_idx = nullptr;
     int32_t *off_blk = nullptr, *pair_ptr = nullptr, *trip = nullptr;
     int32_t *rowobs_ptr = nullptr, *rowobs = nullptr;
-    int32_t *tr_ptr = nullptr, *tr_blk = nullptr;
+    int32_t *sp_ptr = nullptr, *sp_ent = nullptr;   // per row, padded to ent_stride: (block, vector row << 1 | transposed)
+    int32_t ent_stride = 0;
     // linearization / formation
-    void* J = nullptr;                 // [n_obs][24] T
+    void* R = nullptr;                 // [n_obs][24] T: J_c (18) from linearize, K (6) from the point stage
+    void* Jp = nullptr;                // [n_obs][6] T: J_p
     double* e = nullptr;               // [n_obs][2]
-    void* What = nullptr;              // [n_obs][32] T
-    double* g = nullptr;               // [n_obs][9]
+    int32_t* rowobs_pt = nullptr;      // point of each entry of rowobs
+    int32_t n_seg_wg = 0;              // workgroups of the pair stage (XCD-ordered)
     double* ptL = nullptr;             // [n_pts][9]: Cholesky of V* (6), L^-1 l_p (3)
     double *blk = nullptr, *rhs = nullptr, *Minv = nullptr, *Mlearn = nullptr;
     // LM
@@ -178,6 +228,15 @@ struct ba_ctx {
     int32_t n_part = 0;
     ba::Pcg pcg;
     hipEvent_t ev[16] = {};
+    hipStream_t capture_stream = nullptr;
+    bool use_graphs = true;
+    struct PcgGraph {
+        const double* M;
+        double tol;
+        int max_iter;
+        hipGraphExec_t exec;
+    };
+    std::vector<PcgGraph> pcg_graphs;
     bool have_lin = false, have_rcs = false, learned_ready = false;
     double lambda = 0.0;
     double stage_ms[4] = {0, 0, 0, 0};

@@ -10,54 +10,6 @@ namespace {
 
 constexpr int BS = 256;
 
-template <typename T>
-__device__ __forceinline__ void store_rec24(T* dst, const double* Jc, const double* Jp);
-
-template <>
-__device__ __forceinline__ void store_rec24<double>(double* dst, const double* Jc, const double* Jp) {
-    double2* d2 = reinterpret_cast<double2*>(dst);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) d2[i] = make_double2(Jc[2 * i], Jc[2 * i + 1]);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) d2[9 + i] = make_double2(Jp[2 * i], Jp[2 * i + 1]);
-}
-
-template <>
-__device__ __forceinline__ void store_rec24<float>(float* dst, const double* Jc, const double* Jp) {
-    float4* d4 = reinterpret_cast<float4*>(dst);
-    float v[24];
-#pragma unroll
-    for (int i = 0; i < 18; ++i) v[i] = (float)Jc[i];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) v[18 + i] = (float)Jp[i];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) d4[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
-}
-
-template <typename T>
-__device__ __forceinline__ void load_rec24(const T* src, double* v);
-
-template <>
-__device__ __forceinline__ void load_rec24<double>(const double* src, double* v) {
-    const double2* s2 = reinterpret_cast<const double2*>(src);
-#pragma unroll
-    for (int i = 0; i < 12; ++i) {
-        double2 t = s2[i];
-        v[2 * i] = t.x;
-        v[2 * i + 1] = t.y;
-    }
-}
-
-template <>
-__device__ __forceinline__ void load_rec24<float>(const float* src, double* v) {
-    const float4* s4 = reinterpret_cast<const float4*>(src);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        float4 t = s4[i];
-        v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w;
-    }
-}
-
 __global__ __launch_bounds__(BS) void k_project(int64_t n, const double* __restrict__ cams, const double* __restrict__ pts,
                                                 const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_pt,
                                                 const double* __restrict__ noise, double* __restrict__ uv) {
@@ -74,8 +26,8 @@ __global__ __launch_bounds__(BS) void k_project(int64_t n, const double* __restr
 template <typename T>
 __global__ __launch_bounds__(BS) void k_linearize(int n, const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_pt,
                                                   const double* __restrict__ uv, const double* __restrict__ cams,
-                                                  const double* __restrict__ pts, T* __restrict__ J, double* __restrict__ e,
-                                                  double* __restrict__ part) {
+                                                  const double* __restrict__ pts, T* __restrict__ R, T* __restrict__ Jp_out,
+                                                  double* __restrict__ e, double* __restrict__ part) {
     __shared__ double sh[BS / kWave];
     const int k = blockIdx.x * BS + threadIdx.x;
     double cost = 0.0;
@@ -84,7 +36,8 @@ __global__ __launch_bounds__(BS) void k_linearize(int n, const int32_t* __restri
         double pu, pv, Jc[18], Jp[6];
         project_point<true>(cams + (int64_t)obs_cam[k] * 9, X[0], X[1], X[2], pu, pv, Jc, Jp);
         const double eu = pu - uv[k], ev = pv - uv[n + k];
-        store_rec24<T>(J + (int64_t)k * kJStride, Jc, Jp);
+        store_jc(R + (int64_t)k * kRec, Jc);
+        store6(Jp_out + (int64_t)k * 6, Jp);
         reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
         cost = 0.5 * (eu * eu + ev * ev);
     }
@@ -99,8 +52,8 @@ __global__ __launch_bounds__(BS) void k_evaluate(int n, const int32_t* __restric
                                                  const int32_t* __restrict__ obs_row, const double* __restrict__ uv,
                                                  const double* __restrict__ cams, const double* __restrict__ pts,
                                                  const double* __restrict__ dxc, const double* __restrict__ dxp,
-                                                 const T* __restrict__ J, const double* __restrict__ e,
-                                                 double* __restrict__ part, int nb) {
+                                                 const T* __restrict__ R, const T* __restrict__ Jp,
+                                                 const double* __restrict__ e, double* __restrict__ part, int nb) {
     __shared__ double sh[BS / kWave];
     const int k = blockIdx.x * BS + threadIdx.x;
     double cost = 0.0, jdx2 = 0.0, dxl = 0.0;
@@ -120,13 +73,14 @@ __global__ __launch_bounds__(BS) void k_evaluate(int n, const int32_t* __restric
         project_point<false>(c, X[0] + dX[0], X[1] + dX[1], X[2] + dX[2], pu, pv, nullptr, nullptr);
         const double eu = pu - uv[k], ev = pv - uv[n + k];
         cost = 0.5 * (eu * eu + ev * ev);
-        double v[24];
-        load_rec24<T>(J + (int64_t)k * kJStride, v);
+        double v[18], jp[6];
+        load_jc(R + (int64_t)k * kRec, v);
+        load6(Jp + (int64_t)k * 6, jp);
         double g0 = 0.0, g1 = 0.0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) { g0 += v[i] * dc[i]; g1 += v[9 + i] * dc[i]; }
 #pragma unroll
-        for (int i = 0; i < 3; ++i) { g0 += v[18 + i] * dX[i]; g1 += v[21 + i] * dX[i]; }
+        for (int i = 0; i < 3; ++i) { g0 += jp[i] * dX[i]; g1 += jp[3 + i] * dX[i]; }
         const double2 ek = reinterpret_cast<const double2*>(e)[k];
         jdx2 = g0 * g0 + g1 * g1;
         dxl = -(g0 * ek.x + g1 * ek.y);
@@ -177,10 +131,10 @@ void launch_linearize(ba_ctx* c, const double* cams, const double* pts) {
     const int n = (int)c->n_obs, nb = nblk(n);
     if (c->precision == BA_MIXED)
         k_linearize<float><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_uv, cams, pts,
-                                                     (float*)c->J, c->e, c->part);
+                                                     (float*)c->R, (float*)c->Jp, c->e, c->part);
     else
         k_linearize<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_uv, cams, pts,
-                                                      (double*)c->J, c->e, c->part);
+                                                      (double*)c->R, (double*)c->Jp, c->e, c->part);
     k_reduce<<<1, BS, 0, c->stream>>>(c->part, nb, c->scal + 0);
 }
 
@@ -188,10 +142,10 @@ void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const dou
     const int n = (int)c->n_obs, nb = nblk(n);
     if (c->precision == BA_MIXED)
         k_evaluate<float><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts,
-                                                    dxc, dxp, (const float*)c->J, c->e, c->part, nb);
+                                                    dxc, dxp, (const float*)c->R, (const float*)c->Jp, c->e, c->part, nb);
     else
         k_evaluate<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts,
-                                                     dxc, dxp, (const double*)c->J, c->e, c->part, nb);
+                                                     dxc, dxp, (const double*)c->R, (const double*)c->Jp, c->e, c->part, nb);
     k_reduce<<<3, BS, 0, c->stream>>>(c->part, nb, c->scal + 1);   // scal[1] F', [2] |J dx|^2, [3] dx^T l
 }
 

@@ -1,16 +1,17 @@
 // Reduced-camera-system formation (Eq. (3)-(4), Sec. 5) and point
 // back-substitution (Eq. (5)).
 //
-// With V*_p = L_p L_p^T (3x3 Cholesky) every Schur term factors as
-//   W_ip V*_p^-1 W_jp^T = What_ip What_jp^T,   What_ip = W_ip L_p^-T  (9x3),
-//   W_ip V*_p^-1 l_p    = What_ip lhat_p,      lhat_p = L_p^-1 l_p,
-// so the point stage stores one 9x3 record per observation and the camera
-// pairs only need products of those records:
-//   S_ij = delta_ij U*_i - sum_p What_ip What_jp^T,
-//   b_i  = sum_p (-J_ci^T e_ip - What_ip lhat_p).
-// The off-diagonal blocks are segmented reductions over the observation
-// pairs of each camera pair (sorted once by pair, no atomics); the diagonal
-// blocks are reductions over each camera's observations.
+// With V*_p = L_p L_p^T (3x3 Cholesky) and K_a = J_pa L_p^-T (2x3) for an
+// observation a of point p by camera i:
+//   W_ip V*_p^-1 W_jp^T = J_ca^T (K_a K_b^T) J_cb          (camera pair i, j)
+//   U_i - sum_p W_ip V*_p^-1 W_ip^T = sum_a J_ca^T (I - K_a K_a^T) J_ca
+//   b_i = l_c - W V*^-1 l_p = -sum_a J_ca^T (e_a + K_a lhat_p),  lhat_p = L_p^-1 l_p
+//   dx_p = L_p^-T (lhat_p - sum_a K_a^T J_ca dx_c)          (Eq. (5))
+// so the point stage only adds K (6 values) to each observation's J_c record
+// and every later stage reads one 24-value record per observation.  The
+// off-diagonal blocks are segmented reductions over the observation couples
+// of each camera pair (sorted once, no atomics); the diagonal blocks are
+// reductions over each camera's observations.
 #include "ba_common.hpp"
 
 namespace ba {
@@ -20,66 +21,6 @@ namespace {
 constexpr int BS = 256;
 constexpr int WPB = BS / kWave;   // waves per block
 
-template <typename T, int N>
-__device__ __forceinline__ void load_vals(const T* __restrict__ src, double* v);
-
-template <>
-__device__ __forceinline__ void load_vals<double, 24>(const double* __restrict__ src, double* v) {
-    const double2* s2 = reinterpret_cast<const double2*>(src);
-#pragma unroll
-    for (int i = 0; i < 12; ++i) { double2 t = s2[i]; v[2 * i] = t.x; v[2 * i + 1] = t.y; }
-}
-template <>
-__device__ __forceinline__ void load_vals<float, 24>(const float* __restrict__ src, double* v) {
-    const float4* s4 = reinterpret_cast<const float4*>(src);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) { float4 t = s4[i]; v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w; }
-}
-template <>
-__device__ __forceinline__ void load_vals<double, 18>(const double* __restrict__ src, double* v) {
-    const double2* s2 = reinterpret_cast<const double2*>(src);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) { double2 t = s2[i]; v[2 * i] = t.x; v[2 * i + 1] = t.y; }
-}
-template <>
-__device__ __forceinline__ void load_vals<float, 18>(const float* __restrict__ src, double* v) {
-    const float2* s2 = reinterpret_cast<const float2*>(src);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) { float2 t = s2[i]; v[2 * i] = t.x; v[2 * i + 1] = t.y; }
-}
-// W-hat record: 27 values (padded stride 32)
-template <>
-__device__ __forceinline__ void load_vals<double, 27>(const double* __restrict__ src, double* v) {
-    const double2* s2 = reinterpret_cast<const double2*>(src);
-#pragma unroll
-    for (int i = 0; i < 13; ++i) { double2 t = s2[i]; v[2 * i] = t.x; v[2 * i + 1] = t.y; }
-    v[26] = src[26];
-}
-template <>
-__device__ __forceinline__ void load_vals<float, 27>(const float* __restrict__ src, double* v) {
-    const float4* s4 = reinterpret_cast<const float4*>(src);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) { float4 t = s4[i]; v[4 * i] = t.x; v[4 * i + 1] = t.y; v[4 * i + 2] = t.z; v[4 * i + 3] = t.w; }
-    v[24] = src[24]; v[25] = src[25]; v[26] = src[26];
-}
-
-template <typename T>
-__device__ __forceinline__ void store_what(T* dst, const double* v);
-template <>
-__device__ __forceinline__ void store_what<double>(double* dst, const double* v) {
-    double2* d2 = reinterpret_cast<double2*>(dst);
-#pragma unroll
-    for (int i = 0; i < 13; ++i) d2[i] = make_double2(v[2 * i], v[2 * i + 1]);
-    dst[26] = v[26];
-}
-template <>
-__device__ __forceinline__ void store_what<float>(float* dst, const double* v) {
-    float4* d4 = reinterpret_cast<float4*>(dst);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) d4[i] = make_float4((float)v[4 * i], (float)v[4 * i + 1], (float)v[4 * i + 2], (float)v[4 * i + 3]);
-    dst[24] = (float)v[24]; dst[25] = (float)v[25]; dst[26] = (float)v[26];
-}
-
 // ---------------------------------------------------------------------------
 // point stage: one wave per chunk of whole tracks (<= 64 observations), one
 // lane per observation.  Track sums V_p, l_p are reduced through LDS by the
@@ -87,39 +28,35 @@ __device__ __forceinline__ void store_what<float>(float* dst, const double* v) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __restrict__ chunk_ptr,
-                                              const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ obs_row,
-                                              const int32_t* __restrict__ pt_ptr, const T* __restrict__ J,
-                                              const double* __restrict__ e, double lambda, T* __restrict__ What,
-                                              double* __restrict__ g, double* __restrict__ ptL, int* __restrict__ flags) {
+                                              const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ pt_ptr,
+                                              T* __restrict__ R, const T* __restrict__ Jp, const double* __restrict__ e,
+                                              double lambda, double* __restrict__ ptL, int* __restrict__ flags) {
     __shared__ double sP[WPB][kWave][9];
-    __shared__ double sR[WPB][kWave][9];
+    __shared__ double sR[WPB][kWave][6];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int chunk = blockIdx.x * WPB + wv;
     int k0 = 0, k1 = 0;
     if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
     const int k = k0 + lane;
     const bool act = k < k1;
-    double v[24];
-    double e0 = 0.0, e1 = 0.0;
+    double jp[6];
     int p = 0, head = 0, tl = 0;
     if (act) {
-        load_vals<T, 24>(J + (int64_t)k * kJStride, v);
+        load6(Jp + (int64_t)k * 6, jp);
         const double2 ek = reinterpret_cast<const double2*>(e)[k];
-        e0 = ek.x; e1 = ek.y;
         p = obs_pt[k];
         const int b = pt_ptr[p];
         head = b - k0;
         tl = pt_ptr[p + 1] - b;
-        const double* Jp = v + 18;
-        sP[wv][lane][0] = Jp[0] * Jp[0] + Jp[3] * Jp[3];
-        sP[wv][lane][1] = Jp[0] * Jp[1] + Jp[3] * Jp[4];
-        sP[wv][lane][2] = Jp[0] * Jp[2] + Jp[3] * Jp[5];
-        sP[wv][lane][3] = Jp[1] * Jp[1] + Jp[4] * Jp[4];
-        sP[wv][lane][4] = Jp[1] * Jp[2] + Jp[4] * Jp[5];
-        sP[wv][lane][5] = Jp[2] * Jp[2] + Jp[5] * Jp[5];
-        sP[wv][lane][6] = -(Jp[0] * e0 + Jp[3] * e1);
-        sP[wv][lane][7] = -(Jp[1] * e0 + Jp[4] * e1);
-        sP[wv][lane][8] = -(Jp[2] * e0 + Jp[5] * e1);
+        sP[wv][lane][0] = jp[0] * jp[0] + jp[3] * jp[3];
+        sP[wv][lane][1] = jp[0] * jp[1] + jp[3] * jp[4];
+        sP[wv][lane][2] = jp[0] * jp[2] + jp[3] * jp[5];
+        sP[wv][lane][3] = jp[1] * jp[1] + jp[4] * jp[4];
+        sP[wv][lane][4] = jp[1] * jp[2] + jp[4] * jp[5];
+        sP[wv][lane][5] = jp[2] * jp[2] + jp[5] * jp[5];
+        sP[wv][lane][6] = -(jp[0] * ek.x + jp[3] * ek.y);
+        sP[wv][lane][7] = -(jp[1] * ek.x + jp[4] * ek.y);
+        sP[wv][lane][8] = -(jp[2] * ek.x + jp[5] * ek.y);
     }
     __syncthreads();
     if (act && head == lane) {
@@ -129,7 +66,7 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
         for (int q = 0; q < tl; ++q)
 #pragma unroll
             for (int m = 0; m < 9; ++m) s[m] += sP[wv][lane + q][m];
-        // V* = V + lambda diag(V), then V* = L L^T
+        // V* = V + lambda diag(V) = L L^T
         const double V00 = s[0] * (1.0 + lambda), V11 = s[3] * (1.0 + lambda), V22 = s[5] * (1.0 + lambda);
         const double L00 = sqrt(V00);
         const double L10 = s[1] / L00, L20 = s[2] / L00;
@@ -144,193 +81,224 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
         const double y2 = (s[8] - L20 * y0 - L21 * y1) / L22;
         const double r[9] = {L00, L10, L11, L20, L21, L22, y0, y1, y2};
 #pragma unroll
-        for (int m = 0; m < 9; ++m) { sR[wv][lane][m] = r[m]; ptL[(int64_t)p * 9 + m] = r[m]; }
+        for (int m = 0; m < 6; ++m) sR[wv][lane][m] = r[m];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) ptL[(int64_t)p * 9 + m] = r[m];
     }
     __syncthreads();
     if (act) {
         const double L00 = sR[wv][head][0], L10 = sR[wv][head][1], L11 = sR[wv][head][2];
         const double L20 = sR[wv][head][3], L21 = sR[wv][head][4], L22 = sR[wv][head][5];
-        const double h0 = sR[wv][head][6], h1 = sR[wv][head][7], h2 = sR[wv][head][8];
-        const double i00 = 1.0 / L00, i11 = 1.0 / L11, i22 = 1.0 / L22;
-        const double* Jc = v;
-        const double* Jp = v + 18;
-        double wh[27];
-        const int row = obs_row[k];
+        // K = J_p L^-T: row r solves L y = J_p[r]^T
+        double K[6];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            // row i of W = J_c^T J_p, then solve L y = w_i^T
-            const double w0 = Jc[i] * Jp[0] + Jc[9 + i] * Jp[3];
-            const double w1 = Jc[i] * Jp[1] + Jc[9 + i] * Jp[4];
-            const double w2 = Jc[i] * Jp[2] + Jc[9 + i] * Jp[5];
-            const double y0 = w0 * i00;
-            const double y1 = (w1 - L10 * y0) * i11;
-            const double y2 = (w2 - L20 * y0 - L21 * y1) * i22;
-            wh[3 * i] = y0; wh[3 * i + 1] = y1; wh[3 * i + 2] = y2;
+        for (int rr = 0; rr < 2; ++rr) {
+            const double y0 = jp[3 * rr] / L00;
+            const double y1 = (jp[3 * rr + 1] - L10 * y0) / L11;
+            const double y2 = (jp[3 * rr + 2] - L20 * y0 - L21 * y1) / L22;
+            K[3 * rr] = y0; K[3 * rr + 1] = y1; K[3 * rr + 2] = y2;
         }
-        store_what<T>(What + (int64_t)k * kWhatStride, wh);
-        if (row >= 0) {
-            double* gk = g + (int64_t)k * 9;
-#pragma unroll
-            for (int i = 0; i < 9; ++i)
-                gk[i] = -(Jc[i] * e0 + Jc[9 + i] * e1) - (wh[3 * i] * h0 + wh[3 * i + 1] * h1 + wh[3 * i + 2] * h2);
-        }
+        store6(R + (int64_t)k * kRec + 18, K);
     }
 }
 
 // ---------------------------------------------------------------------------
-// off-diagonal pair stage: G lanes per camera pair (BS/G pairs per block),
-// each lane accumulating the full 9x9 product over a strided subset of the
-// pair's observation couples, then a shuffle reduction inside the group.
+// off-diagonal pair stage.  16 lanes per camera pair = 4 couple slots x 4
+// column quarters ({0,1,2}, {3,4}, {5,6}, {7,8}); each lane accumulates the
+// 9 rows of its columns of
+//   S_ij -= J_ca^T (K_a K_b^T) J_cb
+// over the couples of its slot, then the 4 slots are reduced by shuffles.
+// Segments are stored row by row (longest first inside a row); the block
+// index is remapped so that each XCD works through a contiguous range of
+// rows, keeping the records of neighbouring cameras in its L2.
 // ---------------------------------------------------------------------------
-template <typename T, int G>
-__global__ __launch_bounds__(BS) void k_offdiag(int n_seg, const int32_t* __restrict__ off_blk,
+template <typename T>
+__global__ __launch_bounds__(BS) void k_offdiag(int n_seg, int n_wg, const int32_t* __restrict__ off_blk,
                                                 const int32_t* __restrict__ pair_ptr, const int32_t* __restrict__ trip,
-                                                const T* __restrict__ What, double* __restrict__ blk) {
-    const int gl = threadIdx.x % G;
-    const int seg = blockIdx.x * (BS / G) + threadIdx.x / G;
-    double acc[81];
+                                                const T* __restrict__ R, double* __restrict__ blk) {
+    const int per_xcd = (n_wg + 7) / 8;
+    const int wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int gl = threadIdx.x % 16;
+    const int slot = gl / 4, quarter = gl % 4;
+    const int seg = wg * (BS / 16) + threadIdx.x / 16;
+    const int c0 = quarter == 0 ? 0 : 2 * quarter + 1;   // 0, 3, 5, 7
+    const int nc = quarter == 0 ? 3 : 2;
+    double acc[27];
 #pragma unroll
-    for (int m = 0; m < 81; ++m) acc[m] = 0.0;
+    for (int m = 0; m < 27; ++m) acc[m] = 0.0;
     int t0 = 0, t1 = 0;
-    if (seg < n_seg) { t0 = pair_ptr[seg]; t1 = pair_ptr[seg + 1]; }
-    for (int t = t0 + gl; t < t1; t += G) {
+    if (wg < n_wg && seg < n_seg) { t0 = pair_ptr[seg]; t1 = pair_ptr[seg + 1]; }
+    for (int t = t0 + slot; t < t1; t += 4) {
         const int2 ab = reinterpret_cast<const int2*>(trip)[t];
-        double wb[27];
-        load_vals<T, 27>(What + (int64_t)ab.y * kWhatStride, wb);
-        const T* wa_p = What + (int64_t)ab.x * kWhatStride;
+        const T* ra = R + (int64_t)ab.x * kRec;
+        const T* rb = R + (int64_t)ab.y * kRec;
+        double ja[18], ka[6], kb[6], jb0[3], jb1[3];
+        load_jc(ra, ja);
+        load6(ra + 18, ka);
+        load6(rb + 18, kb);
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const double a0 = (double)wa_p[3 * i], a1 = (double)wa_p[3 * i + 1], a2 = (double)wa_p[3 * i + 2];
-#pragma unroll
-            for (int j = 0; j < 9; ++j) acc[i * 9 + j] += a0 * wb[3 * j] + a1 * wb[3 * j + 1] + a2 * wb[3 * j + 2];
+        for (int q = 0; q < 3; ++q) {
+            const int c = c0 + (q < nc ? q : 0);
+            jb0[q] = (double)rb[c];
+            jb1[q] = (double)rb[9 + c];
         }
+        // M = K_a K_b^T (2x2), P = M J_cb (2 x my columns)
+        const double m00 = ka[0] * kb[0] + ka[1] * kb[1] + ka[2] * kb[2];
+        const double m01 = ka[0] * kb[3] + ka[1] * kb[4] + ka[2] * kb[5];
+        const double m10 = ka[3] * kb[0] + ka[4] * kb[1] + ka[5] * kb[2];
+        const double m11 = ka[3] * kb[3] + ka[4] * kb[4] + ka[5] * kb[5];
+        double p0[3], p1[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            p0[q] = m00 * jb0[q] + m01 * jb1[q];
+            p1[q] = m10 * jb0[q] + m11 * jb1[q];
+        }
+#pragma unroll
+        for (int r = 0; r < 9; ++r)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) acc[r * 3 + q] += ja[r] * p0[q] + ja[9 + r] * p1[q];
     }
 #pragma unroll
-    for (int m = 0; m < 81; ++m)
-#pragma unroll
-        for (int o = G / 2; o > 0; o >>= 1) acc[m] += __shfl_xor(acc[m], o, kWave);
-    if (seg < n_seg) {
+    for (int m = 0; m < 27; ++m) {
+        acc[m] += __shfl_xor(acc[m], 4, kWave);
+        acc[m] += __shfl_xor(acc[m], 8, kWave);
+    }
+    if (wg < n_wg && seg < n_seg && slot == 0) {
         double* out = blk + (int64_t)off_blk[seg] * 81;
 #pragma unroll
-        for (int m = 0; m < 81; ++m)
-            if ((m % G) == gl) out[m] = -acc[m];
+        for (int r = 0; r < 9; ++r)
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (q < nc) out[r * 9 + c0 + q] = -acc[r * 3 + q];
     }
 }
 
 // ---------------------------------------------------------------------------
-// diagonal stage: one wave per RCS row over the camera's observations;
-// S_ii = sum (J_c^T J_c - What What^T) + lambda diag(U), b_i = sum g, then
-// the block-Jacobi inverse S_ii^-1 (Cholesky, triangular inverse).
+// diagonal stage: one block per RCS row over the camera's observations;
+// S_ii = sum J_c^T (I - K K^T) J_c + lambda diag(U), U = sum J_c^T J_c,
+// b_i = -sum J_c^T (e + K lhat), then the block-Jacobi inverse S_ii^-1
+// (Cholesky and triangular inverse).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restrict__ rowobs_ptr,
-                                             const int32_t* __restrict__ rowobs, const int32_t* __restrict__ row_ptr,
-                                             const T* __restrict__ J, const T* __restrict__ What,
-                                             const double* __restrict__ g, double lambda, double* __restrict__ blk,
-                                             double* __restrict__ rhs, double* __restrict__ Minv, int* __restrict__ flags) {
-    __shared__ double sS[WPB][81];
-    __shared__ double sL[WPB][81];
-    __shared__ double sb[WPB][9];
+                                             const int32_t* __restrict__ rowobs, const int32_t* __restrict__ rowobs_pt,
+                                             const int32_t* __restrict__ row_ptr, const T* __restrict__ R,
+                                             const double* __restrict__ e, const double* __restrict__ ptL,
+                                             double lambda, double* __restrict__ blk, double* __restrict__ rhs,
+                                             double* __restrict__ Minv, int* __restrict__ flags) {
+    __shared__ double sred[WPB][64];
+    __shared__ double sS[81];
+    __shared__ double sL[81];
+    const int row = blockIdx.x;
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int row = blockIdx.x * WPB + wv;
     double A[45], du[9], bb[9];
 #pragma unroll
     for (int m = 0; m < 45; ++m) A[m] = 0.0;
 #pragma unroll
     for (int m = 0; m < 9; ++m) { du[m] = 0.0; bb[m] = 0.0; }
-    int i0 = 0, i1 = 0;
-    if (row < n_rows) { i0 = rowobs_ptr[row]; i1 = rowobs_ptr[row + 1]; }
-    for (int idx = i0 + lane; idx < i1; idx += kWave) {
+    const int i0 = rowobs_ptr[row], i1 = rowobs_ptr[row + 1];
+    for (int idx = i0 + threadIdx.x; idx < i1; idx += BS) {
         const int k = rowobs[idx];
-        double jc[18], wh[27];
-        load_vals<T, 18>(J + (int64_t)k * kJStride, jc);
-        load_vals<T, 27>(What + (int64_t)k * kWhatStride, wh);
-        const double* gk = g + (int64_t)k * 9;
+        const int p = rowobs_pt[idx];
+        double jc[18], K[6];
+        const T* rk = R + (int64_t)k * kRec;
+        load_jc(rk, jc);
+        load6(rk + 18, K);
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        const double* lh = ptL + (int64_t)p * 9 + 6;
+        const double n00 = 1.0 - (K[0] * K[0] + K[1] * K[1] + K[2] * K[2]);
+        const double n01 = -(K[0] * K[3] + K[1] * K[4] + K[2] * K[5]);
+        const double n11 = 1.0 - (K[3] * K[3] + K[4] * K[4] + K[5] * K[5]);
+        const double v0 = ek.x + K[0] * lh[0] + K[1] * lh[1] + K[2] * lh[2];
+        const double v1 = ek.y + K[3] * lh[0] + K[4] * lh[1] + K[5] * lh[2];
+        double q0[9], q1[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            q0[c] = n00 * jc[c] + n01 * jc[9 + c];
+            q1[c] = n01 * jc[c] + n11 * jc[9 + c];
+        }
         int m = 0;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            du[i] += jc[i] * jc[i] + jc[9 + i] * jc[9 + i];
-            bb[i] += gk[i];
+        for (int r = 0; r < 9; ++r) {
+            du[r] += jc[r] * jc[r] + jc[9 + r] * jc[9 + r];
+            bb[r] -= jc[r] * v0 + jc[9 + r] * v1;
 #pragma unroll
-            for (int j = i; j < 9; ++j, ++m)
-                A[m] += jc[i] * jc[j] + jc[9 + i] * jc[9 + j]
-                        - (wh[3 * i] * wh[3 * j] + wh[3 * i + 1] * wh[3 * j + 1] + wh[3 * i + 2] * wh[3 * j + 2]);
+            for (int c = r; c < 9; ++c, ++m) A[m] += jc[r] * q0[c] + jc[9 + r] * q1[c];
         }
     }
+    // block reduction of the 63 sums: waves by shuffles, then 4 waves via LDS
+    double tot[63];
 #pragma unroll
-    for (int m = 0; m < 45; ++m) A[m] = wave_sum(A[m]);
+    for (int m = 0; m < 45; ++m) tot[m] = wave_sum(A[m]);
 #pragma unroll
-    for (int m = 0; m < 9; ++m) { du[m] = wave_sum(du[m]); bb[m] = wave_sum(bb[m]); }
-    if (lane == 0) {
-        int m = 0;
+    for (int m = 0; m < 9; ++m) { tot[45 + m] = wave_sum(du[m]); tot[54 + m] = wave_sum(bb[m]); }
+    if (lane == 0)
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            sb[wv][i] = bb[i];
+        for (int m = 0; m < 63; ++m) sred[wv][m] = tot[m];
+    __syncthreads();
+    if (threadIdx.x < 63) {
+        const int m = threadIdx.x;
+        double v = 0.0;
 #pragma unroll
-            for (int j = i; j < 9; ++j, ++m) {
-                const double v = A[m] + (i == j ? lambda * du[i] : 0.0);
-                sS[wv][i * 9 + j] = v;
-                sS[wv][j * 9 + i] = v;
+        for (int w = 0; w < WPB; ++w) v += sred[w][m];
+        sred[0][m] = v;   // wave 0's slot m is only read by this thread
+    }
+    __syncthreads();
+    if (threadIdx.x < 81) {
+        const int i = threadIdx.x / 9, j = threadIdx.x % 9;
+        const int a = i < j ? i : j, b = i < j ? j : i;
+        const int m = a * 9 - a * (a - 1) / 2 + (b - a);   // packed upper-triangle index
+        double v = sred[0][m];
+        if (i == j) v += lambda * sred[0][45 + i];
+        sS[threadIdx.x] = v;
+        blk[(int64_t)row_ptr[row] * 81 + threadIdx.x] = v;
+        if (threadIdx.x < 9) rhs[(int64_t)row * 9 + threadIdx.x] = sred[0][54 + threadIdx.x];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // Cholesky S = L L^T, then L^-1 in place (lower triangle)
+        double* L = sL;
+        bool ok = true;
+        for (int j = 0; j < 9; ++j) {
+            double s = sS[j * 9 + j];
+            for (int q = 0; q < j; ++q) s -= L[j * 9 + q] * L[j * 9 + q];
+            if (!(s > 0.0)) { ok = false; s = 1.0; }
+            const double ljj = sqrt(s);
+            L[j * 9 + j] = ljj;
+            for (int i = j + 1; i < 9; ++i) {
+                double t = sS[i * 9 + j];
+                for (int q = 0; q < j; ++q) t -= L[i * 9 + q] * L[j * 9 + q];
+                L[i * 9 + j] = t / ljj;
+            }
+            for (int i = 0; i < j; ++i) L[i * 9 + j] = 0.0;
+        }
+        if (!ok) flags[1] = 1;
+        for (int j = 0; j < 9; ++j) {
+            L[j * 9 + j] = 1.0 / L[j * 9 + j];
+            for (int i = j + 1; i < 9; ++i) {
+                double t = 0.0;
+                for (int q = j; q < i; ++q) t -= L[i * 9 + q] * L[q * 9 + j];
+                L[i * 9 + j] = t / L[i * 9 + i];
             }
         }
     }
     __syncthreads();
-    if (row < n_rows) {
-        double* out = blk + (int64_t)row_ptr[row] * 81;
-        out[lane] = sS[wv][lane];
-        if (lane < 17) out[64 + lane] = sS[wv][64 + lane];
-        if (lane < 9) rhs[(int64_t)row * 9 + lane] = sb[wv][lane];
-        if (lane == 0) {
-            // Cholesky S = L L^T in sL, then L^-1 in place (lower triangle)
-            double* L = sL[wv];
-            const double* S = sS[wv];
-            bool ok = true;
-            for (int j = 0; j < 9; ++j) {
-                double s = S[j * 9 + j];
-                for (int q = 0; q < j; ++q) s -= L[j * 9 + q] * L[j * 9 + q];
-                if (!(s > 0.0)) { ok = false; s = 1.0; }
-                const double ljj = sqrt(s);
-                L[j * 9 + j] = ljj;
-                for (int i = j + 1; i < 9; ++i) {
-                    double t = S[i * 9 + j];
-                    for (int q = 0; q < j; ++q) t -= L[i * 9 + q] * L[j * 9 + q];
-                    L[i * 9 + j] = t / ljj;
-                }
-                for (int i = 0; i < j; ++i) L[i * 9 + j] = 0.0;
-            }
-            if (!ok) flags[1] = 1;
-            // in-place inverse of the lower-triangular L
-            for (int j = 0; j < 9; ++j) {
-                L[j * 9 + j] = 1.0 / L[j * 9 + j];
-                for (int i = j + 1; i < 9; ++i) {
-                    double t = 0.0;
-                    for (int q = j; q < i; ++q) t -= L[i * 9 + q] * L[q * 9 + j];
-                    L[i * 9 + j] = t / L[i * 9 + i];
-                }
-            }
-        }
-    }
-    __syncthreads();
-    if (row < n_rows) {
+    if (threadIdx.x < 81) {
         // S^-1 = L^-T L^-1: entry (i, j) = sum_{q >= max(i,j)} Li[q][i] Li[q][j]
-        const double* Li = sL[wv];
-        double* M = Minv + (int64_t)row * 81;
-        for (int m = lane; m < 81; m += kWave) {
-            const int i = m / 9, j = m % 9;
-            double t = 0.0;
-            for (int q = (i > j ? i : j); q < 9; ++q) t += Li[q * 9 + i] * Li[q * 9 + j];
-            M[m] = t;
-        }
+        const int i = threadIdx.x / 9, j = threadIdx.x % 9;
+        double t = 0.0;
+        for (int q = (i > j ? i : j); q < 9; ++q) t += sL[q * 9 + i] * sL[q * 9 + j];
+        Minv[(int64_t)row * 81 + threadIdx.x] = t;
     }
 }
 
 // ---------------------------------------------------------------------------
-// back-substitution (Eq. (5)): dx_p = L^-T (lhat - sum_a What_a^T dxc_a)
+// back-substitution (Eq. (5)): dx_p = L^-T (lhat - sum_a K_a^T J_ca dxc_a)
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __restrict__ chunk_ptr,
                                                 const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ obs_row,
-                                                const int32_t* __restrict__ pt_ptr, const T* __restrict__ What,
+                                                const int32_t* __restrict__ pt_ptr, const T* __restrict__ R,
                                                 const double* __restrict__ ptL, const double* __restrict__ dxc,
                                                 double* __restrict__ dxp) {
     __shared__ double sP[WPB][kWave][3];
@@ -349,14 +317,21 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
         const int row = obs_row[k];
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         if (row >= 0) {
-            double wh[27];
-            load_vals<T, 27>(What + (int64_t)k * kWhatStride, wh);
+            double jc[18], K[6];
+            const T* rk = R + (int64_t)k * kRec;
+            load_jc(rk, jc);
+            load6(rk + 18, K);
             const double* dc = dxc + (int64_t)row * 9;
+            double g0 = 0.0, g1 = 0.0;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const double c = dc[i];
-                s0 += wh[3 * i] * c; s1 += wh[3 * i + 1] * c; s2 += wh[3 * i + 2] * c;
+                g0 += jc[i] * c;
+                g1 += jc[9 + i] * c;
             }
+            s0 = K[0] * g0 + K[3] * g1;
+            s1 = K[1] * g0 + K[4] * g1;
+            s2 = K[2] * g0 + K[5] * g1;
         }
         sP[wv][lane][0] = s0; sP[wv][lane][1] = s1; sP[wv][lane][2] = s2;
     }
@@ -376,42 +351,41 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
     }
 }
 
-constexpr int kPairLanes = 16;
-
 }  // namespace
 
 void launch_point(ba_ctx* c, double lambda) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
     if (nb == 0) return;
     if (c->precision == BA_MIXED)
-        k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_ptr,
-                                                 (const float*)c->J, c->e, lambda, (float*)c->What, c->g, c->ptL, c->flags);
+        k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->pt_ptr, (float*)c->R,
+                                                 (const float*)c->Jp, c->e, lambda, c->ptL, c->flags);
     else
-        k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_ptr,
-                                                  (const double*)c->J, c->e, lambda, (double*)c->What, c->g, c->ptL, c->flags);
+        k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->pt_ptr, (double*)c->R,
+                                                  (const double*)c->Jp, c->e, lambda, c->ptL, c->flags);
 }
 
 void launch_offdiag(ba_ctx* c) {
-    constexpr int G = kPairLanes;
-    const int nb = (c->n_offseg + (BS / G) - 1) / (BS / G);
-    if (nb == 0) return;
+    const int n_wg = c->n_seg_wg;
+    if (n_wg == 0) return;
+    const int grid = 8 * ((n_wg + 7) / 8);
     if (c->precision == BA_MIXED)
-        k_offdiag<float, G><<<nb, BS, 0, c->stream>>>(c->n_offseg, c->off_blk, c->pair_ptr, c->trip,
-                                                      (const float*)c->What, c->blk);
+        k_offdiag<float><<<grid, BS, 0, c->stream>>>(c->n_offseg, n_wg, c->off_blk, c->pair_ptr, c->trip,
+                                                     (const float*)c->R, c->blk);
     else
-        k_offdiag<double, G><<<nb, BS, 0, c->stream>>>(c->n_offseg, c->off_blk, c->pair_ptr, c->trip,
-                                                       (const double*)c->What, c->blk);
+        k_offdiag<double><<<grid, BS, 0, c->stream>>>(c->n_offseg, n_wg, c->off_blk, c->pair_ptr, c->trip,
+                                                      (const double*)c->R, c->blk);
 }
 
 void launch_diag(ba_ctx* c, double lambda) {
-    const int nb = (c->n_rows + WPB - 1) / WPB;
-    if (nb == 0) return;
+    if (c->n_rows == 0) return;
     if (c->precision == BA_MIXED)
-        k_diag<float><<<nb, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->row_ptr, (const float*)c->J,
-                                                (const float*)c->What, c->g, lambda, c->blk, c->rhs, c->Minv, c->flags);
+        k_diag<float><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->rowobs_pt, c->row_ptr,
+                                                       (const float*)c->R, c->e, c->ptL, lambda, c->blk, c->rhs,
+                                                       c->Minv, c->flags);
     else
-        k_diag<double><<<nb, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->row_ptr, (const double*)c->J,
-                                                 (const double*)c->What, c->g, lambda, c->blk, c->rhs, c->Minv, c->flags);
+        k_diag<double><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->rowobs_pt, c->row_ptr,
+                                                        (const double*)c->R, c->e, c->ptL, lambda, c->blk, c->rhs,
+                                                        c->Minv, c->flags);
 }
 
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
@@ -419,10 +393,10 @@ void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
     if (nb == 0) return;
     if (c->precision == BA_MIXED)
         k_backsub<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_ptr,
-                                                   (const float*)c->What, c->ptL, dxc, dxp);
+                                                   (const float*)c->R, c->ptL, dxc, dxp);
     else
         k_backsub<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_ptr,
-                                                    (const double*)c->What, c->ptL, dxc, dxp);
+                                                    (const double*)c->R, c->ptL, dxc, dxp);
 }
 
 }  // namespace ba
