@@ -54,10 +54,10 @@ def build_scene(kind):
 
 def pair_stage_bytes(n_pairs, n_offseg, precision):
     """Algorithmic bytes of one camera-pair-stage launch: per observation
-    couple its two index words and the two 9x3 W-hat records, per
+    couple its two index words and the two 24-value records (J_c and K), per
     off-diagonal block its 81 FP64 outputs and its segment bounds."""
     es = 4 if precision == "mixed" else 8
-    return n_pairs * (8 + 2 * 27 * es) + n_offseg * (81 * 8 + 8)
+    return n_pairs * (8 + 2 * 24 * es) + n_offseg * (81 * 8 + 8)
 
 
 def traffic_from_profile(kernel_src_hash, kernel):
