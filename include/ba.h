@@ -146,6 +146,7 @@ typedef struct ba_lm_info {
     int32_t accepted;           /* 1 if the step was taken */
     int32_t stop;               /* 1 if an accepted step lowered F by < 1e-12 relative */
     double ms_linearize, ms_form_rcs, ms_pcg, ms_back_substitute, ms_evaluate, ms_total;
+    double ms_precond;          /* learned preconditioner inference (0 for block-Jacobi) */
 } ba_lm_info;
 
 /* One LM iteration (Eq. (1) solved through Eq. (4)-(7) and (5)): linearize
@@ -189,6 +190,77 @@ ba_status ba_get_jacobians(ba_ctx* ctx, double* J, double* e);
 /* Device time in ms of the stages of the last formation:
  * [0] linearize, [1] point stage, [2] off-diagonal pair stage, [3] diagonal stage. */
 ba_status ba_get_stage_ms(ba_ctx* ctx, double* ms4);
+
+/* ------------------------------------------------------------------------
+ * Learned correction to block-Jacobi (extension of Sec. 3.2's block-diagonal
+ * preconditioner).  A message-passing network over the camera-pair graph of
+ * the RCS (blocks (i, j) non-zero iff cameras share points, Sec. 4) outputs
+ * per camera a lower-triangular Lt_i with exp(.) diagonal; the preconditioner
+ * blocks are P_i = L_i^-T Lt_i Lt_i^T L_i^-1 with S_ii = L_i L_i^T, SPD by
+ * construction, and equal to S_ii^-1 (block-Jacobi) when Lt_i = I.
+ * Parameters: a flat FP32 vector of ba_gnn_param_count() values in the order
+ *   Wn[64][64], bn[64], We[96][64], be[64],
+ *   3 x (M_l[192][64], c_l[64], U_l[128][64], u_l[64]), Wd[64][48], bd[48]
+ * (row-major, y = x W + b).  Node input (64): the 36 strictly-upper entries
+ * of diag(S_ii)^-1/2 S_ii diag(S_ii)^-1/2, then log S_ii[r][r] minus their
+ * mean (9), zero padding.  Edge input i->j (96): L_i^-1 S_ij L_j^-T
+ * row-major (81), zero padding.  Layers: h = relu(x Wn + bn),
+ * g = relu(e We + be); 3 x { m_ij = relu([h_i, h_j, g_ij] M_l + c_l),
+ * a_i = mean_j m_ij, h_i += relu([h_i, a_i] U_l + u_l) }; o = h Wd + bd;
+ * Lt diagonal exp(o[0..8]), strict lower row-major o[9..44].  Dense layers
+ * use bf16 operands with FP32 accumulation.  Loss (training): Hutchinson
+ * estimate of |B A - I|_F^2 / (9 n) with A = blockdiag(L)^-1 S blockdiag(L)^-T,
+ * B = blockdiag(Lt Lt^T) and Rademacher probes.
+ * A ba_gnn runs its work on its stream (NULL = default); a network and the
+ * graphs it is used with must not be used concurrently from two threads.
+ * ------------------------------------------------------------------------ */
+typedef struct ba_gnn ba_gnn;
+typedef struct ba_gnn_graph ba_gnn_graph;
+
+int64_t ba_gnn_param_count(void);
+
+/* Copies params (host FP32, ba_gnn_param_count() values); Adam state zero. */
+ba_status ba_gnn_create(const float* params, void* stream, ba_gnn** out);
+void ba_gnn_destroy(ba_gnn* net);
+/* Replaces the parameters (host FP32) and resets the optimiser state. */
+ba_status ba_gnn_set_params(ba_gnn* net, const float* params);
+/* Host copy of the FP32 master parameters. */
+ba_status ba_gnn_get_params(ba_gnn* net, float* params);
+
+/* Network input of one RCS instance: from the context's last formed RCS
+ * (device work on the context stream), or from host arrays row_ptr
+ * [n_rows+1] (int64), col_idx [n_blk] (diagonal first in each row), blocks
+ * [n_blk][81] FP64.  BA_ERR_NOT_SPD if a diagonal block is not SPD. */
+ba_status ba_gnn_graph_from_ctx(ba_ctx* ctx, ba_gnn_graph** out);
+ba_status ba_gnn_graph_from_host(int32_t n_rows, const int64_t* row_ptr, const int32_t* col_idx,
+                                 const double* blk, ba_gnn_graph** out);
+void ba_gnn_graph_destroy(ba_gnn_graph* graph);
+
+/* Loss and (if grad is not NULL) its gradient (host FP32, param order) for
+ * n_probes Rademacher probes: host probes [n_probes][n_rows][9] (+-1), or
+ * NULL to draw them on the device from seed.  Parameters are unchanged. */
+ba_status ba_gnn_loss_grad(ba_gnn* net, ba_gnn_graph* graph, int32_t n_probes, const float* probes,
+                           uint64_t seed, double* loss, float* grad);
+
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, FP32 master weights) on the mean
+ * gradient over n_graphs graphs, probes drawn from seed; *loss = mean loss
+ * before the step. */
+ba_status ba_gnn_train_step(ba_gnn* net, ba_gnn_graph* const* graphs, int32_t n_graphs, int32_t n_probes,
+                            uint64_t seed, float lr, double* loss);
+
+/* Host copy of the preconditioner blocks P [n_rows][81] for a graph. */
+ba_status ba_gnn_preconditioner(ba_gnn* net, ba_gnn_graph* graph, double* P);
+
+/* Uses net (not copied; must outlive its use) for BA_PRECOND_LEARNED in
+ * ba_pcg_solve and ba_lm_step of ctx: after each formation the network runs
+ * on the RCS on the context stream.  NULL detaches. */
+ba_status ba_set_preconditioner_net(ba_ctx* ctx, ba_gnn* net);
+
+/* C[M][N] = A[M][K] B[K][N] on the device's bf16 matrix cores (FP32
+ * accumulation); host row-major arrays, A and B as bf16 bit patterns. */
+ba_status ba_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, const uint16_t* B, float* C);
+
+const char* ba_gnn_last_error(void);
 
 const char* ba_status_str(ba_status s);
 

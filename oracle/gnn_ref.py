@@ -21,7 +21,7 @@ Features (both sides compute them from the RCS):
       log S_ii[r][r] minus their mean over r.
   directed edge i->j (96, 81 used): A_ij row-major (A_ji = A_ij^T).
 Network (hidden 64): h = relu(x Wn + bn); g = relu(e We + be); three layers
-  m_ij = relu([h_i, h_j, g_ij] M_l + c_l), a_i = sum_j m_ij,
+  m_ij = relu([h_i, h_j, g_ij] M_l + c_l), a_i = mean_j m_ij,
   h_i += relu([h_i, a_i] U_l + u_l); output o = h Wd + bd (48, 45 used):
   o[0..8] -> diagonal exp(o), o[9..44] -> strict lower triangle row-major.
 """
@@ -58,20 +58,22 @@ def flatten(d):
     return np.concatenate([np.asarray(d[name], dtype=np.float64).reshape(-1) for name, _ in PARAM_SHAPES])
 
 
-def init_params(seed=0, zero_decoder=True):
-    """He-style random weights, zero biases; zero decoder => P = block-Jacobi."""
+def init_params(seed=0, zero_decoder=True, decoder_scale=0.05):
+    """Random weights with std 1/sqrt(fan_in) (update layers halved), zero
+    biases; zero decoder => P = block-Jacobi."""
     rng = np.random.default_rng(seed)
     d = {}
     for name, shape in PARAM_SHAPES:
         if len(shape) == 2:
-            d[name] = rng.normal(0.0, np.sqrt(2.0 / shape[0]), size=shape)
+            scale = 0.5 if name[0] == "U" else 1.0
+            d[name] = rng.normal(0.0, scale / np.sqrt(shape[0]), size=shape)
         else:
             d[name] = np.zeros(shape)
     if zero_decoder:
         d["Wd"][:] = 0.0
         d["bd"][:] = 0.0
     else:
-        d["Wd"] *= 0.05
+        d["Wd"] *= decoder_scale
     return flatten(d)
 
 
@@ -175,6 +177,7 @@ def forward(w, feat, bf16=False):
     src, dst = g["src"], g["dst"]
     n = g["n"]
     xn, xe = rd(feat["xn"]), rd(feat["xe"])
+    deg = np.diff(g["ptr"]).astype(np.float64)
     c = dict(xn=xn, xe=xe)
     h = _relu(xn @ P["Wn"] + P["bn"])
     ge = _relu(xe @ P["We"] + P["be"])
@@ -186,6 +189,7 @@ def forward(w, feat, bf16=False):
         m = _relu(xm @ P[f"M{l}"] + P[f"c{l}"])
         a = np.zeros((n, H))
         np.add.at(a, src, m)
+        a /= np.maximum(deg, 1)[:, None]
         xu = np.concatenate([hb, rd(a)], axis=1)
         t = _relu(xu @ P[f"U{l}"] + P[f"u{l}"])
         c[f"xm{l}"], c[f"m{l}"], c[f"xu{l}"], c[f"t{l}"] = xm, m, xu, t
@@ -235,6 +239,7 @@ def backward(w, feat, cache, do, bf16=False):
     src, dst = g["src"], g["dst"]
     n = g["n"]
     grads = {name: np.zeros(shape) for name, shape in PARAM_SHAPES}
+    deg = np.diff(g["ptr"]).astype(np.float64)
     dob = rd(do)
     grads["Wd"] = cache["hL"].T @ dob
     grads["bd"] = do.sum(axis=0)
@@ -249,7 +254,7 @@ def backward(w, feat, cache, do, bf16=False):
         dh = dh + dxu[:, :H]
         da = dxu[:, H:]
         m = cache[f"m{l}"]
-        dm_f = da[src] * (m > 0)
+        dm_f = (da / np.maximum(deg, 1)[:, None])[src] * (m > 0)
         dm = rd(dm_f)
         grads[f"M{l}"] = cache[f"xm{l}"].T @ dm
         grads[f"c{l}"] = dm_f.sum(axis=0)

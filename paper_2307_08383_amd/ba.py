@@ -50,7 +50,7 @@ class LMInfo(C.Structure):
                 ("pcg_iters", C.c_int32), ("pcg_status", C.c_int32), ("accepted", C.c_int32),
                 ("stop", C.c_int32), ("ms_linearize", C.c_double), ("ms_form_rcs", C.c_double),
                 ("ms_pcg", C.c_double), ("ms_back_substitute", C.c_double),
-                ("ms_evaluate", C.c_double), ("ms_total", C.c_double)]
+                ("ms_evaluate", C.c_double), ("ms_total", C.c_double), ("ms_precond", C.c_double)]
 
 
 class Sizes(C.Structure):
@@ -76,6 +76,20 @@ SIGNATURES = {
     "ba_get_stage_ms": (C.c_int, [_vp, _dp]),
     "ba_status_str": (C.c_char_p, [C.c_int]),
     "ba_last_error": (C.c_char_p, [_vp]),
+    "ba_gnn_param_count": (C.c_int64, []),
+    "ba_gnn_create": (C.c_int, [_vp, _vp, C.POINTER(C.c_void_p)]),
+    "ba_gnn_destroy": (None, [_vp]),
+    "ba_gnn_set_params": (C.c_int, [_vp, _vp]),
+    "ba_gnn_get_params": (C.c_int, [_vp, _vp]),
+    "ba_gnn_graph_from_ctx": (C.c_int, [_vp, C.POINTER(C.c_void_p)]),
+    "ba_gnn_graph_from_host": (C.c_int, [C.c_int32, _vp, _vp, _vp, C.POINTER(C.c_void_p)]),
+    "ba_gnn_graph_destroy": (None, [_vp]),
+    "ba_gnn_loss_grad": (C.c_int, [_vp, _vp, C.c_int32, _vp, C.c_uint64, _dp, _vp]),
+    "ba_gnn_train_step": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_uint64, C.c_float, _dp]),
+    "ba_gnn_preconditioner": (C.c_int, [_vp, _vp, _vp]),
+    "ba_set_preconditioner_net": (C.c_int, [_vp, _vp]),
+    "ba_gemm_bf16": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp]),
+    "ba_gnn_last_error": (C.c_char_p, []),
 }
 
 _lib = None
@@ -229,3 +243,99 @@ def ba_last_error(ctx=None):
 
 def new_lm_state(lam=1e-4):
     return LMState(lam=lam, nu=2.0, iter=0, flags=0)
+
+
+# ---------------------------------------------------------------------------
+# learned preconditioner
+# ---------------------------------------------------------------------------
+def _gnn_check(status):
+    if status != BA_OK:
+        raise BAError(status, lib().ba_gnn_last_error().decode())
+    return status
+
+
+def ba_gnn_param_count():
+    return int(lib().ba_gnn_param_count())
+
+
+def ba_gnn_create(params, stream=None):
+    """params: float32 host array of ba_gnn_param_count() values."""
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    assert p.size == ba_gnn_param_count()
+    h = C.c_void_p()
+    st = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _gnn_check(lib().ba_gnn_create(_np_ptr(p), st, C.byref(h)))
+    return h
+
+
+def ba_gnn_destroy(net):
+    if net:
+        lib().ba_gnn_destroy(net)
+
+
+def ba_gnn_set_params(net, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _gnn_check(lib().ba_gnn_set_params(net, _np_ptr(p)))
+
+
+def ba_gnn_get_params(net):
+    out = np.empty(ba_gnn_param_count(), np.float32)
+    _gnn_check(lib().ba_gnn_get_params(net, _np_ptr(out)))
+    return out
+
+
+def ba_gnn_graph_from_ctx(ctx):
+    h = C.c_void_p()
+    _check(lib().ba_gnn_graph_from_ctx(ctx, C.byref(h)), ctx)
+    return h
+
+
+def ba_gnn_graph_from_host(row_ptr, col_idx, blk):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    b = np.ascontiguousarray(blk, dtype=np.float64)
+    h = C.c_void_p()
+    _gnn_check(lib().ba_gnn_graph_from_host(len(rp) - 1, _np_ptr(rp), _np_ptr(ci), _np_ptr(b), C.byref(h)))
+    return h
+
+
+def ba_gnn_graph_destroy(g):
+    if g:
+        lib().ba_gnn_graph_destroy(g)
+
+
+def ba_gnn_loss_grad(net, graph, n_probes=4, probes=None, seed=0, want_grad=True):
+    loss = C.c_double(0.0)
+    pr = None if probes is None else np.ascontiguousarray(probes, dtype=np.float32)
+    grad = np.empty(ba_gnn_param_count(), np.float32) if want_grad else None
+    _gnn_check(lib().ba_gnn_loss_grad(net, graph, n_probes, _np_ptr(pr), seed, C.byref(loss), _np_ptr(grad)))
+    return loss.value, grad
+
+
+def ba_gnn_train_step(net, graphs, n_probes=4, seed=0, lr=1e-3):
+    arr = (C.c_void_p * len(graphs))(*[g.value if isinstance(g, C.c_void_p) else g for g in graphs])
+    loss = C.c_double(0.0)
+    _gnn_check(lib().ba_gnn_train_step(net, arr, len(graphs), n_probes, seed, lr, C.byref(loss)))
+    return loss.value
+
+
+def ba_gnn_preconditioner(net, graph, n_rows):
+    P = np.empty((n_rows, 9, 9))
+    _gnn_check(lib().ba_gnn_preconditioner(net, graph, _np_ptr(P)))
+    return P
+
+
+def ba_set_preconditioner_net(ctx, net):
+    _check(lib().ba_set_preconditioner_net(ctx, net), ctx)
+
+
+def ba_gemm_bf16(A_bits, B_bits):
+    """A_bits [M][K], B_bits [K][N]: uint16 bf16 bit patterns; returns C float32."""
+    A = np.ascontiguousarray(A_bits, dtype=np.uint16)
+    B = np.ascontiguousarray(B_bits, dtype=np.uint16)
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    Cm = np.empty((M, N), np.float32)
+    _gnn_check(lib().ba_gemm_bf16(M, N, K, _np_ptr(A), _np_ptr(B), _np_ptr(Cm)))
+    return Cm

@@ -8,6 +8,7 @@
 #include <cstdlib>
 
 #include "ba_common.hpp"
+#include "gnn.hpp"
 
 namespace ba {
 void launch_spmv(ba_ctx* c, const double* x, double* y);
@@ -64,6 +65,10 @@ void free_ctx(ba_ctx* c) {
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& g : c->pcg_graphs) (void)hipGraphExecDestroy(g.exec);
+    if (c->lgraph) {
+        ba::gnn::free_graph(*(ba::gnn::Graph*)c->lgraph);
+        delete (ba::gnn::Graph*)c->lgraph;
+    }
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     delete c;
 }
@@ -374,9 +379,52 @@ ba_status form_rcs_async(ba_ctx* c, double lambda) {
     return BA_OK;
 }
 
+// network inference on the current RCS -> Mlearn (context stream)
+void prepare_learned(ba_ctx* c) {
+    auto* g = (ba::gnn::Graph*)c->lgraph;
+    ba::gnn::compute_features(*g, c->blk, c->stream);
+    ba::gnn::infer_preconditioner(c->net, *g, c->Minv, c->Mlearn, c->stream);
+}
+
 }  // namespace
 
 extern "C" {
+
+ba_status ba_set_preconditioner_net(ba_ctx* c, ba_gnn* net) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    return guarded(c, [&]() {
+        c->net = net;
+        c->learned_ready = net != nullptr;
+        if (net && !c->Mlearn) dalloc(c, &c->Mlearn, (size_t)c->n_rows * 81);
+        if (net && !c->lgraph && c->n_rows > 0) {
+            auto* g = new ba::gnn::Graph();
+            ba::gnn::build_graph(*g, c->n_rows, c->h_row_ptr.data(), c->h_col_idx.data(), c->stream);
+            c->lgraph = g;
+        }
+        return BA_OK;
+    });
+}
+
+ba_status ba_gnn_graph_from_ctx(ba_ctx* c, ba_gnn_graph** out) {
+    if (!c || !out) return BA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!c->have_rcs) { c->err = "no RCS formed"; return BA_ERR_STATE; }
+    if (c->n_rows == 0) { c->err = "no free cameras"; return BA_ERR_INVALID_ARG; }
+    ba_gnn_graph* G = new ba_gnn_graph();
+    ba_status s = guarded(c, [&]() {
+        ba::gnn::build_graph(G->g, c->n_rows, c->h_row_ptr.data(), c->h_col_idx.data(), c->stream);
+        ba::gnn::compute_features(G->g, c->blk, c->stream);
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        return BA_OK;
+    });
+    if (s != BA_OK) {
+        ba::gnn::free_graph(G->g);
+        delete G;
+        return s;
+    }
+    *out = G;
+    return BA_OK;
+}
 
 const char* ba_status_str(ba_status s) {
     switch (s) {
@@ -514,6 +562,7 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
     return guarded(c, [&]() {
         int it = 0;
         double rr = 0.0;
+        if (pre == BA_PRECOND_LEARNED && c->n_rows > 0) prepare_learned(c);
         BA_HIP_CHECK(hipEventRecord(c->ev[6], c->stream));
         ba_status s = BA_OK;
         if (c->n_rows > 0)
@@ -569,6 +618,8 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         int it = 0;
         double rr = 0.0;
         ba_status ps = BA_OK;
+        BA_HIP_CHECK(hipEventRecord(ev[14], c->stream));
+        if (pre == BA_PRECOND_LEARNED && c->n_rows > 0) prepare_learned(c);
         BA_HIP_CHECK(hipEventRecord(ev[6], c->stream));
         if (c->n_rows > 0)
             ps = ba::run_pcg(c, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, tol, max_iter, nullptr, c->dxc, &it, &rr);
@@ -617,6 +668,7 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         I.ms_back_substitute = elapsed(ev[7], ev[9]);
         I.ms_evaluate = elapsed(ev[9], ev[10]);
         I.ms_total = elapsed(ev[8], ev[11]);
+        I.ms_precond = pre == BA_PRECOND_LEARNED ? elapsed(ev[14], ev[6]) : 0.0;
         if (info) *info = I;
         return BA_OK;
     });

@@ -238,6 +238,8 @@ struct ba_ctx {
     };
     std::vector<PcgGraph> pcg_graphs;
     bool have_lin = false, have_rcs = false, learned_ready = false;
+    ba_gnn* net = nullptr;             // learned preconditioner (not owned)
+    void* lgraph = nullptr;            // its graph of this context's pattern (owned)
     double lambda = 0.0;
     double stage_ms[4] = {0, 0, 0, 0};
 };

@@ -1,0 +1,907 @@
+// Learned correction to block-Jacobi preconditioning of the RCS.
+//
+// A message-passing network over the camera-pair graph (the non-zero blocks
+// of the RCS are the camera pairs with common points, Sec. 4) maps each RCS
+// instance to per-camera lower-triangular factors Lt_i (diagonal exp(.)),
+// giving SPD preconditioner blocks P_i = L_i^-T Lt_i Lt_i^T L_i^-1 with
+// S_ii = L_i L_i^T; a zero decoder gives Lt_i = I, i.e. block-Jacobi exactly.
+// Training minimises the Hutchinson estimate of ||B A - I||_F^2 / (9 n) in
+// the block-Jacobi-normalised space A = L^-1 S L^-T, B = blockdiag(Lt Lt^T).
+//
+// All dense layers run on bf16 MFMA (v_mfma_f32_16x16x32_bf16) with FP32
+// accumulation; weight gradients are split over rows and the partial tiles
+// summed in a fixed order, message aggregation is a segmented sum over a
+// source-sorted directed edge list and its backward walks each edge's twin,
+// so forward, backward and the optimiser are deterministic (no atomics).
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "gnn.hpp"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace ba {
+namespace gnn {
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int KSPLIT_ROWS = 2048;     // rows per weight-gradient partial
+
+inline int nblk(int64_t n, int b = BS) { return (int)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// GEMM: C[M][N] = sum_k A(m,k) B(k,n) (+ bias[n]) (relu), with
+// A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] in bf16, FP32
+// accumulation.  One block computes a 64 x 64 tile over the K range
+// [z*kchunk, min(K, (z+1)*kchunk)) and writes it at C + z*zstride.
+// Lane layout of v_mfma_f32_16x16x32_bf16: lane l holds A row l%16 and
+// B column l%16 for k = 8*(l/16) .. +7; the result lane holds column l%16,
+// rows 4*(l/16) .. +3.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_gemm(int M, int N, int K, int kchunk, const __bf16* __restrict__ A,
+                                             int64_t sam, int64_t sak, const __bf16* __restrict__ B, int64_t sbk,
+                                             int64_t sbn, const float* __restrict__ bias, int relu,
+                                             float* __restrict__ C, int64_t ldc, int64_t zstride,
+                                             __bf16* __restrict__ Cb, int64_t ldcb) {
+    __shared__ __bf16 sA[64][40];
+    __shared__ __bf16 sB[32][72];
+    const int tid = threadIdx.x, w = tid / kWave, l = tid % kWave;
+    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    const int k0 = blockIdx.z * kchunk, k1 = min(K, k0 + kchunk);
+    f32x4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const __bf16 zero = (__bf16)0.0f;
+    for (int kb = k0; kb < k1; kb += 32) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int idx = tid + BS * t;
+            const int r = idx / 32, c = idx % 32;
+            const int m = m0 + r, k = kb + c;
+            sA[r][c] = (m < M && k < k1) ? A[(int64_t)m * sam + (int64_t)k * sak] : zero;
+            const int rb = idx / 64, cb = idx % 64;
+            const int kk = kb + rb, nn = n0 + cb;
+            sB[rb][cb] = (kk < k1 && nn < N) ? B[(int64_t)kk * sbk + (int64_t)nn * sbn] : zero;
+        }
+        __syncthreads();
+        bf16x8 a;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = sA[16 * w + l % 16][8 * (l / 16) + j];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            bf16x8 b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b[j] = sB[8 * (l / 16) + j][16 * nt + l % 16];
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    float* Cz = C + (int64_t)blockIdx.z * zstride;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + 16 * w + 4 * (l / 16) + i;
+            const int n = n0 + 16 * nt + l % 16;
+            if (m < M && n < N) {
+                float v = acc[nt][i];
+                if (bias) v += bias[n];
+                if (relu) v = v > 0.f ? v : 0.f;
+                Cz[(int64_t)m * ldc + n] = v;
+                if (Cb) Cb[(int64_t)m * ldcb + n] = (__bf16)v;
+            }
+        }
+}
+
+// out[i] = sum_z part[z][i] in order z = 0, 1, ...
+__global__ __launch_bounds__(BS) void k_sum_split(int64_t n, int nz, const float* __restrict__ part,
+                                                  float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int z = 0; z < nz; ++z) s += part[(int64_t)z * n + i];
+    out[i] = s;
+}
+
+// column sums of a row-major [rows][cols] FP32 matrix, first per chunk of
+// 1024 rows (partial[chunk][col]), then over chunks in order
+__global__ __launch_bounds__(BS) void k_colsum_part(int rows, int cols, const float* __restrict__ src, int64_t ld,
+                                                    float* __restrict__ part) {
+    const int c = threadIdx.x;
+    if (c >= cols) return;
+    const int r0 = blockIdx.x * 1024, r1 = min(rows, r0 + 1024);
+    float s = 0.f;
+    for (int r = r0; r < r1; ++r) s += src[(int64_t)r * ld + c];
+    part[(int64_t)blockIdx.x * cols + c] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_colsum_fin(int nchunk, int cols, const float* __restrict__ part,
+                                                   float* __restrict__ out) {
+    const int c = threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int z = 0; z < nchunk; ++z) s += part[(int64_t)z * cols + c];
+    out[c] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_to_bf16(int64_t n, const float* __restrict__ src, __bf16* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i < n) dst[i] = (__bf16)src[i];
+}
+
+// ---------------------------------------------------------------------------
+// features
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_feat_node(int n, const int32_t* __restrict__ diag_blk,
+                                                  const double* __restrict__ blk, double* __restrict__ Linv,
+                                                  __bf16* __restrict__ xn, int* __restrict__ flags) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= n) return;
+    const double* S = blk + (int64_t)diag_blk[i] * 81;
+    double L[81];
+    for (int q = 0; q < 81; ++q) L[q] = 0.0;
+    bool ok = true;
+    for (int j = 0; j < 9; ++j) {
+        double s = S[j * 9 + j];
+        for (int q = 0; q < j; ++q) s -= L[j * 9 + q] * L[j * 9 + q];
+        if (!(s > 0.0)) { ok = false; s = 1.0; }
+        L[j * 9 + j] = sqrt(s);
+        for (int r = j + 1; r < 9; ++r) {
+            double t = S[r * 9 + j];
+            for (int q = 0; q < j; ++q) t -= L[r * 9 + q] * L[j * 9 + q];
+            L[r * 9 + j] = t / L[j * 9 + j];
+        }
+    }
+    if (!ok) flags[0] = 1;
+    // lower-triangular inverse in place
+    for (int j = 0; j < 9; ++j) {
+        L[j * 9 + j] = 1.0 / L[j * 9 + j];
+        for (int r = j + 1; r < 9; ++r) {
+            double t = 0.0;
+            for (int q = j; q < r; ++q) t -= L[r * 9 + q] * L[q * 9 + j];
+            L[r * 9 + j] = t / L[r * 9 + r];
+        }
+    }
+    for (int q = 0; q < 81; ++q) Linv[(int64_t)i * 81 + q] = L[q];
+    double d[9], ld[9], mean = 0.0;
+    for (int r = 0; r < 9; ++r) {
+        d[r] = 1.0 / sqrt(S[r * 9 + r]);
+        ld[r] = log(S[r * 9 + r]);
+        mean += ld[r];
+    }
+    mean /= 9.0;
+    __bf16* x = xn + (int64_t)i * F_NODE;
+    int q = 0;
+    for (int r = 0; r < 9; ++r)
+        for (int c = r + 1; c < 9; ++c, ++q) x[q] = (__bf16)(S[r * 9 + c] * d[r] * d[c]);
+    for (int r = 0; r < 9; ++r) x[36 + r] = (__bf16)(ld[r] - mean);
+    for (int r = 45; r < F_NODE; ++r) x[r] = (__bf16)0.0f;
+}
+
+__global__ __launch_bounds__(64) void k_feat_edge(int E, const int32_t* __restrict__ esrc, const int32_t* __restrict__ edst,
+                                                  const int32_t* __restrict__ eblk, const int32_t* __restrict__ etr,
+                                                  const double* __restrict__ blk, const double* __restrict__ Linv,
+                                                  float* __restrict__ A, __bf16* __restrict__ xe) {
+    const int e = blockIdx.x * 64 + threadIdx.x;
+    if (e >= E) return;
+    const double* S = blk + (int64_t)eblk[e] * 81;
+    const bool tr = etr[e] != 0;
+    const double* Li = Linv + (int64_t)esrc[e] * 81;
+    const double* Lj = Linv + (int64_t)edst[e] * 81;
+    // T = S_ij Lj^T (S_ij = tr ? S^T : S); A = Li T
+    double T[81];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) {
+            double t = 0.0;
+            for (int q = 0; q <= c; ++q) t += (tr ? S[q * 9 + r] : S[r * 9 + q]) * Lj[c * 9 + q];
+            T[r * 9 + c] = t;
+        }
+    float* Ae = A + (int64_t)e * 81;
+    __bf16* x = xe + (int64_t)e * F_EDGE;
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) {
+            double t = 0.0;
+            for (int q = 0; q <= r; ++q) t += Li[r * 9 + q] * T[q * 9 + c];
+            Ae[r * 9 + c] = (float)t;
+            x[r * 9 + c] = (__bf16)t;
+        }
+    for (int r = 81; r < F_EDGE; ++r) x[r] = (__bf16)0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// message passing pieces
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BS) void k_gather_msg(int E, const int32_t* __restrict__ esrc, const int32_t* __restrict__ edst,
+                                                   const __bf16* __restrict__ Hb, const __bf16* __restrict__ Gb,
+                                                   __bf16* __restrict__ Xm) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= (int64_t)E * 3 * H) return;
+    const int e = (int)(t / (3 * H)), f = (int)(t % (3 * H));
+    __bf16 v;
+    if (f < H) v = Hb[(int64_t)esrc[e] * H + f];
+    else if (f < 2 * H) v = Hb[(int64_t)edst[e] * H + f - H];
+    else v = Gb[(int64_t)e * H + f - 2 * H];
+    Xm[t] = v;
+}
+
+// Xu[i] = [Hb[i], mean over the edges leaving i of Mm]
+__global__ __launch_bounds__(BS) void k_aggregate(int n, const int32_t* __restrict__ eptr, const float* __restrict__ Mm,
+                                                  const __bf16* __restrict__ Hb, __bf16* __restrict__ Xu) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= (int64_t)n * H) return;
+    const int i = (int)(t / H), f = (int)(t % H);
+    float s = 0.f;
+    for (int e = eptr[i]; e < eptr[i + 1]; ++e) s += Mm[(int64_t)e * H + f];
+    const int deg = eptr[i + 1] - eptr[i];
+    if (deg > 0) s /= (float)deg;
+    Xu[(int64_t)i * 2 * H + f] = Hb[(int64_t)i * H + f];
+    Xu[(int64_t)i * 2 * H + H + f] = (__bf16)s;
+}
+
+__global__ __launch_bounds__(BS) void k_residual(int64_t n, float* __restrict__ Hf, const float* __restrict__ T,
+                                                 __bf16* __restrict__ Hb) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const float v = Hf[i] + T[i];
+    Hf[i] = v;
+    Hb[i] = (__bf16)v;
+}
+
+// Rademacher probes from a counter-based hash (splitmix64 finaliser)
+__global__ __launch_bounds__(BS) void k_probes(int64_t n, unsigned long long seed, float* __restrict__ Z) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    unsigned long long x = seed + 0x9E3779B97F4A7C15ull * (unsigned long long)(i + 1);
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    Z[i] = (x & 1ull) ? 1.f : -1.f;
+}
+
+// Y[p][i] = Z[p][i] + sum_{e leaving i} A_e Z[p][dst(e)]
+__global__ __launch_bounds__(BS) void k_normprod(int n, int P, const int32_t* __restrict__ eptr,
+                                                 const int32_t* __restrict__ edst, const float* __restrict__ A,
+                                                 const float* __restrict__ Z, float* __restrict__ Y) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= (int64_t)n * P * 9) return;
+    const int c = (int)(t % 9);
+    const int i = (int)((t / 9) % n);
+    const int p = (int)(t / (9 * (int64_t)n));
+    const float* Zp = Z + (int64_t)p * n * 9;
+    float s = Zp[(int64_t)i * 9 + c];
+    for (int e = eptr[i]; e < eptr[i + 1]; ++e) {
+        const float* Ae = A + (int64_t)e * 81 + c * 9;
+        const float* zj = Zp + (int64_t)edst[e] * 9;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s += Ae[q] * zj[q];
+    }
+    Y[t] = s;
+}
+
+// lower-triangular factor from a decoder row: diagonal exp(o[r]), strict
+// lower part row-major from o[9 ..]
+__device__ __forceinline__ void factor_from_out(const float* o, float* Lt) {
+    int q = 9;
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) {
+            if (c < r) Lt[r * 9 + c] = o[q++];
+            else if (c == r) Lt[r * 9 + c] = expf(o[r]);
+            else Lt[r * 9 + c] = 0.f;
+        }
+}
+
+// per node: loss_i = sum_p |B y - z|^2 (scaled) and d loss / d o
+__global__ __launch_bounds__(64) void k_loss(int n, int P, float scale, const float* __restrict__ O,
+                                             const float* __restrict__ Y, const float* __restrict__ Z,
+                                             float* __restrict__ dO, float* __restrict__ lpart) {
+    __shared__ float red[64];
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    float li = 0.f;
+    if (i < n) {
+        float Lt[81], B[81], Gs[81];
+        factor_from_out(O + (int64_t)i * F_OUT, Lt);
+        for (int r = 0; r < 9; ++r)
+            for (int c = 0; c < 9; ++c) {
+                float s = 0.f;
+                for (int q = 0; q <= (r < c ? r : c); ++q) s += Lt[r * 9 + q] * Lt[c * 9 + q];
+                B[r * 9 + c] = s;
+                Gs[r * 9 + c] = 0.f;
+            }
+        for (int p = 0; p < P; ++p) {
+            const float* y = Y + ((int64_t)p * n + i) * 9;
+            const float* z = Z + ((int64_t)p * n + i) * 9;
+            float res[9];
+            for (int r = 0; r < 9; ++r) {
+                float s = -z[r];
+                for (int c = 0; c < 9; ++c) s += B[r * 9 + c] * y[c];
+                res[r] = s;
+                li += s * s;
+            }
+            for (int r = 0; r < 9; ++r)
+                for (int c = 0; c < 9; ++c) Gs[r * 9 + c] += 2.f * scale * res[r] * y[c];
+        }
+        li *= scale;
+        // dLt = (G + G^T) Lt
+        float* d = dO + (int64_t)i * F_OUT;
+        int q = 9;
+        for (int r = 0; r < 9; ++r)
+            for (int c = 0; c <= r; ++c) {
+                float s = 0.f;
+                for (int k = c; k < 9; ++k) s += (Gs[r * 9 + k] + Gs[k * 9 + r]) * Lt[k * 9 + c];
+                if (c == r) d[r] = s * Lt[r * 9 + r];
+                else d[q++] = s;
+            }
+        for (int r = 45; r < F_OUT; ++r) d[r] = 0.f;
+    }
+    red[threadIdx.x] = li;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float s = 0.f;
+        for (int t = 0; t < 64; ++t) s += red[t];
+        lpart[blockIdx.x] = s;
+    }
+}
+
+__global__ void k_loss_fin(int nb, const float* __restrict__ lpart, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += lpart[b];
+    out[0] = s;
+}
+
+// dX = dY * (Y > 0) in FP32 and bf16
+__global__ __launch_bounds__(BS) void k_relu_back(int64_t n, const float* __restrict__ dY, const float* __restrict__ Y,
+                                                  int64_t ldy, int cols, int64_t lddy, float* __restrict__ out,
+                                                  __bf16* __restrict__ outb) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= n) return;
+    const int64_t r = t / cols, c = t % cols;
+    const float v = Y[r * ldy + c] > 0.f ? dY[r * lddy + c] : 0.f;
+    out[t] = v;
+    outb[t] = (__bf16)v;
+}
+
+// dMm[e] = dXu[src(e)][64 + f] / deg(src(e)) * (Mm[e] > 0)
+__global__ __launch_bounds__(BS) void k_msg_back(int E, const int32_t* __restrict__ esrc, const int32_t* __restrict__ eptr,
+                                                 const float* __restrict__ dXu, const float* __restrict__ Mm,
+                                                 float* __restrict__ dMm, __bf16* __restrict__ dMmb) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= (int64_t)E * H) return;
+    const int e = (int)(t / H), f = (int)(t % H);
+    const int s = esrc[e];
+    const float v = Mm[t] > 0.f ? dXu[(int64_t)s * 2 * H + H + f] / (float)(eptr[s + 1] - eptr[s]) : 0.f;
+    dMm[t] = v;
+    dMmb[t] = (__bf16)v;
+}
+
+// dH[i] += dXu[i][0:64] + sum_{e leaving i} (dXm[e][0:64] + dXm[twin(e)][64:128]);
+// dG[e] += dXm[e][128:192]
+__global__ __launch_bounds__(BS) void k_msg_scatter(int n, const int32_t* __restrict__ eptr,
+                                                    const int32_t* __restrict__ etwin, const float* __restrict__ dXu,
+                                                    const float* __restrict__ dXm, float* __restrict__ dH) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= (int64_t)n * H) return;
+    const int i = (int)(t / H), f = (int)(t % H);
+    float s = dH[t] + dXu[(int64_t)i * 2 * H + f];
+    for (int e = eptr[i]; e < eptr[i + 1]; ++e)
+        s += dXm[(int64_t)e * 3 * H + f] + dXm[(int64_t)etwin[e] * 3 * H + H + f];
+    dH[t] = s;
+}
+
+__global__ __launch_bounds__(BS) void k_edge_grad(int64_t n, const float* __restrict__ dXm, float* __restrict__ dG,
+                                                  int first) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= n) return;
+    const int64_t e = t / H, f = t % H;
+    const float v = dXm[e * 3 * H + 2 * H + f];
+    dG[t] = first ? v : dG[t] + v;
+}
+
+__global__ __launch_bounds__(BS) void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m,
+                                             float* __restrict__ v, const float* __restrict__ g, float lr, float b1,
+                                             float b2, float eps, float bc1, float bc2, __bf16* __restrict__ wb) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[i] = wi;
+    wb[i] = (__bf16)wi;
+}
+
+__global__ __launch_bounds__(BS) void k_accum(int64_t n, const float* __restrict__ g, float* __restrict__ acc, int first,
+                                              float scale) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= n) return;
+    acc[i] = first ? scale * g[i] : acc[i] + scale * g[i];
+}
+
+// P_i = Linv_i^T (Lt Lt^T) Linv_i, written as Minv_i + Linv_i^T (Lt Lt^T - I)
+// Linv_i when the block-Jacobi inverse Minv is given, so that a zero
+// correction reproduces it exactly
+__global__ __launch_bounds__(64) void k_assemble(int n, const float* __restrict__ O, const double* __restrict__ Linv,
+                                                 const double* __restrict__ Minv, double* __restrict__ P) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= n) return;
+    float Ltf[81];
+    factor_from_out(O + (int64_t)i * F_OUT, Ltf);
+    const double* Li = Linv + (int64_t)i * 81;
+    // D = Lt Lt^T (minus I with a base), T = D Li, P = base + Li^T T
+    double D[81];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 9; ++k) s += (double)Ltf[r * 9 + k] * (double)Ltf[c * 9 + k];
+            D[r * 9 + c] = (Minv && r == c) ? s - 1.0 : s;
+        }
+    double Tm[81];
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 9; ++k) s += D[r * 9 + k] * Li[k * 9 + c];
+            Tm[r * 9 + c] = s;
+        }
+    for (int r = 0; r < 9; ++r)
+        for (int c = 0; c < 9; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 9; ++k) s += Li[k * 9 + r] * Tm[k * 9 + c];
+            P[(int64_t)i * 81 + r * 9 + c] = Minv ? Minv[(int64_t)i * 81 + r * 9 + c] + s : s;
+        }
+}
+
+template <typename T>
+void grow(T** p, size_t n) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    BA_HIP_CHECK(hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T)));
+}
+
+void ensure_work(Work& W, int n, int E, int P) {
+    if (n <= W.cap_n && E <= W.cap_E && P <= W.cap_p) return;
+    n = std::max(n, W.cap_n);
+    E = std::max(E, W.cap_E);
+    P = std::max(P, std::max(W.cap_p, 4));
+    const size_t nh = (size_t)n * H, eh = (size_t)E * H;
+    grow(&W.H0, nh); grow(&W.Hf, nh); grow(&W.G, eh); grow(&W.O, (size_t)n * F_OUT);
+    grow(&W.Z, (size_t)P * n * 9); grow(&W.Y, (size_t)P * n * 9);
+    grow(&W.Hb, 4 * nh); grow(&W.Gb, eh);
+    grow(&W.Xm, (size_t)N_LAYERS * 3 * eh); grow(&W.Xu, (size_t)N_LAYERS * 2 * nh);
+    grow(&W.Mm, (size_t)N_LAYERS * eh); grow(&W.T, (size_t)N_LAYERS * nh);
+    grow(&W.dO, (size_t)n * F_OUT); grow(&W.dH, nh); grow(&W.dT, nh); grow(&W.dXu, 2 * nh);
+    grow(&W.dMm, eh); grow(&W.dXm, 3 * eh); grow(&W.dG, eh);
+    grow(&W.dOb, (size_t)n * F_OUT); grow(&W.dTb, nh); grow(&W.dMmb, eh);
+    const size_t big = std::max(nh, eh);
+    grow(&W.dP, big); grow(&W.dPb, big);
+    const size_t rows = std::max(n, E);
+    const size_t nsplit = (rows + KSPLIT_ROWS - 1) / KSPLIT_ROWS;
+    grow(&W.split, nsplit * 3 * H * H);
+    grow(&W.colpart, ((rows + 1023) / 1024) * 3 * H);
+    grow(&W.loss_part, (size_t)n / 64 + 2);
+    grow(&W.loss, 2);
+    W.cap_n = n; W.cap_E = E; W.cap_p = P;
+}
+
+void gemm(hipStream_t st, int M, int N, int K, const __bf16* A, int64_t sam, int64_t sak, const __bf16* B,
+          int64_t sbk, int64_t sbn, const float* bias, bool relu, float* C, int64_t ldc, __bf16* Cb, int64_t ldcb) {
+    if (M == 0) return;
+    dim3 grid(nblk(M, 64), nblk(N, 64), 1);
+    k_gemm<<<grid, BS, 0, st>>>(M, N, K, K, A, sam, sak, B, sbk, sbn, bias, relu ? 1 : 0, C, ldc, 0, Cb, ldcb);
+}
+
+// dW[Kin][Nout] = X^T dY over `rows` rows (X: [rows][ldx] bf16, dY: [rows][ldy] bf16)
+void wgrad(hipStream_t st, Work& W, int Kin, int Nout, int rows, const __bf16* X, int64_t ldx, const __bf16* dY,
+           int64_t ldy, float* dW) {
+    const int nz = std::max(1, (rows + KSPLIT_ROWS - 1) / KSPLIT_ROWS);
+    dim3 grid(nblk(Kin, 64), nblk(Nout, 64), nz);
+    k_gemm<<<grid, BS, 0, st>>>(Kin, Nout, rows, KSPLIT_ROWS, X, 1, ldx, dY, ldy, 1, nullptr, 0, W.split, Nout,
+                                (int64_t)Kin * Nout, nullptr, 0);
+    const int64_t n = (int64_t)Kin * Nout;
+    k_sum_split<<<nblk(n), BS, 0, st>>>(n, nz, W.split, dW);
+}
+
+void colsum(hipStream_t st, Work& W, int rows, int cols, const float* src, int64_t ld, float* out) {
+    const int nc = std::max(1, (rows + 1023) / 1024);
+    k_colsum_part<<<nc, BS, 0, st>>>(rows, cols, src, ld, W.colpart);
+    k_colsum_fin<<<1, BS, 0, st>>>(nc, cols, W.colpart, out);
+}
+
+void forward(ba_gnn* net, Graph& g, hipStream_t st) {
+    Work& W = net->work;
+    const int n = g.n, E = g.E;
+    const __bf16* wb = net->wb;
+    const float* w = net->w;
+    const int64_t nh = (int64_t)n * H, eh = (int64_t)E * H;
+    gemm(st, n, H, F_NODE, g.xn, F_NODE, 1, wb + OFF_WN, H, 1, w + OFF_BN, true, W.H0, H, W.Hb, H);
+    BA_HIP_CHECK(hipMemcpyAsync(W.Hf, W.H0, nh * sizeof(float), hipMemcpyDeviceToDevice, st));
+    if (E > 0) gemm(st, E, H, F_EDGE, g.xe, F_EDGE, 1, wb + OFF_WE, H, 1, w + OFF_BE, true, W.G, H, W.Gb, H);
+    for (int l = 0; l < N_LAYERS; ++l) {
+        __bf16* Hb = W.Hb + l * nh;
+        __bf16* Xm = W.Xm + (int64_t)l * 3 * eh;
+        __bf16* Xu = W.Xu + (int64_t)l * 2 * nh;
+        float* Mm = W.Mm + (int64_t)l * eh;
+        float* T = W.T + (int64_t)l * nh;
+        if (E > 0) {
+            k_gather_msg<<<nblk(3 * eh), BS, 0, st>>>(E, g.esrc, g.edst, Hb, W.Gb, Xm);
+            gemm(st, E, H, 3 * H, Xm, 3 * H, 1, wb + off_M(l), H, 1, w + off_c(l), true, Mm, H, nullptr, 0);
+        }
+        k_aggregate<<<nblk(nh), BS, 0, st>>>(n, g.eptr, Mm, Hb, Xu);
+        gemm(st, n, H, 2 * H, Xu, 2 * H, 1, wb + off_U(l), H, 1, w + off_u(l), true, T, H, nullptr, 0);
+        k_residual<<<nblk(nh), BS, 0, st>>>(nh, W.Hf, T, W.Hb + (l + 1) * nh);
+    }
+    gemm(st, n, F_OUT, H, W.Hb + N_LAYERS * nh, H, 1, wb + OFF_WD, F_OUT, 1, w + OFF_BD, false, W.O, F_OUT, nullptr, 0);
+}
+
+// loss for probes already in W.Z: Y = A Z, loss and dO
+void loss(ba_gnn* net, Graph& g, int P, hipStream_t st) {
+    Work& W = net->work;
+    const int n = g.n;
+    k_normprod<<<nblk((int64_t)n * P * 9), BS, 0, st>>>(n, P, g.eptr, g.edst, g.A, W.Z, W.Y);
+    const float scale = 1.f / (float)(P * 9 * (int64_t)n);
+    const int nb = nblk(n, 64);
+    k_loss<<<nb, 64, 0, st>>>(n, P, scale, W.O, W.Y, W.Z, W.dO, W.loss_part);
+    k_loss_fin<<<1, 64, 0, st>>>(nb, W.loss_part, W.loss);
+}
+
+void backward(ba_gnn* net, Graph& g, float* grad, hipStream_t st) {
+    Work& W = net->work;
+    const int n = g.n, E = g.E;
+    const __bf16* wb = net->wb;
+    const int64_t nh = (int64_t)n * H, eh = (int64_t)E * H;
+    // decoder
+    k_to_bf16<<<nblk((int64_t)n * F_OUT), BS, 0, st>>>((int64_t)n * F_OUT, W.dO, W.dOb);
+    wgrad(st, W, H, F_OUT, n, W.Hb + N_LAYERS * nh, H, W.dOb, F_OUT, grad + OFF_WD);
+    colsum(st, W, n, F_OUT, W.dO, F_OUT, grad + OFF_BD);
+    // dH = dO Wd^T   (B(k=o, n=h) = Wd[h][o])
+    gemm(st, n, H, F_OUT, W.dOb, F_OUT, 1, wb + OFF_WD, 1, F_OUT, nullptr, false, W.dH, H, nullptr, 0);
+    for (int l = N_LAYERS - 1; l >= 0; --l) {
+        const __bf16* Xm = W.Xm + (int64_t)l * 3 * eh;
+        const __bf16* Xu = W.Xu + (int64_t)l * 2 * nh;
+        const float* Mm = W.Mm + (int64_t)l * eh;
+        const float* T = W.T + (int64_t)l * nh;
+        k_relu_back<<<nblk(nh), BS, 0, st>>>(nh, W.dH, T, H, H, H, W.dT, W.dTb);
+        wgrad(st, W, 2 * H, H, n, Xu, 2 * H, W.dTb, H, grad + off_U(l));
+        colsum(st, W, n, H, W.dT, H, grad + off_u(l));
+        gemm(st, n, 2 * H, H, W.dTb, H, 1, wb + off_U(l), 1, H, nullptr, false, W.dXu, 2 * H, nullptr, 0);
+        if (E > 0) {
+            k_msg_back<<<nblk(eh), BS, 0, st>>>(E, g.esrc, g.eptr, W.dXu, Mm, W.dMm, W.dMmb);
+            wgrad(st, W, 3 * H, H, E, Xm, 3 * H, W.dMmb, H, grad + off_M(l));
+            colsum(st, W, E, H, W.dMm, H, grad + off_c(l));
+            gemm(st, E, 3 * H, H, W.dMmb, H, 1, wb + off_M(l), 1, H, nullptr, false, W.dXm, 3 * H, nullptr, 0);
+            k_edge_grad<<<nblk(eh), BS, 0, st>>>(eh, W.dXm, W.dG, l == N_LAYERS - 1);
+        } else {
+            BA_HIP_CHECK(hipMemsetAsync(grad + off_M(l), 0, (3 * H * H + H) * sizeof(float), st));
+        }
+        k_msg_scatter<<<nblk(nh), BS, 0, st>>>(n, g.eptr, g.etwin, W.dXu, W.dXm, W.dH);
+    }
+    // encoders
+    k_relu_back<<<nblk(nh), BS, 0, st>>>(nh, W.dH, W.H0, H, H, H, W.dP, W.dPb);
+    wgrad(st, W, F_NODE, H, n, g.xn, F_NODE, W.dPb, H, grad + OFF_WN);
+    colsum(st, W, n, H, W.dP, H, grad + OFF_BN);
+    if (E > 0) {
+        k_relu_back<<<nblk(eh), BS, 0, st>>>(eh, W.dG, W.G, H, H, H, W.dP, W.dPb);
+        wgrad(st, W, F_EDGE, H, E, g.xe, F_EDGE, W.dPb, H, grad + OFF_WE);
+        colsum(st, W, E, H, W.dP, H, grad + OFF_BE);
+    } else {
+        BA_HIP_CHECK(hipMemsetAsync(grad + OFF_WE, 0, (F_EDGE * H + H) * sizeof(float), st));
+    }
+}
+
+}  // namespace
+
+void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx, hipStream_t st) {
+    struct Ed { int32_t s, d, b, t; };
+    std::vector<Ed> ed;
+    std::vector<int32_t> diag(n);
+    for (int r = 0; r < n; ++r) {
+        diag[r] = (int32_t)row_ptr[r];
+        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+            const int32_t s = col_idx[k];
+            if (s == r) continue;
+            ed.push_back({r, s, (int32_t)k, 0});
+            ed.push_back({s, r, (int32_t)k, 1});
+        }
+    }
+    std::sort(ed.begin(), ed.end(), [](const Ed& a, const Ed& b) { return a.s != b.s ? a.s < b.s : a.d < b.d; });
+    const int E = (int)ed.size();
+    std::vector<int32_t> eptr(n + 1, 0), src(E), dst(E), eb(E), et(E), twin(E);
+    for (int e = 0; e < E; ++e) {
+        src[e] = ed[e].s; dst[e] = ed[e].d; eb[e] = ed[e].b; et[e] = ed[e].t;
+        eptr[ed[e].s + 1]++;
+    }
+    for (int r = 0; r < n; ++r) eptr[r + 1] += eptr[r];
+    for (int e = 0; e < E; ++e) {   // twin: the edge dst -> src, found in dst's sorted list
+        const int32_t a = dst[e], b = src[e];
+        const auto first = dst.begin() + eptr[a], last = dst.begin() + eptr[a + 1];
+        twin[e] = (int32_t)(std::lower_bound(first, last, b) - dst.begin());
+    }
+    g.n = n;
+    g.E = E;
+    auto up = [&](int32_t** p, const std::vector<int32_t>& h) {
+        BA_HIP_CHECK(hipMalloc((void**)p, std::max<size_t>(h.size(), 1) * sizeof(int32_t)));
+        if (!h.empty()) BA_HIP_CHECK(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        g.bytes += h.size() * sizeof(int32_t);
+    };
+    up(&g.eptr, eptr); up(&g.esrc, src); up(&g.edst, dst); up(&g.etwin, twin); up(&g.eblk, eb); up(&g.etr, et);
+    up(&g.diag_blk, diag);
+    BA_HIP_CHECK(hipMalloc((void**)&g.xn, (size_t)std::max(n, 1) * F_NODE * sizeof(__bf16)));
+    BA_HIP_CHECK(hipMalloc((void**)&g.xe, (size_t)std::max(E, 1) * F_EDGE * sizeof(__bf16)));
+    BA_HIP_CHECK(hipMalloc((void**)&g.A, (size_t)std::max(E, 1) * 81 * sizeof(float)));
+    BA_HIP_CHECK(hipMalloc((void**)&g.Linv, (size_t)std::max(n, 1) * 81 * sizeof(double)));
+    BA_HIP_CHECK(hipMalloc((void**)&g.flags, 4 * sizeof(int)));
+    g.bytes += (size_t)n * (F_NODE * 2 + 81 * 8) + (size_t)E * (F_EDGE * 2 + 81 * 4);
+    BA_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void free_graph(Graph& g) {
+    void* p[] = {g.eptr, g.esrc, g.edst, g.etwin, g.eblk, g.etr, g.diag_blk, g.xn, g.xe, g.A, g.Linv, g.flags};
+    for (void* q : p)
+        if (q) (void)hipFree(q);
+    g = Graph();
+}
+
+void compute_features(Graph& g, const double* blk, hipStream_t st) {
+    BA_HIP_CHECK(hipMemsetAsync(g.flags, 0, 4 * sizeof(int), st));
+    if (g.n > 0) k_feat_node<<<nblk(g.n, 64), 64, 0, st>>>(g.n, g.diag_blk, blk, g.Linv, g.xn, g.flags);
+    if (g.E > 0)
+        k_feat_edge<<<nblk(g.E, 64), 64, 0, st>>>(g.E, g.esrc, g.edst, g.eblk, g.etr, blk, g.Linv, g.A, g.xe);
+    BA_HIP_CHECK(hipGetLastError());
+}
+
+void infer_preconditioner(ba_gnn* net, Graph& g, const double* Minv, double* P, hipStream_t st) {
+    ensure_work(net->work, g.n, g.E, 1);
+    forward(net, g, st);
+    k_assemble<<<nblk(g.n, 64), 64, 0, st>>>(g.n, net->work.O, g.Linv, Minv, P);
+    BA_HIP_CHECK(hipGetLastError());
+}
+
+void free_work(Work& W) {
+    void* p[] = {W.H0, W.Hf, W.G, W.O, W.Z, W.Y, W.Hb, W.Gb, W.Xm, W.Xu, W.Mm, W.T, W.dO, W.dH, W.dT, W.dXu,
+                 W.dMm, W.dXm, W.dG, W.dOb, W.dTb, W.dMmb, W.dPb, W.dP, W.split, W.colpart, W.loss_part, W.loss};
+    for (void* q : p)
+        if (q) (void)hipFree(q);
+    W = Work();
+}
+
+// one graph: probes (host or generated), forward, loss, backward into grad
+void loss_grad(ba_gnn* net, Graph& g, int P, const float* probes_host, unsigned long long seed, float* grad,
+               hipStream_t st) {
+    ensure_work(net->work, g.n, g.E, P);
+    Work& W = net->work;
+    const int64_t nz = (int64_t)P * g.n * 9;
+    if (probes_host)
+        BA_HIP_CHECK(hipMemcpyAsync(W.Z, probes_host, nz * sizeof(float), hipMemcpyHostToDevice, st));
+    else
+        k_probes<<<nblk(nz), BS, 0, st>>>(nz, seed, W.Z);
+    forward(net, g, st);
+    loss(net, g, P, st);
+    if (grad) backward(net, g, grad, st);
+    BA_HIP_CHECK(hipGetLastError());
+}
+
+void adam(ba_gnn* net, const float* g, float lr, hipStream_t st) {
+    net->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float bc1 = 1.f - powf(b1, (float)net->step), bc2 = 1.f - powf(b2, (float)net->step);
+    k_adam<<<nblk(N_PARAMS), BS, 0, st>>>(N_PARAMS, net->w, net->m, net->v, g, lr, b1, b2, 1e-8f, bc1, bc2, net->wb);
+}
+
+void accumulate(const float* g, float* acc, bool first, float scale, hipStream_t st) {
+    k_accum<<<nblk(N_PARAMS), BS, 0, st>>>(N_PARAMS, g, acc, first ? 1 : 0, scale);
+}
+
+// plain GEMM entry for tests: C[M][N] = A[M][K] B[K][N] (row-major bf16 bits)
+void test_gemm(int M, int N, int K, const __bf16* A, const __bf16* B, float* C, hipStream_t st) {
+    gemm(st, M, N, K, A, K, 1, B, N, 1, nullptr, false, C, N, nullptr, 0);
+}
+
+}  // namespace gnn
+}  // namespace ba
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_gnn_error;
+
+template <typename F>
+ba_status gnn_guard(std::string* err, F&& f) {
+    try {
+        return f();
+    } catch (const ba_hip_error& e) {
+        if (err) *err = e.what;
+        g_gnn_error = e.what;
+        return BA_ERR_DEVICE;
+    } catch (const std::bad_alloc&) {
+        g_gnn_error = "host allocation failed";
+        return BA_ERR_OUT_OF_MEMORY;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int64_t ba_gnn_param_count(void) { return ba::gnn::N_PARAMS; }
+
+const char* ba_gnn_last_error(void) { return g_gnn_error.c_str(); }
+
+ba_status ba_gnn_create(const float* params, void* stream, ba_gnn** out) {
+    if (!out || !params) return BA_ERR_INVALID_ARG;
+    *out = nullptr;
+    ba_gnn* net = new ba_gnn();
+    net->stream = (hipStream_t)stream;
+    ba_status s = gnn_guard(&net->err, [&]() {
+        const size_t n = ba::gnn::N_PARAMS;
+        BA_HIP_CHECK(hipMalloc((void**)&net->w, n * sizeof(float)));
+        BA_HIP_CHECK(hipMalloc((void**)&net->m, n * sizeof(float)));
+        BA_HIP_CHECK(hipMalloc((void**)&net->v, n * sizeof(float)));
+        BA_HIP_CHECK(hipMalloc((void**)&net->grad, n * sizeof(float)));
+        BA_HIP_CHECK(hipMalloc((void**)&net->gsum, n * sizeof(float)));
+        BA_HIP_CHECK(hipMalloc((void**)&net->wb, n * sizeof(__bf16)));
+        return BA_OK;
+    });
+    if (s == BA_OK) s = ba_gnn_set_params(net, params);
+    if (s != BA_OK) {
+        ba_gnn_destroy(net);
+        return s;
+    }
+    *out = net;
+    return BA_OK;
+}
+
+void ba_gnn_destroy(ba_gnn* net) {
+    if (!net) return;
+    (void)hipStreamSynchronize(net->stream);
+    void* p[] = {net->w, net->m, net->v, net->grad, net->gsum, net->wb};
+    for (void* q : p)
+        if (q) (void)hipFree(q);
+    ba::gnn::free_work(net->work);
+    delete net;
+}
+
+ba_status ba_gnn_set_params(ba_gnn* net, const float* params) {
+    if (!net || !params) return BA_ERR_INVALID_ARG;
+    return gnn_guard(&net->err, [&]() {
+        const size_t n = ba::gnn::N_PARAMS;
+        BA_HIP_CHECK(hipMemcpyAsync(net->w, params, n * sizeof(float), hipMemcpyHostToDevice, net->stream));
+        BA_HIP_CHECK(hipMemsetAsync(net->m, 0, n * sizeof(float), net->stream));
+        BA_HIP_CHECK(hipMemsetAsync(net->v, 0, n * sizeof(float), net->stream));
+        ba::gnn::k_to_bf16<<<ba::gnn::nblk(n), ba::gnn::BS, 0, net->stream>>>(n, net->w, net->wb);
+        BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+        net->step = 0;
+        return BA_OK;
+    });
+}
+
+ba_status ba_gnn_get_params(ba_gnn* net, float* params) {
+    if (!net || !params) return BA_ERR_INVALID_ARG;
+    return gnn_guard(&net->err, [&]() {
+        BA_HIP_CHECK(hipMemcpyAsync(params, net->w, ba::gnn::N_PARAMS * sizeof(float), hipMemcpyDeviceToHost, net->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+        return BA_OK;
+    });
+}
+
+ba_status ba_gnn_graph_from_host(int32_t n_rows, const int64_t* row_ptr, const int32_t* col_idx, const double* blk,
+                                 ba_gnn_graph** out) {
+    if (!out || n_rows <= 0 || !row_ptr || !col_idx || !blk) return BA_ERR_INVALID_ARG;
+    *out = nullptr;
+    for (int32_t r = 0; r < n_rows; ++r)
+        if (row_ptr[r + 1] <= row_ptr[r] || col_idx[row_ptr[r]] != r) {
+            g_gnn_error = "each row needs its diagonal block first";
+            return BA_ERR_INVALID_ARG;
+        }
+    const int64_t n_blk = row_ptr[n_rows];
+    for (int64_t k = 0; k < n_blk; ++k)
+        if (col_idx[k] < 0 || col_idx[k] >= n_rows) {
+            g_gnn_error = "column index out of range";
+            return BA_ERR_INVALID_ARG;
+        }
+    ba_gnn_graph* G = new ba_gnn_graph();
+    double* dblk = nullptr;
+    ba_status s = gnn_guard(nullptr, [&]() {
+        ba::gnn::build_graph(G->g, n_rows, row_ptr, col_idx, nullptr);
+        BA_HIP_CHECK(hipMalloc((void**)&dblk, (size_t)n_blk * 81 * sizeof(double)));
+        BA_HIP_CHECK(hipMemcpy(dblk, blk, (size_t)n_blk * 81 * sizeof(double), hipMemcpyHostToDevice));
+        ba::gnn::compute_features(G->g, dblk, nullptr);
+        int flag = 0;
+        BA_HIP_CHECK(hipMemcpy(&flag, G->g.flags, sizeof(int), hipMemcpyDeviceToHost));
+        BA_HIP_CHECK(hipFree(dblk));
+        dblk = nullptr;
+        if (flag) {
+            g_gnn_error = "a diagonal block is not positive definite";
+            return BA_ERR_NOT_SPD;
+        }
+        return BA_OK;
+    });
+    if (dblk) (void)hipFree(dblk);
+    if (s != BA_OK) {
+        ba::gnn::free_graph(G->g);
+        delete G;
+        return s;
+    }
+    *out = G;
+    return BA_OK;
+}
+
+void ba_gnn_graph_destroy(ba_gnn_graph* G) {
+    if (!G) return;
+    (void)hipDeviceSynchronize();
+    ba::gnn::free_graph(G->g);
+    delete G;
+}
+
+ba_status ba_gnn_loss_grad(ba_gnn* net, ba_gnn_graph* G, int32_t n_probes, const float* probes, uint64_t seed,
+                           double* loss_host, float* grad_host) {
+    if (!net || !G || n_probes <= 0) return BA_ERR_INVALID_ARG;
+    return gnn_guard(&net->err, [&]() {
+        ba::gnn::loss_grad(net, G->g, n_probes, probes, seed, grad_host ? net->grad : nullptr, net->stream);
+        if (loss_host)
+            BA_HIP_CHECK(hipMemcpyAsync(loss_host, net->work.loss, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+        if (grad_host)
+            BA_HIP_CHECK(hipMemcpyAsync(grad_host, net->grad, ba::gnn::N_PARAMS * sizeof(float), hipMemcpyDeviceToHost,
+                                        net->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+        return BA_OK;
+    });
+}
+
+ba_status ba_gnn_train_step(ba_gnn* net, ba_gnn_graph* const* graphs, int32_t n_graphs, int32_t n_probes, uint64_t seed,
+                            float lr, double* loss_host) {
+    if (!net || !graphs || n_graphs <= 0 || n_probes <= 0 || !(lr > 0.f)) return BA_ERR_INVALID_ARG;
+    return gnn_guard(&net->err, [&]() {
+        double total = 0.0;
+        for (int32_t i = 0; i < n_graphs; ++i) {
+            ba::gnn::loss_grad(net, graphs[i]->g, n_probes, nullptr, seed + 0x632BE59BD9B4E019ull * (uint64_t)(i + 1),
+                               net->grad, net->stream);
+            ba::gnn::accumulate(net->grad, net->gsum, i == 0, 1.f / (float)n_graphs, net->stream);
+            double l = 0.0;
+            BA_HIP_CHECK(hipMemcpyAsync(&l, net->work.loss, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+            BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+            total += l;
+        }
+        ba::gnn::adam(net, net->gsum, lr, net->stream);
+        BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+        if (loss_host) *loss_host = total / n_graphs;
+        return BA_OK;
+    });
+}
+
+ba_status ba_gnn_preconditioner(ba_gnn* net, ba_gnn_graph* G, double* P_host) {
+    if (!net || !G || !P_host) return BA_ERR_INVALID_ARG;
+    return gnn_guard(&net->err, [&]() {
+        double* dP = nullptr;
+        BA_HIP_CHECK(hipMalloc((void**)&dP, (size_t)G->g.n * 81 * sizeof(double)));
+        ba::gnn::infer_preconditioner(net, G->g, nullptr, dP, net->stream);
+        BA_HIP_CHECK(hipMemcpyAsync(P_host, dP, (size_t)G->g.n * 81 * sizeof(double), hipMemcpyDeviceToHost, net->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+        BA_HIP_CHECK(hipFree(dP));
+        return BA_OK;
+    });
+}
+
+ba_status ba_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t* A, const uint16_t* B, float* C) {
+    if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !C) return BA_ERR_INVALID_ARG;
+    return gnn_guard(nullptr, [&]() {
+        __bf16 *dA = nullptr, *dB = nullptr;
+        float* dC = nullptr;
+        BA_HIP_CHECK(hipMalloc((void**)&dA, (size_t)M * K * 2));
+        BA_HIP_CHECK(hipMalloc((void**)&dB, (size_t)K * N * 2));
+        BA_HIP_CHECK(hipMalloc((void**)&dC, (size_t)M * N * 4));
+        BA_HIP_CHECK(hipMemcpy(dA, A, (size_t)M * K * 2, hipMemcpyHostToDevice));
+        BA_HIP_CHECK(hipMemcpy(dB, B, (size_t)K * N * 2, hipMemcpyHostToDevice));
+        ba::gnn::test_gemm(M, N, K, dA, dB, dC, nullptr);
+        BA_HIP_CHECK(hipMemcpy(C, dC, (size_t)M * N * 4, hipMemcpyDeviceToHost));
+        BA_HIP_CHECK(hipFree(dA));
+        BA_HIP_CHECK(hipFree(dB));
+        BA_HIP_CHECK(hipFree(dC));
+        return BA_OK;
+    });
+}
+
+}  // extern "C"

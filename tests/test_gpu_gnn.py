@@ -1,0 +1,146 @@
+"""Learned block-Jacobi correction on the GPU against the CPU reference."""
+import numpy as np
+import pytest
+
+from oracle import gnn_ref as G
+from oracle import oracle as orc
+from paper_2307_08383_amd import scenegen
+
+from gpu_util import T, create
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ba = pytest.importorskip("paper_2307_08383_amd.ba")
+
+
+def _bits(x):
+    """bf16 bit patterns (round to nearest even) of a float array."""
+    r = G.bf16_round(x).astype(np.float32)
+    return (r.view(np.uint32) >> 16).astype(np.uint16), r.astype(np.float64)
+
+
+@pytest.mark.parametrize("M,N,K", [(16, 16, 32), (64, 64, 64), (100, 48, 192), (77, 130, 45)])
+def test_gemm_bf16_matches_numpy(M, N, K):
+    rng = np.random.default_rng(M + N + K)
+    Ab, A = _bits(rng.normal(size=(M, K)))
+    Bb, B = _bits(rng.normal(size=(K, N)))
+    C = ba.ba_gemm_bf16(Ab, Bb)
+    ref = A @ B
+    assert np.abs(C - ref).max() <= 1e-5 * np.abs(A).max() * np.abs(B).max() * K
+
+
+def _oracle_rcs(scene, lam=1e-3):
+    P = orc.Problem.from_scene(scene)
+    P.linearize(scene.cams_init, scene.pts_init)
+    P.form_rcs(lam)
+    rp, ci = P.pattern()
+    blk, _ = P.rcs()
+    return rp, ci, blk
+
+
+@pytest.fixture(scope="module")
+def graph_case():
+    s = scenegen.tiny_scene(seed=3, n_pts=200, with_stats=False)
+    rp, ci, blk = _oracle_rcs(s)
+    return rp, ci, blk, G.features(rp, ci, blk)
+
+
+def test_gradients_match_cpu_reference(graph_case):
+    rp, ci, blk, feat = graph_case
+    n = len(rp) - 1
+    w = G.init_params(seed=7, zero_decoder=False)
+    rng = np.random.default_rng(1)
+    z = rng.choice([-1.0, 1.0], size=(4, n, 9))
+    net = ba.ba_gnn_create(w.astype(np.float32))
+    g = ba.ba_gnn_graph_from_host(rp, ci, blk)
+    try:
+        loss, grad = ba.ba_gnn_loss_grad(net, g, 4, z)
+        w32 = w.astype(np.float32).astype(np.float64)
+        loss_ref, grad_ref, _ = G.loss_and_grad(w32, feat, z, bf16=True)
+        assert abs(loss - loss_ref) <= 1e-2 * loss_ref
+        offs = np.cumsum([0] + [int(np.prod(s)) for _, s in G.PARAM_SHAPES])
+        for t, (name, _) in enumerate(G.PARAM_SHAPES):
+            a, b = grad[offs[t]:offs[t + 1]], grad_ref[offs[t]:offs[t + 1]]
+            nb = np.linalg.norm(b)
+            if nb == 0:
+                assert np.linalg.norm(a) == 0, name
+                continue
+            assert np.linalg.norm(a - b) <= 1e-2 * nb, (name, np.linalg.norm(a - b) / nb)
+    finally:
+        ba.ba_gnn_graph_destroy(g)
+        ba.ba_gnn_destroy(net)
+
+
+def test_zero_decoder_is_block_jacobi(graph_case):
+    rp, ci, blk, _ = graph_case
+    n = len(rp) - 1
+    net = ba.ba_gnn_create(G.init_params(seed=2, zero_decoder=True).astype(np.float32))
+    g = ba.ba_gnn_graph_from_host(rp, ci, blk)
+    try:
+        P = ba.ba_gnn_preconditioner(net, g, n)
+        for i in range(n):
+            inv = np.linalg.inv(blk[rp[i]])
+            np.testing.assert_allclose(P[i], inv, rtol=0, atol=1e-10 * np.abs(inv).max())
+    finally:
+        ba.ba_gnn_graph_destroy(g)
+        ba.ba_gnn_destroy(net)
+
+
+def test_learned_preconditioner_spd_and_pcg_path():
+    """Random (non-zero) decoder: SPD blocks; PCG with the learned
+    preconditioner converges to the same solution as block-Jacobi.  Zero
+    decoder: the same iterations as block-Jacobi."""
+    s = scenegen.aerial_grid_scene(seed=4, nx=10, ny=8, n_pts=12000, with_stats=False)
+    uv = orc.observations(s)
+    ctx = create(s, uv)
+    nets = []
+    try:
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-3)
+        n_rows = ba.ba_get_sizes(ctx)["n_rows"]
+        dx_bj = torch.empty((n_rows, 9), dtype=torch.float64, device="cuda")
+        i_bj = ba.ba_pcg_solve(ctx, dx_bj, tol=1e-10, max_iter=5000)
+        for zero in (True, False):
+            net = ba.ba_gnn_create(G.init_params(seed=5, zero_decoder=zero).astype(np.float32))
+            nets.append(net)
+            ba.ba_set_preconditioner_net(ctx, net)
+            dx = torch.empty_like(dx_bj)
+            info = ba.ba_pcg_solve(ctx, dx, tol=1e-10, max_iter=5000, precond=ba.BA_PRECOND_LEARNED)
+            assert info["status"] == 0
+            a, b = dx.cpu().numpy(), dx_bj.cpu().numpy()
+            if zero:
+                assert info["iters"] == i_bj["iters"]
+                assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+            else:
+                assert np.linalg.norm(a - b) <= 1e-7 * np.linalg.norm(b)
+                g = ba.ba_gnn_graph_from_ctx(ctx)
+                P = ba.ba_gnn_preconditioner(net, g, n_rows)
+                ba.ba_gnn_graph_destroy(g)
+                assert min(np.linalg.eigvalsh(0.5 * (Pi + Pi.T)).min() for Pi in P) > 0
+    finally:
+        ba.ba_set_preconditioner_net(ctx, None)
+        for n in nets:
+            ba.ba_gnn_destroy(n)
+        ba.ba_destroy(ctx)
+
+
+def test_training_lowers_the_loss(graph_case):
+    rp, ci, blk, _ = graph_case
+    net = ba.ba_gnn_create(G.init_params(seed=3, zero_decoder=True).astype(np.float32))
+    g = ba.ba_gnn_graph_from_host(rp, ci, blk)
+    try:
+        l0, _ = ba.ba_gnn_loss_grad(net, g, 16, None, seed=99, want_grad=False)
+        for it in range(60):
+            ba.ba_gnn_train_step(net, [g], n_probes=4, seed=1000 + it, lr=2e-3)
+        l1, _ = ba.ba_gnn_loss_grad(net, g, 16, None, seed=99, want_grad=False)
+        assert l1 < 0.95 * l0, (l0, l1)
+        # the optimiser is deterministic
+        w = ba.ba_gnn_get_params(net)
+        ba.ba_gnn_set_params(net, G.init_params(seed=3, zero_decoder=True).astype(np.float32))
+        for it in range(60):
+            ba.ba_gnn_train_step(net, [g], n_probes=4, seed=1000 + it, lr=2e-3)
+        assert np.array_equal(w, ba.ba_gnn_get_params(net))
+    finally:
+        ba.ba_gnn_graph_destroy(g)
+        ba.ba_gnn_destroy(net)
