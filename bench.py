@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-formations", type=int, default=2)
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the learned + mixed vs FP64 block-Jacobi LM comparison")
+    ap.add_argument("--lm-iters", type=int, default=20, help="LM iterations of each compared run")
     return ap.parse_args()
 
 
@@ -76,9 +79,46 @@ def traffic_from_profile(kernel_src_hash, kernel):
     return None
 
 
+def lm_run(scene, obs, precision, learned_weights, iters):
+    """LM run from the scene's start; returns per-iteration infos and the
+    final cost (FP64 cost of the last accepted iterate)."""
+    import torch
+    from paper_2307_08383_amd import ba
+    obs_cam, obs_pt, uv, cf = obs
+    ctx = ba.ba_create(scene.n_cams, scene.n_pts, obs_cam, obs_pt, uv, cf, precision=precision)
+    net = None
+    pre = ba.BA_PRECOND_BLOCK_JACOBI
+    if learned_weights is not None:
+        net = ba.ba_gnn_create(learned_weights)
+        ba.ba_set_preconditioner_net(ctx, net)
+        pre = ba.BA_PRECOND_LEARNED
+    dev = uv.device
+    cams = torch.as_tensor(scene.cams_init, dtype=torch.float64, device=dev).contiguous()
+    pts = torch.as_tensor(scene.pts_init, dtype=torch.float64, device=dev).contiguous()
+    st = ba.new_lm_state(1e-4)
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        infos.append(ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol, precond=pre))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # FP64 cost of the final parameters (the mixed path evaluates cost in FP64 too)
+    final = ba.ba_linearize(ctx, cams, pts)
+    if net is not None:
+        ba.ba_set_preconditioner_net(ctx, None)
+        ba.ba_gnn_destroy(net)
+    ba.ba_destroy(ctx)
+    return dict(ms_per_iter=1e3 * wall / iters, final_cost=final,
+                pcg_iters_mean=float(np.mean([i["pcg_iters"] for i in infos])),
+                precond_ms_mean=float(np.mean([i["ms_precond"] for i in infos])),
+                form_ms_mean=float(np.mean([i["ms_form_rcs"] for i in infos])),
+                pcg_ms_mean=float(np.mean([i["ms_pcg"] for i in infos])))
+
+
 def cpu_baseline(scene, n_form):
     from oracle import oracle as orc
-    nt = os.cpu_count() or 1
+    nt = orc.default_threads()
     uv = orc.observations(scene)
     P = orc.Problem.from_scene(scene, uv, n_threads=nt)
     t0 = time.perf_counter()
@@ -160,6 +200,21 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": alg},
     }
     ba.ba_destroy(ctx)
+    if not args.no_compare:
+        from paper_2307_08383_amd import learned_precond
+        wpath = learned_precond.DEFAULT_WEIGHTS
+        weights = learned_precond.load_weights(wpath) if os.path.exists(wpath) else learned_precond.init_params(0)
+        obs = (obs_cam, obs_pt, uv, cf)
+        base = lm_run(scene, obs, ba.BA_FP64, None, args.lm_iters)
+        alt = lm_run(scene, obs, ba.BA_MIXED, weights, args.lm_iters)
+        out["lm_comparison"] = {
+            "iterations": args.lm_iters,
+            "fp64_block_jacobi": base,
+            "mixed_learned": alt,
+            "learned_weights": os.path.basename(wpath) if os.path.exists(wpath) else "untrained (zero decoder)",
+            "speedup": base["ms_per_iter"] / alt["ms_per_iter"],
+            "final_cost_rel_diff": abs(alt["final_cost"] - base["final_cost"]) / base["final_cost"],
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_sample_formations)
     print(json.dumps(out), flush=True)

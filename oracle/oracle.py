@@ -84,6 +84,14 @@ def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
+def default_threads():
+    """Host threads for the oracle: OMP_NUM_THREADS when set, else all cores."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    return os.cpu_count() or 1
+
+
 def project(cams, pts, obs_cam, obs_pt, noise=None):
     """Observed pixels [2][n_obs] = projection(params) (+ noise)."""
     obs_cam = _c(obs_cam, np.int32)
@@ -119,7 +127,7 @@ class Problem:
         self._keep = (_c(obs_cam, np.int32), _c(obs_pt, np.int32), _c(uv, np.float64),
                       None if cam_fixed is None else _c(cam_fixed, np.uint8))
         n_obs = self._keep[0].size
-        nt = n_threads or os.cpu_count() or 1
+        nt = n_threads or default_threads()
         h = lib().orc_create(n_cams, n_pts, n_obs, self._keep[0], self._keep[1], self._keep[2],
                              _ptr(self._keep[3]), nt)
         if not h:

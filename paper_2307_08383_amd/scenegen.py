@@ -172,9 +172,15 @@ def _assemble(name, seed, rng, centres, cam_fixed, pts, obs_pt, obs_cam,
     cams[:, 7] = k1
     cams[:, 8] = k2
     noise = rng.normal(0.0, 1.0, size=(2, n_obs)) * noise_sigma
+    # start: each pose perturbed about its own centre (a small random
+    # rotation, axis-angle components N(0, 0.01)) and its centre moved by
+    # N(0, 0.05) per coordinate; intrinsics start at their true values
+    from scipy.spatial.transform import Rotation
+    rot_init = Rotation.from_rotvec(rng.normal(0.0, 0.01, size=(n_c, 3))) * rot
+    centres_init = centres + rng.normal(0.0, 0.05, size=(n_c, 3))
     cams_init = cams.copy()
-    cams_init[:, 0:3] += rng.normal(0.0, 0.01, size=(n_c, 3))
-    cams_init[:, 3:6] += rng.normal(0.0, 0.05, size=(n_c, 3))
+    cams_init[:, 0:3] = rot_init.as_rotvec()
+    cams_init[:, 3:6] = _translations(rot_init, centres_init)
     fixed = cam_fixed.astype(bool)
     cams_init[fixed] = cams[fixed]
     pts_init = pts + rng.normal(0.0, 0.05, size=pts.shape)

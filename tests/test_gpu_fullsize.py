@@ -1,0 +1,101 @@
+"""Full-size parity (needs a GPU): the benchmark scene (2,000 cameras, 1.6M
+observations) in FP64 and the strip scene (20,000 cameras, ~20M
+observations) in mixed precision, against the oracle on the same inputs.
+Per-block errors of the mixed path are written to gpurun_out/ when that
+directory exists."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2307_08383_amd import scenegen
+
+from gpu_util import T, block_errors, create
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+ba = pytest.importorskip("paper_2307_08383_amd.ba")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _report(name, d):
+    out = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, name), "w") as f:
+            json.dump(d, f, indent=1)
+    print(name, json.dumps(d), flush=True)
+
+
+def _rcs_case(scene, precision, lam=1e-4):
+    uv = orc.observations(scene)
+    P = orc.Problem.from_scene(scene, uv)
+    P.linearize(scene.cams_init, scene.pts_init)
+    P.form_rcs(lam)
+    ctx = create(scene, uv, precision)
+    try:
+        ba.ba_linearize(ctx, T(scene.cams_init, torch.float64), T(scene.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, lam)
+        rp, ci = ba.ba_get_pattern(ctx)
+        rp_ref, ci_ref = P.pattern()
+        assert np.array_equal(rp, rp_ref) and np.array_equal(ci, ci_ref)
+        blk, rhs = ba.ba_get_rcs(ctx)
+    finally:
+        ba.ba_destroy(ctx)
+    blk_ref, rhs_ref = P.rcs()
+    errs, raw = block_errors(blk, blk_ref, rp_ref, ci_ref)
+    rerr = np.linalg.norm(rhs - rhs_ref, axis=1) / np.linalg.norm(rhs_ref, axis=1)
+    return errs, raw, rerr
+
+
+@pytest.mark.timeout(600)
+def test_benchmark_scene_fp64_rcs():
+    s = scenegen.aerial_grid_scene(seed=0, with_stats=False)
+    errs, raw, rerr = _rcs_case(s, 0)
+    rep = dict(scene=s.name, n_obs=s.n_obs, n_blocks=len(errs), max_block_err=float(errs.max()),
+               p999_block_err=float(np.quantile(errs, 0.999)), max_raw_rel=float(raw.max()),
+               max_rhs_rel=float(rerr.max()))
+    _report("fullsize_fp64_rcs.json", rep)
+    assert errs.max() <= 1e-10 and rerr.max() <= 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_strip_scene_mixed_rcs_errors():
+    s = scenegen.strips_scene(seed=1, with_stats=False)
+    errs, raw, rerr = _rcs_case(s, 1)
+    rep = dict(scene=s.name, n_obs=s.n_obs, n_blocks=len(errs), max_block_err=float(errs.max()),
+               p999_block_err=float(np.quantile(errs, 0.999)), median_block_err=float(np.median(errs)),
+               max_raw_rel=float(raw.max()), p999_raw_rel=float(np.quantile(raw, 0.999)),
+               max_rhs_rel=float(rerr.max()), p999_rhs_rel=float(np.quantile(rerr, 0.999)))
+    _report("fullsize_mixed_rcs_errors.json", rep)
+    assert errs.max() <= 1e-4
+
+
+@pytest.mark.timeout(900)
+def test_benchmark_scene_lm_final_cost():
+    """20 LM iterations (the benchmark configuration): final cost of the
+    FP64 path and of the mixed path against the oracle, rel 1e-6."""
+    s = scenegen.aerial_grid_scene(seed=0, with_stats=False)
+    uv = orc.observations(s)
+    P = orc.Problem.from_scene(s, uv)
+    c_ref, p_ref, hist_ref = orc.lm_run(P, s.cams_init, s.pts_init, 20)
+    F_ref = P.cost(c_ref, p_ref)
+    rep = dict(scene=s.name, oracle_final_cost=F_ref)
+    for precision in (0, 1):
+        ctx = create(s, uv, precision)
+        try:
+            cams = T(s.cams_init, torch.float64)
+            pts = T(s.pts_init, torch.float64)
+            st = ba.new_lm_state(1e-4)
+            for _ in range(20):
+                ba.ba_lm_step(ctx, cams, pts, st)
+            F = P.cost(cams.cpu().numpy(), pts.cpu().numpy())
+        finally:
+            ba.ba_destroy(ctx)
+        rep[f"final_cost_{'fp64' if precision == 0 else 'mixed'}"] = F
+        rep[f"rel_diff_{'fp64' if precision == 0 else 'mixed'}"] = abs(F - F_ref) / F_ref
+    _report("fullsize_lm_final_cost.json", rep)
+    assert rep["rel_diff_fp64"] <= 1e-6 and rep["rel_diff_mixed"] <= 1e-6

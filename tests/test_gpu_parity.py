@@ -148,10 +148,16 @@ def test_pcg_and_back_substitution_parity():
         assert info["status"] == 0 and info["relres"] <= 1e-12
         assert np.linalg.norm(x - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
         assert abs(info["iters"] - oinfo["iters"]) <= max(3, 0.05 * oinfo["iters"])
-        # same tolerance as the LM path
+        # same tolerance as the LM path: near the stop threshold the residual
+        # plateaus, so rounding may move the stopping step by a few; the GPU
+        # solution must meet the tolerance in the oracle's own product
         info6 = ba.ba_pcg_solve(ctx, dxc, tol=1e-6)
         _, oinfo6 = P.pcg(tol=1e-6)
-        assert abs(info6["iters"] - oinfo6["iters"]) <= 2 and info6["relres"] <= 1e-6
+        assert info6["status"] == 0 and info6["relres"] <= 1e-6
+        assert abs(info6["iters"] - oinfo6["iters"]) <= max(3, 0.1 * oinfo6["iters"])
+        _, rhs_ref = P.rcs()
+        true_res = np.linalg.norm(rhs_ref - P.spmv(dxc.cpu().numpy())) / np.linalg.norm(rhs_ref)
+        assert true_res <= 1.5e-6, true_res
         # back-substitution from the same dxc
         dxc_t = T(x_ref, torch.float64)
         dxp = torch.empty((s.n_pts, 3), dtype=torch.float64, device="cuda")
