@@ -43,7 +43,14 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the learned + mixed vs FP64 block-Jacobi LM comparison")
     ap.add_argument("--lm-iters", type=int, default=20, help="LM iterations of each compared run")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this many MiB first, so that hardware "
+                         "byte counters can be scaled against a kernel of known traffic")
     return ap.parse_args()
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def build_scene(kind):
@@ -142,6 +149,7 @@ def main():
 
     dev = torch.device("cuda:0")
     scene = build_scene(args.workload)
+    progress(f"scene {scene.name}: {scene.n_obs} observations")
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     obs_cam = T(scene.obs_cam, torch.int32)
     obs_pt = T(scene.obs_pt, torch.int32)
@@ -151,12 +159,21 @@ def main():
     cf = T(scene.cam_fixed, torch.uint8) if scene.cam_fixed.any() else None
     ctx = ba.ba_create(scene.n_cams, scene.n_pts, obs_cam, obs_pt, uv, cf, precision=prec)
     sizes = ba.ba_get_sizes(ctx)
+    progress(f"context created: {sizes['n_blk']} blocks, {sizes['n_pairs']} observation couples")
     cams = T(scene.cams_init, torch.float64)
     pts = T(scene.pts_init, torch.float64)
     st = ba.new_lm_state(1e-4)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src_buf = torch.ones(n, dtype=torch.float64, device=dev)
+        dst_buf = torch.empty_like(src_buf)
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
     for _ in range(args.warmup):
         ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol)
     torch.cuda.synchronize()
+    progress("warm-up done")
     infos, stages = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -175,7 +192,8 @@ def main():
     alg = pair_stage_bytes(sizes["n_pairs"], n_offseg, args.precision)
     achieved = alg / (pair_ms * 1e-3) / 1e9
     src = open(os.path.join(ROOT, "paper_2307_08383_amd", "csrc", "kernels_rcs.hip"), "rb").read()
-    traffic = traffic_from_profile(hashlib.sha256(src).hexdigest(), "k_offdiag_" + args.precision)
+    traffic = traffic_from_profile(hashlib.sha256(src).hexdigest(),
+                                   f"k_offdiag_{args.workload}_{args.precision}")
     out = {
         "metric": METRIC, "value": value, "unit": "obs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
