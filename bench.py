@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the learned + mixed vs FP64 block-Jacobi LM comparison")
     ap.add_argument("--lm-iters", type=int, default=20, help="LM iterations of each compared run")
+    ap.add_argument("--precond", default="block_jacobi", choices=["block_jacobi", "fsai", "learned"],
+                    help="preconditioner of the timed LM steps")
+    ap.add_argument("--deflate", action="store_true", help="gauge-deflated PCG in the timed LM steps")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first, so that hardware "
                          "byte counters can be scaled against a kernel of known traffic")
@@ -86,19 +89,17 @@ def traffic_from_profile(kernel_src_hash, kernel):
     return None
 
 
-def lm_run(scene, obs, precision, learned_weights, iters):
-    """LM run from the scene's start; returns per-iteration infos and the
+def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=False):
+    """LM run from the scene's start; returns per-iteration means and the
     final cost (FP64 cost of the last accepted iterate)."""
     import torch
     from paper_2307_08383_amd import ba
     obs_cam, obs_pt, uv, cf = obs
     ctx = ba.ba_create(scene.n_cams, scene.n_pts, obs_cam, obs_pt, uv, cf, precision=precision)
     net = None
-    pre = ba.BA_PRECOND_BLOCK_JACOBI
-    if learned_weights is not None:
+    if precond == ba.BA_PRECOND_LEARNED:
         net = ba.ba_gnn_create(learned_weights)
         ba.ba_set_preconditioner_net(ctx, net)
-        pre = ba.BA_PRECOND_LEARNED
     dev = uv.device
     cams = torch.as_tensor(scene.cams_init, dtype=torch.float64, device=dev).contiguous()
     pts = torch.as_tensor(scene.pts_init, dtype=torch.float64, device=dev).contiguous()
@@ -107,7 +108,7 @@ def lm_run(scene, obs, precision, learned_weights, iters):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(iters):
-        infos.append(ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol, precond=pre))
+        infos.append(ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol, precond=precond, deflate=deflate))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # FP64 cost of the final parameters (the mixed path evaluates cost in FP64 too)
@@ -117,6 +118,8 @@ def lm_run(scene, obs, precision, learned_weights, iters):
         ba.ba_gnn_destroy(net)
     ba.ba_destroy(ctx)
     return dict(ms_per_iter=1e3 * wall / iters, final_cost=final,
+                accepted=int(sum(i["accepted"] for i in infos)),
+                pcg_iters=[int(i["pcg_iters"]) for i in infos],
                 pcg_iters_mean=float(np.mean([i["pcg_iters"] for i in infos])),
                 precond_ms_mean=float(np.mean([i["ms_precond"] for i in infos])),
                 form_ms_mean=float(np.mean([i["ms_form_rcs"] for i in infos])),
@@ -170,14 +173,22 @@ def main():
         dst_buf.copy_(src_buf)
         torch.cuda.synchronize()
         del src_buf, dst_buf
+    pre = {"block_jacobi": ba.BA_PRECOND_BLOCK_JACOBI, "fsai": ba.BA_PRECOND_FSAI,
+           "learned": ba.BA_PRECOND_LEARNED}[args.precond]
+    net = None
+    if pre == ba.BA_PRECOND_LEARNED:
+        from paper_2307_08383_amd import learned_precond
+        net = ba.ba_gnn_create(learned_precond.load_weights())
+        ba.ba_set_preconditioner_net(ctx, net)
+    step_kw = dict(pcg_tol=scene.pcg_tol, precond=pre, deflate=args.deflate)
     for _ in range(args.warmup):
-        ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol)
+        ba.ba_lm_step(ctx, cams, pts, st, **step_kw)
     torch.cuda.synchronize()
     progress("warm-up done")
     infos, stages = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        infos.append(ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol))
+        infos.append(ba.ba_lm_step(ctx, cams, pts, st, **step_kw))
         stages.append(ba.ba_get_stage_ms(ctx))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -201,7 +212,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{scene.name} ({scene.n_obs} observations), "
                                f"{'FP64' if args.precision == 'fp64' else 'mixed FP32/FP64'}, "
-                               f"block-Jacobi PCG to rel {scene.pcg_tol:g}",
+                               f"{args.precond.replace('_', '-')}{' + gauge-deflated' if args.deflate else ''} "
+                               f"PCG to rel {scene.pcg_tol:g}",
                    "n_cams": scene.n_cams, "n_pts": scene.n_pts, "n_obs": scene.n_obs,
                    "n_blocks": sizes["n_blk"], "n_pairs": sizes["n_pairs"]},
         "lm_iteration_ms": ms_per_step,
@@ -217,21 +229,32 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": alg},
     }
+    if net is not None:
+        ba.ba_set_preconditioner_net(ctx, None)
+        ba.ba_gnn_destroy(net)
     ba.ba_destroy(ctx)
     if not args.no_compare:
         from paper_2307_08383_amd import learned_precond
         wpath = learned_precond.DEFAULT_WEIGHTS
         weights = learned_precond.load_weights(wpath) if os.path.exists(wpath) else learned_precond.init_params(0)
         obs = (obs_cam, obs_pt, uv, cf)
-        base = lm_run(scene, obs, ba.BA_FP64, None, args.lm_iters)
-        alt = lm_run(scene, obs, ba.BA_MIXED, weights, args.lm_iters)
+        runs = {}
+        for name, prec, pre, defl in [
+                ("fp64_block_jacobi", ba.BA_FP64, ba.BA_PRECOND_BLOCK_JACOBI, False),
+                ("mixed_block_jacobi_deflated", ba.BA_MIXED, ba.BA_PRECOND_BLOCK_JACOBI, True),
+                ("mixed_fsai", ba.BA_MIXED, ba.BA_PRECOND_FSAI, False),
+                ("mixed_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_FSAI, True),
+                ("mixed_learned_block_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED, True)]:
+            runs[name] = lm_run(scene, obs, prec, pre, args.lm_iters, weights, deflate=defl)
+            progress(f"LM comparison {name}: {runs[name]['ms_per_iter']:.2f} ms per iteration")
+        base = runs["fp64_block_jacobi"]
         out["lm_comparison"] = {
             "iterations": args.lm_iters,
-            "fp64_block_jacobi": base,
-            "mixed_learned": alt,
+            **runs,
             "learned_weights": os.path.basename(wpath) if os.path.exists(wpath) else "untrained (zero decoder)",
-            "speedup": base["ms_per_iter"] / alt["ms_per_iter"],
-            "final_cost_rel_diff": abs(alt["final_cost"] - base["final_cost"]) / base["final_cost"],
+            "speedup_vs_fp64_block_jacobi": {k: base["ms_per_iter"] / v["ms_per_iter"] for k, v in runs.items()},
+            "final_cost_rel_diff_vs_fp64_block_jacobi": {
+                k: abs(v["final_cost"] - base["final_cost"]) / base["final_cost"] for k, v in runs.items()},
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_sample_formations)

@@ -52,7 +52,14 @@ typedef enum ba_status {
 } ba_status;
 
 enum { BA_FP64 = 0, BA_MIXED = 1 };
-enum { BA_PRECOND_BLOCK_JACOBI = 0, BA_PRECOND_LEARNED = 1 };
+/* Preconditioners of ba_pcg_solve / ba_lm_step:
+ *   BLOCK_JACOBI: M = blockdiag(S_ii) (Sec. 3.2);
+ *   LEARNED: the learned correction of block-Jacobi (ba_set_preconditioner_net);
+ *   FSAI: factorised sparse approximate inverse M^-1 = G^T G, G block-lower-
+ *     triangular on the lower RCS pattern (at most 27 lower neighbours per
+ *     row, those with the most common points), recomputed after every
+ *     formation from local FP32 factorisations; see ba_get_fsai. */
+enum { BA_PRECOND_BLOCK_JACOBI = 0, BA_PRECOND_LEARNED = 1, BA_PRECOND_FSAI = 2 };
 
 typedef struct ba_ctx ba_ctx;
 
@@ -98,8 +105,10 @@ ba_status ba_form_rcs(ba_ctx* ctx, double lambda);
 typedef struct ba_pcg_opts {
     double tol;                 /* stop when |r_k| / |r_0| <= tol (default 1e-6) */
     int32_t max_iter;           /* iteration cap (default 1000) */
-    int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI or BA_PRECOND_LEARNED */
+    int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED or _FSAI */
     const double* x0;           /* device [n_rows][9] initial guess or NULL (zero) */
+    int32_t deflate;            /* 1: deflate the similarity gauge (see ba_get_gauge) */
+    int32_t reserved;
 } ba_pcg_opts;
 
 typedef struct ba_pcg_info {
@@ -132,7 +141,9 @@ typedef struct ba_lm_state {    /* caller-owned; it is the checkpoint of an LM r
 typedef struct ba_lm_opts {
     double pcg_tol;             /* default 1e-6 */
     int32_t pcg_max_iter;       /* default 1000 */
-    int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI or BA_PRECOND_LEARNED */
+    int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED or _FSAI */
+    int32_t deflate;            /* 1: deflated PCG on the similarity gauge */
+    int32_t reserved;
 } ba_lm_opts;
 
 typedef struct ba_lm_info {
@@ -186,6 +197,33 @@ ba_status ba_get_rcs(ba_ctx* ctx, double* blk, double* rhs);
  * J [n_obs][24] = J_c row 0 (9), J_c row 1 (9), J_p row 0 (3), J_p row 1 (3)
  * (converted to FP64 in mixed precision), e [n_obs][2]; either may be NULL. */
 ba_status ba_get_jacobians(ba_ctx* ctx, double* J, double* e);
+
+/* Host copy (FP32, [n_blk][81], row-major 9x9) of the FSAI factor G of the
+ * current RCS, in the slots of the RCS blocks: the slot of upper block
+ * (s, c), s < c, holds G_cs; a diagonal slot holds G_ss (lower triangular,
+ * positive diagonal); slots of lower neighbours beyond the per-row limit
+ * hold zeros.  Definition (Kolotilina-Yeremin): row i of G is zero outside
+ * its set J_i and satisfies (G S)_ij = 0 for j in J_i, j != i, and
+ * (G S G^T)_ii = I.  BA_ERR_STATE unless a solve or LM step with
+ * BA_PRECOND_FSAI ran on the current RCS. */
+ba_status ba_get_fsai(ba_ctx* ctx, float* G);
+
+/* Gauge deflation.  A similarity transform of the whole scene leaves every
+ * projection of Eq. (1) unchanged, so its seven generators (three rotations,
+ * three translations, one scale) are null vectors of J; their camera parts
+ * W [n_rows][7][9] (column order: rotation x, y, z, translation x, y, z,
+ * scale) are null vectors of the undamped RCS of Eq. (4):
+ *   rotation k:    dw = -J_r(w)^-1 e_k  (J_r: right Jacobian of the
+ *                  axis-angle map), dt = 0;
+ *   translation k: dt = -R(w) e_k;   scale: dt = t;   f, k1, k2 fixed.
+ * With deflate = 1, PCG is the deflated CG of Saad, Yeung, Erhel and
+ * Guyomarc'h on span(W): the start is corrected so that W^T r_0 = 0 and
+ * every search direction is kept S-orthogonal to W.  The iterate converges
+ * to the same S^-1 b; with small damping the gauge directions are the
+ * slowest ones, so deflation removes most of the iterations they cost.
+ * ba_get_gauge copies W (FP64) for the camera parameters of the last
+ * linearization.  BA_ERR_STATE without a formed RCS. */
+ba_status ba_get_gauge(ba_ctx* ctx, double* W);
 
 /* Device time in ms of the stages of the last formation:
  * [0] linearize, [1] point stage, [2] off-diagonal pair stage, [3] diagonal stage. */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libba.so")
 
 BA_OK, BA_ERR_INVALID_ARG, BA_ERR_STATE, BA_ERR_NOT_SPD, BA_ERR_NOT_CONVERGED, BA_ERR_OUT_OF_MEMORY, BA_ERR_DEVICE = range(7)
 BA_FP64, BA_MIXED = 0, 1
-BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED = 0, 1
+BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED, BA_PRECOND_FSAI = 0, 1, 2
 
 
 class ProblemDesc(C.Structure):
@@ -29,7 +29,8 @@ class ProblemDesc(C.Structure):
 
 
 class PcgOpts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32), ("x0", C.c_void_p)]
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32), ("x0", C.c_void_p),
+                ("deflate", C.c_int32), ("reserved", C.c_int32)]
 
 
 class PcgInfo(C.Structure):
@@ -41,7 +42,8 @@ class LMState(C.Structure):
 
 
 class LMOpts(C.Structure):
-    _fields_ = [("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32), ("precond", C.c_int32)]
+    _fields_ = [("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32), ("precond", C.c_int32),
+                ("deflate", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LMInfo(C.Structure):
@@ -73,6 +75,8 @@ SIGNATURES = {
     "ba_get_pattern": (C.c_int, [_vp, _vp, _vp]),
     "ba_get_rcs": (C.c_int, [_vp, _vp, _vp]),
     "ba_get_jacobians": (C.c_int, [_vp, _vp, _vp]),
+    "ba_get_fsai": (C.c_int, [_vp, _vp]),
+    "ba_get_gauge": (C.c_int, [_vp, _vp]),
     "ba_get_stage_ms": (C.c_int, [_vp, _dp]),
     "ba_status_str": (C.c_char_p, [C.c_int]),
     "ba_last_error": (C.c_char_p, [_vp]),
@@ -167,8 +171,8 @@ def ba_form_rcs(ctx, lam):
     _check(lib().ba_form_rcs(ctx, float(lam)), ctx)
 
 
-def ba_pcg_solve(ctx, dxc, tol=1e-6, max_iter=1000, precond=BA_PRECOND_BLOCK_JACOBI, x0=None):
-    o = PcgOpts(tol=tol, max_iter=max_iter, precond=precond, x0=_ptr(x0))
+def ba_pcg_solve(ctx, dxc, tol=1e-6, max_iter=1000, precond=BA_PRECOND_BLOCK_JACOBI, x0=None, deflate=False):
+    o = PcgOpts(tol=tol, max_iter=max_iter, precond=precond, x0=_ptr(x0), deflate=int(bool(deflate)))
     info = PcgInfo()
     st = _check(lib().ba_pcg_solve(ctx, C.byref(o), _ptr(dxc), C.byref(info)), ctx,
                 allow=(BA_ERR_NOT_CONVERGED,))
@@ -180,8 +184,8 @@ def ba_back_substitute(ctx, dxc, dxp):
 
 
 def ba_lm_step(ctx, cams, pts, state: LMState, pcg_tol=1e-6, pcg_max_iter=1000,
-               precond=BA_PRECOND_BLOCK_JACOBI):
-    o = LMOpts(pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter, precond=precond)
+               precond=BA_PRECOND_BLOCK_JACOBI, deflate=False):
+    o = LMOpts(pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter, precond=precond, deflate=int(bool(deflate)))
     info = LMInfo()
     _check(lib().ba_lm_step(ctx, _ptr(cams), _ptr(pts), C.byref(state), C.byref(o), C.byref(info)), ctx)
     return {k: getattr(info, k) for k, _ in LMInfo._fields_}
@@ -225,6 +229,22 @@ def ba_get_jacobians(ctx):
     e = np.empty((s["n_obs"], 2))
     _check(lib().ba_get_jacobians(ctx, _np_ptr(J), _np_ptr(e)), ctx)
     return J, e
+
+
+def ba_get_gauge(ctx):
+    """Gauge vectors of the last linearization, FP64 [n_rows][7][9]."""
+    s = ba_get_sizes(ctx)
+    W = np.empty((max(s["n_rows"], 1), 7, 9))
+    _check(lib().ba_get_gauge(ctx, _np_ptr(W)), ctx)
+    return W[: s["n_rows"]]
+
+
+def ba_get_fsai(ctx):
+    """FSAI factor of the current RCS, FP32 [n_blk][9][9] in the RCS block slots."""
+    s = ba_get_sizes(ctx)
+    G = np.empty((max(s["n_blk"], 1), 9, 9), np.float32)
+    _check(lib().ba_get_fsai(ctx, _np_ptr(G)), ctx)
+    return G[: s["n_blk"]]
 
 
 def ba_get_stage_ms(ctx):

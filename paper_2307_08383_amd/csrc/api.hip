@@ -55,9 +55,11 @@ void free_ctx(ba_ctx* c) {
     void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->pt_ptr, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
                     c->sp_ptr, c->sp_ent, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
-                    c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r, c->pcg.z,
-                    c->pcg.q, c->pcg.d[0], c->pcg.d[1], c->pcg.pA, c->pcg.pB[0], c->pcg.pB[1], c->pcg.state,
-                    c->pcg.scal};
+                    c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
+                    c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
+                    c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
+                    c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
+                    c->fs.gl_ent, c->fs.gu_ent, c->fs.An, c->fs.G};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -226,6 +228,8 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         tb.swap(tb2);
     }
     c->n_seg_wg = (c->n_offseg + 15) / 16;
+    c->h_blk_pairs.assign(c->n_blk, 0);
+    for (int32_t sg = 0; sg < c->n_offseg; ++sg) c->h_blk_pairs[off_blk[sg]] = pair_ptr[sg + 1] - pair_ptr[sg];
     // observations of each RCS row
     std::vector<int32_t> rowobs_ptr(nr + 1, 0), rowobs;
     for (int64_t k = 0; k < n; ++k)
@@ -311,6 +315,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &c->blk, (size_t)c->n_blk * 81);
     dalloc(c, &c->rhs, (size_t)nr * 9);
     dalloc(c, &c->Minv, (size_t)nr * 81);
+    dalloc(c, &c->Linv, (size_t)nr * 81);
     dalloc(c, &c->dxc, (size_t)nr * 9);
     dalloc(c, &c->dxp, (size_t)np * 3);
     c->n_part = (int32_t)(3 * ((n + 255) / 256) + 8);
@@ -319,14 +324,20 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &c->flags, 8);
     Pcg& P = c->pcg;
     dalloc(c, &P.x, (size_t)nr * 9);
-    dalloc(c, &P.r, (size_t)nr * 9);
+    dalloc(c, &P.r[0], (size_t)nr * 9);
+    dalloc(c, &P.r[1], (size_t)nr * 9);
     dalloc(c, &P.z, (size_t)nr * 9);
     dalloc(c, &P.q, (size_t)nr * 9);
-    dalloc(c, &P.d[0], (size_t)nr * 9);
-    dalloc(c, &P.d[1], (size_t)nr * 9);
-    dalloc(c, &P.pA, (size_t)nr + 8);
-    dalloc(c, &P.pB[0], 8 * ((size_t)nr / 28 + 2));
-    dalloc(c, &P.pB[1], 8 * ((size_t)nr / 28 + 2));
+    dalloc(c, &P.d, (size_t)nr * 9);
+    dalloc(c, &P.t, (size_t)nr * 9);
+    dalloc(c, &P.pA, 1024);
+    dalloc(c, &P.pR, 2 * 9 * 1024);
+    dalloc(c, &P.W, (size_t)nr * 63);
+    dalloc(c, &P.SW, (size_t)nr * 63);
+    dalloc(c, &P.Einv, 49);
+    dalloc(c, &P.pW, 7 * 1024);
+    dalloc(c, &P.pE, 49 * 1024);
+    dalloc(c, &c->lin_cams, (size_t)c->n_cams * 9);
     dalloc(c, &P.state, 8);
     dalloc(c, &P.scal, 8);
     BA_HIP_CHECK(hipHostMalloc((void**)&c->h_scal, 32 * sizeof(double), hipHostMallocDefault));
@@ -375,8 +386,28 @@ ba_status form_rcs_async(ba_ctx* c, double lambda) {
     BA_HIP_CHECK(hipEventRecord(c->ev[4], c->stream));
     BA_HIP_CHECK(hipGetLastError());
     c->have_rcs = true;
+    c->fs.ready = false;
+    c->defl_ready = false;
     c->lambda = lambda;
     return BA_OK;
+}
+
+void prepare_defl(ba_ctx* c) {
+    if (!c->defl_ready) {
+        ba::prepare_deflation(c);
+        BA_HIP_CHECK(hipGetLastError());
+        c->defl_ready = true;
+    }
+}
+
+// the FSAI factor of the current RCS (index structure on first use)
+void prepare_fsai(ba_ctx* c) {
+    if (!c->fs.built) ba::build_fsai(c);
+    if (!c->fs.ready) {
+        ba::launch_fsai(c);
+        BA_HIP_CHECK(hipGetLastError());
+        c->fs.ready = true;
+    }
 }
 
 // network inference on the current RCS -> Mlearn (context stream)
@@ -387,6 +418,96 @@ void prepare_learned(ba_ctx* c) {
 }
 
 }  // namespace
+
+namespace ba {
+
+// Index structure of the FSAI factor (host, once per context): the sets J_i
+// (lower neighbours with the most common points, ties to the lower index,
+// then ascending, then i), the G slot of each member, the local tiles and
+// the gather lists of G (lower, per row) and G^T (upper, per row).
+void build_fsai(ba_ctx* c) {
+    const int32_t nr = c->n_rows;
+    const std::vector<int64_t>& rp = c->h_row_ptr;
+    const std::vector<int32_t>& ci = c->h_col_idx;
+    const std::vector<int32_t>& cnt = c->h_blk_pairs;
+    std::vector<std::vector<std::pair<int32_t, int64_t>>> low(nr);
+    std::vector<int32_t> brow(c->n_blk);
+    for (int32_t r = 0; r < nr; ++r)
+        for (int64_t kb = rp[r]; kb < rp[r + 1]; ++kb) {
+            brow[kb] = r;
+            if (kb > rp[r]) low[ci[kb]].push_back({r, kb});
+        }
+    std::vector<int32_t> ptr(nr + 1, 0), J, slot, tile;
+    std::vector<int64_t> tptr(nr + 1, 0);
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> gu(nr);
+    int32_t max_m = 1;
+    for (int32_t i = 0; i < nr; ++i) {
+        auto& L = low[i];
+        std::sort(L.begin(), L.end(), [&](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) {
+            const int32_t cx = cnt[x.second], cy = cnt[y.second];
+            return cx != cy ? cx > cy : x.first < y.first;
+        });
+        if ((int)L.size() > kFsaiM - 1) L.resize(kFsaiM - 1);
+        std::sort(L.begin(), L.end());
+        const int32_t m = (int32_t)L.size() + 1;
+        max_m = std::max(max_m, m);
+        std::vector<int32_t> Jm;
+        for (auto& e : L) {
+            Jm.push_back(e.first);
+            slot.push_back((int32_t)e.second);
+        }
+        Jm.push_back(i);
+        slot.push_back((int32_t)rp[i]);
+        J.insert(J.end(), Jm.begin(), Jm.end());
+        ptr[i + 1] = ptr[i] + m;
+        for (int32_t a = 0; a < m; ++a)
+            for (int32_t b = 0; b <= a; ++b) {
+                if (a == b) {
+                    tile.push_back(-2);
+                    continue;
+                }
+                const int32_t jb = Jm[b], ja = Jm[a];   // jb < ja: upper block (jb, ja)
+                auto first = ci.begin() + rp[jb] + 1, last = ci.begin() + rp[jb + 1];
+                auto it = std::lower_bound(first, last, ja);
+                tile.push_back(it != last && *it == ja ? (int32_t)(it - ci.begin()) : -1);
+            }
+        tptr[i + 1] = tptr[i] + (int64_t)m * (m + 1) / 2;
+        for (int32_t b = 0; b < m; ++b) gu[Jm[b]].push_back({slot[ptr[i] + b], (i << 1) | 1});
+    }
+    int32_t gus = 1;
+    for (auto& g : gu) gus = std::max(gus, (int32_t)g.size());
+    std::vector<int32_t> gl_ent(2 * (size_t)nr * max_m, -1), gu_ent(2 * (size_t)nr * gus, -1);
+    for (int32_t i = 0; i < nr; ++i) {
+        for (int32_t b = 0; b < ptr[i + 1] - ptr[i]; ++b) {
+            const size_t d = (size_t)i * max_m + b;
+            gl_ent[2 * d] = slot[ptr[i] + b];
+            gl_ent[2 * d + 1] = J[ptr[i] + b] << 1;
+        }
+        for (size_t b = 0; b < gu[i].size(); ++b) {
+            const size_t d = (size_t)i * gus + b;
+            gu_ent[2 * d] = gu[i][b].first;
+            gu_ent[2 * d + 1] = gu[i][b].second;
+        }
+    }
+    Fsai& F = c->fs;
+    upload(c, &F.ptr, ptr);
+    upload(c, &F.J, J);
+    upload(c, &F.slot, slot);
+    upload(c, &F.tptr, tptr);
+    upload(c, &F.tile, tile);
+    upload(c, &F.brow, brow);
+    upload(c, &F.gl_ent, gl_ent);
+    upload(c, &F.gu_ent, gu_ent);
+    F.gl_stride = max_m;
+    F.gu_stride = gus;
+    F.max_m = max_m;
+    dalloc(c, &F.An, (size_t)c->n_blk * 81);
+    dalloc(c, &F.G, (size_t)c->n_blk * 81);
+    BA_HIP_CHECK(hipMemsetAsync(F.G, 0, (size_t)c->n_blk * 81 * sizeof(float), c->stream));
+    F.built = true;
+}
+
+}  // namespace ba
 
 extern "C" {
 
@@ -510,6 +631,9 @@ ba_status ba_linearize(ba_ctx* c, const double* cams, const double* pts, double*
     return guarded(c, [&]() {
         BA_HIP_CHECK(hipEventRecord(c->ev[0], c->stream));
         ba::launch_linearize(c, cams, pts);
+        BA_HIP_CHECK(hipMemcpyAsync(c->lin_cams, cams, (size_t)c->n_cams * 9 * sizeof(double),
+                                    hipMemcpyDeviceToDevice, c->stream));
+        c->defl_ready = false;
         BA_HIP_CHECK(hipEventRecord(c->ev[5], c->stream));
         BA_HIP_CHECK(hipGetLastError());
         c->have_lin = true;
@@ -558,16 +682,22 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
     const int pre = o ? o->precond : BA_PRECOND_BLOCK_JACOBI;
     if (!(tol >= 0.0) || max_iter < 0) { c->err = "tol must be >= 0 and max_iter >= 0"; return BA_ERR_INVALID_ARG; }
     if (pre == BA_PRECOND_LEARNED && !c->learned_ready) { c->err = "no learned preconditioner set"; return BA_ERR_STATE; }
-    if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI) { c->err = "unknown preconditioner"; return BA_ERR_INVALID_ARG; }
+    if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI && pre != BA_PRECOND_FSAI) {
+        c->err = "unknown preconditioner";
+        return BA_ERR_INVALID_ARG;
+    }
     return guarded(c, [&]() {
         int it = 0;
         double rr = 0.0;
         if (pre == BA_PRECOND_LEARNED && c->n_rows > 0) prepare_learned(c);
+        if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
+        const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
+        if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(c->ev[6], c->stream));
         ba_status s = BA_OK;
         if (c->n_rows > 0)
-            s = ba::run_pcg(c, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, tol, max_iter, o ? o->x0 : nullptr,
-                            dxc, &it, &rr);
+            s = ba::run_pcg(c, pre == BA_PRECOND_FSAI ? 1 : 0, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, defl,
+                            tol, max_iter, o ? o->x0 : nullptr, dxc, &it, &rr);
         BA_HIP_CHECK(hipEventRecord(c->ev[7], c->stream));
         BA_HIP_CHECK(hipEventSynchronize(c->ev[7]));
         if (info) {
@@ -604,6 +734,10 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
     const int max_iter = o ? o->pcg_max_iter : 1000;
     const int pre = o ? o->precond : BA_PRECOND_BLOCK_JACOBI;
     if (pre == BA_PRECOND_LEARNED && !c->learned_ready) { c->err = "no learned preconditioner set"; return BA_ERR_STATE; }
+    if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI && pre != BA_PRECOND_FSAI) {
+        c->err = "unknown preconditioner";
+        return BA_ERR_INVALID_ARG;
+    }
     return guarded(c, [&]() {
         ba_lm_info I;
         std::memset(&I, 0, sizeof I);
@@ -611,7 +745,12 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         BA_HIP_CHECK(hipEventRecord(ev[8], c->stream));
         const bool relin = !(st->flags & 1) || !c->have_lin;
         BA_HIP_CHECK(hipEventRecord(ev[0], c->stream));
-        if (relin) ba::launch_linearize(c, cams, pts);
+        if (relin) {
+            ba::launch_linearize(c, cams, pts);
+            BA_HIP_CHECK(hipMemcpyAsync(c->lin_cams, cams, (size_t)c->n_cams * 9 * sizeof(double),
+                                        hipMemcpyDeviceToDevice, c->stream));
+            c->defl_ready = false;
+        }
         BA_HIP_CHECK(hipEventRecord(ev[5], c->stream));
         c->have_lin = true;
         form_rcs_async(c, st->lambda);
@@ -620,9 +759,13 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         ba_status ps = BA_OK;
         BA_HIP_CHECK(hipEventRecord(ev[14], c->stream));
         if (pre == BA_PRECOND_LEARNED && c->n_rows > 0) prepare_learned(c);
+        if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
+        const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
+        if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(ev[6], c->stream));
         if (c->n_rows > 0)
-            ps = ba::run_pcg(c, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, tol, max_iter, nullptr, c->dxc, &it, &rr);
+            ps = ba::run_pcg(c, pre == BA_PRECOND_FSAI ? 1 : 0, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, defl,
+                             tol, max_iter, nullptr, c->dxc, &it, &rr);
         else
             BA_HIP_CHECK(hipMemsetAsync(c->dxc, 0, sizeof(double), c->stream));
         BA_HIP_CHECK(hipEventRecord(ev[7], c->stream));
@@ -668,7 +811,7 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         I.ms_back_substitute = elapsed(ev[7], ev[9]);
         I.ms_evaluate = elapsed(ev[9], ev[10]);
         I.ms_total = elapsed(ev[8], ev[11]);
-        I.ms_precond = pre == BA_PRECOND_LEARNED ? elapsed(ev[14], ev[6]) : 0.0;
+        I.ms_precond = (pre != BA_PRECOND_BLOCK_JACOBI || (o && o->deflate)) ? elapsed(ev[14], ev[6]) : 0.0;
         if (info) *info = I;
         return BA_OK;
     });
@@ -687,6 +830,28 @@ ba_status ba_get_rcs(ba_ctx* c, double* blk, double* rhs) {
     return guarded(c, [&]() {
         if (blk) BA_HIP_CHECK(hipMemcpyAsync(blk, c->blk, c->n_blk * 81 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         if (rhs) BA_HIP_CHECK(hipMemcpyAsync(rhs, c->rhs, (size_t)c->n_rows * 9 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        return BA_OK;
+    });
+}
+
+ba_status ba_get_gauge(ba_ctx* c, double* W) {
+    if (!c || !W) return BA_ERR_INVALID_ARG;
+    if (!c->have_rcs) { c->err = "no RCS formed"; return BA_ERR_STATE; }
+    return guarded(c, [&]() {
+        if (c->n_rows > 0) prepare_defl(c);
+        BA_HIP_CHECK(hipMemcpyAsync(W, c->pcg.W, (size_t)c->n_rows * 63 * sizeof(double), hipMemcpyDeviceToHost,
+                                    c->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        return BA_OK;
+    });
+}
+
+ba_status ba_get_fsai(ba_ctx* c, float* G) {
+    if (!c || !G) return BA_ERR_INVALID_ARG;
+    if (!c->fs.ready) { c->err = "no FSAI factor of the current RCS"; return BA_ERR_STATE; }
+    return guarded(c, [&]() {
+        BA_HIP_CHECK(hipMemcpyAsync(G, c->fs.G, (size_t)c->n_blk * 81 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
         BA_HIP_CHECK(hipStreamSynchronize(c->stream));
         return BA_OK;
     });

@@ -179,11 +179,33 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // context
 // ---------------------------------------------------------------------------
 struct Pcg {
-    double *x = nullptr, *r = nullptr, *z = nullptr, *q = nullptr, *d[2] = {nullptr, nullptr};
-    double *pA = nullptr, *pB[2] = {nullptr, nullptr};
-    int* state = nullptr;      // [0] done, [1] iterations, [2] status
+    double *x = nullptr, *r[2] = {nullptr, nullptr}, *z = nullptr, *q = nullptr, *d = nullptr, *t = nullptr;
+    double* pA = nullptr;      // per-block partials of d^T q
+    double* pR = nullptr;      // per-block partials of r^T z, r^T r, (S W)^T z, two step parities
+    double *W = nullptr, *SW = nullptr;   // gauge vectors and S W, [n_rows][7][9]
+    double *Einv = nullptr, *pW = nullptr, *pE = nullptr;
+    int* state = nullptr;      // [0] done, [1] step, [2] status, [3] completed steps
     double* scal = nullptr;    // [0] r0^2, [1] final relres
-    int nA = 0, nB = 0;        // partial counts of the two kernels
+};
+
+// Factorised sparse approximate inverse G (M^-1 = G^T G) on the lower RCS
+// pattern.  Row i's set J_i: at most kFsaiM - 1 lower neighbours (the ones
+// with the most common points) and i itself, ascending.
+constexpr int kFsaiM = 28;
+constexpr int kFsaiTiles = kFsaiM * (kFsaiM + 1) / 2;
+struct Fsai {
+    bool built = false, ready = false;
+    int32_t *ptr = nullptr;           // [n_rows+1] into J / slot
+    int32_t *J = nullptr;             // members of each set
+    int32_t *slot = nullptr;          // block slot of G_{i, J_b}: upper block (J_b, i), or i's diagonal
+    int64_t *tptr = nullptr;          // [n_rows+1] into tile
+    int32_t *tile = nullptr;          // per set, lower tiles (a, b), a >= b, packed a(a+1)/2 + b:
+                                      // upper block (J_b, J_a), -2 on the diagonal, -1 if absent
+    int32_t *brow = nullptr;          // [n_blk] block row of every RCS block
+    int32_t *gl_ent = nullptr, *gu_ent = nullptr;   // (slot, vector row << 1 | transposed)
+    int32_t gl_stride = 0, gu_stride = 0, max_m = 0;
+    float* An = nullptr;              // [n_blk][81] L_r^-1 S_rc L_c^-T of off-diagonal blocks
+    float* G = nullptr;               // [n_blk][81] G in the upper slots
 };
 
 }  // namespace ba
@@ -220,6 +242,10 @@ struct ba_ctx {
     int32_t n_seg_wg = 0;              // workgroups of the pair stage (XCD-ordered)
     double* ptL = nullptr;             // [n_pts][9]: Cholesky of V* (6), L^-1 l_p (3)
     double *blk = nullptr, *rhs = nullptr, *Minv = nullptr, *Mlearn = nullptr;
+    double* Linv = nullptr;            // [n_rows][81] L_i^-1 (lower) of S_ii = L_i L_i^T
+    double* lin_cams = nullptr;        // [n_cams][9] camera parameters of the last linearization
+    bool defl_ready = false;
+    std::vector<int32_t> h_blk_pairs;  // common points of every block (diagonal: 0)
     // LM
     double *dxc = nullptr, *dxp = nullptr, *part = nullptr, *scal = nullptr;
     int* flags = nullptr;
@@ -227,11 +253,14 @@ struct ba_ctx {
     int* h_flags = nullptr;            // pinned
     int32_t n_part = 0;
     ba::Pcg pcg;
+    ba::Fsai fs;
     hipEvent_t ev[16] = {};
     hipStream_t capture_stream = nullptr;
     bool use_graphs = true;
     struct PcgGraph {
         const double* M;
+        int mode;
+        int defl;
         double tol;
         int max_iter;
         hipGraphExec_t exec;
@@ -256,9 +285,17 @@ void launch_diag(ba_ctx* c, double lambda);
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp);
 void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const double* dxc, const double* dxp);
 void launch_update(ba_ctx* c, double* cams, double* pts, const double* dxc, const double* dxp);
-// PCG: returns status; fills iters/relres (synchronises)
-ba_status run_pcg(ba_ctx* c, const double* Mblocks, double tol, int max_iter, const double* x0,
-                  double* out, int* iters, double* relres);
+// PCG: returns status; fills iters/relres (synchronises).  mode 0: block
+// diagonal M^-1 (Mblocks [n_rows][81]); mode 1: M^-1 = G^T G from c->fs.
+// defl: deflate the similarity gauge (prepare_deflation first).
+ba_status run_pcg(ba_ctx* c, int mode, const double* Mblocks, int defl, double tol, int max_iter,
+                  const double* x0, double* out, int* iters, double* relres);
+// gauge vectors of the last linearization's cameras, S W and (W^T S W)^-1
+void prepare_deflation(ba_ctx* c);
+// FSAI: index structure (host, once per context) and the factor of the
+// current RCS (stream-ordered)
+void build_fsai(ba_ctx* c);
+void launch_fsai(ba_ctx* c);
 
 }  // namespace ba
 

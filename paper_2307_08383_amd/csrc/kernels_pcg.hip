@@ -1,5 +1,5 @@
-// Block-diagonal preconditioned CG on the RCS (Sec. 3.2, Eq. (6)-(7)) with
-// the symmetric block product of Sec. 6.2 on upper-triangle storage.
+// Preconditioned CG on the RCS (Sec. 3.2, Eq. (6)-(7)) with the symmetric
+// block product of Sec. 6.2 on upper-triangle storage.
 //
 // Recurrence (Sec. 3.2): y0 = 0, r0 = b, z0 = M^-1 r0, d0 = z0; per step
 //   alpha = r^T z / d^T S d;  y += alpha d;  r -= alpha S d;
@@ -8,14 +8,34 @@
 // S d is formed as q_k = S z_k + beta q_{k-1} (the same vector, since
 // d_k = z_k + beta d_{k-1}), so the block product only reads z.
 //
-// One iteration is two kernels and no host round trip:
-//   A: s = S z (one 256-thread block per block row), q = s + beta q,
-//      d = z + beta d, partial d^T q; also the stop test and iteration cap.
-//   B: alpha = rz / d^T q; y += alpha d; r -= alpha q; z = M^-1 r;
-//      partial r^T z and r^T r; the iteration counter.
-// The iteration number lives in device memory, so a batch of iterations is
-// one fixed HIP graph.  Every block re-sums the partials of the previous
-// kernel in the same order, so all blocks take the same decisions.
+// Two preconditioners:
+//   block-diagonal M^-1 (block-Jacobi inverses, or the learned blocks):
+//     A: s = S z (one wave per block row), q = s + beta q, d = z + beta d,
+//        d^T q; also the stop test and the iteration cap.
+//     B: alpha = rz / d^T q; y += alpha d; r -= alpha q; z = M^-1 r;
+//        r^T z and r^T r; the iteration counter.
+//   factorised M^-1 = G^T G (G block-lower-triangular, FP32 blocks):
+//     A as above;
+//     Bf: alpha; y += alpha d; r' = r - alpha q into the other r buffer;
+//         t = G r' gathered over the row's lower blocks (r' of a neighbour
+//         is formed from its r and q, which are complete); r'^T r'.
+//     Cf: z = G^T t gathered over the row's upper blocks; r'^T z; counter.
+//
+// Optional deflation of the similarity gauge (Saad, Yeung, Erhel and
+// Guyomarc'h's deflated CG): with W the seven gauge vectors of the cameras
+// (camera parts of the null space of J, Eq. (1)), E = W^T S W,
+//   x0 = x_s + W E^-1 W^T r_s, r0 = r_s - (S W) E^-1 W^T r_s,
+//   p = z + beta p - W mu, q = S z + beta q - (S W) mu, mu = E^-1 (S W)^T z,
+// so that W^T r stays zero; (S W)^T z rides along with r^T z.
+//
+// All kernels run the same fixed number of blocks (grid-stride over rows)
+// and leave one partial per block for each scalar product; every block of
+// the next kernel re-sums those partials in the same order, so all blocks
+// take the same decisions and the sums are deterministic.  The iteration
+// number lives in device memory, so a batch of iterations is one fixed HIP
+// graph.
+#include <algorithm>
+
 #include "ba_common.hpp"
 
 namespace ba {
@@ -23,66 +43,121 @@ namespace ba {
 namespace {
 
 constexpr int BS = 256;
-constexpr int GRP = BS / 9;       // 28 lane groups per row in kernel A
-constexpr int RPB = BS / 9;       // rows per block in kernel B (9 threads per row)
+constexpr int WPB = BS / kWave;    // 4 waves per block: one row each in the gathers
+constexpr int GRPW = kWave / 9;    // 7 lane groups of 9 per wave
+constexpr int RPB = BS / 9;        // 28 rows per block pass in kernels init and B
+constexpr int kMaxGrid = 1024;   // the partial buffers hold this many blocks
 
-// state: [0] done, [1] step index as published by kernel A (read by B),
-//        [2] status, [3] completed steps as published by kernel B (read by
-//        the next A).  No kernel writes a word that its own blocks read.
+// state: [0] done, [1] step index as published by kernel A (read by B, Bf,
+//        Cf), [2] status, [3] completed steps as published by B or Cf
+//        (read by the next A).  No kernel writes a word that its own blocks
+//        read.
 // scal:  [0] |r0|^2, [1] final relative residual
+// partials: pA[g] (d^T q of block g), pR[p][g][0..8] (r^T z, r^T r and
+//        (S W)^T z of the step with parity p)
+constexpr int NP = 9;
+constexpr int kW = 7;      // gauge vectors
 
-template <int N>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ const* src, const int* n, const int* stride,
-                                             double* out, double* sh) {
-    double s[N];
+// Fixed-order sum of NV interleaved partial streams of n blocks
+// (src[i * stride + j]); every thread gets the totals.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ src, int n, int stride, double* out,
+                                             double* sh) {
+    double s[NV];
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
-        s[j] = 0.0;
-        for (int i = threadIdx.x; i < n[j]; i += BS) s[j] += src[j][(int64_t)i * stride[j]];
-    }
+    for (int j = 0; j < NV; ++j) s[j] = 0.0;
+    for (int i = threadIdx.x; i < n; i += BS)
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
+        for (int j = 0; j < NV; ++j) s[j] += src[(int64_t)i * stride + j];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
         const double v = wave_sum(s[j]);
-        if ((threadIdx.x % kWave) == 0) sh[j * (BS / kWave) + threadIdx.x / kWave] = v;
+        if (threadIdx.x % kWave == 0) sh[j * WPB + threadIdx.x / kWave] = v;
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < N; ++j) {
+    for (int j = 0; j < NV; ++j) {
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < BS / kWave; ++w) t += sh[j * (BS / kWave) + w];
+        for (int w = 0; w < WPB; ++w) t += sh[j * WPB + w];
         out[j] = t;
     }
     __syncthreads();
 }
 
-// s_row = sum over the row's entries, result in sacc[BS..BS+8] (after sync).
-// Entries are taken two per lane group per round; both entries of a round,
-// then both blocks and vector rows, are requested before any is used.
-__device__ __forceinline__ void row_product(int row, int ent_stride, const int2* __restrict__ ent,
-                                            const double* __restrict__ blk, const double* __restrict__ x, double* sacc) {
-    const int grp = threadIdx.x / 9, comp = threadIdx.x % 9;
+// Block totals of NV per-thread values (fixed shuffle tree, then fixed wave
+// order); valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_totals(const double* v, double* out, double* sh) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const double w = wave_sum(v[j]);
+        if (threadIdx.x % kWave == 0) sh[j * WPB + threadIdx.x / kWave] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < NV; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < WPB; ++w) t += sh[j * WPB + w];
+            out[j] = t;
+        }
+    __syncthreads();
+}
+
+// Block total of per-wave values held in lane 0 of each wave (fixed order);
+// valid in thread 0.
+__device__ __forceinline__ double block_total(double wave_value, double* sh) {
+    if (threadIdx.x % kWave == 0) sh[threadIdx.x / kWave] = wave_value;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int w = 0; w < WPB; ++w) t += sh[w];
+    __syncthreads();
+    return t;
+}
+
+// Row gather by one wave: y[c] = sum over the row's entries e of
+// (B_e or B_e^T) v_e, returned in lanes 0..8 (component c = lane).
+// Entries are (block, vector row << 1 | transposed), padded with block -1;
+// v_e is v0[row] (VM == 0) or v0[row] - alpha v1[row] (VM == 1), vector
+// rows vs apart.  Lane
+// group g (lanes 9g..9g+8) takes entries g, g + 7, ...; two entries per
+// round, both requested before either is used.
+template <typename TB, int VM>
+__device__ __forceinline__ double row_gather(int row, int stride, const int2* __restrict__ ent,
+                                             const TB* __restrict__ blk, const double* __restrict__ v0,
+                                             const double* __restrict__ v1, double alpha, int vs = 9) {
+    const int lane = threadIdx.x % kWave;
+    const int grp = lane / 9, comp = lane % 9;
     double acc = 0.0;
-    if (grp < GRP) {
-        const int2* er = ent + (int64_t)row * ent_stride;
-        for (int e = grp; e < ent_stride; e += 2 * GRP) {
+    if (grp < GRPW) {
+        const int2* er = ent + (int64_t)row * stride;
+        for (int e = grp; e < stride; e += 2 * GRPW) {
             const int2 na = er[e];
-            const int2 nb = (e + GRP < ent_stride) ? er[e + GRP] : make_int2(-1, 0);
+            const int2 nb = (e + GRPW < stride) ? er[e + GRPW] : make_int2(-1, 0);
             if (na.x < 0) break;   // padding: the rest of the row is empty
             const bool hb = nb.x >= 0;
-            const double* Sa = blk + (int64_t)na.x * 81;
-            const double* Sb = blk + (int64_t)(hb ? nb.x : na.x) * 81;
-            const double* xa = x + (int64_t)(na.y >> 1) * 9;
-            const double* xb = x + (int64_t)((hb ? nb.y : na.y) >> 1) * 9;
+            const TB* Sa = blk + (int64_t)na.x * 81;
+            const TB* Sb = blk + (int64_t)(hb ? nb.x : na.x) * 81;
+            const int64_t ia = (int64_t)(na.y >> 1) * vs;
+            const int64_t ib = (int64_t)((hb ? nb.y : na.y) >> 1) * vs;
             const int sa_row = (na.y & 1) ? 1 : 9, sa_col = (na.y & 1) ? 9 : 1;
             const int sb_row = (nb.y & 1) ? 1 : 9, sb_col = (nb.y & 1) ? 9 : 1;
             double va[9], vb[9], ya[9], yb[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) {
-                va[c] = Sa[comp * sa_row + c * sa_col];
-                vb[c] = Sb[comp * sb_row + c * sb_col];
-                ya[c] = xa[c];
-                yb[c] = xb[c];
+                va[c] = (double)Sa[comp * sa_row + c * sa_col];
+                vb[c] = (double)Sb[comp * sb_row + c * sb_col];
+                if (VM == 0) {
+                    ya[c] = v0[ia + c];
+                    yb[c] = v0[ib + c];
+                } else {
+                    ya[c] = v0[ia + c] - alpha * v1[ia + c];
+                    yb[c] = v0[ib + c] - alpha * v1[ib + c];
+                }
             }
 #pragma unroll
             for (int c = 0; c < 9; ++c) acc += va[c] * ya[c];
@@ -92,121 +167,305 @@ __device__ __forceinline__ void row_product(int row, int ent_stride, const int2*
             }
         }
     }
-    sacc[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x < 9) {
-        double v = 0.0;
-        for (int g = 0; g < GRP; ++g) v += sacc[g * 9 + threadIdx.x];
-        sacc[BS + threadIdx.x] = v;
+    // lanes 0..8: sum over the 7 groups in group order
+    double tot = acc;
+#pragma unroll
+    for (int g = 1; g < GRPW; ++g) {
+        const double o = __shfl(acc, lane + 9 * g < kWave ? lane + 9 * g : lane, kWave);
+        tot += o;
     }
-    __syncthreads();
+    return tot;
 }
 
-__global__ __launch_bounds__(BS) void k_pcg_init(int n_rows, const double* __restrict__ rhs, const double* __restrict__ q,
-                                                 const double* __restrict__ x0, const double* __restrict__ M,
-                                                 double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
-                                                 double* __restrict__ pB, int* __restrict__ state,
-                                                 double* __restrict__ scal) {
-    __shared__ double sr[RPB][9];
-    __shared__ double sh[BS / kWave];
-    const int lr = threadIdx.x / 9, i = threadIdx.x % 9;
-    const int row = blockIdx.x * RPB + lr;
-    const bool act = threadIdx.x < RPB * 9 && row < n_rows;
-    double rv = 0.0;
-    if (act) {
-        const int64_t o = (int64_t)row * 9 + i;
-        rv = rhs[o] - (q ? q[o] : 0.0);
-        x[o] = x0 ? x0[o] : 0.0;
-        r[o] = rv;
-        sr[lr][i] = rv;
+// ---------------------------------------------------------------------------
+// gauge deflation set-up
+// ---------------------------------------------------------------------------
+
+// W [n_rows][7][9]: rotation generators (dw = -J_r(w)^-1 e_k), translation
+// generators (dt = -R e_k), scale (dt = t) of every free camera, from the
+// parameters of the last linearization.  J_r^-1 = I + K/2 + c K^2,
+// K = [w]x, c = 1/th^2 - (1 + cos th) / (2 th sin th), with its series
+// near th = 0 and its limit near th = pi.
+__global__ void k_gauge_W(int n_cams, const int32_t* __restrict__ cam_row, const double* __restrict__ cams,
+                          double* __restrict__ W) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_cams) return;
+    const int row = cam_row[c];
+    if (row < 0) return;
+    const double* p = cams + (int64_t)c * 9;
+    const double w0 = p[0], w1 = p[1], w2 = p[2];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+    double a, b, cc;   // R = I + a K + b K^2; J_r^-1 = I + K/2 + cc K^2
+    if (th < 1e-4) {
+        a = 1.0 - th2 / 6.0;
+        b = 0.5 - th2 / 24.0;
+        cc = 1.0 / 12.0 + th2 / 720.0;
+    } else {
+        const double s = sin(th), co = cos(th);
+        a = s / th;
+        b = (1.0 - co) / th2;
+        const double dl = 3.14159265358979323846 - th;
+        cc = (fabs(dl) < 1e-4) ? 1.0 / th2 - dl / (4.0 * th) : 1.0 / th2 - (1.0 + co) / (2.0 * th * s);
+    }
+    const double K[9] = {0.0, -w2, w1, w2, 0.0, -w0, -w1, w0, 0.0};
+    double K2[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double t = 0.0;
+            for (int k = 0; k < 3; ++k) t += K[i * 3 + k] * K[k * 3 + j];
+            K2[i * 3 + j] = t;
+        }
+    double* Wr = W + (int64_t)row * kW * 9;
+    for (int i = 0; i < kW * 9; ++i) Wr[i] = 0.0;
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) {
+            const double id = i == k ? 1.0 : 0.0;
+            Wr[k * 9 + i] = -(id + 0.5 * K[i * 3 + k] + cc * K2[i * 3 + k]);   // -J_r^-1 e_k
+            Wr[(3 + k) * 9 + 3 + i] = -(id + a * K[i * 3 + k] + b * K2[i * 3 + k]);   // -R e_k
+        }
+    for (int i = 0; i < 3; ++i) Wr[6 * 9 + 3 + i] = p[3 + i];
+}
+
+// SW = S W, one wave per block row, the seven columns in turn
+__global__ __launch_bounds__(BS) void k_spmm_W(int n_rows, int ent_stride, const int2* __restrict__ ent,
+                                               const double* __restrict__ blk, const double* __restrict__ W,
+                                               double* __restrict__ SW) {
+    const int lane = threadIdx.x % kWave;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB)
+        for (int v = 0; v < kW; ++v) {
+            const double y = row_gather<double, 0>(row, ent_stride, ent, blk, W + v * 9, nullptr, 0.0, kW * 9);
+            if (lane < 9) SW[(int64_t)row * kW * 9 + v * 9 + lane] = y;
+        }
+}
+
+// partials of E = W^T S W (49 per block)
+__global__ __launch_bounds__(BS) void k_defl_E_part(int n_rows, const double* __restrict__ W,
+                                                    const double* __restrict__ SW, double* __restrict__ pE) {
+    __shared__ double sh[kW * kW * WPB];
+    double e[kW * kW];
+#pragma unroll
+    for (int j = 0; j < kW * kW; ++j) e[j] = 0.0;
+    const int64_t n = (int64_t)n_rows * 9;
+    for (int64_t idx = (int64_t)blockIdx.x * BS + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * BS) {
+        const int64_t row = idx / 9, c = idx % 9;
+        double wv[kW], sv[kW];
+#pragma unroll
+        for (int v = 0; v < kW; ++v) {
+            wv[v] = W[row * kW * 9 + v * 9 + c];
+            sv[v] = SW[row * kW * 9 + v * 9 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < kW; ++u)
+#pragma unroll
+            for (int v = 0; v < kW; ++v) e[u * kW + v] += wv[u] * sv[v];
+    }
+    double t[kW * kW];
+    block_totals<kW * kW>(e, t, sh);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < kW * kW; ++j) pE[(int64_t)blockIdx.x * kW * kW + j] = t[j];
+}
+
+// E from the partials (block order), symmetrised, then E^-1 by Cholesky
+// (one thread).  A non-positive pivot leaves E^-1 = 0: no deflation.
+__global__ void k_defl_E_fin(int n_part, const double* __restrict__ pE, double* __restrict__ Einv,
+                             int* __restrict__ flags) {
+    __shared__ double E[kW * kW];
+    const int j = threadIdx.x;
+    if (j < kW * kW) {
+        double t = 0.0;
+        for (int b = 0; b < n_part; ++b) t += pE[(int64_t)b * kW * kW + j];
+        E[j] = t;
     }
     __syncthreads();
-    double zv = 0.0;
-    if (act) {
-        const double* Mr = M + (int64_t)row * 81 + i * 9;
+    if (threadIdx.x != 0) return;
+    double L[kW * kW], X[kW * kW];
+    bool ok = true;
+    for (int a = 0; a < kW; ++a)
+        for (int b = 0; b <= a; ++b) {
+            double s = 0.5 * (E[a * kW + b] + E[b * kW + a]);
+            for (int k = 0; k < b; ++k) s -= L[a * kW + k] * L[b * kW + k];
+            if (a == b) {
+                if (!(s > 0.0)) { ok = false; s = 1.0; }
+                L[a * kW + a] = sqrt(s);
+            } else {
+                L[a * kW + b] = s / L[b * kW + b];
+            }
+        }
+    // E^-1 = L^-T L^-1, column by column
+    for (int col = 0; col < kW; ++col) {
+        double y[kW];
+        for (int a = 0; a < kW; ++a) {
+            double s = a == col ? 1.0 : 0.0;
+            for (int k = 0; k < a; ++k) s -= L[a * kW + k] * y[k];
+            y[a] = s / L[a * kW + a];
+        }
+        for (int a = kW - 1; a >= 0; --a) {
+            double s = y[a];
+            for (int k = a + 1; k < kW; ++k) s -= L[k * kW + a] * X[k * kW + col];
+            X[a * kW + col] = s / L[a * kW + a];
+        }
+    }
+    for (int i = 0; i < kW * kW; ++i) Einv[i] = ok ? X[i] : 0.0;
+    if (!ok) flags[3] = 1;
+}
+
+// partials of W^T r_s, r_s = rhs - q0 (7 per block)
+__global__ __launch_bounds__(BS) void k_defl_Wr(int n_rows, const double* __restrict__ rhs,
+                                                const double* __restrict__ q0, const double* __restrict__ W,
+                                                double* __restrict__ pW) {
+    __shared__ double sh[kW * WPB];
+    double a[kW];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) zv += Mr[c] * sr[lr][c];
-        z[(int64_t)row * 9 + i] = zv;
-    }
-    double rz = rv * zv, rr = rv * rv;
+    for (int v = 0; v < kW; ++v) a[v] = 0.0;
+    const int64_t n = (int64_t)n_rows * 9;
+    for (int64_t idx = (int64_t)blockIdx.x * BS + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * BS) {
+        const int64_t row = idx / 9, c = idx % 9;
+        const double rs = rhs[idx] - (q0 ? q0[idx] : 0.0);
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        rz += __shfl_xor(rz, off, kWave);
-        rr += __shfl_xor(rr, off, kWave);
+        for (int v = 0; v < kW; ++v) a[v] += W[row * kW * 9 + v * 9 + c] * rs;
     }
-    if ((threadIdx.x % kWave) == 0) {
-        const int w = blockIdx.x * (BS / kWave) + threadIdx.x / kWave;
-        pB[2 * w] = rz;
-        pB[2 * w + 1] = rr;
+    double t[kW];
+    block_totals<kW>(a, t, sh);
+    if (threadIdx.x == 0)
+        for (int v = 0; v < kW; ++v) pW[(int64_t)blockIdx.x * kW + v] = t[v];
+}
+
+// mu = E^-1 a (7x7), every thread
+__device__ __forceinline__ void einv_apply(const double* __restrict__ Einv, const double* a, double* mu) {
+#pragma unroll
+    for (int u = 0; u < kW; ++u) {
+        double t = 0.0;
+#pragma unroll
+        for (int v = 0; v < kW; ++v) t += Einv[u * kW + v] * a[v];
+        mu[u] = t;
     }
+}
+
+// ---------------------------------------------------------------------------
+// PCG kernels
+// ---------------------------------------------------------------------------
+
+// x = x_s (x0 or 0), r = rhs - q0 (q0 = S x0, or 0); deflated: x += W y,
+// r -= SW y with y = E^-1 W^T r_s.  With a block-diagonal preconditioner
+// also z = M^-1 r; partials of r^T z, r^T r, (SW)^T z (parity 0); the state.
+__global__ __launch_bounds__(BS) void k_pcg_init(int n_rows, const double* __restrict__ rhs,
+                                                 const double* __restrict__ q0, const double* __restrict__ x0,
+                                                 const double* __restrict__ M, double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ z,
+                                                 double* __restrict__ pR, int* __restrict__ state,
+                                                 double* __restrict__ scal, int defl, const double* __restrict__ W,
+                                                 const double* __restrict__ SW, const double* __restrict__ Einv,
+                                                 const double* __restrict__ pW, int n_part) {
+    __shared__ double sr[RPB][9];
+    __shared__ double sh[NP * WPB];
+    double y[kW];
+#pragma unroll
+    for (int v = 0; v < kW; ++v) y[v] = 0.0;
+    if (defl) {
+        double a[kW];
+        sum_partials<kW>(pW, n_part, kW, a, sh);
+        einv_apply(Einv, a, y);
+    }
+    const int lr = threadIdx.x / 9, i = threadIdx.x % 9;
+    double acc[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) acc[j] = 0.0;
+    for (int base = blockIdx.x * RPB; base < n_rows; base += gridDim.x * RPB) {
+        const int row = base + lr;
+        const bool act = threadIdx.x < RPB * 9 && row < n_rows;
+        const int64_t o = (int64_t)row * 9 + i;
+        double rv = 0.0;
+        if (act) {
+            double xv = x0 ? x0[o] : 0.0;
+            rv = rhs[o] - (q0 ? q0[o] : 0.0);
+            if (defl) {
+                const double* Wr = W + (int64_t)row * kW * 9 + i;
+                const double* Sr = SW + (int64_t)row * kW * 9 + i;
+#pragma unroll
+                for (int v = 0; v < kW; ++v) {
+                    xv += Wr[v * 9] * y[v];
+                    rv -= Sr[v * 9] * y[v];
+                }
+            }
+            x[o] = xv;
+            r[o] = rv;
+            sr[lr][i] = rv;
+        }
+        __syncthreads();
+        if (act && M) {
+            const double* Mr = M + (int64_t)row * 81 + i * 9;
+            double zv = 0.0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) zv += Mr[c] * sr[lr][c];
+            z[o] = zv;
+            acc[0] += rv * zv;
+            if (defl) {
+                const double* Sr = SW + (int64_t)row * kW * 9 + i;
+#pragma unroll
+                for (int v = 0; v < kW; ++v) acc[2 + v] += Sr[v * 9] * zv;
+            }
+        }
+        acc[1] += rv * rv;
+        __syncthreads();
+    }
+    double t[NP];
+    block_totals<NP>(acc, t, sh);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < NP; ++j) pR[(int64_t)NP * blockIdx.x + j] = t[j];
     if (blockIdx.x == 0 && threadIdx.x == 0) { state[0] = 0; state[1] = 0; state[2] = BA_OK; state[3] = 0; scal[1] = -1.0; }
 }
 
 // plain y = S x
-__global__ __launch_bounds__(BS) void k_spmv(int ent_stride, const int2* __restrict__ ent, const double* __restrict__ blk,
-                                             const double* __restrict__ x, double* __restrict__ y) {
-    __shared__ double sacc[BS + 16];
-    row_product(blockIdx.x, ent_stride, ent, blk, x, sacc);
-    if (threadIdx.x < 9) y[(int64_t)blockIdx.x * 9 + threadIdx.x] = sacc[BS + threadIdx.x];
+__global__ __launch_bounds__(BS) void k_spmv(int n_rows, int ent_stride, const int2* __restrict__ ent,
+                                             const double* __restrict__ blk, const double* __restrict__ x,
+                                             double* __restrict__ y) {
+    const int lane = threadIdx.x % kWave;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const double v = row_gather<double, 0>(row, ent_stride, ent, blk, x, nullptr, 0.0);
+        if (lane < 9) y[(int64_t)row * 9 + lane] = v;
+    }
 }
 
-// kernel A; FIRST: the iteration k = 0 (records |r0|^2, d = z, q = S z).
-// The block product, the partials of both parities and the state are all
-// loaded before any decision, so the kernel is two dependent memory round
-// trips (entries, then blocks and z).
+// t = G r (initial step of the factorised preconditioner)
+__global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, int stride, const int2* __restrict__ ent,
+                                                     const float* __restrict__ G, const double* __restrict__ r,
+                                                     double* __restrict__ t) {
+    const int lane = threadIdx.x % kWave;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const double v = row_gather<float, 0>(row, stride, ent, G, r, nullptr, 0.0);
+        if (lane < 9) t[(int64_t)row * 9 + lane] = v;
+    }
+}
+
+// kernel A; FIRST: the iteration k = 0 (records |r0|^2).
 template <bool FIRST>
-__global__ __launch_bounds__(BS) void k_pcg_A(int ent_stride, const int2* __restrict__ ent,
+__global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, int ent_stride, const int2* __restrict__ ent,
                                               const double* __restrict__ blk, const double* __restrict__ z,
-                                              double* __restrict__ d, double* __restrict__ q, double* __restrict__ pA,
-                                              const double* __restrict__ pB0, const double* __restrict__ pB1, int nB,
+                                              double* __restrict__ d, double* __restrict__ q,
+                                              double* __restrict__ pA, const double* __restrict__ pR, int n_part,
                                               int* __restrict__ state, double* __restrict__ scal, double tol,
-                                              int max_iter) {
-    __shared__ double sh[4 * (BS / kWave)];
-    __shared__ double sacc[BS + 16];
-    const int row = blockIdx.x;
+                                              int max_iter, int defl, const double* __restrict__ W,
+                                              const double* __restrict__ SW, const double* __restrict__ Einv) {
+    __shared__ double sh[NP * WPB];
     const int done = state[0];
     const int k = state[3];
-    double zv = 0.0, qo = 0.0, dold = 0.0;
-    const int64_t o = (int64_t)row * 9 + (threadIdx.x < 9 ? threadIdx.x : 0);
-    if (threadIdx.x < 9) {
-        zv = z[o];
-        if (!FIRST) { qo = q[o]; dold = d[o]; }
-    }
-    // rz, rr of both parities (pB0: even steps, pB1: odd steps), requested
-    // before the product so that they arrive with its first round trip
-    double ps[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < nB; i += BS) {
-        const double2 a = reinterpret_cast<const double2*>(pB0)[i];
-        ps[0] += a.x; ps[1] += a.y;
-        if (!FIRST) {
-            const double2 b = reinterpret_cast<const double2*>(pB1)[i];
-            ps[2] += b.x; ps[3] += b.y;
-        }
-    }
-    row_product(row, ent_stride, ent, blk, z, sacc);
-    double s[4];
+    // rz_k, rr_k, (SW)^T z_k (parity k) and rz_{k-1} (other parity)
+    double s[NP + 1];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const double v = wave_sum(ps[j]);
-        if ((threadIdx.x % kWave) == 0) sh[j * (BS / kWave) + threadIdx.x / kWave] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < BS / kWave; ++w) t += sh[j * (BS / kWave) + w];
-        s[j] = t;
-    }
+    for (int j = 0; j < NP + 1; ++j) s[j] = 0.0;
+    const double* pk = pR + (int64_t)NP * n_part * (k & 1);
+    if (defl)
+        sum_partials<NP>(pk, n_part, NP, s, sh);
+    else
+        sum_partials<2>(pk, n_part, NP, s, sh);
+    if (!FIRST) sum_partials<1>(pR + (int64_t)NP * n_part * ((k + 1) & 1), n_part, NP, s + NP, sh);
     if (done) return;
-    const double rz = (k & 1) ? s[2] : s[0];
-    const double rr = (k & 1) ? s[3] : s[1];
-    const double rz_old = (k & 1) ? s[0] : s[2];
+    const double rz = s[0], rr = s[1], rz_old = FIRST ? 1.0 : s[NP];
     const double r0sq = FIRST ? rr : scal[0];
-    if (FIRST && row == 0 && threadIdx.x == 0) scal[0] = rr;
+    if (FIRST && blockIdx.x == 0 && threadIdx.x == 0) scal[0] = rr;
     const bool conv = (rr == 0.0) || (sqrt(rr) <= tol * sqrt(r0sq));
     if (conv || k >= max_iter) {
-        if (row == 0 && threadIdx.x == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
             state[0] = 1;
             state[2] = conv ? BA_OK : BA_ERR_NOT_CONVERGED;
             scal[1] = r0sq > 0.0 ? sqrt(rr / r0sq) : 0.0;
@@ -214,114 +473,245 @@ __global__ __launch_bounds__(BS) void k_pcg_A(int ent_stride, const int2* __rest
         return;
     }
     const double beta = FIRST ? 0.0 : rz / rz_old;
-    if (row == 0 && threadIdx.x == 0) state[1] = k;
-    if (threadIdx.x < 9) {
-        const double sv = sacc[BS + threadIdx.x];
-        const double qv = FIRST ? sv : sv + beta * qo;
-        const double dv = FIRST ? zv : zv + beta * dold;
-        q[o] = qv;
-        d[o] = dv;
-        double dq = dv * qv;
-        // sum of the 9 components held by lanes 0..8
+    double mu[kW];
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            const double o2 = __shfl_down(dq, off, 16);
-            if (threadIdx.x + off < 9) dq += o2;
+    for (int v = 0; v < kW; ++v) mu[v] = 0.0;
+    if (defl) einv_apply(Einv, s + 2, mu);
+    if (blockIdx.x == 0 && threadIdx.x == 0) state[1] = k;
+    const int lane = threadIdx.x % kWave;
+    double dq = 0.0;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const int64_t o = (int64_t)row * 9 + (lane < 9 ? lane : 0);
+        double zv = 0.0, qo = 0.0, dold = 0.0, wm = 0.0, swm = 0.0;
+        if (lane < 9) {
+            zv = z[o];
+            if (!FIRST) { qo = q[o]; dold = d[o]; }
+            if (defl) {
+                const double* Wr = W + (int64_t)row * kW * 9 + lane;
+                const double* Sr = SW + (int64_t)row * kW * 9 + lane;
+#pragma unroll
+                for (int v = 0; v < kW; ++v) {
+                    wm += Wr[v * 9] * mu[v];
+                    swm += Sr[v * 9] * mu[v];
+                }
+            }
         }
-        if (threadIdx.x == 0) pA[row] = dq;
+        const double sv = row_gather<double, 0>(row, ent_stride, ent, blk, z, nullptr, 0.0);
+        if (lane < 9) {
+            const double qv = (FIRST ? sv : sv + beta * qo) - swm;
+            const double dv = (FIRST ? zv : zv + beta * dold) - wm;
+            q[o] = qv;
+            d[o] = dv;
+            dq += dv * qv;
+        }
     }
+    const double t = block_total(wave_sum(dq), sh);
+    if (threadIdx.x == 0) pA[blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restrict__ M, const double* __restrict__ d,
                                               const double* __restrict__ q, double* __restrict__ x,
                                               double* __restrict__ r, double* __restrict__ z,
-                                              const double* __restrict__ pA, int nA, double* __restrict__ pB0,
-                                              double* __restrict__ pB1, int nB, int* __restrict__ state) {
-    __shared__ double sh[3 * (BS / kWave)];
+                                              const double* __restrict__ pA, double* __restrict__ pR, int n_part,
+                                              int* __restrict__ state, int defl, const double* __restrict__ SW) {
+    __shared__ double sh[NP * WPB];
     __shared__ double sr[RPB][9];
     const int done = state[0];
     const int k = state[1];
-    const int lr = threadIdx.x / 9, i = threadIdx.x % 9;
-    const int row = blockIdx.x * RPB + lr;
-    const bool act = threadIdx.x < RPB * 9 && row < n_rows;
-    double Mr[9], dv = 0.0, qv = 0.0, xv = 0.0, rv0 = 0.0;
-    const int64_t o = (int64_t)row * 9 + i;
-    if (act) {
-        const double* Mp = M + (int64_t)row * 81 + i * 9;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) Mr[c] = Mp[c];
-        dv = d[o]; qv = q[o]; xv = x[o]; rv0 = r[o];
-    }
-    const double* src[3] = {pA, pB0, pB1};
-    const int n[3] = {nA, nB, nB};
-    const int stride[3] = {1, 2, 2};
-    double s[3];
-    sum_partials<3>(src, n, stride, s, sh);
+    double s[2];
+    sum_partials<1>(pA, n_part, 1, s, sh);
+    sum_partials<1>(pR + (int64_t)NP * n_part * (k & 1), n_part, NP, s + 1, sh);
     if (done) return;
-    const double dq = s[0], rz = (k & 1) ? s[2] : s[1];
-    double* pk1 = (k & 1) ? pB0 : pB1;
+    const double dq = s[0], rz = s[1];
     if (!(dq > 0.0)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) { state[0] = 1; state[2] = BA_ERR_NOT_SPD; }
         return;
     }
     const double alpha = rz / dq;
-    double rv = 0.0;
-    if (act) {
-        x[o] = xv + alpha * dv;
-        rv = rv0 - alpha * qv;
-        r[o] = rv;
-        sr[lr][i] = rv;
-    }
-    __syncthreads();
-    double zv = 0.0;
-    if (act) {
+    const int lr = threadIdx.x / 9, i = threadIdx.x % 9;
+    double acc[NP];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) zv += Mr[c] * sr[lr][c];
-        z[o] = zv;
-    }
-    // per-wave partials of r^T z and r^T r (4 per block)
-    double rzn = rv * zv, rr = rv * rv;
+    for (int j = 0; j < NP; ++j) acc[j] = 0.0;
+    for (int base = blockIdx.x * RPB; base < n_rows; base += gridDim.x * RPB) {
+        const int row = base + lr;
+        const bool act = threadIdx.x < RPB * 9 && row < n_rows;
+        const int64_t o = (int64_t)row * 9 + i;
+        double rv = 0.0;
+        if (act) {
+            x[o] += alpha * d[o];
+            rv = r[o] - alpha * q[o];
+            r[o] = rv;
+            sr[lr][i] = rv;
+        }
+        __syncthreads();
+        if (act) {
+            const double* Mr = M + (int64_t)row * 81 + i * 9;
+            double zv = 0.0;
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        rzn += __shfl_xor(rzn, off, kWave);
-        rr += __shfl_xor(rr, off, kWave);
+            for (int c = 0; c < 9; ++c) zv += Mr[c] * sr[lr][c];
+            z[o] = zv;
+            acc[0] += rv * zv;
+            acc[1] += rv * rv;
+            if (defl) {
+                const double* Sr = SW + (int64_t)row * kW * 9 + i;
+#pragma unroll
+                for (int v = 0; v < kW; ++v) acc[2 + v] += Sr[v * 9] * zv;
+            }
+        }
+        __syncthreads();
     }
-    if ((threadIdx.x % kWave) == 0) {
-        const int w = blockIdx.x * (BS / kWave) + threadIdx.x / kWave;
-        pk1[2 * w] = rzn;
-        pk1[2 * w + 1] = rr;
-    }
+    double t[NP];
+    block_totals<NP>(acc, t, sh);
+    double* out = pR + (int64_t)NP * n_part * ((k + 1) & 1) + (int64_t)NP * blockIdx.x;
+    if (threadIdx.x == 0)
+        for (int j = 0; j < NP; ++j) out[j] = t[j];
     if (blockIdx.x == 0 && threadIdx.x == 0) state[3] = k + 1;
 }
 
-void enqueue_iterations(ba_ctx* c, const double* M, double tol, int max_iter, int count, hipStream_t st) {
+// factorised preconditioner, first half: update and t = G r'
+__global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, int stride, const int2* __restrict__ ent,
+                                               const float* __restrict__ G, const double* __restrict__ d,
+                                               const double* __restrict__ q, double* __restrict__ x,
+                                               double* __restrict__ r0buf, double* __restrict__ r1buf,
+                                               double* __restrict__ t, const double* __restrict__ pA,
+                                               double* __restrict__ pR, int n_part, int* __restrict__ state) {
+    __shared__ double sh[2 * WPB];
+    const int done = state[0];
+    const int k = state[1];
+    double s[2];
+    sum_partials<1>(pA, n_part, 1, s, sh);
+    sum_partials<1>(pR + (int64_t)NP * n_part * (k & 1), n_part, NP, s + 1, sh);
+    if (done) return;
+    const double dq = s[0], rz = s[1];
+    if (!(dq > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) { state[0] = 1; state[2] = BA_ERR_NOT_SPD; }
+        return;
+    }
+    const double alpha = rz / dq;
+    const double* rin = (k & 1) ? r1buf : r0buf;
+    double* rout = (k & 1) ? r0buf : r1buf;
+    const int lane = threadIdx.x % kWave;
+    double rr = 0.0;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const double tv = row_gather<float, 1>(row, stride, ent, G, rin, q, alpha);
+        if (lane < 9) {
+            const int64_t o = (int64_t)row * 9 + lane;
+            x[o] += alpha * d[o];
+            const double rv = rin[o] - alpha * q[o];
+            rout[o] = rv;
+            t[o] = tv;
+            rr += rv * rv;
+        }
+    }
+    const double tot = block_total(wave_sum(rr), sh);
+    if (threadIdx.x == 0) pR[(int64_t)NP * n_part * ((k + 1) & 1) + (int64_t)NP * blockIdx.x + 1] = tot;
+}
+
+// factorised preconditioner, second half: z = G^T t, r'^T z, (SW)^T z.
+// INIT: the initial z0 (r in buffer 0, parity 0, no counter update).
+template <bool INIT>
+__global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, int stride, const int2* __restrict__ ent,
+                                               const float* __restrict__ G, const double* __restrict__ t,
+                                               const double* __restrict__ r0buf, const double* __restrict__ r1buf,
+                                               double* __restrict__ z, double* __restrict__ pR, int n_part,
+                                               int* __restrict__ state, int defl, const double* __restrict__ SW) {
+    __shared__ double sh[NP * WPB];
+    int k = -1;
+    if (!INIT) {
+        if (state[0]) return;
+        k = state[1];
+    }
+    const double* r = ((k + 1) & 1) ? r1buf : r0buf;
+    const int lane = threadIdx.x % kWave;
+    double acc[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) acc[j] = 0.0;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const double zv = row_gather<float, 0>(row, stride, ent, G, t, nullptr, 0.0);
+        if (lane < 9) {
+            const int64_t o = (int64_t)row * 9 + lane;
+            z[o] = zv;
+            acc[0] += r[o] * zv;
+            if (defl) {
+                const double* Sr = SW + (int64_t)row * kW * 9 + lane;
+#pragma unroll
+                for (int v = 0; v < kW; ++v) acc[2 + v] += Sr[v * 9] * zv;
+            }
+        }
+    }
+    double tot[NP];
+    block_totals<NP>(acc, tot, sh);
+    double* out = pR + (int64_t)NP * n_part * ((k + 1) & 1) + (int64_t)NP * blockIdx.x;
+    if (threadIdx.x == 0) {
+        out[0] = tot[0];
+        for (int j = 2; j < NP; ++j) out[j] = tot[j];
+    }
+    if (!INIT && blockIdx.x == 0 && threadIdx.x == 0) state[3] = k + 1;
+}
+
+int grid_of(int n_rows) { return std::max(1, std::min((n_rows + WPB - 1) / WPB, kMaxGrid)); }
+
+void enqueue_iterations(ba_ctx* c, int mode, const double* M, int defl, double tol, int max_iter, int count,
+                        hipStream_t st) {
     Pcg& P = c->pcg;
-    const int nr = c->n_rows, nB = (nr + RPB - 1) / RPB, nPB = nB * (BS / kWave);
+    const int nr = c->n_rows, g = grid_of(nr);
     for (int i = 0; i < count; ++i) {
-        k_pcg_A<false><<<nr, BS, 0, st>>>(c->ent_stride, (const int2*)c->sp_ent, c->blk, P.z, P.d[0], P.q, P.pA,
-                                          P.pB[0], P.pB[1], nPB, P.state, P.scal, tol, max_iter);
-        k_pcg_B<<<nB, BS, 0, st>>>(nr, M, P.d[0], P.q, P.x, P.r, P.z, P.pA, nr, P.pB[0], P.pB[1], nPB, P.state);
+        k_pcg_A<false><<<g, BS, 0, st>>>(nr, c->ent_stride, (const int2*)c->sp_ent, c->blk, P.z, P.d, P.q, P.pA,
+                                         P.pR, g, P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
+        if (mode == 0) {
+            k_pcg_B<<<g, BS, 0, st>>>(nr, M, P.d, P.q, P.x, P.r[0], P.z, P.pA, P.pR, g, P.state, defl, P.SW);
+        } else {
+            k_pcg_Bf<<<g, BS, 0, st>>>(nr, c->fs.gl_stride, (const int2*)c->fs.gl_ent, c->fs.G, P.d, P.q, P.x,
+                                       P.r[0], P.r[1], P.t, P.pA, P.pR, g, P.state);
+            k_pcg_Cf<false><<<g, BS, 0, st>>>(nr, c->fs.gu_stride, (const int2*)c->fs.gu_ent, c->fs.G, P.t, P.r[0],
+                                              P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
+        }
     }
 }
 
 }  // namespace
 
-ba_status run_pcg(ba_ctx* c, const double* M, double tol, int max_iter, const double* x0, double* out, int* iters,
-                  double* relres) {
+// Gauge vectors of the last linearization, S W and E^-1 of the current RCS
+void prepare_deflation(ba_ctx* c) {
     Pcg& P = c->pcg;
-    const int nr = c->n_rows;
-    const int nB = (nr + RPB - 1) / RPB, nPB = nB * (BS / kWave);
+    const int nr = c->n_rows, g = grid_of(nr);
+    hipStream_t st = c->stream;
+    k_gauge_W<<<(c->n_cams + 255) / 256, 256, 0, st>>>(c->n_cams, c->cam_row, c->lin_cams, P.W);
+    k_spmm_W<<<g, BS, 0, st>>>(nr, c->ent_stride, (const int2*)c->sp_ent, c->blk, P.W, P.SW);
+    k_defl_E_part<<<g, BS, 0, st>>>(nr, P.W, P.SW, P.pE);
+    k_defl_E_fin<<<1, 64, 0, st>>>(g, P.pE, P.Einv, c->flags);
+}
+
+ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, int max_iter, const double* x0,
+                  double* out, int* iters, double* relres) {
+    Pcg& P = c->pcg;
+    const int nr = c->n_rows, g = grid_of(nr);
     hipStream_t st = c->stream;
     const double* q0 = nullptr;
     if (x0) {
-        k_spmv<<<nr, BS, 0, st>>>(c->ent_stride, (const int2*)c->sp_ent, c->blk, x0, P.q);
+        k_spmv<<<g, BS, 0, st>>>(nr, c->ent_stride, (const int2*)c->sp_ent, c->blk, x0, P.q);
         q0 = P.q;
     }
-    k_pcg_init<<<nB, BS, 0, st>>>(nr, c->rhs, q0, x0, M, P.x, P.r, P.z, P.pB[0], P.state, P.scal);
-    k_pcg_A<true><<<nr, BS, 0, st>>>(c->ent_stride, (const int2*)c->sp_ent, c->blk, P.z, P.d[0], P.q, P.pA, P.pB[0],
-                                     P.pB[1], nPB, P.state, P.scal, tol, max_iter);
-    if (max_iter > 0)
-        k_pcg_B<<<nB, BS, 0, st>>>(nr, M, P.d[0], P.q, P.x, P.r, P.z, P.pA, nr, P.pB[0], P.pB[1], nPB, P.state);
+    if (defl) k_defl_Wr<<<g, BS, 0, st>>>(nr, c->rhs, q0, P.W, P.pW);
+    k_pcg_init<<<g, BS, 0, st>>>(nr, c->rhs, q0, x0, mode == 0 ? M : nullptr, P.x, P.r[0], P.z, P.pR, P.state, P.scal,
+                                 defl, P.W, P.SW, P.Einv, P.pW, g);
+    if (mode != 0) {
+        k_gather_lower<<<g, BS, 0, st>>>(nr, c->fs.gl_stride, (const int2*)c->fs.gl_ent, c->fs.G, P.r[0], P.t);
+        k_pcg_Cf<true><<<g, BS, 0, st>>>(nr, c->fs.gu_stride, (const int2*)c->fs.gu_ent, c->fs.G, P.t, P.r[0], P.r[1],
+                                         P.z, P.pR, g, P.state, defl, P.SW);
+    }
+    k_pcg_A<true><<<g, BS, 0, st>>>(nr, c->ent_stride, (const int2*)c->sp_ent, c->blk, P.z, P.d, P.q, P.pA, P.pR, g,
+                                    P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
+    if (max_iter > 0) {
+        if (mode == 0) {
+            k_pcg_B<<<g, BS, 0, st>>>(nr, M, P.d, P.q, P.x, P.r[0], P.z, P.pA, P.pR, g, P.state, defl, P.SW);
+        } else {
+            k_pcg_Bf<<<g, BS, 0, st>>>(nr, c->fs.gl_stride, (const int2*)c->fs.gl_ent, c->fs.G, P.d, P.q, P.x,
+                                       P.r[0], P.r[1], P.t, P.pA, P.pR, g, P.state);
+            k_pcg_Cf<false><<<g, BS, 0, st>>>(nr, c->fs.gu_stride, (const int2*)c->fs.gu_ent, c->fs.G, P.t, P.r[0],
+                                              P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
+        }
+    }
     // remaining iterations in fixed batches (a captured graph when possible);
     // the stop flag of a batch is read back while the next batch runs, and
     // kernels after the stop return at once
@@ -329,17 +719,18 @@ ba_status run_pcg(ba_ctx* c, const double* M, double tol, int max_iter, const do
     const int n_batches = max_iter > 0 ? (max_iter + batch - 1) / batch : 0;
     hipGraphExec_t exec = nullptr;
     if (c->use_graphs && n_batches > 0) {
-        for (auto& g : c->pcg_graphs)
-            if (g.M == M && g.tol == tol && g.max_iter == max_iter) exec = g.exec;
+        for (auto& gr : c->pcg_graphs)
+            if (gr.M == M && gr.mode == mode && gr.defl == defl && gr.tol == tol && gr.max_iter == max_iter)
+                exec = gr.exec;
         if (!exec) {
             hipStream_t cs = c->capture_stream;
             hipGraph_t graph = nullptr;
             BA_HIP_CHECK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-            enqueue_iterations(c, M, tol, max_iter, batch, cs);
+            enqueue_iterations(c, mode, M, defl, tol, max_iter, batch, cs);
             BA_HIP_CHECK(hipStreamEndCapture(cs, &graph));
             BA_HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             BA_HIP_CHECK(hipGraphDestroy(graph));
-            c->pcg_graphs.push_back({M, tol, max_iter, exec});
+            c->pcg_graphs.push_back({M, mode, defl, tol, max_iter, exec});
         }
     }
     hipEvent_t evb[2] = {c->ev[12], c->ev[13]};
@@ -351,7 +742,7 @@ ba_status run_pcg(ba_ctx* c, const double* M, double tol, int max_iter, const do
             if (exec)
                 BA_HIP_CHECK(hipGraphLaunch(exec, st));
             else
-                enqueue_iterations(c, M, tol, max_iter, batch, st);
+                enqueue_iterations(c, mode, M, defl, tol, max_iter, batch, st);
             ++launched;
             BA_HIP_CHECK(hipMemcpyAsync(hflag[slot], P.state, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
             BA_HIP_CHECK(hipEventRecord(evb[slot], st));
@@ -377,7 +768,7 @@ ba_status run_pcg(ba_ctx* c, const double* M, double tol, int max_iter, const do
 
 void launch_spmv(ba_ctx* c, const double* x, double* y) {
     if (c->n_rows == 0) return;
-    k_spmv<<<c->n_rows, BS, 0, c->stream>>>(c->ent_stride, (const int2*)c->sp_ent, c->blk, x, y);
+    k_spmv<<<grid_of(c->n_rows), BS, 0, c->stream>>>(c->n_rows, c->ent_stride, (const int2*)c->sp_ent, c->blk, x, y);
 }
 
 }  // namespace ba

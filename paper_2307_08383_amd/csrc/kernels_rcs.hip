@@ -185,7 +185,8 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
                                              const int32_t* __restrict__ row_ptr, const T* __restrict__ R,
                                              const double* __restrict__ e, const double* __restrict__ ptL,
                                              double lambda, double* __restrict__ blk, double* __restrict__ rhs,
-                                             double* __restrict__ Minv, int* __restrict__ flags) {
+                                             double* __restrict__ Minv, double* __restrict__ Linv,
+                                             int* __restrict__ flags) {
     __shared__ double sred[WPB][64];
     __shared__ double sS[81];
     __shared__ double sL[81];
@@ -289,6 +290,7 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
         double t = 0.0;
         for (int q = (i > j ? i : j); q < 9; ++q) t += sL[q * 9 + i] * sL[q * 9 + j];
         Minv[(int64_t)row * 81 + threadIdx.x] = t;
+        Linv[(int64_t)row * 81 + threadIdx.x] = sL[threadIdx.x];
     }
 }
 
@@ -381,11 +383,11 @@ void launch_diag(ba_ctx* c, double lambda) {
     if (c->precision == BA_MIXED)
         k_diag<float><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->rowobs_pt, c->row_ptr,
                                                        (const float*)c->R, c->e, c->ptL, lambda, c->blk, c->rhs,
-                                                       c->Minv, c->flags);
+                                                       c->Minv, c->Linv, c->flags);
     else
         k_diag<double><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->rowobs_pt, c->row_ptr,
                                                         (const double*)c->R, c->e, c->ptL, lambda, c->blk, c->rhs,
-                                                        c->Minv, c->flags);
+                                                        c->Minv, c->Linv, c->flags);
 }
 
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
