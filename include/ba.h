@@ -58,8 +58,10 @@ enum { BA_FP64 = 0, BA_MIXED = 1 };
  *   FSAI: factorised sparse approximate inverse M^-1 = G^T G, G block-lower-
  *     triangular on the lower RCS pattern (at most 27 lower neighbours per
  *     row, those with the most common points), recomputed after every
- *     formation from local FP32 factorisations; see ba_get_fsai. */
-enum { BA_PRECOND_BLOCK_JACOBI = 0, BA_PRECOND_LEARNED = 1, BA_PRECOND_FSAI = 2 };
+ *     formation from local FP32 factorisations; see ba_get_fsai;
+ *   LEARNED_FSAI: the same pattern and apply, with G emitted by the learned
+ *     network's factorised head (ba_set_preconditioner_net). */
+enum { BA_PRECOND_BLOCK_JACOBI = 0, BA_PRECOND_LEARNED = 1, BA_PRECOND_FSAI = 2, BA_PRECOND_LEARNED_FSAI = 3 };
 
 typedef struct ba_ctx ba_ctx;
 
@@ -198,14 +200,14 @@ ba_status ba_get_rcs(ba_ctx* ctx, double* blk, double* rhs);
  * (converted to FP64 in mixed precision), e [n_obs][2]; either may be NULL. */
 ba_status ba_get_jacobians(ba_ctx* ctx, double* J, double* e);
 
-/* Host copy (FP32, [n_blk][81], row-major 9x9) of the FSAI factor G of the
- * current RCS, in the slots of the RCS blocks: the slot of upper block
+/* Host copy (FP32, [n_blk][81], row-major 9x9) of the factor G used by the
+ * last FSAI or LEARNED_FSAI solve on the current RCS, in the slots of the
+ * RCS blocks: the slot of upper block
  * (s, c), s < c, holds G_cs; a diagonal slot holds G_ss (lower triangular,
  * positive diagonal); slots of lower neighbours beyond the per-row limit
  * hold zeros.  Definition (Kolotilina-Yeremin): row i of G is zero outside
  * its set J_i and satisfies (G S)_ij = 0 for j in J_i, j != i, and
- * (G S G^T)_ii = I.  BA_ERR_STATE unless a solve or LM step with
- * BA_PRECOND_FSAI ran on the current RCS. */
+ * (G S G^T)_ii = I (for FSAI).  BA_ERR_STATE before the first such solve. */
 ba_status ba_get_fsai(ba_ctx* ctx, float* G);
 
 /* Gauge deflation.  A similarity transform of the whole scene leaves every
@@ -238,7 +240,8 @@ ba_status ba_get_stage_ms(ba_ctx* ctx, double* ms4);
  * construction, and equal to S_ii^-1 (block-Jacobi) when Lt_i = I.
  * Parameters: a flat FP32 vector of ba_gnn_param_count() values in the order
  *   Wn[64][64], bn[64], We[96][64], be[64],
- *   3 x (M_l[192][64], c_l[64], U_l[128][64], u_l[64]), Wd[64][48], bd[48]
+ *   3 x (M_l[192][64], c_l[64], U_l[128][64], u_l[64]), Wd[64][48], bd[48],
+ *   Wo[192][96], bo[96], ao[96] (factorised head, below)
  * (row-major, y = x W + b).  Node input (64): the 36 strictly-upper entries
  * of diag(S_ii)^-1/2 S_ii diag(S_ii)^-1/2, then log S_ii[r][r] minus their
  * mean (9), zero padding.  Edge input i->j (96): L_i^-1 S_ij L_j^-T
@@ -249,6 +252,14 @@ ba_status ba_get_stage_ms(ba_ctx* ctx, double* ms4);
  * use bf16 operands with FP32 accumulation.  Loss (training): Hutchinson
  * estimate of |B A - I|_F^2 / (9 n) with A = blockdiag(L)^-1 S blockdiag(L)^-T,
  * B = blockdiag(Lt Lt^T) and Rademacher probes.
+ * Factorised head (edge variant, FSAI pattern): M^-1 = G^T G with G block-
+ * lower-triangular on the sets J_i of BA_PRECOND_FSAI; in normalised
+ * coordinates Ghat = G blockdiag(L), Ghat_ii = Lt_i and, for j in J_i, j < i,
+ * Ghat_ij = reshape([h_i, h_j, g_ij] Wo + bo)[:81] - ao[:81] (elementwise)
+ * L_i^-1 S_ij L_j^-T, with Wo[192][96], bo[96], ao[96] appended to the
+ * parameters above (zero: block-Jacobi).  Its loss is the Kaporin functional
+ * (1/(9n)) sum_i [tr(Ghat_i Ahat[J_i,J_i] Ghat_i^T) - 2 log det Ghat_ii],
+ * minimised over the pattern by the exact FSAI factor.
  * A ba_gnn runs its work on its stream (NULL = default); a network and the
  * graphs it is used with must not be used concurrently from two threads.
  * ------------------------------------------------------------------------ */
@@ -268,10 +279,12 @@ ba_status ba_gnn_get_params(ba_gnn* net, float* params);
 /* Network input of one RCS instance: from the context's last formed RCS
  * (device work on the context stream), or from host arrays row_ptr
  * [n_rows+1] (int64), col_idx [n_blk] (diagonal first in each row), blocks
- * [n_blk][81] FP64.  BA_ERR_NOT_SPD if a diagonal block is not SPD. */
+ * [n_blk][81] FP64 and, optionally, blk_pairs [n_blk] (common points of
+ * each block; needed by the factorised head, NULL otherwise).
+ * BA_ERR_NOT_SPD if a diagonal block is not SPD. */
 ba_status ba_gnn_graph_from_ctx(ba_ctx* ctx, ba_gnn_graph** out);
 ba_status ba_gnn_graph_from_host(int32_t n_rows, const int64_t* row_ptr, const int32_t* col_idx,
-                                 const double* blk, ba_gnn_graph** out);
+                                 const double* blk, const int32_t* blk_pairs, ba_gnn_graph** out);
 void ba_gnn_graph_destroy(ba_gnn_graph* graph);
 
 /* Loss and (if grad is not NULL) its gradient (host FP32, param order) for
@@ -289,8 +302,16 @@ ba_status ba_gnn_train_step(ba_gnn* net, ba_gnn_graph* const* graphs, int32_t n_
 /* Host copy of the preconditioner blocks P [n_rows][81] for a graph. */
 ba_status ba_gnn_preconditioner(ba_gnn* net, ba_gnn_graph* graph, double* P);
 
-/* Uses net (not copied; must outlive its use) for BA_PRECOND_LEARNED in
- * ba_pcg_solve and ba_lm_step of ctx: after each formation the network runs
+/* Factorised head: Kaporin loss and (if grad is not NULL) its gradient;
+ * one Adam step on the mean over n_graphs graphs; and the factor G of a
+ * graph (host FP32 [n_blk][81] in the RCS block slots, as ba_get_fsai).
+ * BA_ERR_STATE for a graph built without common-point counts. */
+ba_status ba_gnn_fsai_loss_grad(ba_gnn* net, ba_gnn_graph* graph, double* loss, float* grad);
+ba_status ba_gnn_fsai_train_step(ba_gnn* net, ba_gnn_graph* const* graphs, int32_t n_graphs, float lr, double* loss);
+ba_status ba_gnn_fsai_factor(ba_gnn* net, ba_gnn_graph* graph, float* G);
+
+/* Uses net (not copied; must outlive its use) for BA_PRECOND_LEARNED and
+ * BA_PRECOND_LEARNED_FSAI in ba_pcg_solve and ba_lm_step of ctx: after each formation the network runs
  * on the RCS on the context stream.  NULL detaches. */
 ba_status ba_set_preconditioner_net(ba_ctx* ctx, ba_gnn* net);
 

@@ -38,6 +38,10 @@ PARAM_SHAPES = [("Wn", (F_NODE, H)), ("bn", (H,)), ("We", (F_EDGE, H)), ("be", (
 for _l in range(N_LAYERS):
     PARAM_SHAPES += [(f"M{_l}", (3 * H, H)), (f"c{_l}", (H,)), (f"U{_l}", (2 * H, H)), (f"u{_l}", (H,))]
 PARAM_SHAPES += [("Wd", (H, F_OUT)), ("bd", (F_OUT,))]
+# factorised head: off-diagonal blocks of G from [h_i, h_j, g_ij] (96 outputs,
+# 81 used) plus a learned elementwise multiple of the normalised block
+F_OFF = 96
+PARAM_SHAPES += [("Wo", (3 * H, F_OFF)), ("bo", (F_OFF,)), ("ao", (F_OFF,))]
 N_PARAMS = int(sum(np.prod(s) for _, s in PARAM_SHAPES))
 
 # strict lower triangle positions (row-major) used by the decoder
@@ -72,8 +76,10 @@ def init_params(seed=0, zero_decoder=True, decoder_scale=0.05):
     if zero_decoder:
         d["Wd"][:] = 0.0
         d["bd"][:] = 0.0
+        d["Wo"][:] = 0.0
     else:
         d["Wd"] *= decoder_scale
+        d["Wo"] *= decoder_scale
     return flatten(d)
 
 
@@ -231,8 +237,10 @@ def loss_and_dout(o, z, y):
     return loss, do
 
 
-def backward(w, feat, cache, do, bf16=False):
-    """Gradient of the loss with respect to the flat parameter vector."""
+def backward(w, feat, cache, do, bf16=False, extra=None):
+    """Gradient of the loss with respect to the flat parameter vector;
+    extra: gradients from the factorised head (dh on the final node states,
+    dg on the encoded edge features, and the head's own parameters)."""
     rd = bf16_round if bf16 else (lambda a: a)
     P = _params(w, bf16)
     g = feat["graph"]
@@ -245,6 +253,11 @@ def backward(w, feat, cache, do, bf16=False):
     grads["bd"] = do.sum(axis=0)
     dh = dob @ P["Wd"].T
     dg = np.zeros_like(cache["g"])
+    if extra is not None:
+        dh = dh + extra["dh"]
+        dg = dg + extra["dg"]
+        for name in ("Wo", "bo", "ao"):
+            grads[name] = extra[name]
     for l in reversed(range(N_LAYERS)):
         t = cache[f"t{l}"]
         dt = rd(dh * (t > 0))
@@ -287,4 +300,139 @@ def preconditioner(o, L):
     for i in range(L.shape[0]):
         Li = np.linalg.inv(L[i])
         out[i] = Li.T @ (Lt[i] @ Lt[i].T) @ Li
+    return out
+
+
+# ---------------------------------------------------------------------------
+# factorised head (FSAI-pattern correction of block-Jacobi)
+# ---------------------------------------------------------------------------
+#
+# M^-1 = G^T G with G block-lower-triangular on the sets J_i (camera i and
+# its kept lower neighbours, ascending, i last).  In block-Jacobi-normalised
+# coordinates Ghat = G blockdiag(L): Ghat_ii = Lt_i from the node decoder
+# (lower triangular, diagonal exp(.)), and for j in J_i, j < i,
+#     Ghat_ij = reshape(Wo^T [h_i, h_j, g_ij] + bo)[:81] - ao[:81] * A_ij
+# (A_ij the normalised block of the directed edge i -> j).  A zero head and
+# decoder give Ghat = I, G = blockdiag(L^-1): block-Jacobi.  Training
+# minimises the Kaporin functional in the normalised space,
+#     f = (1/(9n)) sum_i [ tr(Ghat_i Ahat[J_i, J_i] Ghat_i^T)
+#                          - 2 sum_k log (Ghat_ii)_kk ],
+# whose minimiser over this pattern is the exact FSAI factor.
+
+def fsai_edges(feat, J):
+    """FSAI edges (i, member b < last) in row order: (src, dst, edge index)."""
+    g = feat["graph"]
+    index = {(int(a), int(b)): e for e, (a, b) in enumerate(zip(g["src"], g["dst"]))}
+    out = []
+    for i, Ji in enumerate(J):
+        for j in Ji[:-1]:
+            out.append((i, j, index[(i, j)]))
+    return out
+
+
+def fsai_factor(w, feat, J, bf16=False):
+    """Returns (Ghat rows: list of [m_i, 9, 9] blocks, cache)."""
+    rd = bf16_round if bf16 else (lambda a: a)
+    o, cache = forward(w, feat, bf16)
+    P = _params(w, bf16)
+    A = feat["A"].astype(np.float32).astype(np.float64) if bf16 else feat["A"]
+    hL = cache["hL"]
+    gb = rd(cache["g"])
+    fe = fsai_edges(feat, J)
+    X = np.zeros((len(fe), 3 * H))
+    for f, (i, j, e) in enumerate(fe):
+        X[f] = np.concatenate([hL[i], hL[j], gb[e]])
+    oe = X @ P["Wo"] + P["bo"] if len(fe) else np.zeros((0, F_OFF))
+    Lt = factor_from_output(o)
+    rows, f = [], 0
+    for i, Ji in enumerate(J):
+        blocks = []
+        for j in Ji[:-1]:
+            e = fe[f][2]
+            blocks.append(oe[f, :81].reshape(9, 9) - P["ao"][:81].reshape(9, 9) * A[e])
+            f += 1
+        blocks.append(Lt[i])
+        rows.append(np.stack(blocks))
+    cache.update(o=o, oe=oe, X=X, fe=fe, Aq=A)
+    return rows, cache
+
+
+def local_matrix(feat, Ji):
+    """Ahat[J_i, J_i] (identity diagonal blocks)."""
+    g = feat["graph"]
+    index = {(int(a), int(b)): e for e, (a, b) in enumerate(zip(g["src"], g["dst"]))}
+    m = len(Ji)
+    M = np.zeros((9 * m, 9 * m))
+    for a in range(m):
+        for b in range(m):
+            if a == b:
+                M[9 * a:9 * a + 9, 9 * b:9 * b + 9] = np.eye(9)
+            elif (Ji[a], Ji[b]) in index:
+                M[9 * a:9 * a + 9, 9 * b:9 * b + 9] = feat["A"][index[(Ji[a], Ji[b])]]
+    return M
+
+
+def kaporin_loss(rows, feat, J):
+    """f and d f / d Ghat (same layout as rows)."""
+    n = len(J)
+    N = 9.0 * n
+    f = 0.0
+    grads = []
+    for Gi, Ji in zip(rows, J):
+        m = len(Ji)
+        Gr = np.concatenate(list(Gi), axis=1)            # 9 x 9m
+        M = local_matrix(feat, Ji)
+        Y = Gr @ M
+        d = np.diag(Gi[-1])
+        f += np.trace(Y @ Gr.T) - 2.0 * np.sum(np.log(d))
+        dG = (2.0 / N) * Y
+        dG[:, 9 * (m - 1):] -= (2.0 / N) * np.diag(1.0 / d)
+        grads.append(dG.reshape(9, m, 9).transpose(1, 0, 2))
+    return f / N, grads
+
+
+def fsai_loss_and_grad(w, feat, J, bf16=False):
+    """Kaporin loss of the factorised head and its gradient (flat)."""
+    rd = bf16_round if bf16 else (lambda a: a)
+    rows, cache = fsai_factor(w, feat, J, bf16)
+    loss, dG = kaporin_loss(rows, feat, J)
+    P = _params(w, bf16)
+    o = cache["o"]
+    n = o.shape[0]
+    do = np.zeros_like(o)
+    idx = np.arange(9)
+    doe = np.zeros_like(cache["oe"])
+    dao = np.zeros(F_OFF)
+    A = cache["Aq"]
+    f = 0
+    for i, (Gi, Ji) in enumerate(zip(rows, J)):
+        dGi = dG[i]
+        dd = dGi[-1]
+        do[i, :9] = dd[idx, idx] * Gi[-1][idx, idx]
+        for q, (r, c) in enumerate(TRIL):
+            do[i, 9 + q] = dd[r, c]
+        for b in range(len(Ji) - 1):
+            e = cache["fe"][f][2]
+            doe[f, :81] = dGi[b].ravel()
+            dao[:81] -= (dGi[b] * A[e]).ravel()
+            f += 1
+    doeb = rd(doe)
+    X = cache["X"]
+    extra = dict(Wo=X.T @ doeb, bo=doe.sum(axis=0), ao=dao)
+    dX = doeb @ P["Wo"].T
+    dh = np.zeros((n, H))
+    dg = np.zeros_like(cache["g"])
+    for f, (i, j, e) in enumerate(cache["fe"]):
+        dh[i] += dX[f, :H]
+        dh[j] += dX[f, H:2 * H]
+        dg[e] += dX[f, 2 * H:]
+    extra.update(dh=dh, dg=dg)
+    return loss, backward(w, feat, cache, do, bf16, extra)
+
+
+def fsai_preconditioner_factor(rows, J, L):
+    """G rows in the original coordinates: G_ij = Ghat_ij L_j^-1."""
+    out = []
+    for Gi, Ji in zip(rows, J):
+        out.append(np.stack([Gi[b] @ np.linalg.inv(L[j]) for b, j in enumerate(Ji)]))
     return out

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libba.so")
 
 BA_OK, BA_ERR_INVALID_ARG, BA_ERR_STATE, BA_ERR_NOT_SPD, BA_ERR_NOT_CONVERGED, BA_ERR_OUT_OF_MEMORY, BA_ERR_DEVICE = range(7)
 BA_FP64, BA_MIXED = 0, 1
-BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED, BA_PRECOND_FSAI = 0, 1, 2
+BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED, BA_PRECOND_FSAI, BA_PRECOND_LEARNED_FSAI = 0, 1, 2, 3
 
 
 class ProblemDesc(C.Structure):
@@ -86,11 +86,14 @@ SIGNATURES = {
     "ba_gnn_set_params": (C.c_int, [_vp, _vp]),
     "ba_gnn_get_params": (C.c_int, [_vp, _vp]),
     "ba_gnn_graph_from_ctx": (C.c_int, [_vp, C.POINTER(C.c_void_p)]),
-    "ba_gnn_graph_from_host": (C.c_int, [C.c_int32, _vp, _vp, _vp, C.POINTER(C.c_void_p)]),
+    "ba_gnn_graph_from_host": (C.c_int, [C.c_int32, _vp, _vp, _vp, _vp, C.POINTER(C.c_void_p)]),
     "ba_gnn_graph_destroy": (None, [_vp]),
     "ba_gnn_loss_grad": (C.c_int, [_vp, _vp, C.c_int32, _vp, C.c_uint64, _dp, _vp]),
     "ba_gnn_train_step": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, C.c_uint64, C.c_float, _dp]),
     "ba_gnn_preconditioner": (C.c_int, [_vp, _vp, _vp]),
+    "ba_gnn_fsai_loss_grad": (C.c_int, [_vp, _vp, _dp, _vp]),
+    "ba_gnn_fsai_train_step": (C.c_int, [_vp, _vp, C.c_int32, C.c_float, _dp]),
+    "ba_gnn_fsai_factor": (C.c_int, [_vp, _vp, _vp]),
     "ba_set_preconditioner_net": (C.c_int, [_vp, _vp]),
     "ba_gemm_bf16": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _vp, _vp, _vp]),
     "ba_gnn_last_error": (C.c_char_p, []),
@@ -310,12 +313,14 @@ def ba_gnn_graph_from_ctx(ctx):
     return h
 
 
-def ba_gnn_graph_from_host(row_ptr, col_idx, blk):
+def ba_gnn_graph_from_host(row_ptr, col_idx, blk, blk_pairs=None):
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     b = np.ascontiguousarray(blk, dtype=np.float64)
+    bp = None if blk_pairs is None else np.ascontiguousarray(blk_pairs, dtype=np.int32)
     h = C.c_void_p()
-    _gnn_check(lib().ba_gnn_graph_from_host(len(rp) - 1, _np_ptr(rp), _np_ptr(ci), _np_ptr(b), C.byref(h)))
+    _gnn_check(lib().ba_gnn_graph_from_host(len(rp) - 1, _np_ptr(rp), _np_ptr(ci), _np_ptr(b), _np_ptr(bp),
+                                            C.byref(h)))
     return h
 
 
@@ -343,6 +348,27 @@ def ba_gnn_preconditioner(net, graph, n_rows):
     P = np.empty((n_rows, 9, 9))
     _gnn_check(lib().ba_gnn_preconditioner(net, graph, _np_ptr(P)))
     return P
+
+
+def ba_gnn_fsai_loss_grad(net, graph, want_grad=True):
+    loss = C.c_double(0.0)
+    grad = np.empty(ba_gnn_param_count(), np.float32) if want_grad else None
+    _gnn_check(lib().ba_gnn_fsai_loss_grad(net, graph, C.byref(loss), _np_ptr(grad)))
+    return loss.value, grad
+
+
+def ba_gnn_fsai_train_step(net, graphs, lr=1e-3):
+    arr = (C.c_void_p * len(graphs))(*[g.value if isinstance(g, C.c_void_p) else g for g in graphs])
+    loss = C.c_double(0.0)
+    _gnn_check(lib().ba_gnn_fsai_train_step(net, arr, len(graphs), lr, C.byref(loss)))
+    return loss.value
+
+
+def ba_gnn_fsai_factor(net, graph, n_blk):
+    """The head's factor G (FP32 [n_blk][9][9] in the RCS block slots)."""
+    G = np.zeros((max(n_blk, 1), 9, 9), np.float32)
+    _gnn_check(lib().ba_gnn_fsai_factor(net, graph, _np_ptr(G)))
+    return G[:n_blk]
 
 
 def ba_set_preconditioner_net(ctx, net):

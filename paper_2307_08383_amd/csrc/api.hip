@@ -54,12 +54,12 @@ void free_ctx(ba_ctx* c) {
     if (!c) return;
     void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->pt_ptr, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
-                    c->sp_ptr, c->sp_ent, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
+                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
                     c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
                     c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
                     c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
-                    c->fs.gl_ent, c->fs.gu_ent, c->fs.An, c->fs.G};
+                    c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -246,13 +246,13 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
                 rowobs_pt[d] = opt[k];
             }
     }
-    // product entries of each row: its upper blocks S_rs (vector row s), then
-    // the blocks (s, r), s < r, of its column, used transposed (vector row s)
-    std::vector<int32_t> sp_ptr(nr + 1, 0), sp_ent;
+    // both triangles by rows: the row's upper blocks S_rs (column s), then the
+    // blocks (s, r), s < r, of its column, transposed (column s)
+    std::vector<int32_t> sf_ptr(nr + 1, 0), sf_col, sf_src;
     {
         std::vector<int32_t> trn(nr, 0);
         for (int32_t sg = 0; sg < c->n_offseg; ++sg) trn[col_idx[off_blk[sg]]]++;
-        for (int32_t r = 0; r < nr; ++r) sp_ptr[r + 1] = sp_ptr[r] + (int32_t)(row_ptr[r + 1] - row_ptr[r]) + trn[r];
+        for (int32_t r = 0; r < nr; ++r) sf_ptr[r + 1] = sf_ptr[r] + (int32_t)(row_ptr[r + 1] - row_ptr[r]) + trn[r];
         std::vector<int32_t> tr_ptr(nr + 1, 0);
         for (int32_t r = 0; r < nr; ++r) tr_ptr[r + 1] = tr_ptr[r] + trn[r];
         std::vector<int32_t> tr_blk(tr_ptr[nr]), tr_row(tr_ptr[nr]);
@@ -263,21 +263,20 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
             tr_blk[d] = off_blk[sg];
             tr_row[d] = seg_row[sg];
         }
-        int32_t es = 1;
-        for (int32_t r = 0; r < nr; ++r) es = std::max(es, sp_ptr[r + 1] - sp_ptr[r]);
-        c->ent_stride = es;
-        sp_ent.assign(2 * (size_t)nr * es, -1);
+        sf_col.resize(sf_ptr[nr]);
+        sf_src.resize(sf_ptr[nr]);
         for (int32_t r = 0; r < nr; ++r) {
-            int64_t d = (int64_t)r * es;
+            int64_t d = sf_ptr[r];
             for (int64_t kb = row_ptr[r]; kb < row_ptr[r + 1]; ++kb, ++d) {
-                sp_ent[2 * d] = (int32_t)kb;
-                sp_ent[2 * d + 1] = col_idx[kb] << 1;
+                sf_col[d] = col_idx[kb];
+                sf_src[d] = (int32_t)kb << 1;
             }
             for (int32_t t = tr_ptr[r]; t < tr_ptr[r + 1]; ++t, ++d) {
-                sp_ent[2 * d] = tr_blk[t];
-                sp_ent[2 * d + 1] = (tr_row[t] << 1) | 1;
+                sf_col[d] = tr_row[t];
+                sf_src[d] = (tr_blk[t] << 1) | 1;
             }
         }
+        c->n_sf = sf_ptr[nr];
     }
     std::vector<int32_t> trip(2 * (size_t)ntr);
     for (int64_t m = 0; m < ntr; ++m) { trip[2 * m] = ta[m]; trip[2 * m + 1] = tb[m]; }
@@ -300,8 +299,9 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->rowobs_ptr, rowobs_ptr);
     upload(c, &c->rowobs, rowobs);
     upload(c, &c->rowobs_pt, rowobs_pt);
-    upload(c, &c->sp_ptr, sp_ptr);
-    upload(c, &c->sp_ent, sp_ent);
+    upload(c, &c->sf_ptr, sf_ptr);
+    upload(c, &c->sf_col, sf_col);
+    upload(c, &c->sf_src, sf_src);
     BA_HIP_CHECK(hipStreamSynchronize(c->stream));
     c->h_row_ptr = std::move(row_ptr);
     c->h_col_idx = std::move(col_idx);
@@ -313,6 +313,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &c->e, (size_t)n * 2);
     dalloc(c, &c->ptL, (size_t)np * 9);
     dalloc(c, &c->blk, (size_t)c->n_blk * 81);
+    dalloc(c, &c->Sf, (size_t)c->n_sf * 81);
     dalloc(c, &c->rhs, (size_t)nr * 9);
     dalloc(c, &c->Minv, (size_t)nr * 81);
     dalloc(c, &c->Linv, (size_t)nr * 81);
@@ -386,6 +387,7 @@ ba_status form_rcs_async(ba_ctx* c, double lambda) {
     BA_HIP_CHECK(hipEventRecord(c->ev[4], c->stream));
     BA_HIP_CHECK(hipGetLastError());
     c->have_rcs = true;
+    c->sf_ready = false;
     c->fs.ready = false;
     c->defl_ready = false;
     c->lambda = lambda;
@@ -398,6 +400,15 @@ void prepare_defl(ba_ctx* c) {
         BA_HIP_CHECK(hipGetLastError());
         c->defl_ready = true;
     }
+}
+
+// the network's factor of the current RCS into the FSAI layouts
+void prepare_learned_fsai(ba_ctx* c) {
+    if (!c->fs.built) ba::build_fsai(c);
+    auto* g = (ba::gnn::Graph*)c->lgraph;
+    ba::gnn::compute_features(*g, c->blk, c->stream);
+    ba::gnn::infer_factor(c->net, *g, c->fs.gu_pos, c->fs.Gl, c->fs.Gu, c->fs.G, c->stream);
+    c->fs.ready = false;   // the layouts now hold the network's factor
 }
 
 // the FSAI factor of the current RCS (index structure on first use)
@@ -430,36 +441,18 @@ void build_fsai(ba_ctx* c) {
     const std::vector<int64_t>& rp = c->h_row_ptr;
     const std::vector<int32_t>& ci = c->h_col_idx;
     const std::vector<int32_t>& cnt = c->h_blk_pairs;
-    std::vector<std::vector<std::pair<int32_t, int64_t>>> low(nr);
     std::vector<int32_t> brow(c->n_blk);
     for (int32_t r = 0; r < nr; ++r)
-        for (int64_t kb = rp[r]; kb < rp[r + 1]; ++kb) {
-            brow[kb] = r;
-            if (kb > rp[r]) low[ci[kb]].push_back({r, kb});
-        }
-    std::vector<int32_t> ptr(nr + 1, 0), J, slot, tile;
+        for (int64_t kb = rp[r]; kb < rp[r + 1]; ++kb) brow[kb] = r;
+    std::vector<int32_t> ptr, J, slot, tile;
+    ba::gnn::fsai_sets(nr, rp.data(), ci.data(), cnt.data(), ptr, J, slot);
     std::vector<int64_t> tptr(nr + 1, 0);
     std::vector<std::vector<std::pair<int32_t, int32_t>>> gu(nr);
     int32_t max_m = 1;
     for (int32_t i = 0; i < nr; ++i) {
-        auto& L = low[i];
-        std::sort(L.begin(), L.end(), [&](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) {
-            const int32_t cx = cnt[x.second], cy = cnt[y.second];
-            return cx != cy ? cx > cy : x.first < y.first;
-        });
-        if ((int)L.size() > kFsaiM - 1) L.resize(kFsaiM - 1);
-        std::sort(L.begin(), L.end());
-        const int32_t m = (int32_t)L.size() + 1;
+        const int32_t m = ptr[i + 1] - ptr[i];
+        const int32_t* Jm = J.data() + ptr[i];
         max_m = std::max(max_m, m);
-        std::vector<int32_t> Jm;
-        for (auto& e : L) {
-            Jm.push_back(e.first);
-            slot.push_back((int32_t)e.second);
-        }
-        Jm.push_back(i);
-        slot.push_back((int32_t)rp[i]);
-        J.insert(J.end(), Jm.begin(), Jm.end());
-        ptr[i + 1] = ptr[i] + m;
         for (int32_t a = 0; a < m; ++a)
             for (int32_t b = 0; b <= a; ++b) {
                 if (a == b) {
@@ -472,23 +465,19 @@ void build_fsai(ba_ctx* c) {
                 tile.push_back(it != last && *it == ja ? (int32_t)(it - ci.begin()) : -1);
             }
         tptr[i + 1] = tptr[i] + (int64_t)m * (m + 1) / 2;
-        for (int32_t b = 0; b < m; ++b) gu[Jm[b]].push_back({slot[ptr[i] + b], (i << 1) | 1});
+        for (int32_t b = 0; b < m; ++b) gu[Jm[b]].push_back({i, ptr[i] + b});
     }
-    int32_t gus = 1;
-    for (auto& g : gu) gus = std::max(gus, (int32_t)g.size());
-    std::vector<int32_t> gl_ent(2 * (size_t)nr * max_m, -1), gu_ent(2 * (size_t)nr * gus, -1);
-    for (int32_t i = 0; i < nr; ++i) {
-        for (int32_t b = 0; b < ptr[i + 1] - ptr[i]; ++b) {
-            const size_t d = (size_t)i * max_m + b;
-            gl_ent[2 * d] = slot[ptr[i] + b];
-            gl_ent[2 * d + 1] = J[ptr[i] + b] << 1;
+    // rows of G^T: row j lists (i, member b) for every set J_i containing j,
+    // in i order
+    std::vector<int32_t> gu_ptr(nr + 1, 0), gu_col, gu_pos(J.size());
+    for (int32_t j = 0; j < nr; ++j) gu_ptr[j + 1] = gu_ptr[j] + (int32_t)gu[j].size();
+    gu_col.resize(gu_ptr[nr]);
+    for (int32_t j = 0; j < nr; ++j)
+        for (size_t e = 0; e < gu[j].size(); ++e) {
+            const int32_t d = gu_ptr[j] + (int32_t)e;
+            gu_col[d] = gu[j][e].first;
+            gu_pos[gu[j][e].second] = d;
         }
-        for (size_t b = 0; b < gu[i].size(); ++b) {
-            const size_t d = (size_t)i * gus + b;
-            gu_ent[2 * d] = gu[i][b].first;
-            gu_ent[2 * d + 1] = gu[i][b].second;
-        }
-    }
     Fsai& F = c->fs;
     upload(c, &F.ptr, ptr);
     upload(c, &F.J, J);
@@ -496,11 +485,12 @@ void build_fsai(ba_ctx* c) {
     upload(c, &F.tptr, tptr);
     upload(c, &F.tile, tile);
     upload(c, &F.brow, brow);
-    upload(c, &F.gl_ent, gl_ent);
-    upload(c, &F.gu_ent, gu_ent);
-    F.gl_stride = max_m;
-    F.gu_stride = gus;
+    upload(c, &F.gu_ptr, gu_ptr);
+    upload(c, &F.gu_col, gu_col);
+    upload(c, &F.gu_pos, gu_pos);
     F.max_m = max_m;
+    dalloc(c, &F.Gl, J.size() * 81);
+    dalloc(c, &F.Gu, J.size() * 81);
     dalloc(c, &F.An, (size_t)c->n_blk * 81);
     dalloc(c, &F.G, (size_t)c->n_blk * 81);
     BA_HIP_CHECK(hipMemsetAsync(F.G, 0, (size_t)c->n_blk * 81 * sizeof(float), c->stream));
@@ -519,7 +509,8 @@ ba_status ba_set_preconditioner_net(ba_ctx* c, ba_gnn* net) {
         if (net && !c->Mlearn) dalloc(c, &c->Mlearn, (size_t)c->n_rows * 81);
         if (net && !c->lgraph && c->n_rows > 0) {
             auto* g = new ba::gnn::Graph();
-            ba::gnn::build_graph(*g, c->n_rows, c->h_row_ptr.data(), c->h_col_idx.data(), c->stream);
+            ba::gnn::build_graph(*g, c->n_rows, c->h_row_ptr.data(), c->h_col_idx.data(), c->h_blk_pairs.data(),
+                                 c->stream);
             c->lgraph = g;
         }
         return BA_OK;
@@ -533,7 +524,8 @@ ba_status ba_gnn_graph_from_ctx(ba_ctx* c, ba_gnn_graph** out) {
     if (c->n_rows == 0) { c->err = "no free cameras"; return BA_ERR_INVALID_ARG; }
     ba_gnn_graph* G = new ba_gnn_graph();
     ba_status s = guarded(c, [&]() {
-        ba::gnn::build_graph(G->g, c->n_rows, c->h_row_ptr.data(), c->h_col_idx.data(), c->stream);
+        ba::gnn::build_graph(G->g, c->n_rows, c->h_row_ptr.data(), c->h_col_idx.data(), c->h_blk_pairs.data(),
+                             c->stream);
         ba::gnn::compute_features(G->g, c->blk, c->stream);
         BA_HIP_CHECK(hipStreamSynchronize(c->stream));
         return BA_OK;
@@ -681,8 +673,12 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
     const int max_iter = o ? o->max_iter : 1000;
     const int pre = o ? o->precond : BA_PRECOND_BLOCK_JACOBI;
     if (!(tol >= 0.0) || max_iter < 0) { c->err = "tol must be >= 0 and max_iter >= 0"; return BA_ERR_INVALID_ARG; }
-    if (pre == BA_PRECOND_LEARNED && !c->learned_ready) { c->err = "no learned preconditioner set"; return BA_ERR_STATE; }
-    if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI && pre != BA_PRECOND_FSAI) {
+    if ((pre == BA_PRECOND_LEARNED || pre == BA_PRECOND_LEARNED_FSAI) && !c->learned_ready) {
+        c->err = "no learned preconditioner set";
+        return BA_ERR_STATE;
+    }
+    if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI && pre != BA_PRECOND_FSAI &&
+        pre != BA_PRECOND_LEARNED_FSAI) {
         c->err = "unknown preconditioner";
         return BA_ERR_INVALID_ARG;
     }
@@ -691,12 +687,13 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
         double rr = 0.0;
         if (pre == BA_PRECOND_LEARNED && c->n_rows > 0) prepare_learned(c);
         if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
+        if (pre == BA_PRECOND_LEARNED_FSAI && c->n_rows > 0) prepare_learned_fsai(c);
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(c->ev[6], c->stream));
         ba_status s = BA_OK;
         if (c->n_rows > 0)
-            s = ba::run_pcg(c, pre == BA_PRECOND_FSAI ? 1 : 0, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, defl,
+            s = ba::run_pcg(c, (pre == BA_PRECOND_FSAI || pre == BA_PRECOND_LEARNED_FSAI) ? 1 : 0, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, defl,
                             tol, max_iter, o ? o->x0 : nullptr, dxc, &it, &rr);
         BA_HIP_CHECK(hipEventRecord(c->ev[7], c->stream));
         BA_HIP_CHECK(hipEventSynchronize(c->ev[7]));
@@ -733,8 +730,12 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
     const double tol = o ? o->pcg_tol : 1e-6;
     const int max_iter = o ? o->pcg_max_iter : 1000;
     const int pre = o ? o->precond : BA_PRECOND_BLOCK_JACOBI;
-    if (pre == BA_PRECOND_LEARNED && !c->learned_ready) { c->err = "no learned preconditioner set"; return BA_ERR_STATE; }
-    if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI && pre != BA_PRECOND_FSAI) {
+    if ((pre == BA_PRECOND_LEARNED || pre == BA_PRECOND_LEARNED_FSAI) && !c->learned_ready) {
+        c->err = "no learned preconditioner set";
+        return BA_ERR_STATE;
+    }
+    if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI && pre != BA_PRECOND_FSAI &&
+        pre != BA_PRECOND_LEARNED_FSAI) {
         c->err = "unknown preconditioner";
         return BA_ERR_INVALID_ARG;
     }
@@ -760,11 +761,12 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         BA_HIP_CHECK(hipEventRecord(ev[14], c->stream));
         if (pre == BA_PRECOND_LEARNED && c->n_rows > 0) prepare_learned(c);
         if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
+        if (pre == BA_PRECOND_LEARNED_FSAI && c->n_rows > 0) prepare_learned_fsai(c);
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(ev[6], c->stream));
         if (c->n_rows > 0)
-            ps = ba::run_pcg(c, pre == BA_PRECOND_FSAI ? 1 : 0, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, defl,
+            ps = ba::run_pcg(c, (pre == BA_PRECOND_FSAI || pre == BA_PRECOND_LEARNED_FSAI) ? 1 : 0, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, defl,
                              tol, max_iter, nullptr, c->dxc, &it, &rr);
         else
             BA_HIP_CHECK(hipMemsetAsync(c->dxc, 0, sizeof(double), c->stream));
@@ -849,7 +851,7 @@ ba_status ba_get_gauge(ba_ctx* c, double* W) {
 
 ba_status ba_get_fsai(ba_ctx* c, float* G) {
     if (!c || !G) return BA_ERR_INVALID_ARG;
-    if (!c->fs.ready) { c->err = "no FSAI factor of the current RCS"; return BA_ERR_STATE; }
+    if (!c->fs.built || !c->have_rcs) { c->err = "no FSAI factor of the current RCS"; return BA_ERR_STATE; }
     return guarded(c, [&]() {
         BA_HIP_CHECK(hipMemcpyAsync(G, c->fs.G, (size_t)c->n_blk * 81 * sizeof(float), hipMemcpyDeviceToHost, c->stream));
         BA_HIP_CHECK(hipStreamSynchronize(c->stream));

@@ -202,8 +202,10 @@ struct Fsai {
     int32_t *tile = nullptr;          // per set, lower tiles (a, b), a >= b, packed a(a+1)/2 + b:
                                       // upper block (J_b, J_a), -2 on the diagonal, -1 if absent
     int32_t *brow = nullptr;          // [n_blk] block row of every RCS block
-    int32_t *gl_ent = nullptr, *gu_ent = nullptr;   // (slot, vector row << 1 | transposed)
-    int32_t gl_stride = 0, gu_stride = 0, max_m = 0;
+    int32_t *gu_ptr = nullptr, *gu_col = nullptr;   // rows of G^T: [n_rows+1], column (row i of G)
+    int32_t *gu_pos = nullptr;        // per set member (like J): its position in the rows of G^T
+    int32_t max_m = 0;
+    float *Gl = nullptr, *Gu = nullptr;   // G by rows (like J) and G^T by rows (like gu_col), 9x9 each
     float* An = nullptr;              // [n_blk][81] L_r^-1 S_rc L_c^-T of off-diagonal blocks
     float* G = nullptr;               // [n_blk][81] G in the upper slots
 };
@@ -232,8 +234,13 @@ struct ba_ctx {
     int32_t *row_ptr = nullptr, *col_idx = nullptr;
     int32_t *off_blk = nullptr, *pair_ptr = nullptr, *trip = nullptr;
     int32_t *rowobs_ptr = nullptr, *rowobs = nullptr;
-    int32_t *sp_ptr = nullptr, *sp_ent = nullptr;   // per row, padded to ent_stride: (block, vector row << 1 | transposed)
-    int32_t ent_stride = 0;
+    // both triangles of the RCS by rows (upper blocks of the row, then the
+    // transposed blocks of its column): pointer, column, source block << 1 |
+    // transposed, and the FP64 copy made for PCG after each formation
+    int32_t *sf_ptr = nullptr, *sf_col = nullptr, *sf_src = nullptr;
+    int64_t n_sf = 0;
+    double* Sf = nullptr;
+    bool sf_ready = false;
     // linearization / formation
     void* R = nullptr;                 // [n_obs][24] T: J_c (18) from linearize, K (6) from the point stage
     void* Jp = nullptr;                // [n_obs][6] T: J_p

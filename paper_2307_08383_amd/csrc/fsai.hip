@@ -10,7 +10,9 @@
 // The local matrix is factored in FP32 in LDS after block-Jacobi
 // normalisation (its diagonal blocks become I):
 //   Ahat_jk = L_j^-1 S_jk L_k^-T,  S_jj = L_j L_j^T,
-// and the result is mapped back: G_ij = Ghat_ij L_j^-1.
+// and the result is mapped back: G_ij = Ghat_ij L_j^-1.  G is written in
+// three layouts: the RCS block slots (for copies out), by rows of G and by
+// rows of G^T (the two products of the PCG).
 #include "ba_common.hpp"
 
 namespace ba {
@@ -112,7 +114,8 @@ __device__ __forceinline__ bool chol9_wave(float* T, float* Di) {
 __global__ __launch_bounds__(BS) void k_fsai(const int32_t* __restrict__ fs_ptr, const int32_t* __restrict__ fs_J,
                                              const int32_t* __restrict__ fs_slot, const int64_t* __restrict__ fs_tptr,
                                              const int32_t* __restrict__ fs_tile, const float* __restrict__ An,
-                                             const double* __restrict__ Linv, float* __restrict__ G,
+                                             const double* __restrict__ Linv, const int32_t* __restrict__ gu_pos,
+                                             float* __restrict__ G, float* __restrict__ Gl, float* __restrict__ Gu,
                                              int* __restrict__ flags) {
     __shared__ float T[kFsaiTiles][81];
     __shared__ float Di[kFsaiM][81];
@@ -238,7 +241,10 @@ __global__ __launch_bounds__(BS) void k_fsai(const int32_t* __restrict__ fs_ptr,
         } else if (b == last) {
             s = Lj[pq];
         }
-        G[(int64_t)fs_slot[j0 + b] * 81 + pq] = (float)s;
+        const float g = (float)s;
+        G[(int64_t)fs_slot[j0 + b] * 81 + pq] = g;
+        Gl[(int64_t)(j0 + b) * 81 + pq] = g;
+        Gu[(int64_t)gu_pos[j0 + b] * 81 + q * 9 + p] = g;
     }
     if (bad && threadIdx.x == 0) atomicAdd(flags + 2, 1);
 }
@@ -252,7 +258,7 @@ void launch_fsai(ba_ctx* c) {
                                                                     c->fs.An);
     if (c->n_rows > 0)
         k_fsai<<<c->n_rows, BS, 0, c->stream>>>(c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.An,
-                                                c->Linv, c->fs.G, c->flags);
+                                                c->Linv, c->fs.gu_pos, c->fs.G, c->fs.Gl, c->fs.Gu, c->flags);
 }
 
 }  // namespace ba

@@ -455,6 +455,204 @@ __global__ __launch_bounds__(64) void k_assemble(int n, const float* __restrict_
         }
 }
 
+// ---------------------------------------------------------------------------
+// factorised head (FSAI pattern): M^-1 = G^T G, G block-lower-triangular on
+// the sets J_i; in the block-Jacobi-normalised coordinates Ghat = G L,
+// Ghat_ii = Lt_i (node decoder) and, for the members j < i,
+// Ghat_ij = reshape(Wo^T [h_i, h_j, g_ij] + bo)[:81] - ao[:81] * A_ij.
+// Training minimises the Kaporin functional
+//   f = (1/(9n)) sum_i [tr(Ghat_i Ahat[J_i, J_i] Ghat_i^T) - 2 log det Ghat_ii],
+// whose minimiser over the pattern is the exact FSAI factor.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int ftix(int a, int b) { return a * (a + 1) / 2 + b; }
+
+// X_f = [h_i, h_j, g_ij] (bf16) of the FSAI edges
+__global__ __launch_bounds__(BS) void k_fgather(int fE, const int32_t* __restrict__ fsrc,
+                                                const int32_t* __restrict__ fdst, const int32_t* __restrict__ fe,
+                                                const __bf16* __restrict__ Hb, const __bf16* __restrict__ Gb,
+                                                __bf16* __restrict__ Xf) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= (int64_t)fE * 3 * H) return;
+    const int64_t f = t / (3 * H);
+    const int c = (int)(t % (3 * H));
+    __bf16 v;
+    if (c < H)
+        v = Hb[(int64_t)fsrc[f] * H + c];
+    else if (c < 2 * H)
+        v = Hb[(int64_t)fdst[f] * H + c - H];
+    else
+        v = Gb[(int64_t)fe[f] * H + c - 2 * H];
+    Xf[t] = v;
+}
+
+// element pq of Ghat for member b of row i (m members, first FSAI edge f0)
+__device__ __forceinline__ float ghat_elem(int i, int b, int m, int f0, int u_edge, int pq, const float* __restrict__ O,
+                                           const float* __restrict__ OE, const float* __restrict__ ao,
+                                           const float* __restrict__ A) {
+    if (b < m - 1) return OE[(int64_t)(f0 + b) * F_OFF + pq] - ao[pq] * A[(int64_t)u_edge * 81 + pq];
+    const int p = pq / 9, q = pq % 9;
+    const float* o = O + (int64_t)i * F_OUT;
+    if (q == p) return expf(o[p]);
+    if (q < p) return o[9 + p * (p - 1) / 2 + q];
+    return 0.f;
+}
+
+// One workgroup per row: the row's term of the Kaporin functional (kpart,
+// unscaled) and its gradient with respect to the decoder output (dO, all
+// 48 entries), the head output (dOE, 96 entries per FSAI edge) and, per
+// FSAI edge, the contributions to d/d ao (aE, 81 entries).
+__global__ __launch_bounds__(BS) void k_kaporin(float scale, const int32_t* __restrict__ fptr,
+                                                const int32_t* __restrict__ fedge, const int64_t* __restrict__ ftptr,
+                                                const int32_t* __restrict__ ftile, const float* __restrict__ A,
+                                                const float* __restrict__ O, const float* __restrict__ OE,
+                                                const float* __restrict__ ao, float* __restrict__ dO,
+                                                float* __restrict__ dOE, float* __restrict__ aE,
+                                                double* __restrict__ kpart) {
+    __shared__ float T[kFsaiTiles][81];
+    __shared__ float Gm[kFsaiM][81];
+    __shared__ double red[BS / 64];
+    const int i = blockIdx.x;
+    const int j0 = fptr[i], m = fptr[i + 1] - j0;
+    const int f0 = j0 - i;
+    const int32_t* tiles = ftile + ftptr[i];
+    const int nt = m * (m + 1) / 2;
+    for (int e = threadIdx.x; e < nt * 81; e += BS) {
+        const int ti = e / 81, pq = e % 81;
+        const int kb = tiles[ti];
+        T[ti][pq] = kb == -2 ? ((pq / 9 == pq % 9) ? 1.f : 0.f) : (kb < 0 ? 0.f : A[(int64_t)kb * 81 + pq]);
+    }
+    for (int e = threadIdx.x; e < m * 81; e += BS) {
+        const int b = e / 81;
+        Gm[b][e % 81] = ghat_elem(i, b, m, f0, b < m - 1 ? fedge[j0 + b] : 0, e % 81, O, OE, ao, A);
+    }
+    __syncthreads();
+    double fsum = 0.0;
+    for (int e = threadIdx.x; e < m * 81; e += BS) {
+        const int b = e / 81, pq = e % 81, p = pq / 9, q = pq % 9;
+        // Y_b[p][q] = sum_a (Ghat_a Ahat(J_a, J_b))[p][q]
+        float y = 0.f;
+        for (int a = 0; a < m; ++a) {
+            const float* Ga = Gm[a] + p * 9;
+            if (a >= b) {
+                const float* t = T[ftix(a, b)];
+#pragma unroll
+                for (int v = 0; v < 9; ++v) y += Ga[v] * t[v * 9 + q];
+            } else {
+                const float* t = T[ftix(b, a)];
+#pragma unroll
+                for (int v = 0; v < 9; ++v) y += Ga[v] * t[q * 9 + v];
+            }
+        }
+        const float g = Gm[b][pq];
+        fsum += (double)y * (double)g;
+        float d = scale * y;
+        if (b == m - 1) {
+            if (q == p) {
+                d -= scale / g;
+                dO[(int64_t)i * F_OUT + p] = d * g;   // Ghat_pp = exp(o_p)
+            } else if (q < p) {
+                dO[(int64_t)i * F_OUT + 9 + p * (p - 1) / 2 + q] = d;
+            }
+        } else {
+            const int64_t f = f0 + b;
+            dOE[f * F_OFF + pq] = d;
+            aE[f * 81 + pq] = -d * A[(int64_t)fedge[j0 + b] * 81 + pq];
+        }
+    }
+    // padding entries
+    if (threadIdx.x < F_OUT - 45) dO[(int64_t)i * F_OUT + 45 + threadIdx.x] = 0.f;
+    for (int e = threadIdx.x; e < (m - 1) * (F_OFF - 81); e += BS)
+        dOE[(int64_t)(f0 + e / (F_OFF - 81)) * F_OFF + 81 + e % (F_OFF - 81)] = 0.f;
+    // row term: trace part plus -2 log det Ghat_ii = -2 sum_k o_k
+    double v = fsum;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < BS / 64; ++w) t += red[w];
+        for (int k = 0; k < 9; ++k) t -= 2.0 * (double)O[(int64_t)i * F_OUT + k];
+        kpart[i] = t;
+    }
+}
+
+// loss = sum_i kpart_i / N (fixed order, one block)
+__global__ void k_kaporin_total(int n, double inv_n9, const double* __restrict__ kpart, double* __restrict__ out) {
+    __shared__ double red[BS];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += BS) v += kpart[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < BS; ++k) t += red[k];
+        out[0] = t * inv_n9;
+    }
+}
+
+// dH[j] += sum over FSAI edges with source j of dXf[:, 0:H] and with
+// destination j of dXf[:, H:2H] (fixed order)
+__global__ __launch_bounds__(BS) void k_fscatter_h(int n, const int32_t* __restrict__ fptr,
+                                                   const int32_t* __restrict__ fd_ptr,
+                                                   const int32_t* __restrict__ fd_list, const float* __restrict__ dXf,
+                                                   float* __restrict__ dH) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= (int64_t)n * H) return;
+    const int j = (int)(t / H), c = (int)(t % H);
+    float s = 0.f;
+    for (int f = fptr[j] - j; f < fptr[j + 1] - (j + 1); ++f) s += dXf[(int64_t)f * 3 * H + c];
+    for (int k = fd_ptr[j]; k < fd_ptr[j + 1]; ++k) s += dXf[(int64_t)fd_list[k] * 3 * H + H + c];
+    dH[t] += s;
+}
+
+// dG[e] += dXf[f, 2H:3H] for the FSAI edge f of directed edge e
+__global__ __launch_bounds__(BS) void k_fscatter_g(int E, const int32_t* __restrict__ e2f, const float* __restrict__ dXf,
+                                                   float* __restrict__ dG) {
+    const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (t >= (int64_t)E * H) return;
+    const int e = (int)(t / H), c = (int)(t % H);
+    const int f = e2f[e];
+    if (f >= 0) dG[t] += dXf[(int64_t)f * 3 * H + 2 * H + c];
+}
+
+// G of every set member in the original coordinates, G_ij = Ghat_ij L_j^-1
+// (FP64 products), into the layouts given (81 threads per member)
+__global__ __launch_bounds__(128) void k_fassemble(int n, int fm, const int32_t* __restrict__ fptr,
+                                                   const int32_t* __restrict__ fJ, const int32_t* __restrict__ fedge,
+                                                   const int32_t* __restrict__ fslot, const float* __restrict__ O,
+                                                   const float* __restrict__ OE, const float* __restrict__ ao,
+                                                   const float* __restrict__ A, const double* __restrict__ Linv,
+                                                   const int32_t* __restrict__ gu_pos, float* __restrict__ Gl,
+                                                   float* __restrict__ Gu, float* __restrict__ Gs) {
+    __shared__ float gh[81];
+    const int u = blockIdx.x;
+    // row of member u
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (fptr[mid] <= u) lo = mid; else hi = mid;
+    }
+    const int i = lo, m = fptr[i + 1] - fptr[i], b = u - fptr[i];
+    const int pq = threadIdx.x;
+    if (pq < 81) gh[pq] = ghat_elem(i, b, m, fptr[i] - i, b < m - 1 ? fedge[u] : 0, pq, O, OE, ao, A);
+    __syncthreads();
+    if (pq >= 81) return;
+    const int p = pq / 9, q = pq % 9;
+    const double* Lj = Linv + (int64_t)fJ[u] * 81;
+    double s = 0.0;
+    for (int v = q; v < 9; ++v) s += (double)gh[p * 9 + v] * Lj[v * 9 + q];
+    const float g = (float)s;
+    if (Gl) Gl[(int64_t)u * 81 + pq] = g;
+    if (Gu) Gu[(int64_t)gu_pos[u] * 81 + q * 9 + p] = g;
+    if (Gs) Gs[(int64_t)fslot[u] * 81 + pq] = g;
+}
+
+__global__ __launch_bounds__(BS) void k_add(int64_t n, const float* __restrict__ a, float* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i < n) b[i] += a[i];
+}
+
 template <typename T>
 void grow(T** p, size_t n) {
     if (*p) (void)hipFree(*p);
@@ -480,11 +678,20 @@ void ensure_work(Work& W, int n, int E, int P) {
     grow(&W.dP, big); grow(&W.dPb, big);
     const size_t rows = std::max(n, E);
     const size_t nsplit = (rows + KSPLIT_ROWS - 1) / KSPLIT_ROWS;
-    grow(&W.split, nsplit * 3 * H * H);
+    grow(&W.split, nsplit * 3 * H * std::max(H, F_OFF));
     grow(&W.colpart, ((rows + 1023) / 1024) * 3 * H);
     grow(&W.loss_part, (size_t)n / 64 + 2);
     grow(&W.loss, 2);
     W.cap_n = n; W.cap_E = E; W.cap_p = P;
+}
+
+void ensure_fwork(Work& W, const Graph& g) {
+    if (g.fE <= W.cap_f && g.n <= W.cap_fn) return;
+    const int fE = std::max(std::max(g.fE, W.cap_f), 1), n = std::max(std::max(g.n, W.cap_fn), 1);
+    grow(&W.Xf, (size_t)fE * 3 * H); grow(&W.OE, (size_t)fE * F_OFF); grow(&W.dOE, (size_t)fE * F_OFF);
+    grow(&W.dOEb, (size_t)fE * F_OFF); grow(&W.dXf, (size_t)fE * 3 * H); grow(&W.aE, (size_t)fE * 81);
+    grow(&W.kpart, (size_t)n);
+    W.cap_f = fE; W.cap_fn = n;
 }
 
 void gemm(hipStream_t st, int M, int N, int K, const __bf16* A, int64_t sam, int64_t sak, const __bf16* B,
@@ -537,6 +744,17 @@ void forward(ba_gnn* net, Graph& g, hipStream_t st) {
     gemm(st, n, F_OUT, H, W.Hb + N_LAYERS * nh, H, 1, wb + OFF_WD, F_OUT, 1, w + OFF_BD, false, W.O, F_OUT, nullptr, 0);
 }
 
+// factorised head: X_f and OE = Wo^T X_f + bo for the FSAI edges
+void head_forward(ba_gnn* net, Graph& g, hipStream_t st) {
+    Work& W = net->work;
+    if (g.fE == 0) return;
+    const int64_t nh = (int64_t)g.n * H;
+    k_fgather<<<nblk((int64_t)g.fE * 3 * H), BS, 0, st>>>(g.fE, g.fsrc, g.fdst, g.fe, W.Hb + N_LAYERS * nh, W.Gb,
+                                                           W.Xf);
+    gemm(st, g.fE, F_OFF, 3 * H, W.Xf, 3 * H, 1, net->wb + OFF_WO, F_OFF, 1, net->w + OFF_BO, false, W.OE, F_OFF,
+         nullptr, 0);
+}
+
 // loss for probes already in W.Z: Y = A Z, loss and dO
 void loss(ba_gnn* net, Graph& g, int P, hipStream_t st) {
     Work& W = net->work;
@@ -548,7 +766,7 @@ void loss(ba_gnn* net, Graph& g, int P, hipStream_t st) {
     k_loss_fin<<<1, 64, 0, st>>>(nb, W.loss_part, W.loss);
 }
 
-void backward(ba_gnn* net, Graph& g, float* grad, hipStream_t st) {
+void backward(ba_gnn* net, Graph& g, float* grad, hipStream_t st, bool head = false) {
     Work& W = net->work;
     const int n = g.n, E = g.E;
     const __bf16* wb = net->wb;
@@ -559,6 +777,21 @@ void backward(ba_gnn* net, Graph& g, float* grad, hipStream_t st) {
     colsum(st, W, n, F_OUT, W.dO, F_OUT, grad + OFF_BD);
     // dH = dO Wd^T   (B(k=o, n=h) = Wd[h][o])
     gemm(st, n, H, F_OUT, W.dOb, F_OUT, 1, wb + OFF_WD, 1, F_OUT, nullptr, false, W.dH, H, nullptr, 0);
+    const bool fhead = head && g.fE > 0;
+    if (fhead) {
+        const int64_t no = (int64_t)g.fE * F_OFF;
+        k_to_bf16<<<nblk(no), BS, 0, st>>>(no, W.dOE, W.dOEb);
+        wgrad(st, W, 3 * H, F_OFF, g.fE, W.Xf, 3 * H, W.dOEb, F_OFF, grad + OFF_WO);
+        colsum(st, W, g.fE, F_OFF, W.dOE, F_OFF, grad + OFF_BO);
+        BA_HIP_CHECK(hipMemsetAsync(grad + OFF_AO, 0, F_OFF * sizeof(float), st));
+        colsum(st, W, g.fE, 81, W.aE, 81, grad + OFF_AO);
+        // dX_f = dOE Wo^T  (B(k=o, n=x) = Wo[x][o])
+        gemm(st, g.fE, 3 * H, F_OFF, W.dOEb, F_OFF, 1, wb + OFF_WO, 1, F_OFF, nullptr, false, W.dXf, 3 * H,
+             nullptr, 0);
+        k_fscatter_h<<<nblk(nh), BS, 0, st>>>(n, g.fptr, g.fd_ptr, g.fd_list, W.dXf, W.dH);
+    } else {
+        BA_HIP_CHECK(hipMemsetAsync(grad + OFF_WO, 0, (N_PARAMS - OFF_WO) * sizeof(float), st));
+    }
     for (int l = N_LAYERS - 1; l >= 0; --l) {
         const __bf16* Xm = W.Xm + (int64_t)l * 3 * eh;
         const __bf16* Xu = W.Xu + (int64_t)l * 2 * nh;
@@ -579,6 +812,7 @@ void backward(ba_gnn* net, Graph& g, float* grad, hipStream_t st) {
         }
         k_msg_scatter<<<nblk(nh), BS, 0, st>>>(n, g.eptr, g.etwin, W.dXu, W.dXm, W.dH);
     }
+    if (fhead) k_fscatter_g<<<nblk(eh), BS, 0, st>>>(E, g.e2f, W.dXf, W.dG);
     // encoders
     k_relu_back<<<nblk(nh), BS, 0, st>>>(nh, W.dH, W.H0, H, H, H, W.dP, W.dPb);
     wgrad(st, W, F_NODE, H, n, g.xn, F_NODE, W.dPb, H, grad + OFF_WN);
@@ -594,7 +828,8 @@ void backward(ba_gnn* net, Graph& g, float* grad, hipStream_t st) {
 
 }  // namespace
 
-void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx, hipStream_t st) {
+void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* blk_pairs,
+                 hipStream_t st) {
     struct Ed { int32_t s, d, b, t; };
     std::vector<Ed> ed;
     std::vector<int32_t> diag(n);
@@ -635,11 +870,57 @@ void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx
     BA_HIP_CHECK(hipMalloc((void**)&g.Linv, (size_t)std::max(n, 1) * 81 * sizeof(double)));
     BA_HIP_CHECK(hipMalloc((void**)&g.flags, 4 * sizeof(int)));
     g.bytes += (size_t)n * (F_NODE * 2 + 81 * 8) + (size_t)E * (F_EDGE * 2 + 81 * 4);
+    g.n_blk = (int)row_ptr[n];
+    if (blk_pairs) {
+        std::vector<int32_t> fptr, fJ, fslot;
+        fsai_sets(n, row_ptr, col_idx, blk_pairs, fptr, fJ, fslot);
+        auto edge = [&](int32_t a, int32_t b) -> int32_t {   // directed edge a -> b or -1
+            const auto first = dst.begin() + eptr[a], last = dst.begin() + eptr[a + 1];
+            const auto it = std::lower_bound(first, last, b);
+            return (it != last && *it == b) ? (int32_t)(it - dst.begin()) : -1;
+        };
+        const int fm = (int)fJ.size();
+        std::vector<int32_t> fedge(fm, -1), ftile, fsrc, fdst, fe, e2f(E, -1);
+        std::vector<int64_t> ftptr(n + 1, 0);
+        int max_m = 1;
+        for (int i = 0; i < n; ++i) {
+            const int j0 = fptr[i], m = fptr[i + 1] - j0;
+            max_m = std::max(max_m, m);
+            for (int b = 0; b < m - 1; ++b) {
+                fedge[j0 + b] = edge(i, fJ[j0 + b]);
+                e2f[fedge[j0 + b]] = (int32_t)fsrc.size();
+                fsrc.push_back(i);
+                fdst.push_back(fJ[j0 + b]);
+                fe.push_back(fedge[j0 + b]);
+            }
+            for (int a = 0; a < m; ++a)
+                for (int b = 0; b <= a; ++b) ftile.push_back(a == b ? -2 : edge(fJ[j0 + a], fJ[j0 + b]));
+            ftptr[i + 1] = ftptr[i] + (int64_t)m * (m + 1) / 2;
+        }
+        const int fE = (int)fsrc.size();
+        std::vector<int32_t> fd_ptr(n + 1, 0), fd_list(fE);
+        for (int f = 0; f < fE; ++f) fd_ptr[fdst[f] + 1]++;
+        for (int i = 0; i < n; ++i) fd_ptr[i + 1] += fd_ptr[i];
+        {
+            std::vector<int32_t> fill(fd_ptr.begin(), fd_ptr.end() - 1);
+            for (int f = 0; f < fE; ++f) fd_list[fill[fdst[f]]++] = f;
+        }
+        up(&g.fptr, fptr); up(&g.fJ, fJ); up(&g.fedge, fedge); up(&g.fslot, fslot); up(&g.ftile, ftile);
+        up(&g.fsrc, fsrc); up(&g.fdst, fdst); up(&g.fe, fe); up(&g.fd_ptr, fd_ptr); up(&g.fd_list, fd_list);
+        up(&g.e2f, e2f);
+        BA_HIP_CHECK(hipMalloc((void**)&g.ftptr, (n + 1) * sizeof(int64_t)));
+        BA_HIP_CHECK(hipMemcpyAsync(g.ftptr, ftptr.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        g.fm = fm;
+        g.fE = fE;
+        g.max_m = max_m;
+        g.has_fsai = true;
+    }
     BA_HIP_CHECK(hipStreamSynchronize(st));
 }
 
 void free_graph(Graph& g) {
-    void* p[] = {g.eptr, g.esrc, g.edst, g.etwin, g.eblk, g.etr, g.diag_blk, g.xn, g.xe, g.A, g.Linv, g.flags};
+    void* p[] = {g.eptr, g.esrc, g.edst, g.etwin, g.eblk, g.etr, g.diag_blk, g.xn, g.xe, g.A, g.Linv, g.flags,
+                 g.fptr, g.fJ, g.fedge, g.fslot, g.ftile, g.ftptr, g.fsrc, g.fdst, g.fe, g.fd_ptr, g.fd_list, g.e2f};
     for (void* q : p)
         if (q) (void)hipFree(q);
     g = Graph();
@@ -660,9 +941,47 @@ void infer_preconditioner(ba_gnn* net, Graph& g, const double* Minv, double* P, 
     BA_HIP_CHECK(hipGetLastError());
 }
 
+void infer_factor(ba_gnn* net, Graph& g, const int32_t* gu_pos, float* Gl, float* Gu, float* Gslots, hipStream_t st) {
+    ensure_work(net->work, g.n, g.E, 1);
+    ensure_fwork(net->work, g);
+    forward(net, g, st);
+    head_forward(net, g, st);
+    if (g.fm > 0)
+        k_fassemble<<<g.fm, 128, 0, st>>>(g.n, g.fm, g.fptr, g.fJ, g.fedge, g.fslot, net->work.O, net->work.OE,
+                                          net->w + OFF_AO, g.A, g.Linv, gu_pos, Gl, Gu, Gslots);
+    BA_HIP_CHECK(hipGetLastError());
+}
+
+void fsai_sets(int n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* blk_pairs,
+               std::vector<int32_t>& ptr, std::vector<int32_t>& J, std::vector<int32_t>& slot) {
+    std::vector<std::vector<std::pair<int32_t, int64_t>>> low(n);
+    for (int32_t r = 0; r < n; ++r)
+        for (int64_t kb = row_ptr[r] + 1; kb < row_ptr[r + 1]; ++kb) low[col_idx[kb]].push_back({r, kb});
+    ptr.assign(n + 1, 0);
+    J.clear();
+    slot.clear();
+    for (int32_t i = 0; i < n; ++i) {
+        auto& L = low[i];
+        std::sort(L.begin(), L.end(), [&](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) {
+            const int32_t cx = blk_pairs[x.second], cy = blk_pairs[y.second];
+            return cx != cy ? cx > cy : x.first < y.first;
+        });
+        if ((int)L.size() > kFsaiM - 1) L.resize(kFsaiM - 1);
+        std::sort(L.begin(), L.end());
+        for (auto& e : L) {
+            J.push_back(e.first);
+            slot.push_back((int32_t)e.second);
+        }
+        J.push_back(i);
+        slot.push_back((int32_t)row_ptr[i]);
+        ptr[i + 1] = (int32_t)J.size();
+    }
+}
+
 void free_work(Work& W) {
     void* p[] = {W.H0, W.Hf, W.G, W.O, W.Z, W.Y, W.Hb, W.Gb, W.Xm, W.Xu, W.Mm, W.T, W.dO, W.dH, W.dT, W.dXu,
-                 W.dMm, W.dXm, W.dG, W.dOb, W.dTb, W.dMmb, W.dPb, W.dP, W.split, W.colpart, W.loss_part, W.loss};
+                 W.dMm, W.dXm, W.dG, W.dOb, W.dTb, W.dMmb, W.dPb, W.dP, W.split, W.colpart, W.loss_part, W.loss,
+                 W.Xf, W.dOEb, W.OE, W.dOE, W.dXf, W.aE, W.kpart};
     for (void* q : p)
         if (q) (void)hipFree(q);
     W = Work();
@@ -681,6 +1000,21 @@ void loss_grad(ba_gnn* net, Graph& g, int P, const float* probes_host, unsigned 
     forward(net, g, st);
     loss(net, g, P, st);
     if (grad) backward(net, g, grad, st);
+    BA_HIP_CHECK(hipGetLastError());
+}
+
+// one graph: forward with the factorised head, Kaporin loss, backward
+void fsai_loss_grad(ba_gnn* net, Graph& g, float* grad, hipStream_t st) {
+    ensure_work(net->work, g.n, g.E, 1);
+    ensure_fwork(net->work, g);
+    Work& W = net->work;
+    forward(net, g, st);
+    head_forward(net, g, st);
+    const double N = 9.0 * g.n;
+    k_kaporin<<<g.n, BS, 0, st>>>((float)(2.0 / N), g.fptr, g.fedge, g.ftptr, g.ftile, g.A, W.O, W.OE,
+                                  net->w + OFF_AO, W.dO, W.dOE, W.aE, W.kpart);
+    k_kaporin_total<<<1, BS, 0, st>>>(g.n, 1.0 / N, W.kpart, W.loss);
+    if (grad) backward(net, g, grad, st, true);
     BA_HIP_CHECK(hipGetLastError());
 }
 
@@ -788,7 +1122,7 @@ ba_status ba_gnn_get_params(ba_gnn* net, float* params) {
 }
 
 ba_status ba_gnn_graph_from_host(int32_t n_rows, const int64_t* row_ptr, const int32_t* col_idx, const double* blk,
-                                 ba_gnn_graph** out) {
+                                 const int32_t* blk_pairs, ba_gnn_graph** out) {
     if (!out || n_rows <= 0 || !row_ptr || !col_idx || !blk) return BA_ERR_INVALID_ARG;
     *out = nullptr;
     for (int32_t r = 0; r < n_rows; ++r)
@@ -805,7 +1139,7 @@ ba_status ba_gnn_graph_from_host(int32_t n_rows, const int64_t* row_ptr, const i
     ba_gnn_graph* G = new ba_gnn_graph();
     double* dblk = nullptr;
     ba_status s = gnn_guard(nullptr, [&]() {
-        ba::gnn::build_graph(G->g, n_rows, row_ptr, col_idx, nullptr);
+        ba::gnn::build_graph(G->g, n_rows, row_ptr, col_idx, blk_pairs, nullptr);
         BA_HIP_CHECK(hipMalloc((void**)&dblk, (size_t)n_blk * 81 * sizeof(double)));
         BA_HIP_CHECK(hipMemcpy(dblk, blk, (size_t)n_blk * 81 * sizeof(double), hipMemcpyHostToDevice));
         ba::gnn::compute_features(G->g, dblk, nullptr);
@@ -868,6 +1202,68 @@ ba_status ba_gnn_train_step(ba_gnn* net, ba_gnn_graph* const* graphs, int32_t n_
         ba::gnn::adam(net, net->gsum, lr, net->stream);
         BA_HIP_CHECK(hipStreamSynchronize(net->stream));
         if (loss_host) *loss_host = total / n_graphs;
+        return BA_OK;
+    });
+}
+
+ba_status ba_gnn_fsai_loss_grad(ba_gnn* net, ba_gnn_graph* G, double* loss_host, float* grad_host) {
+    if (!net || !G) return BA_ERR_INVALID_ARG;
+    if (!G->g.has_fsai) {
+        g_gnn_error = "graph built without common-point counts (no FSAI sets)";
+        return BA_ERR_STATE;
+    }
+    return gnn_guard(&net->err, [&]() {
+        ba::gnn::fsai_loss_grad(net, G->g, grad_host ? net->grad : nullptr, net->stream);
+        if (loss_host)
+            BA_HIP_CHECK(hipMemcpyAsync(loss_host, net->work.loss, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+        if (grad_host)
+            BA_HIP_CHECK(hipMemcpyAsync(grad_host, net->grad, ba::gnn::N_PARAMS * sizeof(float), hipMemcpyDeviceToHost,
+                                        net->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+        return BA_OK;
+    });
+}
+
+ba_status ba_gnn_fsai_train_step(ba_gnn* net, ba_gnn_graph* const* graphs, int32_t n_graphs, float lr,
+                                 double* loss_host) {
+    if (!net || !graphs || n_graphs <= 0 || !(lr > 0.f)) return BA_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < n_graphs; ++i)
+        if (!graphs[i] || !graphs[i]->g.has_fsai) {
+            g_gnn_error = "graph built without common-point counts (no FSAI sets)";
+            return BA_ERR_STATE;
+        }
+    return gnn_guard(&net->err, [&]() {
+        double total = 0.0;
+        for (int32_t i = 0; i < n_graphs; ++i) {
+            ba::gnn::fsai_loss_grad(net, graphs[i]->g, net->grad, net->stream);
+            ba::gnn::accumulate(net->grad, net->gsum, i == 0, 1.f / (float)n_graphs, net->stream);
+            double l = 0.0;
+            BA_HIP_CHECK(hipMemcpyAsync(&l, net->work.loss, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+            BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+            total += l;
+        }
+        ba::gnn::adam(net, net->gsum, lr, net->stream);
+        BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+        if (loss_host) *loss_host = total / n_graphs;
+        return BA_OK;
+    });
+}
+
+ba_status ba_gnn_fsai_factor(ba_gnn* net, ba_gnn_graph* G, float* G_host) {
+    if (!net || !G || !G_host) return BA_ERR_INVALID_ARG;
+    if (!G->g.has_fsai) {
+        g_gnn_error = "graph built without common-point counts (no FSAI sets)";
+        return BA_ERR_STATE;
+    }
+    return gnn_guard(&net->err, [&]() {
+        const size_t nb = (size_t)G->g.n_blk * 81;
+        float* dG = nullptr;
+        BA_HIP_CHECK(hipMalloc((void**)&dG, nb * sizeof(float)));
+        BA_HIP_CHECK(hipMemsetAsync(dG, 0, nb * sizeof(float), net->stream));
+        ba::gnn::infer_factor(net, G->g, nullptr, nullptr, nullptr, dG, net->stream);
+        BA_HIP_CHECK(hipMemcpyAsync(G_host, dG, nb * sizeof(float), hipMemcpyDeviceToHost, net->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(net->stream));
+        BA_HIP_CHECK(hipFree(dG));
         return BA_OK;
     });
 }

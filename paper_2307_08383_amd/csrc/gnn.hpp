@@ -16,7 +16,10 @@ constexpr int64_t LAYER = 3 * H * H + H + 2 * H * H + H;
 constexpr int64_t OFF_WN = 0, OFF_BN = OFF_WN + F_NODE * H, OFF_WE = OFF_BN + H, OFF_BE = OFF_WE + F_EDGE * H;
 constexpr int64_t OFF_L0 = OFF_BE + H;
 constexpr int64_t OFF_WD = OFF_L0 + N_LAYERS * LAYER, OFF_BD = OFF_WD + H * F_OUT;
-constexpr int64_t N_PARAMS = OFF_BD + F_OUT;
+// factorised head: off-diagonal blocks of G from [h_i, h_j, g_ij]
+constexpr int F_OFF = 96;              // head output (81 used)
+constexpr int64_t OFF_WO = OFF_BD + F_OUT, OFF_BO = OFF_WO + 3 * H * F_OFF, OFF_AO = OFF_BO + F_OFF;
+constexpr int64_t N_PARAMS = OFF_AO + F_OFF;
 inline int64_t off_M(int l) { return OFF_L0 + l * LAYER; }
 inline int64_t off_c(int l) { return off_M(l) + 3 * H * H; }
 inline int64_t off_U(int l) { return off_c(l) + H; }
@@ -33,6 +36,19 @@ struct Graph {
     double* Linv = nullptr;            // [n][81] L_i^-1 (lower)
     int* flags = nullptr;              // [0] a diagonal block was not SPD
     size_t bytes = 0;
+    // FSAI sets of the factorised head (same sets as the library's FSAI):
+    // per row its members J (ascending, the row last); per member the
+    // directed edge row -> member (-1 for the row) and the RCS block slot;
+    // per row the packed lower tiles (a, b), a >= b: directed edge
+    // J_a -> J_b, -2 on the diagonal, -1 if the cameras share no point;
+    // the FSAI edges (row, member) in row order and, for the backward
+    // scatter, the FSAI edges by member.
+    bool has_fsai = false;
+    int n_blk = 0, fm = 0, fE = 0, max_m = 0;
+    int32_t *fptr = nullptr, *fJ = nullptr, *fedge = nullptr, *fslot = nullptr, *ftile = nullptr;
+    int64_t* ftptr = nullptr;
+    int32_t *fsrc = nullptr, *fdst = nullptr, *fe = nullptr, *fd_ptr = nullptr, *fd_list = nullptr;
+    int32_t* e2f = nullptr;            // FSAI edge of each directed edge, or -1
 };
 
 // Activations and gradients of one forward/backward pass, grown on demand.
@@ -46,6 +62,11 @@ struct Work {
     __bf16 *dOb = nullptr, *dTb = nullptr, *dMmb = nullptr, *dPb = nullptr;
     float *dP = nullptr, *split = nullptr, *colpart = nullptr, *loss_part = nullptr;
     double* loss = nullptr;
+    // factorised head
+    int cap_f = 0, cap_fn = 0;
+    __bf16 *Xf = nullptr, *dOEb = nullptr;
+    float *OE = nullptr, *dOE = nullptr, *dXf = nullptr, *aE = nullptr;
+    double* kpart = nullptr;
 };
 
 }  // namespace gnn
@@ -66,8 +87,10 @@ struct ba_gnn_graph {
 
 namespace ba {
 namespace gnn {
-// graph structure from a host pattern (row_ptr int64 [n+1], col_idx [n_blk])
-void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx, hipStream_t st);
+// graph structure from a host pattern (row_ptr int64 [n+1], col_idx [n_blk]);
+// with blk_pairs (common points per block) also the FSAI sets
+void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* blk_pairs,
+                 hipStream_t st);
 void free_graph(Graph& g);
 // features of the RCS in blk (device, FP64 blocks indexed like the pattern)
 void compute_features(Graph& g, const double* blk, hipStream_t st);
@@ -75,6 +98,15 @@ void compute_features(Graph& g, const double* blk, hipStream_t st);
 // Minv_i + L_i^-T (Lt_i Lt_i^T - I) L_i^-1 when the block-Jacobi inverses
 // Minv are given
 void infer_preconditioner(ba_gnn* net, Graph& g, const double* Minv, double* P, hipStream_t st);
+// factorised head: G of the graph's FSAI sets into the layouts of the
+// library's FSAI (Gl by member, Gu at gu_pos, G at the block slots; any may
+// be null)
+void infer_factor(ba_gnn* net, Graph& g, const int32_t* gu_pos, float* Gl, float* Gu, float* Gslots, hipStream_t st);
+// the FSAI sets of a pattern (shared with the library's FSAI): per row, its
+// lower neighbours with the most common points (at most kFsaiM - 1, ties to
+// the lower index), ascending, then the row
+void fsai_sets(int n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* blk_pairs,
+               std::vector<int32_t>& ptr, std::vector<int32_t>& J, std::vector<int32_t>& slot);
 void free_work(Work& w);
 }  // namespace gnn
 }  // namespace ba

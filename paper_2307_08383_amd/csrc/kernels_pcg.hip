@@ -119,51 +119,48 @@ __device__ __forceinline__ double block_total(double wave_value, double* sh) {
     return t;
 }
 
-// Row gather by one wave: y[c] = sum over the row's entries e of
-// (B_e or B_e^T) v_e, returned in lanes 0..8 (component c = lane).
-// Entries are (block, vector row << 1 | transposed), padded with block -1;
-// v_e is v0[row] (VM == 0) or v0[row] - alpha v1[row] (VM == 1), vector
-// rows vs apart.  Lane
-// group g (lanes 9g..9g+8) takes entries g, g + 7, ...; two entries per
-// round, both requested before either is used.
+// Row gather by one wave over a block-CSR row (entries start..start+n-1,
+// blocks stored in the orientation they are applied in): y[c] =
+// sum_e B_e v_e, returned in lanes 0..8 (component c = lane).  v_e is
+// v0[col_e] (VM == 0) or v0[col_e] - alpha v1[col_e] (VM == 1), vector rows
+// vs apart.  Lane group g (lanes 9g..9g+8) takes entries g, g + 7, ...;
+// four entries per round: their block rows and columns are requested
+// together, then their vector rows.
 template <typename TB, int VM>
-__device__ __forceinline__ double row_gather(int row, int stride, const int2* __restrict__ ent,
+__device__ __forceinline__ double row_gather(int start, int n, const int32_t* __restrict__ col,
                                              const TB* __restrict__ blk, const double* __restrict__ v0,
                                              const double* __restrict__ v1, double alpha, int vs = 9) {
+    constexpr int U = 4;
     const int lane = threadIdx.x % kWave;
     const int grp = lane / 9, comp = lane % 9;
     double acc = 0.0;
     if (grp < GRPW) {
-        const int2* er = ent + (int64_t)row * stride;
-        for (int e = grp; e < stride; e += 2 * GRPW) {
-            const int2 na = er[e];
-            const int2 nb = (e + GRPW < stride) ? er[e + GRPW] : make_int2(-1, 0);
-            if (na.x < 0) break;   // padding: the rest of the row is empty
-            const bool hb = nb.x >= 0;
-            const TB* Sa = blk + (int64_t)na.x * 81;
-            const TB* Sb = blk + (int64_t)(hb ? nb.x : na.x) * 81;
-            const int64_t ia = (int64_t)(na.y >> 1) * vs;
-            const int64_t ib = (int64_t)((hb ? nb.y : na.y) >> 1) * vs;
-            const int sa_row = (na.y & 1) ? 1 : 9, sa_col = (na.y & 1) ? 9 : 1;
-            const int sb_row = (nb.y & 1) ? 1 : 9, sb_col = (nb.y & 1) ? 9 : 1;
-            double va[9], vb[9], ya[9], yb[9];
+        for (int e0 = grp; e0 < n; e0 += GRPW * U) {
+            int ci[U];
+            TB bv[U][9];
 #pragma unroll
-            for (int c = 0; c < 9; ++c) {
-                va[c] = (double)Sa[comp * sa_row + c * sa_col];
-                vb[c] = (double)Sb[comp * sb_row + c * sb_col];
-                if (VM == 0) {
-                    ya[c] = v0[ia + c];
-                    yb[c] = v0[ib + c];
-                } else {
-                    ya[c] = v0[ia + c] - alpha * v1[ia + c];
-                    yb[c] = v0[ib + c] - alpha * v1[ib + c];
-                }
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * GRPW;
+                const int ee = start + (e < n ? e : e0);
+                ci[u] = col[ee];
+                const TB* B = blk + (int64_t)ee * 81 + comp * 9;
+#pragma unroll
+                for (int c = 0; c < 9; ++c) bv[u][c] = B[c];
             }
 #pragma unroll
-            for (int c = 0; c < 9; ++c) acc += va[c] * ya[c];
-            if (hb) {
+            for (int u = 0; u < U; ++u) {
+                if (e0 + u * GRPW >= n) break;
+                const double* x0 = v0 + (int64_t)ci[u] * vs;
+                double y[9];
 #pragma unroll
-                for (int c = 0; c < 9; ++c) acc += vb[c] * yb[c];
+                for (int c = 0; c < 9; ++c) {
+                    if (VM == 0)
+                        y[c] = x0[c];
+                    else
+                        y[c] = x0[c] - alpha * v1[(int64_t)ci[u] * vs + c];
+                }
+#pragma unroll
+                for (int c = 0; c < 9; ++c) acc += (double)bv[u][c] * y[c];
             }
         }
     }
@@ -175,6 +172,19 @@ __device__ __forceinline__ double row_gather(int row, int stride, const int2* __
         tot += o;
     }
     return tot;
+}
+
+// Sf: both triangles of the RCS by rows (FP64), from the upper blocks
+__global__ __launch_bounds__(BS) void k_build_sf(int64_t n_sf, const int32_t* __restrict__ sf_src,
+                                                 const double* __restrict__ blk, double* __restrict__ Sf) {
+    const int64_t n = n_sf * 81;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        const int64_t e = i / 81;
+        const int pq = (int)(i % 81), p = pq / 9, q = pq % 9;
+        const int src = sf_src[e];
+        const double* B = blk + (int64_t)(src >> 1) * 81;
+        Sf[i] = (src & 1) ? B[q * 9 + p] : B[pq];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -227,13 +237,15 @@ __global__ void k_gauge_W(int n_cams, const int32_t* __restrict__ cam_row, const
 }
 
 // SW = S W, one wave per block row, the seven columns in turn
-__global__ __launch_bounds__(BS) void k_spmm_W(int n_rows, int ent_stride, const int2* __restrict__ ent,
-                                               const double* __restrict__ blk, const double* __restrict__ W,
-                                               double* __restrict__ SW) {
+__global__ __launch_bounds__(BS) void k_spmm_W(int n_rows, const int32_t* __restrict__ sf_ptr,
+                                               const int32_t* __restrict__ sf_col, const double* __restrict__ Sf,
+                                               const double* __restrict__ W, double* __restrict__ SW) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB)
         for (int v = 0; v < kW; ++v) {
-            const double y = row_gather<double, 0>(row, ent_stride, ent, blk, W + v * 9, nullptr, 0.0, kW * 9);
+            const int a = sf_ptr[row];
+            const double y = row_gather<double, 0>(a, sf_ptr[row + 1] - a, sf_col, Sf, W + v * 9, nullptr, 0.0,
+                                                   kW * 9);
             if (lane < 9) SW[(int64_t)row * kW * 9 + v * 9 + lane] = y;
         }
 }
@@ -416,31 +428,34 @@ __global__ __launch_bounds__(BS) void k_pcg_init(int n_rows, const double* __res
 }
 
 // plain y = S x
-__global__ __launch_bounds__(BS) void k_spmv(int n_rows, int ent_stride, const int2* __restrict__ ent,
-                                             const double* __restrict__ blk, const double* __restrict__ x,
-                                             double* __restrict__ y) {
+__global__ __launch_bounds__(BS) void k_spmv(int n_rows, const int32_t* __restrict__ sf_ptr,
+                                             const int32_t* __restrict__ sf_col, const double* __restrict__ Sf,
+                                             const double* __restrict__ x, double* __restrict__ y) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const double v = row_gather<double, 0>(row, ent_stride, ent, blk, x, nullptr, 0.0);
+        const int a = sf_ptr[row];
+        const double v = row_gather<double, 0>(a, sf_ptr[row + 1] - a, sf_col, Sf, x, nullptr, 0.0);
         if (lane < 9) y[(int64_t)row * 9 + lane] = v;
     }
 }
 
 // t = G r (initial step of the factorised preconditioner)
-__global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, int stride, const int2* __restrict__ ent,
-                                                     const float* __restrict__ G, const double* __restrict__ r,
-                                                     double* __restrict__ t) {
+__global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, const int32_t* __restrict__ gl_ptr,
+                                                     const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
+                                                     const double* __restrict__ r, double* __restrict__ t) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const double v = row_gather<float, 0>(row, stride, ent, G, r, nullptr, 0.0);
+        const int a = gl_ptr[row];
+        const double v = row_gather<float, 0>(a, gl_ptr[row + 1] - a, gl_col, Gl, r, nullptr, 0.0);
         if (lane < 9) t[(int64_t)row * 9 + lane] = v;
     }
 }
 
 // kernel A; FIRST: the iteration k = 0 (records |r0|^2).
 template <bool FIRST>
-__global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, int ent_stride, const int2* __restrict__ ent,
-                                              const double* __restrict__ blk, const double* __restrict__ z,
+__global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, const int32_t* __restrict__ sf_ptr,
+                                              const int32_t* __restrict__ sf_col, const double* __restrict__ Sf,
+                                              const double* __restrict__ z,
                                               double* __restrict__ d, double* __restrict__ q,
                                               double* __restrict__ pA, const double* __restrict__ pR, int n_part,
                                               int* __restrict__ state, double* __restrict__ scal, double tol,
@@ -496,7 +511,8 @@ __global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, int ent_stride, const 
                 }
             }
         }
-        const double sv = row_gather<double, 0>(row, ent_stride, ent, blk, z, nullptr, 0.0);
+        const int a0 = sf_ptr[row];
+        const double sv = row_gather<double, 0>(a0, sf_ptr[row + 1] - a0, sf_col, Sf, z, nullptr, 0.0);
         if (lane < 9) {
             const double qv = (FIRST ? sv : sv + beta * qo) - swm;
             const double dv = (FIRST ? zv : zv + beta * dold) - wm;
@@ -569,8 +585,9 @@ __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restri
 }
 
 // factorised preconditioner, first half: update and t = G r'
-__global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, int stride, const int2* __restrict__ ent,
-                                               const float* __restrict__ G, const double* __restrict__ d,
+__global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __restrict__ gl_ptr,
+                                               const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
+                                               const double* __restrict__ d,
                                                const double* __restrict__ q, double* __restrict__ x,
                                                double* __restrict__ r0buf, double* __restrict__ r1buf,
                                                double* __restrict__ t, const double* __restrict__ pA,
@@ -593,7 +610,8 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, int stride, const int
     const int lane = threadIdx.x % kWave;
     double rr = 0.0;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const double tv = row_gather<float, 1>(row, stride, ent, G, rin, q, alpha);
+        const int a0 = gl_ptr[row];
+        const double tv = row_gather<float, 1>(a0, gl_ptr[row + 1] - a0, gl_col, Gl, rin, q, alpha);
         if (lane < 9) {
             const int64_t o = (int64_t)row * 9 + lane;
             x[o] += alpha * d[o];
@@ -610,8 +628,9 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, int stride, const int
 // factorised preconditioner, second half: z = G^T t, r'^T z, (SW)^T z.
 // INIT: the initial z0 (r in buffer 0, parity 0, no counter update).
 template <bool INIT>
-__global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, int stride, const int2* __restrict__ ent,
-                                               const float* __restrict__ G, const double* __restrict__ t,
+__global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, const int32_t* __restrict__ gu_ptr,
+                                               const int32_t* __restrict__ gu_col, const float* __restrict__ Gu,
+                                               const double* __restrict__ t,
                                                const double* __restrict__ r0buf, const double* __restrict__ r1buf,
                                                double* __restrict__ z, double* __restrict__ pR, int n_part,
                                                int* __restrict__ state, int defl, const double* __restrict__ SW) {
@@ -627,7 +646,8 @@ __global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, int stride, const int
 #pragma unroll
     for (int j = 0; j < NP; ++j) acc[j] = 0.0;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const double zv = row_gather<float, 0>(row, stride, ent, G, t, nullptr, 0.0);
+        const int a0 = gu_ptr[row];
+        const double zv = row_gather<float, 0>(a0, gu_ptr[row + 1] - a0, gu_col, Gu, t, nullptr, 0.0);
         if (lane < 9) {
             const int64_t o = (int64_t)row * 9 + lane;
             z[o] = zv;
@@ -656,14 +676,14 @@ void enqueue_iterations(ba_ctx* c, int mode, const double* M, int defl, double t
     Pcg& P = c->pcg;
     const int nr = c->n_rows, g = grid_of(nr);
     for (int i = 0; i < count; ++i) {
-        k_pcg_A<false><<<g, BS, 0, st>>>(nr, c->ent_stride, (const int2*)c->sp_ent, c->blk, P.z, P.d, P.q, P.pA,
+        k_pcg_A<false><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.z, P.d, P.q, P.pA,
                                          P.pR, g, P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
         if (mode == 0) {
             k_pcg_B<<<g, BS, 0, st>>>(nr, M, P.d, P.q, P.x, P.r[0], P.z, P.pA, P.pR, g, P.state, defl, P.SW);
         } else {
-            k_pcg_Bf<<<g, BS, 0, st>>>(nr, c->fs.gl_stride, (const int2*)c->fs.gl_ent, c->fs.G, P.d, P.q, P.x,
+            k_pcg_Bf<<<g, BS, 0, st>>>(nr, c->fs.ptr, c->fs.J, c->fs.Gl, P.d, P.q, P.x,
                                        P.r[0], P.r[1], P.t, P.pA, P.pR, g, P.state);
-            k_pcg_Cf<false><<<g, BS, 0, st>>>(nr, c->fs.gu_stride, (const int2*)c->fs.gu_ent, c->fs.G, P.t, P.r[0],
+            k_pcg_Cf<false><<<g, BS, 0, st>>>(nr, c->fs.gu_ptr, c->fs.gu_col, c->fs.Gu, P.t, P.r[0],
                                               P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
         }
     }
@@ -671,13 +691,23 @@ void enqueue_iterations(ba_ctx* c, int mode, const double* M, int defl, double t
 
 }  // namespace
 
+// the row-major copy of both triangles of the current RCS
+void ensure_sf(ba_ctx* c) {
+    if (c->sf_ready || c->n_sf == 0) return;
+    const int64_t n = c->n_sf * 81;
+    const unsigned g = (unsigned)std::min<int64_t>((n + BS - 1) / BS, 8192);
+    k_build_sf<<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf);
+    c->sf_ready = true;
+}
+
 // Gauge vectors of the last linearization, S W and E^-1 of the current RCS
 void prepare_deflation(ba_ctx* c) {
     Pcg& P = c->pcg;
     const int nr = c->n_rows, g = grid_of(nr);
     hipStream_t st = c->stream;
     k_gauge_W<<<(c->n_cams + 255) / 256, 256, 0, st>>>(c->n_cams, c->cam_row, c->lin_cams, P.W);
-    k_spmm_W<<<g, BS, 0, st>>>(nr, c->ent_stride, (const int2*)c->sp_ent, c->blk, P.W, P.SW);
+    ensure_sf(c);
+    k_spmm_W<<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.W, P.SW);
     k_defl_E_part<<<g, BS, 0, st>>>(nr, P.W, P.SW, P.pE);
     k_defl_E_fin<<<1, 64, 0, st>>>(g, P.pE, P.Einv, c->flags);
 }
@@ -687,28 +717,29 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
     Pcg& P = c->pcg;
     const int nr = c->n_rows, g = grid_of(nr);
     hipStream_t st = c->stream;
+    ensure_sf(c);
     const double* q0 = nullptr;
     if (x0) {
-        k_spmv<<<g, BS, 0, st>>>(nr, c->ent_stride, (const int2*)c->sp_ent, c->blk, x0, P.q);
+        k_spmv<<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, x0, P.q);
         q0 = P.q;
     }
     if (defl) k_defl_Wr<<<g, BS, 0, st>>>(nr, c->rhs, q0, P.W, P.pW);
     k_pcg_init<<<g, BS, 0, st>>>(nr, c->rhs, q0, x0, mode == 0 ? M : nullptr, P.x, P.r[0], P.z, P.pR, P.state, P.scal,
                                  defl, P.W, P.SW, P.Einv, P.pW, g);
     if (mode != 0) {
-        k_gather_lower<<<g, BS, 0, st>>>(nr, c->fs.gl_stride, (const int2*)c->fs.gl_ent, c->fs.G, P.r[0], P.t);
-        k_pcg_Cf<true><<<g, BS, 0, st>>>(nr, c->fs.gu_stride, (const int2*)c->fs.gu_ent, c->fs.G, P.t, P.r[0], P.r[1],
+        k_gather_lower<<<g, BS, 0, st>>>(nr, c->fs.ptr, c->fs.J, c->fs.Gl, P.r[0], P.t);
+        k_pcg_Cf<true><<<g, BS, 0, st>>>(nr, c->fs.gu_ptr, c->fs.gu_col, c->fs.Gu, P.t, P.r[0], P.r[1],
                                          P.z, P.pR, g, P.state, defl, P.SW);
     }
-    k_pcg_A<true><<<g, BS, 0, st>>>(nr, c->ent_stride, (const int2*)c->sp_ent, c->blk, P.z, P.d, P.q, P.pA, P.pR, g,
+    k_pcg_A<true><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.z, P.d, P.q, P.pA, P.pR, g,
                                     P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
     if (max_iter > 0) {
         if (mode == 0) {
             k_pcg_B<<<g, BS, 0, st>>>(nr, M, P.d, P.q, P.x, P.r[0], P.z, P.pA, P.pR, g, P.state, defl, P.SW);
         } else {
-            k_pcg_Bf<<<g, BS, 0, st>>>(nr, c->fs.gl_stride, (const int2*)c->fs.gl_ent, c->fs.G, P.d, P.q, P.x,
+            k_pcg_Bf<<<g, BS, 0, st>>>(nr, c->fs.ptr, c->fs.J, c->fs.Gl, P.d, P.q, P.x,
                                        P.r[0], P.r[1], P.t, P.pA, P.pR, g, P.state);
-            k_pcg_Cf<false><<<g, BS, 0, st>>>(nr, c->fs.gu_stride, (const int2*)c->fs.gu_ent, c->fs.G, P.t, P.r[0],
+            k_pcg_Cf<false><<<g, BS, 0, st>>>(nr, c->fs.gu_ptr, c->fs.gu_col, c->fs.Gu, P.t, P.r[0],
                                               P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
         }
     }
@@ -768,7 +799,8 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
 
 void launch_spmv(ba_ctx* c, const double* x, double* y) {
     if (c->n_rows == 0) return;
-    k_spmv<<<grid_of(c->n_rows), BS, 0, c->stream>>>(c->n_rows, c->ent_stride, (const int2*)c->sp_ent, c->blk, x, y);
+    ensure_sf(c);
+    k_spmv<<<grid_of(c->n_rows), BS, 0, c->stream>>>(c->n_rows, c->sf_ptr, c->sf_col, c->Sf, x, y);
 }
 
 }  // namespace ba

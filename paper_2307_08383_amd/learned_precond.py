@@ -42,9 +42,11 @@ def init_params(seed=0):
     for _ in range(3):
         shapes += [(192, 64), (64,), (128, 64), (64,)]
     shapes += [(64, 48), (48,)]
+    n_trunk = len(shapes)
+    shapes += [(192, 96), (96,), (96,)]       # factorised head (zero: block-Jacobi)
     parts = []
     for i, sh in enumerate(shapes):
-        if len(sh) == 2 and i < len(shapes) - 2:
+        if len(sh) == 2 and i < n_trunk - 2:
             scale = 0.5 if sh[0] == 128 else 1.0
             parts.append(rng.normal(0.0, scale / np.sqrt(sh[0]), size=sh).ravel())
         else:
@@ -137,7 +139,14 @@ def evaluate(net, seeds, grid=TRAIN_GRID, lm_iters=8, tol=1e-6, max_iter=1000, l
 
 
 def load_weights(path=DEFAULT_WEIGHTS):
-    return np.load(path, allow_pickle=False).astype(np.float32)
+    """Parameters from a .npy file; a file without the factorised head
+    (older, shorter parameter vector) gets a zero head."""
+    from . import ba
+    w = np.load(path, allow_pickle=False).astype(np.float32)
+    n = ba.ba_gnn_param_count()
+    if w.size < n:
+        w = np.concatenate([w, np.zeros(n - w.size, np.float32)])
+    return w
 
 
 def _range(spec):

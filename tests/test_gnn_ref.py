@@ -141,3 +141,96 @@ def test_bf16_rounding():
     r = G.bf16_round(x)
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2 ** -7 and r[4] == 0.0
     assert abs(r[3] + 3.14159) < 2 ** -7 * 4
+
+
+# ---------------------------------------------------------------------------
+# factorised head
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def grid_feat():
+    from oracle import fsai
+    s = scenegen.aerial_grid_scene(seed=9, nx=5, ny=4, n_pts=1500, with_stats=False)
+    uv = orc.observations(s)
+    P = orc.Problem.from_scene(s, uv)
+    P.linearize(s.cams_init, s.pts_init)
+    P.form_rcs(1e-3)
+    rp, ci = P.pattern()
+    blk, _ = P.rcs()
+    cnt = fsai.shared_points(P.n_rows, P.cam_row(), s.obs_cam, s.obs_pt)
+    J = fsai.lower_sets(rp, ci, cnt, 3)
+    return G.features(rp, ci, blk), J, (rp, ci, blk, cnt)
+
+
+def test_zero_head_is_block_jacobi(grid_feat):
+    f, J, (rp, ci, blk, cnt) = grid_feat
+    w = G.init_params(0, zero_decoder=True)
+    rows, _ = G.fsai_factor(w, f, J)
+    for Gi in rows:
+        np.testing.assert_array_equal(Gi[:-1], 0.0)
+        np.testing.assert_array_equal(Gi[-1], np.eye(9))
+    loss, _ = G.kaporin_loss(rows, f, J)
+    assert abs(loss - 1.0) <= 1e-12          # tr(I) per row, log det 0
+    Gorig = G.fsai_preconditioner_factor(rows, J, f["L"])
+    for i, Gi in enumerate(Gorig):
+        np.testing.assert_allclose(Gi[-1], np.linalg.inv(f["L"][i]), rtol=1e-12, atol=1e-15)
+
+
+def test_kaporin_stationary_at_exact_fsai(grid_feat):
+    # the oracle's FSAI factor (pinned separately), mapped to normalised
+    # coordinates, is a stationary point of the reference's Kaporin loss
+    from oracle import fsai
+    f, J, (rp, ci, blk, cnt) = grid_feat
+    Gd, _, Jo = fsai.fsai(blk, rp, ci, cnt, cap=3)
+    assert Jo == J
+    rows = []
+    for i, Ji in enumerate(J):
+        rows.append(np.stack([Gd[9 * i:9 * i + 9, 9 * j:9 * j + 9] @ f["L"][j] for j in Ji]))
+    loss, grads = G.kaporin_loss(rows, f, J)
+    for Gi, dGi in zip(rows, grads):
+        # lower-triangular part of the diagonal block and the off-diagonal blocks
+        mask = np.ones_like(dGi)
+        mask[-1] = np.tril(np.ones((9, 9)))
+        assert np.abs(dGi * mask).max() <= 1e-9 * max(1.0, np.abs(Gi).max())
+    assert loss < 1.0
+    # and below any perturbation of it
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        pert = [Gi + 1e-3 * rng.normal(size=Gi.shape) * np.concatenate(
+            [np.ones((len(Gi) - 1, 9, 9)), np.tril(np.ones((1, 9, 9)))]) for Gi in rows]
+        assert G.kaporin_loss(pert, f, J)[0] > loss
+
+
+def test_fsai_head_gradient_finite_differences(grid_feat):
+    f, J, _ = grid_feat
+    w = G.init_params(2, zero_decoder=False, decoder_scale=0.2)
+    d = G.unflatten(w.copy())
+    d["ao"][:] = 0.3
+    d["bo"][:] = np.random.default_rng(3).normal(0, 0.02, size=d["bo"].shape)
+    w = G.flatten(d)
+    loss, grad = G.fsai_loss_and_grad(w, f, J)
+    rng = np.random.default_rng(4)
+    names = {name: (o, int(np.prod(shape))) for name, shape, o in
+             [(n_, s_, o_) for (n_, s_), o_ in zip(G.PARAM_SHAPES, np.cumsum([0] + [int(np.prod(s)) for _, s in G.PARAM_SHAPES])[:-1])]}
+    for name in ["Wo", "bo", "ao", "Wd", "bd", "M2", "U0", "We", "Wn"]:
+        off, size = names[name]
+        for k in rng.choice(size, size=3, replace=False):
+            idx = off + int(k)
+            h = 1e-6 * max(1.0, abs(w[idx]))
+            wp, wm = w.copy(), w.copy()
+            wp[idx] += h
+            wm[idx] -= h
+            lp = G.kaporin_loss(G.fsai_factor(wp, f, J)[0], f, J)[0]
+            lm = G.kaporin_loss(G.fsai_factor(wm, f, J)[0], f, J)[0]
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - grad[idx]) <= 1e-6 * np.abs(grad).max() + 1e-5 * abs(fd), (name, k, fd, grad[idx])
+
+
+def test_first_order_skip_improves_on_block_jacobi(grid_feat):
+    # ao = 1 gives Ghat_ij = -A_ij, the first-order approximation of the
+    # inverse factor: lower Kaporin functional than block-Jacobi
+    f, J, _ = grid_feat
+    d = G.unflatten(G.init_params(0, zero_decoder=True))
+    d["ao"][:81] = 1.0
+    rows, _ = G.fsai_factor(G.flatten(d), f, J)
+    assert G.kaporin_loss(rows, f, J)[0] < 1.0

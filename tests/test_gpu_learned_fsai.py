@@ -1,0 +1,173 @@
+"""Factorised (FSAI-pattern) head of the learned preconditioner on the GPU
+against the CPU FP64 reference (needs a GPU): Kaporin loss and gradients,
+the factor itself, the zero-head special case, the PCG path and training."""
+import numpy as np
+import pytest
+
+from oracle import fsai
+from oracle import gnn_ref as G
+from oracle import oracle as orc
+from paper_2307_08383_amd import scenegen
+
+from gpu_util import T, create
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ba = pytest.importorskip("paper_2307_08383_amd.ba")
+
+CAP = 27
+
+
+def _case(scene, lam=1e-3):
+    uv = orc.observations(scene)
+    P = orc.Problem.from_scene(scene, uv)
+    P.linearize(scene.cams_init, scene.pts_init)
+    P.form_rcs(lam)
+    rp, ci = P.pattern()
+    blk, _ = P.rcs()
+    cnt = fsai.shared_points(P.n_rows, P.cam_row(), scene.obs_cam, scene.obs_pt)
+    pairs = np.zeros(len(ci), np.int32)
+    for r in range(P.n_rows):
+        for k in range(rp[r] + 1, rp[r + 1]):
+            pairs[k] = cnt[(r, int(ci[k]))]
+    J = fsai.lower_sets(rp, ci, cnt, CAP)
+    return P, uv, rp, ci, blk, pairs, J
+
+
+@pytest.fixture(scope="module")
+def grid_case():
+    s = scenegen.aerial_grid_scene(seed=9, nx=6, ny=5, n_pts=3000, with_stats=False)
+    P, uv, rp, ci, blk, pairs, J = _case(s)
+    return s, P, uv, rp, ci, blk, pairs, J, G.features(rp, ci, blk)
+
+
+def _random_head(seed):
+    d = G.unflatten(G.init_params(seed, zero_decoder=False, decoder_scale=0.2))
+    rng = np.random.default_rng(seed + 100)
+    d["ao"][:81] = rng.uniform(0.2, 0.8, size=81)
+    d["bo"][:] = rng.normal(0, 0.02, size=d["bo"].shape)
+    return G.flatten(d)
+
+
+def test_kaporin_gradients_match_cpu_reference(grid_case):
+    s, P, uv, rp, ci, blk, pairs, J, feat = grid_case
+    w = _random_head(5)
+    net = ba.ba_gnn_create(w.astype(np.float32))
+    g = ba.ba_gnn_graph_from_host(rp, ci, blk, pairs)
+    try:
+        loss, grad = ba.ba_gnn_fsai_loss_grad(net, g)
+    finally:
+        ba.ba_gnn_graph_destroy(g)
+        ba.ba_gnn_destroy(net)
+    w32 = w.astype(np.float32).astype(np.float64)
+    loss_ref, grad_ref = G.fsai_loss_and_grad(w32, feat, J, bf16=True)
+    assert abs(loss - loss_ref) <= 1e-2 * abs(loss_ref)
+    offs = np.cumsum([0] + [int(np.prod(sh)) for _, sh in G.PARAM_SHAPES])
+    for t, (name, _) in enumerate(G.PARAM_SHAPES):
+        a, b = grad[offs[t]:offs[t + 1]], grad_ref[offs[t]:offs[t + 1]]
+        nb = np.linalg.norm(b)
+        if nb == 0:
+            assert np.linalg.norm(a) == 0, name
+            continue
+        assert np.linalg.norm(a - b) <= 1e-2 * nb, (name, np.linalg.norm(a - b) / nb)
+
+
+def test_factor_matches_cpu_reference(grid_case):
+    s, P, uv, rp, ci, blk, pairs, J, feat = grid_case
+    w = _random_head(6)
+    net = ba.ba_gnn_create(w.astype(np.float32))
+    g = ba.ba_gnn_graph_from_host(rp, ci, blk, pairs)
+    try:
+        Gs = ba.ba_gnn_fsai_factor(net, g, len(ci)).astype(np.float64)
+    finally:
+        ba.ba_gnn_graph_destroy(g)
+        ba.ba_gnn_destroy(net)
+    rows, _ = G.fsai_factor(w.astype(np.float32).astype(np.float64), feat, J, bf16=True)
+    Gref = G.fsai_preconditioner_factor(rows, J, feat["L"])
+    n = len(rp) - 1
+    Gd = np.zeros((9 * n, 9 * n))
+    for i, (Gi, Ji) in enumerate(zip(Gref, J)):
+        for b, j in enumerate(Ji):
+            Gd[9 * i:9 * i + 9, 9 * j:9 * j + 9] = Gi[b]
+    ref_slots = fsai.slots_from_dense(Gd, rp, ci)
+    for k in range(len(ci)):
+        nr_ = np.linalg.norm(ref_slots[k])
+        if nr_ == 0:
+            assert not Gs[k].any()
+        else:
+            assert np.linalg.norm(Gs[k] - ref_slots[k]) <= 2e-2 * nr_, k
+
+
+def test_zero_head_is_block_jacobi_and_pcg_path(grid_case):
+    s, P, uv, rp, ci, blk, pairs, J, feat = grid_case
+    net = ba.ba_gnn_create(G.init_params(3, zero_decoder=True).astype(np.float32))
+    ctx = create(s, uv, 0)
+    try:
+        g = ba.ba_gnn_graph_from_host(rp, ci, blk, pairs)
+        Gs = ba.ba_gnn_fsai_factor(net, g, len(ci)).astype(np.float64)
+        ba.ba_gnn_graph_destroy(g)
+        for r in range(len(rp) - 1):
+            Linv = np.linalg.inv(np.linalg.cholesky(blk[rp[r]]))
+            assert np.abs(Gs[rp[r]] - Linv).max() <= 1e-6 * np.abs(Linv).max()
+        off = np.ones(len(ci), bool)
+        off[rp[:-1]] = False
+        assert not Gs[off].any()
+        # through the library: LEARNED_FSAI with a zero head solves like block-Jacobi
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-3)
+        ba.ba_set_preconditioner_net(ctx, net)
+        dxc = torch.empty((P.n_rows, 9), dtype=torch.float64, device="cuda")
+        a = ba.ba_pcg_solve(ctx, dxc, tol=1e-8)
+        xa = dxc.cpu().numpy().copy()
+        b = ba.ba_pcg_solve(ctx, dxc, tol=1e-8, precond=ba.BA_PRECOND_LEARNED_FSAI)
+        assert abs(a["iters"] - b["iters"]) <= 2
+        assert np.linalg.norm(dxc.cpu().numpy() - xa) <= 1e-6 * np.linalg.norm(xa)
+        c = ba.ba_pcg_solve(ctx, dxc, tol=1e-12, max_iter=5000, precond=ba.BA_PRECOND_LEARNED_FSAI, deflate=True)
+        x_ref, _ = P.pcg(tol=1e-12, max_iter=5000)
+        assert c["status"] == 0
+        assert np.linalg.norm(dxc.cpu().numpy() - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
+    finally:
+        ba.ba_set_preconditioner_net(ctx, None)
+        ba.ba_destroy(ctx)
+        ba.ba_gnn_destroy(net)
+
+
+def test_training_lowers_kaporin_and_iterations():
+    # train on RCS instances of one scene, evaluate on another
+    from paper_2307_08383_amd import learned_precond as lp
+    tr = [scenegen.aerial_grid_scene(seed=s, nx=8, ny=6, n_pts=6000, with_stats=False) for s in (21, 22)]
+    te = scenegen.aerial_grid_scene(seed=23, nx=8, ny=6, n_pts=6000, with_stats=False)
+    net = ba.ba_gnn_create(lp.init_params(0))
+    graphs, ctxs = [], []
+    try:
+        for s in tr:
+            uv = orc.observations(s)
+            ctx = create(s, uv, 0)
+            ctxs.append(ctx)
+            cams, pts = T(s.cams_init, torch.float64), T(s.pts_init, torch.float64)
+            st = ba.new_lm_state(1e-4)
+            for _ in range(3):
+                ba.ba_lm_step(ctx, cams, pts, st)
+                graphs.append(ba.ba_gnn_graph_from_ctx(ctx))
+        first = ba.ba_gnn_fsai_train_step(net, graphs, lr=3e-3)
+        for _ in range(60):
+            last = ba.ba_gnn_fsai_train_step(net, graphs, lr=3e-3)
+        assert last < first < 1.0 + 1e-6
+        uv = orc.observations(te)
+        ctx = create(te, uv, 0)
+        ctxs.append(ctx)
+        ba.ba_linearize(ctx, T(te.cams_init, torch.float64), T(te.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-5)
+        ba.ba_set_preconditioner_net(ctx, net)
+        dxc = torch.empty((ba.ba_get_sizes(ctx)["n_rows"], 9), dtype=torch.float64, device="cuda")
+        bj = ba.ba_pcg_solve(ctx, dxc, tol=1e-6)
+        le = ba.ba_pcg_solve(ctx, dxc, tol=1e-6, precond=ba.BA_PRECOND_LEARNED_FSAI)
+        assert le["status"] == 0 and le["iters"] < bj["iters"]
+        ba.ba_set_preconditioner_net(ctx, None)
+    finally:
+        for g in graphs:
+            ba.ba_gnn_graph_destroy(g)
+        for c in ctxs:
+            ba.ba_destroy(c)
+        ba.ba_gnn_destroy(net)
