@@ -42,8 +42,12 @@ def parse():
     ap.add_argument("--cpu-sample-formations", type=int, default=2)
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the learned + mixed vs FP64 block-Jacobi LM comparison")
-    ap.add_argument("--lm-iters", type=int, default=20, help="LM iterations of each compared run")
-    ap.add_argument("--precond", default="block_jacobi", choices=["block_jacobi", "fsai", "learned"],
+    ap.add_argument("--lm-iters", type=int, default=None,
+                    help="LM iterations of each compared run (default: the workload's budget)")
+    ap.add_argument("--compare", default="all",
+                    help="comma-separated subset of the compared runs, or 'all'")
+    ap.add_argument("--precond", default="block_jacobi",
+                    choices=["block_jacobi", "fsai", "learned", "learned_fsai"],
                     help="preconditioner of the timed LM steps")
     ap.add_argument("--deflate", action="store_true", help="gauge-deflated PCG in the timed LM steps")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -97,7 +101,7 @@ def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=
     obs_cam, obs_pt, uv, cf = obs
     ctx = ba.ba_create(scene.n_cams, scene.n_pts, obs_cam, obs_pt, uv, cf, precision=precision)
     net = None
-    if precond == ba.BA_PRECOND_LEARNED:
+    if precond in (ba.BA_PRECOND_LEARNED, ba.BA_PRECOND_LEARNED_FSAI):
         net = ba.ba_gnn_create(learned_weights)
         ba.ba_set_preconditioner_net(ctx, net)
     dev = uv.device
@@ -174,11 +178,12 @@ def main():
         torch.cuda.synchronize()
         del src_buf, dst_buf
     pre = {"block_jacobi": ba.BA_PRECOND_BLOCK_JACOBI, "fsai": ba.BA_PRECOND_FSAI,
-           "learned": ba.BA_PRECOND_LEARNED}[args.precond]
+           "learned": ba.BA_PRECOND_LEARNED, "learned_fsai": ba.BA_PRECOND_LEARNED_FSAI}[args.precond]
     net = None
-    if pre == ba.BA_PRECOND_LEARNED:
+    if pre in (ba.BA_PRECOND_LEARNED, ba.BA_PRECOND_LEARNED_FSAI):
         from paper_2307_08383_amd import learned_precond
-        net = ba.ba_gnn_create(learned_precond.load_weights())
+        net = ba.ba_gnn_create(learned_precond.load_weights(
+            learned_precond.DEFAULT_FSAI_WEIGHTS if pre == ba.BA_PRECOND_LEARNED_FSAI else learned_precond.DEFAULT_WEIGHTS))
         ba.ba_set_preconditioner_net(ctx, net)
     step_kw = dict(pcg_tol=scene.pcg_tol, precond=pre, deflate=args.deflate)
     for _ in range(args.warmup):
@@ -234,24 +239,35 @@ def main():
         ba.ba_gnn_destroy(net)
     ba.ba_destroy(ctx)
     if not args.no_compare:
-        from paper_2307_08383_amd import learned_precond
-        wpath = learned_precond.DEFAULT_WEIGHTS
-        weights = learned_precond.load_weights(wpath) if os.path.exists(wpath) else learned_precond.init_params(0)
+        from paper_2307_08383_amd import learned_precond as lp
+
+        def weights(path):
+            return (lp.load_weights(path), os.path.basename(path)) if os.path.exists(path) else \
+                (lp.init_params(0), "untrained (zero head: block-Jacobi)")
+        wb, wb_name = weights(lp.DEFAULT_WEIGHTS)
+        wf, wf_name = weights(lp.DEFAULT_FSAI_WEIGHTS)
         obs = (obs_cam, obs_pt, uv, cf)
         runs = {}
-        for name, prec, pre, defl in [
-                ("fp64_block_jacobi", ba.BA_FP64, ba.BA_PRECOND_BLOCK_JACOBI, False),
-                ("mixed_block_jacobi_deflated", ba.BA_MIXED, ba.BA_PRECOND_BLOCK_JACOBI, True),
-                ("mixed_fsai", ba.BA_MIXED, ba.BA_PRECOND_FSAI, False),
-                ("mixed_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_FSAI, True),
-                ("mixed_learned_block_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED, True)]:
-            runs[name] = lm_run(scene, obs, prec, pre, args.lm_iters, weights, deflate=defl)
+        lm_iters = args.lm_iters or scene.lm_iterations
+        variants = [
+                ("fp64_block_jacobi", ba.BA_FP64, ba.BA_PRECOND_BLOCK_JACOBI, False, None),
+                ("mixed_block_jacobi_deflated", ba.BA_MIXED, ba.BA_PRECOND_BLOCK_JACOBI, True, None),
+                ("mixed_fsai", ba.BA_MIXED, ba.BA_PRECOND_FSAI, False, None),
+                ("mixed_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_FSAI, True, None),
+                ("mixed_learned_block_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED, True, wb),
+                ("mixed_learned_fsai", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, False, wf),
+                ("mixed_learned_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, True, wf)]
+        keep = None if args.compare == "all" else set(args.compare.split(","))
+        for name, prec, pre, defl, w in variants:
+            if keep is not None and name not in keep and name != "fp64_block_jacobi":
+                continue
+            runs[name] = lm_run(scene, obs, prec, pre, lm_iters, w, deflate=defl)
             progress(f"LM comparison {name}: {runs[name]['ms_per_iter']:.2f} ms per iteration")
         base = runs["fp64_block_jacobi"]
         out["lm_comparison"] = {
-            "iterations": args.lm_iters,
+            "iterations": lm_iters,
             **runs,
-            "learned_weights": os.path.basename(wpath) if os.path.exists(wpath) else "untrained (zero decoder)",
+            "learned_weights": {"block": wb_name, "fsai": wf_name},
             "speedup_vs_fp64_block_jacobi": {k: base["ms_per_iter"] / v["ms_per_iter"] for k, v in runs.items()},
             "final_cost_rel_diff_vs_fp64_block_jacobi": {
                 k: abs(v["final_cost"] - base["final_cost"]) / base["final_cost"] for k, v in runs.items()},

@@ -38,10 +38,13 @@ PARAM_SHAPES = [("Wn", (F_NODE, H)), ("bn", (H,)), ("We", (F_EDGE, H)), ("be", (
 for _l in range(N_LAYERS):
     PARAM_SHAPES += [(f"M{_l}", (3 * H, H)), (f"c{_l}", (H,)), (f"U{_l}", (2 * H, H)), (f"u{_l}", (H,))]
 PARAM_SHAPES += [("Wd", (H, F_OUT)), ("bd", (F_OUT,))]
-# factorised head: off-diagonal blocks of G from [h_i, h_j, g_ij] (96 outputs,
-# 81 used) plus a learned elementwise multiple of the normalised block
+# factorised head: off-diagonal blocks of G from [h_i, h_j, g_ij] through one
+# hidden ReLU layer (96 outputs, 81 used) plus a learned elementwise multiple
+# of the normalised block
 F_OFF = 96
-PARAM_SHAPES += [("Wo", (3 * H, F_OFF)), ("bo", (F_OFF,)), ("ao", (F_OFF,))]
+HO = 128
+PARAM_SHAPES += [("Wo1", (3 * H, HO)), ("bo1", (HO,)), ("Wo2", (HO, F_OFF)), ("bo2", (F_OFF,)),
+                 ("ao", (F_OFF,))]
 N_PARAMS = int(sum(np.prod(s) for _, s in PARAM_SHAPES))
 
 # strict lower triangle positions (row-major) used by the decoder
@@ -76,10 +79,10 @@ def init_params(seed=0, zero_decoder=True, decoder_scale=0.05):
     if zero_decoder:
         d["Wd"][:] = 0.0
         d["bd"][:] = 0.0
-        d["Wo"][:] = 0.0
+        d["Wo2"][:] = 0.0
     else:
         d["Wd"] *= decoder_scale
-        d["Wo"] *= decoder_scale
+        d["Wo2"] *= decoder_scale
     return flatten(d)
 
 
@@ -256,7 +259,7 @@ def backward(w, feat, cache, do, bf16=False, extra=None):
     if extra is not None:
         dh = dh + extra["dh"]
         dg = dg + extra["dg"]
-        for name in ("Wo", "bo", "ao"):
+        for name in ("Wo1", "bo1", "Wo2", "bo2", "ao"):
             grads[name] = extra[name]
     for l in reversed(range(N_LAYERS)):
         t = cache[f"t{l}"]
@@ -311,7 +314,8 @@ def preconditioner(o, L):
 # its kept lower neighbours, ascending, i last).  In block-Jacobi-normalised
 # coordinates Ghat = G blockdiag(L): Ghat_ii = Lt_i from the node decoder
 # (lower triangular, diagonal exp(.)), and for j in J_i, j < i,
-#     Ghat_ij = reshape(Wo^T [h_i, h_j, g_ij] + bo)[:81] - ao[:81] * A_ij
+#     Ghat_ij = reshape(Wo2^T relu(Wo1^T [h_i, h_j, g_ij] + bo1) + bo2)[:81]
+#               - ao[:81] * A_ij
 # (A_ij the normalised block of the directed edge i -> j).  A zero head and
 # decoder give Ghat = I, G = blockdiag(L^-1): block-Jacobi.  Training
 # minimises the Kaporin functional in the normalised space,
@@ -342,7 +346,8 @@ def fsai_factor(w, feat, J, bf16=False):
     X = np.zeros((len(fe), 3 * H))
     for f, (i, j, e) in enumerate(fe):
         X[f] = np.concatenate([hL[i], hL[j], gb[e]])
-    oe = X @ P["Wo"] + P["bo"] if len(fe) else np.zeros((0, F_OFF))
+    z1 = _relu(X @ P["Wo1"] + P["bo1"]) if len(fe) else np.zeros((0, HO))
+    oe = rd(z1) @ P["Wo2"] + P["bo2"] if len(fe) else np.zeros((0, F_OFF))
     Lt = factor_from_output(o)
     rows, f = [], 0
     for i, Ji in enumerate(J):
@@ -353,7 +358,7 @@ def fsai_factor(w, feat, J, bf16=False):
             f += 1
         blocks.append(Lt[i])
         rows.append(np.stack(blocks))
-    cache.update(o=o, oe=oe, X=X, fe=fe, Aq=A)
+    cache.update(o=o, oe=oe, X=X, z1=z1, fe=fe, Aq=A)
     return rows, cache
 
 
@@ -417,9 +422,11 @@ def fsai_loss_and_grad(w, feat, J, bf16=False):
             dao[:81] -= (dGi[b] * A[e]).ravel()
             f += 1
     doeb = rd(doe)
-    X = cache["X"]
-    extra = dict(Wo=X.T @ doeb, bo=doe.sum(axis=0), ao=dao)
-    dX = doeb @ P["Wo"].T
+    X, z1 = cache["X"], cache["z1"]
+    dz1 = (doeb @ P["Wo2"].T) * (z1 > 0)
+    dz1b = rd(dz1)
+    extra = dict(Wo2=rd(z1).T @ doeb, bo2=doe.sum(axis=0), ao=dao, Wo1=X.T @ dz1b, bo1=dz1.sum(axis=0))
+    dX = dz1b @ P["Wo1"].T
     dh = np.zeros((n, H))
     dg = np.zeros_like(cache["g"])
     for f, (i, j, e) in enumerate(cache["fe"]):

@@ -55,11 +55,10 @@ __global__ __launch_bounds__(BS) void k_fsai_norm(int64_t n_blk, const int32_t* 
     }
 }
 
-// Cholesky of a 9x9 SPD tile and the inverse of its factor, by the 64 lanes
-// of one wave (lane l < 45 holds lower element (r, c), l = r(r+1)/2 + c).
-// Writes L (lower, zero upper) over T and L^-1 (lower) into Di; returns
-// false if a pivot was not positive (the wave's lanes agree).
-__device__ __forceinline__ bool chol9_wave(float* T, float* Di) {
+// Cholesky of a 9x9 SPD tile by the 64 lanes of one wave (lane l < 45 holds
+// lower element (r, c), l = r(r+1)/2 + c); writes L (lower, zero upper) over
+// T; returns false if a pivot was not positive (the wave's lanes agree).
+__device__ __forceinline__ bool chol9_wave(float* T) {
     const int l = threadIdx.x % kWave;
     const bool act = l < 45;
     int rr = 0;
@@ -80,32 +79,9 @@ __device__ __forceinline__ bool chol9_wave(float* T, float* Di) {
         const float y = __shfl(v, lc, kWave);
         if (upd) v -= x * y;
     }
-    // X = L^-1 by distance from the diagonal: X_cc = 1 / L_cc,
-    // X_rc = -(sum_{c <= q < r} L_rq X_qc) / L_rr
-    const float ldiag = __shfl(v, act ? rr * (rr + 1) / 2 + rr : 0, kWave);
-    float xv = (act && rr == cc) ? 1.f / v : 0.f;
-#pragma unroll
-    for (int s = 1; s < 9; ++s) {
-        float acc = 0.f;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int q = cc + j;
-            const bool use = act && (rr - cc) == s && j < s;
-            const int lq = use ? rr * (rr + 1) / 2 + q : 0;     // L_r,q
-            const int xq = use ? q * (q + 1) / 2 + cc : 0;      // X_q,c
-            const float a = __shfl(v, lq, kWave);
-            const float b = __shfl(xv, xq, kWave);
-            if (use) acc += a * b;
-        }
-        if (act && (rr - cc) == s) xv = -acc / ldiag;
-    }
     if (act) {
         T[rr * 9 + cc] = v;
-        Di[rr * 9 + cc] = xv;
-        if (rr != cc) {
-            T[cc * 9 + rr] = 0.f;
-            Di[cc * 9 + rr] = 0.f;
-        }
+        if (rr != cc) T[cc * 9 + rr] = 0.f;
     }
     return ok;
 }
@@ -118,7 +94,6 @@ __global__ __launch_bounds__(BS) void k_fsai(const int32_t* __restrict__ fs_ptr,
                                              float* __restrict__ G, float* __restrict__ Gl, float* __restrict__ Gu,
                                              int* __restrict__ flags) {
     __shared__ float T[kFsaiTiles][81];
-    __shared__ float Di[kFsaiM][81];
     __shared__ float sP[3][81];
     __shared__ float sC[81];
     __shared__ int s_bad;
@@ -143,25 +118,27 @@ __global__ __launch_bounds__(BS) void k_fsai(const int32_t* __restrict__ fs_ptr,
     __syncthreads();
     for (int b = 0; b < m; ++b) {
         if (threadIdx.x < kWave) {
-            const bool ok = chol9_wave(T[tix(b, b)], Di[b]);
+            const bool ok = chol9_wave(T[tix(b, b)]);
             if (!ok && threadIdx.x == 0) s_bad = 1;
         }
         __syncthreads();
-        // panel: L_ab = T_ab L_bb^-T, one thread per (a, row p)
+        // panel: L_ab L_bb^T = T_ab, row p of L_ab by forward substitution
+        // (one thread per (a, p))
+        const float* Lbb = T[tix(b, b)];
         const int np = (m - 1 - b) * 9;
         for (int task = threadIdx.x; task < np; task += BS) {
             const int a = b + 1 + task / 9, p = task % 9;
             float* Tr = &T[tix(a, b)][p * 9];
-            float u[9];
-#pragma unroll
-            for (int c = 0; c < 9; ++c) u[c] = Tr[c];
+            float x[9];
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                float s = 0.f;
+                float s = Tr[q];
 #pragma unroll
-                for (int c = 0; c <= q; ++c) s += u[c] * Di[b][q * 9 + c];
-                Tr[q] = s;
+                for (int c = 0; c < q; ++c) s -= x[c] * Lbb[q * 9 + c];
+                x[q] = s / Lbb[q * 9 + q];
             }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) Tr[q] = x[q];
         }
         __syncthreads();
         // trailing update: T_ac -= L_ab L_cb^T for b < c <= a, one thread
@@ -199,10 +176,26 @@ __global__ __launch_bounds__(BS) void k_fsai(const int32_t* __restrict__ fs_ptr,
         __syncthreads();
     }
     // last block row of L^-1: R_{m-1} = L_{m-1,m-1}^-1; for b < m-1
-    // R_b = -(sum_{a > b} R_a L_ab) L_bb^-1.  R_a is kept in tile (m-1, a)
+    // R_b L_bb = -(sum_{a > b} R_a L_ab).  R_a is kept in tile (m-1, a)
     // (tile (m-1, b) still holds L_{m-1,b} when R_b is formed).
     const int last = m - 1;
-    if (threadIdx.x < 81) T[tix(last, last)][threadIdx.x] = Di[last][threadIdx.x];
+    if (threadIdx.x < 9) {
+        // column c of L^-1 by forward substitution
+        const int c = threadIdx.x;
+        const float* L = T[tix(last, last)];
+        float x[9];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            float s = (r == c) ? 1.f : 0.f;
+#pragma unroll
+            for (int q = 0; q < r; ++q) s -= L[r * 9 + q] * x[q];
+            x[r] = r < c ? 0.f : s / L[r * 9 + r];
+        }
+#pragma unroll
+        for (int r = 0; r < 9; ++r) sC[r * 9 + c] = x[r];
+    }
+    __syncthreads();
+    if (threadIdx.x < 81) T[tix(last, last)][threadIdx.x] = sC[threadIdx.x];
     __syncthreads();
     for (int b = last - 1; b >= 0; --b) {
         if (threadIdx.x < 243) {
@@ -217,14 +210,23 @@ __global__ __launch_bounds__(BS) void k_fsai(const int32_t* __restrict__ fs_ptr,
             sP[part][pq] = s;
         }
         __syncthreads();
-        if (threadIdx.x < 81) sC[threadIdx.x] = sP[0][threadIdx.x] + sP[1][threadIdx.x] + sP[2][threadIdx.x];
-        __syncthreads();
-        if (threadIdx.x < 81) {
-            const int p = threadIdx.x / 9, q = threadIdx.x % 9;
-            float s = 0.f;
-            for (int u = q; u < 9; ++u) s += sC[p * 9 + u] * Di[b][u * 9 + q];
-            T[tix(last, b)][threadIdx.x] = -s;
+        if (threadIdx.x < 9) {
+            // row p of R_b: R_b L_bb = -C, backward over q
+            const int p = threadIdx.x;
+            const float* Lbb = T[tix(b, b)];
+            float r[9];
+#pragma unroll
+            for (int q = 8; q >= 0; --q) {
+                float s = -(sP[0][p * 9 + q] + sP[1][p * 9 + q] + sP[2][p * 9 + q]);
+#pragma unroll
+                for (int u = q + 1; u < 9; ++u) s -= r[u] * Lbb[u * 9 + q];
+                r[q] = s / Lbb[q * 9 + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 9; ++q) sC[p * 9 + q] = r[q];
         }
+        __syncthreads();
+        if (threadIdx.x < 81) T[tix(last, b)][threadIdx.x] = sC[threadIdx.x];
         __syncthreads();
     }
     // G_{i, J_b} = R_b L_{J_b}^-1 (FP64 accumulation); block-Jacobi row if

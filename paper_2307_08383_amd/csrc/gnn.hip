@@ -459,7 +459,8 @@ __global__ __launch_bounds__(64) void k_assemble(int n, const float* __restrict_
 // factorised head (FSAI pattern): M^-1 = G^T G, G block-lower-triangular on
 // the sets J_i; in the block-Jacobi-normalised coordinates Ghat = G L,
 // Ghat_ii = Lt_i (node decoder) and, for the members j < i,
-// Ghat_ij = reshape(Wo^T [h_i, h_j, g_ij] + bo)[:81] - ao[:81] * A_ij.
+// Ghat_ij = reshape(Wo2^T relu(Wo1^T [h_i, h_j, g_ij] + bo1) + bo2)[:81]
+//           - ao[:81] * A_ij.
 // Training minimises the Kaporin functional
 //   f = (1/(9n)) sum_i [tr(Ghat_i Ahat[J_i, J_i] Ghat_i^T) - 2 log det Ghat_ii],
 // whose minimiser over the pattern is the exact FSAI factor.
@@ -678,7 +679,7 @@ void ensure_work(Work& W, int n, int E, int P) {
     grow(&W.dP, big); grow(&W.dPb, big);
     const size_t rows = std::max(n, E);
     const size_t nsplit = (rows + KSPLIT_ROWS - 1) / KSPLIT_ROWS;
-    grow(&W.split, nsplit * 3 * H * std::max(H, F_OFF));
+    grow(&W.split, nsplit * 3 * H * std::max(std::max(H, F_OFF), HO));
     grow(&W.colpart, ((rows + 1023) / 1024) * 3 * H);
     grow(&W.loss_part, (size_t)n / 64 + 2);
     grow(&W.loss, 2);
@@ -690,6 +691,8 @@ void ensure_fwork(Work& W, const Graph& g) {
     const int fE = std::max(std::max(g.fE, W.cap_f), 1), n = std::max(std::max(g.n, W.cap_fn), 1);
     grow(&W.Xf, (size_t)fE * 3 * H); grow(&W.OE, (size_t)fE * F_OFF); grow(&W.dOE, (size_t)fE * F_OFF);
     grow(&W.dOEb, (size_t)fE * F_OFF); grow(&W.dXf, (size_t)fE * 3 * H); grow(&W.aE, (size_t)fE * 81);
+    grow(&W.Z1, (size_t)fE * HO); grow(&W.Z1b, (size_t)fE * HO); grow(&W.dZ1, (size_t)fE * HO);
+    grow(&W.dZ1p, (size_t)fE * HO); grow(&W.dZ1b, (size_t)fE * HO);
     grow(&W.kpart, (size_t)n);
     W.cap_f = fE; W.cap_fn = n;
 }
@@ -744,14 +747,16 @@ void forward(ba_gnn* net, Graph& g, hipStream_t st) {
     gemm(st, n, F_OUT, H, W.Hb + N_LAYERS * nh, H, 1, wb + OFF_WD, F_OUT, 1, w + OFF_BD, false, W.O, F_OUT, nullptr, 0);
 }
 
-// factorised head: X_f and OE = Wo^T X_f + bo for the FSAI edges
+// factorised head: X_f, Z1 = relu(Wo1^T X_f + bo1), OE = Wo2^T Z1 + bo2 for
+// the FSAI edges
 void head_forward(ba_gnn* net, Graph& g, hipStream_t st) {
     Work& W = net->work;
     if (g.fE == 0) return;
     const int64_t nh = (int64_t)g.n * H;
     k_fgather<<<nblk((int64_t)g.fE * 3 * H), BS, 0, st>>>(g.fE, g.fsrc, g.fdst, g.fe, W.Hb + N_LAYERS * nh, W.Gb,
                                                            W.Xf);
-    gemm(st, g.fE, F_OFF, 3 * H, W.Xf, 3 * H, 1, net->wb + OFF_WO, F_OFF, 1, net->w + OFF_BO, false, W.OE, F_OFF,
+    gemm(st, g.fE, HO, 3 * H, W.Xf, 3 * H, 1, net->wb + OFF_WO1, HO, 1, net->w + OFF_BO1, true, W.Z1, HO, W.Z1b, HO);
+    gemm(st, g.fE, F_OFF, HO, W.Z1b, HO, 1, net->wb + OFF_WO2, F_OFF, 1, net->w + OFF_BO2, false, W.OE, F_OFF,
          nullptr, 0);
 }
 
@@ -781,16 +786,21 @@ void backward(ba_gnn* net, Graph& g, float* grad, hipStream_t st, bool head = fa
     if (fhead) {
         const int64_t no = (int64_t)g.fE * F_OFF;
         k_to_bf16<<<nblk(no), BS, 0, st>>>(no, W.dOE, W.dOEb);
-        wgrad(st, W, 3 * H, F_OFF, g.fE, W.Xf, 3 * H, W.dOEb, F_OFF, grad + OFF_WO);
-        colsum(st, W, g.fE, F_OFF, W.dOE, F_OFF, grad + OFF_BO);
+        wgrad(st, W, HO, F_OFF, g.fE, W.Z1b, HO, W.dOEb, F_OFF, grad + OFF_WO2);
+        colsum(st, W, g.fE, F_OFF, W.dOE, F_OFF, grad + OFF_BO2);
         BA_HIP_CHECK(hipMemsetAsync(grad + OFF_AO, 0, F_OFF * sizeof(float), st));
         colsum(st, W, g.fE, 81, W.aE, 81, grad + OFF_AO);
-        // dX_f = dOE Wo^T  (B(k=o, n=x) = Wo[x][o])
-        gemm(st, g.fE, 3 * H, F_OFF, W.dOEb, F_OFF, 1, wb + OFF_WO, 1, F_OFF, nullptr, false, W.dXf, 3 * H,
-             nullptr, 0);
+        // dZ1 = dOE Wo2^T, through the ReLU, then Wo1
+        gemm(st, g.fE, HO, F_OFF, W.dOEb, F_OFF, 1, wb + OFF_WO2, 1, F_OFF, nullptr, false, W.dZ1, HO, nullptr, 0);
+        const int64_t nz = (int64_t)g.fE * HO;
+        k_relu_back<<<nblk(nz), BS, 0, st>>>(nz, W.dZ1, W.Z1, HO, HO, HO, W.dZ1p, W.dZ1b);
+        wgrad(st, W, 3 * H, HO, g.fE, W.Xf, 3 * H, W.dZ1b, HO, grad + OFF_WO1);
+        colsum(st, W, g.fE, HO, W.dZ1p, HO, grad + OFF_BO1);
+        // dX_f = dZ1 Wo1^T  (B(k=o, n=x) = Wo1[x][o])
+        gemm(st, g.fE, 3 * H, HO, W.dZ1b, HO, 1, wb + OFF_WO1, 1, HO, nullptr, false, W.dXf, 3 * H, nullptr, 0);
         k_fscatter_h<<<nblk(nh), BS, 0, st>>>(n, g.fptr, g.fd_ptr, g.fd_list, W.dXf, W.dH);
     } else {
-        BA_HIP_CHECK(hipMemsetAsync(grad + OFF_WO, 0, (N_PARAMS - OFF_WO) * sizeof(float), st));
+        BA_HIP_CHECK(hipMemsetAsync(grad + OFF_HEAD, 0, (N_PARAMS - OFF_HEAD) * sizeof(float), st));
     }
     for (int l = N_LAYERS - 1; l >= 0; --l) {
         const __bf16* Xm = W.Xm + (int64_t)l * 3 * eh;
@@ -981,7 +991,7 @@ void fsai_sets(int n, const int64_t* row_ptr, const int32_t* col_idx, const int3
 void free_work(Work& W) {
     void* p[] = {W.H0, W.Hf, W.G, W.O, W.Z, W.Y, W.Hb, W.Gb, W.Xm, W.Xu, W.Mm, W.T, W.dO, W.dH, W.dT, W.dXu,
                  W.dMm, W.dXm, W.dG, W.dOb, W.dTb, W.dMmb, W.dPb, W.dP, W.split, W.colpart, W.loss_part, W.loss,
-                 W.Xf, W.dOEb, W.OE, W.dOE, W.dXf, W.aE, W.kpart};
+                 W.Xf, W.dOEb, W.OE, W.dOE, W.dXf, W.aE, W.kpart, W.Z1, W.Z1b, W.dZ1, W.dZ1p, W.dZ1b};
     for (void* q : p)
         if (q) (void)hipFree(q);
     W = Work();

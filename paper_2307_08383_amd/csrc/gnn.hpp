@@ -16,9 +16,13 @@ constexpr int64_t LAYER = 3 * H * H + H + 2 * H * H + H;
 constexpr int64_t OFF_WN = 0, OFF_BN = OFF_WN + F_NODE * H, OFF_WE = OFF_BN + H, OFF_BE = OFF_WE + F_EDGE * H;
 constexpr int64_t OFF_L0 = OFF_BE + H;
 constexpr int64_t OFF_WD = OFF_L0 + N_LAYERS * LAYER, OFF_BD = OFF_WD + H * F_OUT;
-// factorised head: off-diagonal blocks of G from [h_i, h_j, g_ij]
+// factorised head: off-diagonal blocks of G from [h_i, h_j, g_ij] through
+// one hidden layer of HO units
 constexpr int F_OFF = 96;              // head output (81 used)
-constexpr int64_t OFF_WO = OFF_BD + F_OUT, OFF_BO = OFF_WO + 3 * H * F_OFF, OFF_AO = OFF_BO + F_OFF;
+constexpr int HO = 128;                // head hidden width
+constexpr int64_t OFF_WO1 = OFF_BD + F_OUT, OFF_BO1 = OFF_WO1 + 3 * H * HO, OFF_WO2 = OFF_BO1 + HO;
+constexpr int64_t OFF_BO2 = OFF_WO2 + HO * F_OFF, OFF_AO = OFF_BO2 + F_OFF;
+constexpr int64_t OFF_HEAD = OFF_WO1;
 constexpr int64_t N_PARAMS = OFF_AO + F_OFF;
 inline int64_t off_M(int l) { return OFF_L0 + l * LAYER; }
 inline int64_t off_c(int l) { return off_M(l) + 3 * H * H; }
@@ -64,8 +68,8 @@ struct Work {
     double* loss = nullptr;
     // factorised head
     int cap_f = 0, cap_fn = 0;
-    __bf16 *Xf = nullptr, *dOEb = nullptr;
-    float *OE = nullptr, *dOE = nullptr, *dXf = nullptr, *aE = nullptr;
+    __bf16 *Xf = nullptr, *dOEb = nullptr, *Z1b = nullptr, *dZ1b = nullptr;
+    float *OE = nullptr, *dOE = nullptr, *dXf = nullptr, *aE = nullptr, *Z1 = nullptr, *dZ1 = nullptr, *dZ1p = nullptr;
     double* kpart = nullptr;
 };
 

@@ -206,13 +206,14 @@ def test_fsai_head_gradient_finite_differences(grid_feat):
     w = G.init_params(2, zero_decoder=False, decoder_scale=0.2)
     d = G.unflatten(w.copy())
     d["ao"][:] = 0.3
-    d["bo"][:] = np.random.default_rng(3).normal(0, 0.02, size=d["bo"].shape)
+    d["bo2"][:] = np.random.default_rng(3).normal(0, 0.02, size=d["bo2"].shape)
+    d["bo1"][:] = np.random.default_rng(4).normal(0, 0.05, size=d["bo1"].shape)
     w = G.flatten(d)
     loss, grad = G.fsai_loss_and_grad(w, f, J)
     rng = np.random.default_rng(4)
     names = {name: (o, int(np.prod(shape))) for name, shape, o in
              [(n_, s_, o_) for (n_, s_), o_ in zip(G.PARAM_SHAPES, np.cumsum([0] + [int(np.prod(s)) for _, s in G.PARAM_SHAPES])[:-1])]}
-    for name in ["Wo", "bo", "ao", "Wd", "bd", "M2", "U0", "We", "Wn"]:
+    for name in ["Wo1", "bo1", "Wo2", "bo2", "ao", "Wd", "bd", "M2", "U0", "We", "Wn"]:
         off, size = names[name]
         for k in rng.choice(size, size=3, replace=False):
             idx = off + int(k)

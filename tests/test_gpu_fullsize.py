@@ -1,6 +1,8 @@
 """Full-size parity (needs a GPU): the benchmark scene (2,000 cameras, 1.6M
-observations) in FP64 and the strip scene (20,000 cameras, ~20M
-observations) in mixed precision, against the oracle on the same inputs.
+observations) in FP64, the strip scene (20,000 cameras, ~20M observations)
+and the partition scene (60,000 free cameras plus a ring of fixed ones,
+~100M observations) in mixed precision, against the oracle on the same
+inputs.
 Per-block errors of the mixed path are written to gpurun_out/ when that
 directory exists."""
 import json
@@ -99,3 +101,16 @@ def test_benchmark_scene_lm_final_cost():
         rep[f"rel_diff_{'fp64' if precision == 0 else 'mixed'}"] = abs(F - F_ref) / F_ref
     _report("fullsize_lm_final_cost.json", rep)
     assert rep["rel_diff_fp64"] <= 1e-6 and rep["rel_diff_mixed"] <= 1e-6
+
+
+@pytest.mark.timeout(1200)
+def test_partition_scene_mixed_rcs_errors():
+    s = scenegen.partition_scene(seed=2, with_stats=False)
+    errs, raw, rerr = _rcs_case(s, 1)
+    rep = dict(scene=s.name, n_obs=s.n_obs, n_fixed=int(s.cam_fixed.sum()), n_blocks=len(errs),
+               max_block_err=float(errs.max()), p999_block_err=float(np.quantile(errs, 0.999)),
+               median_block_err=float(np.median(errs)), max_raw_rel=float(raw.max()),
+               p999_raw_rel=float(np.quantile(raw, 0.999)), max_rhs_rel=float(rerr.max()),
+               p999_rhs_rel=float(np.quantile(rerr, 0.999)))
+    _report("fullsize_partition_mixed_rcs_errors.json", rep)
+    assert errs.max() <= 1e-4

@@ -46,7 +46,8 @@ def _random_head(seed):
     d = G.unflatten(G.init_params(seed, zero_decoder=False, decoder_scale=0.2))
     rng = np.random.default_rng(seed + 100)
     d["ao"][:81] = rng.uniform(0.2, 0.8, size=81)
-    d["bo"][:] = rng.normal(0, 0.02, size=d["bo"].shape)
+    d["bo2"][:] = rng.normal(0, 0.02, size=d["bo2"].shape)
+    d["bo1"][:] = rng.normal(0, 0.05, size=d["bo1"].shape)
     return G.flatten(d)
 
 
