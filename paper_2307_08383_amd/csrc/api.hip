@@ -52,9 +52,9 @@ void upload(ba_ctx* c, T** p, const std::vector<T>& h) {
 
 void free_ctx(ba_ctx* c) {
     if (!c) return;
-    void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->pt_ptr, c->chunk_ptr, c->cam_row,
+    void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->pt_trk, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
-                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
+                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
                     c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
                     c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
@@ -87,27 +87,52 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         if (!std::isfinite(uv[k]) || !std::isfinite(uv[n + k]))
             throw ba_invalid{"obs_uv of observation " + std::to_string(k) + " is not finite"};
     }
-    // (point, camera) order
-    std::vector<int32_t> ptr(np + 1, 0);
-    for (int64_t k = 0; k < n; ++k) ptr[pt[k] + 1]++;
+    // internal order: whole tracks, points by the lowest camera that sees
+    // them (ties by point), observations of a track by camera.  Points seen by
+    // one neighbourhood of cameras end up close together, so the records that
+    // a camera pair (or a camera) reads lie in a narrow window of memory.
+    std::vector<int32_t> cnt(np, 0), key(np, nc);
+    for (int64_t k = 0; k < n; ++k) {
+        cnt[pt[k]]++;
+        key[pt[k]] = std::min(key[pt[k]], cam[k]);
+    }
     for (int32_t p = 0; p < np; ++p) {
-        const int t = ptr[p + 1];
+        const int t = cnt[p];
         if (t < 2) throw ba_invalid{"point " + std::to_string(p) + " has " + std::to_string(t) + " observations (need >= 2)"};
         if (t > kMaxTrack) throw ba_invalid{"point " + std::to_string(p) + " has more than 64 observations"};
-        ptr[p + 1] += ptr[p];
+    }
+    std::vector<int32_t> ord(np);   // internal position -> point (counting sort by key, stable)
+    {
+        std::vector<int64_t> kc(nc + 1, 0);
+        for (int32_t p = 0; p < np; ++p) kc[key[p] + 1]++;
+        for (int32_t i = 0; i < nc; ++i) kc[i + 1] += kc[i];
+        for (int32_t p = 0; p < np; ++p) ord[kc[key[p]]++] = p;
+    }
+    std::vector<int32_t>().swap(key);
+    std::vector<int32_t> ptr(np + 1, 0);   // track start by internal position
+    std::vector<int32_t> trk(2 * (size_t)np);   // (track start, length) by point
+    for (int32_t q = 0; q < np; ++q) {
+        const int32_t p = ord[q];
+        ptr[q + 1] = ptr[q] + cnt[p];
+        trk[2 * (size_t)p] = ptr[q];
+        trk[2 * (size_t)p + 1] = cnt[p];
     }
     std::vector<int64_t> perm(n);
     {
-        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        std::vector<int32_t> fill(np);
+        for (int32_t p = 0; p < np; ++p) fill[p] = trk[2 * (size_t)p];
         for (int64_t k = 0; k < n; ++k) perm[fill[pt[k]]++] = k;
     }
-    for (int32_t p = 0; p < np; ++p) {
-        auto b = perm.begin() + ptr[p], e = perm.begin() + ptr[p + 1];
+    for (int32_t q = 0; q < np; ++q) {
+        auto b = perm.begin() + ptr[q], e = perm.begin() + ptr[q + 1];
         std::sort(b, e, [&](int64_t x, int64_t y) { return cam[x] < cam[y]; });
         for (auto it = b + 1; it < e; ++it)
             if (cam[*it] == cam[*(it - 1)])
-                throw ba_invalid{"duplicate observation of point " + std::to_string(p) + " by camera " + std::to_string(cam[*it])};
+                throw ba_invalid{"duplicate observation of point " + std::to_string(ord[q]) + " by camera " +
+                                 std::to_string(cam[*it])};
     }
+    std::vector<int32_t>().swap(ord);
+    std::vector<int32_t>().swap(cnt);
     std::vector<int32_t> cam_row(nc);
     int32_t nr = 0;
     for (int32_t i = 0; i < nc; ++i) cam_row[i] = (!fixed.empty() && fixed[i]) ? -1 : nr++;
@@ -227,7 +252,66 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         ta.swap(ta2);
         tb.swap(tb2);
     }
-    c->n_seg_wg = (c->n_offseg + 15) / 16;
+    // pair-stage work units.  One lane group works through a unit's couples
+    // one after another, so a long segment would set the stage's duration on
+    // small problems: segments longer than the cap are cut into chunks that
+    // write partial blocks, summed afterwards in chunk order.  The cap is a
+    // quarter of the average work of one of the lane groups the chip holds at
+    // once (256 CUs x 16 waves x 4 groups), at least 8 steps of 4 couples.
+    // A wave runs until the longest of its four units ends, so inside windows
+    // of 32 rows the units are ordered longest first (neighbouring units have
+    // similar lengths, and the rows a CU works on stay close together); the
+    // waves are then cut into 8 contiguous ranges of equal work, one per XCD.
+    std::vector<int32_t> unit_rng, unit_dst, lseg_blk, lseg_ptr{0};
+    {
+        struct Unit { int32_t win, t0, t1, dst; };
+        std::vector<Unit> units;
+        int64_t steps = 0;
+        for (int32_t sg = 0; sg < c->n_offseg; ++sg) steps += (pair_ptr[sg + 1] - pair_ptr[sg] + 3) / 4;
+        const int64_t groups = 256 * 16 * 4;
+        const int64_t cap = 4 * std::max<int64_t>(8, steps / (4 * groups));
+        int32_t n_p = 0;
+        for (int32_t sg = 0; sg < c->n_offseg; ++sg) {
+            const int32_t a = pair_ptr[sg], b = pair_ptr[sg + 1], w = seg_row[sg] / 32;
+            if (b - a <= cap) {
+                units.push_back({w, a, b, off_blk[sg]});
+                continue;
+            }
+            for (int64_t t = a; t < b; t += cap) {
+                units.push_back({w, (int32_t)t, (int32_t)std::min<int64_t>(t + cap, b), -(n_p + 1)});
+                ++n_p;
+            }
+            lseg_blk.push_back(off_blk[sg]);
+            lseg_ptr.push_back(n_p);
+        }
+        std::stable_sort(units.begin(), units.end(), [](const Unit& x, const Unit& y) {
+            return x.win != y.win ? x.win < y.win : x.t1 - x.t0 > y.t1 - y.t0;
+        });
+        const int32_t nu = (int32_t)units.size();
+        for (const Unit& u : units) {
+            unit_rng.push_back(u.t0);
+            unit_rng.push_back(u.t1);
+            unit_dst.push_back(u.dst);
+        }
+        // XCD ranges of equal work: a wave costs its longest unit's steps plus one
+        const int32_t nw = (nu + 3) / 4;
+        std::vector<int64_t> cum(nw + 1, 0);
+        for (int32_t w = 0; w < nw; ++w) {
+            int32_t st = 0;
+            for (int32_t u = 4 * w; u < std::min(nu, 4 * w + 4); ++u) st = std::max(st, (units[u].t1 - units[u].t0 + 3) / 4);
+            cum[w + 1] = cum[w] + st + 1;
+        }
+        c->xcd_wv[0] = 0;
+        for (int x = 1; x < 8; ++x) {
+            const int64_t target = cum[nw] * x / 8;
+            c->xcd_wv[x] = (int32_t)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
+            c->xcd_wv[x] = std::max(c->xcd_wv[x], c->xcd_wv[x - 1]);
+        }
+        c->xcd_wv[8] = nw;
+        c->n_unit = nu;
+        c->n_lseg = (int32_t)lseg_blk.size();
+        c->n_pblk = n_p;
+    }
     c->h_blk_pairs.assign(c->n_blk, 0);
     for (int32_t sg = 0; sg < c->n_offseg; ++sg) c->h_blk_pairs[off_blk[sg]] = pair_ptr[sg + 1] - pair_ptr[sg];
     // observations of each RCS row
@@ -288,7 +372,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->obs_pt, opt);
     upload(c, &c->obs_row, orow);
     upload(c, &c->obs_uv, ouv);
-    upload(c, &c->pt_ptr, ptr);
+    upload(c, &c->pt_trk, trk);
     upload(c, &c->chunk_ptr, chunk);
     upload(c, &c->cam_row, cam_row);
     upload(c, &c->row_ptr, row_ptr32);
@@ -296,6 +380,10 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->off_blk, off_blk);
     upload(c, &c->pair_ptr, pair_ptr);
     upload(c, &c->trip, trip);
+    upload(c, &c->unit_rng, unit_rng);
+    upload(c, &c->unit_dst, unit_dst);
+    upload(c, &c->lseg_blk, lseg_blk);
+    upload(c, &c->lseg_ptr, lseg_ptr);
     upload(c, &c->rowobs_ptr, rowobs_ptr);
     upload(c, &c->rowobs, rowobs);
     upload(c, &c->rowobs_pt, rowobs_pt);
@@ -312,6 +400,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, (char**)&c->Jp, (size_t)n * 6 * es);
     dalloc(c, &c->e, (size_t)n * 2);
     dalloc(c, &c->ptL, (size_t)np * 9);
+    dalloc(c, &c->pblk, (size_t)c->n_pblk * 81);
     dalloc(c, &c->blk, (size_t)c->n_blk * 81);
     dalloc(c, &c->Sf, (size_t)c->n_sf * 81);
     dalloc(c, &c->rhs, (size_t)nr * 9);

@@ -224,10 +224,11 @@ struct ba_ctx {
     std::vector<int64_t> h_row_ptr;
     std::vector<int32_t> h_col_idx;
     std::vector<int64_t> h_perm;       // internal observation -> caller index
-    // device: observations in internal (point, camera) order
+    // device: observations in internal order (whole tracks, points by their
+    // lowest camera, each track by camera)
     int32_t *obs_cam = nullptr, *obs_pt = nullptr, *obs_row = nullptr;
     double* obs_uv = nullptr;          // [2][n_obs]
-    int32_t* pt_ptr = nullptr;         // [n_pts+1]
+    int32_t* pt_trk = nullptr;         // [n_pts][2]: start of the point's track, its length
     int32_t* chunk_ptr = nullptr;      // [n_chunk+1] point-aligned chunks of <= 64 observations
     int32_t* cam_row = nullptr;        // [n_cams] RCS row or -1
     // pattern
@@ -246,7 +247,15 @@ struct ba_ctx {
     void* Jp = nullptr;                // [n_obs][6] T: J_p
     double* e = nullptr;               // [n_obs][2]
     int32_t* rowobs_pt = nullptr;      // point of each entry of rowobs
-    int32_t n_seg_wg = 0;              // workgroups of the pair stage (XCD-ordered)
+    // pair-stage work units: couple ranges unit_rng[u] = [t0, t1) and
+    // destinations (block index, or -(partial block + 1) for a chunk of a
+    // split segment); split segment l sums partial blocks
+    // [lseg_ptr[l], lseg_ptr[l+1]) into block lseg_blk[l].  Waves (4 units
+    // each) [xcd_wv[x], xcd_wv[x+1]) run on XCD x.
+    int32_t n_unit = 0, n_lseg = 0, n_pblk = 0;
+    int32_t xcd_wv[9] = {0};
+    int32_t *unit_rng = nullptr, *unit_dst = nullptr, *lseg_blk = nullptr, *lseg_ptr = nullptr;
+    double* pblk = nullptr;            // [n_pblk][81]
     double* ptL = nullptr;             // [n_pts][9]: Cholesky of V* (6), L^-1 l_p (3)
     double *blk = nullptr, *rhs = nullptr, *Minv = nullptr, *Mlearn = nullptr;
     double* Linv = nullptr;            // [n_rows][81] L_i^-1 (lower) of S_ii = L_i L_i^T

@@ -28,7 +28,7 @@ constexpr int WPB = BS / kWave;   // waves per block
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __restrict__ chunk_ptr,
-                                              const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ pt_ptr,
+                                              const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ pt_trk,
                                               T* __restrict__ R, const T* __restrict__ Jp, const double* __restrict__ e,
                                               double lambda, double* __restrict__ ptL, int* __restrict__ flags) {
     __shared__ double sP[WPB][kWave][9];
@@ -45,9 +45,9 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
         load6(Jp + (int64_t)k * 6, jp);
         const double2 ek = reinterpret_cast<const double2*>(e)[k];
         p = obs_pt[k];
-        const int b = pt_ptr[p];
-        head = b - k0;
-        tl = pt_ptr[p + 1] - b;
+        const int2 tk = reinterpret_cast<const int2*>(pt_trk)[p];
+        head = tk.x - k0;
+        tl = tk.y;
         sP[wv][lane][0] = jp[0] * jp[0] + jp[3] * jp[3];
         sP[wv][lane][1] = jp[0] * jp[1] + jp[3] * jp[4];
         sP[wv][lane][2] = jp[0] * jp[2] + jp[3] * jp[5];
@@ -103,74 +103,144 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
 }
 
 // ---------------------------------------------------------------------------
-// off-diagonal pair stage.  16 lanes per camera pair = 4 couple slots x 4
-// column quarters ({0,1,2}, {3,4}, {5,6}, {7,8}); each lane accumulates the
-// 9 rows of its columns of
+// off-diagonal pair stage.  One wave per workgroup, 16 lanes per camera pair
+// = 4 couple slots x 4 column quarters ({0,1,2}, {3,4}, {5,6}, {7,8}); each
+// lane accumulates the 9 rows of its columns of
 //   S_ij -= J_ca^T (K_a K_b^T) J_cb
 // over the couples of its slot, then the 4 slots are reduced by shuffles.
-// Segments are stored row by row (longest first inside a row); the block
-// index is remapped so that each XCD works through a contiguous range of
-// rows, keeping the records of neighbouring cameras in its L2.
+// A lane group works on one unit: a whole segment, or a chunk of a long one
+// whose partial block is summed by k_pair_sum.  Each step stages the two records of the wave's 16 couples through LDS
+// with contiguous 16-byte loads spread over the whole wave (every record is
+// fetched once per step instead of once per lane of its couple), so a wave
+// has all of a step's record bytes in flight at once.  Units are stored in
+// windows of rows (longest first inside a window); workgroup b runs on XCD
+// b mod 8, which takes the waves of its own contiguous range of rows (ranges
+// of equal work), keeping the records of neighbouring cameras in its L2.
 // ---------------------------------------------------------------------------
+constexpr int kPairWave = 4;   // units (camera pairs or chunks) per wave
+
+struct XcdRanges { int wv[9]; };
+
 template <typename T>
-__global__ __launch_bounds__(BS) void k_offdiag(int n_seg, int n_wg, const int32_t* __restrict__ off_blk,
-                                                const int32_t* __restrict__ pair_ptr, const int32_t* __restrict__ trip,
-                                                const T* __restrict__ R, double* __restrict__ blk) {
-    const int per_xcd = (n_wg + 7) / 8;
-    const int wg = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    const int gl = threadIdx.x % 16;
+struct Chunk;
+template <>
+struct Chunk<double> { using V = double2; };
+template <>
+struct Chunk<float> { using V = float4; };
+
+template <typename T>
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_offdiag(int n_unit, XcdRanges xr, const int32_t* __restrict__ unit_rng,
+                                                   const int32_t* __restrict__ unit_dst,
+                                                   const int32_t* __restrict__ trip, const T* __restrict__ R,
+                                                   double* __restrict__ blk, double* __restrict__ pblk) {
+    using V = typename Chunk<T>::V;
+    constexpr int kVal = sizeof(V) / sizeof(T);                      // values per chunk (2 or 4)
+    constexpr int kCh = kRec / kVal;                                 // chunks per record (12 or 6)
+    constexpr int kCpl = 4 * kPairWave;                              // couples per step
+    constexpr int kLoads = kCpl * 2 * kCh / kWave;                   // chunk loads per lane per step
+    constexpr int kCS = 2 * kRec + (sizeof(T) == 8 ? 2 : 4);         // couple stride in LDS (padded)
+    static_assert(kLoads * kWave == kCpl * 2 * kCh, "staging must tile the wave");
+    __shared__ __align__(16) T sC[kCpl * kCS];
+    __shared__ int2 sT[kCpl];
+    const int xcd = blockIdx.x % 8;
+    const int wv = xr.wv[xcd] + (int)(blockIdx.x / 8);
+    if (wv >= xr.wv[xcd + 1]) return;   // whole workgroup (one wave) leaves
+    const int lane = threadIdx.x;
+    const int grp = lane / 16, gl = lane % 16;
     const int slot = gl / 4, quarter = gl % 4;
-    const int seg = wg * (BS / 16) + threadIdx.x / 16;
+    const int unit = wv * kPairWave + grp;
     const int c0 = quarter == 0 ? 0 : 2 * quarter + 1;   // 0, 3, 5, 7
     const int nc = quarter == 0 ? 3 : 2;
+    const bool live = unit < n_unit;
+    int t0 = 0, t1 = 0;
+    if (live) { const int2 r = reinterpret_cast<const int2*>(unit_rng)[unit]; t0 = r.x; t1 = r.y; }
+    // wave-uniform step count: the longest of the wave's units
+    int steps = (t1 - t0 + 3) / 4;
+    steps = max(steps, __shfl_xor(steps, 16, kWave));
+    steps = max(steps, __shfl_xor(steps, 32, kWave));
     double acc[27];
 #pragma unroll
     for (int m = 0; m < 27; ++m) acc[m] = 0.0;
-    int t0 = 0, t1 = 0;
-    if (wg < n_wg && seg < n_seg) { t0 = pair_ptr[seg]; t1 = pair_ptr[seg + 1]; }
-    for (int t = t0 + slot; t < t1; t += 4) {
-        const int2 ab = reinterpret_cast<const int2*>(trip)[t];
-        const T* ra = R + (int64_t)ab.x * kRec;
-        const T* rb = R + (int64_t)ab.y * kRec;
-        double ja[18], ka[6], kb[6], jb0[3], jb1[3];
-        load_jc(ra, ja);
-        load6(ra + 18, ka);
-        load6(rb + 18, kb);
+    const T* me = sC + (grp * 4 + slot) * kCS;
+    for (int st = 0; st < steps; ++st) {
+        const int t = t0 + 4 * st + slot;
+        const bool ok = t < t1;
+        if (quarter == 0) sT[grp * 4 + slot] = ok ? reinterpret_cast<const int2*>(trip)[t] : make_int2(-1, -1);
+        __syncthreads();
+        V v[kLoads];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int c = c0 + (q < nc ? q : 0);
-            jb0[q] = (double)rb[c];
-            jb1[q] = (double)rb[9 + c];
-        }
-        // M = K_a K_b^T (2x2), P = M J_cb (2 x my columns)
-        const double m00 = ka[0] * kb[0] + ka[1] * kb[1] + ka[2] * kb[2];
-        const double m01 = ka[0] * kb[3] + ka[1] * kb[4] + ka[2] * kb[5];
-        const double m10 = ka[3] * kb[0] + ka[4] * kb[1] + ka[5] * kb[2];
-        const double m11 = ka[3] * kb[3] + ka[4] * kb[4] + ka[5] * kb[5];
-        double p0[3], p1[3];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            p0[q] = m00 * jb0[q] + m01 * jb1[q];
-            p1[q] = m10 * jb0[q] + m11 * jb1[q];
+        for (int k = 0; k < kLoads; ++k) {
+            const int ch = k * kWave + lane;
+            const int ci = ch / (2 * kCh), part = ch % (2 * kCh);
+            const int2 ab = sT[ci];
+            const int o = part < kCh ? ab.x : ab.y;
+            if (o >= 0) v[k] = reinterpret_cast<const V*>(R + (int64_t)o * kRec)[part % kCh];
+            else v[k] = V{};
         }
 #pragma unroll
-        for (int r = 0; r < 9; ++r)
+        for (int k = 0; k < kLoads; ++k) {
+            const int ch = k * kWave + lane;
+            const int ci = ch / (2 * kCh), part = ch % (2 * kCh);
+            *reinterpret_cast<V*>(sC + ci * kCS + (part / kCh) * kRec + (part % kCh) * kVal) = v[k];
+        }
+        __syncthreads();
+        if (ok) {
+            double ka[6], kb[6], jb0[3], jb1[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) acc[r * 3 + q] += ja[r] * p0[q] + ja[9 + r] * p1[q];
+            for (int m = 0; m < 6; ++m) { ka[m] = (double)me[18 + m]; kb[m] = (double)me[kRec + 18 + m]; }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int c = c0 + (q < nc ? q : 0);
+                jb0[q] = (double)me[kRec + c];
+                jb1[q] = (double)me[kRec + 9 + c];
+            }
+            // M = K_a K_b^T (2x2), P = M J_cb (2 x my columns)
+            const double m00 = ka[0] * kb[0] + ka[1] * kb[1] + ka[2] * kb[2];
+            const double m01 = ka[0] * kb[3] + ka[1] * kb[4] + ka[2] * kb[5];
+            const double m10 = ka[3] * kb[0] + ka[4] * kb[1] + ka[5] * kb[2];
+            const double m11 = ka[3] * kb[3] + ka[4] * kb[4] + ka[5] * kb[5];
+            double p0[3], p1[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                p0[q] = m00 * jb0[q] + m01 * jb1[q];
+                p1[q] = m10 * jb0[q] + m11 * jb1[q];
+            }
+#pragma unroll
+            for (int r = 0; r < 9; ++r) {
+                const double a0 = (double)me[r], a1 = (double)me[9 + r];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) acc[r * 3 + q] += a0 * p0[q] + a1 * p1[q];
+            }
+        }
+        __syncthreads();
     }
 #pragma unroll
     for (int m = 0; m < 27; ++m) {
         acc[m] += __shfl_xor(acc[m], 4, kWave);
         acc[m] += __shfl_xor(acc[m], 8, kWave);
     }
-    if (wg < n_wg && seg < n_seg && slot == 0) {
-        double* out = blk + (int64_t)off_blk[seg] * 81;
+    if (live && slot == 0) {
+        const int dst = unit_dst[unit];
+        double* out = dst >= 0 ? blk + (int64_t)dst * 81 : pblk + (int64_t)(-dst - 1) * 81;
 #pragma unroll
         for (int r = 0; r < 9; ++r)
 #pragma unroll
             for (int q = 0; q < 3; ++q)
                 if (q < nc) out[r * 9 + c0 + q] = -acc[r * 3 + q];
     }
+}
+
+// Blocks of split segments: the sum of their chunks' partial blocks, in
+// chunk order (one thread per block entry).
+__global__ __launch_bounds__(BS) void k_pair_sum(int n_lseg, const int32_t* __restrict__ lseg_blk,
+                                                 const int32_t* __restrict__ lseg_ptr,
+                                                 const double* __restrict__ pblk, double* __restrict__ blk) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= (int64_t)n_lseg * 81) return;
+    const int l = (int)(i / 81), e = (int)(i % 81);
+    double v = 0.0;
+    for (int p = lseg_ptr[l]; p < lseg_ptr[l + 1]; ++p) v += pblk[(int64_t)p * 81 + e];
+    blk[(int64_t)lseg_blk[l] * 81 + e] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -300,7 +370,7 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
 template <typename T>
 __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __restrict__ chunk_ptr,
                                                 const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ obs_row,
-                                                const int32_t* __restrict__ pt_ptr, const T* __restrict__ R,
+                                                const int32_t* __restrict__ pt_trk, const T* __restrict__ R,
                                                 const double* __restrict__ ptL, const double* __restrict__ dxc,
                                                 double* __restrict__ dxp) {
     __shared__ double sP[WPB][kWave][3];
@@ -313,9 +383,9 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
     int p = 0, head = -1, tl = 0;
     if (act) {
         p = obs_pt[k];
-        const int b = pt_ptr[p];
-        head = b - k0;
-        tl = pt_ptr[p + 1] - b;
+        const int2 tk = reinterpret_cast<const int2*>(pt_trk)[p];
+        head = tk.x - k0;
+        tl = tk.y;
         const int row = obs_row[k];
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         if (row >= 0) {
@@ -359,23 +429,31 @@ void launch_point(ba_ctx* c, double lambda) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
     if (nb == 0) return;
     if (c->precision == BA_MIXED)
-        k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->pt_ptr, (float*)c->R,
+        k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->pt_trk, (float*)c->R,
                                                  (const float*)c->Jp, c->e, lambda, c->ptL, c->flags);
     else
-        k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->pt_ptr, (double*)c->R,
+        k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->pt_trk, (double*)c->R,
                                                   (const double*)c->Jp, c->e, lambda, c->ptL, c->flags);
 }
 
 void launch_offdiag(ba_ctx* c) {
-    const int n_wg = c->n_seg_wg;
-    if (n_wg == 0) return;
-    const int grid = 8 * ((n_wg + 7) / 8);
+    if (c->n_unit == 0) return;
+    XcdRanges xr;
+    int most = 0;
+    for (int x = 0; x < 9; ++x) xr.wv[x] = c->xcd_wv[x];
+    for (int x = 0; x < 8; ++x) most = std::max(most, xr.wv[x + 1] - xr.wv[x]);
+    const int grid = 8 * most;
     if (c->precision == BA_MIXED)
-        k_offdiag<float><<<grid, BS, 0, c->stream>>>(c->n_offseg, n_wg, c->off_blk, c->pair_ptr, c->trip,
-                                                     (const float*)c->R, c->blk);
+        k_offdiag<float><<<grid, kWave, 0, c->stream>>>(c->n_unit, xr, c->unit_rng, c->unit_dst, c->trip,
+                                                        (const float*)c->R, c->blk, c->pblk);
     else
-        k_offdiag<double><<<grid, BS, 0, c->stream>>>(c->n_offseg, n_wg, c->off_blk, c->pair_ptr, c->trip,
-                                                      (const double*)c->R, c->blk);
+        k_offdiag<double><<<grid, kWave, 0, c->stream>>>(c->n_unit, xr, c->unit_rng, c->unit_dst, c->trip,
+                                                         (const double*)c->R, c->blk, c->pblk);
+    if (c->n_lseg > 0) {
+        const int64_t n = (int64_t)c->n_lseg * 81;
+        k_pair_sum<<<(unsigned)((n + BS - 1) / BS), BS, 0, c->stream>>>(c->n_lseg, c->lseg_blk, c->lseg_ptr,
+                                                                        c->pblk, c->blk);
+    }
 }
 
 void launch_diag(ba_ctx* c, double lambda) {
@@ -394,10 +472,10 @@ void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
     if (nb == 0) return;
     if (c->precision == BA_MIXED)
-        k_backsub<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_ptr,
+        k_backsub<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_trk,
                                                    (const float*)c->R, c->ptL, dxc, dxp);
     else
-        k_backsub<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_ptr,
+        k_backsub<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_trk,
                                                     (const double*)c->R, c->ptL, dxc, dxp);
 }
 
