@@ -52,7 +52,7 @@ void upload(ba_ctx* c, T** p, const std::vector<T>& h) {
 
 void free_ctx(ba_ctx* c) {
     if (!c) return;
-    void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->pt_trk, c->chunk_ptr, c->cam_row,
+    void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->chunk_q, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
                     c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
                     c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
@@ -110,7 +110,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     }
     std::vector<int32_t>().swap(key);
     std::vector<int32_t> ptr(np + 1, 0);   // track start by internal position
-    std::vector<int32_t> trk(2 * (size_t)np);   // (track start, length) by point
+    std::vector<int32_t> trk(2 * (size_t)np);   // (track start, length) by point, for the permutation
     for (int32_t q = 0; q < np; ++q) {
         const int32_t p = ord[q];
         ptr[q + 1] = ptr[q] + cnt[p];
@@ -133,6 +133,10 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     }
     std::vector<int32_t>().swap(ord);
     std::vector<int32_t>().swap(cnt);
+    std::vector<int32_t>().swap(trk);
+    std::vector<int32_t> oq(n);   // internal point index of each internal observation
+    for (int32_t q = 0; q < np; ++q)
+        for (int32_t k = ptr[q]; k < ptr[q + 1]; ++k) oq[k] = q;
     std::vector<int32_t> cam_row(nc);
     int32_t nr = 0;
     for (int32_t i = 0; i < nc; ++i) cam_row[i] = (!fixed.empty() && fixed[i]) ? -1 : nr++;
@@ -147,10 +151,14 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         ouv[k] = uv[s];
         ouv[n + k] = uv[n + s];
     }
-    // point-aligned chunks of at most 64 observations
-    std::vector<int32_t> chunk{0};
-    for (int32_t p = 0; p < np; ++p)
-        if (ptr[p + 1] - chunk.back() > kMaxTrack) chunk.push_back(ptr[p]);
+    // point-aligned chunks of at most 64 observations, and the internal index
+    // of each chunk's first point
+    std::vector<int32_t> chunk{0}, chunk_q{0};
+    for (int32_t q = 0; q < np; ++q)
+        if (ptr[q + 1] - chunk.back() > kMaxTrack) {
+            chunk.push_back(ptr[q]);
+            chunk_q.push_back(q);
+        }
     chunk.push_back((int32_t)n);
     c->n_chunk = (int32_t)chunk.size() - 1;
     // observation couples of every pair of free cameras sharing a point
@@ -327,7 +335,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
             if (orow[k] >= 0) {
                 const int32_t d = fill[orow[k]]++;
                 rowobs[d] = (int32_t)k;
-                rowobs_pt[d] = opt[k];
+                rowobs_pt[d] = oq[k];
             }
     }
     // both triangles by rows: the row's upper blocks S_rs (column s), then the
@@ -372,7 +380,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->obs_pt, opt);
     upload(c, &c->obs_row, orow);
     upload(c, &c->obs_uv, ouv);
-    upload(c, &c->pt_trk, trk);
+    upload(c, &c->chunk_q, chunk_q);
     upload(c, &c->chunk_ptr, chunk);
     upload(c, &c->cam_row, cam_row);
     upload(c, &c->row_ptr, row_ptr32);
@@ -465,10 +473,11 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
-ba_status form_rcs_async(ba_ctx* c, double lambda) {
-    BA_HIP_CHECK(hipMemsetAsync(c->flags, 0, 8 * sizeof(int), c->stream));
+// point_done: the point stage already ran, fused with the linearization
+ba_status form_rcs_async(ba_ctx* c, double lambda, bool point_done = false) {
+    if (!point_done) BA_HIP_CHECK(hipMemsetAsync(c->flags, 0, 8 * sizeof(int), c->stream));
     BA_HIP_CHECK(hipEventRecord(c->ev[1], c->stream));
-    ba::launch_point(c, lambda);
+    if (!point_done) ba::launch_point(c, lambda);
     BA_HIP_CHECK(hipEventRecord(c->ev[2], c->stream));
     ba::launch_offdiag(c);
     BA_HIP_CHECK(hipEventRecord(c->ev[3], c->stream));
@@ -836,14 +845,16 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         const bool relin = !(st->flags & 1) || !c->have_lin;
         BA_HIP_CHECK(hipEventRecord(ev[0], c->stream));
         if (relin) {
-            ba::launch_linearize(c, cams, pts);
+            // linearization and point stage in one pass (the records are written whole)
+            BA_HIP_CHECK(hipMemsetAsync(c->flags, 0, 8 * sizeof(int), c->stream));
+            ba::launch_linearize_point(c, cams, pts, st->lambda);
             BA_HIP_CHECK(hipMemcpyAsync(c->lin_cams, cams, (size_t)c->n_cams * 9 * sizeof(double),
                                         hipMemcpyDeviceToDevice, c->stream));
             c->defl_ready = false;
         }
         BA_HIP_CHECK(hipEventRecord(ev[5], c->stream));
         c->have_lin = true;
-        form_rcs_async(c, st->lambda);
+        form_rcs_async(c, st->lambda, relin);
         int it = 0;
         double rr = 0.0;
         ba_status ps = BA_OK;

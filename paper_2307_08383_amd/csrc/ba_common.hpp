@@ -228,7 +228,7 @@ struct ba_ctx {
     // lowest camera, each track by camera)
     int32_t *obs_cam = nullptr, *obs_pt = nullptr, *obs_row = nullptr;
     double* obs_uv = nullptr;          // [2][n_obs]
-    int32_t* pt_trk = nullptr;         // [n_pts][2]: start of the point's track, its length
+    int32_t* chunk_q = nullptr;        // [n_chunk] internal index of each chunk's first point
     int32_t* chunk_ptr = nullptr;      // [n_chunk+1] point-aligned chunks of <= 64 observations
     int32_t* cam_row = nullptr;        // [n_cams] RCS row or -1
     // pattern
@@ -246,7 +246,7 @@ struct ba_ctx {
     void* R = nullptr;                 // [n_obs][24] T: J_c (18) from linearize, K (6) from the point stage
     void* Jp = nullptr;                // [n_obs][6] T: J_p
     double* e = nullptr;               // [n_obs][2]
-    int32_t* rowobs_pt = nullptr;      // point of each entry of rowobs
+    int32_t* rowobs_pt = nullptr;      // internal point index of each entry of rowobs
     // pair-stage work units: couple ranges unit_rng[u] = [t0, t1) and
     // destinations (block index, or -(partial block + 1) for a chunk of a
     // split segment); split segment l sums partial blocks
@@ -256,7 +256,7 @@ struct ba_ctx {
     int32_t xcd_wv[9] = {0};
     int32_t *unit_rng = nullptr, *unit_dst = nullptr, *lseg_blk = nullptr, *lseg_ptr = nullptr;
     double* pblk = nullptr;            // [n_pblk][81]
-    double* ptL = nullptr;             // [n_pts][9]: Cholesky of V* (6), L^-1 l_p (3)
+    double* ptL = nullptr;             // [n_pts][9] by internal point index: Cholesky of V* (6), L^-1 l_p (3)
     double *blk = nullptr, *rhs = nullptr, *Minv = nullptr, *Mlearn = nullptr;
     double* Linv = nullptr;            // [n_rows][81] L_i^-1 (lower) of S_ii = L_i L_i^T
     double* lin_cams = nullptr;        // [n_cams][9] camera parameters of the last linearization
@@ -296,6 +296,9 @@ void launch_project(const double* cams, const double* pts, const int32_t* obs_ca
                     int64_t n_obs, const double* noise, double* uv, hipStream_t st);
 void launch_linearize(ba_ctx* c, const double* cams, const double* pts);      // -> J, e, scal[0] = F
 void launch_point(ba_ctx* c, double lambda);
+// linearize + point stage in one pass (J, e, scal[0] = F, K, point terms)
+void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, double lambda);
+void launch_reduce(const double* part, int n, double* out, hipStream_t st);   // out = sum of part[0..n)
 void launch_offdiag(ba_ctx* c);
 void launch_diag(ba_ctx* c, double lambda);
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp);

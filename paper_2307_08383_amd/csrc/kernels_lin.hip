@@ -138,6 +138,10 @@ void launch_linearize(ba_ctx* c, const double* cams, const double* pts) {
     k_reduce<<<1, BS, 0, c->stream>>>(c->part, nb, c->scal + 0);
 }
 
+void launch_reduce(const double* part, int n, double* out, hipStream_t st) {
+    k_reduce<<<1, BS, 0, st>>>(part, n, out);
+}
+
 void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const double* dxc, const double* dxp) {
     const int n = (int)c->n_obs, nb = nblk(n);
     if (c->precision == BA_MIXED)

@@ -21,6 +21,24 @@ namespace {
 constexpr int BS = 256;
 constexpr int WPB = BS / kWave;   // waves per block
 
+// Track of a lane of a wave that holds a chunk of whole tracks (lane i holds
+// the chunk's observation i, i < len; a track's observations are adjacent):
+// the lane of the track's first observation, the track length and the
+// track's index among the chunk's tracks.  Called by every lane of the wave.
+struct Track { int head, len, idx; };
+__device__ __forceinline__ Track chunk_track(bool act, int p, int lane, int len) {
+    const int prev = __shfl_up(p, 1, kWave);
+    const bool first = act && (lane == 0 || prev != p);
+    const unsigned long long heads = __ballot(first);
+    const unsigned long long upto = heads & (~0ull >> (63 - lane));   // heads at lanes <= lane
+    const unsigned long long after = heads & ~upto;                   // heads at lanes > lane
+    Track t;
+    t.head = upto ? 63 - __clzll(upto) : 0;
+    t.len = (after ? __ffsll((long long)after) - 1 : len) - t.head;
+    t.idx = __popcll(upto) - 1;
+    return t;
+}
+
 // ---------------------------------------------------------------------------
 // point stage: one wave per chunk of whole tracks (<= 64 observations), one
 // lane per observation.  Track sums V_p, l_p are reduced through LDS by the
@@ -28,7 +46,7 @@ constexpr int WPB = BS / kWave;   // waves per block
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __restrict__ chunk_ptr,
-                                              const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ pt_trk,
+                                              const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ chunk_q,
                                               T* __restrict__ R, const T* __restrict__ Jp, const double* __restrict__ e,
                                               double lambda, double* __restrict__ ptL, int* __restrict__ flags) {
     __shared__ double sP[WPB][kWave][9];
@@ -40,14 +58,13 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
     const int k = k0 + lane;
     const bool act = k < k1;
     double jp[6];
-    int p = 0, head = 0, tl = 0;
+    const int p = act ? obs_pt[k] : -1;
+    const Track tk = chunk_track(act, p, lane, k1 - k0);
+    const int head = tk.head, tl = tk.len;
+    const int64_t q = chunk < n_chunk ? (int64_t)chunk_q[chunk] + tk.idx : 0;   // internal point index
     if (act) {
         load6(Jp + (int64_t)k * 6, jp);
         const double2 ek = reinterpret_cast<const double2*>(e)[k];
-        p = obs_pt[k];
-        const int2 tk = reinterpret_cast<const int2*>(pt_trk)[p];
-        head = tk.x - k0;
-        tl = tk.y;
         sP[wv][lane][0] = jp[0] * jp[0] + jp[3] * jp[3];
         sP[wv][lane][1] = jp[0] * jp[1] + jp[3] * jp[4];
         sP[wv][lane][2] = jp[0] * jp[2] + jp[3] * jp[5];
@@ -83,7 +100,7 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
 #pragma unroll
         for (int m = 0; m < 6; ++m) sR[wv][lane][m] = r[m];
 #pragma unroll
-        for (int m = 0; m < 9; ++m) ptL[(int64_t)p * 9 + m] = r[m];
+        for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
     }
     __syncthreads();
     if (act) {
@@ -98,6 +115,104 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
             const double y2 = (jp[3 * rr + 2] - L20 * y0 - L21 * y1) / L22;
             K[3 * rr] = y0; K[3 * rr + 1] = y1; K[3 * rr + 2] = y2;
         }
+        store6(R + (int64_t)k * kRec + 18, K);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// linearization fused with the point stage (the LM step after an accepted
+// step): one wave per chunk of whole tracks, one lane per observation.  Each
+// lane forms its residual and Jacobian blocks (Eq. (1)); J_c and J_p are
+// rounded to T first, so the results equal k_linearize followed by k_point.
+// The track sums go through LDS as in k_point, and every record is written
+// whole (J_c, then K) by its lane, with no partial-record writes.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(BS) void k_linpoint(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
+                                                 const int32_t* __restrict__ obs_cam,
+                                                 const int32_t* __restrict__ obs_pt,
+                                                 const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
+                                                 const double* __restrict__ cams, const double* __restrict__ pts,
+                                                 double lambda, T* __restrict__ R, T* __restrict__ Jp_out,
+                                                 double* __restrict__ e, double* __restrict__ ptL,
+                                                 double* __restrict__ part, int* __restrict__ flags) {
+    __shared__ double sP[WPB][kWave][9];
+    __shared__ double sR[WPB][kWave][6];
+    __shared__ double sh[WPB];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int chunk = blockIdx.x * WPB + wv;
+    int k0 = 0, k1 = 0;
+    if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
+    const int k = k0 + lane;
+    const bool act = k < k1;
+    double jc[18], jp[6];
+    double cost = 0.0;
+    const int p = act ? obs_pt[k] : -1;
+    const Track tk = chunk_track(act, p, lane, k1 - k0);
+    const int head = tk.head, tl = tk.len;
+    const int64_t q = chunk < n_chunk ? (int64_t)chunk_q[chunk] + tk.idx : 0;   // internal point index
+    if (act) {
+        const double* X = pts + (int64_t)p * 3;
+        double pu, pv;
+        project_point<true>(cams + (int64_t)obs_cam[k] * 9, X[0], X[1], X[2], pu, pv, jc, jp);
+#pragma unroll
+        for (int m = 0; m < 18; ++m) jc[m] = (double)(T)jc[m];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) jp[m] = (double)(T)jp[m];
+        const double eu = pu - uv[k], ev = pv - uv[n + k];
+        store6(Jp_out + (int64_t)k * 6, jp);
+        reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
+        cost = 0.5 * (eu * eu + ev * ev);
+        sP[wv][lane][0] = jp[0] * jp[0] + jp[3] * jp[3];
+        sP[wv][lane][1] = jp[0] * jp[1] + jp[3] * jp[4];
+        sP[wv][lane][2] = jp[0] * jp[2] + jp[3] * jp[5];
+        sP[wv][lane][3] = jp[1] * jp[1] + jp[4] * jp[4];
+        sP[wv][lane][4] = jp[1] * jp[2] + jp[4] * jp[5];
+        sP[wv][lane][5] = jp[2] * jp[2] + jp[5] * jp[5];
+        sP[wv][lane][6] = -(jp[0] * eu + jp[3] * ev);
+        sP[wv][lane][7] = -(jp[1] * eu + jp[4] * ev);
+        sP[wv][lane][8] = -(jp[2] * eu + jp[5] * ev);
+    }
+    const double csum = block_sum<BS>(cost, sh);   // contains the barrier for sP
+    if (threadIdx.x == 0) part[blockIdx.x] = csum;
+    if (act && head == lane) {
+        double s[9];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) s[m] = 0.0;
+        for (int q = 0; q < tl; ++q)
+#pragma unroll
+            for (int m = 0; m < 9; ++m) s[m] += sP[wv][lane + q][m];
+        const double V00 = s[0] * (1.0 + lambda), V11 = s[3] * (1.0 + lambda), V22 = s[5] * (1.0 + lambda);
+        const double L00 = sqrt(V00);
+        const double L10 = s[1] / L00, L20 = s[2] / L00;
+        const double d1 = V11 - L10 * L10;
+        const double L11 = sqrt(d1);
+        const double L21 = (s[4] - L20 * L10) / L11;
+        const double d2 = V22 - L20 * L20 - L21 * L21;
+        const double L22 = sqrt(d2);
+        if (!(V00 > 0.0) || !(d1 > 0.0) || !(d2 > 0.0)) flags[0] = 1;
+        const double y0 = s[6] / L00;
+        const double y1 = (s[7] - L10 * y0) / L11;
+        const double y2 = (s[8] - L20 * y0 - L21 * y1) / L22;
+        const double r[9] = {L00, L10, L11, L20, L21, L22, y0, y1, y2};
+#pragma unroll
+        for (int m = 0; m < 6; ++m) sR[wv][lane][m] = r[m];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
+    }
+    __syncthreads();
+    if (act) {
+        const double L00 = sR[wv][head][0], L10 = sR[wv][head][1], L11 = sR[wv][head][2];
+        const double L20 = sR[wv][head][3], L21 = sR[wv][head][4], L22 = sR[wv][head][5];
+        double K[6];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const double y0 = jp[3 * rr] / L00;
+            const double y1 = (jp[3 * rr + 1] - L10 * y0) / L11;
+            const double y2 = (jp[3 * rr + 2] - L20 * y0 - L21 * y1) / L22;
+            K[3 * rr] = y0; K[3 * rr + 1] = y1; K[3 * rr + 2] = y2;
+        }
+        store_jc(R + (int64_t)k * kRec, jc);
         store6(R + (int64_t)k * kRec + 18, K);
     }
 }
@@ -244,7 +359,7 @@ __global__ __launch_bounds__(BS) void k_pair_sum(int n_lseg, const int32_t* __re
 }
 
 // ---------------------------------------------------------------------------
-// diagonal stage: one block per RCS row over the camera's observations;
+// diagonal stage: one workgroup per RCS row over the camera's observations;
 // S_ii = sum J_c^T (I - K K^T) J_c + lambda diag(U), U = sum J_c^T J_c,
 // b_i = -sum J_c^T (e + K lhat), then the block-Jacobi inverse S_ii^-1
 // (Cholesky and triangular inverse).
@@ -276,7 +391,7 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
         load_jc(rk, jc);
         load6(rk + 18, K);
         const double2 ek = reinterpret_cast<const double2*>(e)[k];
-        const double* lh = ptL + (int64_t)p * 9 + 6;
+        const double* lh = ptL + (int64_t)p * 9 + 6;   // p: internal point index
         const double n00 = 1.0 - (K[0] * K[0] + K[1] * K[1] + K[2] * K[2]);
         const double n01 = -(K[0] * K[3] + K[1] * K[4] + K[2] * K[5]);
         const double n11 = 1.0 - (K[3] * K[3] + K[4] * K[4] + K[5] * K[5]);
@@ -370,7 +485,7 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
 template <typename T>
 __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __restrict__ chunk_ptr,
                                                 const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ obs_row,
-                                                const int32_t* __restrict__ pt_trk, const T* __restrict__ R,
+                                                const int32_t* __restrict__ chunk_q, const T* __restrict__ R,
                                                 const double* __restrict__ ptL, const double* __restrict__ dxc,
                                                 double* __restrict__ dxp) {
     __shared__ double sP[WPB][kWave][3];
@@ -380,12 +495,11 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
     if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
     const int k = k0 + lane;
     const bool act = k < k1;
-    int p = 0, head = -1, tl = 0;
+    const int p = act ? obs_pt[k] : -1;
+    const Track tk = chunk_track(act, p, lane, k1 - k0);
+    const int head = tk.head, tl = tk.len;
+    const int64_t q = chunk < n_chunk ? (int64_t)chunk_q[chunk] + tk.idx : 0;   // internal point index
     if (act) {
-        p = obs_pt[k];
-        const int2 tk = reinterpret_cast<const int2*>(pt_trk)[p];
-        head = tk.x - k0;
-        tl = tk.y;
         const int row = obs_row[k];
         double s0 = 0.0, s1 = 0.0, s2 = 0.0;
         if (row >= 0) {
@@ -411,7 +525,7 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
     if (act && head == lane) {
         double u0 = 0.0, u1 = 0.0, u2 = 0.0;
         for (int q = 0; q < tl; ++q) { u0 += sP[wv][lane + q][0]; u1 += sP[wv][lane + q][1]; u2 += sP[wv][lane + q][2]; }
-        const double* L = ptL + (int64_t)p * 9;
+        const double* L = ptL + q * 9;
         u0 = L[6] - u0; u1 = L[7] - u1; u2 = L[8] - u2;
         // L^T x = u with L = [[L00,0,0],[L10,L11,0],[L20,L21,L22]]
         const double x2 = u2 / L[5];
@@ -429,11 +543,26 @@ void launch_point(ba_ctx* c, double lambda) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
     if (nb == 0) return;
     if (c->precision == BA_MIXED)
-        k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->pt_trk, (float*)c->R,
+        k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (float*)c->R,
                                                  (const float*)c->Jp, c->e, lambda, c->ptL, c->flags);
     else
-        k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->pt_trk, (double*)c->R,
+        k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (double*)c->R,
                                                   (const double*)c->Jp, c->e, lambda, c->ptL, c->flags);
+}
+
+void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, double lambda) {
+    const int nb = (c->n_chunk + WPB - 1) / WPB;
+    if (nb == 0) return;
+    const int n = (int)c->n_obs;
+    if (c->precision == BA_MIXED)
+        k_linpoint<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
+                                                    c->obs_uv, cams, pts, lambda, (float*)c->R, (float*)c->Jp, c->e,
+                                                    c->ptL, c->part, c->flags);
+    else
+        k_linpoint<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
+                                                     c->obs_uv, cams, pts, lambda, (double*)c->R, (double*)c->Jp,
+                                                     c->e, c->ptL, c->part, c->flags);
+    launch_reduce(c->part, nb, c->scal + 0, c->stream);
 }
 
 void launch_offdiag(ba_ctx* c) {
@@ -472,10 +601,10 @@ void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
     if (nb == 0) return;
     if (c->precision == BA_MIXED)
-        k_backsub<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_trk,
+        k_backsub<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
                                                    (const float*)c->R, c->ptL, dxc, dxp);
     else
-        k_backsub<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->pt_trk,
+        k_backsub<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
                                                     (const double*)c->R, c->ptL, dxc, dxp);
 }
 
