@@ -50,6 +50,8 @@ def parse():
                     choices=["block_jacobi", "fsai", "learned", "learned_fsai"],
                     help="preconditioner of the timed LM steps")
     ap.add_argument("--deflate", action="store_true", help="gauge-deflated PCG in the timed LM steps")
+    ap.add_argument("--solver-fp32", action="store_true",
+                    help="PCG products on an FP32 copy of S in the timed LM steps")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first, so that hardware "
                          "byte counters can be scaled against a kernel of known traffic")
@@ -93,7 +95,7 @@ def traffic_from_profile(kernel_src_hash, kernel):
     return None
 
 
-def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=False):
+def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=False, solver_fp32=False):
     """LM run from the scene's start; returns per-iteration means and the
     final cost (FP64 cost of the last accepted iterate)."""
     import torch
@@ -112,7 +114,8 @@ def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(iters):
-        infos.append(ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol, precond=precond, deflate=deflate))
+        infos.append(ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol, precond=precond, deflate=deflate,
+                                   solver_fp32=solver_fp32))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # FP64 cost of the final parameters (the mixed path evaluates cost in FP64 too)
@@ -185,7 +188,7 @@ def main():
         net = ba.ba_gnn_create(learned_precond.load_weights(
             learned_precond.DEFAULT_FSAI_WEIGHTS if pre == ba.BA_PRECOND_LEARNED_FSAI else learned_precond.DEFAULT_WEIGHTS))
         ba.ba_set_preconditioner_net(ctx, net)
-    step_kw = dict(pcg_tol=scene.pcg_tol, precond=pre, deflate=args.deflate)
+    step_kw = dict(pcg_tol=scene.pcg_tol, precond=pre, deflate=args.deflate, solver_fp32=args.solver_fp32)
     for _ in range(args.warmup):
         ba.ba_lm_step(ctx, cams, pts, st, **step_kw)
     torch.cuda.synchronize()
@@ -217,7 +220,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{scene.name} ({scene.n_obs} observations), "
                                f"{'FP64' if args.precision == 'fp64' else 'mixed FP32/FP64'}, "
-                               f"{args.precond.replace('_', '-')}{' + gauge-deflated' if args.deflate else ''} "
+                               f"{args.precond.replace('_', '-')}{' + gauge-deflated' if args.deflate else ''}"
+                               f"{' (FP32 solver matrix)' if args.solver_fp32 else ''} "
                                f"PCG to rel {scene.pcg_tol:g}",
                    "n_cams": scene.n_cams, "n_pts": scene.n_pts, "n_obs": scene.n_obs,
                    "n_blocks": sizes["n_blk"], "n_pairs": sizes["n_pairs"]},
@@ -256,12 +260,16 @@ def main():
                 ("mixed_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_FSAI, True, None),
                 ("mixed_learned_block_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED, True, wb),
                 ("mixed_learned_fsai", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, False, wf),
-                ("mixed_learned_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, True, wf)]
+                ("mixed_learned_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, True, wf),
+                # the same with the solver's products on an FP32 copy of S
+                ("mixed_s32_block_jacobi_deflated", ba.BA_MIXED, ba.BA_PRECOND_BLOCK_JACOBI, True, None),
+                ("mixed_s32_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_FSAI, True, None),
+                ("mixed_s32_learned_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, True, wf)]
         keep = None if args.compare == "all" else set(args.compare.split(","))
         for name, prec, pre, defl, w in variants:
             if keep is not None and name not in keep and name != "fp64_block_jacobi":
                 continue
-            runs[name] = lm_run(scene, obs, prec, pre, lm_iters, w, deflate=defl)
+            runs[name] = lm_run(scene, obs, prec, pre, lm_iters, w, deflate=defl, solver_fp32="_s32_" in name)
             progress(f"LM comparison {name}: {runs[name]['ms_per_iter']:.2f} ms per iteration")
         base = runs["fp64_block_jacobi"]
         out["lm_comparison"] = {

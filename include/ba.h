@@ -110,7 +110,10 @@ typedef struct ba_pcg_opts {
     int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED or _FSAI */
     const double* x0;           /* device [n_rows][9] initial guess or NULL (zero) */
     int32_t deflate;            /* 1: deflate the similarity gauge (see ba_get_gauge) */
-    int32_t reserved;
+    int32_t solver_fp32;        /* 1: the products with S read an FP32 copy of S (rounded
+                                   once from the FP64 RCS); vectors, scalar products and
+                                   the stop test stay FP64.  PCG then solves the system of
+                                   that rounded S (relative entry error <= 2^-24). */
 } ba_pcg_opts;
 
 typedef struct ba_pcg_info {
@@ -145,7 +148,7 @@ typedef struct ba_lm_opts {
     int32_t pcg_max_iter;       /* default 1000 */
     int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED or _FSAI */
     int32_t deflate;            /* 1: deflated PCG on the similarity gauge */
-    int32_t reserved;
+    int32_t solver_fp32;        /* 1: PCG products with an FP32 copy of S (see ba_pcg_opts) */
 } ba_lm_opts;
 
 typedef struct ba_lm_info {

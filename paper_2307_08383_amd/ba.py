@@ -30,7 +30,7 @@ class ProblemDesc(C.Structure):
 
 class PcgOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32), ("x0", C.c_void_p),
-                ("deflate", C.c_int32), ("reserved", C.c_int32)]
+                ("deflate", C.c_int32), ("solver_fp32", C.c_int32)]
 
 
 class PcgInfo(C.Structure):
@@ -43,7 +43,7 @@ class LMState(C.Structure):
 
 class LMOpts(C.Structure):
     _fields_ = [("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32), ("precond", C.c_int32),
-                ("deflate", C.c_int32), ("reserved", C.c_int32)]
+                ("deflate", C.c_int32), ("solver_fp32", C.c_int32)]
 
 
 class LMInfo(C.Structure):
@@ -174,8 +174,10 @@ def ba_form_rcs(ctx, lam):
     _check(lib().ba_form_rcs(ctx, float(lam)), ctx)
 
 
-def ba_pcg_solve(ctx, dxc, tol=1e-6, max_iter=1000, precond=BA_PRECOND_BLOCK_JACOBI, x0=None, deflate=False):
-    o = PcgOpts(tol=tol, max_iter=max_iter, precond=precond, x0=_ptr(x0), deflate=int(bool(deflate)))
+def ba_pcg_solve(ctx, dxc, tol=1e-6, max_iter=1000, precond=BA_PRECOND_BLOCK_JACOBI, x0=None, deflate=False,
+                 solver_fp32=False):
+    o = PcgOpts(tol=tol, max_iter=max_iter, precond=precond, x0=_ptr(x0), deflate=int(bool(deflate)),
+                solver_fp32=int(bool(solver_fp32)))
     info = PcgInfo()
     st = _check(lib().ba_pcg_solve(ctx, C.byref(o), _ptr(dxc), C.byref(info)), ctx,
                 allow=(BA_ERR_NOT_CONVERGED,))
@@ -187,8 +189,9 @@ def ba_back_substitute(ctx, dxc, dxp):
 
 
 def ba_lm_step(ctx, cams, pts, state: LMState, pcg_tol=1e-6, pcg_max_iter=1000,
-               precond=BA_PRECOND_BLOCK_JACOBI, deflate=False):
-    o = LMOpts(pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter, precond=precond, deflate=int(bool(deflate)))
+               precond=BA_PRECOND_BLOCK_JACOBI, deflate=False, solver_fp32=False):
+    o = LMOpts(pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter, precond=precond, deflate=int(bool(deflate)),
+               solver_fp32=int(bool(solver_fp32)))
     info = LMInfo()
     _check(lib().ba_lm_step(ctx, _ptr(cams), _ptr(pts), C.byref(state), C.byref(o), C.byref(info)), ctx)
     return {k: getattr(info, k) for k, _ in LMInfo._fields_}

@@ -54,7 +54,7 @@ void free_ctx(ba_ctx* c) {
     if (!c) return;
     void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->chunk_q, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
-                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
+                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->Sf32, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
                     c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
                     c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
@@ -486,13 +486,21 @@ ba_status form_rcs_async(ba_ctx* c, double lambda, bool point_done = false) {
     BA_HIP_CHECK(hipGetLastError());
     c->have_rcs = true;
     c->sf_ready = false;
+    c->sf32_ready = false;
     c->fs.ready = false;
     c->defl_ready = false;
     c->lambda = lambda;
     return BA_OK;
 }
 
+// selects the S copy of the next solve (allocating the FP32 one on first use)
+void select_solver_matrix(ba_ctx* c, int fp32) {
+    c->s32 = fp32 ? 1 : 0;
+    if (c->s32 && !c->Sf32) dalloc(c, &c->Sf32, (size_t)std::max<int64_t>(c->n_sf, 1) * 81);
+}
+
 void prepare_defl(ba_ctx* c) {
+    if (c->defl_ready && c->defl_s32 != c->s32) c->defl_ready = false;
     if (!c->defl_ready) {
         ba::prepare_deflation(c);
         BA_HIP_CHECK(hipGetLastError());
@@ -787,6 +795,7 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
         if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
         if (pre == BA_PRECOND_LEARNED_FSAI && c->n_rows > 0) prepare_learned_fsai(c);
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
+        select_solver_matrix(c, o ? o->solver_fp32 : 0);
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(c->ev[6], c->stream));
         ba_status s = BA_OK;
@@ -863,6 +872,7 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
         if (pre == BA_PRECOND_LEARNED_FSAI && c->n_rows > 0) prepare_learned_fsai(c);
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
+        select_solver_matrix(c, o ? o->solver_fp32 : 0);
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(ev[6], c->stream));
         if (c->n_rows > 0)

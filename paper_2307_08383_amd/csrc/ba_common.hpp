@@ -242,6 +242,10 @@ struct ba_ctx {
     int64_t n_sf = 0;
     double* Sf = nullptr;
     bool sf_ready = false;
+    float* Sf32 = nullptr;             // FP32 copy of Sf for solver_fp32 (allocated on first use)
+    bool sf32_ready = false;
+    int s32 = 0;                       // the current solve uses Sf32
+    int defl_s32 = 0;                  // precision of S in the deflation set-up (S W, E)
     // linearization / formation
     void* R = nullptr;                 // [n_obs][24] T: J_c (18) from linearize, K (6) from the point stage
     void* Jp = nullptr;                // [n_obs][6] T: J_p
@@ -277,6 +281,7 @@ struct ba_ctx {
         const double* M;
         int mode;
         int defl;
+        int s32;
         double tol;
         int max_iter;
         hipGraphExec_t exec;

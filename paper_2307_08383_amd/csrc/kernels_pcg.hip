@@ -119,8 +119,24 @@ __device__ __forceinline__ double block_total(double wave_value, double* sh) {
     return t;
 }
 
+// Nine consecutive values (one block row) with wide loads: rows start on
+// 4-byte (FP32) or 8-byte (FP64) boundaries, which 16-byte global loads
+// accept, so a row takes 3 (FP32) or 5 (FP64) loads instead of 9.
+struct __attribute__((packed, aligned(4))) Row3f { float a, b, c; };
+typedef double Row2d __attribute__((ext_vector_type(2), aligned(8)));
+__device__ __forceinline__ void load_row9(const float* __restrict__ p, float* v) {
+    const Row3f* r = reinterpret_cast<const Row3f*>(p);
+    const Row3f x = r[0], y = r[1], z = r[2];
+    v[0] = x.a; v[1] = x.b; v[2] = x.c; v[3] = y.a; v[4] = y.b; v[5] = y.c; v[6] = z.a; v[7] = z.b; v[8] = z.c;
+}
+__device__ __forceinline__ void load_row9(const double* __restrict__ p, double* v) {
+    const Row2d* r = reinterpret_cast<const Row2d*>(p);
+    const Row2d a = r[0], b = r[1], c = r[2], d = r[3];
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y; v[6] = d.x; v[7] = d.y; v[8] = p[8];
+}
+
 // Row gather by one wave over a block-CSR row (entries start..start+n-1,
-// blocks stored in the orientation they are applied in): y[c] =
+// blocks stored row-major in the orientation they are applied in): y[c] =
 // sum_e B_e v_e, returned in lanes 0..8 (component c = lane).  v_e is
 // v0[col_e] (VM == 0) or v0[col_e] - alpha v1[col_e] (VM == 1), vector rows
 // vs apart.  Lane group g (lanes 9g..9g+8) takes entries g, g + 7, ...;
@@ -143,21 +159,18 @@ __device__ __forceinline__ double row_gather(int start, int n, const int32_t* __
                 const int e = e0 + u * GRPW;
                 const int ee = start + (e < n ? e : e0);
                 ci[u] = col[ee];
-                const TB* B = blk + (int64_t)ee * 81 + comp * 9;
-#pragma unroll
-                for (int c = 0; c < 9; ++c) bv[u][c] = B[c];
+                load_row9(blk + (int64_t)ee * 81 + comp * 9, bv[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (e0 + u * GRPW >= n) break;
-                const double* x0 = v0 + (int64_t)ci[u] * vs;
                 double y[9];
+                load_row9(v0 + (int64_t)ci[u] * vs, y);
+                if (VM == 1) {
+                    double y1[9];
+                    load_row9(v1 + (int64_t)ci[u] * vs, y1);
 #pragma unroll
-                for (int c = 0; c < 9; ++c) {
-                    if (VM == 0)
-                        y[c] = x0[c];
-                    else
-                        y[c] = x0[c] - alpha * v1[(int64_t)ci[u] * vs + c];
+                    for (int c = 0; c < 9; ++c) y[c] -= alpha * y1[c];
                 }
 #pragma unroll
                 for (int c = 0; c < 9; ++c) acc += (double)bv[u][c] * y[c];
@@ -174,16 +187,18 @@ __device__ __forceinline__ double row_gather(int start, int n, const int32_t* __
     return tot;
 }
 
-// Sf: both triangles of the RCS by rows (FP64), from the upper blocks
+// Sf: both triangles of the RCS by rows (FP64, or rounded to FP32), from the
+// upper blocks
+template <typename TS>
 __global__ __launch_bounds__(BS) void k_build_sf(int64_t n_sf, const int32_t* __restrict__ sf_src,
-                                                 const double* __restrict__ blk, double* __restrict__ Sf) {
+                                                 const double* __restrict__ blk, TS* __restrict__ Sf) {
     const int64_t n = n_sf * 81;
     for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
         const int64_t e = i / 81;
         const int pq = (int)(i % 81), p = pq / 9, q = pq % 9;
         const int src = sf_src[e];
         const double* B = blk + (int64_t)(src >> 1) * 81;
-        Sf[i] = (src & 1) ? B[q * 9 + p] : B[pq];
+        Sf[i] = (TS)((src & 1) ? B[q * 9 + p] : B[pq]);
     }
 }
 
@@ -237,14 +252,15 @@ __global__ void k_gauge_W(int n_cams, const int32_t* __restrict__ cam_row, const
 }
 
 // SW = S W, one wave per block row, the seven columns in turn
+template <typename TS>
 __global__ __launch_bounds__(BS) void k_spmm_W(int n_rows, const int32_t* __restrict__ sf_ptr,
-                                               const int32_t* __restrict__ sf_col, const double* __restrict__ Sf,
+                                               const int32_t* __restrict__ sf_col, const TS* __restrict__ Sf,
                                                const double* __restrict__ W, double* __restrict__ SW) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB)
         for (int v = 0; v < kW; ++v) {
             const int a = sf_ptr[row];
-            const double y = row_gather<double, 0>(a, sf_ptr[row + 1] - a, sf_col, Sf, W + v * 9, nullptr, 0.0,
+            const double y = row_gather<TS, 0>(a, sf_ptr[row + 1] - a, sf_col, Sf, W + v * 9, nullptr, 0.0,
                                                    kW * 9);
             if (lane < 9) SW[(int64_t)row * kW * 9 + v * 9 + lane] = y;
         }
@@ -428,13 +444,14 @@ __global__ __launch_bounds__(BS) void k_pcg_init(int n_rows, const double* __res
 }
 
 // plain y = S x
+template <typename TS>
 __global__ __launch_bounds__(BS) void k_spmv(int n_rows, const int32_t* __restrict__ sf_ptr,
-                                             const int32_t* __restrict__ sf_col, const double* __restrict__ Sf,
+                                             const int32_t* __restrict__ sf_col, const TS* __restrict__ Sf,
                                              const double* __restrict__ x, double* __restrict__ y) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a = sf_ptr[row];
-        const double v = row_gather<double, 0>(a, sf_ptr[row + 1] - a, sf_col, Sf, x, nullptr, 0.0);
+        const double v = row_gather<TS, 0>(a, sf_ptr[row + 1] - a, sf_col, Sf, x, nullptr, 0.0);
         if (lane < 9) y[(int64_t)row * 9 + lane] = v;
     }
 }
@@ -452,9 +469,9 @@ __global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, const int32_t* 
 }
 
 // kernel A; FIRST: the iteration k = 0 (records |r0|^2).
-template <bool FIRST>
+template <bool FIRST, typename TS>
 __global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, const int32_t* __restrict__ sf_ptr,
-                                              const int32_t* __restrict__ sf_col, const double* __restrict__ Sf,
+                                              const int32_t* __restrict__ sf_col, const TS* __restrict__ Sf,
                                               const double* __restrict__ z,
                                               double* __restrict__ d, double* __restrict__ q,
                                               double* __restrict__ pA, const double* __restrict__ pR, int n_part,
@@ -512,7 +529,7 @@ __global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, const int32_t* __restr
             }
         }
         const int a0 = sf_ptr[row];
-        const double sv = row_gather<double, 0>(a0, sf_ptr[row + 1] - a0, sf_col, Sf, z, nullptr, 0.0);
+        const double sv = row_gather<TS, 0>(a0, sf_ptr[row + 1] - a0, sf_col, Sf, z, nullptr, 0.0);
         if (lane < 9) {
             const double qv = (FIRST ? sv : sv + beta * qo) - swm;
             const double dv = (FIRST ? zv : zv + beta * dold) - wm;
@@ -671,13 +688,33 @@ __global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, const int32_t* __rest
 
 int grid_of(int n_rows) { return std::max(1, std::min((n_rows + WPB - 1) / WPB, kMaxGrid)); }
 
+// S products with the matrix copy of the current solve (FP64 Sf or FP32 Sf32)
+template <bool FIRST>
+void launch_A(ba_ctx* c, int g, double tol, int max_iter, int defl, hipStream_t st) {
+    Pcg& P = c->pcg;
+    const int nr = c->n_rows;
+    if (c->s32)
+        k_pcg_A<FIRST, float><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf32, P.z, P.d, P.q, P.pA, P.pR, g,
+                                                P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
+    else
+        k_pcg_A<FIRST, double><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.z, P.d, P.q, P.pA, P.pR, g,
+                                                 P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
+}
+
+void launch_spmv_cur(ba_ctx* c, const double* x, double* y, hipStream_t st) {
+    const int g = grid_of(c->n_rows);
+    if (c->s32)
+        k_spmv<float><<<g, BS, 0, st>>>(c->n_rows, c->sf_ptr, c->sf_col, c->Sf32, x, y);
+    else
+        k_spmv<double><<<g, BS, 0, st>>>(c->n_rows, c->sf_ptr, c->sf_col, c->Sf, x, y);
+}
+
 void enqueue_iterations(ba_ctx* c, int mode, const double* M, int defl, double tol, int max_iter, int count,
                         hipStream_t st) {
     Pcg& P = c->pcg;
     const int nr = c->n_rows, g = grid_of(nr);
     for (int i = 0; i < count; ++i) {
-        k_pcg_A<false><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.z, P.d, P.q, P.pA,
-                                         P.pR, g, P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
+        launch_A<false>(c, g, tol, max_iter, defl, st);
         if (mode == 0) {
             k_pcg_B<<<g, BS, 0, st>>>(nr, M, P.d, P.q, P.x, P.r[0], P.z, P.pA, P.pR, g, P.state, defl, P.SW);
         } else {
@@ -691,13 +728,20 @@ void enqueue_iterations(ba_ctx* c, int mode, const double* M, int defl, double t
 
 }  // namespace
 
-// the row-major copy of both triangles of the current RCS
+// the row-major copy of both triangles of the current RCS (and, for an
+// FP32 solve, its rounded copy)
 void ensure_sf(ba_ctx* c) {
-    if (c->sf_ready || c->n_sf == 0) return;
+    if (c->n_sf == 0) return;
     const int64_t n = c->n_sf * 81;
     const unsigned g = (unsigned)std::min<int64_t>((n + BS - 1) / BS, 8192);
-    k_build_sf<<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf);
-    c->sf_ready = true;
+    if (!c->sf_ready) {
+        k_build_sf<double><<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf);
+        c->sf_ready = true;
+    }
+    if (c->s32 && !c->sf32_ready) {
+        k_build_sf<float><<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf32);
+        c->sf32_ready = true;
+    }
 }
 
 // Gauge vectors of the last linearization, S W and E^-1 of the current RCS
@@ -707,7 +751,11 @@ void prepare_deflation(ba_ctx* c) {
     hipStream_t st = c->stream;
     k_gauge_W<<<(c->n_cams + 255) / 256, 256, 0, st>>>(c->n_cams, c->cam_row, c->lin_cams, P.W);
     ensure_sf(c);
-    k_spmm_W<<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.W, P.SW);
+    if (c->s32)
+        k_spmm_W<float><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf32, P.W, P.SW);
+    else
+        k_spmm_W<double><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.W, P.SW);
+    c->defl_s32 = c->s32;
     k_defl_E_part<<<g, BS, 0, st>>>(nr, P.W, P.SW, P.pE);
     k_defl_E_fin<<<1, 64, 0, st>>>(g, P.pE, P.Einv, c->flags);
 }
@@ -720,7 +768,7 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
     ensure_sf(c);
     const double* q0 = nullptr;
     if (x0) {
-        k_spmv<<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, x0, P.q);
+        launch_spmv_cur(c, x0, P.q, st);
         q0 = P.q;
     }
     if (defl) k_defl_Wr<<<g, BS, 0, st>>>(nr, c->rhs, q0, P.W, P.pW);
@@ -731,8 +779,7 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
         k_pcg_Cf<true><<<g, BS, 0, st>>>(nr, c->fs.gu_ptr, c->fs.gu_col, c->fs.Gu, P.t, P.r[0], P.r[1],
                                          P.z, P.pR, g, P.state, defl, P.SW);
     }
-    k_pcg_A<true><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.z, P.d, P.q, P.pA, P.pR, g,
-                                    P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
+    launch_A<true>(c, g, tol, max_iter, defl, st);
     if (max_iter > 0) {
         if (mode == 0) {
             k_pcg_B<<<g, BS, 0, st>>>(nr, M, P.d, P.q, P.x, P.r[0], P.z, P.pA, P.pR, g, P.state, defl, P.SW);
@@ -751,7 +798,8 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
     hipGraphExec_t exec = nullptr;
     if (c->use_graphs && n_batches > 0) {
         for (auto& gr : c->pcg_graphs)
-            if (gr.M == M && gr.mode == mode && gr.defl == defl && gr.tol == tol && gr.max_iter == max_iter)
+            if (gr.M == M && gr.mode == mode && gr.defl == defl && gr.s32 == c->s32 && gr.tol == tol &&
+                gr.max_iter == max_iter)
                 exec = gr.exec;
         if (!exec) {
             hipStream_t cs = c->capture_stream;
@@ -761,7 +809,7 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
             BA_HIP_CHECK(hipStreamEndCapture(cs, &graph));
             BA_HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             BA_HIP_CHECK(hipGraphDestroy(graph));
-            c->pcg_graphs.push_back({M, mode, defl, tol, max_iter, exec});
+            c->pcg_graphs.push_back({M, mode, defl, c->s32, tol, max_iter, exec});
         }
     }
     hipEvent_t evb[2] = {c->ev[12], c->ev[13]};
@@ -800,7 +848,7 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
 void launch_spmv(ba_ctx* c, const double* x, double* y) {
     if (c->n_rows == 0) return;
     ensure_sf(c);
-    k_spmv<<<grid_of(c->n_rows), BS, 0, c->stream>>>(c->n_rows, c->sf_ptr, c->sf_col, c->Sf, x, y);
+    k_spmv<double><<<grid_of(c->n_rows), BS, 0, c->stream>>>(c->n_rows, c->sf_ptr, c->sf_col, c->Sf, x, y);
 }
 
 }  // namespace ba
