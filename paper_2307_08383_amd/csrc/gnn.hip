@@ -96,6 +96,61 @@ __global__ __launch_bounds__(BS) void k_gemm(int M, int N, int K, int kchunk, co
         }
 }
 
+// The same product for row-major A [M][K] and B [K][N] (unit column
+// strides), K a multiple of 32, N a multiple of 8, rows 16-byte aligned:
+// every thread brings one 8-value vector of the A tile and one of the B tile
+// per K step; B is stored transposed in LDS so that each MFMA operand is one
+// 16-byte LDS read.  Same tiles, lane layout and accumulation order as k_gemm.
+__global__ __launch_bounds__(BS) void k_gemm_v(int M, int N, int K, const __bf16* __restrict__ A, int64_t lda,
+                                               const __bf16* __restrict__ B, int64_t ldb,
+                                               const float* __restrict__ bias, int relu, float* __restrict__ C,
+                                               int64_t ldc, __bf16* __restrict__ Cb, int64_t ldcb) {
+    __shared__ __align__(16) __bf16 sA[64][40];
+    __shared__ __align__(16) __bf16 sBt[64][40];
+    const int tid = threadIdx.x, w = tid / kWave, l = tid % kWave;
+    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    const int ar = tid / 4, ac = (tid % 4) * 8;   // A tile: row, first k
+    const int bk = tid / 8, bn = (tid % 8) * 8;   // B tile: k, first n
+    const bool aok = m0 + ar < M, bok = n0 + bn < N;
+    const __bf16* Ap = A + (int64_t)(m0 + ar) * lda + ac;
+    const __bf16* Bp = B + (int64_t)bk * ldb + n0 + bn;
+    f32x4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 zero8;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) zero8[j] = (__bf16)0.0f;
+    for (int kb = 0; kb < K; kb += 32) {
+        const bf16x8 av = aok ? *reinterpret_cast<const bf16x8*>(Ap + kb) : zero8;
+        const bf16x8 bv = bok ? *reinterpret_cast<const bf16x8*>(Bp + (int64_t)kb * ldb) : zero8;
+        *reinterpret_cast<bf16x8*>(&sA[ar][ac]) = av;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sBt[bn + j][bk] = bv[j];
+        __syncthreads();
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sA[16 * w + l % 16][8 * (l / 16)]);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sBt[16 * nt + l % 16][8 * (l / 16)]);
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + 16 * w + 4 * (l / 16) + i;
+            const int n = n0 + 16 * nt + l % 16;
+            if (m < M && n < N) {
+                float v = acc[nt][i];
+                if (bias) v += bias[n];
+                if (relu) v = v > 0.f ? v : 0.f;
+                C[(int64_t)m * ldc + n] = v;
+                if (Cb) Cb[(int64_t)m * ldcb + n] = (__bf16)v;
+            }
+        }
+}
+
 // out[i] = sum_z part[z][i] in order z = 0, 1, ...
 __global__ __launch_bounds__(BS) void k_sum_split(int64_t n, int nz, const float* __restrict__ part,
                                                   float* __restrict__ out) {
@@ -181,34 +236,42 @@ __global__ __launch_bounds__(64) void k_feat_node(int n, const int32_t* __restri
     for (int r = 45; r < F_NODE; ++r) x[r] = (__bf16)0.0f;
 }
 
-__global__ __launch_bounds__(64) void k_feat_edge(int E, const int32_t* __restrict__ esrc, const int32_t* __restrict__ edst,
-                                                  const int32_t* __restrict__ eblk, const int32_t* __restrict__ etr,
-                                                  const double* __restrict__ blk, const double* __restrict__ Linv,
-                                                  float* __restrict__ A, __bf16* __restrict__ xe) {
-    const int e = blockIdx.x * 64 + threadIdx.x;
-    if (e >= E) return;
-    const double* S = blk + (int64_t)eblk[e] * 81;
-    const bool tr = etr[e] != 0;
-    const double* Li = Linv + (int64_t)esrc[e] * 81;
-    const double* Lj = Linv + (int64_t)edst[e] * 81;
-    // T = S_ij Lj^T (S_ij = tr ? S^T : S); A = Li T
-    double T[81];
-    for (int r = 0; r < 9; ++r)
-        for (int c = 0; c < 9; ++c) {
-            double t = 0.0;
-            for (int q = 0; q <= c; ++q) t += (tr ? S[q * 9 + r] : S[r * 9 + q]) * Lj[c * 9 + q];
-            T[r * 9 + c] = t;
-        }
-    float* Ae = A + (int64_t)e * 81;
-    __bf16* x = xe + (int64_t)e * F_EDGE;
-    for (int r = 0; r < 9; ++r)
-        for (int c = 0; c < 9; ++c) {
-            double t = 0.0;
-            for (int q = 0; q <= r; ++q) t += Li[r * 9 + q] * T[q * 9 + c];
-            Ae[r * 9 + c] = (float)t;
-            x[r * 9 + c] = (__bf16)t;
-        }
-    for (int r = 81; r < F_EDGE; ++r) x[r] = (__bf16)0.0f;
+// Normalised edge blocks A_e = L_i^-1 S_ij L_j^-T (FP32) and their bf16
+// features.  Three edges per workgroup, one thread per block entry: the
+// three blocks of an edge are staged in LDS with contiguous loads, then the
+// two triangular products are formed in two passes (same summation order as
+// a thread-per-edge loop).
+constexpr int kFE = 3;   // edges per workgroup
+__global__ __launch_bounds__(256) void k_feat_edge(int E, const int32_t* __restrict__ esrc, const int32_t* __restrict__ edst,
+                                                   const int32_t* __restrict__ eblk, const int32_t* __restrict__ etr,
+                                                   const double* __restrict__ blk, const double* __restrict__ Linv,
+                                                   float* __restrict__ A, __bf16* __restrict__ xe) {
+    __shared__ double sS[kFE][81], sLi[kFE][81], sLj[kFE][81], sT[kFE][81];
+    const int le = threadIdx.x / 81, pq = threadIdx.x % 81;
+    const int e = blockIdx.x * kFE + le;
+    const bool act = le < kFE && e < E;
+    const int r = pq / 9, c = pq % 9;
+    if (act) {
+        const double* S = blk + (int64_t)eblk[e] * 81;
+        sS[le][pq] = etr[e] != 0 ? S[c * 9 + r] : S[pq];   // S_ij as applied
+        sLi[le][pq] = Linv[(int64_t)esrc[e] * 81 + pq];
+        sLj[le][pq] = Linv[(int64_t)edst[e] * 81 + pq];
+    }
+    __syncthreads();
+    if (act) {   // T = S_ij Lj^T
+        double t = 0.0;
+        for (int q = 0; q <= c; ++q) t += sS[le][r * 9 + q] * sLj[le][c * 9 + q];
+        sT[le][pq] = t;
+    }
+    __syncthreads();
+    if (act) {   // A = Li T
+        double t = 0.0;
+        for (int q = 0; q <= r; ++q) t += sLi[le][r * 9 + q] * sT[le][q * 9 + c];
+        A[(int64_t)e * 81 + pq] = (float)t;
+        __bf16* x = xe + (int64_t)e * F_EDGE;
+        x[pq] = (__bf16)t;
+        if (pq < F_EDGE - 81) x[81 + pq] = (__bf16)0.0f;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -701,7 +764,12 @@ void gemm(hipStream_t st, int M, int N, int K, const __bf16* A, int64_t sam, int
           int64_t sbk, int64_t sbn, const float* bias, bool relu, float* C, int64_t ldc, __bf16* Cb, int64_t ldcb) {
     if (M == 0) return;
     dim3 grid(nblk(M, 64), nblk(N, 64), 1);
-    k_gemm<<<grid, BS, 0, st>>>(M, N, K, K, A, sam, sak, B, sbk, sbn, bias, relu ? 1 : 0, C, ldc, 0, Cb, ldcb);
+    const bool vec = sak == 1 && sbn == 1 && K % 32 == 0 && N % 8 == 0 && sam % 8 == 0 && sbk % 8 == 0 &&
+                     reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
+    if (vec)
+        k_gemm_v<<<grid, BS, 0, st>>>(M, N, K, A, sam, B, sbk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb);
+    else
+        k_gemm<<<grid, BS, 0, st>>>(M, N, K, K, A, sam, sak, B, sbk, sbn, bias, relu ? 1 : 0, C, ldc, 0, Cb, ldcb);
 }
 
 // dW[Kin][Nout] = X^T dY over `rows` rows (X: [rows][ldx] bf16, dY: [rows][ldy] bf16)
@@ -940,7 +1008,7 @@ void compute_features(Graph& g, const double* blk, hipStream_t st) {
     BA_HIP_CHECK(hipMemsetAsync(g.flags, 0, 4 * sizeof(int), st));
     if (g.n > 0) k_feat_node<<<nblk(g.n, 64), 64, 0, st>>>(g.n, g.diag_blk, blk, g.Linv, g.xn, g.flags);
     if (g.E > 0)
-        k_feat_edge<<<nblk(g.E, 64), 64, 0, st>>>(g.E, g.esrc, g.edst, g.eblk, g.etr, blk, g.Linv, g.A, g.xe);
+        k_feat_edge<<<(g.E + kFE - 1) / kFE, 256, 0, st>>>(g.E, g.esrc, g.edst, g.eblk, g.etr, blk, g.Linv, g.A, g.xe);
     BA_HIP_CHECK(hipGetLastError());
 }
 

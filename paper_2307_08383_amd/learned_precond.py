@@ -111,20 +111,24 @@ def collect_graphs(seeds, grid=TRAIN_GRID, lm_iters=8, log=print, grids=None):
     return graphs
 
 
-def train(net, graphs, epochs=6, batch=8, lr=1e-3, seed=0, log=print, head="block"):
+def train(net, graphs, epochs=6, batch=8, lr=1e-3, seed=0, log=print, head="block", cosine=False):
+    """Adam steps over shuffled mini-batches; with cosine, the step size
+    follows a half cosine from lr down to lr / 20 over the whole run."""
     from . import ba
     rng = np.random.default_rng(seed)
     hist = []
     step = 0
+    n_steps = epochs * ((len(graphs) + batch - 1) // batch)
     for ep in range(epochs):
         order = rng.permutation(len(graphs))
         losses = []
         for b in range(0, len(order), batch):
             sel = [graphs[i] for i in order[b:b + batch]]
+            lr_t = lr * (0.05 + 0.95 * 0.5 * (1.0 + np.cos(np.pi * step / n_steps))) if cosine else lr
             if head == "fsai":
-                losses.append(ba.ba_gnn_fsai_train_step(net, sel, lr=lr))
+                losses.append(ba.ba_gnn_fsai_train_step(net, sel, lr=lr_t))
             else:
-                losses.append(ba.ba_gnn_train_step(net, sel, n_probes=4, seed=int(rng.integers(1 << 62)), lr=lr))
+                losses.append(ba.ba_gnn_train_step(net, sel, n_probes=4, seed=int(rng.integers(1 << 62)), lr=lr_t))
             step += 1
         hist.append(float(np.mean(losses)))
         log(f"epoch {ep}: mean loss {hist[-1]:.6f} ({step} steps)")
@@ -203,6 +207,7 @@ def main():
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--cosine", action="store_true", help="half-cosine step-size decay to lr / 20")
     ap.add_argument("--out", default=None)
     ap.add_argument("--report", default=None)
     ap.add_argument("--eval-full-seeds", default="",
@@ -220,7 +225,8 @@ def main():
     log(f"collected {len(graphs)} graphs in {time.time() - t0:.1f} s")
     net = ba.ba_gnn_create(init_params(0))
     t1 = time.time()
-    hist = train(net, graphs, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log, head=args.head)
+    hist = train(net, graphs, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log, head=args.head,
+                 cosine=args.cosine)
     log(f"trained in {time.time() - t1:.1f} s")
     for g in graphs:
         ba.ba_gnn_graph_destroy(g)
@@ -228,7 +234,7 @@ def main():
     np.save(out, w, allow_pickle=False)
     rep = dict(head=args.head, kinds=kinds, grids={k: KINDS[k] for k in kinds}, train_seeds=args.train_seeds,
                eval_seeds=args.eval_seeds, lm_iters=args.lm_iters, epochs=args.epochs, batch=args.batch,
-               lr=args.lr, loss_history=hist)
+               lr=args.lr, cosine=args.cosine, loss_history=hist)
     eval_kinds = args.eval_kinds.split(",") if args.eval_kinds else kinds
     for k in eval_kinds:
         ev = evaluate(net, _range(args.eval_seeds), grid=KINDS[k], lm_iters=args.lm_iters, log=log, head=args.head)
