@@ -141,14 +141,18 @@ __device__ __forceinline__ void load_row9(const double* __restrict__ p, double* 
 // v0[col_e] (VM == 0) or v0[col_e] - alpha v1[col_e] (VM == 1), vector rows
 // vs apart.  Lane group g (lanes 9g..9g+8) takes entries g, g + 7, ...;
 // four entries per round: their block rows and columns are requested
-// together, then their vector rows.
+// together; lane c of a group loads component c of each entry's vector row
+// and the group shares the nine values through its LDS slot (one global
+// load per entry instead of nine copies of the row).
 template <typename TB, int VM>
 __device__ __forceinline__ double row_gather(int start, int n, const int32_t* __restrict__ col,
                                              const TB* __restrict__ blk, const double* __restrict__ v0,
                                              const double* __restrict__ v1, double alpha, int vs = 9) {
     constexpr int U = 4;
+    __shared__ double sx[WPB][GRPW * U][9];
     const int lane = threadIdx.x % kWave;
     const int grp = lane / 9, comp = lane % 9;
+    double (*xs)[9] = sx[threadIdx.x / kWave] + grp * U;
     double acc = 0.0;
     if (grp < GRPW) {
         for (int e0 = grp; e0 < n; e0 += GRPW * U) {
@@ -163,17 +167,15 @@ __device__ __forceinline__ double row_gather(int start, int n, const int32_t* __
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                double x = v0[(int64_t)ci[u] * vs + comp];
+                if (VM == 1) x -= alpha * v1[(int64_t)ci[u] * vs + comp];
+                xs[u][comp] = x;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
                 if (e0 + u * GRPW >= n) break;
-                double y[9];
-                load_row9(v0 + (int64_t)ci[u] * vs, y);
-                if (VM == 1) {
-                    double y1[9];
-                    load_row9(v1 + (int64_t)ci[u] * vs, y1);
 #pragma unroll
-                    for (int c = 0; c < 9; ++c) y[c] -= alpha * y1[c];
-                }
-#pragma unroll
-                for (int c = 0; c < 9; ++c) acc += (double)bv[u][c] * y[c];
+                for (int c = 0; c < 9; ++c) acc += (double)bv[u][c] * xs[u][c];
             }
         }
     }
