@@ -54,7 +54,7 @@ void free_ctx(ba_ctx* c) {
     if (!c) return;
     void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->chunk_q, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
-                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->Sf32, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->rowobs_pt, c->ptL, c->blk, c->rhs, c->Minv,
+                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->Sf32, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->obs_rpos, c->ebar, c->ptL, c->blk, c->rhs, c->Minv,
                     c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
                     c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
@@ -134,9 +134,6 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     std::vector<int32_t>().swap(ord);
     std::vector<int32_t>().swap(cnt);
     std::vector<int32_t>().swap(trk);
-    std::vector<int32_t> oq(n);   // internal point index of each internal observation
-    for (int32_t q = 0; q < np; ++q)
-        for (int32_t k = ptr[q]; k < ptr[q + 1]; ++k) oq[k] = q;
     std::vector<int32_t> cam_row(nc);
     int32_t nr = 0;
     for (int32_t i = 0; i < nc; ++i) cam_row[i] = (!fixed.empty() && fixed[i]) ? -1 : nr++;
@@ -328,14 +325,14 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         if (orow[k] >= 0) rowobs_ptr[orow[k] + 1]++;
     for (int32_t r = 0; r < nr; ++r) rowobs_ptr[r + 1] += rowobs_ptr[r];
     rowobs.resize(rowobs_ptr[nr]);
-    std::vector<int32_t> rowobs_pt(rowobs_ptr[nr]);
+    std::vector<int32_t> obs_rpos(n, -1);   // position of each observation in its row's list
     {
         std::vector<int32_t> fill(rowobs_ptr.begin(), rowobs_ptr.end() - 1);
         for (int64_t k = 0; k < n; ++k)
             if (orow[k] >= 0) {
                 const int32_t d = fill[orow[k]]++;
                 rowobs[d] = (int32_t)k;
-                rowobs_pt[d] = oq[k];
+                obs_rpos[k] = d;
             }
     }
     // both triangles by rows: the row's upper blocks S_rs (column s), then the
@@ -394,7 +391,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->lseg_ptr, lseg_ptr);
     upload(c, &c->rowobs_ptr, rowobs_ptr);
     upload(c, &c->rowobs, rowobs);
-    upload(c, &c->rowobs_pt, rowobs_pt);
+    upload(c, &c->obs_rpos, obs_rpos);
     upload(c, &c->sf_ptr, sf_ptr);
     upload(c, &c->sf_col, sf_col);
     upload(c, &c->sf_src, sf_src);
@@ -408,6 +405,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, (char**)&c->Jp, (size_t)n * 6 * es);
     dalloc(c, &c->e, (size_t)n * 2);
     dalloc(c, &c->ptL, (size_t)np * 9);
+    dalloc(c, &c->ebar, (size_t)rowobs_ptr[nr] * 2);
     dalloc(c, &c->pblk, (size_t)c->n_pblk * 81);
     dalloc(c, &c->blk, (size_t)c->n_blk * 81);
     dalloc(c, &c->Sf, (size_t)c->n_sf * 81);

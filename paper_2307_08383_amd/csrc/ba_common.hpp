@@ -250,7 +250,8 @@ struct ba_ctx {
     void* R = nullptr;                 // [n_obs][24] T: J_c (18) from linearize, K (6) from the point stage
     void* Jp = nullptr;                // [n_obs][6] T: J_p
     double* e = nullptr;               // [n_obs][2]
-    int32_t* rowobs_pt = nullptr;      // internal point index of each entry of rowobs
+    int32_t* obs_rpos = nullptr;       // [n_obs] position in rowobs (-1: fixed camera)
+    double* ebar = nullptr;            // [n_rowobs][2] e + K lhat in rowobs order (point stage -> diagonal)
     // pair-stage work units: couple ranges unit_rng[u] = [t0, t1) and
     // destinations (block index, or -(partial block + 1) for a chunk of a
     // split segment); split segment l sums partial blocks

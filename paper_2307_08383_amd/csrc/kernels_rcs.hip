@@ -39,6 +39,34 @@ __device__ __forceinline__ Track chunk_track(bool act, int p, int lane, int len)
     return t;
 }
 
+// K = J_p L^-T from the point terms r = (L00, L10, L11, L20, L21, L22, lhat):
+// row r of K solves L y = J_p[r]^T.
+__device__ __forceinline__ void point_K(const double* r, const double* jp, double* K) {
+    const double L00 = r[0], L10 = r[1], L11 = r[2], L20 = r[3], L21 = r[4], L22 = r[5];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+        const double y0 = jp[3 * rr] / L00;
+        const double y1 = (jp[3 * rr + 1] - L10 * y0) / L11;
+        const double y2 = (jp[3 * rr + 2] - L20 * y0 - L21 * y1) / L22;
+        K[3 * rr] = y0; K[3 * rr + 1] = y1; K[3 * rr + 2] = y2;
+    }
+}
+
+// ebar = e + K lhat, with K as stored (T), at the observation's position in
+// its camera's list (rpos < 0: fixed camera, no RCS row).  The diagonal
+// stage reads it in that order instead of gathering e and lhat.
+template <typename T>
+__device__ __forceinline__ void store_ebar(const double* r, const double* K, double eu, double ev, int rpos,
+                                           double* __restrict__ ebar) {
+    if (rpos < 0) return;
+    double Kt[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) Kt[m] = (double)(T)K[m];
+    const double v0 = eu + Kt[0] * r[6] + Kt[1] * r[7] + Kt[2] * r[8];
+    const double v1 = ev + Kt[3] * r[6] + Kt[4] * r[7] + Kt[5] * r[8];
+    reinterpret_cast<double2*>(ebar)[rpos] = make_double2(v0, v1);
+}
+
 // ---------------------------------------------------------------------------
 // point stage: one wave per chunk of whole tracks (<= 64 observations), one
 // lane per observation.  Track sums V_p, l_p are reduced through LDS by the
@@ -48,9 +76,10 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __restrict__ chunk_ptr,
                                               const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ chunk_q,
                                               T* __restrict__ R, const T* __restrict__ Jp, const double* __restrict__ e,
-                                              double lambda, double* __restrict__ ptL, int* __restrict__ flags) {
+                                              double lambda, double* __restrict__ ptL, const int32_t* __restrict__ obs_rpos,
+                                              double* __restrict__ ebar, int* __restrict__ flags) {
     __shared__ double sP[WPB][kWave][9];
-    __shared__ double sR[WPB][kWave][6];
+    __shared__ double sR[WPB][kWave][9];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int chunk = blockIdx.x * WPB + wv;
     int k0 = 0, k1 = 0;
@@ -58,13 +87,14 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
     const int k = k0 + lane;
     const bool act = k < k1;
     double jp[6];
+    double2 ek = make_double2(0.0, 0.0);
     const int p = act ? obs_pt[k] : -1;
     const Track tk = chunk_track(act, p, lane, k1 - k0);
     const int head = tk.head, tl = tk.len;
     const int64_t q = chunk < n_chunk ? (int64_t)chunk_q[chunk] + tk.idx : 0;   // internal point index
     if (act) {
         load6(Jp + (int64_t)k * 6, jp);
-        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        ek = reinterpret_cast<const double2*>(e)[k];
         sP[wv][lane][0] = jp[0] * jp[0] + jp[3] * jp[3];
         sP[wv][lane][1] = jp[0] * jp[1] + jp[3] * jp[4];
         sP[wv][lane][2] = jp[0] * jp[2] + jp[3] * jp[5];
@@ -98,24 +128,16 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
         const double y2 = (s[8] - L20 * y0 - L21 * y1) / L22;
         const double r[9] = {L00, L10, L11, L20, L21, L22, y0, y1, y2};
 #pragma unroll
-        for (int m = 0; m < 6; ++m) sR[wv][lane][m] = r[m];
+        for (int m = 0; m < 9; ++m) sR[wv][lane][m] = r[m];
 #pragma unroll
         for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
     }
     __syncthreads();
     if (act) {
-        const double L00 = sR[wv][head][0], L10 = sR[wv][head][1], L11 = sR[wv][head][2];
-        const double L20 = sR[wv][head][3], L21 = sR[wv][head][4], L22 = sR[wv][head][5];
-        // K = J_p L^-T: row r solves L y = J_p[r]^T
         double K[6];
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
-            const double y0 = jp[3 * rr] / L00;
-            const double y1 = (jp[3 * rr + 1] - L10 * y0) / L11;
-            const double y2 = (jp[3 * rr + 2] - L20 * y0 - L21 * y1) / L22;
-            K[3 * rr] = y0; K[3 * rr + 1] = y1; K[3 * rr + 2] = y2;
-        }
+        point_K(sR[wv][head], jp, K);
         store6(R + (int64_t)k * kRec + 18, K);
+        store_ebar<T>(sR[wv][head], K, ek.x, ek.y, obs_rpos[k], ebar);
     }
 }
 
@@ -135,9 +157,10 @@ __global__ __launch_bounds__(BS) void k_linpoint(int n_chunk, const int32_t* __r
                                                  const double* __restrict__ cams, const double* __restrict__ pts,
                                                  double lambda, T* __restrict__ R, T* __restrict__ Jp_out,
                                                  double* __restrict__ e, double* __restrict__ ptL,
+                                                 const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
     __shared__ double sP[WPB][kWave][9];
-    __shared__ double sR[WPB][kWave][6];
+    __shared__ double sR[WPB][kWave][9];
     __shared__ double sh[WPB];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int chunk = blockIdx.x * WPB + wv;
@@ -146,7 +169,7 @@ __global__ __launch_bounds__(BS) void k_linpoint(int n_chunk, const int32_t* __r
     const int k = k0 + lane;
     const bool act = k < k1;
     double jc[18], jp[6];
-    double cost = 0.0;
+    double cost = 0.0, eu = 0.0, ev = 0.0;
     const int p = act ? obs_pt[k] : -1;
     const Track tk = chunk_track(act, p, lane, k1 - k0);
     const int head = tk.head, tl = tk.len;
@@ -159,7 +182,8 @@ __global__ __launch_bounds__(BS) void k_linpoint(int n_chunk, const int32_t* __r
         for (int m = 0; m < 18; ++m) jc[m] = (double)(T)jc[m];
 #pragma unroll
         for (int m = 0; m < 6; ++m) jp[m] = (double)(T)jp[m];
-        const double eu = pu - uv[k], ev = pv - uv[n + k];
+        eu = pu - uv[k];
+        ev = pv - uv[n + k];
         store6(Jp_out + (int64_t)k * 6, jp);
         reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
         cost = 0.5 * (eu * eu + ev * ev);
@@ -196,24 +220,17 @@ __global__ __launch_bounds__(BS) void k_linpoint(int n_chunk, const int32_t* __r
         const double y2 = (s[8] - L20 * y0 - L21 * y1) / L22;
         const double r[9] = {L00, L10, L11, L20, L21, L22, y0, y1, y2};
 #pragma unroll
-        for (int m = 0; m < 6; ++m) sR[wv][lane][m] = r[m];
+        for (int m = 0; m < 9; ++m) sR[wv][lane][m] = r[m];
 #pragma unroll
         for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
     }
     __syncthreads();
     if (act) {
-        const double L00 = sR[wv][head][0], L10 = sR[wv][head][1], L11 = sR[wv][head][2];
-        const double L20 = sR[wv][head][3], L21 = sR[wv][head][4], L22 = sR[wv][head][5];
         double K[6];
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
-            const double y0 = jp[3 * rr] / L00;
-            const double y1 = (jp[3 * rr + 1] - L10 * y0) / L11;
-            const double y2 = (jp[3 * rr + 2] - L20 * y0 - L21 * y1) / L22;
-            K[3 * rr] = y0; K[3 * rr + 1] = y1; K[3 * rr + 2] = y2;
-        }
+        point_K(sR[wv][head], jp, K);
         store_jc(R + (int64_t)k * kRec, jc);
         store6(R + (int64_t)k * kRec + 18, K);
+        store_ebar<T>(sR[wv][head], K, eu, ev, obs_rpos[k], ebar);
     }
 }
 
@@ -366,10 +383,8 @@ __global__ __launch_bounds__(BS) void k_pair_sum(int n_lseg, const int32_t* __re
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restrict__ rowobs_ptr,
-                                             const int32_t* __restrict__ rowobs, const int32_t* __restrict__ rowobs_pt,
-                                             const int32_t* __restrict__ row_ptr, const T* __restrict__ R,
-                                             const double* __restrict__ e, const double* __restrict__ ptL,
-                                             double lambda, double* __restrict__ blk, double* __restrict__ rhs,
+                                             const int32_t* __restrict__ rowobs, const int32_t* __restrict__ row_ptr,
+                                             const T* __restrict__ R, const double* __restrict__ ebar, double lambda, double* __restrict__ blk, double* __restrict__ rhs,
                                              double* __restrict__ Minv, double* __restrict__ Linv,
                                              int* __restrict__ flags) {
     __shared__ double sred[WPB][64];
@@ -385,18 +400,15 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
     const int i0 = rowobs_ptr[row], i1 = rowobs_ptr[row + 1];
     for (int idx = i0 + threadIdx.x; idx < i1; idx += BS) {
         const int k = rowobs[idx];
-        const int p = rowobs_pt[idx];
         double jc[18], K[6];
         const T* rk = R + (int64_t)k * kRec;
         load_jc(rk, jc);
         load6(rk + 18, K);
-        const double2 ek = reinterpret_cast<const double2*>(e)[k];
-        const double* lh = ptL + (int64_t)p * 9 + 6;   // p: internal point index
+        const double2 v = reinterpret_cast<const double2*>(ebar)[idx];   // e + K lhat
         const double n00 = 1.0 - (K[0] * K[0] + K[1] * K[1] + K[2] * K[2]);
         const double n01 = -(K[0] * K[3] + K[1] * K[4] + K[2] * K[5]);
         const double n11 = 1.0 - (K[3] * K[3] + K[4] * K[4] + K[5] * K[5]);
-        const double v0 = ek.x + K[0] * lh[0] + K[1] * lh[1] + K[2] * lh[2];
-        const double v1 = ek.y + K[3] * lh[0] + K[4] * lh[1] + K[5] * lh[2];
+        const double v0 = v.x, v1 = v.y;
         double q0[9], q1[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
@@ -544,10 +556,12 @@ void launch_point(ba_ctx* c, double lambda) {
     if (nb == 0) return;
     if (c->precision == BA_MIXED)
         k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (float*)c->R,
-                                                 (const float*)c->Jp, c->e, lambda, c->ptL, c->flags);
+                                                 (const float*)c->Jp, c->e, lambda, c->ptL, c->obs_rpos, c->ebar,
+                                                 c->flags);
     else
         k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (double*)c->R,
-                                                  (const double*)c->Jp, c->e, lambda, c->ptL, c->flags);
+                                                  (const double*)c->Jp, c->e, lambda, c->ptL, c->obs_rpos, c->ebar,
+                                                  c->flags);
 }
 
 void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, double lambda) {
@@ -557,11 +571,11 @@ void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, do
     if (c->precision == BA_MIXED)
         k_linpoint<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
                                                     c->obs_uv, cams, pts, lambda, (float*)c->R, (float*)c->Jp, c->e,
-                                                    c->ptL, c->part, c->flags);
+                                                    c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
     else
         k_linpoint<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
                                                      c->obs_uv, cams, pts, lambda, (double*)c->R, (double*)c->Jp,
-                                                     c->e, c->ptL, c->part, c->flags);
+                                                     c->e, c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
     launch_reduce(c->part, nb, c->scal + 0, c->stream);
 }
 
@@ -588,12 +602,12 @@ void launch_offdiag(ba_ctx* c) {
 void launch_diag(ba_ctx* c, double lambda) {
     if (c->n_rows == 0) return;
     if (c->precision == BA_MIXED)
-        k_diag<float><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->rowobs_pt, c->row_ptr,
-                                                       (const float*)c->R, c->e, c->ptL, lambda, c->blk, c->rhs,
+        k_diag<float><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->row_ptr,
+                                                       (const float*)c->R, c->ebar, lambda, c->blk, c->rhs,
                                                        c->Minv, c->Linv, c->flags);
     else
-        k_diag<double><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->rowobs_pt, c->row_ptr,
-                                                        (const double*)c->R, c->e, c->ptL, lambda, c->blk, c->rhs,
+        k_diag<double><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->row_ptr,
+                                                        (const double*)c->R, c->ebar, lambda, c->blk, c->rhs,
                                                         c->Minv, c->Linv, c->flags);
 }
 
