@@ -14,6 +14,7 @@
 // source-sorted directed edge list and its backward walks each edge's twin,
 // so forward, backward and the optimiser are deterministic (no atomics).
 #include <algorithm>
+#include <stdexcept>
 #include <cstring>
 #include <vector>
 
@@ -101,8 +102,19 @@ __global__ __launch_bounds__(BS) void k_gemm(int M, int N, int K, int kchunk, co
 // every thread brings one 8-value vector of the A tile and one of the B tile
 // per K step; B is stored transposed in LDS so that each MFMA operand is one
 // 16-byte LDS read.  Same tiles, lane layout and accumulation order as k_gemm.
+// Rows of a message input [h_src, h_dst, g_edge] (3 x H values, bf16) read
+// in place: row m is H[src[m]], H[dst[m]], G[eid ? eid[m] : m].
+struct GatherRows {
+    const int32_t* src;
+    const int32_t* dst;
+    const int32_t* eid;
+    const __bf16* Hn;
+    const __bf16* Ge;
+};
+
+template <bool GA>
 __global__ __launch_bounds__(BS) void k_gemm_v(int M, int N, int K, const __bf16* __restrict__ A, int64_t lda,
-                                               const __bf16* __restrict__ B, int64_t ldb,
+                                               GatherRows gr, const __bf16* __restrict__ B, int64_t ldb,
                                                const float* __restrict__ bias, int relu, float* __restrict__ C,
                                                int64_t ldc, __bf16* __restrict__ Cb, int64_t ldcb) {
     __shared__ __align__(16) __bf16 sA[64][40];
@@ -113,6 +125,13 @@ __global__ __launch_bounds__(BS) void k_gemm_v(int M, int N, int K, const __bf16
     const int bk = tid / 8, bn = (tid % 8) * 8;   // B tile: k, first n
     const bool aok = m0 + ar < M, bok = n0 + bn < N;
     const __bf16* Ap = A + (int64_t)(m0 + ar) * lda + ac;
+    const __bf16* seg[3] = {nullptr, nullptr, nullptr};   // GA: the row's three H-wide pieces
+    if (GA && aok) {
+        const int m = m0 + ar;
+        seg[0] = gr.Hn + (int64_t)gr.src[m] * H;
+        seg[1] = gr.Hn + (int64_t)gr.dst[m] * H;
+        seg[2] = gr.Ge + (int64_t)(gr.eid ? gr.eid[m] : m) * H;
+    }
     const __bf16* Bp = B + (int64_t)bk * ldb + n0 + bn;
     f32x4 acc[4];
 #pragma unroll
@@ -121,7 +140,15 @@ __global__ __launch_bounds__(BS) void k_gemm_v(int M, int N, int K, const __bf16
 #pragma unroll
     for (int j = 0; j < 8; ++j) zero8[j] = (__bf16)0.0f;
     for (int kb = 0; kb < K; kb += 32) {
-        const bf16x8 av = aok ? *reinterpret_cast<const bf16x8*>(Ap + kb) : zero8;
+        bf16x8 av = zero8;
+        if (aok) {
+            if (GA) {
+                const int k = kb + ac;   // a vector never straddles two H-wide pieces
+                av = *reinterpret_cast<const bf16x8*>(seg[k / H] + k % H);
+            } else {
+                av = *reinterpret_cast<const bf16x8*>(Ap + kb);
+            }
+        }
         const bf16x8 bv = bok ? *reinterpret_cast<const bf16x8*>(Bp + (int64_t)kb * ldb) : zero8;
         *reinterpret_cast<bf16x8*>(&sA[ar][ac]) = av;
 #pragma unroll
@@ -767,9 +794,22 @@ void gemm(hipStream_t st, int M, int N, int K, const __bf16* A, int64_t sam, int
     const bool vec = sak == 1 && sbn == 1 && K % 32 == 0 && N % 8 == 0 && sam % 8 == 0 && sbk % 8 == 0 &&
                      reinterpret_cast<uintptr_t>(A) % 16 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0;
     if (vec)
-        k_gemm_v<<<grid, BS, 0, st>>>(M, N, K, A, sam, B, sbk, bias, relu ? 1 : 0, C, ldc, Cb, ldcb);
+        k_gemm_v<false><<<grid, BS, 0, st>>>(M, N, K, A, sam, GatherRows{}, B, sbk, bias, relu ? 1 : 0, C, ldc, Cb,
+                                             ldcb);
     else
         k_gemm<<<grid, BS, 0, st>>>(M, N, K, K, A, sam, sak, B, sbk, sbn, bias, relu ? 1 : 0, C, ldc, 0, Cb, ldcb);
+}
+
+// C = [H[src], H[dst], G[eid]] B (+ bias) (relu) without forming the input
+// rows (K = 3 H; B row-major [3 H][N], N a multiple of 8)
+void gemm_gather(hipStream_t st, int M, int N, const GatherRows& gr, const __bf16* B, const float* bias, bool relu,
+                 float* C, int64_t ldc, __bf16* Cb, int64_t ldcb) {
+    if (M == 0) return;
+    if (N % 8 != 0 || reinterpret_cast<uintptr_t>(B) % 16 != 0 || reinterpret_cast<uintptr_t>(gr.Hn) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(gr.Ge) % 16 != 0)
+        throw std::runtime_error("gemm_gather: operands must be 16-byte aligned, N a multiple of 8");
+    dim3 grid(nblk(M, 64), nblk(N, 64), 1);
+    k_gemm_v<true><<<grid, BS, 0, st>>>(M, N, 3 * H, nullptr, 0, gr, B, N, bias, relu ? 1 : 0, C, ldc, Cb, ldcb);
 }
 
 // dW[Kin][Nout] = X^T dY over `rows` rows (X: [rows][ldx] bf16, dY: [rows][ldy] bf16)
@@ -789,7 +829,9 @@ void colsum(hipStream_t st, Work& W, int rows, int cols, const float* src, int64
     k_colsum_fin<<<1, BS, 0, st>>>(nc, cols, W.colpart, out);
 }
 
-void forward(ba_gnn* net, Graph& g, hipStream_t st) {
+// train: also form the message inputs X_m (the backward pass needs them);
+// inference reads them in place inside the GEMM
+void forward(ba_gnn* net, Graph& g, hipStream_t st, bool train = true) {
     Work& W = net->work;
     const int n = g.n, E = g.E;
     const __bf16* wb = net->wb;
@@ -804,9 +846,12 @@ void forward(ba_gnn* net, Graph& g, hipStream_t st) {
         __bf16* Xu = W.Xu + (int64_t)l * 2 * nh;
         float* Mm = W.Mm + (int64_t)l * eh;
         float* T = W.T + (int64_t)l * nh;
-        if (E > 0) {
+        if (E > 0 && train) {
             k_gather_msg<<<nblk(3 * eh), BS, 0, st>>>(E, g.esrc, g.edst, Hb, W.Gb, Xm);
             gemm(st, E, H, 3 * H, Xm, 3 * H, 1, wb + off_M(l), H, 1, w + off_c(l), true, Mm, H, nullptr, 0);
+        } else if (E > 0) {
+            gemm_gather(st, E, H, GatherRows{g.esrc, g.edst, nullptr, Hb, W.Gb}, wb + off_M(l), w + off_c(l), true,
+                        Mm, H, nullptr, 0);
         }
         k_aggregate<<<nblk(nh), BS, 0, st>>>(n, g.eptr, Mm, Hb, Xu);
         gemm(st, n, H, 2 * H, Xu, 2 * H, 1, wb + off_U(l), H, 1, w + off_u(l), true, T, H, nullptr, 0);
@@ -817,13 +862,19 @@ void forward(ba_gnn* net, Graph& g, hipStream_t st) {
 
 // factorised head: X_f, Z1 = relu(Wo1^T X_f + bo1), OE = Wo2^T Z1 + bo2 for
 // the FSAI edges
-void head_forward(ba_gnn* net, Graph& g, hipStream_t st) {
+void head_forward(ba_gnn* net, Graph& g, hipStream_t st, bool train = true) {
     Work& W = net->work;
     if (g.fE == 0) return;
     const int64_t nh = (int64_t)g.n * H;
-    k_fgather<<<nblk((int64_t)g.fE * 3 * H), BS, 0, st>>>(g.fE, g.fsrc, g.fdst, g.fe, W.Hb + N_LAYERS * nh, W.Gb,
-                                                           W.Xf);
-    gemm(st, g.fE, HO, 3 * H, W.Xf, 3 * H, 1, net->wb + OFF_WO1, HO, 1, net->w + OFF_BO1, true, W.Z1, HO, W.Z1b, HO);
+    if (train) {
+        k_fgather<<<nblk((int64_t)g.fE * 3 * H), BS, 0, st>>>(g.fE, g.fsrc, g.fdst, g.fe, W.Hb + N_LAYERS * nh,
+                                                               W.Gb, W.Xf);
+        gemm(st, g.fE, HO, 3 * H, W.Xf, 3 * H, 1, net->wb + OFF_WO1, HO, 1, net->w + OFF_BO1, true, W.Z1, HO, W.Z1b,
+             HO);
+    } else {
+        gemm_gather(st, g.fE, HO, GatherRows{g.fsrc, g.fdst, g.fe, W.Hb + N_LAYERS * nh, W.Gb}, net->wb + OFF_WO1,
+                    net->w + OFF_BO1, true, W.Z1, HO, W.Z1b, HO);
+    }
     gemm(st, g.fE, F_OFF, HO, W.Z1b, HO, 1, net->wb + OFF_WO2, F_OFF, 1, net->w + OFF_BO2, false, W.OE, F_OFF,
          nullptr, 0);
 }
@@ -1014,7 +1065,7 @@ void compute_features(Graph& g, const double* blk, hipStream_t st) {
 
 void infer_preconditioner(ba_gnn* net, Graph& g, const double* Minv, double* P, hipStream_t st) {
     ensure_work(net->work, g.n, g.E, 1);
-    forward(net, g, st);
+    forward(net, g, st, false);
     k_assemble<<<nblk(g.n, 64), 64, 0, st>>>(g.n, net->work.O, g.Linv, Minv, P);
     BA_HIP_CHECK(hipGetLastError());
 }
@@ -1022,8 +1073,8 @@ void infer_preconditioner(ba_gnn* net, Graph& g, const double* Minv, double* P, 
 void infer_factor(ba_gnn* net, Graph& g, const int32_t* gu_pos, float* Gl, float* Gu, float* Gslots, hipStream_t st) {
     ensure_work(net->work, g.n, g.E, 1);
     ensure_fwork(net->work, g);
-    forward(net, g, st);
-    head_forward(net, g, st);
+    forward(net, g, st, false);
+    head_forward(net, g, st, false);
     if (g.fm > 0)
         k_fassemble<<<g.fm, 128, 0, st>>>(g.n, g.fm, g.fptr, g.fJ, g.fedge, g.fslot, net->work.O, net->work.OE,
                                           net->w + OFF_AO, g.A, g.Linv, gu_pos, Gl, Gu, Gslots);

@@ -189,6 +189,53 @@ __device__ __forceinline__ double row_gather(int start, int n, const int32_t* __
     return tot;
 }
 
+// S W for the kW gauge vectors of one block row (W rows kW * 9 apart): the
+// row's blocks are read once for all of them; results in lanes 0..8 of
+// out[v].  Same entry order and group sums as row_gather.
+template <typename TB>
+__device__ __forceinline__ void row_gather_w(int start, int n, const int32_t* __restrict__ col,
+                                             const TB* __restrict__ blk, const double* __restrict__ W, double* out) {
+    constexpr int U = 4;
+    __shared__ double sxw[WPB][GRPW * U][9];
+    const int lane = threadIdx.x % kWave;
+    const int grp = lane / 9, comp = lane % 9;
+    double (*xs)[9] = sxw[threadIdx.x / kWave] + grp * U;
+    double acc[kW];
+#pragma unroll
+    for (int v = 0; v < kW; ++v) acc[v] = 0.0;
+    if (grp < GRPW) {
+        for (int e0 = grp; e0 < n; e0 += GRPW * U) {
+            int ci[U];
+            TB bv[U][9];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * GRPW;
+                const int ee = start + (e < n ? e : e0);
+                ci[u] = col[ee];
+                load_row9(blk + (int64_t)ee * 81 + comp * 9, bv[u]);
+            }
+#pragma unroll
+            for (int v = 0; v < kW; ++v) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) xs[u][comp] = W[(int64_t)ci[u] * kW * 9 + v * 9 + comp];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (e0 + u * GRPW >= n) break;
+#pragma unroll
+                    for (int c = 0; c < 9; ++c) acc[v] += (double)bv[u][c] * xs[u][c];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < kW; ++v) {
+        double tot = acc[v];
+#pragma unroll
+        for (int g = 1; g < GRPW; ++g) tot += __shfl(acc[v], lane + 9 * g < kWave ? lane + 9 * g : lane, kWave);
+        out[v] = tot;
+    }
+}
+
 // Sf: both triangles of the RCS by rows (FP64, or rounded to FP32), from the
 // upper blocks
 template <typename TS>
@@ -259,13 +306,14 @@ __global__ __launch_bounds__(BS) void k_spmm_W(int n_rows, const int32_t* __rest
                                                const int32_t* __restrict__ sf_col, const TS* __restrict__ Sf,
                                                const double* __restrict__ W, double* __restrict__ SW) {
     const int lane = threadIdx.x % kWave;
-    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB)
-        for (int v = 0; v < kW; ++v) {
-            const int a = sf_ptr[row];
-            const double y = row_gather<TS, 0>(a, sf_ptr[row + 1] - a, sf_col, Sf, W + v * 9, nullptr, 0.0,
-                                                   kW * 9);
-            if (lane < 9) SW[(int64_t)row * kW * 9 + v * 9 + lane] = y;
-        }
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const int a = sf_ptr[row];
+        double y[kW];
+        row_gather_w<TS>(a, sf_ptr[row + 1] - a, sf_col, Sf, W, y);
+        if (lane < 9)
+#pragma unroll
+            for (int v = 0; v < kW; ++v) SW[(int64_t)row * kW * 9 + v * 9 + lane] = y[v];
+    }
 }
 
 // partials of E = W^T S W (49 per block)
