@@ -32,15 +32,15 @@ __device__ __forceinline__ void rot_coeffs(double s, double& a, double& b, doubl
         as = -1.0 / 6 + s * (2.0 / 120 + s * (-3.0 / 5040 + s * (4.0 / 362880 + s * (-5.0 / 39916800 + s * (6.0 / 6227020800.0 + s * (-7.0 / 1307674368000.0))))));
         bs = -1.0 / 24 + s * (2.0 / 720 + s * (-3.0 / 40320 + s * (4.0 / 3628800 + s * (-5.0 / 479001600 + s * (6.0 / 87178291200.0 + s * (-7.0 / 20922789888000.0))))));
     } else {
-        double th = sqrt(s);
+        const double th = sqrt(s), it = 1.0 / th, is = it * it;   // one division
         double sn, cs;
         sincos(th, &sn, &cs);
-        double sh = sin(0.5 * th);
-        double omc = 2.0 * sh * sh;   // 1 - cos th without cancellation
-        a = sn / th;
-        b = omc / s;
-        as = (th * cs - sn) / (2.0 * s * th);
-        bs = (th * sn - 2.0 * omc) / (2.0 * s * s);
+        const double sh = sin(0.5 * th);
+        const double omc = 2.0 * sh * sh;   // 1 - cos th without cancellation
+        a = sn * it;
+        b = omc * is;
+        as = (th * cs - sn) * (0.5 * is * it);
+        bs = (th * sn - 2.0 * omc) * (0.5 * is * is);
     }
 }
 

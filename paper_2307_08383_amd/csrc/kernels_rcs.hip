@@ -39,15 +39,36 @@ __device__ __forceinline__ Track chunk_track(bool act, int p, int lane, int len)
     return t;
 }
 
-// K = J_p L^-T from the point terms r = (L00, L10, L11, L20, L21, L22, lhat):
-// row r of K solves L y = J_p[r]^T.
+// Point terms from the track sums s = (V: 00 01 02 11 12 22, l_p): the
+// Cholesky factor of V* = V + lambda diag(V), lhat = L^-1 l_p and the
+// reciprocals of L's diagonal, r = (L00, L10, L11, L20, L21, L22, lhat,
+// 1/L00, 1/L11, 1/L22).  Returns false if V* is not positive definite.
+constexpr int kPT = 12;   // point terms shared with a track's lanes
+__device__ __forceinline__ bool point_terms(const double* s, double lambda, double* r) {
+    const double V00 = s[0] * (1.0 + lambda), V11 = s[3] * (1.0 + lambda), V22 = s[5] * (1.0 + lambda);
+    const double L00 = sqrt(V00), i00 = 1.0 / L00;
+    const double L10 = s[1] * i00, L20 = s[2] * i00;
+    const double d1 = V11 - L10 * L10;
+    const double L11 = sqrt(d1), i11 = 1.0 / L11;
+    const double L21 = (s[4] - L20 * L10) * i11;
+    const double d2 = V22 - L20 * L20 - L21 * L21;
+    const double L22 = sqrt(d2), i22 = 1.0 / L22;
+    const double y0 = s[6] * i00;
+    const double y1 = (s[7] - L10 * y0) * i11;
+    const double y2 = (s[8] - L20 * y0 - L21 * y1) * i22;
+    r[0] = L00; r[1] = L10; r[2] = L11; r[3] = L20; r[4] = L21; r[5] = L22;
+    r[6] = y0; r[7] = y1; r[8] = y2; r[9] = i00; r[10] = i11; r[11] = i22;
+    return V00 > 0.0 && d1 > 0.0 && d2 > 0.0;
+}
+
+// K = J_p L^-T from the point terms r: row r of K solves L y = J_p[r]^T.
 __device__ __forceinline__ void point_K(const double* r, const double* jp, double* K) {
-    const double L00 = r[0], L10 = r[1], L11 = r[2], L20 = r[3], L21 = r[4], L22 = r[5];
+    const double L10 = r[1], L20 = r[3], L21 = r[4], i00 = r[9], i11 = r[10], i22 = r[11];
 #pragma unroll
     for (int rr = 0; rr < 2; ++rr) {
-        const double y0 = jp[3 * rr] / L00;
-        const double y1 = (jp[3 * rr + 1] - L10 * y0) / L11;
-        const double y2 = (jp[3 * rr + 2] - L20 * y0 - L21 * y1) / L22;
+        const double y0 = jp[3 * rr] * i00;
+        const double y1 = (jp[3 * rr + 1] - L10 * y0) * i11;
+        const double y2 = (jp[3 * rr + 2] - L20 * y0 - L21 * y1) * i22;
         K[3 * rr] = y0; K[3 * rr + 1] = y1; K[3 * rr + 2] = y2;
     }
 }
@@ -78,8 +99,7 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
                                               T* __restrict__ R, const T* __restrict__ Jp, const double* __restrict__ e,
                                               double lambda, double* __restrict__ ptL, const int32_t* __restrict__ obs_rpos,
                                               double* __restrict__ ebar, int* __restrict__ flags) {
-    __shared__ double sP[WPB][kWave][9];
-    __shared__ double sR[WPB][kWave][9];
+    __shared__ double sP[WPB][kWave][kPT];   // track sums, then the head's point terms
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int chunk = blockIdx.x * WPB + wv;
     int k0 = 0, k1 = 0;
@@ -113,31 +133,20 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
         for (int q = 0; q < tl; ++q)
 #pragma unroll
             for (int m = 0; m < 9; ++m) s[m] += sP[wv][lane + q][m];
-        // V* = V + lambda diag(V) = L L^T
-        const double V00 = s[0] * (1.0 + lambda), V11 = s[3] * (1.0 + lambda), V22 = s[5] * (1.0 + lambda);
-        const double L00 = sqrt(V00);
-        const double L10 = s[1] / L00, L20 = s[2] / L00;
-        const double d1 = V11 - L10 * L10;
-        const double L11 = sqrt(d1);
-        const double L21 = (s[4] - L20 * L10) / L11;
-        const double d2 = V22 - L20 * L20 - L21 * L21;
-        const double L22 = sqrt(d2);
-        if (!(V00 > 0.0) || !(d1 > 0.0) || !(d2 > 0.0)) flags[0] = 1;
-        const double y0 = s[6] / L00;
-        const double y1 = (s[7] - L10 * y0) / L11;
-        const double y2 = (s[8] - L20 * y0 - L21 * y1) / L22;
-        const double r[9] = {L00, L10, L11, L20, L21, L22, y0, y1, y2};
+        double r[kPT];
+        if (!point_terms(s, lambda, r)) flags[0] = 1;
+        // the head's own row is read by no other lane: it holds the track's terms now
 #pragma unroll
-        for (int m = 0; m < 9; ++m) sR[wv][lane][m] = r[m];
+        for (int m = 0; m < kPT; ++m) sP[wv][lane][m] = r[m];
 #pragma unroll
         for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
     }
     __syncthreads();
     if (act) {
         double K[6];
-        point_K(sR[wv][head], jp, K);
+        point_K(sP[wv][head], jp, K);
         store6(R + (int64_t)k * kRec + 18, K);
-        store_ebar<T>(sR[wv][head], K, ek.x, ek.y, obs_rpos[k], ebar);
+        store_ebar<T>(sP[wv][head], K, ek.x, ek.y, obs_rpos[k], ebar);
     }
 }
 
@@ -150,7 +159,7 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
 // whole (J_c, then K) by its lane, with no partial-record writes.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(BS) void k_linpoint(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
+__device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
                                                  const int32_t* __restrict__ obs_cam,
                                                  const int32_t* __restrict__ obs_pt,
                                                  const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
@@ -159,8 +168,7 @@ __global__ __launch_bounds__(BS) void k_linpoint(int n_chunk, const int32_t* __r
                                                  double* __restrict__ e, double* __restrict__ ptL,
                                                  const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
-    __shared__ double sP[WPB][kWave][9];
-    __shared__ double sR[WPB][kWave][9];
+    __shared__ double sP[WPB][kWave][kPT];   // track sums, then the head's point terms
     __shared__ double sh[WPB];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int chunk = blockIdx.x * WPB + wv;
@@ -206,32 +214,47 @@ __global__ __launch_bounds__(BS) void k_linpoint(int n_chunk, const int32_t* __r
         for (int q = 0; q < tl; ++q)
 #pragma unroll
             for (int m = 0; m < 9; ++m) s[m] += sP[wv][lane + q][m];
-        const double V00 = s[0] * (1.0 + lambda), V11 = s[3] * (1.0 + lambda), V22 = s[5] * (1.0 + lambda);
-        const double L00 = sqrt(V00);
-        const double L10 = s[1] / L00, L20 = s[2] / L00;
-        const double d1 = V11 - L10 * L10;
-        const double L11 = sqrt(d1);
-        const double L21 = (s[4] - L20 * L10) / L11;
-        const double d2 = V22 - L20 * L20 - L21 * L21;
-        const double L22 = sqrt(d2);
-        if (!(V00 > 0.0) || !(d1 > 0.0) || !(d2 > 0.0)) flags[0] = 1;
-        const double y0 = s[6] / L00;
-        const double y1 = (s[7] - L10 * y0) / L11;
-        const double y2 = (s[8] - L20 * y0 - L21 * y1) / L22;
-        const double r[9] = {L00, L10, L11, L20, L21, L22, y0, y1, y2};
+        double r[kPT];
+        if (!point_terms(s, lambda, r)) flags[0] = 1;
+        // the head's own row is read by no other lane: it holds the track's terms now
 #pragma unroll
-        for (int m = 0; m < 9; ++m) sR[wv][lane][m] = r[m];
+        for (int m = 0; m < kPT; ++m) sP[wv][lane][m] = r[m];
 #pragma unroll
         for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
     }
     __syncthreads();
     if (act) {
         double K[6];
-        point_K(sR[wv][head], jp, K);
+        point_K(sP[wv][head], jp, K);
         store_jc(R + (int64_t)k * kRec, jc);
         store6(R + (int64_t)k * kRec + 18, K);
-        store_ebar<T>(sR[wv][head], K, eu, ev, obs_rpos[k], ebar);
+        store_ebar<T>(sP[wv][head], K, eu, ev, obs_rpos[k], ebar);
     }
+}
+
+// FP32 records: 96 registers allow five waves per SIMD without spilling;
+// the FP64 build keeps the default (it would spill).
+__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(5))) void k_linpoint_f(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
+                                                 const int32_t* __restrict__ obs_cam,
+                                                 const int32_t* __restrict__ obs_pt,
+                                                 const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
+                                                 const double* __restrict__ cams, const double* __restrict__ pts,
+                                                 double lambda, float* __restrict__ R, float* __restrict__ Jp_out,
+                                                 double* __restrict__ e, double* __restrict__ ptL,
+                                                 const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
+                                                 double* __restrict__ part, int* __restrict__ flags) {
+    linpoint<float>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, Jp_out, e, ptL, obs_rpos, ebar, part, flags);
+}
+__global__ __launch_bounds__(BS) void k_linpoint_d(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
+                                                 const int32_t* __restrict__ obs_cam,
+                                                 const int32_t* __restrict__ obs_pt,
+                                                 const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
+                                                 const double* __restrict__ cams, const double* __restrict__ pts,
+                                                 double lambda, double* __restrict__ R, double* __restrict__ Jp_out,
+                                                 double* __restrict__ e, double* __restrict__ ptL,
+                                                 const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
+                                                 double* __restrict__ part, int* __restrict__ flags) {
+    linpoint<double>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, Jp_out, e, ptL, obs_rpos, ebar, part, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,11 +592,11 @@ void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, do
     if (nb == 0) return;
     const int n = (int)c->n_obs;
     if (c->precision == BA_MIXED)
-        k_linpoint<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
+        k_linpoint_f<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
                                                     c->obs_uv, cams, pts, lambda, (float*)c->R, (float*)c->Jp, c->e,
                                                     c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
     else
-        k_linpoint<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
+        k_linpoint_d<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
                                                      c->obs_uv, cams, pts, lambda, (double*)c->R, (double*)c->Jp,
                                                      c->e, c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
     launch_reduce(c->part, nb, c->scal + 0, c->stream);
