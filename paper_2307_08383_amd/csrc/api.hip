@@ -263,10 +263,59 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     // write partial blocks, summed afterwards in chunk order.  The cap is a
     // quarter of the average work of one of the lane groups the chip holds at
     // once (256 CUs x 16 waves x 4 groups), at least 8 steps of 4 couples.
-    // A wave runs until the longest of its four units ends, so inside windows
-    // of 32 rows the units are ordered longest first (neighbouring units have
-    // similar lengths, and the rows a CU works on stay close together); the
-    // waves are then cut into 8 contiguous ranges of equal work, one per XCD.
+    // A wave runs until the longest of its four units ends, so inside each
+    // camera cluster (below) the units are ordered longest first (neighbouring
+    // units have similar lengths); the waves are then cut into 8 contiguous
+    // ranges of equal work, one per XCD.
+    // The order of the units follows camera clusters: breadth-first growth
+    // over the co-visibility graph from the lowest unassigned row, up to
+    // about 4 MB of records per cluster (an XCD's L2; 1, 2, 16 and 64 MB
+    // measured slower).  A point's track is read by the rows
+    // of each of its cameras; inside a compact cluster those rows run close
+    // together on one XCD, so the track's records come from L2 / MALL instead
+    // of HBM after the first of them.
+    std::vector<int32_t> clus(nr, -1);
+    {
+        std::vector<int32_t> adj_ptr(nr + 1, 0), adj;
+        for (int32_t r = 0; r < nr; ++r)
+            for (int64_t kb = row_ptr[r] + 1; kb < row_ptr[r + 1]; ++kb) {
+                adj_ptr[r + 1]++;
+                adj_ptr[col_idx[kb] + 1]++;
+            }
+        for (int32_t r = 0; r < nr; ++r) adj_ptr[r + 1] += adj_ptr[r];
+        adj.resize(adj_ptr[nr]);
+        {
+            std::vector<int32_t> fill(adj_ptr.begin(), adj_ptr.end() - 1);
+            for (int32_t r = 0; r < nr; ++r)
+                for (int64_t kb = row_ptr[r] + 1; kb < row_ptr[r + 1]; ++kb) {
+                    adj[fill[r]++] = col_idx[kb];
+                    adj[fill[col_idx[kb]]++] = r;
+                }
+        }
+        std::vector<int64_t> row_obs(nr, 0);
+        for (int64_t k = 0; k < n; ++k)
+            if (orow[k] >= 0) row_obs[orow[k]]++;
+        const double rec = (double)kRec * (c->precision == BA_MIXED ? sizeof(float) : sizeof(double));
+        const double budget = 4.0 * (1 << 20);   // one XCD's L2
+        std::vector<int32_t> queue;
+        int32_t n_cl = 0;
+        for (int32_t s0 = 0; s0 < nr; ++s0) {
+            if (clus[s0] >= 0) continue;
+            queue.assign(1, s0);
+            clus[s0] = n_cl;
+            double bytes = 0.0;
+            for (size_t h = 0; h < queue.size() && bytes < budget; ++h) {
+                const int32_t r = queue[h];
+                bytes += (double)row_obs[r] * rec;
+                for (int32_t e = adj_ptr[r]; e < adj_ptr[r + 1] && bytes < budget; ++e)
+                    if (clus[adj[e]] < 0) {
+                        clus[adj[e]] = n_cl;
+                        queue.push_back(adj[e]);
+                    }
+            }
+            ++n_cl;
+        }
+    }
     std::vector<int32_t> unit_rng, unit_dst, lseg_blk, lseg_ptr{0};
     {
         struct Unit { int32_t win, t0, t1, dst; };
@@ -277,7 +326,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         const int64_t cap = 4 * std::max<int64_t>(8, steps / (4 * groups));
         int32_t n_p = 0;
         for (int32_t sg = 0; sg < c->n_offseg; ++sg) {
-            const int32_t a = pair_ptr[sg], b = pair_ptr[sg + 1], w = seg_row[sg] / 32;
+            const int32_t a = pair_ptr[sg], b = pair_ptr[sg + 1], w = clus[seg_row[sg]];
             if (b - a <= cap) {
                 units.push_back({w, a, b, off_blk[sg]});
                 continue;
