@@ -12,6 +12,11 @@ second through linearize + formation, device time of the timed steps);
 ms_per_step = LM-iteration wall time; the roofline entry covers the
 dominant formation kernel (the camera-pair stage); cpu_baseline is the C
 oracle on the host cores for a bounded sample of the same workload.
+lm_comparison: LM runs of the preconditioner / precision variants on the
+same scene; lm_comparison_partition: the key variants on the one-GPU share
+of the 60,000-camera partition (25M points, ~100M observations, mixed
+precision and the learned preconditioner against plain FP64 block-Jacobi,
+10 LM iterations).
 """
 from __future__ import annotations
 
@@ -50,6 +55,8 @@ def parse():
                     choices=["block_jacobi", "fsai", "learned", "learned_fsai"],
                     help="preconditioner of the timed LM steps")
     ap.add_argument("--deflate", action="store_true", help="gauge-deflated PCG in the timed LM steps")
+    ap.add_argument("--no-partition-compare", action="store_true",
+                    help="skip the LM comparison on the 60,000-camera partition after the default run")
     ap.add_argument("--solver-fp32", action="store_true",
                     help="PCG products on an FP32 copy of S in the timed LM steps")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -148,6 +155,74 @@ def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=
                 pcg_ms_mean=float(np.mean([i["ms_pcg"] for i in infos])))
 
 
+def device_observations(scene, dev):
+    """Observations on the device: indices, pixels = projection of the true
+    parameters + the scene's noise (by the library's own projection), fixed
+    camera flags (or None)."""
+    import torch
+    from paper_2307_08383_amd import ba
+    T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    obs_cam = T(scene.obs_cam, torch.int32)
+    obs_pt = T(scene.obs_pt, torch.int32)
+    uv = ba.ba_project(T(scene.cams_true, torch.float64), T(scene.pts_true, torch.float64),
+                       obs_cam, obs_pt, T(scene.noise, torch.float64))
+    cf = T(scene.cam_fixed, torch.uint8) if scene.cam_fixed.any() else None
+    return obs_cam, obs_pt, uv, cf
+
+
+# variants of the LM comparison: name, precision, preconditioner, deflation
+# (the "_s32_" ones run the solver's products on an FP32 copy of S)
+COMPARE_VARIANTS = [
+    ("fp64_block_jacobi", "fp64", "block_jacobi", False),
+    ("mixed_block_jacobi_deflated", "mixed", "block_jacobi", True),
+    ("mixed_fsai", "mixed", "fsai", False),
+    ("mixed_fsai_deflated", "mixed", "fsai", True),
+    ("mixed_learned_block_deflated", "mixed", "learned", True),
+    ("mixed_learned_fsai", "mixed", "learned_fsai", False),
+    ("mixed_learned_fsai_deflated", "mixed", "learned_fsai", True),
+    ("mixed_s32_block_jacobi_deflated", "mixed", "block_jacobi", True),
+    ("mixed_s32_fsai_deflated", "mixed", "fsai", True),
+    ("mixed_s32_learned_fsai_deflated", "mixed", "learned_fsai", True)]
+# the subset run on the 60,000-camera partition (the one-GPU share the
+# learned-vs-block-Jacobi comparison is defined on) after the default run
+PARTITION_VARIANTS = ["fp64_block_jacobi", "mixed_block_jacobi_deflated", "mixed_fsai_deflated",
+                      "mixed_learned_fsai_deflated", "mixed_s32_block_jacobi_deflated",
+                      "mixed_s32_learned_fsai_deflated"]
+
+
+def lm_comparison(scene, obs, names, lm_iters):
+    """Each named variant from the scene's start for lm_iters LM iterations;
+    ms per iteration, final FP64 cost and the ratios to FP64 block-Jacobi."""
+    from paper_2307_08383_amd import ba
+    from paper_2307_08383_amd import learned_precond as lp
+
+    def weights(path):
+        return (lp.load_weights(path), os.path.basename(path)) if os.path.exists(path) else \
+            (lp.init_params(0), "untrained (zero head: block-Jacobi)")
+    wb, wb_name = weights(lp.DEFAULT_WEIGHTS)
+    wf, wf_name = weights(lp.DEFAULT_FSAI_WEIGHTS)
+    pre_of = {"block_jacobi": ba.BA_PRECOND_BLOCK_JACOBI, "fsai": ba.BA_PRECOND_FSAI,
+              "learned": ba.BA_PRECOND_LEARNED, "learned_fsai": ba.BA_PRECOND_LEARNED_FSAI}
+    w_of = {"learned": wb, "learned_fsai": wf}
+    runs = {}
+    for name, precision, precond, defl in COMPARE_VARIANTS:
+        if name not in names and name != "fp64_block_jacobi":
+            continue
+        prec = ba.BA_MIXED if precision == "mixed" else ba.BA_FP64
+        runs[name] = lm_run(scene, obs, prec, pre_of[precond], lm_iters, w_of.get(precond), deflate=defl,
+                            solver_fp32="_s32_" in name)
+        progress(f"LM comparison {scene.name} {name}: {runs[name]['ms_per_iter']:.2f} ms per iteration")
+    base = runs["fp64_block_jacobi"]
+    return {
+        "scene": scene.name, "n_obs": scene.n_obs, "iterations": lm_iters,
+        **runs,
+        "learned_weights": {"block": wb_name, "fsai": wf_name},
+        "speedup_vs_fp64_block_jacobi": {k: base["ms_per_iter"] / v["ms_per_iter"] for k, v in runs.items()},
+        "final_cost_rel_diff_vs_fp64_block_jacobi": {
+            k: abs(v["final_cost"] - base["final_cost"]) / base["final_cost"] for k, v in runs.items()},
+    }
+
+
 def cpu_baseline(scene, n_form):
     from oracle import oracle as orc
     nt = orc.default_threads()
@@ -176,12 +251,8 @@ def main():
     scene = build_scene(args.workload)
     progress(f"scene {scene.name}: {scene.n_obs} observations")
     T = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    obs_cam = T(scene.obs_cam, torch.int32)
-    obs_pt = T(scene.obs_pt, torch.int32)
-    uv = ba.ba_project(T(scene.cams_true, torch.float64), T(scene.pts_true, torch.float64),
-                       obs_cam, obs_pt, T(scene.noise, torch.float64))
+    obs_cam, obs_pt, uv, cf = device_observations(scene, dev)
     prec = ba.BA_MIXED if args.precision == "mixed" else ba.BA_FP64
-    cf = T(scene.cam_fixed, torch.uint8) if scene.cam_fixed.any() else None
     ctx = ba.ba_create(scene.n_cams, scene.n_pts, obs_cam, obs_pt, uv, cf, precision=prec)
     sizes = ba.ba_get_sizes(ctx)
     progress(f"context created: {sizes['n_blk']} blocks, {sizes['n_pairs']} observation couples")
@@ -258,43 +329,16 @@ def main():
         ba.ba_gnn_destroy(net)
     ba.ba_destroy(ctx)
     if not args.no_compare:
-        from paper_2307_08383_amd import learned_precond as lp
-
-        def weights(path):
-            return (lp.load_weights(path), os.path.basename(path)) if os.path.exists(path) else \
-                (lp.init_params(0), "untrained (zero head: block-Jacobi)")
-        wb, wb_name = weights(lp.DEFAULT_WEIGHTS)
-        wf, wf_name = weights(lp.DEFAULT_FSAI_WEIGHTS)
+        names = [v[0] for v in COMPARE_VARIANTS] if args.compare == "all" else args.compare.split(",")
         obs = (obs_cam, obs_pt, uv, cf)
-        runs = {}
-        lm_iters = args.lm_iters or scene.lm_iterations
-        variants = [
-                ("fp64_block_jacobi", ba.BA_FP64, ba.BA_PRECOND_BLOCK_JACOBI, False, None),
-                ("mixed_block_jacobi_deflated", ba.BA_MIXED, ba.BA_PRECOND_BLOCK_JACOBI, True, None),
-                ("mixed_fsai", ba.BA_MIXED, ba.BA_PRECOND_FSAI, False, None),
-                ("mixed_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_FSAI, True, None),
-                ("mixed_learned_block_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED, True, wb),
-                ("mixed_learned_fsai", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, False, wf),
-                ("mixed_learned_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, True, wf),
-                # the same with the solver's products on an FP32 copy of S
-                ("mixed_s32_block_jacobi_deflated", ba.BA_MIXED, ba.BA_PRECOND_BLOCK_JACOBI, True, None),
-                ("mixed_s32_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_FSAI, True, None),
-                ("mixed_s32_learned_fsai_deflated", ba.BA_MIXED, ba.BA_PRECOND_LEARNED_FSAI, True, wf)]
-        keep = None if args.compare == "all" else set(args.compare.split(","))
-        for name, prec, pre, defl, w in variants:
-            if keep is not None and name not in keep and name != "fp64_block_jacobi":
-                continue
-            runs[name] = lm_run(scene, obs, prec, pre, lm_iters, w, deflate=defl, solver_fp32="_s32_" in name)
-            progress(f"LM comparison {name}: {runs[name]['ms_per_iter']:.2f} ms per iteration")
-        base = runs["fp64_block_jacobi"]
-        out["lm_comparison"] = {
-            "iterations": lm_iters,
-            **runs,
-            "learned_weights": {"block": wb_name, "fsai": wf_name},
-            "speedup_vs_fp64_block_jacobi": {k: base["ms_per_iter"] / v["ms_per_iter"] for k, v in runs.items()},
-            "final_cost_rel_diff_vs_fp64_block_jacobi": {
-                k: abs(v["final_cost"] - base["final_cost"]) / base["final_cost"] for k, v in runs.items()},
-        }
+        out["lm_comparison"] = lm_comparison(scene, obs, names, args.lm_iters or scene.lm_iterations)
+        if args.workload != "partition" and not args.no_partition_compare:
+            pscene = build_scene("partition")
+            progress(f"scene {pscene.name}: {pscene.n_obs} observations")
+            pobs = device_observations(pscene, dev)
+            out["lm_comparison_partition"] = lm_comparison(pscene, pobs, PARTITION_VARIANTS, pscene.lm_iterations)
+            del pobs
+            torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(scene, args.cpu_sample_formations)
     print(json.dumps(out), flush=True)
