@@ -223,6 +223,55 @@ def lm_comparison(scene, obs, names, lm_iters):
     }
 
 
+def formation_roofline(scene, sizes, precision, t_form_ms):
+    """Algorithmic HBM bytes of one formation (linearize + point stage, pair
+    stage, diagonal stage; the per-unit counts of the kernels' design) over
+    its device time."""
+    es = 4 if precision == "mixed" else 8
+    n, npt = scene.n_obs, scene.n_pts
+    free_obs = int((~scene.cam_fixed.astype(bool))[scene.obs_cam].sum())
+    lin = n * (28 + 24 * es + 6 * es + 16 + 16) + npt * (24 + 72)
+    pair = pair_stage_bytes(sizes["n_pairs"], sizes["n_blk"] - sizes["n_rows"], precision)
+    diag = free_obs * (24 * es + 16 + 4) + sizes["n_rows"] * 1368
+    total = lin + pair + diag
+    achieved = total / (t_form_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "bytes_per_obs": total / n, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "stages": {"linearize_point": lin, "pair": pair, "diag": diag}}
+
+
+def copy_peak_gbs(dev, mib=2048, reps=5):
+    """Measured streaming bandwidth: the best of `reps` device copies of
+    `mib` MiB (bytes read + written per copy), timed with events."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * mib * (1 << 20) / (best * 1e-3) / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, n_form):
     from oracle import oracle as orc
     nt = orc.default_threads()
@@ -233,9 +282,16 @@ def cpu_baseline(scene, n_form):
         P.linearize(scene.cams_init, scene.pts_init)
         P.form_rcs(1e-4)
     dt = time.perf_counter() - t0
+    # one thread, one formation
+    P1 = orc.Problem.from_scene(scene, uv, n_threads=1)
+    t1 = time.perf_counter()
+    P1.linearize(scene.cams_init, scene.pts_init)
+    P1.form_rcs(1e-4)
+    dt1 = time.perf_counter() - t1
     return {"value": scene.n_obs * n_form / dt, "unit": "obs/s", "cores": nt, "kind": "oracle",
             "sample": f"the full scene ({scene.n_obs} observations), {n_form} formations "
-                      f"(linearize + RCS formation), {dt:.2f} s"}
+                      f"(linearize + RCS formation), {dt:.2f} s",
+            "single_thread_value": scene.n_obs / dt1, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -323,7 +379,12 @@ def main():
         "roofline": {"kernel": "k_offdiag (camera-pair stage)", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": alg},
+        "formation_roofline": formation_roofline(scene, sizes, args.precision, t_form),
     }
+    cp = copy_peak_gbs(dev)
+    out["roofline"]["copy_peak"] = cp
+    out["roofline"]["frac_of_copy_peak"] = achieved / cp
+    out["formation_roofline"]["frac_of_copy_peak"] = out["formation_roofline"]["achieved"] / cp
     if net is not None:
         ba.ba_set_preconditioner_net(ctx, None)
         ba.ba_gnn_destroy(net)

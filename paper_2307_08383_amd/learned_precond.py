@@ -45,6 +45,7 @@ KINDS = {
     "aerial_full": dict(nx=50, ny=40, n_pts=400_000),
     "partition": ("partition", TRAIN_PARTITION),
     "partition_mid": ("partition", dict(nx=60, ny=50, n_pts=1_250_000)),
+    "partition_big": ("partition", dict(nx=120, ny=100, n_pts=5_000_000)),
 }
 
 
