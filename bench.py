@@ -59,6 +59,8 @@ def parse():
                     help="skip the LM comparison on the 60,000-camera partition after the default run")
     ap.add_argument("--solver-fp32", action="store_true",
                     help="PCG products on an FP32 copy of S in the timed LM steps")
+    ap.add_argument("--product", default="auto", choices=["auto", "full", "upper"],
+                    help="layout of the PCG product S z in the timed LM steps and the comparisons")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first, so that hardware "
                          "byte counters can be scaled against a kernel of known traffic")
@@ -102,7 +104,8 @@ def traffic_from_profile(kernel_src_hash, kernel):
     return None
 
 
-def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=False, solver_fp32=False):
+def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=False, solver_fp32=False,
+           product=0):
     """LM run from the scene's start; returns per-iteration means and the
     final cost (FP64 cost of the last accepted iterate)."""
     import torch
@@ -128,7 +131,7 @@ def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=
         ba.ba_form_rcs(ctx, 1e-4)
         dx = torch.empty((ba.ba_get_sizes(ctx)["n_rows"], 9), dtype=torch.float64, device=dev)
         ba.ba_pcg_solve(ctx, dx, tol=scene.pcg_tol, max_iter=1, precond=precond, deflate=deflate,
-                        solver_fp32=solver_fp32)
+                        solver_fp32=solver_fp32, product=product)
         torch.cuda.synchronize()
         setup_ms = 1e3 * (time.perf_counter() - t_s)
     st = ba.new_lm_state(1e-4)
@@ -137,7 +140,7 @@ def lm_run(scene, obs, precision, precond, iters, learned_weights=None, deflate=
     t0 = time.perf_counter()
     for _ in range(iters):
         infos.append(ba.ba_lm_step(ctx, cams, pts, st, pcg_tol=scene.pcg_tol, precond=precond, deflate=deflate,
-                                   solver_fp32=solver_fp32))
+                                   solver_fp32=solver_fp32, product=product))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     # FP64 cost of the final parameters (the mixed path evaluates cost in FP64 too)
@@ -172,6 +175,8 @@ def device_observations(scene, dev):
 
 # variants of the LM comparison: name, precision, preconditioner, deflation
 # (the "_s32_" ones run the solver's products on an FP32 copy of S)
+PRODUCTS = {"auto": 0, "full": 1, "upper": 2}   # BA_PRODUCT_*
+
 COMPARE_VARIANTS = [
     ("fp64_block_jacobi", "fp64", "block_jacobi", False),
     ("mixed_block_jacobi_deflated", "mixed", "block_jacobi", True),
@@ -190,7 +195,7 @@ PARTITION_VARIANTS = ["fp64_block_jacobi", "mixed_block_jacobi_deflated", "mixed
                       "mixed_s32_learned_fsai_deflated"]
 
 
-def lm_comparison(scene, obs, names, lm_iters):
+def lm_comparison(scene, obs, names, lm_iters, product=0):
     """Each named variant from the scene's start for lm_iters LM iterations;
     ms per iteration, final FP64 cost and the ratios to FP64 block-Jacobi."""
     from paper_2307_08383_amd import ba
@@ -210,7 +215,7 @@ def lm_comparison(scene, obs, names, lm_iters):
             continue
         prec = ba.BA_MIXED if precision == "mixed" else ba.BA_FP64
         runs[name] = lm_run(scene, obs, prec, pre_of[precond], lm_iters, w_of.get(precond), deflate=defl,
-                            solver_fp32="_s32_" in name)
+                            solver_fp32="_s32_" in name, product=product)
         progress(f"LM comparison {scene.name} {name}: {runs[name]['ms_per_iter']:.2f} ms per iteration")
     base = runs["fp64_block_jacobi"]
     return {
@@ -330,7 +335,8 @@ def main():
         net = ba.ba_gnn_create(learned_precond.load_weights(
             learned_precond.DEFAULT_FSAI_WEIGHTS if pre == ba.BA_PRECOND_LEARNED_FSAI else learned_precond.DEFAULT_WEIGHTS))
         ba.ba_set_preconditioner_net(ctx, net)
-    step_kw = dict(pcg_tol=scene.pcg_tol, precond=pre, deflate=args.deflate, solver_fp32=args.solver_fp32)
+    step_kw = dict(pcg_tol=scene.pcg_tol, precond=pre, deflate=args.deflate, solver_fp32=args.solver_fp32,
+                   product=PRODUCTS[args.product])
     for _ in range(args.warmup):
         ba.ba_lm_step(ctx, cams, pts, st, **step_kw)
     torch.cuda.synchronize()
@@ -366,7 +372,7 @@ def main():
                                f"{' (FP32 solver matrix)' if args.solver_fp32 else ''} "
                                f"PCG to rel {scene.pcg_tol:g}",
                    "n_cams": scene.n_cams, "n_pts": scene.n_pts, "n_obs": scene.n_obs,
-                   "n_blocks": sizes["n_blk"], "n_pairs": sizes["n_pairs"]},
+                   "n_blocks": sizes["n_blk"], "n_pairs": sizes["n_pairs"], "pcg_product": args.product},
         "lm_iteration_ms": ms_per_step,
         "formation_ms": t_form,
         "stages_ms": {"linearize": float(st_arr[:, 0][st_arr[:, 0] > 0].mean()) if (st_arr[:, 0] > 0).any() else 0.0,
@@ -392,12 +398,14 @@ def main():
     if not args.no_compare:
         names = [v[0] for v in COMPARE_VARIANTS] if args.compare == "all" else args.compare.split(",")
         obs = (obs_cam, obs_pt, uv, cf)
-        out["lm_comparison"] = lm_comparison(scene, obs, names, args.lm_iters or scene.lm_iterations)
+        out["lm_comparison"] = lm_comparison(scene, obs, names, args.lm_iters or scene.lm_iterations,
+                                             PRODUCTS[args.product])
         if args.workload != "partition" and not args.no_partition_compare:
             pscene = build_scene("partition")
             progress(f"scene {pscene.name}: {pscene.n_obs} observations")
             pobs = device_observations(pscene, dev)
-            out["lm_comparison_partition"] = lm_comparison(pscene, pobs, PARTITION_VARIANTS, pscene.lm_iterations)
+            out["lm_comparison_partition"] = lm_comparison(pscene, pobs, PARTITION_VARIANTS, pscene.lm_iterations,
+                                                           PRODUCTS[args.product])
             del pobs
             torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -114,7 +114,23 @@ typedef struct ba_pcg_opts {
                                    once from the FP64 RCS); vectors, scalar products and
                                    the stop test stay FP64.  PCG then solves the system of
                                    that rounded S (relative entry error <= 2^-24). */
+    int32_t product;            /* layout of the iteration's product S z (Sec. 6.2):
+                                   BA_PRODUCT_AUTO (0), _FULL or _UPPER, see below */
+    int32_t reserved;           /* 0 */
 } ba_pcg_opts;
+
+/* The product S z of a PCG iteration.  FULL: every block row of both
+ * triangles (a copy of S made after each formation) is gathered by its own
+ * wave, so each stored block is read twice.  UPPER: each stored upper block
+ * S_rs (s >= r) is read once; its wave forms S_rs z_s for row r and
+ * S_rs^T z_r for row s, the latter is written per block and a second kernel
+ * sums them per row in a fixed order (72 extra bytes written and read per
+ * block, against 648 (FP64) or 324 (FP32) bytes of a second block read).
+ * Both are deterministic; they differ only in the summation order.  AUTO
+ * takes UPPER when the copy of both triangles would exceed 256 MiB (about
+ * the GPU's last-level cache), FULL otherwise (one kernel less per
+ * iteration on small systems). */
+enum { BA_PRODUCT_AUTO = 0, BA_PRODUCT_FULL = 1, BA_PRODUCT_UPPER = 2 };
 
 typedef struct ba_pcg_info {
     int32_t iters;              /* CG iterations (matrix-vector products) done */
@@ -129,6 +145,13 @@ typedef struct ba_pcg_info {
  * BA_ERR_NOT_CONVERGED (dxc still valid) or BA_ERR_NOT_SPD as warnings/errors;
  * BA_ERR_STATE without a formed RCS. */
 ba_status ba_pcg_solve(ba_ctx* ctx, const ba_pcg_opts* opts, double* dxc, ba_pcg_info* info_host);
+
+/* Sec. 6.2: y = S x with the RCS formed last, computed as one product of a
+ * PCG iteration (layout `product`, BA_PRODUCT_*, and with solver_fp32 = 1
+ * the FP32 copy of S).  x, y: distinct device arrays [n_rows][9], owned by
+ * the caller.  Synchronises the context stream.  Errors: BA_ERR_STATE (no
+ * RCS), BA_ERR_INVALID_ARG (null or identical arrays, unknown layout). */
+ba_status ba_rcs_product(ba_ctx* ctx, const double* x, double* y, int32_t product, int32_t solver_fp32);
 
 /* Eq. (5): dxp = V*^-1 (l_p - sum_i W_ip^T dxc_i) for every point (device
  * [n_pts][3]) from the RCS formed last.  dxc: device [n_rows][9]. */
@@ -149,6 +172,7 @@ typedef struct ba_lm_opts {
     int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED or _FSAI */
     int32_t deflate;            /* 1: deflated PCG on the similarity gauge */
     int32_t solver_fp32;        /* 1: PCG products with an FP32 copy of S (see ba_pcg_opts) */
+    int32_t product;            /* BA_PRODUCT_AUTO, _FULL or _UPPER (see ba_pcg_opts) */
 } ba_lm_opts;
 
 typedef struct ba_lm_info {

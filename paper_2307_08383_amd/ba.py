@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libba.so")
 BA_OK, BA_ERR_INVALID_ARG, BA_ERR_STATE, BA_ERR_NOT_SPD, BA_ERR_NOT_CONVERGED, BA_ERR_OUT_OF_MEMORY, BA_ERR_DEVICE = range(7)
 BA_FP64, BA_MIXED = 0, 1
 BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED, BA_PRECOND_FSAI, BA_PRECOND_LEARNED_FSAI = 0, 1, 2, 3
+BA_PRODUCT_AUTO, BA_PRODUCT_FULL, BA_PRODUCT_UPPER = 0, 1, 2
 
 
 class ProblemDesc(C.Structure):
@@ -30,7 +31,8 @@ class ProblemDesc(C.Structure):
 
 class PcgOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32), ("x0", C.c_void_p),
-                ("deflate", C.c_int32), ("solver_fp32", C.c_int32)]
+                ("deflate", C.c_int32), ("solver_fp32", C.c_int32), ("product", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class PcgInfo(C.Structure):
@@ -43,7 +45,7 @@ class LMState(C.Structure):
 
 class LMOpts(C.Structure):
     _fields_ = [("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32), ("precond", C.c_int32),
-                ("deflate", C.c_int32), ("solver_fp32", C.c_int32)]
+                ("deflate", C.c_int32), ("solver_fp32", C.c_int32), ("product", C.c_int32)]
 
 
 class LMInfo(C.Structure):
@@ -68,6 +70,7 @@ SIGNATURES = {
     "ba_linearize": (C.c_int, [_vp, _vp, _vp, _dp]),
     "ba_form_rcs": (C.c_int, [_vp, C.c_double]),
     "ba_pcg_solve": (C.c_int, [_vp, C.POINTER(PcgOpts), _vp, C.POINTER(PcgInfo)]),
+    "ba_rcs_product": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.c_int32]),
     "ba_back_substitute": (C.c_int, [_vp, _vp, _vp]),
     "ba_lm_step": (C.c_int, [_vp, _vp, _vp, C.POINTER(LMState), C.POINTER(LMOpts), C.POINTER(LMInfo)]),
     "ba_project": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
@@ -175,13 +178,18 @@ def ba_form_rcs(ctx, lam):
 
 
 def ba_pcg_solve(ctx, dxc, tol=1e-6, max_iter=1000, precond=BA_PRECOND_BLOCK_JACOBI, x0=None, deflate=False,
-                 solver_fp32=False):
+                 solver_fp32=False, product=BA_PRODUCT_AUTO):
     o = PcgOpts(tol=tol, max_iter=max_iter, precond=precond, x0=_ptr(x0), deflate=int(bool(deflate)),
-                solver_fp32=int(bool(solver_fp32)))
+                solver_fp32=int(bool(solver_fp32)), product=int(product))
     info = PcgInfo()
     st = _check(lib().ba_pcg_solve(ctx, C.byref(o), _ptr(dxc), C.byref(info)), ctx,
                 allow=(BA_ERR_NOT_CONVERGED,))
     return dict(iters=info.iters, status=info.status, relres=info.relres, ms=info.ms, returned=st)
+
+
+def ba_rcs_product(ctx, x, y, product=BA_PRODUCT_AUTO, solver_fp32=False):
+    """y = S x (device [n_rows][9] tensors) as one PCG product would form it."""
+    _check(lib().ba_rcs_product(ctx, _ptr(x), _ptr(y), int(product), int(bool(solver_fp32))), ctx)
 
 
 def ba_back_substitute(ctx, dxc, dxp):
@@ -189,9 +197,9 @@ def ba_back_substitute(ctx, dxc, dxp):
 
 
 def ba_lm_step(ctx, cams, pts, state: LMState, pcg_tol=1e-6, pcg_max_iter=1000,
-               precond=BA_PRECOND_BLOCK_JACOBI, deflate=False, solver_fp32=False):
+               precond=BA_PRECOND_BLOCK_JACOBI, deflate=False, solver_fp32=False, product=BA_PRODUCT_AUTO):
     o = LMOpts(pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter, precond=precond, deflate=int(bool(deflate)),
-               solver_fp32=int(bool(solver_fp32)))
+               solver_fp32=int(bool(solver_fp32)), product=int(product))
     info = LMInfo()
     _check(lib().ba_lm_step(ctx, _ptr(cams), _ptr(pts), C.byref(state), C.byref(o), C.byref(info)), ctx)
     return {k: getattr(info, k) for k, _ in LMInfo._fields_}

@@ -11,7 +11,7 @@
 #include "gnn.hpp"
 
 namespace ba {
-void launch_spmv(ba_ctx* c, const double* x, double* y);
+void launch_product(ba_ctx* c, const double* x, double* y);
 }
 
 namespace {
@@ -54,9 +54,9 @@ void free_ctx(ba_ctx* c) {
     if (!c) return;
     void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->chunk_q, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
-                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->Sf32, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->obs_rpos, c->ebar, c->ptL, c->blk, c->rhs, c->Minv,
+                    c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->Sf32, c->Su32, c->lo_ptr, c->lo_blk, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->obs_rpos, c->ebar, c->ptL, c->blk, c->rhs, c->Minv,
                     c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
-                    c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
+                    c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.u, c->pcg.tb, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
                     c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
                     c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G};
@@ -387,6 +387,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     // both triangles by rows: the row's upper blocks S_rs (column s), then the
     // blocks (s, r), s < r, of its column, transposed (column s)
     std::vector<int32_t> sf_ptr(nr + 1, 0), sf_col, sf_src;
+    std::vector<int32_t> lo_ptr, lo_blk;   // upper blocks (s, r), s < r, of each column r
     {
         std::vector<int32_t> trn(nr, 0);
         for (int32_t sg = 0; sg < c->n_offseg; ++sg) trn[col_idx[off_blk[sg]]]++;
@@ -415,6 +416,8 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
             }
         }
         c->n_sf = sf_ptr[nr];
+        lo_ptr = std::move(tr_ptr);
+        lo_blk = std::move(tr_blk);
     }
     std::vector<int32_t> trip(2 * (size_t)ntr);
     for (int64_t m = 0; m < ntr; ++m) { trip[2 * m] = ta[m]; trip[2 * m + 1] = tb[m]; }
@@ -444,6 +447,8 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->sf_ptr, sf_ptr);
     upload(c, &c->sf_col, sf_col);
     upload(c, &c->sf_src, sf_src);
+    upload(c, &c->lo_ptr, lo_ptr);
+    upload(c, &c->lo_blk, lo_blk);
     BA_HIP_CHECK(hipStreamSynchronize(c->stream));
     c->h_row_ptr = std::move(row_ptr);
     c->h_col_idx = std::move(col_idx);
@@ -475,6 +480,8 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &P.q, (size_t)nr * 9);
     dalloc(c, &P.d, (size_t)nr * 9);
     dalloc(c, &P.t, (size_t)nr * 9);
+    dalloc(c, &P.u, (size_t)nr * 9);
+    dalloc(c, &P.tb, (size_t)c->n_blk * 9);
     dalloc(c, &P.pA, 1024);
     dalloc(c, &P.pR, 2 * 9 * 1024);
     dalloc(c, &P.W, (size_t)nr * 63);
@@ -534,16 +541,21 @@ ba_status form_rcs_async(ba_ctx* c, double lambda, bool point_done = false) {
     c->have_rcs = true;
     c->sf_ready = false;
     c->sf32_ready = false;
+    c->su32_ready = false;
     c->fs.ready = false;
     c->defl_ready = false;
     c->lambda = lambda;
     return BA_OK;
 }
 
-// selects the S copy of the next solve (allocating the FP32 one on first use)
-void select_solver_matrix(ba_ctx* c, int fp32) {
+// selects the S copy and the product layout of the next solve (allocating
+// the FP32 copies on first use)
+void select_solver_matrix(ba_ctx* c, int fp32, int product) {
     c->s32 = fp32 ? 1 : 0;
+    const double full_bytes = (double)c->n_sf * 81 * (c->s32 ? sizeof(float) : sizeof(double));
+    c->upper = (product == BA_PRODUCT_UPPER || (product == BA_PRODUCT_AUTO && full_bytes > 256.0 * (1 << 20))) ? 1 : 0;
     if (c->s32 && !c->Sf32) dalloc(c, &c->Sf32, (size_t)std::max<int64_t>(c->n_sf, 1) * 81);
+    if (c->upper && c->s32 && !c->Su32) dalloc(c, &c->Su32, (size_t)c->n_blk * 81);
 }
 
 void prepare_defl(ba_ctx* c) {
@@ -826,6 +838,10 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
     const int max_iter = o ? o->max_iter : 1000;
     const int pre = o ? o->precond : BA_PRECOND_BLOCK_JACOBI;
     if (!(tol >= 0.0) || max_iter < 0) { c->err = "tol must be >= 0 and max_iter >= 0"; return BA_ERR_INVALID_ARG; }
+    if (o && (o->product < BA_PRODUCT_AUTO || o->product > BA_PRODUCT_UPPER)) {
+        c->err = "unknown product layout";
+        return BA_ERR_INVALID_ARG;
+    }
     if ((pre == BA_PRECOND_LEARNED || pre == BA_PRECOND_LEARNED_FSAI) && !c->learned_ready) {
         c->err = "no learned preconditioner set";
         return BA_ERR_STATE;
@@ -842,7 +858,7 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
         if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
         if (pre == BA_PRECOND_LEARNED_FSAI && c->n_rows > 0) prepare_learned_fsai(c);
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
-        select_solver_matrix(c, o ? o->solver_fp32 : 0);
+        select_solver_matrix(c, o ? o->solver_fp32 : 0, o ? o->product : BA_PRODUCT_AUTO);
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(c->ev[6], c->stream));
         ba_status s = BA_OK;
@@ -860,6 +876,20 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
         if (s == BA_ERR_NOT_SPD) c->err = "d^T S d <= 0 in PCG";
         if (s == BA_ERR_NOT_CONVERGED) c->err = "PCG reached max_iter";
         return s;
+    });
+}
+
+ba_status ba_rcs_product(ba_ctx* c, const double* x, double* y, int32_t product, int32_t solver_fp32) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!c->have_rcs) { c->err = "ba_rcs_product needs a formed RCS"; return BA_ERR_STATE; }
+    if (!x || !y || x == y) { c->err = "x and y must be distinct device arrays"; return BA_ERR_INVALID_ARG; }
+    if (product < BA_PRODUCT_AUTO || product > BA_PRODUCT_UPPER) { c->err = "unknown product layout"; return BA_ERR_INVALID_ARG; }
+    return guarded(c, [&]() {
+        select_solver_matrix(c, solver_fp32, product);
+        ba::launch_product(c, x, y);
+        BA_HIP_CHECK(hipGetLastError());
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        return BA_OK;
     });
 }
 
@@ -893,6 +923,10 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         c->err = "unknown preconditioner";
         return BA_ERR_INVALID_ARG;
     }
+    if (o && (o->product < BA_PRODUCT_AUTO || o->product > BA_PRODUCT_UPPER)) {
+        c->err = "unknown product layout";
+        return BA_ERR_INVALID_ARG;
+    }
     return guarded(c, [&]() {
         ba_lm_info I;
         std::memset(&I, 0, sizeof I);
@@ -919,7 +953,7 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
         if (pre == BA_PRECOND_LEARNED_FSAI && c->n_rows > 0) prepare_learned_fsai(c);
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
-        select_solver_matrix(c, o ? o->solver_fp32 : 0);
+        select_solver_matrix(c, o ? o->solver_fp32 : 0, o ? o->product : BA_PRODUCT_AUTO);
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(ev[6], c->stream));
         if (c->n_rows > 0)

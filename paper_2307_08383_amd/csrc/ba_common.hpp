@@ -186,6 +186,9 @@ struct Pcg {
     double *Einv = nullptr, *pW = nullptr, *pE = nullptr;
     int* state = nullptr;      // [0] done, [1] step, [2] status, [3] completed steps
     double* scal = nullptr;    // [0] r0^2, [1] final relres
+    // UPPER product: u [n_rows][9] = the upper blocks' part of S z,
+    // tb [n_blk][9] = S_rs^T z_r of each stored block
+    double *u = nullptr, *tb = nullptr;
 };
 
 // Factorised sparse approximate inverse G (M^-1 = G^T G) on the lower RCS
@@ -244,7 +247,12 @@ struct ba_ctx {
     bool sf_ready = false;
     float* Sf32 = nullptr;             // FP32 copy of Sf for solver_fp32 (allocated on first use)
     bool sf32_ready = false;
+    float* Su32 = nullptr;             // [n_blk][81] upper blocks in FP32, each transposed (UPPER product)
+    bool su32_ready = false;
+    // blocks (r, s), r < s, of each column s, ascending r (UPPER product)
+    int32_t *lo_ptr = nullptr, *lo_blk = nullptr;
     int s32 = 0;                       // the current solve uses Sf32
+    int upper = 0;                     // the current solve reads each upper block once (UPPER)
     int defl_s32 = 0;                  // precision of S in the deflation set-up (S W, E)
     // linearization / formation
     void* R = nullptr;                 // [n_obs][24] T: J_c (18) from linearize, K (6) from the point stage
@@ -283,6 +291,7 @@ struct ba_ctx {
         int mode;
         int defl;
         int s32;
+        int upper;
         double tol;
         int max_iter;
         hipGraphExec_t exec;

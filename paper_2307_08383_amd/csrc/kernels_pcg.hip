@@ -28,6 +28,12 @@
 //   p = z + beta p - W mu, q = S z + beta q - (S W) mu, mu = E^-1 (S W)^T z,
 // so that W^T r stays zero; (S W)^T z rides along with r^T z.
 //
+// The product S z takes one of two layouts: FULL gathers every block row of
+// both triangles (a copy made after each formation: each stored block is
+// read twice); UPPER reads each stored upper block once (kernel A1 forms
+// S_rs z_s for row r and writes S_rs^T z_r per block, kernel A2 sums those
+// per row s in a fixed order and finishes A).
+//
 // All kernels run the same fixed number of blocks (grid-stride over rows)
 // and leave one partial per block for each scalar product; every block of
 // the next kernel re-sums those partials in the same order, so all blocks
@@ -248,6 +254,18 @@ __global__ __launch_bounds__(BS) void k_build_sf(int64_t n_sf, const int32_t* __
         const int src = sf_src[e];
         const double* B = blk + (int64_t)(src >> 1) * 81;
         Sf[i] = (TS)((src & 1) ? B[q * 9 + p] : B[pq]);
+    }
+}
+
+// Su32: the upper blocks rounded to FP32, each stored transposed (so that a
+// column of S_rs is a contiguous row for the UPPER product)
+__global__ __launch_bounds__(BS) void k_build_su32(int64_t n_blk, const double* __restrict__ blk,
+                                                   float* __restrict__ Su) {
+    const int64_t n = n_blk * 81;
+    for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+        const int64_t e = i / 81;
+        const int pq = (int)(i % 81), p = pq / 9, q = pq % 9;
+        Su[i] = (float)blk[e * 81 + q * 9 + p];
     }
 }
 
@@ -518,17 +536,15 @@ __global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, const int32_t* 
     }
 }
 
-// kernel A; FIRST: the iteration k = 0 (records |r0|^2).
-template <bool FIRST, typename TS>
-__global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, const int32_t* __restrict__ sf_ptr,
-                                              const int32_t* __restrict__ sf_col, const TS* __restrict__ Sf,
-                                              const double* __restrict__ z,
-                                              double* __restrict__ d, double* __restrict__ q,
-                                              double* __restrict__ pA, const double* __restrict__ pR, int n_part,
-                                              int* __restrict__ state, double* __restrict__ scal, double tol,
-                                              int max_iter, int defl, const double* __restrict__ W,
-                                              const double* __restrict__ SW, const double* __restrict__ Einv) {
-    __shared__ double sh[NP * WPB];
+// Decisions of kernel A from the partials of the previous step: false if
+// the solve is over (stop test or iteration cap; with DECIDE the kernel's
+// block 0 records it), else beta and, when deflating, mu = E^-1 (S W)^T z.
+// Without DECIDE (the second kernel of the UPPER product) only the flag
+// that the first kernel left is read.
+template <bool FIRST, bool DECIDE>
+__device__ __forceinline__ bool a_step(const double* __restrict__ pR, int n_part, int* __restrict__ state,
+                                       double* __restrict__ scal, double tol, int max_iter, int defl,
+                                       const double* __restrict__ Einv, double* sh, double& beta, double* mu) {
     const int done = state[0];
     const int k = state[3];
     // rz_k, rr_k, (SW)^T z_k (parity k) and rz_{k-1} (other parity)
@@ -541,55 +557,240 @@ __global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, const int32_t* __restr
     else
         sum_partials<2>(pk, n_part, NP, s, sh);
     if (!FIRST) sum_partials<1>(pR + (int64_t)NP * n_part * ((k + 1) & 1), n_part, NP, s + NP, sh);
-    if (done) return;
+    if (done) return false;
     const double rz = s[0], rr = s[1], rz_old = FIRST ? 1.0 : s[NP];
-    const double r0sq = FIRST ? rr : scal[0];
-    if (FIRST && blockIdx.x == 0 && threadIdx.x == 0) scal[0] = rr;
-    const bool conv = (rr == 0.0) || (sqrt(rr) <= tol * sqrt(r0sq));
-    if (conv || k >= max_iter) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            state[0] = 1;
-            state[2] = conv ? BA_OK : BA_ERR_NOT_CONVERGED;
-            scal[1] = r0sq > 0.0 ? sqrt(rr / r0sq) : 0.0;
+    if (DECIDE) {
+        const double r0sq = FIRST ? rr : scal[0];
+        if (FIRST && blockIdx.x == 0 && threadIdx.x == 0) scal[0] = rr;
+        const bool conv = (rr == 0.0) || (sqrt(rr) <= tol * sqrt(r0sq));
+        if (conv || k >= max_iter) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                state[0] = 1;
+                state[2] = conv ? BA_OK : BA_ERR_NOT_CONVERGED;
+                scal[1] = r0sq > 0.0 ? sqrt(rr / r0sq) : 0.0;
+            }
+            return false;
         }
-        return;
+        if (blockIdx.x == 0 && threadIdx.x == 0) state[1] = k;
     }
-    const double beta = FIRST ? 0.0 : rz / rz_old;
-    double mu[kW];
+    beta = FIRST ? 0.0 : rz / rz_old;
 #pragma unroll
     for (int v = 0; v < kW; ++v) mu[v] = 0.0;
     if (defl) einv_apply(Einv, s + 2, mu);
-    if (blockIdx.x == 0 && threadIdx.x == 0) state[1] = k;
+    return true;
+}
+
+// The end of kernel A for the block row of this wave, given sv = (S z)_row
+// in lanes 0..8: q = sv + beta q - (S W) mu, d = z + beta d - W mu; returns
+// the lane's share of d^T q.
+template <bool FIRST>
+__device__ __forceinline__ double a_finish(int row, double sv, const double* __restrict__ z, double* __restrict__ d,
+                                           double* __restrict__ q, double beta, int defl, const double* __restrict__ W,
+                                           const double* __restrict__ SW, const double* mu) {
     const int lane = threadIdx.x % kWave;
+    if (lane >= 9) return 0.0;
+    const int64_t o = (int64_t)row * 9 + lane;
+    double wm = 0.0, swm = 0.0;
+    if (defl) {
+        const double* Wr = W + (int64_t)row * kW * 9 + lane;
+        const double* Sr = SW + (int64_t)row * kW * 9 + lane;
+#pragma unroll
+        for (int v = 0; v < kW; ++v) {
+            wm += Wr[v * 9] * mu[v];
+            swm += Sr[v * 9] * mu[v];
+        }
+    }
+    const double zv = z[o];
+    const double qv = (FIRST ? sv : sv + beta * q[o]) - swm;
+    const double dv = (FIRST ? zv : zv + beta * d[o]) - wm;
+    q[o] = qv;
+    d[o] = dv;
+    return dv * qv;
+}
+
+// kernel A (FULL product); FIRST: the iteration k = 0 (records |r0|^2).
+template <bool FIRST, typename TS>
+__global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, const int32_t* __restrict__ sf_ptr,
+                                              const int32_t* __restrict__ sf_col, const TS* __restrict__ Sf,
+                                              const double* __restrict__ z,
+                                              double* __restrict__ d, double* __restrict__ q,
+                                              double* __restrict__ pA, const double* __restrict__ pR, int n_part,
+                                              int* __restrict__ state, double* __restrict__ scal, double tol,
+                                              int max_iter, int defl, const double* __restrict__ W,
+                                              const double* __restrict__ SW, const double* __restrict__ Einv) {
+    __shared__ double sh[NP * WPB];
+    double beta, mu[kW];
+    if (!a_step<FIRST, true>(pR, n_part, state, scal, tol, max_iter, defl, Einv, sh, beta, mu)) return;
     double dq = 0.0;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const int64_t o = (int64_t)row * 9 + (lane < 9 ? lane : 0);
-        double zv = 0.0, qo = 0.0, dold = 0.0, wm = 0.0, swm = 0.0;
-        if (lane < 9) {
-            zv = z[o];
-            if (!FIRST) { qo = q[o]; dold = d[o]; }
-            if (defl) {
-                const double* Wr = W + (int64_t)row * kW * 9 + lane;
-                const double* Sr = SW + (int64_t)row * kW * 9 + lane;
-#pragma unroll
-                for (int v = 0; v < kW; ++v) {
-                    wm += Wr[v * 9] * mu[v];
-                    swm += Sr[v * 9] * mu[v];
-                }
-            }
-        }
         const int a0 = sf_ptr[row];
         const double sv = row_gather<TS, 0>(a0, sf_ptr[row + 1] - a0, sf_col, Sf, z, nullptr, 0.0);
-        if (lane < 9) {
-            const double qv = (FIRST ? sv : sv + beta * qo) - swm;
-            const double dv = (FIRST ? zv : zv + beta * dold) - wm;
-            q[o] = qv;
-            d[o] = dv;
-            dq += dv * qv;
-        }
+        dq += a_finish<FIRST>(row, sv, z, d, q, beta, defl, W, SW, mu);
     }
     const double t = block_total(wave_sum(dq), sh);
     if (threadIdx.x == 0) pA[blockIdx.x] = t;
+}
+
+// Column c of a 9x9 block: stored row-major (TR false: nine loads 72 bytes
+// apart, lanes of a group contiguous) or stored transposed (TR true: one
+// row of the stored block, with wide loads).
+template <bool TR, typename TS>
+__device__ __forceinline__ void load_col9(const TS* __restrict__ b, int c, TS* v) {
+    if (TR) {
+        load_row9(b + c * 9, v);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = b[i * 9 + c];
+    }
+}
+
+// UPPER product, first kernel: the wave of block row r walks the row's
+// stored blocks B_e = S_{r,s_e} (the diagonal block first, then s_e > r);
+// lane c of a group of nine holds column c of its block, so
+//   (B_e^T z_r)_c = sum_i B_e[i][c] z_r[i]      needs only that lane: written
+//                                               to tb[e] for s_e != r;
+//   (S z)_r[i] += B_e[i][c] z_{s_e}[c]           is summed over the lanes once
+//                                               per row (wave sums, fixed).
+// Every stored block is read once.  Returns (S z)_r restricted to the upper
+// blocks in lanes 0..8.
+template <bool TR, typename TS>
+__device__ __forceinline__ double row_upper(int row, int start, int n, const int32_t* __restrict__ col,
+                                            const TS* __restrict__ blk, const double* __restrict__ z,
+                                            double* __restrict__ tb) {
+    constexpr int U = sizeof(TS) == 8 ? 2 : 4;   // blocks in flight per group (144 bytes per lane)
+    const int lane = threadIdx.x % kWave;
+    const int grp = lane / 9, comp = lane % 9;
+    double zr[9], acc[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { zr[i] = z[(int64_t)row * 9 + i]; acc[i] = 0.0; }
+    if (grp < GRPW) {
+        for (int e0 = grp; e0 < n; e0 += GRPW * U) {
+            int ci[U];
+            TS bv[U][9];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * GRPW;
+                const int ee = start + (e < n ? e : e0);
+                ci[u] = col[ee];
+                load_col9<TR>(blk + (int64_t)ee * 81, comp, bv[u]);
+            }
+            double zs[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) zs[u] = z[(int64_t)ci[u] * 9 + comp];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * GRPW;
+                if (e >= n) break;
+                double t = 0.0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const double b = (double)bv[u][i];
+                    acc[i] += b * zs[u];
+                    t += b * zr[i];
+                }
+                if (e > 0) tb[(int64_t)(start + e) * 9 + comp] = t;
+            }
+        }
+    }
+    double out = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const double v = wave_sum(acc[i]);
+        if (lane == i) out = v;
+    }
+    return out;
+}
+
+template <bool FIRST, bool TR, typename TS>
+__global__ __launch_bounds__(BS) void k_pcg_A1(int n_rows, const int32_t* __restrict__ row_ptr,
+                                               const int32_t* __restrict__ col_idx, const TS* __restrict__ blk,
+                                               const double* __restrict__ z, double* __restrict__ u,
+                                               double* __restrict__ tb, const double* __restrict__ pR, int n_part,
+                                               int* __restrict__ state, double* __restrict__ scal, double tol,
+                                               int max_iter, int defl, const double* __restrict__ Einv) {
+    __shared__ double sh[NP * WPB];
+    double beta, mu[kW];
+    if (!a_step<FIRST, true>(pR, n_part, state, scal, tol, max_iter, defl, Einv, sh, beta, mu)) return;
+    const int lane = threadIdx.x % kWave;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const int a0 = row_ptr[row];
+        const double v = row_upper<TR, TS>(row, a0, row_ptr[row + 1] - a0, col_idx, blk, z, tb);
+        if (lane < 9) u[(int64_t)row * 9 + lane] = v;
+    }
+}
+
+// (S z)_s from the UPPER product's two parts: u_s plus the transposed
+// products tb of the blocks (r, s), r < s, of column s (ascending r; lane
+// group g sums entries g, g + 7, ..., then the groups in order).  Lanes 0..8.
+__device__ __forceinline__ double column_sum(int row, const int32_t* __restrict__ lo_ptr,
+                                             const int32_t* __restrict__ lo_blk, const double* __restrict__ u,
+                                             const double* __restrict__ tb) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x % kWave;
+    const int grp = lane / 9, comp = lane % 9;
+    const int a0 = lo_ptr[row], n = lo_ptr[row + 1] - a0;
+    double acc = 0.0;
+    if (grp < GRPW) {
+        for (int e0 = grp; e0 < n; e0 += GRPW * U) {
+            double v[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const int e = e0 + k * GRPW;
+                v[k] = e < n ? tb[(int64_t)lo_blk[a0 + e] * 9 + comp] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) acc += v[k];
+        }
+    }
+    double tot = acc;
+#pragma unroll
+    for (int g = 1; g < GRPW; ++g) tot += __shfl(acc, lane + 9 * g < kWave ? lane + 9 * g : lane, kWave);
+    return lane < 9 ? u[(int64_t)row * 9 + lane] + tot : 0.0;
+}
+
+// UPPER product, second kernel: (S z)_s (column_sum), then the end of
+// kernel A.
+template <bool FIRST>
+__global__ __launch_bounds__(BS) void k_pcg_A2(int n_rows, const int32_t* __restrict__ lo_ptr,
+                                               const int32_t* __restrict__ lo_blk, const double* __restrict__ u,
+                                               const double* __restrict__ tb, const double* __restrict__ z,
+                                               double* __restrict__ d, double* __restrict__ q,
+                                               double* __restrict__ pA, const double* __restrict__ pR, int n_part,
+                                               int* __restrict__ state, int defl, const double* __restrict__ W,
+                                               const double* __restrict__ SW, const double* __restrict__ Einv) {
+    __shared__ double sh[NP * WPB];
+    double beta, mu[kW];
+    if (!a_step<FIRST, false>(pR, n_part, state, nullptr, 0.0, 0, defl, Einv, sh, beta, mu)) return;
+    double dq = 0.0;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const double sv = column_sum(row, lo_ptr, lo_blk, u, tb);
+        dq += a_finish<FIRST>(row, sv, z, d, q, beta, defl, W, SW, mu);
+    }
+    const double t = block_total(wave_sum(dq), sh);
+    if (threadIdx.x == 0) pA[blockIdx.x] = t;
+}
+
+// plain y = S x with the UPPER product (two kernels)
+template <bool TR, typename TS>
+__global__ __launch_bounds__(BS) void k_upper_part(int n_rows, const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col_idx, const TS* __restrict__ blk,
+                                                   const double* __restrict__ x, double* __restrict__ u,
+                                                   double* __restrict__ tb) {
+    const int lane = threadIdx.x % kWave;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const int a0 = row_ptr[row];
+        const double v = row_upper<TR, TS>(row, a0, row_ptr[row + 1] - a0, col_idx, blk, x, tb);
+        if (lane < 9) u[(int64_t)row * 9 + lane] = v;
+    }
+}
+__global__ __launch_bounds__(BS) void k_upper_sum(int n_rows, const int32_t* __restrict__ lo_ptr,
+                                                  const int32_t* __restrict__ lo_blk, const double* __restrict__ u,
+                                                  const double* __restrict__ tb, double* __restrict__ y) {
+    const int lane = threadIdx.x % kWave;
+    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+        const double v = column_sum(row, lo_ptr, lo_blk, u, tb);
+        if (lane < 9) y[(int64_t)row * 9 + lane] = v;
+    }
 }
 
 __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restrict__ M, const double* __restrict__ d,
@@ -738,11 +939,23 @@ __global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, const int32_t* __rest
 
 int grid_of(int n_rows) { return std::max(1, std::min((n_rows + WPB - 1) / WPB, kMaxGrid)); }
 
-// S products with the matrix copy of the current solve (FP64 Sf or FP32 Sf32)
+// S products of the current solve: FULL (FP64 Sf or FP32 Sf32) or UPPER
+// (the FP64 upper blocks, or their transposed FP32 copy Su32)
 template <bool FIRST>
 void launch_A(ba_ctx* c, int g, double tol, int max_iter, int defl, hipStream_t st) {
     Pcg& P = c->pcg;
     const int nr = c->n_rows;
+    if (c->upper) {
+        if (c->s32)
+            k_pcg_A1<FIRST, true, float><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->Su32, P.z, P.u, P.tb, P.pR,
+                                                          g, P.state, P.scal, tol, max_iter, defl, P.Einv);
+        else
+            k_pcg_A1<FIRST, false, double><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->blk, P.z, P.u, P.tb,
+                                                            P.pR, g, P.state, P.scal, tol, max_iter, defl, P.Einv);
+        k_pcg_A2<FIRST><<<g, BS, 0, st>>>(nr, c->lo_ptr, c->lo_blk, P.u, P.tb, P.z, P.d, P.q, P.pA, P.pR, g, P.state,
+                                          defl, P.W, P.SW, P.Einv);
+        return;
+    }
     if (c->s32)
         k_pcg_A<FIRST, float><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf32, P.z, P.d, P.q, P.pA, P.pR, g,
                                                 P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
@@ -791,6 +1004,11 @@ void ensure_sf(ba_ctx* c) {
     if (c->s32 && !c->sf32_ready) {
         k_build_sf<float><<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf32);
         c->sf32_ready = true;
+    }
+    if (c->s32 && c->upper && !c->su32_ready && c->n_blk > 0) {
+        const unsigned gu = (unsigned)std::min<int64_t>((c->n_blk * 81 + BS - 1) / BS, 8192);
+        k_build_su32<<<gu, BS, 0, c->stream>>>(c->n_blk, c->blk, c->Su32);
+        c->su32_ready = true;
     }
 }
 
@@ -848,8 +1066,8 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
     hipGraphExec_t exec = nullptr;
     if (c->use_graphs && n_batches > 0) {
         for (auto& gr : c->pcg_graphs)
-            if (gr.M == M && gr.mode == mode && gr.defl == defl && gr.s32 == c->s32 && gr.tol == tol &&
-                gr.max_iter == max_iter)
+            if (gr.M == M && gr.mode == mode && gr.defl == defl && gr.s32 == c->s32 && gr.upper == c->upper &&
+                gr.tol == tol && gr.max_iter == max_iter)
                 exec = gr.exec;
         if (!exec) {
             hipStream_t cs = c->capture_stream;
@@ -859,7 +1077,7 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
             BA_HIP_CHECK(hipStreamEndCapture(cs, &graph));
             BA_HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             BA_HIP_CHECK(hipGraphDestroy(graph));
-            c->pcg_graphs.push_back({M, mode, defl, c->s32, tol, max_iter, exec});
+            c->pcg_graphs.push_back({M, mode, defl, c->s32, c->upper, tol, max_iter, exec});
         }
     }
     hipEvent_t evb[2] = {c->ev[12], c->ev[13]};
@@ -895,10 +1113,22 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
     return (ba_status)c->h_flags[6];
 }
 
-void launch_spmv(ba_ctx* c, const double* x, double* y) {
+// y = S x in the layout selected for the next solve (c->upper, c->s32)
+void launch_product(ba_ctx* c, const double* x, double* y) {
     if (c->n_rows == 0) return;
     ensure_sf(c);
-    k_spmv<double><<<grid_of(c->n_rows), BS, 0, c->stream>>>(c->n_rows, c->sf_ptr, c->sf_col, c->Sf, x, y);
+    const int nr = c->n_rows, g = grid_of(nr);
+    hipStream_t st = c->stream;
+    if (c->upper) {
+        Pcg& P = c->pcg;
+        if (c->s32)
+            k_upper_part<true, float><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->Su32, x, P.u, P.tb);
+        else
+            k_upper_part<false, double><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->blk, x, P.u, P.tb);
+        k_upper_sum<<<g, BS, 0, st>>>(nr, c->lo_ptr, c->lo_blk, P.u, P.tb, y);
+    } else {
+        launch_spmv_cur(c, x, y, st);
+    }
 }
 
 }  // namespace ba

@@ -2,7 +2,7 @@
 observations) in FP64, the strip scene (20,000 cameras, ~20M observations)
 and the partition scene (60,000 free cameras plus a ring of fixed ones,
 ~100M observations) in mixed precision, against the oracle on the same
-inputs.
+inputs; on the two large scenes also the PCG product S x in both layouts.
 Per-block errors of the mixed path are written to gpurun_out/ when that
 directory exists."""
 import json
@@ -32,12 +32,29 @@ def _report(name, d):
     print(name, json.dumps(d), flush=True)
 
 
-def _rcs_case(scene, precision, lam=1e-4):
+def _block_product(blk, rp, ci, x):
+    """y = S x from the upper blocks (both triangles), and |S| |x|."""
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    y = np.zeros_like(x)
+    a = np.zeros_like(x)
+    np.add.at(y, rows, np.einsum("kij,kj->ki", blk, x[ci]))
+    np.add.at(a, rows, np.einsum("kij,kj->ki", np.abs(blk), np.abs(x[ci])))
+    off = ci != rows
+    np.add.at(y, ci[off], np.einsum("kji,kj->ki", blk[off], x[rows[off]]))
+    np.add.at(a, ci[off], np.einsum("kji,kj->ki", np.abs(blk[off]), np.abs(x[rows[off]])))
+    return y, a
+
+
+def _rcs_case(scene, precision, lam=1e-4, products=None):
+    """Per-block RCS errors against the oracle; with `products` (a dict) also
+    y = S x in both PCG product layouts for one random x, checked against
+    the product of the stored blocks and of the oracle's blocks."""
     uv = orc.observations(scene)
     P = orc.Problem.from_scene(scene, uv)
     P.linearize(scene.cams_init, scene.pts_init)
     P.form_rcs(lam)
     ctx = create(scene, uv, precision)
+    ys = {}
     try:
         ba.ba_linearize(ctx, T(scene.cams_init, torch.float64), T(scene.pts_init, torch.float64))
         ba.ba_form_rcs(ctx, lam)
@@ -45,11 +62,24 @@ def _rcs_case(scene, precision, lam=1e-4):
         rp_ref, ci_ref = P.pattern()
         assert np.array_equal(rp, rp_ref) and np.array_equal(ci, ci_ref)
         blk, rhs = ba.ba_get_rcs(ctx)
+        if products is not None:
+            x = np.random.default_rng(5).standard_normal((len(rp) - 1, 9))
+            xd = T(x, torch.float64)
+            for prod in (ba.BA_PRODUCT_FULL, ba.BA_PRODUCT_UPPER):
+                y = torch.empty_like(xd)
+                ba.ba_rcs_product(ctx, xd, y, product=prod)
+                ys[prod] = y.cpu().numpy()
     finally:
         ba.ba_destroy(ctx)
     blk_ref, rhs_ref = P.rcs()
     errs, raw = block_errors(blk, blk_ref, rp_ref, ci_ref)
     rerr = np.linalg.norm(rhs - rhs_ref, axis=1) / np.linalg.norm(rhs_ref, axis=1)
+    if products is not None:
+        y_own, a_own = _block_product(blk, rp, ci, x)
+        y_ref, a_ref = _block_product(blk_ref, rp_ref, ci_ref, x)
+        for prod, name in ((ba.BA_PRODUCT_FULL, "full"), (ba.BA_PRODUCT_UPPER, "upper")):
+            products[f"{name}_vs_stored_blocks"] = float(np.max(np.abs(ys[prod] - y_own) / a_own))
+            products[f"{name}_vs_oracle_blocks"] = float(np.max(np.abs(ys[prod] - y_ref) / a_ref))
     return errs, raw, rerr
 
 
@@ -67,13 +97,23 @@ def test_benchmark_scene_fp64_rcs():
 @pytest.mark.timeout(900)
 def test_strip_scene_mixed_rcs_errors():
     s = scenegen.strips_scene(seed=1, with_stats=False)
-    errs, raw, rerr = _rcs_case(s, 1)
+    prods = {}
+    errs, raw, rerr = _rcs_case(s, 1, products=prods)
     rep = dict(scene=s.name, n_obs=s.n_obs, n_blocks=len(errs), max_block_err=float(errs.max()),
                p999_block_err=float(np.quantile(errs, 0.999)), median_block_err=float(np.median(errs)),
                max_raw_rel=float(raw.max()), p999_raw_rel=float(np.quantile(raw, 0.999)),
-               max_rhs_rel=float(rerr.max()), p999_rhs_rel=float(np.quantile(rerr, 0.999)))
+               max_rhs_rel=float(rerr.max()), p999_rhs_rel=float(np.quantile(rerr, 0.999)), products=prods)
     _report("fullsize_mixed_rcs_errors.json", rep)
     assert errs.max() <= 1e-4
+    _check_products(prods)
+
+
+def _check_products(prods):
+    """Both layouts form S x of the stored blocks up to summation order, and
+    match the oracle's S within the per-block tolerance of the mixed path."""
+    for name in ("full", "upper"):
+        assert prods[f"{name}_vs_stored_blocks"] <= 1e-13
+        assert prods[f"{name}_vs_oracle_blocks"] <= 1e-4
 
 
 @pytest.mark.timeout(900)
@@ -106,11 +146,13 @@ def test_benchmark_scene_lm_final_cost():
 @pytest.mark.timeout(1200)
 def test_partition_scene_mixed_rcs_errors():
     s = scenegen.partition_scene(seed=2, with_stats=False)
-    errs, raw, rerr = _rcs_case(s, 1)
+    prods = {}
+    errs, raw, rerr = _rcs_case(s, 1, products=prods)
     rep = dict(scene=s.name, n_obs=s.n_obs, n_fixed=int(s.cam_fixed.sum()), n_blocks=len(errs),
                max_block_err=float(errs.max()), p999_block_err=float(np.quantile(errs, 0.999)),
                median_block_err=float(np.median(errs)), max_raw_rel=float(raw.max()),
                p999_raw_rel=float(np.quantile(raw, 0.999)), max_rhs_rel=float(rerr.max()),
-               p999_rhs_rel=float(np.quantile(rerr, 0.999)))
+               p999_rhs_rel=float(np.quantile(rerr, 0.999)), products=prods)
     _report("fullsize_partition_mixed_rcs_errors.json", rep)
     assert errs.max() <= 1e-4
+    _check_products(prods)

@@ -1,0 +1,173 @@
+"""The RCS product of a PCG iteration in its two layouts (needs a GPU):
+FULL (each block row of both triangles gathered, every stored block read
+twice) and UPPER (every stored upper block read once, its transposed
+product summed per column by a second kernel).  Both must form y = S x of
+the stored blocks up to summation order, match the oracle's S, and give
+PCG / LM runs with the same results."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2307_08383_amd import scenegen
+
+from gpu_util import T, create
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ba = pytest.importorskip("paper_2307_08383_amd.ba")
+
+
+def _dense(blk, rp, ci, dtype=np.float64):
+    n = len(rp) - 1
+    S = np.zeros((9 * n, 9 * n))
+    for r in range(n):
+        for k in range(rp[r], rp[r + 1]):
+            c = ci[k]
+            B = blk[k].astype(dtype).astype(np.float64)
+            S[9 * r:9 * r + 9, 9 * c:9 * c + 9] = B
+            if c != r:
+                S[9 * c:9 * c + 9, 9 * r:9 * r + 9] = B.T
+    return S
+
+
+SCENES = {
+    # 80 cameras, up to ~40 blocks per row: several groups of a wave per row
+    "aerial": lambda: scenegen.aerial_grid_scene(seed=4, nx=10, ny=8, n_pts=10000, with_stats=False),
+    # free cameras with a ring of fixed ones: rows of uneven length, columns
+    # without lower blocks
+    "partition": lambda: scenegen.partition_scene(seed=3, nx=12, ny=10, ring=2, n_pts=30000, with_stats=False),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(SCENES))
+def formed(request):
+    s = SCENES[request.param]()
+    uv = orc.observations(s)
+    P = orc.Problem.from_scene(s, uv)
+    P.linearize(s.cams_init, s.pts_init)
+    P.form_rcs(1e-3)
+    blk_ref, rhs_ref = P.rcs()
+    rp, ci = P.pattern()
+    return request.param, s, uv, _dense(blk_ref, rp, ci), rhs_ref.ravel()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_product_layouts(formed, precision, fp32):
+    name, s, uv, S_ref, _ = formed
+    ctx = create(s, uv, precision)
+    try:
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-3)
+        rp, ci = ba.ba_get_pattern(ctx)
+        blk, _ = ba.ba_get_rcs(ctx)
+        n = len(rp) - 1
+        x = np.random.default_rng(11).standard_normal((n, 9))
+        xd = T(x, torch.float64)
+        out = {}
+        for prod in (ba.BA_PRODUCT_FULL, ba.BA_PRODUCT_UPPER):
+            y = torch.full((n, 9), np.nan, dtype=torch.float64, device="cuda")
+            ba.ba_rcs_product(ctx, xd, y, product=prod, solver_fp32=fp32)
+            out[prod] = y.cpu().numpy().ravel()
+        # again: the UPPER product is deterministic
+        y = torch.empty((n, 9), dtype=torch.float64, device="cuda")
+        ba.ba_rcs_product(ctx, xd, y, product=ba.BA_PRODUCT_UPPER, solver_fp32=fp32)
+        assert np.array_equal(y.cpu().numpy().ravel(), out[ba.BA_PRODUCT_UPPER])
+    finally:
+        ba.ba_destroy(ctx)
+    # the product of the stored blocks (rounded to FP32 for the FP32 copy),
+    # exact up to summation order: bound by |S| |x| per entry
+    S_own = _dense(blk, rp, ci, np.float32 if fp32 else np.float64)
+    xv = x.ravel()
+    y_exact = S_own @ xv
+    scale = np.abs(S_own) @ np.abs(xv)
+    for prod, yv in out.items():
+        assert np.all(np.isfinite(yv)), prod
+        assert np.all(np.abs(yv - y_exact) <= 1e-13 * scale), prod
+    # against the oracle's S: the stored blocks' own error (1e-10 FP64; the
+    # FP32 operands of the mixed path and the FP32 copy at 1e-4 per block)
+    tol = 1e-10 if (precision == 0 and not fp32) else 1e-4
+    y_ref = S_ref @ xv
+    scale_ref = np.abs(S_ref) @ np.abs(xv)
+    for prod, yv in out.items():
+        assert np.all(np.abs(yv - y_ref) <= tol * scale_ref), (name, prod)
+
+
+@pytest.mark.parametrize("precond,deflate,fp32", [(0, False, False), (0, True, False), (2, True, False),
+                                                   (0, False, True), (2, True, True)])
+def test_upper_pcg_solves(formed, precond, deflate, fp32):
+    name, s, uv, S_ref, b = formed
+    ctx = create(s, uv, 0)
+    try:
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-3)
+        rp, ci = ba.ba_get_pattern(ctx)
+        blk, _ = ba.ba_get_rcs(ctx)
+        n = len(rp) - 1
+        dx = torch.empty((n, 9), dtype=torch.float64, device="cuda")
+        kw = dict(tol=1e-10, max_iter=5000, precond=precond, deflate=deflate, solver_fp32=fp32)
+        i_full = ba.ba_pcg_solve(ctx, dx, product=ba.BA_PRODUCT_FULL, **kw)
+        x_full = dx.cpu().numpy().ravel().copy()
+        i_up = ba.ba_pcg_solve(ctx, dx, product=ba.BA_PRODUCT_UPPER, **kw)
+        x_up = dx.cpu().numpy().ravel().copy()
+        i_up2 = ba.ba_pcg_solve(ctx, dx, product=ba.BA_PRODUCT_UPPER, **kw)
+        assert np.array_equal(dx.cpu().numpy().ravel(), x_up) and i_up2["iters"] == i_up["iters"]
+    finally:
+        ba.ba_destroy(ctx)
+    assert i_full["status"] == 0 and i_up["status"] == 0
+    assert abs(i_up["iters"] - i_full["iters"]) <= max(2, 0.05 * i_full["iters"])
+    S_own = _dense(blk, rp, ci, np.float32 if fp32 else np.float64)
+    nb = np.linalg.norm(b)
+    # each solves the system of the stored (or rounded) blocks
+    for xv in (x_full, x_up):
+        assert np.linalg.norm(b - S_own @ xv) <= (1e-7 if fp32 else 1e-9) * nb
+    # and the two solutions agree within what the stopping tolerance leaves
+    ev = np.linalg.eigvalsh(S_own)
+    assert np.linalg.norm(x_up - x_full) <= 3.0 * (ev[-1] / ev[0]) * 1e-10 * np.linalg.norm(x_full)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_lm_with_upper_product_final_cost(precision):
+    s = scenegen.aerial_grid_scene(seed=7, nx=8, ny=6, n_pts=6000, with_stats=False)
+    uv = orc.observations(s)
+    P = orc.Problem.from_scene(s, uv)
+    c_ref, p_ref, _ = orc.lm_run(P, s.cams_init, s.pts_init, 10)
+    F_ref = P.cost(c_ref, p_ref)
+    ctx = create(s, uv, precision)
+    try:
+        cams = T(s.cams_init, torch.float64)
+        pts = T(s.pts_init, torch.float64)
+        st = ba.new_lm_state(1e-4)
+        for _ in range(10):
+            info = ba.ba_lm_step(ctx, cams, pts, st, product=ba.BA_PRODUCT_UPPER)
+            assert info["pcg_status"] in (0, ba.BA_ERR_NOT_CONVERGED)
+        F = P.cost(cams.cpu().numpy(), pts.cpu().numpy())
+    finally:
+        ba.ba_destroy(ctx)
+    assert abs(F - F_ref) <= 1e-6 * F_ref
+
+
+def test_product_argument_errors(formed):
+    _, s, uv, _, _ = formed
+    ctx = create(s, uv, 0)
+    try:
+        n = ba.ba_get_sizes(ctx)["n_rows"]
+        x = torch.zeros((n, 9), dtype=torch.float64, device="cuda")
+        y = torch.zeros_like(x)
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_rcs_product(ctx, x, y)   # no RCS yet
+        assert ei.value.status == ba.BA_ERR_STATE
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-3)
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_rcs_product(ctx, x, y, product=3)
+        assert ei.value.status == ba.BA_ERR_INVALID_ARG
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_rcs_product(ctx, x, x)
+        assert ei.value.status == ba.BA_ERR_INVALID_ARG
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_pcg_solve(ctx, y, product=7)
+        assert ei.value.status == ba.BA_ERR_INVALID_ARG
+    finally:
+        ba.ba_destroy(ctx)
