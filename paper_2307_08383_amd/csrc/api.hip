@@ -59,7 +59,7 @@ void free_ctx(ba_ctx* c) {
                     c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.u, c->pcg.tb, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
                     c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
-                    c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G};
+                    c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.gu_src, c->fs.tg, c->pcg.bm, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -482,6 +482,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &P.t, (size_t)nr * 9);
     dalloc(c, &P.u, (size_t)nr * 9);
     dalloc(c, &P.tb, (size_t)c->n_blk * 9);
+    dalloc(c, &P.bm, 8);
     dalloc(c, &P.pA, 1024);
     dalloc(c, &P.pR, 2 * 9 * 1024);
     dalloc(c, &P.W, (size_t)nr * 63);
@@ -653,9 +654,13 @@ void build_fsai(ba_ctx* c) {
     upload(c, &F.gu_ptr, gu_ptr);
     upload(c, &F.gu_col, gu_col);
     upload(c, &F.gu_pos, gu_pos);
+    std::vector<int32_t> gu_src(gu_pos.size());
+    for (size_t p = 0; p < gu_pos.size(); ++p) gu_src[gu_pos[p]] = (int32_t)p;
+    upload(c, &F.gu_src, gu_src);
     F.max_m = max_m;
     dalloc(c, &F.Gl, J.size() * 81);
     dalloc(c, &F.Gu, J.size() * 81);
+    dalloc(c, &F.tg, J.size() * 9);
     dalloc(c, &F.An, (size_t)c->n_blk * 81);
     dalloc(c, &F.G, (size_t)c->n_blk * 81);
     BA_HIP_CHECK(hipMemsetAsync(F.G, 0, (size_t)c->n_blk * 81 * sizeof(float), c->stream));

@@ -189,6 +189,7 @@ struct Pcg {
     // UPPER product: u [n_rows][9] = the upper blocks' part of S z,
     // tb [n_blk][9] = S_rs^T z_r of each stored block
     double *u = nullptr, *tb = nullptr;
+    double* bm = nullptr;      // [8] beta and mu of the step, from the first UPPER kernel to the second
 };
 
 // Factorised sparse approximate inverse G (M^-1 = G^T G) on the lower RCS
@@ -211,6 +212,8 @@ struct Fsai {
     float *Gl = nullptr, *Gu = nullptr;   // G by rows (like J) and G^T by rows (like gu_col), 9x9 each
     float* An = nullptr;              // [n_blk][81] L_r^-1 S_rc L_c^-T of off-diagonal blocks
     float* G = nullptr;               // [n_blk][81] G in the upper slots
+    int32_t* gu_src = nullptr;        // entry of Gl for each entry of Gu (inverse of gu_pos)
+    double* tg = nullptr;             // [entries][9] G_ij^T t_i per entry of Gl (UPPER apply of G^T)
 };
 
 }  // namespace ba

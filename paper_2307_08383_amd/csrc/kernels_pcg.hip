@@ -524,24 +524,80 @@ __global__ __launch_bounds__(BS) void k_spmv(int n_rows, const int32_t* __restri
     }
 }
 
-// t = G r (initial step of the factorised preconditioner)
+// One-read apply of a factor's transpose: once a wave holds t_row (lanes
+// 0..8 of tv), the transposed products B_e^T t_row of the row's blocks
+// (FP32, stored row-major as applied) are written per entry to tg, from
+// blocks the row's gather has just brought into the cache; lane c of a
+// group of nine forms component c from column c of its block.
+__device__ __forceinline__ void row_transposed(int start, int n, const float* __restrict__ blk, double tv,
+                                               double* __restrict__ tg) {
+    constexpr int U = 4;
+    const int lane = threadIdx.x % kWave;
+    const int grp = lane / 9, comp = lane % 9;
+    double tr[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) tr[i] = __shfl(tv, i, kWave);
+    if (grp >= GRPW) return;
+    for (int e0 = grp; e0 < n; e0 += GRPW * U) {
+        float bv[U][9];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * GRPW;
+            const int ee = start + (e < n ? e : e0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) bv[u][i] = blk[(int64_t)ee * 81 + i * 9 + comp];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u * GRPW;
+            if (e >= n) break;
+            double y = 0.0;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) y += (double)bv[u][i] * tr[i];
+            tg[(int64_t)(start + e) * 9 + comp] = y;
+        }
+    }
+}
+
+// init + sum of v[src[a0 + e]][c] for e = 0..n-1 in ascending e (one lane
+// per component; each round requests up to 16 indices, then their values)
+__device__ __forceinline__ double index_sum(int a0, int n, const int32_t* __restrict__ src,
+                                            const double* __restrict__ v, int c, double init) {
+    constexpr int U = 16;
+    double acc = init;
+    for (int e0 = 0; e0 < n; e0 += U) {
+        int bi[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) bi[k] = e0 + k < n ? src[a0 + e0 + k] : -1;
+        double w[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) w[k] = bi[k] >= 0 ? v[(int64_t)bi[k] * 9 + c] : 0.0;
+#pragma unroll
+        for (int k = 0; k < U; ++k) acc += w[k];
+    }
+    return acc;
+}
+
+// t = G r (initial step of the factorised preconditioner); UP: also the
+// transposed products G_row,j^T t_row per entry (tg)
+template <bool UP>
 __global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, const int32_t* __restrict__ gl_ptr,
                                                      const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
-                                                     const double* __restrict__ r, double* __restrict__ t) {
+                                                     const double* __restrict__ r, double* __restrict__ t,
+                                                     double* __restrict__ tg) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const int a = gl_ptr[row];
-        const double v = row_gather<float, 0>(a, gl_ptr[row + 1] - a, gl_col, Gl, r, nullptr, 0.0);
+        const int a = gl_ptr[row], n = gl_ptr[row + 1] - a;
+        const double v = row_gather<float, 0>(a, n, gl_col, Gl, r, nullptr, 0.0);
         if (lane < 9) t[(int64_t)row * 9 + lane] = v;
+        if (UP) row_transposed(a, n, Gl, v, tg);
     }
 }
 
 // Decisions of kernel A from the partials of the previous step: false if
-// the solve is over (stop test or iteration cap; with DECIDE the kernel's
-// block 0 records it), else beta and, when deflating, mu = E^-1 (S W)^T z.
-// Without DECIDE (the second kernel of the UPPER product) only the flag
-// that the first kernel left is read.
-template <bool FIRST, bool DECIDE>
+// the solve is over (stop test or iteration cap, recorded by block 0),
+// else beta and, when deflating, mu = E^-1 (S W)^T z.
+template <bool FIRST>
 __device__ __forceinline__ bool a_step(const double* __restrict__ pR, int n_part, int* __restrict__ state,
                                        double* __restrict__ scal, double tol, int max_iter, int defl,
                                        const double* __restrict__ Einv, double* sh, double& beta, double* mu) {
@@ -559,20 +615,18 @@ __device__ __forceinline__ bool a_step(const double* __restrict__ pR, int n_part
     if (!FIRST) sum_partials<1>(pR + (int64_t)NP * n_part * ((k + 1) & 1), n_part, NP, s + NP, sh);
     if (done) return false;
     const double rz = s[0], rr = s[1], rz_old = FIRST ? 1.0 : s[NP];
-    if (DECIDE) {
-        const double r0sq = FIRST ? rr : scal[0];
-        if (FIRST && blockIdx.x == 0 && threadIdx.x == 0) scal[0] = rr;
-        const bool conv = (rr == 0.0) || (sqrt(rr) <= tol * sqrt(r0sq));
-        if (conv || k >= max_iter) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                state[0] = 1;
-                state[2] = conv ? BA_OK : BA_ERR_NOT_CONVERGED;
-                scal[1] = r0sq > 0.0 ? sqrt(rr / r0sq) : 0.0;
-            }
-            return false;
+    const double r0sq = FIRST ? rr : scal[0];
+    if (FIRST && blockIdx.x == 0 && threadIdx.x == 0) scal[0] = rr;
+    const bool conv = (rr == 0.0) || (sqrt(rr) <= tol * sqrt(r0sq));
+    if (conv || k >= max_iter) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            state[0] = 1;
+            state[2] = conv ? BA_OK : BA_ERR_NOT_CONVERGED;
+            scal[1] = r0sq > 0.0 ? sqrt(rr / r0sq) : 0.0;
         }
-        if (blockIdx.x == 0 && threadIdx.x == 0) state[1] = k;
+        return false;
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) state[1] = k;
     beta = FIRST ? 0.0 : rz / rz_old;
 #pragma unroll
     for (int v = 0; v < kW; ++v) mu[v] = 0.0;
@@ -580,20 +634,19 @@ __device__ __forceinline__ bool a_step(const double* __restrict__ pR, int n_part
     return true;
 }
 
-// The end of kernel A for the block row of this wave, given sv = (S z)_row
-// in lanes 0..8: q = sv + beta q - (S W) mu, d = z + beta d - W mu; returns
-// the lane's share of d^T q.
+// The end of kernel A for component c of block row `row`, given
+// sv = (S z)_row[c]: q = sv + beta q - (S W) mu, d = z + beta d - W mu;
+// returns the component's share of d^T q.
 template <bool FIRST>
-__device__ __forceinline__ double a_finish(int row, double sv, const double* __restrict__ z, double* __restrict__ d,
-                                           double* __restrict__ q, double beta, int defl, const double* __restrict__ W,
-                                           const double* __restrict__ SW, const double* mu) {
-    const int lane = threadIdx.x % kWave;
-    if (lane >= 9) return 0.0;
-    const int64_t o = (int64_t)row * 9 + lane;
+__device__ __forceinline__ double a_finish(int row, int c, double sv, const double* __restrict__ z,
+                                           double* __restrict__ d, double* __restrict__ q, double beta, int defl,
+                                           const double* __restrict__ W, const double* __restrict__ SW,
+                                           const double* mu) {
+    const int64_t o = (int64_t)row * 9 + c;
     double wm = 0.0, swm = 0.0;
     if (defl) {
-        const double* Wr = W + (int64_t)row * kW * 9 + lane;
-        const double* Sr = SW + (int64_t)row * kW * 9 + lane;
+        const double* Wr = W + (int64_t)row * kW * 9 + c;
+        const double* Sr = SW + (int64_t)row * kW * 9 + c;
 #pragma unroll
         for (int v = 0; v < kW; ++v) {
             wm += Wr[v * 9] * mu[v];
@@ -620,12 +673,13 @@ __global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, const int32_t* __restr
                                               const double* __restrict__ SW, const double* __restrict__ Einv) {
     __shared__ double sh[NP * WPB];
     double beta, mu[kW];
-    if (!a_step<FIRST, true>(pR, n_part, state, scal, tol, max_iter, defl, Einv, sh, beta, mu)) return;
+    if (!a_step<FIRST>(pR, n_part, state, scal, tol, max_iter, defl, Einv, sh, beta, mu)) return;
+    const int lane = threadIdx.x % kWave;
     double dq = 0.0;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a0 = sf_ptr[row];
         const double sv = row_gather<TS, 0>(a0, sf_ptr[row + 1] - a0, sf_col, Sf, z, nullptr, 0.0);
-        dq += a_finish<FIRST>(row, sv, z, d, q, beta, defl, W, SW, mu);
+        if (lane < 9) dq += a_finish<FIRST>(row, lane, sv, z, d, q, beta, defl, W, SW, mu);
     }
     const double t = block_total(wave_sum(dq), sh);
     if (threadIdx.x == 0) pA[blockIdx.x] = t;
@@ -707,10 +761,17 @@ __global__ __launch_bounds__(BS) void k_pcg_A1(int n_rows, const int32_t* __rest
                                                const double* __restrict__ z, double* __restrict__ u,
                                                double* __restrict__ tb, const double* __restrict__ pR, int n_part,
                                                int* __restrict__ state, double* __restrict__ scal, double tol,
-                                               int max_iter, int defl, const double* __restrict__ Einv) {
+                                               int max_iter, int defl, const double* __restrict__ Einv,
+                                               double* __restrict__ bm) {
     __shared__ double sh[NP * WPB];
     double beta, mu[kW];
-    if (!a_step<FIRST, true>(pR, n_part, state, scal, tol, max_iter, defl, Einv, sh, beta, mu)) return;
+    if (!a_step<FIRST>(pR, n_part, state, scal, tol, max_iter, defl, Einv, sh, beta, mu)) return;
+    // the step's beta and mu for the second kernel (every block has the same)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        bm[0] = beta;
+#pragma unroll
+        for (int v = 0; v < kW; ++v) bm[1 + v] = mu[v];
+    }
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a0 = row_ptr[row];
@@ -719,52 +780,45 @@ __global__ __launch_bounds__(BS) void k_pcg_A1(int n_rows, const int32_t* __rest
     }
 }
 
-// (S z)_s from the UPPER product's two parts: u_s plus the transposed
-// products tb of the blocks (r, s), r < s, of column s (ascending r; lane
-// group g sums entries g, g + 7, ..., then the groups in order).  Lanes 0..8.
-__device__ __forceinline__ double column_sum(int row, const int32_t* __restrict__ lo_ptr,
+// (S z)_s[c] from the UPPER product's two parts: u_s plus the transposed
+// products tb of the blocks (r, s), r < s, of column s, summed in ascending
+// r by the lane group that owns row s (lane c of the group: component c).
+// A wave owns seven rows at a time, so their dependent index and value
+// loads overlap.
+__device__ __forceinline__ double column_sum(int row, int c, const int32_t* __restrict__ lo_ptr,
                                              const int32_t* __restrict__ lo_blk, const double* __restrict__ u,
                                              const double* __restrict__ tb) {
-    constexpr int U = 4;
-    const int lane = threadIdx.x % kWave;
-    const int grp = lane / 9, comp = lane % 9;
-    const int a0 = lo_ptr[row], n = lo_ptr[row + 1] - a0;
-    double acc = 0.0;
-    if (grp < GRPW) {
-        for (int e0 = grp; e0 < n; e0 += GRPW * U) {
-            double v[U];
-#pragma unroll
-            for (int k = 0; k < U; ++k) {
-                const int e = e0 + k * GRPW;
-                v[k] = e < n ? tb[(int64_t)lo_blk[a0 + e] * 9 + comp] : 0.0;
-            }
-#pragma unroll
-            for (int k = 0; k < U; ++k) acc += v[k];
-        }
-    }
-    double tot = acc;
-#pragma unroll
-    for (int g = 1; g < GRPW; ++g) tot += __shfl(acc, lane + 9 * g < kWave ? lane + 9 * g : lane, kWave);
-    return lane < 9 ? u[(int64_t)row * 9 + lane] + tot : 0.0;
+    const int a0 = lo_ptr[row];
+    return index_sum(a0, lo_ptr[row + 1] - a0, lo_blk, tb, c, u[(int64_t)row * 9 + c]);
 }
 
 // UPPER product, second kernel: (S z)_s (column_sum), then the end of
-// kernel A.
+// kernel A with the beta and mu that the first kernel published; lane group
+// g of wave w takes rows (block * WPB + w) * 7 + g, ...
 template <bool FIRST>
 __global__ __launch_bounds__(BS) void k_pcg_A2(int n_rows, const int32_t* __restrict__ lo_ptr,
                                                const int32_t* __restrict__ lo_blk, const double* __restrict__ u,
                                                const double* __restrict__ tb, const double* __restrict__ z,
                                                double* __restrict__ d, double* __restrict__ q,
-                                               double* __restrict__ pA, const double* __restrict__ pR, int n_part,
-                                               int* __restrict__ state, int defl, const double* __restrict__ W,
-                                               const double* __restrict__ SW, const double* __restrict__ Einv) {
-    __shared__ double sh[NP * WPB];
-    double beta, mu[kW];
-    if (!a_step<FIRST, false>(pR, n_part, state, nullptr, 0.0, 0, defl, Einv, sh, beta, mu)) return;
+                                               double* __restrict__ pA, const int* __restrict__ state, int defl,
+                                               const double* __restrict__ W, const double* __restrict__ SW,
+                                               const double* __restrict__ bm) {
+    __shared__ double sh[WPB];
+    if (state[0]) return;   // the first kernel stopped the solve
+    const double beta = bm[0];
+    double mu[kW];
+#pragma unroll
+    for (int v = 0; v < kW; ++v) mu[v] = bm[1 + v];
+    const int lane = threadIdx.x % kWave;
+    const int grp = lane / 9, comp = lane % 9;
     double dq = 0.0;
-    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const double sv = column_sum(row, lo_ptr, lo_blk, u, tb);
-        dq += a_finish<FIRST>(row, sv, z, d, q, beta, defl, W, SW, mu);
+    if (grp < GRPW) {
+        for (int r0 = (blockIdx.x * WPB + threadIdx.x / kWave) * GRPW; r0 < n_rows; r0 += gridDim.x * WPB * GRPW) {
+            const int row = r0 + grp;
+            if (row >= n_rows) break;
+            const double sv = column_sum(row, comp, lo_ptr, lo_blk, u, tb);
+            dq += a_finish<FIRST>(row, comp, sv, z, d, q, beta, defl, W, SW, mu);
+        }
     }
     const double t = block_total(wave_sum(dq), sh);
     if (threadIdx.x == 0) pA[blockIdx.x] = t;
@@ -787,9 +841,12 @@ __global__ __launch_bounds__(BS) void k_upper_sum(int n_rows, const int32_t* __r
                                                   const int32_t* __restrict__ lo_blk, const double* __restrict__ u,
                                                   const double* __restrict__ tb, double* __restrict__ y) {
     const int lane = threadIdx.x % kWave;
-    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const double v = column_sum(row, lo_ptr, lo_blk, u, tb);
-        if (lane < 9) y[(int64_t)row * 9 + lane] = v;
+    const int grp = lane / 9, comp = lane % 9;
+    if (grp >= GRPW) return;
+    for (int r0 = (blockIdx.x * WPB + threadIdx.x / kWave) * GRPW; r0 < n_rows; r0 += gridDim.x * WPB * GRPW) {
+        const int row = r0 + grp;
+        if (row >= n_rows) break;
+        y[(int64_t)row * 9 + comp] = column_sum(row, comp, lo_ptr, lo_blk, u, tb);
     }
 }
 
@@ -852,13 +909,17 @@ __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restri
     if (blockIdx.x == 0 && threadIdx.x == 0) state[3] = k + 1;
 }
 
-// factorised preconditioner, first half: update and t = G r'
+// factorised preconditioner, first half: update and t = G r'; UP: also
+// the transposed products G_row,j^T t_row per entry (tg) for the one-read
+// apply of G^T
+template <bool UP>
 __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __restrict__ gl_ptr,
                                                const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
                                                const double* __restrict__ d,
                                                const double* __restrict__ q, double* __restrict__ x,
                                                double* __restrict__ r0buf, double* __restrict__ r1buf,
-                                               double* __restrict__ t, const double* __restrict__ pA,
+                                               double* __restrict__ t, double* __restrict__ tg,
+                                               const double* __restrict__ pA,
                                                double* __restrict__ pR, int n_part, int* __restrict__ state) {
     __shared__ double sh[2 * WPB];
     const int done = state[0];
@@ -878,16 +939,17 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
     const int lane = threadIdx.x % kWave;
     double rr = 0.0;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const int a0 = gl_ptr[row];
-        const double tv = row_gather<float, 1>(a0, gl_ptr[row + 1] - a0, gl_col, Gl, rin, q, alpha);
+        const int a0 = gl_ptr[row], n = gl_ptr[row + 1] - a0;
+        const double tv = row_gather<float, 1>(a0, n, gl_col, Gl, rin, q, alpha);
         if (lane < 9) {
             const int64_t o = (int64_t)row * 9 + lane;
             x[o] += alpha * d[o];
             const double rv = rin[o] - alpha * q[o];
             rout[o] = rv;
-            t[o] = tv;
+            if (!UP) t[o] = tv;
             rr += rv * rv;
         }
+        if (UP) row_transposed(a0, n, Gl, tv, tg);
     }
     const double tot = block_total(wave_sum(rr), sh);
     if (threadIdx.x == 0) pR[(int64_t)NP * n_part * ((k + 1) & 1) + (int64_t)NP * blockIdx.x + 1] = tot;
@@ -895,10 +957,14 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
 
 // factorised preconditioner, second half: z = G^T t, r'^T z, (SW)^T z.
 // INIT: the initial z0 (r in buffer 0, parity 0, no counter update).
-template <bool INIT>
+// UP: z_j = sum of the transposed products tg of the entries (i, j) of
+// column j of G (ascending i, one lane group per row) instead of a gather
+// over a transposed copy of G.
+template <bool INIT, bool UP>
 __global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, const int32_t* __restrict__ gu_ptr,
                                                const int32_t* __restrict__ gu_col, const float* __restrict__ Gu,
-                                               const double* __restrict__ t,
+                                               const double* __restrict__ t, const int32_t* __restrict__ gu_src,
+                                               const double* __restrict__ tg,
                                                const double* __restrict__ r0buf, const double* __restrict__ r1buf,
                                                double* __restrict__ z, double* __restrict__ pR, int n_part,
                                                int* __restrict__ state, int defl, const double* __restrict__ SW) {
@@ -913,18 +979,31 @@ __global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, const int32_t* __rest
     double acc[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) acc[j] = 0.0;
-    for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
-        const int a0 = gu_ptr[row];
-        const double zv = row_gather<float, 0>(a0, gu_ptr[row + 1] - a0, gu_col, Gu, t, nullptr, 0.0);
-        if (lane < 9) {
-            const int64_t o = (int64_t)row * 9 + lane;
-            z[o] = zv;
-            acc[0] += r[o] * zv;
-            if (defl) {
-                const double* Sr = SW + (int64_t)row * kW * 9 + lane;
+    auto finish = [&](int row, int c, double zv) {
+        const int64_t o = (int64_t)row * 9 + c;
+        z[o] = zv;
+        acc[0] += r[o] * zv;
+        if (defl) {
+            const double* Sr = SW + (int64_t)row * kW * 9 + c;
 #pragma unroll
-                for (int v = 0; v < kW; ++v) acc[2 + v] += Sr[v * 9] * zv;
+            for (int v = 0; v < kW; ++v) acc[2 + v] += Sr[v * 9] * zv;
+        }
+    };
+    if (UP) {
+        const int grp = lane / 9, comp = lane % 9;
+        if (grp < GRPW)
+            for (int r0 = (blockIdx.x * WPB + threadIdx.x / kWave) * GRPW; r0 < n_rows;
+                 r0 += gridDim.x * WPB * GRPW) {
+                const int row = r0 + grp;
+                if (row >= n_rows) break;
+                const int a0 = gu_ptr[row];
+                finish(row, comp, index_sum(a0, gu_ptr[row + 1] - a0, gu_src, tg, comp, 0.0));
             }
+    } else {
+        for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
+            const int a0 = gu_ptr[row];
+            const double zv = row_gather<float, 0>(a0, gu_ptr[row + 1] - a0, gu_col, Gu, t, nullptr, 0.0);
+            if (lane < 9) finish(row, lane, zv);
         }
     }
     double tot[NP];
@@ -948,12 +1027,12 @@ void launch_A(ba_ctx* c, int g, double tol, int max_iter, int defl, hipStream_t 
     if (c->upper) {
         if (c->s32)
             k_pcg_A1<FIRST, true, float><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->Su32, P.z, P.u, P.tb, P.pR,
-                                                          g, P.state, P.scal, tol, max_iter, defl, P.Einv);
+                                                          g, P.state, P.scal, tol, max_iter, defl, P.Einv, P.bm);
         else
             k_pcg_A1<FIRST, false, double><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->blk, P.z, P.u, P.tb,
-                                                            P.pR, g, P.state, P.scal, tol, max_iter, defl, P.Einv);
-        k_pcg_A2<FIRST><<<g, BS, 0, st>>>(nr, c->lo_ptr, c->lo_blk, P.u, P.tb, P.z, P.d, P.q, P.pA, P.pR, g, P.state,
-                                          defl, P.W, P.SW, P.Einv);
+                                                            P.pR, g, P.state, P.scal, tol, max_iter, defl, P.Einv, P.bm);
+        k_pcg_A2<FIRST><<<g, BS, 0, st>>>(nr, c->lo_ptr, c->lo_blk, P.u, P.tb, P.z, P.d, P.q, P.pA, P.state, defl,
+                                          P.W, P.SW, P.bm);
         return;
     }
     if (c->s32)
@@ -964,12 +1043,57 @@ void launch_A(ba_ctx* c, int g, double tol, int max_iter, int defl, hipStream_t 
                                                  P.state, P.scal, tol, max_iter, defl, P.W, P.SW, P.Einv);
 }
 
-void launch_spmv_cur(ba_ctx* c, const double* x, double* y, hipStream_t st) {
-    const int g = grid_of(c->n_rows);
-    if (c->s32)
-        k_spmv<float><<<g, BS, 0, st>>>(c->n_rows, c->sf_ptr, c->sf_col, c->Sf32, x, y);
-    else
-        k_spmv<double><<<g, BS, 0, st>>>(c->n_rows, c->sf_ptr, c->sf_col, c->Sf, x, y);
+// Kernels Bf and Cf of an iteration with the factorised preconditioner
+// (UPPER: G^T applied from the transposed products of Bf)
+void launch_factor_step(ba_ctx* c, int g, int defl, hipStream_t st) {
+    Pcg& P = c->pcg;
+    Fsai& F = c->fs;
+    const int nr = c->n_rows;
+    if (c->upper) {
+        k_pcg_Bf<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
+                                         P.pR, g, P.state);
+        k_pcg_Cf<false, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0], P.r[1],
+                                                P.z, P.pR, g, P.state, defl, P.SW);
+    } else {
+        k_pcg_Bf<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
+                                          P.pR, g, P.state);
+        k_pcg_Cf<false, false><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
+                                                 P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
+    }
+}
+
+// z0 = G^T G r0 (the initial preconditioner application)
+void launch_factor_init(ba_ctx* c, int g, int defl, hipStream_t st) {
+    Pcg& P = c->pcg;
+    Fsai& F = c->fs;
+    const int nr = c->n_rows;
+    if (c->upper) {
+        k_gather_lower<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, P.r[0], P.t, F.tg);
+        k_pcg_Cf<true, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0], P.r[1],
+                                               P.z, P.pR, g, P.state, defl, P.SW);
+    } else {
+        k_gather_lower<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, P.r[0], P.t, F.tg);
+        k_pcg_Cf<true, false><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
+                                                P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
+    }
+}
+
+// y = S x with the copies of the current solve (FULL: Sf or Sf32; UPPER:
+// the upper blocks or Su32, through the u / tb buffers)
+void product_cur(ba_ctx* c, const double* x, double* y, hipStream_t st) {
+    const int nr = c->n_rows, g = grid_of(nr);
+    if (c->upper) {
+        Pcg& P = c->pcg;
+        if (c->s32)
+            k_upper_part<true, float><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->Su32, x, P.u, P.tb);
+        else
+            k_upper_part<false, double><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->blk, x, P.u, P.tb);
+        k_upper_sum<<<g, BS, 0, st>>>(nr, c->lo_ptr, c->lo_blk, P.u, P.tb, y);
+    } else if (c->s32) {
+        k_spmv<float><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf32, x, y);
+    } else {
+        k_spmv<double><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, x, y);
+    }
 }
 
 void enqueue_iterations(ba_ctx* c, int mode, const double* M, int defl, double tol, int max_iter, int count,
@@ -981,29 +1105,30 @@ void enqueue_iterations(ba_ctx* c, int mode, const double* M, int defl, double t
         if (mode == 0) {
             k_pcg_B<<<g, BS, 0, st>>>(nr, M, P.d, P.q, P.x, P.r[0], P.z, P.pA, P.pR, g, P.state, defl, P.SW);
         } else {
-            k_pcg_Bf<<<g, BS, 0, st>>>(nr, c->fs.ptr, c->fs.J, c->fs.Gl, P.d, P.q, P.x,
-                                       P.r[0], P.r[1], P.t, P.pA, P.pR, g, P.state);
-            k_pcg_Cf<false><<<g, BS, 0, st>>>(nr, c->fs.gu_ptr, c->fs.gu_col, c->fs.Gu, P.t, P.r[0],
-                                              P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
+            launch_factor_step(c, g, defl, st);
         }
     }
 }
 
 }  // namespace
 
-// the row-major copy of both triangles of the current RCS (and, for an
-// FP32 solve, its rounded copy)
-void ensure_sf(ba_ctx* c) {
+// The copies of the current RCS that the next products read: the
+// row-major copy of both triangles (FULL products, and with `full` always)
+// and its FP32 rounding for an FP32 solve; for an FP32 UPPER solve the
+// transposed FP32 upper blocks.
+void ensure_sf(ba_ctx* c, bool full) {
     if (c->n_sf == 0) return;
     const int64_t n = c->n_sf * 81;
     const unsigned g = (unsigned)std::min<int64_t>((n + BS - 1) / BS, 8192);
-    if (!c->sf_ready) {
-        k_build_sf<double><<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf);
-        c->sf_ready = true;
-    }
-    if (c->s32 && !c->sf32_ready) {
-        k_build_sf<float><<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf32);
-        c->sf32_ready = true;
+    if (full || !c->upper) {
+        if (!c->sf_ready) {
+            k_build_sf<double><<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf);
+            c->sf_ready = true;
+        }
+        if (c->s32 && !c->sf32_ready) {
+            k_build_sf<float><<<g, BS, 0, c->stream>>>(c->n_sf, c->sf_src, c->blk, c->Sf32);
+            c->sf32_ready = true;
+        }
     }
     if (c->s32 && c->upper && !c->su32_ready && c->n_blk > 0) {
         const unsigned gu = (unsigned)std::min<int64_t>((c->n_blk * 81 + BS - 1) / BS, 8192);
@@ -1018,7 +1143,7 @@ void prepare_deflation(ba_ctx* c) {
     const int nr = c->n_rows, g = grid_of(nr);
     hipStream_t st = c->stream;
     k_gauge_W<<<(c->n_cams + 255) / 256, 256, 0, st>>>(c->n_cams, c->cam_row, c->lin_cams, P.W);
-    ensure_sf(c);
+    ensure_sf(c, true);
     if (c->s32)
         k_spmm_W<float><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf32, P.W, P.SW);
     else
@@ -1033,29 +1158,24 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
     Pcg& P = c->pcg;
     const int nr = c->n_rows, g = grid_of(nr);
     hipStream_t st = c->stream;
-    ensure_sf(c);
+    ensure_sf(c, false);
     const double* q0 = nullptr;
     if (x0) {
-        launch_spmv_cur(c, x0, P.q, st);
+        product_cur(c, x0, P.q, st);
         q0 = P.q;
     }
     if (defl) k_defl_Wr<<<g, BS, 0, st>>>(nr, c->rhs, q0, P.W, P.pW);
     k_pcg_init<<<g, BS, 0, st>>>(nr, c->rhs, q0, x0, mode == 0 ? M : nullptr, P.x, P.r[0], P.z, P.pR, P.state, P.scal,
                                  defl, P.W, P.SW, P.Einv, P.pW, g);
     if (mode != 0) {
-        k_gather_lower<<<g, BS, 0, st>>>(nr, c->fs.ptr, c->fs.J, c->fs.Gl, P.r[0], P.t);
-        k_pcg_Cf<true><<<g, BS, 0, st>>>(nr, c->fs.gu_ptr, c->fs.gu_col, c->fs.Gu, P.t, P.r[0], P.r[1],
-                                         P.z, P.pR, g, P.state, defl, P.SW);
+        launch_factor_init(c, g, defl, st);
     }
     launch_A<true>(c, g, tol, max_iter, defl, st);
     if (max_iter > 0) {
         if (mode == 0) {
             k_pcg_B<<<g, BS, 0, st>>>(nr, M, P.d, P.q, P.x, P.r[0], P.z, P.pA, P.pR, g, P.state, defl, P.SW);
         } else {
-            k_pcg_Bf<<<g, BS, 0, st>>>(nr, c->fs.ptr, c->fs.J, c->fs.Gl, P.d, P.q, P.x,
-                                       P.r[0], P.r[1], P.t, P.pA, P.pR, g, P.state);
-            k_pcg_Cf<false><<<g, BS, 0, st>>>(nr, c->fs.gu_ptr, c->fs.gu_col, c->fs.Gu, P.t, P.r[0],
-                                              P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
+            launch_factor_step(c, g, defl, st);
         }
     }
     // remaining iterations in fixed batches (a captured graph when possible);
@@ -1116,19 +1236,8 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
 // y = S x in the layout selected for the next solve (c->upper, c->s32)
 void launch_product(ba_ctx* c, const double* x, double* y) {
     if (c->n_rows == 0) return;
-    ensure_sf(c);
-    const int nr = c->n_rows, g = grid_of(nr);
-    hipStream_t st = c->stream;
-    if (c->upper) {
-        Pcg& P = c->pcg;
-        if (c->s32)
-            k_upper_part<true, float><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->Su32, x, P.u, P.tb);
-        else
-            k_upper_part<false, double><<<g, BS, 0, st>>>(nr, c->row_ptr, c->col_idx, c->blk, x, P.u, P.tb);
-        k_upper_sum<<<g, BS, 0, st>>>(nr, c->lo_ptr, c->lo_blk, P.u, P.tb, y);
-    } else {
-        launch_spmv_cur(c, x, y, st);
-    }
+    ensure_sf(c, false);
+    product_cur(c, x, y, c->stream);
 }
 
 }  // namespace ba

@@ -171,3 +171,27 @@ def test_product_argument_errors(formed):
         assert ei.value.status == ba.BA_ERR_INVALID_ARG
     finally:
         ba.ba_destroy(ctx)
+
+
+@pytest.mark.parametrize("product", [1, 2])
+def test_pcg_from_initial_guess(formed, product):
+    """x0 given: the initial product S x0 in each layout; the solve from it
+    reaches the solution of the stored system."""
+    _, s, uv, _, b = formed
+    ctx = create(s, uv, 0)
+    try:
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-3)
+        rp, ci = ba.ba_get_pattern(ctx)
+        blk, _ = ba.ba_get_rcs(ctx)
+        n = len(rp) - 1
+        dx = torch.empty((n, 9), dtype=torch.float64, device="cuda")
+        ba.ba_pcg_solve(ctx, dx, tol=1e-10, max_iter=5000, product=product)
+        x0 = (0.5 * dx).contiguous()
+        info = ba.ba_pcg_solve(ctx, dx, tol=1e-10, max_iter=5000, x0=x0, product=product)
+        xv = dx.cpu().numpy().ravel()
+    finally:
+        ba.ba_destroy(ctx)
+    assert info["status"] == 0
+    S_own = _dense(blk, rp, ci)
+    assert np.linalg.norm(b - S_own @ xv) <= 1e-9 * np.linalg.norm(b)
