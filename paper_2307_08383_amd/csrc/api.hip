@@ -59,7 +59,7 @@ void free_ctx(ba_ctx* c) {
                     c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.u, c->pcg.tb, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
                     c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
-                    c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.gu_src, c->fs.tg, c->pcg.bm, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G};
+                    c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.gu_src, c->fs.gl_self, c->fs.tg, c->pcg.bm, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -573,13 +573,16 @@ void prepare_learned_fsai(ba_ctx* c) {
     if (!c->fs.built) ba::build_fsai(c);
     auto* g = (ba::gnn::Graph*)c->lgraph;
     ba::gnn::compute_features(*g, c->blk, c->stream);
-    ba::gnn::infer_factor(c->net, *g, c->fs.gu_pos, c->fs.Gl, c->fs.Gu, c->fs.G, c->stream);
+    ba::gnn::infer_factor(c->net, *g, c->upper ? c->fs.gl_self : c->fs.gu_pos, c->fs.Gl, c->fs.Gu, c->fs.G,
+                          c->stream);
+    c->fs.gu_upper = c->upper;
     c->fs.ready = false;   // the layouts now hold the network's factor
 }
 
 // the FSAI factor of the current RCS (index structure on first use)
 void prepare_fsai(ba_ctx* c) {
     if (!c->fs.built) ba::build_fsai(c);
+    if (c->fs.ready && c->fs.gu_upper != c->upper) c->fs.ready = false;
     if (!c->fs.ready) {
         ba::launch_fsai(c);
         BA_HIP_CHECK(hipGetLastError());
@@ -657,6 +660,9 @@ void build_fsai(ba_ctx* c) {
     std::vector<int32_t> gu_src(gu_pos.size());
     for (size_t p = 0; p < gu_pos.size(); ++p) gu_src[gu_pos[p]] = (int32_t)p;
     upload(c, &F.gu_src, gu_src);
+    std::vector<int32_t> gl_self(gu_pos.size());
+    for (size_t p = 0; p < gl_self.size(); ++p) gl_self[p] = (int32_t)p;
+    upload(c, &F.gl_self, gl_self);
     F.max_m = max_m;
     dalloc(c, &F.Gl, J.size() * 81);
     dalloc(c, &F.Gu, J.size() * 81);
@@ -859,11 +865,11 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
     return guarded(c, [&]() {
         int it = 0;
         double rr = 0.0;
+        select_solver_matrix(c, o ? o->solver_fp32 : 0, o ? o->product : BA_PRODUCT_AUTO);
         if (pre == BA_PRECOND_LEARNED && c->n_rows > 0) prepare_learned(c);
         if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
         if (pre == BA_PRECOND_LEARNED_FSAI && c->n_rows > 0) prepare_learned_fsai(c);
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
-        select_solver_matrix(c, o ? o->solver_fp32 : 0, o ? o->product : BA_PRODUCT_AUTO);
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(c->ev[6], c->stream));
         ba_status s = BA_OK;
@@ -954,11 +960,11 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         double rr = 0.0;
         ba_status ps = BA_OK;
         BA_HIP_CHECK(hipEventRecord(ev[14], c->stream));
+        select_solver_matrix(c, o ? o->solver_fp32 : 0, o ? o->product : BA_PRODUCT_AUTO);
         if (pre == BA_PRECOND_LEARNED && c->n_rows > 0) prepare_learned(c);
         if (pre == BA_PRECOND_FSAI && c->n_rows > 0) prepare_fsai(c);
         if (pre == BA_PRECOND_LEARNED_FSAI && c->n_rows > 0) prepare_learned_fsai(c);
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
-        select_solver_matrix(c, o ? o->solver_fp32 : 0, o ? o->product : BA_PRODUCT_AUTO);
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(ev[6], c->stream));
         if (c->n_rows > 0)

@@ -213,6 +213,11 @@ struct Fsai {
     float* An = nullptr;              // [n_blk][81] L_r^-1 S_rc L_c^-T of off-diagonal blocks
     float* G = nullptr;               // [n_blk][81] G in the upper slots
     int32_t* gu_src = nullptr;        // entry of Gl for each entry of Gu (inverse of gu_pos)
+    // Gu holds G^T by rows of G^T (entry gu_pos[e] for Gl entry e; FULL
+    // products), or, with gu_upper, each Gl block transposed at its own
+    // entry (gl_self = identity; the UPPER apply reads columns of G as rows)
+    int32_t* gl_self = nullptr;
+    int gu_upper = 0;
     double* tg = nullptr;             // [entries][9] G_ij^T t_i per entry of Gl (UPPER apply of G^T)
 };
 

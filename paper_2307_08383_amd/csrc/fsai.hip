@@ -260,7 +260,9 @@ void launch_fsai(ba_ctx* c) {
                                                                     c->fs.An);
     if (c->n_rows > 0)
         k_fsai<<<c->n_rows, BS, 0, c->stream>>>(c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.An,
-                                                c->Linv, c->fs.gu_pos, c->fs.G, c->fs.Gl, c->fs.Gu, c->flags);
+                                                c->Linv, c->upper ? c->fs.gl_self : c->fs.gu_pos, c->fs.G, c->fs.Gl,
+                                                c->fs.Gu, c->flags);
+    c->fs.gu_upper = c->upper;
 }
 
 }  // namespace ba

@@ -141,6 +141,19 @@ __device__ __forceinline__ void load_row9(const double* __restrict__ p, double* 
     v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y; v[6] = d.x; v[7] = d.y; v[8] = p[8];
 }
 
+// Column c of a 9x9 block: stored row-major (TR false: nine loads one
+// block row apart, the lanes of a group contiguous) or stored transposed (TR true: one
+// row of the stored block, with wide loads).
+template <bool TR, typename TS>
+__device__ __forceinline__ void load_col9(const TS* __restrict__ b, int c, TS* v) {
+    if (TR) {
+        load_row9(b + c * 9, v);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = b[i * 9 + c];
+    }
+}
+
 // Row gather by one wave over a block-CSR row (entries start..start+n-1,
 // blocks stored row-major in the orientation they are applied in): y[c] =
 // sum_e B_e v_e, returned in lanes 0..8 (component c = lane).  v_e is
@@ -524,39 +537,76 @@ __global__ __launch_bounds__(BS) void k_spmv(int n_rows, const int32_t* __restri
     }
 }
 
-// One-read apply of a factor's transpose: once a wave holds t_row (lanes
-// 0..8 of tv), the transposed products B_e^T t_row of the row's blocks
-// (FP32, stored row-major as applied) are written per entry to tg, from
-// blocks the row's gather has just brought into the cache; lane c of a
-// group of nine forms component c from column c of its block.
-__device__ __forceinline__ void row_transposed(int start, int n, const float* __restrict__ blk, double tv,
+// One-read apply of a factor and its transpose over one block row (FP32
+// blocks B_e with columns col_e, each stored transposed so that a column is
+// one wide load): lane c of a group of nine holds column c of its blocks, so
+//   t_row[i] = sum_e sum_c B_e[i][c] v_e[c]   accumulates in the lane (its
+//              own component of each v_e) and is summed over the wave once;
+//   (B_e^T t_row)[c] = sum_i B_e[i][c] t_row[i]   needs only that lane: written
+//              to tg per entry.
+// v_e = v0[col_e] (VM 0) or v0[col_e] - alpha v1[col_e] (VM 1).  Rows of up
+// to 28 entries keep their blocks in registers between the two products;
+// longer rows load them again.  Returns t_row in lanes 0..8.
+template <int VM>
+__device__ __forceinline__ double row_factor_t(int start, int n, const int32_t* __restrict__ col,
+                                               const float* __restrict__ blkT, const double* __restrict__ v0,
+                                               const double* __restrict__ v1, double alpha,
                                                double* __restrict__ tg) {
     constexpr int U = 4;
     const int lane = threadIdx.x % kWave;
     const int grp = lane / 9, comp = lane % 9;
-    double tr[9];
+    double acc[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) tr[i] = __shfl(tv, i, kWave);
-    if (grp >= GRPW) return;
-    for (int e0 = grp; e0 < n; e0 += GRPW * U) {
-        float bv[U][9];
+    for (int i = 0; i < 9; ++i) acc[i] = 0.0;
+    float bv[U][9];
+    const bool one_round = n <= GRPW * U;   // wave-uniform
+    if (grp < GRPW) {
+        for (int e0 = grp; e0 < n; e0 += GRPW * U) {
+            double x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * GRPW;
-            const int ee = start + (e < n ? e : e0);
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * GRPW;
+                const int ee = start + (e < n ? e : e0);
+                const int cj = col[ee];
+                load_col9<true>(blkT + (int64_t)ee * 81, comp, bv[u]);
+                x[u] = v0[(int64_t)cj * 9 + comp];
+                if (VM == 1) x[u] -= alpha * v1[(int64_t)cj * 9 + comp];
+            }
 #pragma unroll
-            for (int i = 0; i < 9; ++i) bv[u][i] = blk[(int64_t)ee * 81 + i * 9 + comp];
-        }
+            for (int u = 0; u < U; ++u) {
+                if (e0 + u * GRPW >= n) break;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int e = e0 + u * GRPW;
-            if (e >= n) break;
-            double y = 0.0;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) y += (double)bv[u][i] * tr[i];
-            tg[(int64_t)(start + e) * 9 + comp] = y;
+                for (int i = 0; i < 9; ++i) acc[i] += (double)bv[u][i] * x[u];
+            }
         }
     }
+    double t[9], out = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        t[i] = wave_sum(acc[i]);
+        if (lane == i) out = t[i];
+    }
+    if (grp < GRPW) {
+        for (int e0 = grp; e0 < n; e0 += GRPW * U) {
+            if (!one_round) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int e = e0 + u * GRPW;
+                    load_col9<true>(blkT + (int64_t)(start + (e < n ? e : e0)) * 81, comp, bv[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * GRPW;
+                if (e >= n) break;
+                double y = 0.0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) y += (double)bv[u][i] * t[i];
+                tg[(int64_t)(start + e) * 9 + comp] = y;
+            }
+        }
+    }
+    return out;
 }
 
 // init + sum of v[src[a0 + e]][c] for e = 0..n-1 in ascending e (one lane
@@ -578,19 +628,20 @@ __device__ __forceinline__ double index_sum(int a0, int n, const int32_t* __rest
     return acc;
 }
 
-// t = G r (initial step of the factorised preconditioner); UP: also the
-// transposed products G_row,j^T t_row per entry (tg)
+// t = G r (initial step of the factorised preconditioner); UP: from the
+// transposed blocks GlT, with the transposed products G_row,j^T t_row per
+// entry (tg)
 template <bool UP>
 __global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, const int32_t* __restrict__ gl_ptr,
                                                      const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
-                                                     const double* __restrict__ r, double* __restrict__ t,
-                                                     double* __restrict__ tg) {
+                                                     const float* __restrict__ GlT, const double* __restrict__ r,
+                                                     double* __restrict__ t, double* __restrict__ tg) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a = gl_ptr[row], n = gl_ptr[row + 1] - a;
-        const double v = row_gather<float, 0>(a, n, gl_col, Gl, r, nullptr, 0.0);
+        const double v = UP ? row_factor_t<0>(a, n, gl_col, GlT, r, nullptr, 0.0, tg)
+                            : row_gather<float, 0>(a, n, gl_col, Gl, r, nullptr, 0.0);
         if (lane < 9) t[(int64_t)row * 9 + lane] = v;
-        if (UP) row_transposed(a, n, Gl, v, tg);
     }
 }
 
@@ -685,18 +736,6 @@ __global__ __launch_bounds__(BS) void k_pcg_A(int n_rows, const int32_t* __restr
     if (threadIdx.x == 0) pA[blockIdx.x] = t;
 }
 
-// Column c of a 9x9 block: stored row-major (TR false: nine loads 72 bytes
-// apart, lanes of a group contiguous) or stored transposed (TR true: one
-// row of the stored block, with wide loads).
-template <bool TR, typename TS>
-__device__ __forceinline__ void load_col9(const TS* __restrict__ b, int c, TS* v) {
-    if (TR) {
-        load_row9(b + c * 9, v);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) v[i] = b[i * 9 + c];
-    }
-}
 
 // UPPER product, first kernel: the wave of block row r walks the row's
 // stored blocks B_e = S_{r,s_e} (the diagonal block first, then s_e > r);
@@ -909,12 +948,13 @@ __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restri
     if (blockIdx.x == 0 && threadIdx.x == 0) state[3] = k + 1;
 }
 
-// factorised preconditioner, first half: update and t = G r'; UP: also
-// the transposed products G_row,j^T t_row per entry (tg) for the one-read
-// apply of G^T
+// factorised preconditioner, first half: update and t = G r'; UP: from the
+// transposed blocks GlT, with the transposed products G_row,j^T t_row per
+// entry (tg) for the one-read apply of G^T
 template <bool UP>
 __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __restrict__ gl_ptr,
                                                const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
+                                               const float* __restrict__ GlT,
                                                const double* __restrict__ d,
                                                const double* __restrict__ q, double* __restrict__ x,
                                                double* __restrict__ r0buf, double* __restrict__ r1buf,
@@ -940,7 +980,8 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
     double rr = 0.0;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a0 = gl_ptr[row], n = gl_ptr[row + 1] - a0;
-        const double tv = row_gather<float, 1>(a0, n, gl_col, Gl, rin, q, alpha);
+        const double tv = UP ? row_factor_t<1>(a0, n, gl_col, GlT, rin, q, alpha, tg)
+                             : row_gather<float, 1>(a0, n, gl_col, Gl, rin, q, alpha);
         if (lane < 9) {
             const int64_t o = (int64_t)row * 9 + lane;
             x[o] += alpha * d[o];
@@ -949,7 +990,6 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
             if (!UP) t[o] = tv;
             rr += rv * rv;
         }
-        if (UP) row_transposed(a0, n, Gl, tv, tg);
     }
     const double tot = block_total(wave_sum(rr), sh);
     if (threadIdx.x == 0) pR[(int64_t)NP * n_part * ((k + 1) & 1) + (int64_t)NP * blockIdx.x + 1] = tot;
@@ -1049,13 +1089,14 @@ void launch_factor_step(ba_ctx* c, int g, int defl, hipStream_t st) {
     Pcg& P = c->pcg;
     Fsai& F = c->fs;
     const int nr = c->n_rows;
+    if (F.gu_upper != c->upper) throw ba_hip_error(hipErrorInvalidValue, "factor apply (layout of the transposed blocks)", __FILE__, __LINE__);
     if (c->upper) {
-        k_pcg_Bf<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
+        k_pcg_Bf<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
                                          P.pR, g, P.state);
         k_pcg_Cf<false, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0], P.r[1],
                                                 P.z, P.pR, g, P.state, defl, P.SW);
     } else {
-        k_pcg_Bf<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
+        k_pcg_Bf<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
                                           P.pR, g, P.state);
         k_pcg_Cf<false, false><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
                                                  P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
@@ -1067,12 +1108,13 @@ void launch_factor_init(ba_ctx* c, int g, int defl, hipStream_t st) {
     Pcg& P = c->pcg;
     Fsai& F = c->fs;
     const int nr = c->n_rows;
+    if (F.gu_upper != c->upper) throw ba_hip_error(hipErrorInvalidValue, "factor apply (layout of the transposed blocks)", __FILE__, __LINE__);
     if (c->upper) {
-        k_gather_lower<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, P.r[0], P.t, F.tg);
+        k_gather_lower<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg);
         k_pcg_Cf<true, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0], P.r[1],
                                                P.z, P.pR, g, P.state, defl, P.SW);
     } else {
-        k_gather_lower<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, P.r[0], P.t, F.tg);
+        k_gather_lower<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg);
         k_pcg_Cf<true, false><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
                                                 P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
     }

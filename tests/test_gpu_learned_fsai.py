@@ -172,3 +172,36 @@ def test_training_lowers_kaporin_and_iterations():
         for c in ctxs:
             ba.ba_destroy(c)
         ba.ba_gnn_destroy(net)
+
+
+def test_learned_factor_in_both_product_layouts(grid_case):
+    """A non-trivial learned factor applied with the FULL layout (G and a
+    transposed copy by rows of G^T) and with the UPPER layout (transposed
+    blocks in G's own entry order, G^T from per-entry products): the same
+    iterations up to rounding, both solving the system."""
+    s, P, uv, rp, ci, blk, pairs, J, feat = grid_case
+    net = ba.ba_gnn_create(_random_head(5).astype(np.float32))
+    ctx = create(s, uv, 0)
+    try:
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-3)
+        ba.ba_set_preconditioner_net(ctx, net)
+        dxc = torch.empty((P.n_rows, 9), dtype=torch.float64, device="cuda")
+        out = {}
+        for prod in (ba.BA_PRODUCT_FULL, ba.BA_PRODUCT_UPPER, ba.BA_PRODUCT_FULL):
+            info = ba.ba_pcg_solve(ctx, dxc, tol=1e-10, max_iter=5000, precond=ba.BA_PRECOND_LEARNED_FSAI,
+                                   deflate=True, product=prod)
+            assert info["status"] == 0
+            out.setdefault(prod, []).append((info["iters"], dxc.cpu().numpy().copy()))
+    finally:
+        ba.ba_set_preconditioner_net(ctx, None)
+        ba.ba_destroy(ctx)
+        ba.ba_gnn_destroy(net)
+    (i_f, x_f), (i_f2, x_f2) = out[ba.BA_PRODUCT_FULL]
+    (i_u, x_u), = out[ba.BA_PRODUCT_UPPER]
+    # switching layouts back and forth re-emits the factor in the layout used
+    assert i_f2 == i_f and np.array_equal(x_f2, x_f)
+    assert abs(i_u - i_f) <= max(2, 0.05 * i_f)
+    x_ref, _ = P.pcg(tol=1e-12, max_iter=5000)
+    for xv in (x_f, x_u):
+        assert np.linalg.norm(xv - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
