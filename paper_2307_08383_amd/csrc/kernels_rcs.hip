@@ -399,10 +399,13 @@ __global__ __launch_bounds__(BS) void k_pair_sum(int n_lseg, const int32_t* __re
 }
 
 // ---------------------------------------------------------------------------
-// diagonal stage: one workgroup per RCS row over the camera's observations;
-// S_ii = sum J_c^T (I - K K^T) J_c + lambda diag(U), U = sum J_c^T J_c,
-// b_i = -sum J_c^T (e + K lhat), then the block-Jacobi inverse S_ii^-1
-// (Cholesky and triangular inverse).
+// diagonal stage: one wave per RCS row over the camera's observations
+// (four rows per workgroup); S_ii = sum J_c^T (I - K K^T) J_c +
+// lambda diag(U), U = sum J_c^T J_c, b_i = -sum J_c^T (e + K lhat), then the
+// block-Jacobi inverse S_ii^-1 (Cholesky and triangular inverse).  A lane
+// holds 63 FP64 sums, which allows two waves per SIMD: with a wave per row a
+// CU works on eight rows at once, and while one lane of a wave factors its
+// row's block the other waves keep loading.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restrict__ rowobs_ptr,
@@ -411,17 +414,18 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
                                              double* __restrict__ Minv, double* __restrict__ Linv,
                                              int* __restrict__ flags) {
     __shared__ double sred[WPB][64];
-    __shared__ double sS[81];
-    __shared__ double sL[81];
-    const int row = blockIdx.x;
+    __shared__ double sS[WPB][81];
+    __shared__ double sL[WPB][81];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int row = blockIdx.x * WPB + wv;
+    const bool live = row < n_rows;   // wave-uniform; every wave takes part in the barriers
     double A[45], du[9], bb[9];
 #pragma unroll
     for (int m = 0; m < 45; ++m) A[m] = 0.0;
 #pragma unroll
     for (int m = 0; m < 9; ++m) { du[m] = 0.0; bb[m] = 0.0; }
-    const int i0 = rowobs_ptr[row], i1 = rowobs_ptr[row + 1];
-    for (int idx = i0 + threadIdx.x; idx < i1; idx += BS) {
+    const int i0 = live ? rowobs_ptr[row] : 0, i1 = live ? rowobs_ptr[row + 1] : 0;
+    for (int idx = i0 + lane; idx < i1; idx += kWave) {
         const int k = rowobs[idx];
         double jc[18], K[6];
         const T* rk = R + (int64_t)k * kRec;
@@ -447,47 +451,45 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
             for (int c = r; c < 9; ++c, ++m) A[m] += jc[r] * q0[c] + jc[9 + r] * q1[c];
         }
     }
-    // block reduction of the 63 sums: waves by shuffles, then 4 waves via LDS
-    double tot[63];
+    // the wave's 63 sums (fixed shuffle tree), each stored as soon as it is
+    // formed so that the totals do not occupy registers
 #pragma unroll
-    for (int m = 0; m < 45; ++m) tot[m] = wave_sum(A[m]);
+    for (int m = 0; m < 45; ++m) {
+        const double t = wave_sum(A[m]);
+        if (lane == 0) sred[wv][m] = t;
+    }
 #pragma unroll
-    for (int m = 0; m < 9; ++m) { tot[45 + m] = wave_sum(du[m]); tot[54 + m] = wave_sum(bb[m]); }
-    if (lane == 0)
-#pragma unroll
-        for (int m = 0; m < 63; ++m) sred[wv][m] = tot[m];
-    __syncthreads();
-    if (threadIdx.x < 63) {
-        const int m = threadIdx.x;
-        double v = 0.0;
-#pragma unroll
-        for (int w = 0; w < WPB; ++w) v += sred[w][m];
-        sred[0][m] = v;   // wave 0's slot m is only read by this thread
+    for (int m = 0; m < 9; ++m) {
+        const double t = wave_sum(du[m]), w = wave_sum(bb[m]);
+        if (lane == 0) { sred[wv][45 + m] = t; sred[wv][54 + m] = w; }
     }
     __syncthreads();
-    if (threadIdx.x < 81) {
-        const int i = threadIdx.x / 9, j = threadIdx.x % 9;
-        const int a = i < j ? i : j, b = i < j ? j : i;
-        const int m = a * 9 - a * (a - 1) / 2 + (b - a);   // packed upper-triangle index
-        double v = sred[0][m];
-        if (i == j) v += lambda * sred[0][45 + i];
-        sS[threadIdx.x] = v;
-        blk[(int64_t)row_ptr[row] * 81 + threadIdx.x] = v;
-        if (threadIdx.x < 9) rhs[(int64_t)row * 9 + threadIdx.x] = sred[0][54 + threadIdx.x];
+    double* S = sS[wv];
+    double* L = sL[wv];
+    if (live) {
+        for (int e = lane; e < 81; e += kWave) {
+            const int i = e / 9, j = e % 9;
+            const int a = i < j ? i : j, b = i < j ? j : i;
+            const int m = a * 9 - a * (a - 1) / 2 + (b - a);   // packed upper-triangle index
+            double v = sred[wv][m];
+            if (i == j) v += lambda * sred[wv][45 + i];
+            S[e] = v;
+            blk[(int64_t)row_ptr[row] * 81 + e] = v;
+        }
+        if (lane < 9) rhs[(int64_t)row * 9 + lane] = sred[wv][54 + lane];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (live && lane == 0) {
         // Cholesky S = L L^T, then L^-1 in place (lower triangle)
-        double* L = sL;
         bool ok = true;
         for (int j = 0; j < 9; ++j) {
-            double s = sS[j * 9 + j];
-            for (int q = 0; q < j; ++q) s -= L[j * 9 + q] * L[j * 9 + q];
-            if (!(s > 0.0)) { ok = false; s = 1.0; }
-            const double ljj = sqrt(s);
+            double sj = S[j * 9 + j];
+            for (int q = 0; q < j; ++q) sj -= L[j * 9 + q] * L[j * 9 + q];
+            if (!(sj > 0.0)) { ok = false; sj = 1.0; }
+            const double ljj = sqrt(sj);
             L[j * 9 + j] = ljj;
             for (int i = j + 1; i < 9; ++i) {
-                double t = sS[i * 9 + j];
+                double t = S[i * 9 + j];
                 for (int q = 0; q < j; ++q) t -= L[i * 9 + q] * L[j * 9 + q];
                 L[i * 9 + j] = t / ljj;
             }
@@ -504,13 +506,15 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
         }
     }
     __syncthreads();
-    if (threadIdx.x < 81) {
+    if (live) {
         // S^-1 = L^-T L^-1: entry (i, j) = sum_{q >= max(i,j)} Li[q][i] Li[q][j]
-        const int i = threadIdx.x / 9, j = threadIdx.x % 9;
-        double t = 0.0;
-        for (int q = (i > j ? i : j); q < 9; ++q) t += sL[q * 9 + i] * sL[q * 9 + j];
-        Minv[(int64_t)row * 81 + threadIdx.x] = t;
-        Linv[(int64_t)row * 81 + threadIdx.x] = sL[threadIdx.x];
+        for (int e = lane; e < 81; e += kWave) {
+            const int i = e / 9, j = e % 9;
+            double t = 0.0;
+            for (int q = (i > j ? i : j); q < 9; ++q) t += L[q * 9 + i] * L[q * 9 + j];
+            Minv[(int64_t)row * 81 + e] = t;
+            Linv[(int64_t)row * 81 + e] = L[e];
+        }
     }
 }
 
@@ -625,11 +629,11 @@ void launch_offdiag(ba_ctx* c) {
 void launch_diag(ba_ctx* c, double lambda) {
     if (c->n_rows == 0) return;
     if (c->precision == BA_MIXED)
-        k_diag<float><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->row_ptr,
+        k_diag<float><<<(c->n_rows + WPB - 1) / WPB, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->row_ptr,
                                                        (const float*)c->R, c->ebar, lambda, c->blk, c->rhs,
                                                        c->Minv, c->Linv, c->flags);
     else
-        k_diag<double><<<c->n_rows, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->row_ptr,
+        k_diag<double><<<(c->n_rows + WPB - 1) / WPB, BS, 0, c->stream>>>(c->n_rows, c->rowobs_ptr, c->rowobs, c->row_ptr,
                                                         (const double*)c->R, c->ebar, lambda, c->blk, c->rhs,
                                                         c->Minv, c->Linv, c->flags);
 }
