@@ -55,7 +55,7 @@ void free_ctx(ba_ctx* c) {
     void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->chunk_q, c->chunk_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
                     c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->Sf32, c->Su32, c->lo_ptr, c->lo_blk, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->obs_rpos, c->ebar, c->ptL, c->blk, c->rhs, c->Minv,
-                    c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
+                    c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->part2, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
                     c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.u, c->pcg.tb, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
                     c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
@@ -470,6 +470,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &c->dxp, (size_t)np * 3);
     c->n_part = (int32_t)(3 * ((n + 255) / 256) + 8);
     dalloc(c, &c->part, (size_t)c->n_part);
+    dalloc(c, &c->part2, (size_t)3 * ba::kReduceParts);
     dalloc(c, &c->scal, 16);
     dalloc(c, &c->flags, 8);
     Pcg& P = c->pcg;

@@ -285,6 +285,7 @@ struct ba_ctx {
     std::vector<int32_t> h_blk_pairs;  // common points of every block (diagonal: 0)
     // LM
     double *dxc = nullptr, *dxp = nullptr, *part = nullptr, *scal = nullptr;
+    double* part2 = nullptr;           // [3][kReduceParts] first-pass sums of launch_reduce
     int* flags = nullptr;
     double* h_scal = nullptr;          // pinned
     int* h_flags = nullptr;            // pinned
@@ -321,7 +322,9 @@ void launch_linearize(ba_ctx* c, const double* cams, const double* pts);      //
 void launch_point(ba_ctx* c, double lambda);
 // linearize + point stage in one pass (J, e, scal[0] = F, K, point terms)
 void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, double lambda);
-void launch_reduce(const double* part, int n, double* out, hipStream_t st);   // out = sum of part[0..n)
+constexpr int kReduceParts = 1024;   // pieces of the first pass of launch_reduce
+// out[j] = sum of part[j*n .. j*n + n) for j < count (<= 3), fixed order
+void launch_reduce(ba_ctx* c, const double* part, int n, int count, double* out);
 void launch_offdiag(ba_ctx* c);
 void launch_diag(ba_ctx* c, double lambda);
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp);

@@ -2,6 +2,8 @@
 // blocks, Sec. 3.1), candidate-cost / model evaluation and the parameter
 // update of an accepted LM step.  One lane per observation, observations in
 // the context's (point, camera) order so that point reads stream.
+#include <algorithm>
+
 #include "ba_common.hpp"
 
 namespace ba {
@@ -95,14 +97,19 @@ __global__ __launch_bounds__(BS) void k_evaluate(int n, const int32_t* __restric
     }
 }
 
-// out[j] = sum of part[j*n .. j*n + n) in a fixed order (one block per j)
-__global__ __launch_bounds__(BS) void k_reduce(const double* __restrict__ part, int n, double* __restrict__ out) {
+// out[j * ostride + b] = sum of part[j*n + b*chunk .. j*n + min(n, (b+1)*chunk))
+// in a fixed order (block (b, j); b = 0 with chunk >= n sums the whole
+// vector)
+__global__ __launch_bounds__(BS) void k_reduce(const double* __restrict__ part, int n, int chunk,
+                                               double* __restrict__ out, int ostride) {
     __shared__ double sh[BS / kWave];
-    const double* p = part + (int64_t)blockIdx.x * n;
+    const int j = blockIdx.y, b = blockIdx.x;
+    const double* p = part + (int64_t)j * n;
+    const int lo = b * chunk, hi = min(n, lo + chunk);
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += BS) s += p[i];
+    for (int i = lo + threadIdx.x; i < hi; i += BS) s += p[i];
     s = block_sum<BS>(s, sh);
-    if (threadIdx.x == 0) out[blockIdx.x] = s;
+    if (threadIdx.x == 0) out[(int64_t)j * ostride + b] = s;
 }
 
 __global__ __launch_bounds__(BS) void k_update(int n_cams, int n_pts, const int32_t* __restrict__ cam_row,
@@ -135,11 +142,23 @@ void launch_linearize(ba_ctx* c, const double* cams, const double* pts) {
     else
         k_linearize<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_uv, cams, pts,
                                                       (double*)c->R, (double*)c->Jp, c->e, c->part);
-    k_reduce<<<1, BS, 0, c->stream>>>(c->part, nb, c->scal + 0);
+    launch_reduce(c, c->part, nb, 1, c->scal + 0);
 }
 
-void launch_reduce(const double* part, int n, double* out, hipStream_t st) {
-    k_reduce<<<1, BS, 0, st>>>(part, n, out);
+// out[j] = sum of part[j*n .. j*n + n), j < count (count <= 3), in a fixed
+// order: long vectors in two passes (up to kReduceParts contiguous pieces
+// summed by separate blocks into c->part2, then the pieces in order), so
+// that the sum is not left to a single block
+void launch_reduce(ba_ctx* c, const double* part, int n, int count, double* out) {
+    constexpr int kPiece = 2048;
+    if (n <= 2 * kPiece) {
+        k_reduce<<<dim3(1, count), BS, 0, c->stream>>>(part, n, n, out, 1);
+        return;
+    }
+    const int pieces = std::min(kReduceParts, (n + kPiece - 1) / kPiece);
+    const int chunk = (n + pieces - 1) / pieces;
+    k_reduce<<<dim3(pieces, count), BS, 0, c->stream>>>(part, n, chunk, c->part2, kReduceParts);
+    k_reduce<<<dim3(1, count), BS, 0, c->stream>>>(c->part2, kReduceParts, pieces, out, 1);
 }
 
 void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const double* dxc, const double* dxp) {
@@ -150,7 +169,7 @@ void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const dou
     else
         k_evaluate<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts,
                                                      dxc, dxp, (const double*)c->R, (const double*)c->Jp, c->e, c->part, nb);
-    k_reduce<<<3, BS, 0, c->stream>>>(c->part, nb, c->scal + 1);   // scal[1] F', [2] |J dx|^2, [3] dx^T l
+    launch_reduce(c, c->part, nb, 3, c->scal + 1);   // scal[1] F', [2] |J dx|^2, [3] dx^T l
 }
 
 void launch_update(ba_ctx* c, double* cams, double* pts, const double* dxc, const double* dxp) {

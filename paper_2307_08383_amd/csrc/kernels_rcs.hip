@@ -603,7 +603,7 @@ void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, do
         k_linpoint_d<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
                                                      c->obs_uv, cams, pts, lambda, (double*)c->R, (double*)c->Jp,
                                                      c->e, c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
-    launch_reduce(c->part, nb, c->scal + 0, c->stream);
+    launch_reduce(c, c->part, nb, 1, c->scal + 0);
 }
 
 void launch_offdiag(ba_ctx* c) {
