@@ -483,7 +483,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &P.t, (size_t)nr * 9);
     dalloc(c, &P.u, (size_t)nr * 9);
     dalloc(c, &P.tb, (size_t)c->n_blk * 9);
-    dalloc(c, &P.bm, 8);
+    dalloc(c, &P.bm, 8 + 49);
     dalloc(c, &P.pA, 1024);
     dalloc(c, &P.pR, 2 * 9 * 1024);
     dalloc(c, &P.W, (size_t)nr * 63);

@@ -189,7 +189,8 @@ struct Pcg {
     // UPPER product: u [n_rows][9] = the upper blocks' part of S z,
     // tb [n_blk][9] = S_rs^T z_r of each stored block
     double *u = nullptr, *tb = nullptr;
-    double* bm = nullptr;      // [8] beta and mu of the step, from the first UPPER kernel to the second
+    double* bm = nullptr;      // [8] beta and mu of the step, from the first UPPER kernel to the
+                               // second; [8..57) the sums of E = W^T S W (deflation set-up)
 };
 
 // Factorised sparse approximate inverse G (M^-1 = G^T G) on the lower RCS

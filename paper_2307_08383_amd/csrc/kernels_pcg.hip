@@ -374,17 +374,24 @@ __global__ __launch_bounds__(BS) void k_defl_E_part(int n_rows, const double* __
         for (int j = 0; j < kW * kW; ++j) pE[(int64_t)blockIdx.x * kW * kW + j] = t[j];
 }
 
-// E from the partials (block order), symmetrised, then E^-1 by Cholesky
-// (one thread).  A non-positive pivot leaves E^-1 = 0: no deflation.
-__global__ void k_defl_E_fin(int n_part, const double* __restrict__ pE, double* __restrict__ Einv,
-                             int* __restrict__ flags) {
+// E[j] = sum of the partials of entry j over the blocks (one block per
+// entry, fixed order)
+__global__ __launch_bounds__(BS) void k_defl_E_sum(int n_part, const double* __restrict__ pE,
+                                                   double* __restrict__ E) {
+    __shared__ double sh[WPB];
+    const int j = blockIdx.x;
+    double t = 0.0;
+    for (int b = threadIdx.x; b < n_part; b += BS) t += pE[(int64_t)b * kW * kW + j];
+    t = block_sum<BS>(t, sh);
+    if (threadIdx.x == 0) E[j] = t;
+}
+
+// E symmetrised, then E^-1 by Cholesky (one thread).  A non-positive pivot
+// leaves E^-1 = 0: no deflation.
+__global__ void k_defl_E_fin(const double* __restrict__ Esum, double* __restrict__ Einv, int* __restrict__ flags) {
     __shared__ double E[kW * kW];
     const int j = threadIdx.x;
-    if (j < kW * kW) {
-        double t = 0.0;
-        for (int b = 0; b < n_part; ++b) t += pE[(int64_t)b * kW * kW + j];
-        E[j] = t;
-    }
+    if (j < kW * kW) E[j] = Esum[j];
     __syncthreads();
     if (threadIdx.x != 0) return;
     double L[kW * kW], X[kW * kW];
@@ -1192,7 +1199,8 @@ void prepare_deflation(ba_ctx* c) {
         k_spmm_W<double><<<g, BS, 0, st>>>(nr, c->sf_ptr, c->sf_col, c->Sf, P.W, P.SW);
     c->defl_s32 = c->s32;
     k_defl_E_part<<<g, BS, 0, st>>>(nr, P.W, P.SW, P.pE);
-    k_defl_E_fin<<<1, 64, 0, st>>>(g, P.pE, P.Einv, c->flags);
+    k_defl_E_sum<<<kW * kW, BS, 0, st>>>(g, P.pE, P.bm + 8);
+    k_defl_E_fin<<<1, 64, 0, st>>>(P.bm + 8, P.Einv, c->flags);
 }
 
 ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, int max_iter, const double* x0,
