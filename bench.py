@@ -302,7 +302,7 @@ def cpu_baseline(scene, n_form):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build covers the one-GPU share of the "
+        print("bench.py runs on one GPU only: the library covers the one-GPU share of the "
               "problem and uses no collectives; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
