@@ -107,7 +107,7 @@ ba_status ba_form_rcs(ba_ctx* ctx, double lambda);
 typedef struct ba_pcg_opts {
     double tol;                 /* stop when |r_k| / |r_0| <= tol (default 1e-6) */
     int32_t max_iter;           /* iteration cap (default 1000) */
-    int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED or _FSAI */
+    int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED, _FSAI or _LEARNED_FSAI */
     const double* x0;           /* device [n_rows][9] initial guess or NULL (zero) */
     int32_t deflate;            /* 1: deflate the similarity gauge (see ba_get_gauge) */
     int32_t solver_fp32;        /* 1: the products with S read an FP32 copy of S (rounded
@@ -169,7 +169,7 @@ typedef struct ba_lm_state {    /* caller-owned; it is the checkpoint of an LM r
 typedef struct ba_lm_opts {
     double pcg_tol;             /* default 1e-6 */
     int32_t pcg_max_iter;       /* default 1000 */
-    int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED or _FSAI */
+    int32_t precond;            /* BA_PRECOND_BLOCK_JACOBI, _LEARNED, _FSAI or _LEARNED_FSAI */
     int32_t deflate;            /* 1: deflated PCG on the similarity gauge */
     int32_t solver_fp32;        /* 1: PCG products with an FP32 copy of S (see ba_pcg_opts) */
     int32_t product;            /* BA_PRODUCT_AUTO, _FULL or _UPPER (see ba_pcg_opts) */
@@ -268,7 +268,8 @@ ba_status ba_get_stage_ms(ba_ctx* ctx, double* ms4);
  * Parameters: a flat FP32 vector of ba_gnn_param_count() values in the order
  *   Wn[64][64], bn[64], We[96][64], be[64],
  *   3 x (M_l[192][64], c_l[64], U_l[128][64], u_l[64]), Wd[64][48], bd[48],
- *   Wo[192][96], bo[96], ao[96] (factorised head, below)
+ *   Wo1[192][128], bo1[128], Wo2[128][96], bo2[96], ao[96] (factorised head,
+ *   below); 112,496 values in all
  * (row-major, y = x W + b).  Node input (64): the 36 strictly-upper entries
  * of diag(S_ii)^-1/2 S_ii diag(S_ii)^-1/2, then log S_ii[r][r] minus their
  * mean (9), zero padding.  Edge input i->j (96): L_i^-1 S_ij L_j^-T
@@ -282,9 +283,11 @@ ba_status ba_get_stage_ms(ba_ctx* ctx, double* ms4);
  * Factorised head (edge variant, FSAI pattern): M^-1 = G^T G with G block-
  * lower-triangular on the sets J_i of BA_PRECOND_FSAI; in normalised
  * coordinates Ghat = G blockdiag(L), Ghat_ii = Lt_i and, for j in J_i, j < i,
- * Ghat_ij = reshape([h_i, h_j, g_ij] Wo + bo)[:81] - ao[:81] (elementwise)
- * L_i^-1 S_ij L_j^-T, with Wo[192][96], bo[96], ao[96] appended to the
- * parameters above (zero: block-Jacobi).  Its loss is the Kaporin functional
+ *   z_ij = relu([h_i, h_j, g_ij] Wo1 + bo1)                (128 values),
+ *   Ghat_ij = reshape(z_ij Wo2 + bo2)[:81] - ao[:81] (elementwise) L_i^-1 S_ij L_j^-T,
+ * (h after the third layer), with Wo1[192][128], bo1[128], Wo2[128][96],
+ * bo2[96], ao[96] at the end of the parameters above (Wo2, bo2 and ao
+ * zero: block-Jacobi).  Its loss is the Kaporin functional
  * (1/(9n)) sum_i [tr(Ghat_i Ahat[J_i,J_i] Ghat_i^T) - 2 log det Ghat_ii],
  * minimised over the pattern by the exact FSAI factor.
  * A ba_gnn runs its work on its stream (NULL = default); a network and the

@@ -38,3 +38,37 @@ def test_status_strings_without_gpu():
     from paper_2307_08383_amd import ba
     assert ba.ba_status_str(ba.BA_OK) == "ok"
     assert "converge" in ba.ba_status_str(ba.BA_ERR_NOT_CONVERGED)
+
+
+def _documented_param_layout():
+    """(name, shape) list of the network parameters as include/ba.h documents
+    them (the block after "in the order"), with "3 x (...)" expanded."""
+    src = open(os.path.join(ROOT, "include", "ba.h")).read()
+    body = src.split("in the order", 1)[1].split("(row-major", 1)[0]
+    body = re.sub(r"\s*\*\s*", " ", body)
+    body = re.sub(r"\(factorised head,.*?\)", "", body, flags=re.S)
+    out = []
+    for rep, group in re.findall(r"(?:(\d+) x \(([^)]*)\))", body):
+        for _ in range(int(rep)):
+            for name, dims in re.findall(r"([A-Za-z_]+)((?:\[\d+\])+)", group):
+                out.append((name, tuple(int(d) for d in re.findall(r"\d+", dims))))
+        body = body.replace(f"{rep} x ({group})", "@LAYERS@", 1)
+    pre, post = body.split("@LAYERS@")
+    ent = lambda s: [(n, tuple(int(d) for d in re.findall(r"\d+", ds)))
+                     for n, ds in re.findall(r"([A-Za-z_0-9]+)((?:\[\d+\])+)", s)]
+    return ent(pre) + out + ent(post)
+
+
+def test_documented_network_layout_matches_library_and_reference():
+    """The header's parameter list has the library's parameter count and the
+    shapes, in order, of the CPU reference network."""
+    import numpy as np
+    from oracle import gnn_ref
+    from paper_2307_08383_amd import ba
+    doc = _documented_param_layout()
+    n_doc = sum(int(np.prod(s)) for _, s in doc)
+    assert n_doc == ba.ba_gnn_param_count()
+    ref = [tuple(s) for _, s in gnn_ref.PARAM_SHAPES]
+    assert [s for _, s in doc] == ref
+    assert [n for n, _ in doc][-5:] == ["Wo1", "bo1", "Wo2", "bo2", "ao"]
+    assert f"{n_doc:,} values in all" in open(os.path.join(ROOT, "include", "ba.h")).read()
