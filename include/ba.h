@@ -48,7 +48,9 @@ typedef enum ba_status {
     BA_ERR_NOT_SPD = 3,        /* a damped V_p, an RCS diagonal block or d^T S d was not positive */
     BA_ERR_NOT_CONVERGED = 4,  /* warning: PCG hit max_iter; its result is still returned */
     BA_ERR_OUT_OF_MEMORY = 5,  /* device allocation failed (or the workspace cap was exceeded) */
-    BA_ERR_DEVICE = 6          /* a HIP runtime call failed */
+    BA_ERR_DEVICE = 6,         /* a HIP runtime call failed */
+    BA_ERR_RANGE = 7           /* a Jacobian entry does not fit the record type (above 3.4e38 for
+                                  the FP32 records of mixed precision) or a residual is not finite */
 } ba_status;
 
 enum { BA_FP64 = 0, BA_MIXED = 1 };
@@ -94,14 +96,18 @@ void ba_destroy(ba_ctx* ctx);
 /* Sec. 3.1: residuals e and Jacobian blocks J_c (2x9) and J_p (2x3) of every
  * observation at cams (device [n_cams][9]) and pts (device [n_pts][3]);
  * cost F = 1/2 sum |e|^2 in FP64 is written to *cost_host when non-NULL
- * (this synchronises).  The parameters are read during the call only. */
+ * (this synchronises; then BA_ERR_RANGE is returned if a Jacobian entry
+ * does not fit the record type or a residual is not finite, and
+ * ba_form_rcs reports it in any case).  The parameters are read during the
+ * call only. */
 ba_status ba_linearize(ba_ctx* ctx, const double* cams, const double* pts, double* cost_host);
 
 /* Eq. (3)-(4), Sec. 5: forms the RCS S = U* - W V*^-1 W^T and its right-hand
  * side b = l_c - W V*^-1 l_p from the last linearization with damping
  * lambda >= 0, plus the block-Jacobi factors of its diagonal blocks.
  * Errors: BA_ERR_STATE (no linearization), BA_ERR_INVALID_ARG (lambda < 0 or
- * not finite), BA_ERR_NOT_SPD (a V*_p or S_ii is not positive definite). */
+ * not finite), BA_ERR_RANGE (the linearization did not fit the records),
+ * BA_ERR_NOT_SPD (a V*_p or S_ii is not positive definite). */
 ba_status ba_form_rcs(ba_ctx* ctx, double lambda);
 
 typedef struct ba_pcg_opts {
@@ -137,13 +143,18 @@ typedef struct ba_pcg_info {
     int32_t status;             /* BA_OK, BA_ERR_NOT_CONVERGED or BA_ERR_NOT_SPD */
     double relres;              /* final |r| / |r_0| */
     double ms;                  /* device time of the solve */
+    int32_t precond_fallback;   /* 1: the learned preconditioner failed (d^T S d <= 0 or a
+                                   non-finite residual) and the result is block-Jacobi's */
+    int32_t reserved;
 } ba_pcg_info;
 
 /* Sec. 3.2, Eq. (6)-(7): preconditioned CG on S dxc = b with M = the
  * block-diagonal of S (or the learned preconditioner, see below); result in
  * dxc (device [n_rows][9]).  opts may be NULL for the defaults.  Returns
  * BA_ERR_NOT_CONVERGED (dxc still valid) or BA_ERR_NOT_SPD as warnings/errors;
- * BA_ERR_STATE without a formed RCS. */
+ * BA_ERR_STATE without a formed RCS.  A learned preconditioner that fails
+ * (d^T S d <= 0, or a non-finite residual) is replaced by block-Jacobi for
+ * the same solve, reported in info->precond_fallback. */
 ba_status ba_pcg_solve(ba_ctx* ctx, const ba_pcg_opts* opts, double* dxc, ba_pcg_info* info_host);
 
 /* Sec. 6.2: y = S x with the RCS formed last, computed as one product of a
@@ -187,6 +198,10 @@ typedef struct ba_lm_info {
     int32_t stop;               /* 1 if an accepted step lowered F by < 1e-12 relative */
     double ms_linearize, ms_form_rcs, ms_pcg, ms_back_substitute, ms_evaluate, ms_total;
     double ms_precond;          /* learned preconditioner inference (0 for block-Jacobi) */
+    int32_t precond_fallback;   /* 1: the learned preconditioner failed on this step's RCS
+                                   (d^T S d <= 0 or a non-finite residual) and the step was
+                                   solved again with block-Jacobi */
+    int32_t reserved;
 } ba_lm_info;
 
 /* One LM iteration (Eq. (1) solved through Eq. (4)-(7) and (5)): linearize
@@ -196,7 +211,11 @@ typedef struct ba_lm_info {
  * pts (device, updated in place) take the step and
  * lambda *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; otherwise lambda *= nu,
  * nu *= 2 and the parameters are untouched.  Every attempt counts one
- * iteration.  opts may be NULL for the defaults. */
+ * iteration.  A learned preconditioner that fails on the step's RCS is
+ * replaced by block-Jacobi within the step (info->precond_fallback).
+ * BA_ERR_RANGE: the linearization did not fit the records (see
+ * ba_linearize); no step is taken and state is unchanged.
+ * opts may be NULL for the defaults. */
 ba_status ba_lm_step(ba_ctx* ctx, double* cams, double* pts, ba_lm_state* state,
                      const ba_lm_opts* opts, ba_lm_info* info_host);
 

@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libba.so")
 
-BA_OK, BA_ERR_INVALID_ARG, BA_ERR_STATE, BA_ERR_NOT_SPD, BA_ERR_NOT_CONVERGED, BA_ERR_OUT_OF_MEMORY, BA_ERR_DEVICE = range(7)
+(BA_OK, BA_ERR_INVALID_ARG, BA_ERR_STATE, BA_ERR_NOT_SPD, BA_ERR_NOT_CONVERGED, BA_ERR_OUT_OF_MEMORY, BA_ERR_DEVICE,
+ BA_ERR_RANGE) = range(8)
 BA_FP64, BA_MIXED = 0, 1
 BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED, BA_PRECOND_FSAI, BA_PRECOND_LEARNED_FSAI = 0, 1, 2, 3
 BA_PRODUCT_AUTO, BA_PRODUCT_FULL, BA_PRODUCT_UPPER = 0, 1, 2
@@ -36,7 +37,8 @@ class PcgOpts(C.Structure):
 
 
 class PcgInfo(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double), ("ms", C.c_double)]
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("relres", C.c_double), ("ms", C.c_double),
+                ("precond_fallback", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LMState(C.Structure):
@@ -54,7 +56,8 @@ class LMInfo(C.Structure):
                 ("pcg_iters", C.c_int32), ("pcg_status", C.c_int32), ("accepted", C.c_int32),
                 ("stop", C.c_int32), ("ms_linearize", C.c_double), ("ms_form_rcs", C.c_double),
                 ("ms_pcg", C.c_double), ("ms_back_substitute", C.c_double),
-                ("ms_evaluate", C.c_double), ("ms_total", C.c_double), ("ms_precond", C.c_double)]
+                ("ms_evaluate", C.c_double), ("ms_total", C.c_double), ("ms_precond", C.c_double),
+                ("precond_fallback", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -184,7 +187,8 @@ def ba_pcg_solve(ctx, dxc, tol=1e-6, max_iter=1000, precond=BA_PRECOND_BLOCK_JAC
     info = PcgInfo()
     st = _check(lib().ba_pcg_solve(ctx, C.byref(o), _ptr(dxc), C.byref(info)), ctx,
                 allow=(BA_ERR_NOT_CONVERGED,))
-    return dict(iters=info.iters, status=info.status, relres=info.relres, ms=info.ms, returned=st)
+    return dict(iters=info.iters, status=info.status, relres=info.relres, ms=info.ms,
+                precond_fallback=info.precond_fallback, returned=st)
 
 
 def ba_rcs_product(ctx, x, y, product=BA_PRODUCT_AUTO, solver_fp32=False):

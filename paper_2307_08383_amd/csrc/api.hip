@@ -22,6 +22,9 @@ using ba::Pcg;
 
 thread_local std::string g_create_error;
 
+const char* const kRangeMsg =
+    "a Jacobian entry exceeds the range of the record type (FP32 in mixed precision) or a residual is not finite";
+
 struct ba_oom {
     std::string what;
 };
@@ -531,7 +534,11 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 
 // point_done: the point stage already ran, fused with the linearization
 ba_status form_rcs_async(ba_ctx* c, double lambda, bool point_done = false) {
-    if (!point_done) BA_HIP_CHECK(hipMemsetAsync(c->flags, 0, 8 * sizeof(int), c->stream));
+    if (!point_done) {
+        // flags[2] (records out of range) belongs to the linearization and stays
+        BA_HIP_CHECK(hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->stream));
+        BA_HIP_CHECK(hipMemsetAsync(c->flags + 3, 0, 5 * sizeof(int), c->stream));
+    }
     BA_HIP_CHECK(hipEventRecord(c->ev[1], c->stream));
     if (!point_done) ba::launch_point(c, lambda);
     BA_HIP_CHECK(hipEventRecord(c->ev[2], c->stream));
@@ -589,6 +596,14 @@ void prepare_fsai(ba_ctx* c) {
         BA_HIP_CHECK(hipGetLastError());
         c->fs.ready = true;
     }
+}
+
+// a learned preconditioner gave a solve that cannot be used: d^T S d was
+// not positive (non-finite or indefinite preconditioner) or the residual is
+// not finite; block-Jacobi then solves the system instead
+bool learned_failed(int pre, ba_status s, double relres) {
+    return (pre == BA_PRECOND_LEARNED || pre == BA_PRECOND_LEARNED_FSAI) &&
+           (s == BA_ERR_NOT_SPD || !std::isfinite(relres));
 }
 
 // network inference on the current RCS -> Mlearn (context stream)
@@ -725,6 +740,7 @@ const char* ba_status_str(ba_status s) {
         case BA_ERR_NOT_CONVERGED: return "PCG did not converge";
         case BA_ERR_OUT_OF_MEMORY: return "out of memory";
         case BA_ERR_DEVICE: return "HIP runtime error";
+        case BA_ERR_RANGE: return "value outside the range of the record type";
     }
     return "unknown status";
 }
@@ -799,6 +815,7 @@ ba_status ba_linearize(ba_ctx* c, const double* cams, const double* pts, double*
     if (!cams || !pts) { c->err = "null parameter arrays"; return BA_ERR_INVALID_ARG; }
     return guarded(c, [&]() {
         BA_HIP_CHECK(hipEventRecord(c->ev[0], c->stream));
+        BA_HIP_CHECK(hipMemsetAsync(c->flags + 2, 0, sizeof(int), c->stream));
         ba::launch_linearize(c, cams, pts);
         BA_HIP_CHECK(hipMemcpyAsync(c->lin_cams, cams, (size_t)c->n_cams * 9 * sizeof(double),
                                     hipMemcpyDeviceToDevice, c->stream));
@@ -809,8 +826,10 @@ ba_status ba_linearize(ba_ctx* c, const double* cams, const double* pts, double*
         c->have_rcs = false;
         if (cost_host) {
             BA_HIP_CHECK(hipMemcpyAsync(c->h_scal, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            BA_HIP_CHECK(hipMemcpyAsync(c->h_flags + 2, c->flags + 2, sizeof(int), hipMemcpyDeviceToHost, c->stream));
             BA_HIP_CHECK(hipStreamSynchronize(c->stream));
             *cost_host = c->h_scal[0];
+            if (c->h_flags[2]) { c->err = kRangeMsg; return BA_ERR_RANGE; }
         }
         return BA_OK;
     });
@@ -822,8 +841,9 @@ ba_status ba_form_rcs(ba_ctx* c, double lambda) {
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) { c->err = "lambda must be finite and >= 0"; return BA_ERR_INVALID_ARG; }
     return guarded(c, [&]() {
         form_rcs_async(c, lambda);
-        BA_HIP_CHECK(hipMemcpyAsync(c->h_flags, c->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(c->h_flags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
         BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        if (c->h_flags[2]) { c->err = kRangeMsg; return BA_ERR_RANGE; }
         if (c->h_flags[0]) { c->err = "a damped point block V* is not positive definite"; return BA_ERR_NOT_SPD; }
         if (c->h_flags[1]) { c->err = "an RCS diagonal block is not positive definite"; return BA_ERR_NOT_SPD; }
         return BA_OK;
@@ -874,9 +894,15 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(c->ev[6], c->stream));
         ba_status s = BA_OK;
-        if (c->n_rows > 0)
+        int fell_back = 0;
+        if (c->n_rows > 0) {
             s = ba::run_pcg(c, (pre == BA_PRECOND_FSAI || pre == BA_PRECOND_LEARNED_FSAI) ? 1 : 0, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, defl,
                             tol, max_iter, o ? o->x0 : nullptr, dxc, &it, &rr);
+            if (learned_failed(pre, s, rr)) {
+                fell_back = 1;
+                s = ba::run_pcg(c, 0, c->Minv, defl, tol, max_iter, o ? o->x0 : nullptr, dxc, &it, &rr);
+            }
+        }
         BA_HIP_CHECK(hipEventRecord(c->ev[7], c->stream));
         BA_HIP_CHECK(hipEventSynchronize(c->ev[7]));
         if (info) {
@@ -884,6 +910,8 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
             info->status = s;
             info->relres = rr;
             info->ms = elapsed(c->ev[6], c->ev[7]);
+            info->precond_fallback = fell_back;
+            info->reserved = 0;
         }
         if (s == BA_ERR_NOT_SPD) c->err = "d^T S d <= 0 in PCG";
         if (s == BA_ERR_NOT_CONVERGED) c->err = "PCG reached max_iter";
@@ -968,10 +996,16 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         const int defl = (o && o->deflate && c->n_rows > 0) ? 1 : 0;
         if (defl) prepare_defl(c);
         BA_HIP_CHECK(hipEventRecord(ev[6], c->stream));
-        if (c->n_rows > 0)
+        if (c->n_rows > 0) {
             ps = ba::run_pcg(c, (pre == BA_PRECOND_FSAI || pre == BA_PRECOND_LEARNED_FSAI) ? 1 : 0, pre == BA_PRECOND_LEARNED ? c->Mlearn : c->Minv, defl,
                              tol, max_iter, nullptr, c->dxc, &it, &rr);
-        else
+            if (learned_failed(pre, ps, rr)) {
+                // the network's preconditioner is not usable on this RCS (not
+                // SPD, or non-finite): solve again with block-Jacobi
+                I.precond_fallback = 1;
+                ps = ba::run_pcg(c, 0, c->Minv, defl, tol, max_iter, nullptr, c->dxc, &it, &rr);
+            }
+        } else
             BA_HIP_CHECK(hipMemsetAsync(c->dxc, 0, sizeof(double), c->stream));
         BA_HIP_CHECK(hipEventRecord(ev[7], c->stream));
         ba::launch_back_substitute(c, c->dxc, c->dxp);
@@ -979,7 +1013,7 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         ba::launch_evaluate(c, cams, pts, c->dxc, c->dxp);
         BA_HIP_CHECK(hipEventRecord(ev[10], c->stream));
         BA_HIP_CHECK(hipMemcpyAsync(c->h_scal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        BA_HIP_CHECK(hipMemcpyAsync(c->h_flags, c->flags, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(c->h_flags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
         BA_HIP_CHECK(hipStreamSynchronize(c->stream));
         BA_HIP_CHECK(hipGetLastError());
         const double F = c->h_scal[0], Fn = c->h_scal[1], jdx2 = c->h_scal[2], dxl = c->h_scal[3];
@@ -991,6 +1025,15 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         I.pcg_iters = it;
         I.pcg_status = ps;
         I.pcg_relres = rr;
+        if (c->h_flags[2]) {
+            // the linearization does not fit the records: no step is taken and
+            // the state is left as it was
+            BA_HIP_CHECK(hipEventRecord(ev[11], c->stream));
+            BA_HIP_CHECK(hipEventSynchronize(ev[11]));
+            if (info) *info = I;
+            c->err = kRangeMsg;
+            return BA_ERR_RANGE;
+        }
         const bool formed = !c->h_flags[0] && !c->h_flags[1];
         if (!formed) I.pcg_status = BA_ERR_NOT_SPD;
         const bool ok = formed && (ps == BA_OK || ps == BA_ERR_NOT_CONVERGED) && L > 0.0 && std::isfinite(Fn) && Fn < F;

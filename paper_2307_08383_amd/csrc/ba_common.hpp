@@ -106,6 +106,19 @@ __device__ __forceinline__ void project_point(const double* __restrict__ c, doub
     Jp[5] = E10 * R02 + E11 * R12 + E12 * R22;
 }
 
+// The Jacobian blocks of an observation fit the record type T (FP32 records
+// overflow above 3.4e38) and the residual is finite.  NaN compares false.
+template <typename T>
+__device__ __forceinline__ bool records_in_range(const double* Jc, const double* Jp, double eu, double ev) {
+    constexpr double kMax = sizeof(T) == 4 ? 3.4028234663852886e38 : 1.7976931348623157e308;
+    bool ok = fabs(eu) <= 1.7976931348623157e308 && fabs(ev) <= 1.7976931348623157e308;
+#pragma unroll
+    for (int m = 0; m < 18; ++m) ok = ok && fabs(Jc[m]) <= kMax;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) ok = ok && fabs(Jp[m]) <= kMax;
+    return ok;
+}
+
 // Typed record access (T = double, or float for the mixed-precision path).
 // Records start on 16-byte boundaries (24 values of 8 or 4 bytes); the K part
 // and the separate J_p rows are 8-byte aligned.

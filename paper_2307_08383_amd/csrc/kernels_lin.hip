@@ -29,7 +29,8 @@ template <typename T>
 __global__ __launch_bounds__(BS) void k_linearize(int n, const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_pt,
                                                   const double* __restrict__ uv, const double* __restrict__ cams,
                                                   const double* __restrict__ pts, T* __restrict__ R, T* __restrict__ Jp_out,
-                                                  double* __restrict__ e, double* __restrict__ part) {
+                                                  double* __restrict__ e, double* __restrict__ part,
+                                                  int* __restrict__ flags) {
     __shared__ double sh[BS / kWave];
     const int k = blockIdx.x * BS + threadIdx.x;
     double cost = 0.0;
@@ -38,6 +39,7 @@ __global__ __launch_bounds__(BS) void k_linearize(int n, const int32_t* __restri
         double pu, pv, Jc[18], Jp[6];
         project_point<true>(cams + (int64_t)obs_cam[k] * 9, X[0], X[1], X[2], pu, pv, Jc, Jp);
         const double eu = pu - uv[k], ev = pv - uv[n + k];
+        if (!records_in_range<T>(Jc, Jp, eu, ev)) flags[2] = 1;
         store_jc(R + (int64_t)k * kRec, Jc);
         store6(Jp_out + (int64_t)k * 6, Jp);
         reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
@@ -138,10 +140,10 @@ void launch_linearize(ba_ctx* c, const double* cams, const double* pts) {
     const int n = (int)c->n_obs, nb = nblk(n);
     if (c->precision == BA_MIXED)
         k_linearize<float><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_uv, cams, pts,
-                                                     (float*)c->R, (float*)c->Jp, c->e, c->part);
+                                                     (float*)c->R, (float*)c->Jp, c->e, c->part, c->flags);
     else
         k_linearize<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_uv, cams, pts,
-                                                      (double*)c->R, (double*)c->Jp, c->e, c->part);
+                                                      (double*)c->R, (double*)c->Jp, c->e, c->part, c->flags);
     launch_reduce(c, c->part, nb, 1, c->scal + 0);
 }
 

@@ -186,12 +186,13 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
         const double* X = pts + (int64_t)p * 3;
         double pu, pv;
         project_point<true>(cams + (int64_t)obs_cam[k] * 9, X[0], X[1], X[2], pu, pv, jc, jp);
+        eu = pu - uv[k];
+        ev = pv - uv[n + k];
+        if (!records_in_range<T>(jc, jp, eu, ev)) flags[2] = 1;
 #pragma unroll
         for (int m = 0; m < 18; ++m) jc[m] = (double)(T)jc[m];
 #pragma unroll
         for (int m = 0; m < 6; ++m) jp[m] = (double)(T)jp[m];
-        eu = pu - uv[k];
-        ev = pv - uv[n + k];
         store6(Jp_out + (int64_t)k * 6, jp);
         reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
         cost = 0.5 * (eu * eu + ev * ev);

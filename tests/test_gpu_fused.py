@@ -1,0 +1,111 @@
+"""The linearization fused with the point stage (the path every LM step takes
+when it relinearizes) against the oracle, element by element (needs a GPU).
+
+ba_lm_step forms J, e, the point terms and the RCS with the fused kernel;
+the context keeps them, so after a step the getters return what that
+kernel wrote.  They are compared with
+  - the oracle at the same parameters and damping (Sec. 3.1 Eq. (1),
+    Eq. (3)-(4); back-substitution Eq. (5) through the point terms):
+    J to 1e-11 (FP64) / 1e-6 (FP32 records) of each row's scale, RCS blocks
+    to 1e-10 / 1e-4 in the floored per-block metric, rhs 1e-9 / 1e-4;
+  - the separate kernels (ba_linearize + ba_form_rcs) at the same inputs:
+    the same rounding steps, so J, e and every RCS block are bit-identical.
+Both the first step (from the start) and the step after an accepted one
+are checked."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_2307_08383_amd import scenegen
+
+from gpu_util import T, block_errors, create
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+ba = pytest.importorskip("paper_2307_08383_amd.ba")
+
+
+def _scene(kind):
+    if kind == "tiny":
+        return scenegen.tiny_scene(seed=0, with_stats=False)
+    s = scenegen.aerial_grid_scene(seed=4, nx=10, ny=8, n_pts=20000, with_stats=False)
+    if kind == "fixed":
+        s.cam_fixed[[0, 9, 40, 79]] = 1
+    return s
+
+
+def _check_against_oracle(ctx, P, cams, pts, lam, precision, rng):
+    """J, e, RCS and the point terms (through back-substitution) of ctx
+    against the oracle at (cams, pts, lam)."""
+    F_ref = P.linearize(cams, pts)
+    P.form_rcs(lam)
+    e_ref, Jc, Jp = P.linearization()
+    J, e = ba.ba_get_jacobians(ctx)
+    J_ref = np.concatenate([Jc.reshape(-1, 18), Jp.reshape(-1, 6)], axis=1)
+    scale = np.abs(J_ref).max(axis=1, keepdims=True)
+    jtol = 1e-11 if precision == 0 else 1e-6
+    assert (np.abs(J - J_ref) / scale).max() <= jtol
+    np.testing.assert_allclose(e, e_ref, rtol=0, atol=1e-9)
+    blk, rhs = ba.ba_get_rcs(ctx)
+    blk_ref, rhs_ref = P.rcs()
+    rp, ci = P.pattern()
+    errs, raw = block_errors(blk, blk_ref, rp, ci)
+    assert errs.max() <= (1e-10 if precision == 0 else 1e-4), (errs.max(), raw.max())
+    rerr = np.linalg.norm(rhs - rhs_ref, axis=1) / np.linalg.norm(rhs_ref, axis=1)
+    assert rerr.max() <= (1e-9 if precision == 0 else 1e-4), rerr.max()
+    # back-substitution reads the point terms (Cholesky factor of V*, L^-1 l_p)
+    # that the fused kernel stored
+    dxc = rng.standard_normal((P.n_rows, 9)) * 1e-3
+    dxp = torch.empty((P.n_pts, 3), dtype=torch.float64, device="cuda")
+    ba.ba_back_substitute(ctx, T(dxc, torch.float64), dxp)
+    dxp_ref = P.back_substitute(dxc)
+    btol = 1e-10 if precision == 0 else 1e-4
+    assert np.abs(dxp.cpu().numpy() - dxp_ref).max() <= btol * np.abs(dxp_ref).max()
+    return F_ref, J, e, blk, rhs
+
+
+def _separate(scene, uv, precision, cams, pts, lam):
+    """J, e, RCS from ba_linearize + ba_form_rcs in a fresh context."""
+    ctx = create(scene, uv, precision)
+    try:
+        ba.ba_linearize(ctx, T(cams, torch.float64), T(pts, torch.float64))
+        ba.ba_form_rcs(ctx, lam)
+        J, e = ba.ba_get_jacobians(ctx)
+        blk, rhs = ba.ba_get_rcs(ctx)
+    finally:
+        ba.ba_destroy(ctx)
+    return J, e, blk, rhs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("kind", ["tiny", "mid", "fixed"])
+def test_fused_path_elementwise(kind, precision):
+    s = _scene(kind)
+    uv = orc.observations(s)
+    P = orc.Problem.from_scene(s, uv)
+    rng = np.random.default_rng(17)
+    ctx = create(s, uv, precision)
+    try:
+        cams = T(s.cams_init, torch.float64)
+        pts = T(s.pts_init, torch.float64)
+        st = ba.new_lm_state(1e-4)
+        checked_after_accept = False
+        for step in range(4):
+            c0, p0, lam0 = cams.cpu().numpy().copy(), pts.cpu().numpy().copy(), st.lam
+            relin = not (st.flags & 1)
+            info = ba.ba_lm_step(ctx, cams, pts, st)
+            if not relin:
+                continue
+            F_ref, J, e, blk, rhs = _check_against_oracle(ctx, P, c0, p0, lam0, precision, rng)
+            assert abs(info["cost"] - F_ref) <= 1e-11 * F_ref
+            J2, e2, blk2, rhs2 = _separate(s, uv, precision, c0, p0, lam0)
+            assert np.array_equal(J, J2) and np.array_equal(e, e2)
+            assert np.array_equal(blk, blk2) and np.array_equal(rhs, rhs2)
+            if step > 0:
+                checked_after_accept = True
+                break
+            assert info["accepted"] == 1
+        assert checked_after_accept
+    finally:
+        ba.ba_destroy(ctx)

@@ -206,15 +206,41 @@ def test_lm_trajectory(precision):
         st = ba.new_lm_state(1e-4)
         hist = []
         for _ in range(10):
-            hist.append(ba.ba_lm_step(ctx, cams, pts, st))
+            lam0, nu0 = st.lam, st.nu
+            h = ba.ba_lm_step(ctx, cams, pts, st)
+            h.update(lam_factor=st.lam / lam0, nu_after=st.nu, nu_before=nu0)
+            hist.append(h)
         # each step solves the RCS only to PCG rel 1e-6, so iterates agree to
         # about that level; the cost of each iterate is compared at 1e-6
         tol = 1e-6 if precision == 0 else 1e-5
+        lam_prev, nu_ref = 1e-4, 2.0
+        n_acc = n_rej = 0
+        in_sync = True   # every earlier decision agreed (a tie may go either way)
         for h, r in zip(hist, hist_ref):
-            # decisions are compared while the step is far from a tie
-            if (r["cost"] - r["cost_new"]) > 1e-8 * r["cost"]:
+            # oracle's damping factor of this step and its nu afterwards
+            r_factor = r["lambda_after"] / lam_prev
+            lam_prev = r["lambda_after"]
+            nu_ref_before = nu_ref
+            nu_ref = 2.0 if r["accepted"] else 2.0 * nu_ref
+            # decisions (accept and reject) are compared while the step is far
+            # from a tie
+            if abs(r["cost"] - r["cost_new"]) > 1e-8 * r["cost"]:
                 assert h["accepted"] == r["accepted"]
                 assert abs(h["cost"] - r["cost"]) <= tol * r["cost"]
+            if h["accepted"] != r["accepted"]:
+                in_sync = False
+            if in_sync and abs(r["cost"] - r["cost_new"]) > 1e-8 * r["cost"]:
+                assert h["nu_before"] == nu_ref_before and h["nu_after"] == nu_ref
+                if r["accepted"]:
+                    n_acc += 1
+                    # lambda *= max(1/3, 1 - (2 rho - 1)^3): compared where the
+                    # gain ratio is well resolved by both sides' costs
+                    if r["cost"] - r["cost_new"] > 1e-4 * r["cost"]:
+                        assert h["lam_factor"] == pytest.approx(r_factor, rel=1e-3 if precision == 0 else 1e-2)
+                else:
+                    n_rej += 1
+                    assert h["lam_factor"] == r_factor == nu_ref_before
+        assert n_acc >= 3
         F_fin = min(h["cost_new"] if h["accepted"] else h["cost"] for h in hist)
         F_ref_fin = min(h["cost_new"] if h["accepted"] else h["cost"] for h in hist_ref)
         assert abs(F_fin - F_ref_fin) <= 1e-6 * F_ref_fin
@@ -307,3 +333,89 @@ def test_workspace_cap_out_of_memory():
         b.ba_create(s.n_cams, s.n_pts, T(s.obs_cam, torch.int32), T(s.obs_pt, torch.int32),
                     T(uv, torch.float64), workspace_cap=4096)
     assert ei.value.status == b.BA_ERR_OUT_OF_MEMORY
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_formation_not_spd(precision):
+    """BA_ERR_NOT_SPD from formation.  A camera with focal length 0 has
+    J_c = 0 in its rotation, translation and distortion columns (each carries
+    the factor f), so its diagonal RCS block has zero rows; with every focal
+    length 0 also J_p = 0, so every V_p is 0.  The oracle's U_ii, V_p agree
+    (its formation fails on V_p, its diagonal block has a zero row).  An LM
+    step on such an RCS is rejected and leaves the parameters unchanged."""
+    s = scenegen.tiny_scene(seed=0, with_stats=False)
+    uv = orc.observations(s)
+    bad_cam = s.cams_init.copy()
+    bad_cam[3, 6] = 0.0
+    P = orc.Problem.from_scene(s, uv)
+    P.linearize(bad_cam, s.pts_init)
+    P.form_rcs(1e-4)
+    blk_ref, _ = P.rcs()
+    rp, _ = P.pattern()
+    assert not np.any(blk_ref[rp[3]][0])   # zero row: not positive definite
+    all_bad = s.cams_init.copy()
+    all_bad[:, 6] = 0.0
+    P.linearize(all_bad, s.pts_init)
+    with pytest.raises(RuntimeError):
+        P.form_rcs(1e-4)
+    ctx = create(s, uv, precision)
+    try:
+        ba.ba_linearize(ctx, T(bad_cam, torch.float64), T(s.pts_init, torch.float64))
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_form_rcs(ctx, 1e-4)
+        assert ei.value.status == ba.BA_ERR_NOT_SPD and "diagonal" in str(ei.value)
+        ba.ba_linearize(ctx, T(all_bad, torch.float64), T(s.pts_init, torch.float64))
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_form_rcs(ctx, 1e-4)
+        assert ei.value.status == ba.BA_ERR_NOT_SPD and "point" in str(ei.value)
+        cams = T(bad_cam, torch.float64)
+        pts = T(s.pts_init, torch.float64)
+        st = ba.new_lm_state(1e-4)
+        info = ba.ba_lm_step(ctx, cams, pts, st, pcg_max_iter=50)
+        assert info["accepted"] == 0 and info["pcg_status"] == ba.BA_ERR_NOT_SPD
+        assert np.array_equal(cams.cpu().numpy(), bad_cam) and np.array_equal(pts.cpu().numpy(), s.pts_init)
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_mixed_records_out_of_range():
+    """BA_ERR_RANGE: a point 1e-9 in front of a camera's image plane gives
+    image coordinates near 1e9 and distortion derivatives near 1e48, beyond
+    FP32 (3.4e38) but within FP64.  The FP64 path linearizes; the mixed path
+    reports the overflow from ba_linearize, ba_form_rcs and ba_lm_step (no
+    step, state unchanged)."""
+    from scipy.spatial.transform import Rotation
+    s = scenegen.tiny_scene(seed=0, with_stats=False)
+    uv = orc.observations(s)
+    c0, p0 = int(s.obs_cam[0]), int(s.obs_pt[0])
+    R = Rotation.from_rotvec(s.cams_init[c0, :3]).as_matrix()
+    pts0 = s.pts_init.copy()
+    pts0[p0] = R.T @ (np.array([1.0, 0.5, 1e-9]) - s.cams_init[c0, 3:6])
+    F_ref, e_ref, Jc, Jp = orc.linearize(s.cams_init, pts0, s.obs_cam, s.obs_pt, uv)
+    assert np.isfinite(F_ref) and np.abs(Jc).max() > 1e40 and np.abs(Jc).max() < 1e300
+    ctx = create(s, uv, 0)
+    try:
+        F = ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(pts0, torch.float64))
+        # the camera-frame depth 1e-9 carries an absolute rounding error near
+        # 1e-15 on either side, and F grows like depth^-10 here
+        assert np.isfinite(F) and F == pytest.approx(F_ref, rel=1e-2)
+    finally:
+        ba.ba_destroy(ctx)
+    ctx = create(s, uv, 1)
+    try:
+        cams = T(s.cams_init, torch.float64)
+        pts = T(pts0, torch.float64)
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_linearize(ctx, cams, pts)
+        assert ei.value.status == ba.BA_ERR_RANGE
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_form_rcs(ctx, 1e-4)
+        assert ei.value.status == ba.BA_ERR_RANGE
+        st = ba.new_lm_state(1e-4)
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_lm_step(ctx, cams, pts, st)
+        assert ei.value.status == ba.BA_ERR_RANGE
+        assert st.lam == 1e-4 and st.nu == 2.0 and st.iter == 0
+        assert np.array_equal(cams.cpu().numpy(), s.cams_init) and np.array_equal(pts.cpu().numpy(), pts0)
+    finally:
+        ba.ba_destroy(ctx)
