@@ -188,19 +188,43 @@ def test_observation_order_invariance():
     np.testing.assert_allclose(rhs2, rhs, atol=1e-11 * np.abs(rhs).max())
 
 
+def _dense_rcs(s, uv, lam):
+    """S = H_cc - H_cp H_pp^-1 H_pc of the damped dense normal matrix,
+    assembled from the per-observation Jacobian blocks (dense LAPACK)."""
+    F, e, Jc, Jp = orc.linearize(s.cams_init, s.pts_init, s.obs_cam, s.obs_pt, uv)
+    nc, npt = s.n_cams, s.n_pts
+    J = np.zeros((2 * s.n_obs, 9 * nc + 3 * npt))
+    for k in range(s.n_obs):
+        c, p = s.obs_cam[k], s.obs_pt[k]
+        J[2 * k:2 * k + 2, 9 * c:9 * c + 9] = Jc[k]
+        J[2 * k:2 * k + 2, 9 * nc + 3 * p:9 * nc + 3 * p + 3] = Jp[k]
+    H = J.T @ J
+    H[np.diag_indices_from(H)] *= 1.0 + lam
+    m = 9 * nc
+    return H[:m, :m] - H[:m, m:] @ np.linalg.solve(H[m:, m:], H[m:, :m])
+
+
 def test_bsmc_bytes_eq9():
-    """Eq. (9) with c unknowns per camera, the sparsity alpha taken as the
-    fraction of non-zero blocks of the full (both triangles) n x n block
-    matrix, so that the upper triangle holds (alpha n^2 + n)/2 blocks."""
+    """Eq. (9) against an independent count.  The sparsity alpha is the
+    fraction of non-zero 9x9 blocks (both triangles, with the diagonal) of
+    the dense RCS built by dense elimination on the full normal matrix,
+    without the oracle's pattern; the oracle's BSMC byte count must equal
+    Eq. (9) evaluated with that alpha, for c = 9 and c = 11 unknowns per
+    camera.  Eq. (10) is then checked against Y_C / Y_B of Eq. (8)-(9)
+    (with its denominator term 3 alpha read as 3 alpha n)."""
     s = scenegen.tiny_scene(seed=4, n_pts=40, n_grid=4, t_hi=3, with_stats=False)
-    P = orc.Problem.from_scene(s)
-    n = P.n_rows
-    alpha = (2 * P.n_blk - n) / n ** 2
+    uv = orc.observations(s)
+    S = _dense_rcs(s, uv, 1e-3)
+    n = s.n_cams
+    nz = np.array([[np.abs(S[9 * i:9 * i + 9, 9 * j:9 * j + 9]).max() > 0 for j in range(n)] for i in range(n)])
+    assert nz.sum() < n * n           # a sparse case: some cameras share no point
+    alpha = nz.sum() / n ** 2
+    P = orc.Problem.from_scene(s, uv)
+    assert P.n_rows == n
     for c in (9, 11):
         YB = (alpha * n * n + n) / 2 * c * c * 8 + (alpha * n * n + n) / 2 * 3 * 4 + n * 4
-        assert abs(P.bsmc_bytes(c) - YB) < 1e-6
+        assert abs(P.bsmc_bytes(c) - YB) < 1e-6 * YB
         YC = alpha * n * n * c * c * 8 + alpha * n * n * c * c * 4 + n * c * 4
-        # Eq. (10) holds with the denominator term 3*alpha*n (printed as 3*alpha)
         ratio10 = (6 * alpha * n * c * c + 2 * c) / (2 * alpha * n * c * c + 2 * c * c + 3 * alpha * n + 5)
         assert abs(YC / YB - ratio10) < 1e-12 * ratio10
 
