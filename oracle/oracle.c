@@ -736,6 +736,117 @@ int orc_lm_step(orc_problem* P, double* cams, double* pts, orc_lm_state* st,
 /* BSMC memory in bytes from the stored pattern (Eq. (9) counted on the
  * actual blocks: c*c doubles and 3 ints per stored block, plus one int per
  * row). */
+/* ------------------------------------------------------------------------ */
+/* re-triangulation of points with the cameras held fixed                     */
+/* ------------------------------------------------------------------------ */
+/* The paper's alternative to Eq. (5): after the camera step the points are
+ * "triangulated by camera poses" (Sec. 3.1, after Eq. (5); Sec. 6 names it
+ * among the costly steps).  For each point, with every camera fixed:
+ *   - linear start (init = 1): each observed pixel is undistorted (the
+ *     radius r of the normalised image point solves r (1 + k1 r^2 + k2 r^4)
+ *     = |pixel| / f, by Newton's method from r = |pixel| / f), giving (x, y)
+ *     with R X + t parallel to (x, y, 1); the two linear equations
+ *       (x R_3 - R_1) X = t_1 - x t_3,   (y R_3 - R_2) X = t_2 - y t_3
+ *     of every observation are solved in the least-squares sense (normal
+ *     equations, 3x3);
+ *   - otherwise the start is the given point;
+ *   - then n_gn Gauss-Newton steps on the point's reprojection error,
+ *     X += (Jp^T Jp)^-1 (-Jp^T e), with Jp and e from the dual-number
+ *     projection.
+ * A point whose 3x3 normal matrix is not positive definite keeps its start
+ * (or its last iterate) and is counted.  which (or NULL: every point) lists
+ * the points to triangulate; pts_out receives them (others untouched).
+ * Returns the number of points that failed. */
+static double undistort_radius(double rho, double k1, double k2) {
+    double r = rho;
+    for (int it = 0; it < 60; ++it) {
+        double r2 = r * r;
+        double g = r * (1.0 + k1 * r2 + k2 * r2 * r2) - rho;
+        double dg = 1.0 + 3.0 * k1 * r2 + 5.0 * k2 * r2 * r2;
+        double step = g / dg;
+        r -= step;
+        if (fabs(step) <= 1e-17 * (1.0 + r)) break;
+    }
+    return r;
+}
+
+static void rotation_matrix(const double* w, double R[9]) {
+    /* columns R e_j from the same Rodrigues map as the projection */
+    dual wd[3], e[3], out[3];
+    for (int i = 0; i < 3; ++i) wd[i] = dconst(w[i]);
+    for (int j = 0; j < 3; ++j) {
+        for (int i = 0; i < 3; ++i) e[i] = dconst(i == j ? 1.0 : 0.0);
+        rotate(wd, e, out);
+        for (int i = 0; i < 3; ++i) R[i * 3 + j] = out[i].v;
+    }
+}
+
+/* 3x3 SPD solve A x = b through the cofactor inverse; 0 if not PD */
+static int solve3_spd(const double A[9], const double b[3], double x[3]) {
+    double Ai[9];
+    if (!inv3_spd(A, Ai)) return 0;
+    for (int i = 0; i < 3; ++i) x[i] = Ai[i * 3 + 0] * b[0] + Ai[i * 3 + 1] * b[1] + Ai[i * 3 + 2] * b[2];
+    return 1;
+}
+
+int64_t orc_triangulate(const orc_problem* P, const double* cams, const double* pts_start, double* pts_out,
+                        const int32_t* which, int64_t n_which, int32_t init, int32_t n_gn) {
+    const int64_t n = which ? n_which : P->n_pts;
+    int64_t failed = 0;
+    #pragma omp parallel for schedule(dynamic, 256) reduction(+:failed)
+    for (int64_t ii = 0; ii < n; ++ii) {
+        const int32_t p = which ? which[ii] : (int32_t)ii;
+        double X[3] = {pts_start[(int64_t)p * 3], pts_start[(int64_t)p * 3 + 1], pts_start[(int64_t)p * 3 + 2]};
+        int ok = 1;
+        if (init) {
+            double A[9] = {0}, b[3] = {0};
+            for (int64_t q = P->pt_ptr[p]; q < P->pt_ptr[p + 1]; ++q) {
+                const int64_t k = P->pt_obs[q];
+                const double* c = cams + (int64_t)P->obs_cam[k] * NCP;
+                const double u = P->uv[k], v = P->uv[P->n_obs + k];
+                const double rho = sqrt(u * u + v * v) / c[6];
+                double x = 0.0, y = 0.0;
+                if (rho > 0.0) {
+                    const double r = undistort_radius(rho, c[7], c[8]);
+                    x = u / c[6] * (r / rho);
+                    y = v / c[6] * (r / rho);
+                }
+                double R[9];
+                rotation_matrix(c, R);
+                const double a1[3] = {x * R[6] - R[0], x * R[7] - R[1], x * R[8] - R[2]};
+                const double a2[3] = {y * R[6] - R[3], y * R[7] - R[4], y * R[8] - R[5]};
+                const double b1 = c[3] - x * c[5], b2 = c[4] - y * c[5];
+                for (int i = 0; i < 3; ++i) {
+                    for (int j = 0; j < 3; ++j) A[i * 3 + j] += a1[i] * a1[j] + a2[i] * a2[j];
+                    b[i] += a1[i] * b1 + a2[i] * b2;
+                }
+            }
+            double X0[3];
+            if (solve3_spd(A, b, X0)) { X[0] = X0[0]; X[1] = X0[1]; X[2] = X0[2]; }
+            else ok = 0;
+        }
+        for (int it = 0; ok && it < n_gn; ++it) {
+            double V[9] = {0}, g[3] = {0};
+            for (int64_t q = P->pt_ptr[p]; q < P->pt_ptr[p + 1]; ++q) {
+                const int64_t k = P->pt_obs[q];
+                dual pr[2];
+                project_dual(cams + (int64_t)P->obs_cam[k] * NCP, X, pr);
+                const double e0 = pr[0].v - P->uv[k], e1 = pr[1].v - P->uv[P->n_obs + k];
+                for (int i = 0; i < 3; ++i) {
+                    for (int j = 0; j < 3; ++j) V[i * 3 + j] += pr[0].d[9 + i] * pr[0].d[9 + j] + pr[1].d[9 + i] * pr[1].d[9 + j];
+                    g[i] -= pr[0].d[9 + i] * e0 + pr[1].d[9 + i] * e1;
+                }
+            }
+            double dX[3];
+            if (!solve3_spd(V, g, dX)) { ok = 0; break; }
+            for (int i = 0; i < 3; ++i) X[i] += dX[i];
+        }
+        if (!ok) failed += 1;
+        for (int i = 0; i < 3; ++i) pts_out[(int64_t)p * 3 + i] = X[i];
+    }
+    return failed;
+}
+
 int64_t orc_bsmc_bytes(const orc_problem* P, int32_t c) {
     return P->n_blk * (int64_t)c * c * 8 + P->n_blk * 3 * 4 + (int64_t)P->n_rows * 4;
 }

@@ -70,6 +70,8 @@ def lib():
         L.orc_lm_step.argtypes = [vp, _f64p, _f64p, C.POINTER(LMState), C.POINTER(LMInfo),
                                   C.c_double, C.c_int32]
         L.orc_lm_step.restype = C.c_int
+        L.orc_triangulate.argtypes = [vp, _f64p, _f64p, _f64p, vp, C.c_int64, C.c_int32, C.c_int32]
+        L.orc_triangulate.restype = C.c_int64
         L.orc_bsmc_bytes.argtypes = [vp, C.c_int32]
         L.orc_bsmc_bytes.restype = C.c_int64
         _lib = L
@@ -218,6 +220,16 @@ class Problem:
         info = LMInfo()
         lib().orc_lm_step(self.h, cams, pts, C.byref(state), C.byref(info), float(tol), int(max_iter))
         return {k: getattr(info, k) for k, _ in LMInfo._fields_}
+
+    def triangulate(self, cams, pts_start, init=True, n_gn=5, which=None):
+        """Points re-estimated with the cameras fixed (linear start when init,
+        then n_gn Gauss-Newton steps); returns (pts [n_pts][3], n_failed).
+        Points outside `which` (when given) keep their start values."""
+        out = np.array(pts_start, dtype=np.float64, order="C")
+        w = None if which is None else _c(which, np.int32)
+        nf = lib().orc_triangulate(self.h, _c(cams, np.float64), _c(pts_start, np.float64), out, _ptr(w),
+                                   0 if w is None else w.size, int(bool(init)), int(n_gn))
+        return out, int(nf)
 
     def bsmc_bytes(self, c=9):
         return lib().orc_bsmc_bytes(self.h, c)
