@@ -136,7 +136,7 @@ typedef struct ba_pcg_opts {
  * takes UPPER when the copy of both triangles would exceed 256 MiB (about
  * the GPU's last-level cache), FULL otherwise (one kernel less per
  * iteration on small systems). */
-enum { BA_PRODUCT_AUTO = 0, BA_PRODUCT_FULL = 1, BA_PRODUCT_UPPER = 2 };
+enum { BA_PRODUCT_AUTO = 0, BA_PRODUCT_FULL = 1, BA_PRODUCT_UPPER = 2, BA_PRODUCT_CSR = 3 };
 
 typedef struct ba_pcg_info {
     int32_t iters;              /* CG iterations (matrix-vector products) done */
@@ -159,9 +159,13 @@ ba_status ba_pcg_solve(ba_ctx* ctx, const ba_pcg_opts* opts, double* dxc, ba_pcg
 
 /* Sec. 6.2: y = S x with the RCS formed last, computed as one product of a
  * PCG iteration (layout `product`, BA_PRODUCT_*, and with solver_fp32 = 1
- * the FP32 copy of S).  x, y: distinct device arrays [n_rows][9], owned by
- * the caller.  Synchronises the context stream.  Errors: BA_ERR_STATE (no
- * RCS), BA_ERR_INVALID_ARG (null or identical arrays, unknown layout). */
+ * the FP32 copy of S).  BA_PRODUCT_CSR instead multiplies with a scalar
+ * CSR copy of both triangles (the format of Sec. 4.1 Eq. (8) that BSMC is
+ * compared with; built from the blocks on first use after each formation,
+ * FP64 only, one wave per scalar row; not a PCG layout).  x, y: distinct
+ * device arrays [n_rows][9], owned by the caller.  Synchronises the context
+ * stream.  Errors: BA_ERR_STATE (no RCS), BA_ERR_INVALID_ARG (null or
+ * identical arrays, unknown layout, CSR with solver_fp32). */
 ba_status ba_rcs_product(ba_ctx* ctx, const double* x, double* y, int32_t product, int32_t solver_fp32);
 
 /* Eq. (5): dxp = V*^-1 (l_p - sum_i W_ip^T dxc_i) for every point (device
@@ -184,6 +188,10 @@ typedef struct ba_lm_opts {
     int32_t deflate;            /* 1: deflated PCG on the similarity gauge */
     int32_t solver_fp32;        /* 1: PCG products with an FP32 copy of S (see ba_pcg_opts) */
     int32_t product;            /* BA_PRODUCT_AUTO, _FULL or _UPPER (see ba_pcg_opts) */
+    int32_t retriangulate;      /* 0: points by Eq. (5); k in 1..100: after Eq. (5) the points
+                                   are re-triangulated with the candidate cameras (ba_triangulate,
+                                   k Gauss-Newton steps from the Eq. (5) points); the gain ratio
+                                   and the update then use those points */
 } ba_lm_opts;
 
 typedef struct ba_lm_info {
@@ -201,7 +209,8 @@ typedef struct ba_lm_info {
     int32_t precond_fallback;   /* 1: the learned preconditioner failed on this step's RCS
                                    (d^T S d <= 0 or a non-finite residual) and the step was
                                    solved again with block-Jacobi */
-    int32_t reserved;
+    int32_t tri_failed;         /* points whose re-triangulation failed (they keep their last
+                                   iterate; 0 without retriangulate) */
 } ba_lm_info;
 
 /* One LM iteration (Eq. (1) solved through Eq. (4)-(7) and (5)): linearize
@@ -218,6 +227,21 @@ typedef struct ba_lm_info {
  * opts may be NULL for the defaults. */
 ba_status ba_lm_step(ba_ctx* ctx, double* cams, double* pts, ba_lm_state* state,
                      const ba_lm_opts* opts, ba_lm_info* info_host);
+
+/* Re-triangulation, the alternative to Eq. (5) of Sec. 3.1 (points
+ * "triangulated by camera poses"): every point of the context is
+ * re-estimated from its observations with the cameras cams (device
+ * [n_cams][9]) held fixed.  Start: the given pts (device [n_pts][3]), or
+ * with linear_init = 1 a linear multi-view solve (each pixel undistorted by
+ * Newton's method on r (1 + k1 r^2 + k2 r^4) = |pixel| / f, then the
+ * least-squares point of the equations (x R_3 - R_1) X = t_1 - x t_3,
+ * (y R_3 - R_2) X = t_2 - y t_3); then n_gn (0..100) Gauss-Newton steps on
+ * the point's reprojection error.  pts is overwritten with the result; a
+ * point whose 3x3 normal matrix is not positive definite keeps its start
+ * (its last iterate) and is counted in *n_failed (host, may be NULL).
+ * Synchronises the context stream. */
+ba_status ba_triangulate(ba_ctx* ctx, const double* cams, double* pts, int32_t linear_init, int32_t n_gn,
+                         int64_t* n_failed);
 
 /* Projection of Sec. 3.1's camera model, without a context: uv (device
  * [2][n_obs]) = pixel of point obs_pt[k] in camera obs_cam[k] (+ noise
@@ -240,6 +264,23 @@ ba_status ba_get_pattern(ba_ctx* ctx, int64_t* row_ptr, int32_t* col_idx);
 
 /* Host copies of the last formed RCS: blocks [n_blk][81], rhs [n_rows][9]; either may be NULL. */
 ba_status ba_get_rcs(ba_ctx* ctx, double* blk, double* rhs);
+
+/* Bytes of the RCS in each storage layout (Sec. 4.1): bsmc_bytes = the
+ * upper 9x9 blocks (FP64) + one column index per block + the block-row
+ * pointer (Eq. (9) counts three indices per block); full_bytes = the
+ * two-triangle copy of the FULL product (blocks, column and source index
+ * per entry, row pointer); csr_nnz = 81 (2 n_blk - n_rows) scalar
+ * non-zeros of both triangles and csr_bytes = 12 bytes per non-zero + the
+ * scalar row pointer (exactly Eq. (8) with c = 9). */
+typedef struct ba_store_sizes {
+    int64_t bsmc_bytes, full_bytes, csr_nnz, csr_bytes;
+} ba_store_sizes;
+ba_status ba_get_store_sizes(const ba_ctx* ctx, ba_store_sizes* out);
+
+/* Host copy of the CSR copy of the last formed RCS (built if needed):
+ * row_ptr [9 n_rows + 1], col [nnz] ascending within each scalar row, val
+ * [nnz] FP64; *nnz receives the count.  Any pointer may be NULL. */
+ba_status ba_get_csr(ba_ctx* ctx, int32_t* row_ptr, int32_t* col, double* val, int64_t* nnz);
 
 /* Host copies of the last linearization in the caller's observation order:
  * J [n_obs][24] = J_c row 0 (9), J_c row 1 (9), J_p row 0 (3), J_p row 1 (3)

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libba.so")
  BA_ERR_RANGE) = range(8)
 BA_FP64, BA_MIXED = 0, 1
 BA_PRECOND_BLOCK_JACOBI, BA_PRECOND_LEARNED, BA_PRECOND_FSAI, BA_PRECOND_LEARNED_FSAI = 0, 1, 2, 3
-BA_PRODUCT_AUTO, BA_PRODUCT_FULL, BA_PRODUCT_UPPER = 0, 1, 2
+BA_PRODUCT_AUTO, BA_PRODUCT_FULL, BA_PRODUCT_UPPER, BA_PRODUCT_CSR = 0, 1, 2, 3
 
 
 class ProblemDesc(C.Structure):
@@ -47,7 +47,8 @@ class LMState(C.Structure):
 
 class LMOpts(C.Structure):
     _fields_ = [("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32), ("precond", C.c_int32),
-                ("deflate", C.c_int32), ("solver_fp32", C.c_int32), ("product", C.c_int32)]
+                ("deflate", C.c_int32), ("solver_fp32", C.c_int32), ("product", C.c_int32),
+                ("retriangulate", C.c_int32)]
 
 
 class LMInfo(C.Structure):
@@ -57,12 +58,17 @@ class LMInfo(C.Structure):
                 ("stop", C.c_int32), ("ms_linearize", C.c_double), ("ms_form_rcs", C.c_double),
                 ("ms_pcg", C.c_double), ("ms_back_substitute", C.c_double),
                 ("ms_evaluate", C.c_double), ("ms_total", C.c_double), ("ms_precond", C.c_double),
-                ("precond_fallback", C.c_int32), ("reserved", C.c_int32)]
+                ("precond_fallback", C.c_int32), ("tri_failed", C.c_int32)]
 
 
 class Sizes(C.Structure):
     _fields_ = [("n_cams", C.c_int32), ("n_pts", C.c_int32), ("n_rows", C.c_int32), ("precision", C.c_int32),
                 ("n_obs", C.c_int64), ("n_blk", C.c_int64), ("n_pairs", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+class StoreSizes(C.Structure):
+    _fields_ = [("bsmc_bytes", C.c_int64), ("full_bytes", C.c_int64), ("csr_nnz", C.c_int64),
+                ("csr_bytes", C.c_int64)]
 
 
 # exported symbol -> (restype, argtypes)
@@ -77,10 +83,13 @@ SIGNATURES = {
     "ba_back_substitute": (C.c_int, [_vp, _vp, _vp]),
     "ba_lm_step": (C.c_int, [_vp, _vp, _vp, C.POINTER(LMState), C.POINTER(LMOpts), C.POINTER(LMInfo)]),
     "ba_project": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
+    "ba_triangulate": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
     "ba_get_sizes": (C.c_int, [_vp, C.POINTER(Sizes)]),
     "ba_get_pattern": (C.c_int, [_vp, _vp, _vp]),
     "ba_get_rcs": (C.c_int, [_vp, _vp, _vp]),
     "ba_get_jacobians": (C.c_int, [_vp, _vp, _vp]),
+    "ba_get_csr": (C.c_int, [_vp, _vp, _vp, _vp, C.POINTER(C.c_int64)]),
+    "ba_get_store_sizes": (C.c_int, [_vp, C.POINTER(StoreSizes)]),
     "ba_get_fsai": (C.c_int, [_vp, _vp]),
     "ba_get_gauge": (C.c_int, [_vp, _vp]),
     "ba_get_stage_ms": (C.c_int, [_vp, _dp]),
@@ -201,12 +210,21 @@ def ba_back_substitute(ctx, dxc, dxp):
 
 
 def ba_lm_step(ctx, cams, pts, state: LMState, pcg_tol=1e-6, pcg_max_iter=1000,
-               precond=BA_PRECOND_BLOCK_JACOBI, deflate=False, solver_fp32=False, product=BA_PRODUCT_AUTO):
+               precond=BA_PRECOND_BLOCK_JACOBI, deflate=False, solver_fp32=False, product=BA_PRODUCT_AUTO,
+               retriangulate=0):
     o = LMOpts(pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter, precond=precond, deflate=int(bool(deflate)),
-               solver_fp32=int(bool(solver_fp32)), product=int(product))
+               solver_fp32=int(bool(solver_fp32)), product=int(product), retriangulate=int(retriangulate))
     info = LMInfo()
     _check(lib().ba_lm_step(ctx, _ptr(cams), _ptr(pts), C.byref(state), C.byref(o), C.byref(info)), ctx)
     return {k: getattr(info, k) for k, _ in LMInfo._fields_}
+
+
+def ba_triangulate(ctx, cams, pts, linear_init=True, n_gn=5):
+    """Re-triangulates every point in place (pts: device [n_pts][3]) with the
+    cameras fixed; returns the number of points that failed."""
+    nf = C.c_int64(0)
+    _check(lib().ba_triangulate(ctx, _ptr(cams), _ptr(pts), int(bool(linear_init)), int(n_gn), C.byref(nf)), ctx)
+    return nf.value
 
 
 def ba_project(cams, pts, obs_cam, obs_pt, noise=None, out=None, stream=None):
@@ -247,6 +265,24 @@ def ba_get_jacobians(ctx):
     e = np.empty((s["n_obs"], 2))
     _check(lib().ba_get_jacobians(ctx, _np_ptr(J), _np_ptr(e)), ctx)
     return J, e
+
+
+def ba_get_store_sizes(ctx):
+    s = StoreSizes()
+    _check(lib().ba_get_store_sizes(ctx, C.byref(s)), ctx)
+    return {k: getattr(s, k) for k, _ in StoreSizes._fields_}
+
+
+def ba_get_csr(ctx):
+    """CSR copy of the last formed RCS: (row_ptr [9 n_rows + 1], col, val)."""
+    s = ba_get_sizes(ctx)
+    nnz = C.c_int64(0)
+    _check(lib().ba_get_csr(ctx, None, None, None, C.byref(nnz)), ctx)
+    rp = np.empty(9 * s["n_rows"] + 1, np.int32)
+    col = np.empty(max(nnz.value, 1), np.int32)
+    val = np.empty(max(nnz.value, 1))
+    _check(lib().ba_get_csr(ctx, _np_ptr(rp), _np_ptr(col), _np_ptr(val), None), ctx)
+    return rp, col[: nnz.value], val[: nnz.value]
 
 
 def ba_get_gauge(ctx):

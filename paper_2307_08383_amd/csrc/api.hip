@@ -62,7 +62,8 @@ void free_ctx(ba_ctx* c) {
                     c->pcg.r[1], c->pcg.z, c->pcg.q, c->pcg.d, c->pcg.t, c->pcg.u, c->pcg.tb, c->pcg.pA, c->pcg.pR, c->pcg.W, c->pcg.SW, c->pcg.Einv,
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
                     c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
-                    c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.gu_src, c->fs.gl_self, c->fs.tg, c->pcg.bm, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G};
+                    c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.gu_src, c->fs.gl_self, c->fs.tg, c->pcg.bm, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G,
+                    c->tri_failed, c->csr.bptr, c->csr.slot_src, c->csr.slot_col, c->csr.slot_row, c->csr.rowptr, c->csr.col, c->csr.val};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -476,6 +477,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &c->part2, (size_t)3 * ba::kReduceParts);
     dalloc(c, &c->scal, 16);
     dalloc(c, &c->flags, 8);
+    dalloc(c, &c->tri_failed, 1);
     Pcg& P = c->pcg;
     dalloc(c, &P.x, (size_t)nr * 9);
     dalloc(c, &P.r[0], (size_t)nr * 9);
@@ -553,6 +555,7 @@ ba_status form_rcs_async(ba_ctx* c, double lambda, bool point_done = false) {
     c->su32_ready = false;
     c->fs.ready = false;
     c->defl_ready = false;
+    c->csr.ready = false;
     c->lambda = lambda;
     return BA_OK;
 }
@@ -604,6 +607,16 @@ void prepare_fsai(ba_ctx* c) {
 bool learned_failed(int pre, ba_status s, double relres) {
     return (pre == BA_PRECOND_LEARNED || pre == BA_PRECOND_LEARNED_FSAI) &&
            (s == BA_ERR_NOT_SPD || !std::isfinite(relres));
+}
+
+// the CSR copy of the current RCS (index structure on first use)
+void prepare_csr(ba_ctx* c) {
+    if (!c->csr.built) ba::build_csr(c);
+    if (!c->csr.ready) {
+        ba::launch_csr_fill(c);
+        BA_HIP_CHECK(hipGetLastError());
+        c->csr.ready = true;
+    }
 }
 
 // network inference on the current RCS -> Mlearn (context stream)
@@ -687,6 +700,58 @@ void build_fsai(ba_ctx* c) {
     dalloc(c, &F.G, (size_t)c->n_blk * 81);
     BA_HIP_CHECK(hipMemsetAsync(F.G, 0, (size_t)c->n_blk * 81 * sizeof(float), c->stream));
     F.built = true;
+}
+
+// Index structure of the CSR copy (host, once per context): per block row
+// its slots in ascending column order (the transposed blocks (s, r), s < r,
+// of column r, then the row's own upper blocks, diagonal first), each
+// slot's source block (<< 1 | transposed), block column and row, and the
+// scalar row pointer (row 9 r + a starts at 81 P_r + 9 m_r a for the P_r
+// slots before row r and the m_r slots of row r).
+void build_csr(ba_ctx* c) {
+    const int32_t nr = c->n_rows;
+    const std::vector<int64_t>& rp = c->h_row_ptr;
+    const std::vector<int32_t>& ci = c->h_col_idx;
+    std::vector<std::vector<int32_t>> lower(nr);
+    std::vector<int32_t> brow(c->n_blk);
+    for (int32_t r = 0; r < nr; ++r)
+        for (int64_t kb = rp[r]; kb < rp[r + 1]; ++kb) {
+            brow[kb] = r;
+            if (kb > rp[r]) lower[ci[kb]].push_back((int32_t)kb);
+        }
+    std::vector<int32_t> bptr(nr + 1, 0), src, col, row;
+    for (int32_t r = 0; r < nr; ++r) {
+        for (int32_t kb : lower[r]) {
+            src.push_back(kb << 1 | 1);
+            col.push_back(brow[kb]);
+            row.push_back(r);
+        }
+        for (int64_t kb = rp[r]; kb < rp[r + 1]; ++kb) {
+            src.push_back((int32_t)kb << 1);
+            col.push_back(ci[kb]);
+            row.push_back(r);
+        }
+        bptr[r + 1] = (int32_t)src.size();
+    }
+    const int64_t nnz = 81 * (int64_t)src.size();
+    if (nnz >= INT32_MAX) throw ba_invalid{"the CSR copy would need 2^31 or more non-zeros"};
+    std::vector<int32_t> rowptr(9 * (size_t)nr + 1);
+    for (int32_t r = 0; r < nr; ++r) {
+        const int64_t m = bptr[r + 1] - bptr[r];
+        for (int a = 0; a < 9; ++a) rowptr[9 * (size_t)r + a] = (int32_t)(81 * (int64_t)bptr[r] + 9 * m * a);
+    }
+    rowptr[9 * (size_t)nr] = (int32_t)nnz;
+    Csr& C = c->csr;
+    upload(c, &C.bptr, bptr);
+    upload(c, &C.slot_src, src);
+    upload(c, &C.slot_col, col);
+    upload(c, &C.slot_row, row);
+    upload(c, &C.rowptr, rowptr);
+    dalloc(c, &C.col, (size_t)nnz);
+    dalloc(c, &C.val, (size_t)nnz);
+    C.n_slot = (int64_t)src.size();
+    C.nnz = nnz;
+    C.built = true;
 }
 
 }  // namespace ba
@@ -810,6 +875,22 @@ ba_status ba_project(const double* cams, const double* pts, const int32_t* obs_c
     return hipGetLastError() == hipSuccess ? BA_OK : BA_ERR_DEVICE;
 }
 
+ba_status ba_triangulate(ba_ctx* c, const double* cams, double* pts, int32_t linear_init, int32_t n_gn,
+                         int64_t* n_failed) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!cams || !pts) { c->err = "null parameter arrays"; return BA_ERR_INVALID_ARG; }
+    if (n_gn < 0 || n_gn > 100) { c->err = "n_gn must be 0..100"; return BA_ERR_INVALID_ARG; }
+    return guarded(c, [&]() {
+        BA_HIP_CHECK(hipMemsetAsync(c->tri_failed, 0, sizeof(int), c->stream));
+        ba::launch_triangulate(c, cams, nullptr, pts, pts, 0, linear_init ? 1 : 0, n_gn, c->tri_failed);
+        BA_HIP_CHECK(hipGetLastError());
+        BA_HIP_CHECK(hipMemcpyAsync(c->h_flags + 3, c->tri_failed, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        if (n_failed) *n_failed = c->h_flags[3];
+        return BA_OK;
+    });
+}
+
 ba_status ba_linearize(ba_ctx* c, const double* cams, const double* pts, double* cost_host) {
     if (!c) return BA_ERR_INVALID_ARG;
     if (!cams || !pts) { c->err = "null parameter arrays"; return BA_ERR_INVALID_ARG; }
@@ -923,8 +1004,16 @@ ba_status ba_rcs_product(ba_ctx* c, const double* x, double* y, int32_t product,
     if (!c) return BA_ERR_INVALID_ARG;
     if (!c->have_rcs) { c->err = "ba_rcs_product needs a formed RCS"; return BA_ERR_STATE; }
     if (!x || !y || x == y) { c->err = "x and y must be distinct device arrays"; return BA_ERR_INVALID_ARG; }
-    if (product < BA_PRODUCT_AUTO || product > BA_PRODUCT_UPPER) { c->err = "unknown product layout"; return BA_ERR_INVALID_ARG; }
+    if (product < BA_PRODUCT_AUTO || product > BA_PRODUCT_CSR) { c->err = "unknown product layout"; return BA_ERR_INVALID_ARG; }
+    if (product == BA_PRODUCT_CSR && solver_fp32) { c->err = "the CSR copy is FP64 only"; return BA_ERR_INVALID_ARG; }
     return guarded(c, [&]() {
+        if (product == BA_PRODUCT_CSR) {
+            prepare_csr(c);
+            ba::launch_csr_spmv(c, x, y);
+            BA_HIP_CHECK(hipGetLastError());
+            BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+            return BA_OK;
+        }
         select_solver_matrix(c, solver_fp32, product);
         ba::launch_product(c, x, y);
         BA_HIP_CHECK(hipGetLastError());
@@ -965,6 +1054,10 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
     }
     if (o && (o->product < BA_PRODUCT_AUTO || o->product > BA_PRODUCT_UPPER)) {
         c->err = "unknown product layout";
+        return BA_ERR_INVALID_ARG;
+    }
+    if (o && (o->retriangulate < 0 || o->retriangulate > 100)) {
+        c->err = "retriangulate must be 0..100 Gauss-Newton steps";
         return BA_ERR_INVALID_ARG;
     }
     return guarded(c, [&]() {
@@ -1009,6 +1102,16 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
             BA_HIP_CHECK(hipMemsetAsync(c->dxc, 0, sizeof(double), c->stream));
         BA_HIP_CHECK(hipEventRecord(ev[7], c->stream));
         ba::launch_back_substitute(c, c->dxc, c->dxp);
+        const int n_tri = o ? o->retriangulate : 0;
+        if (n_tri > 0) {
+            // the points re-triangulated with the candidate cameras, starting
+            // from the back-substituted ones; dxp becomes their displacement
+            BA_HIP_CHECK(hipMemsetAsync(c->tri_failed, 0, sizeof(int), c->stream));
+            ba::launch_triangulate(c, cams, c->dxc, pts, c->dxp, 1, 0, n_tri, c->tri_failed);
+            BA_HIP_CHECK(hipMemcpyAsync(c->h_flags + 3, c->tri_failed, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        } else {
+            c->h_flags[3] = 0;
+        }
         BA_HIP_CHECK(hipEventRecord(ev[9], c->stream));
         ba::launch_evaluate(c, cams, pts, c->dxc, c->dxp);
         BA_HIP_CHECK(hipEventRecord(ev[10], c->stream));
@@ -1025,6 +1128,7 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         I.pcg_iters = it;
         I.pcg_status = ps;
         I.pcg_relres = rr;
+        I.tri_failed = c->h_flags[3];
         if (c->h_flags[2]) {
             // the linearization does not fit the records: no step is taken and
             // the state is left as it was
@@ -1103,6 +1207,33 @@ ba_status ba_get_fsai(ba_ctx* c, float* G) {
         BA_HIP_CHECK(hipStreamSynchronize(c->stream));
         return BA_OK;
     });
+}
+
+ba_status ba_get_csr(ba_ctx* c, int32_t* row_ptr, int32_t* col, double* val, int64_t* nnz) {
+    if (!c) return BA_ERR_INVALID_ARG;
+    if (!c->have_rcs) { c->err = "no RCS formed"; return BA_ERR_STATE; }
+    return guarded(c, [&]() {
+        prepare_csr(c);
+        const ba::Csr& C = c->csr;
+        if (nnz) *nnz = C.nnz;
+        if (row_ptr)
+            BA_HIP_CHECK(hipMemcpyAsync(row_ptr, C.rowptr, (9 * (size_t)c->n_rows + 1) * sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, c->stream));
+        if (col) BA_HIP_CHECK(hipMemcpyAsync(col, C.col, C.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        if (val) BA_HIP_CHECK(hipMemcpyAsync(val, C.val, C.nnz * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        return BA_OK;
+    });
+}
+
+ba_status ba_get_store_sizes(const ba_ctx* c, ba_store_sizes* o) {
+    if (!c || !o) return BA_ERR_INVALID_ARG;
+    const int64_t nb = c->n_blk, nr = c->n_rows, both = 2 * nb - nr;
+    o->bsmc_bytes = nb * 81 * 8 + nb * 4 + (nr + 1) * 4;
+    o->full_bytes = c->n_sf * 81 * 8 + c->n_sf * 4 * 2 + (nr + 1) * 4;
+    o->csr_nnz = 81 * both;
+    o->csr_bytes = 81 * both * (8 + 4) + (9 * nr + 1) * 4;
+    return BA_OK;
 }
 
 ba_status ba_get_jacobians(ba_ctx* c, double* J, double* e) {

@@ -50,7 +50,7 @@ __device__ __forceinline__ void rot_coeffs(double s, double& a, double& b, doubl
 //   dP/dw = 2 as (w x X) w^T - a [X]x + 2 bs (w x (w x X)) w^T
 //           + b ((w.X) I + w X^T - 2 X w^T)
 //   dP/dX = R = I + a [w]x + b (w w^T - s I)
-template <bool JAC>
+template <bool JAC, bool JC = true>
 __device__ __forceinline__ void project_point(const double* __restrict__ c, double X0, double X1, double X2,
                                               double& pu, double& pv, double* Jc, double* Jp) {
     const double w0 = c[0], w1 = c[1], w2 = c[2];
@@ -74,6 +74,7 @@ __device__ __forceinline__ void project_point(const double* __restrict__ c, doub
     const double A00 = f * (d + 2.0 * x * x * dd), A01 = f * (2.0 * x * y * dd), A11 = f * (d + 2.0 * y * y * dd);
     const double E00 = A00 * iz, E01 = A01 * iz, E02 = -(A00 * x + A01 * y) * iz;
     const double E10 = A01 * iz, E11 = A11 * iz, E12 = -(A01 * x + A11 * y) * iz;
+    if (JC) {
     const double wX = w0 * X0 + w1 * X1 + w2 * X2;
     const double g0 = 2.0 * (as * cx0 + bs * cc0), g1 = 2.0 * (as * cx1 + bs * cc1), g2 = 2.0 * (as * cx2 + bs * cc2);
     const double M00 = g0 * w0 + b * (wX + w0 * X0 - 2.0 * X0 * w0);
@@ -95,6 +96,7 @@ __device__ __forceinline__ void project_point(const double* __restrict__ c, doub
     Jc[11] = E10 * M02 + E11 * M12 + E12 * M22;
     Jc[12] = E10; Jc[13] = E11; Jc[14] = E12;
     Jc[15] = d * y; Jc[16] = f * y * r2; Jc[17] = f * y * r2 * r2;
+    }
     const double R00 = 1.0 + b * (w0 * w0 - s), R01 = -a * w2 + b * w0 * w1, R02 = a * w1 + b * w0 * w2;
     const double R10 = a * w2 + b * w1 * w0, R11 = 1.0 + b * (w1 * w1 - s), R12 = -a * w0 + b * w1 * w2;
     const double R20 = -a * w1 + b * w2 * w0, R21 = a * w0 + b * w2 * w1, R22 = 1.0 + b * (w2 * w2 - s);
@@ -173,6 +175,24 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Track of a lane of a wave that holds a chunk of whole tracks (lane i holds
+// the chunk's observation i, i < len; a track's observations are adjacent):
+// the lane of the track's first observation, the track length and the
+// track's index among the chunk's tracks.  Called by every lane of the wave.
+struct Track { int head, len, idx; };
+__device__ __forceinline__ Track chunk_track(bool act, int p, int lane, int len) {
+    const int prev = __shfl_up(p, 1, kWave);
+    const bool first = act && (lane == 0 || prev != p);
+    const unsigned long long heads = __ballot(first);
+    const unsigned long long upto = heads & (~0ull >> (63 - lane));   // heads at lanes <= lane
+    const unsigned long long after = heads & ~upto;                   // heads at lanes > lane
+    Track t;
+    t.head = upto ? 63 - __clzll(upto) : 0;
+    t.len = (after ? __ffsll((long long)after) - 1 : len) - t.head;
+    t.idx = __popcll(upto) - 1;
+    return t;
+}
+
 // Deterministic block sum (fixed shuffle tree, then fixed LDS order); the
 // result is valid in thread 0.
 template <int BS>
@@ -233,6 +253,21 @@ struct Fsai {
     int32_t* gl_self = nullptr;
     int gu_upper = 0;
     double* tg = nullptr;             // [entries][9] G_ij^T t_i per entry of Gl (UPPER apply of G^T)
+};
+
+// Scalar CSR copy of both triangles of the RCS (the layout BSMC is compared
+// with): block slots of each block row in ascending column order, the
+// scalar row pointer, columns and values.
+struct Csr {
+    bool built = false, ready = false;
+    int64_t n_slot = 0, nnz = 0;
+    int32_t *bptr = nullptr;       // [n_rows+1] first slot of each block row
+    int32_t *slot_src = nullptr;   // [n_slot] source block << 1 | transposed
+    int32_t *slot_col = nullptr;   // [n_slot] block column
+    int32_t *slot_row = nullptr;   // [n_slot] block row
+    int32_t *rowptr = nullptr;     // [9 n_rows + 1]
+    int32_t *col = nullptr;        // [nnz]
+    double* val = nullptr;         // [nnz]
 };
 
 }  // namespace ba
@@ -301,11 +336,13 @@ struct ba_ctx {
     double *dxc = nullptr, *dxp = nullptr, *part = nullptr, *scal = nullptr;
     double* part2 = nullptr;           // [3][kReduceParts] first-pass sums of launch_reduce
     int* flags = nullptr;
+    int* tri_failed = nullptr;         // [1] points whose re-triangulation failed
     double* h_scal = nullptr;          // pinned
     int* h_flags = nullptr;            // pinned
     int32_t n_part = 0;
     ba::Pcg pcg;
     ba::Fsai fs;
+    ba::Csr csr;
     hipEvent_t ev[16] = {};
     hipStream_t capture_stream = nullptr;
     bool use_graphs = true;
@@ -355,6 +392,16 @@ void prepare_deflation(ba_ctx* c);
 // current RCS (stream-ordered)
 void build_fsai(ba_ctx* c);
 void launch_fsai(ba_ctx* c);
+// CSR copy: index structure (host, once per context), values of the current
+// RCS, and y = S x on it
+void build_csr(ba_ctx* c);
+void launch_csr_fill(ba_ctx* c);
+void launch_csr_spmv(ba_ctx* c, const double* x, double* y);
+// re-triangulation of every point with cameras cams (+ dxc by RCS row when
+// not null): start pts (+ out when delta), linear start if `linear`, n_gn
+// Gauss-Newton steps; out = X, or X - pts when delta; failures counted
+void launch_triangulate(ba_ctx* c, const double* cams, const double* dxc, const double* pts, double* out, int delta,
+                        int linear, int n_gn, int* n_failed);
 
 }  // namespace ba
 

@@ -21,24 +21,6 @@ namespace {
 constexpr int BS = 256;
 constexpr int WPB = BS / kWave;   // waves per block
 
-// Track of a lane of a wave that holds a chunk of whole tracks (lane i holds
-// the chunk's observation i, i < len; a track's observations are adjacent):
-// the lane of the track's first observation, the track length and the
-// track's index among the chunk's tracks.  Called by every lane of the wave.
-struct Track { int head, len, idx; };
-__device__ __forceinline__ Track chunk_track(bool act, int p, int lane, int len) {
-    const int prev = __shfl_up(p, 1, kWave);
-    const bool first = act && (lane == 0 || prev != p);
-    const unsigned long long heads = __ballot(first);
-    const unsigned long long upto = heads & (~0ull >> (63 - lane));   // heads at lanes <= lane
-    const unsigned long long after = heads & ~upto;                   // heads at lanes > lane
-    Track t;
-    t.head = upto ? 63 - __clzll(upto) : 0;
-    t.len = (after ? __ffsll((long long)after) - 1 : len) - t.head;
-    t.idx = __popcll(upto) - 1;
-    return t;
-}
-
 // Point terms from the track sums s = (V: 00 01 02 11 12 22, l_p): the
 // Cholesky factor of V* = V + lambda diag(V), lhat = L^-1 l_p and the
 // reciprocals of L's diagonal, r = (L00, L10, L11, L20, L21, L22, lhat,

@@ -195,3 +195,72 @@ def test_pcg_from_initial_guess(formed, product):
     assert info["status"] == 0
     S_own = _dense(blk, rp, ci)
     assert np.linalg.norm(b - S_own @ xv) <= 1e-9 * np.linalg.norm(b)
+
+
+def _expected_csr(blk, rp, ci):
+    """Scalar CSR of both triangles from the upper blocks: every entry of
+    every non-zero block (zeros inside a block included), rows sorted by
+    column (numpy sort, independent of the library's slot order)."""
+    n = len(rp) - 1
+    rows_b = np.repeat(np.arange(n), np.diff(rp))
+    a, b = np.meshgrid(np.arange(9), np.arange(9), indexing="ij")
+    R, Cc, V = [], [], []
+    for k in range(len(ci)):
+        r, c = rows_b[k], ci[k]
+        R.append(9 * r + a.ravel()); Cc.append(9 * c + b.ravel()); V.append(blk[k].ravel())
+        if c != r:
+            R.append(9 * c + a.ravel()); Cc.append(9 * r + b.ravel()); V.append(blk[k].T.ravel())
+    R, Cc, V = np.concatenate(R), np.concatenate(Cc), np.concatenate(V)
+    order = np.lexsort((Cc, R))
+    rowptr = np.concatenate([[0], np.cumsum(np.bincount(R, minlength=9 * n))])
+    return rowptr, Cc[order], V[order]
+
+
+def test_csr_copy_and_product(formed):
+    """The CSR copy (Sec. 4.1 Eq. (8)) holds exactly the stored blocks as
+    scalar rows sorted by column; its product equals the block layouts' up
+    to summation order and the oracle's S; its byte count is Eq. (8) with
+    c = 9 (plus the closing row pointer) and exceeds the BSMC store's by
+    the factor Eq. (10) predicts, less the two indices per block that this
+    store does not keep."""
+    name, s, uv, S_ref, _ = formed
+    ctx = create(s, uv, 0)
+    try:
+        ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
+        ba.ba_form_rcs(ctx, 1e-3)
+        blk, _ = ba.ba_get_rcs(ctx)
+        rp, ci = ba.ba_get_pattern(ctx)
+        rowptr, col, val = ba.ba_get_csr(ctx)
+        e_rowptr, e_col, e_val = _expected_csr(blk, rp, ci)
+        assert np.array_equal(rowptr, e_rowptr) and np.array_equal(col, e_col)
+        assert np.array_equal(val, e_val)
+        n = len(rp) - 1
+        x = np.random.default_rng(11).standard_normal((n, 9))
+        xd = T(x, torch.float64)
+        y_csr, y_full = torch.empty_like(xd), torch.empty_like(xd)
+        ba.ba_rcs_product(ctx, xd, y_csr, product=ba.BA_PRODUCT_CSR)
+        ba.ba_rcs_product(ctx, xd, y_full, product=ba.BA_PRODUCT_FULL)
+        scale = np.abs(S_ref) @ np.abs(x.ravel())
+        assert np.max(np.abs(y_csr.cpu().numpy().ravel() - y_full.cpu().numpy().ravel()) / scale) <= 1e-13
+        assert np.max(np.abs(y_csr.cpu().numpy().ravel() - S_ref @ x.ravel()) / scale) <= 1e-10
+        with pytest.raises(ba.BAError):
+            ba.ba_rcs_product(ctx, xd, y_csr, product=ba.BA_PRODUCT_CSR, solver_fp32=True)
+        # a new formation refreshes the copy
+        ba.ba_form_rcs(ctx, 0.5)
+        blk2, _ = ba.ba_get_rcs(ctx)
+        _, _, val2 = ba.ba_get_csr(ctx)
+        assert np.array_equal(val2, _expected_csr(blk2, rp, ci)[2])
+        sz = ba.ba_get_store_sizes(ctx)
+        nb = len(ci)
+        alpha = (2 * nb - n) / n ** 2
+        c = 9
+        eq8 = alpha * n * n * c * c * 8 + alpha * n * n * c * c * 4 + n * c * 4
+        eq9 = (alpha * n * n + n) / 2 * c * c * 8 + (alpha * n * n + n) / 2 * 3 * 4 + n * 4
+        assert sz["csr_nnz"] == len(col) == 81 * (2 * nb - n)
+        assert sz["csr_bytes"] == round(eq8) + 4
+        assert sz["bsmc_bytes"] == round(eq9) - 2 * 4 * nb + 4
+        ratio10 = (6 * alpha * n * c * c + 2 * c) / (2 * alpha * n * c * c + 2 * c * c + 3 * alpha * n + 5)
+        assert abs(eq8 / eq9 - ratio10) < 1e-12 * ratio10
+        assert sz["csr_bytes"] / sz["bsmc_bytes"] >= ratio10
+    finally:
+        ba.ba_destroy(ctx)
