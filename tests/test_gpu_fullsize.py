@@ -270,8 +270,13 @@ def test_partition_lm_against_oracle_run(partition_case):
     the same budget (stored by tests/golden/make_partition_lm.py from the
     oracle alone): FP64 block-Jacobi, and mixed precision with the learned
     factorised preconditioner and gauge deflation.  Decisions are compared
-    where the oracle's step is far from a tie; costs per iteration and the
-    final cost at rel 1e-6."""
+    where the oracle's step is far from a tie and the final cost at rel 1e-6.
+    FP64 block-Jacobi runs the oracle's algorithm, so its cost at every
+    iteration is held to rel 1e-6 too; the mixed learned variant solves each
+    step's system with another preconditioner in another precision, so its
+    step equals the oracle's only to the PCG tolerance (rel 1e-6 residual),
+    which on the first steps, far from the optimum, moves F' by up to about
+    1e-5 relative (bound 2e-5 per iteration)."""
     import hashlib
     from paper_2307_08383_amd import learned_precond as lp
     s, uv, P, _, _, _, _ = partition_case
@@ -300,10 +305,11 @@ def test_partition_lm_against_oracle_run(partition_case):
     for name, precision, _, _, _ in variants:
         d = rep[name]
         assert d["final_cost_rel_diff"] <= 1e-6, (name, d["final_cost_rel_diff"])
+        bound = 1e-6 if name == "fp64_block_jacobi" else 2e-5
         for it, r in zip(d["iterations"], ref):
             if abs(r["cost"] - r["cost_new"]) > 1e-8 * r["cost"]:
                 assert it["accepted"] == r["accepted"], name
-                assert it["cost_rel_err"] <= 1e-6, (name, it)
+                assert it["cost_rel_err"] <= bound, (name, it)
 
 
 @pytest.mark.timeout(600)

@@ -146,8 +146,12 @@ def test_optimiser_step_is_adam(head):
             # each update is about lr per entry; FP32 rounding of its terms
             # stays far below 1e-3 of it
             assert np.abs(got - w).max() <= 1e-3 * lr + 1e-6 * np.abs(w).max(), t
-            moved = np.abs(got - w0) > 0.5 * lr
-            assert moved.mean() > 0.5
+            if t == 1:
+                # Adam's first step moves every parameter with a gradient by ~lr
+                # (the other head's parameters have none)
+                live = gsum != 0
+                assert live.mean() > 0.3
+                assert (np.abs(got - w0)[live] > 0.5 * lr).mean() > 0.9
             w = got   # continue from the library's weights (rounding only)
     finally:
         for g in graphs:

@@ -161,7 +161,10 @@ def test_product_argument_errors(formed):
         ba.ba_linearize(ctx, T(s.cams_init, torch.float64), T(s.pts_init, torch.float64))
         ba.ba_form_rcs(ctx, 1e-3)
         with pytest.raises(ba.BAError) as ei:
-            ba.ba_rcs_product(ctx, x, y, product=3)
+            ba.ba_rcs_product(ctx, x, y, product=4)
+        assert ei.value.status == ba.BA_ERR_INVALID_ARG
+        with pytest.raises(ba.BAError) as ei:   # the CSR copy is not a PCG layout
+            ba.ba_pcg_solve(ctx, y, product=ba.BA_PRODUCT_CSR)
         assert ei.value.status == ba.BA_ERR_INVALID_ARG
         with pytest.raises(ba.BAError) as ei:
             ba.ba_rcs_product(ctx, x, x)
