@@ -12,6 +12,8 @@
 // off-diagonal blocks are segmented reductions over the observation couples
 // of each camera pair (sorted once, no atomics); the diagonal blocks are
 // reductions over each camera's observations.
+#include <type_traits>
+
 #include "ba_common.hpp"
 
 namespace ba {
@@ -132,6 +134,16 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
     }
 }
 
+// n_bytes (a multiple of CH) from LDS to global memory, contiguous CH-byte
+// chunks spread over the wave's lanes (one fully used cache line per few
+// lanes per instruction)
+template <int CH>
+__device__ __forceinline__ void wave_copy_out(char* __restrict__ dst, const char* src, int n_bytes, int lane) {
+    using V = typename std::conditional<CH == 16, uint4, uint2>::type;
+    for (int o = lane * CH; o < n_bytes; o += kWave * CH)
+        *reinterpret_cast<V*>(dst + o) = *reinterpret_cast<const V*>(src + o);
+}
+
 // ---------------------------------------------------------------------------
 // linearization fused with the point stage (the LM step after an accepted
 // step): one wave per chunk of whole tracks, one lane per observation.  Each
@@ -150,7 +162,7 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
                                                  double* __restrict__ e, double* __restrict__ ptL,
                                                  const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
-    __shared__ double sP[WPB][kWave][kPT];   // track sums, then the head's point terms
+    __shared__ __align__(16) double sP[WPB][kWave][kPT];   // track sums, the head's point terms, then staging
     __shared__ double sh[WPB];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int chunk = blockIdx.x * WPB + wv;
@@ -175,7 +187,6 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
         for (int m = 0; m < 18; ++m) jc[m] = (double)(T)jc[m];
 #pragma unroll
         for (int m = 0; m < 6; ++m) jp[m] = (double)(T)jp[m];
-        store6(Jp_out + (int64_t)k * 6, jp);
         reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
         cost = 0.5 * (eu * eu + ev * ev);
         sP[wv][lane][0] = jp[0] * jp[0] + jp[3] * jp[3];
@@ -206,13 +217,37 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
         for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
     }
     __syncthreads();
+    double K[6];
     if (act) {
-        double K[6];
         point_K(sP[wv][head], jp, K);
-        store_jc(R + (int64_t)k * kRec, jc);
-        store6(R + (int64_t)k * kRec + 18, K);
         store_ebar<T>(sP[wv][head], K, eu, ev, obs_rpos[k], ebar);
     }
+    __syncthreads();   // every lane has its point terms: sP is free for staging
+    // The wave's records (J_c, K) and J_p rows are contiguous in memory; they
+    // are staged through the wave's 6 KB of sP and written with contiguous
+    // 16-byte (or 8-byte) chunks spread over the lanes, instead of each lane
+    // writing its own record at a 192-byte (96-byte) stride.
+    char* stage = reinterpret_cast<char*>(&sP[wv][0][0]);
+    constexpr int kStageB = kWave * kPT * (int)sizeof(double);
+    constexpr int kRecB = kRec * (int)sizeof(T);
+    constexpr int kPer = kStageB / kRecB;      // records per round: 32 (FP64), 64 (FP32)
+    const int nrec = k1 - k0;
+#pragma unroll
+    for (int r0 = 0; r0 < kWave; r0 += kPer) {
+        if (act && lane >= r0 && lane < r0 + kPer) {
+            T* d = reinterpret_cast<T*>(stage + (lane - r0) * kRecB);
+            store_jc(d, jc);
+            store6(d + 18, K);
+        }
+        __syncthreads();
+        wave_copy_out<16>(reinterpret_cast<char*>(R + (int64_t)(k0 + r0) * kRec), stage,
+                          max(0, min(nrec - r0, kPer)) * kRecB, lane);
+        __syncthreads();
+    }
+    constexpr int kJpB = 6 * (int)sizeof(T);
+    if (act) store6(reinterpret_cast<T*>(stage + lane * kJpB), jp);
+    __syncthreads();
+    wave_copy_out<kJpB % 16 == 0 ? 16 : 8>(reinterpret_cast<char*>(Jp_out + (int64_t)k0 * 6), stage, nrec * kJpB, lane);
 }
 
 // FP32 records: 96 registers allow five waves per SIMD without spilling;
