@@ -162,9 +162,16 @@ def evaluate(net, seeds, grid=TRAIN_GRID, lm_iters=8, tol=1e-6, max_iter=1000, l
             row = dict(seed=s, lm_iter=it)
             ref = None
             for name, pre, defl in variants:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
                 r = ba.ba_pcg_solve(ctx, dx, tol=tol, max_iter=max_iter, precond=pre, deflate=defl)
+                torch.cuda.synchronize()
                 row[name + "_iters"] = r["iters"]
                 row[name + "_ms"] = r["ms"]
+                # with the preconditioner's set-up on this RCS (network
+                # inference, exact FSAI, deflation space)
+                row[name + "_wall_ms"] = 1e3 * (time.perf_counter() - t0)
+                row[name + "_capped"] = int(r["status"] == ba.BA_ERR_NOT_CONVERGED)
                 if ref is None:
                     ref = dx.clone()
                 else:
@@ -179,6 +186,8 @@ def evaluate(net, seeds, grid=TRAIN_GRID, lm_iters=8, tol=1e-6, max_iter=1000, l
     for name, _, _ in variants:
         out[name + "_iters"] = sum(r[name + "_iters"] for r in rows)
         out[name + "_ms"] = sum(r[name + "_ms"] for r in rows)
+        out[name + "_wall_ms"] = sum(r[name + "_wall_ms"] for r in rows)
+        out[name + "_capped"] = sum(r[name + "_capped"] for r in rows)
     out["iter_ratio"] = out["learned_iters"] / max(out["bj_iters"], 1)
     return out
 
@@ -215,11 +224,31 @@ def main():
                     help="held-out seeds evaluated on the full 50 x 40 aerial grid as well")
     ap.add_argument("--kinds", default="aerial", help="training scene kinds, comma separated: " + ", ".join(KINDS))
     ap.add_argument("--eval-kinds", default="", help="scene kinds evaluated on held-out seeds (default: --kinds)")
+    ap.add_argument("--eval-only", action="store_true",
+                    help="no training: evaluate the weights of --weights (default: the head's shipped weights)")
+    ap.add_argument("--weights", default=None)
     args = ap.parse_args()
     from . import ba
     out = args.out or (DEFAULT_FSAI_WEIGHTS if args.head == "fsai" else DEFAULT_WEIGHTS)
     log = lambda m: print(m, flush=True)
     t0 = time.time()
+    if args.eval_only:
+        wpath = args.weights or (DEFAULT_FSAI_WEIGHTS if args.head == "fsai" else DEFAULT_WEIGHTS)
+        net = ba.ba_gnn_create(load_weights(wpath))
+        rep = dict(head=args.head, weights=os.path.basename(wpath), eval_seeds=args.eval_seeds,
+                   lm_iters=args.lm_iters)
+        for k in (args.eval_kinds or "aerial_full").split(","):
+            ev = evaluate(net, _range(args.eval_seeds), grid=KINDS[k], lm_iters=args.lm_iters, log=log,
+                          head=args.head)
+            rep["eval_" + k] = dict((kk, v) for kk, v in ev.items() if kk != "rows")
+            rep["eval_" + k + "_rows"] = ev["rows"]
+            log(json.dumps(rep["eval_" + k]))
+        ba.ba_gnn_destroy(net)
+        if args.report:
+            with open(args.report, "w") as f:
+                json.dump(rep, f, indent=1)
+        log(f"evaluated in {time.time() - t0:.1f} s")
+        return
     kinds = args.kinds.split(",")
     grids = [KINDS[k] for k in kinds]
     graphs = collect_graphs(_range(args.train_seeds), lm_iters=args.lm_iters, log=log, grids=grids)

@@ -310,6 +310,70 @@ def partition_scene(seed=2, noise_sigma=0.5, nx=250, ny=240, ring=2, n_pts=25_00
                      pcg_tol=1e-6, with_stats=with_stats)
 
 
+@dataclasses.dataclass
+class SharedScene:
+    """Images sharing the interior parameters of their physical camera:
+    exterior [n_img][6] (axis-angle w, t), interior [n_phys][5] (f, cx, cy,
+    k1, k2), img_cam [n_img] (physical camera of each image)."""
+    name: str
+    seed: int
+    n_img: int
+    n_phys: int
+    n_pts: int
+    n_obs: int
+    img_cam: np.ndarray        # int32 [n_img]
+    ext_true: np.ndarray       # float64 [n_img][6]
+    intr_true: np.ndarray      # float64 [n_phys][5]
+    pts_true: np.ndarray       # float64 [n_pts][3]
+    ext_init: np.ndarray
+    intr_init: np.ndarray
+    pts_init: np.ndarray
+    obs_img: np.ndarray        # int32 [n_obs]
+    obs_pt: np.ndarray         # int32 [n_obs]
+    noise: np.ndarray          # float64 [2][n_obs]
+    img_fixed: np.ndarray      # uint8 [n_img]
+
+
+def shared_intrinsics_scene(seed=0, nx=10, ny=8, n_pts=20_000, n_phys=4, noise_sigma=0.5, altitude=2.5,
+                            relief=0.25, intr_sigma=0.0):
+    """The aerial grid (nadir images on an nx x ny grid, 60% overlap, tracks
+    truncated-geometric on [2, 12] with mean 4, each point seen by its t
+    nearest images) flown with n_phys physical cameras: image i is taken by
+    camera i mod n_phys.  Interior: f ~ U(950, 1050) px, principal point
+    (cx, cy) ~ U(-5, 5) px, k1 ~ U(-0.05, 0.05), k2 ~ U(-0.01, 0.01).  Start:
+    poses perturbed as in the other scenes, interior parameters moved by
+    N(0, intr_sigma) relative (0: at their true values)."""
+    rng = np.random.default_rng(seed)
+    xs = np.arange(nx, dtype=np.float64)
+    ys = np.arange(ny, dtype=np.float64)
+    gx, gy = np.meshgrid(xs, ys, indexing="xy")
+    centres = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, altitude)], axis=1)
+    n_img = centres.shape[0]
+    half = 0.5 * altitude
+    pts = np.stack([rng.uniform(xs[0] - half, xs[-1] + half, n_pts),
+                    rng.uniform(ys[0] - half, ys[-1] + half, n_pts),
+                    rng.uniform(0.0, relief, n_pts)], axis=1)
+    t, _ = _truncated_geometric(rng, n_pts, 2, 12, 4.0)
+    obs_pt, obs_img = _nearest_cams(centres[:, :2], pts[:, :2], t, 12)
+    intr = np.stack([rng.uniform(950.0, 1050.0, n_phys), rng.uniform(-5.0, 5.0, n_phys),
+                     rng.uniform(-5.0, 5.0, n_phys), rng.uniform(-0.05, 0.05, n_phys),
+                     rng.uniform(-0.01, 0.01, n_phys)], axis=1)
+    w, rot = _nadir_rotvecs(rng, n_img, 0.02)
+    ext = np.concatenate([w, _translations(rot, centres)], axis=1)
+    noise = rng.normal(0.0, 1.0, size=(2, obs_pt.size)) * noise_sigma
+    from scipy.spatial.transform import Rotation
+    rot_init = Rotation.from_rotvec(rng.normal(0.0, 0.01, size=(n_img, 3))) * rot
+    centres_init = centres + rng.normal(0.0, 0.05, size=(n_img, 3))
+    ext_init = np.concatenate([rot_init.as_rotvec(), _translations(rot_init, centres_init)], axis=1)
+    intr_init = intr * (1.0 + rng.normal(0.0, 1.0, size=intr.shape) * intr_sigma)
+    pts_init = pts + rng.normal(0.0, 0.05, size=pts.shape)
+    return SharedScene(name=f"shared-{n_img}img-{n_phys}cam-{n_pts}pt", seed=seed, n_img=n_img, n_phys=n_phys,
+                       n_pts=n_pts, n_obs=int(obs_pt.size), img_cam=(np.arange(n_img) % n_phys).astype(np.int32),
+                       ext_true=ext, intr_true=intr, pts_true=pts, ext_init=ext_init, intr_init=intr_init,
+                       pts_init=pts_init, obs_img=obs_img.astype(np.int32), obs_pt=obs_pt.astype(np.int32),
+                       noise=noise, img_fixed=np.zeros(n_img, np.uint8))
+
+
 WORKLOADS = {
     "tiny": tiny_scene,
     "aerial": aerial_grid_scene,
