@@ -90,6 +90,41 @@ typedef struct ba_problem_desc {
  * NULL on error and the message is available from ba_last_error(NULL). */
 ba_status ba_create(const ba_problem_desc* desc, ba_ctx** out);
 
+/* Shared intrinsics (Sec. 4.1 counts c = 11 unknowns per camera, 6 exterior
+ * and 5 interior; Table 2's datasets have fewer physical cameras than
+ * images): image i has exterior parameters [w (3) axis-angle, t (3)] and is
+ * taken by physical camera img_cam[i], whose interior parameters
+ * [f, cx, cy, k1, k2] all its images share; pixel = (f d x + cx, f d y + cy)
+ * with x, y, d as above.  In a context made by ba_create_shared the
+ * parameter array `cams` of ba_linearize and ba_lm_step is device
+ * [n_imgs * 6 + n_phys * 5]: the exterior parameters of every image, then the
+ * interior parameters of every physical camera.  RCS rows are the free
+ * images (exterior block in slots 0..5 of the row's 9) followed by the
+ * physical cameras (interior block in slots 0..4); the unused slots carry an
+ * identity diagonal and a zero right-hand side, so their solution is 0.
+ * Block (u, v) is present iff a point is observed through both rows (an
+ * image's row and its camera's row always are).  FP64 only; PCG with
+ * block-Jacobi or FSAI (no deflation, no learned network), no
+ * re-triangulation, no ba_get_jacobians or ba_triangulate.  Other fields and
+ * errors as in ba_problem_desc / ba_create; img_cam entries outside
+ * [0, n_phys) give BA_ERR_INVALID_ARG. */
+typedef struct ba_shared_desc {
+    int32_t n_imgs;             /* images, > 0 */
+    int32_t n_phys;             /* physical cameras, > 0 */
+    int32_t n_pts;              /* points, > 0 */
+    int32_t reserved;           /* 0 */
+    int64_t n_obs;              /* observations, 0 < n_obs < 2^30 */
+    const int32_t* obs_img;     /* device [n_obs]: image of each observation */
+    const int32_t* obs_pt;      /* device [n_obs] */
+    const double* obs_uv;       /* device [2][n_obs] */
+    const int32_t* img_cam;     /* device [n_imgs]: physical camera of each image */
+    const uint8_t* img_fixed;   /* device [n_imgs] or NULL: exterior held fixed */
+    void* stream;
+    size_t workspace_cap;
+} ba_shared_desc;
+
+ba_status ba_create_shared(const ba_shared_desc* desc, ba_ctx** out);
+
 /* Frees the context and its device workspace.  NULL is a no-op. */
 void ba_destroy(ba_ctx* ctx);
 

@@ -258,3 +258,55 @@ class SharedProblem:
         rhs = np.zeros((n_nodes, 9))
         rhs[node, slot] = b
         return rp, ci, blk, rhs
+
+    def dense_step(self, ext, intr, pts, lam):
+        """Solution of the damped normal equations (Eq. (1)) over all unknowns
+        by a dense solve: (dx_ext [n_img][6], dx_intr [n_phys][5],
+        dx_pts [n_pts][3]), F, and the predicted decrease dx^T l - 1/2 |J dx|^2."""
+        F, e, Je, Jq, Jp = linearize(ext, intr, self.img_cam, pts, self.obs_img, self.obs_pt, self.uv)
+        m = self.m
+        J = np.zeros((2 * len(self.obs_img), m + 3 * self.n_pts))
+        for k in range(len(self.obs_img)):
+            idx, Jc = self._cam_cols(k, Je, Jq)
+            J[2 * k:2 * k + 2, idx] = Jc
+            p = self.obs_pt[k]
+            J[2 * k:2 * k + 2, m + 3 * p:m + 3 * p + 3] = Jp[k]
+        H = J.T @ J
+        g = -J.T @ e.ravel()
+        A = H + lam * np.diag(np.diag(H))
+        dx = np.linalg.solve(A, g)
+        pred = float(dx @ g - 0.5 * np.sum((J @ dx) ** 2))
+        dext = np.zeros((self.n_img, NE))
+        for i in range(self.n_img):
+            ei = self.ext_index(i)
+            if ei is not None:
+                dext[i] = dx[ei]
+        dintr = np.stack([dx[self.intr_index(k)] for k in range(self.n_phys)])
+        return dext, dintr, dx[m:].reshape(-1, 3), F, pred
+
+    def cost(self, ext, intr, pts):
+        return linearize(ext, intr, self.img_cam, pts, self.obs_img, self.obs_pt, self.uv)[0]
+
+
+def lm_run(problem, ext, intr, pts, iterations, lam0=1e-4):
+    """Fixed budget of LM iterations with exact steps (dense solves) and the
+    damping schedule of the 9-parameter oracle: accept iff the predicted
+    decrease is positive and F' < F; on accept lambda *= max(1/3,
+    1 - (2 rho - 1)^3), nu = 2; on reject lambda *= nu, nu *= 2."""
+    ext, intr, pts = ext.copy(), intr.copy(), pts.copy()
+    lam, nu = lam0, 2.0
+    hist = []
+    for _ in range(iterations):
+        dext, dintr, dpts, F, pred = problem.dense_step(ext, intr, pts, lam)
+        Fn = problem.cost(ext + dext, intr + dintr, pts + dpts)
+        rho = (F - Fn) / pred
+        ok = pred > 0 and Fn < F
+        if ok:
+            ext, intr, pts = ext + dext, intr + dintr, pts + dpts
+            lam *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+            nu = 2.0
+        else:
+            lam *= nu
+            nu *= 2.0
+        hist.append(dict(cost=F, cost_new=Fn, accepted=int(ok), rho=rho, lambda_after=lam))
+    return ext, intr, pts, hist

@@ -30,6 +30,13 @@ class ProblemDesc(C.Structure):
                 ("stream", C.c_void_p), ("workspace_cap", C.c_size_t)]
 
 
+class SharedDesc(C.Structure):
+    _fields_ = [("n_imgs", C.c_int32), ("n_phys", C.c_int32), ("n_pts", C.c_int32), ("reserved", C.c_int32),
+                ("n_obs", C.c_int64), ("obs_img", C.c_void_p), ("obs_pt", C.c_void_p), ("obs_uv", C.c_void_p),
+                ("img_cam", C.c_void_p), ("img_fixed", C.c_void_p), ("stream", C.c_void_p),
+                ("workspace_cap", C.c_size_t)]
+
+
 class PcgOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precond", C.c_int32), ("x0", C.c_void_p),
                 ("deflate", C.c_int32), ("solver_fp32", C.c_int32), ("product", C.c_int32),
@@ -76,6 +83,7 @@ _vp, _dp = C.c_void_p, C.POINTER(C.c_double)
 SIGNATURES = {
     "ba_create": (C.c_int, [C.POINTER(ProblemDesc), C.POINTER(C.c_void_p)]),
     "ba_destroy": (None, [_vp]),
+    "ba_create_shared": (C.c_int, [C.POINTER(SharedDesc), C.POINTER(C.c_void_p)]),
     "ba_linearize": (C.c_int, [_vp, _vp, _vp, _dp]),
     "ba_form_rcs": (C.c_int, [_vp, C.c_double]),
     "ba_pcg_solve": (C.c_int, [_vp, C.POINTER(PcgOpts), _vp, C.POINTER(PcgInfo)]),
@@ -171,6 +179,20 @@ def ba_create(n_cams, n_pts, obs_cam, obs_pt, obs_uv, cam_fixed=None, precision=
                     precision=precision, reserved=0, stream=_stream(stream), workspace_cap=workspace_cap)
     h = C.c_void_p()
     _check(lib().ba_create(C.byref(d), C.byref(h)))
+    return h
+
+
+def ba_create_shared(n_imgs, n_phys, n_pts, obs_img, obs_pt, obs_uv, img_cam, img_fixed=None, stream=None,
+                     workspace_cap=0):
+    """Shared-intrinsics context: obs_img/obs_pt int32 [n_obs], obs_uv float64
+    [2][n_obs], img_cam int32 [n_imgs], img_fixed uint8 [n_imgs] or None."""
+    import torch
+    assert obs_img.dtype == torch.int32 and obs_pt.dtype == torch.int32 and img_cam.dtype == torch.int32
+    d = SharedDesc(n_imgs=n_imgs, n_phys=n_phys, n_pts=n_pts, reserved=0, n_obs=obs_img.numel(),
+                   obs_img=_ptr(obs_img), obs_pt=_ptr(obs_pt), obs_uv=_ptr(obs_uv), img_cam=_ptr(img_cam),
+                   img_fixed=_ptr(img_fixed), stream=_stream(stream), workspace_cap=workspace_cap)
+    h = C.c_void_p()
+    _check(lib().ba_create_shared(C.byref(d), C.byref(h)))
     return h
 
 

@@ -63,7 +63,7 @@ void free_ctx(ba_ctx* c) {
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
                     c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
                     c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.gu_src, c->fs.gl_self, c->fs.tg, c->pcg.bm, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G,
-                    c->tri_failed, c->csr.bptr, c->csr.slot_src, c->csr.slot_col, c->csr.slot_row, c->csr.rowptr, c->csr.col, c->csr.val};
+                    c->tri_failed, c->img_cam, c->lin_params, c->lin_pts, c->csr.bptr, c->csr.slot_src, c->csr.slot_col, c->csr.slot_row, c->csr.rowptr, c->csr.col, c->csr.val};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -141,6 +141,11 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     std::vector<int32_t> cam_row(nc);
     int32_t nr = 0;
     for (int32_t i = 0; i < nc; ++i) cam_row[i] = (!fixed.empty() && fixed[i]) ? -1 : nr++;
+    // shared intrinsics: the physical cameras' interior blocks are rows after
+    // the free images' exterior blocks
+    const bool shared = c->shared;
+    c->n_free = nr;
+    if (shared) nr += c->n_phys;
     c->n_rows = nr;
     std::vector<int32_t> ocam(n), opt(n), orow(n);
     std::vector<double> ouv(2 * n);
@@ -162,40 +167,58 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         }
     chunk.push_back((int32_t)n);
     c->n_chunk = (int32_t)chunk.size() - 1;
-    // observation couples of every pair of free cameras sharing a point
-    int64_t ntr = 0;
-    for (int32_t p = 0; p < np; ++p) {
-        int64_t f = 0;
-        for (int32_t k = ptr[p]; k < ptr[p + 1]; ++k) f += orow[k] >= 0;
-        ntr += f * (f - 1) / 2;
+    // records: one per observation (J_c, K), or with shared intrinsics two
+    // (exterior part at the image's row, interior part at its camera's row);
+    // rrow is the RCS row of each record (-1: fixed), rptr the tracks
+    const int64_t n_rec = shared ? 2 * n : n;
+    std::vector<int32_t> rrow(n_rec), rptr(np + 1);
+    for (int64_t k = 0; k < n; ++k) {
+        if (shared) {
+            rrow[2 * k] = orow[k];
+            rrow[2 * k + 1] = c->n_free + c->h_img_cam[ocam[k]];
+        } else {
+            rrow[k] = orow[k];
+        }
     }
+    for (int32_t q = 0; q <= np; ++q) rptr[q] = shared ? 2 * ptr[q] : ptr[q];
+    // couples of records of a track whose rows differ (each unordered pair
+    // once, oriented from the lower row); with shared intrinsics also every
+    // ordered pair of records on the same row, itself included: those sum
+    // into the diagonal block (a camera's images seeing one point)
+    auto take = [&](int32_t a, int32_t b) {
+        const int32_t ra = rrow[a], rb = rrow[b];
+        if (ra < 0 || rb < 0) return false;
+        return shared ? ra <= rb : a < b;
+    };
+    int64_t ntr = 0;
+    for (int32_t p = 0; p < np; ++p)
+        for (int32_t a = rptr[p]; a < rptr[p + 1]; ++a)
+            for (int32_t b = shared ? rptr[p] : a + 1; b < rptr[p + 1]; ++b)
+                if (take(a, b)) ntr += 1;
     if (ntr > INT32_MAX) throw ba_invalid{"too many camera-pair couples for 32-bit indices"};
     std::vector<int32_t> ta(ntr), tb(ntr);
     {
         int64_t m = 0;
         for (int32_t p = 0; p < np; ++p)
-            for (int32_t a = ptr[p]; a < ptr[p + 1]; ++a) {
-                if (orow[a] < 0) continue;
-                for (int32_t b = a + 1; b < ptr[p + 1]; ++b)
-                    if (orow[b] >= 0) { ta[m] = a; tb[m] = b; ++m; }
-            }
+            for (int32_t a = rptr[p]; a < rptr[p + 1]; ++a)
+                for (int32_t b = shared ? rptr[p] : a + 1; b < rptr[p + 1]; ++b)
+                    if (take(a, b)) { ta[m] = a; tb[m] = b; ++m; }
     }
-    // stable two-pass counting sort by (row(a), row(b)); rows increase along
-    // a track because cameras do, so row(a) < row(b)
+    // stable two-pass counting sort by (row(a), row(b)); row(a) <= row(b)
     std::vector<int32_t> ta2(ntr), tb2(ntr);
     {
         std::vector<int64_t> cnt(nr + 1, 0);
-        for (int64_t m = 0; m < ntr; ++m) cnt[orow[tb[m]] + 1]++;
+        for (int64_t m = 0; m < ntr; ++m) cnt[rrow[tb[m]] + 1]++;
         for (int32_t r = 0; r < nr; ++r) cnt[r + 1] += cnt[r];
         for (int64_t m = 0; m < ntr; ++m) {
-            const int64_t d = cnt[orow[tb[m]]]++;
+            const int64_t d = cnt[rrow[tb[m]]]++;
             ta2[d] = ta[m]; tb2[d] = tb[m];
         }
         std::fill(cnt.begin(), cnt.end(), 0);
-        for (int64_t m = 0; m < ntr; ++m) cnt[orow[ta2[m]] + 1]++;
+        for (int64_t m = 0; m < ntr; ++m) cnt[rrow[ta2[m]] + 1]++;
         for (int32_t r = 0; r < nr; ++r) cnt[r + 1] += cnt[r];
         for (int64_t m = 0; m < ntr; ++m) {
-            const int64_t d = cnt[orow[ta2[m]]]++;
+            const int64_t d = cnt[rrow[ta2[m]]]++;
             ta[d] = ta2[m]; tb[d] = tb2[m];
         }
     }
@@ -213,14 +236,18 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
             row_ptr[r] = blk_id;
             col_idx.push_back(r);
             ++blk_id;
-            while (m < ntr && orow[ta[m]] == r) {
-                const int32_t s = orow[tb[m]];
-                off_blk.push_back((int32_t)blk_id);
+            while (m < ntr && rrow[ta[m]] == r) {
+                const int32_t s = rrow[tb[m]];
                 pair_ptr.push_back((int32_t)m);
                 seg_row.push_back(r);
-                col_idx.push_back(s);
-                ++blk_id;
-                while (m < ntr && orow[ta[m]] == r && orow[tb[m]] == s) ++m;
+                if (s == r) {
+                    off_blk.push_back((int32_t)row_ptr[r]);   // same-row couples: the diagonal block
+                } else {
+                    off_blk.push_back((int32_t)blk_id);
+                    col_idx.push_back(s);
+                    ++blk_id;
+                }
+                while (m < ntr && rrow[ta[m]] == r && rrow[tb[m]] == s) ++m;
             }
         }
         row_ptr[nr] = blk_id;
@@ -297,8 +324,8 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
                 }
         }
         std::vector<int64_t> row_obs(nr, 0);
-        for (int64_t k = 0; k < n; ++k)
-            if (orow[k] >= 0) row_obs[orow[k]]++;
+        for (int64_t k = 0; k < n_rec; ++k)
+            if (rrow[k] >= 0) row_obs[rrow[k]]++;
         const double rec = (double)kRec * (c->precision == BA_MIXED ? sizeof(float) : sizeof(double));
         const double budget = 4.0 * (1 << 20);   // one XCD's L2
         std::vector<int32_t> queue;
@@ -371,19 +398,20 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         c->n_pblk = n_p;
     }
     c->h_blk_pairs.assign(c->n_blk, 0);
-    for (int32_t sg = 0; sg < c->n_offseg; ++sg) c->h_blk_pairs[off_blk[sg]] = pair_ptr[sg + 1] - pair_ptr[sg];
-    // observations of each RCS row
+    for (int32_t sg = 0; sg < c->n_offseg; ++sg)
+        if (off_blk[sg] != row_ptr[seg_row[sg]]) c->h_blk_pairs[off_blk[sg]] = pair_ptr[sg + 1] - pair_ptr[sg];
+    // records of each RCS row
     std::vector<int32_t> rowobs_ptr(nr + 1, 0), rowobs;
-    for (int64_t k = 0; k < n; ++k)
-        if (orow[k] >= 0) rowobs_ptr[orow[k] + 1]++;
+    for (int64_t k = 0; k < n_rec; ++k)
+        if (rrow[k] >= 0) rowobs_ptr[rrow[k] + 1]++;
     for (int32_t r = 0; r < nr; ++r) rowobs_ptr[r + 1] += rowobs_ptr[r];
     rowobs.resize(rowobs_ptr[nr]);
-    std::vector<int32_t> obs_rpos(n, -1);   // position of each observation in its row's list
+    std::vector<int32_t> obs_rpos(n_rec, -1);   // position of each record in its row's list
     {
         std::vector<int32_t> fill(rowobs_ptr.begin(), rowobs_ptr.end() - 1);
-        for (int64_t k = 0; k < n; ++k)
-            if (orow[k] >= 0) {
-                const int32_t d = fill[orow[k]]++;
+        for (int64_t k = 0; k < n_rec; ++k)
+            if (rrow[k] >= 0) {
+                const int32_t d = fill[rrow[k]]++;
                 rowobs[d] = (int32_t)k;
                 obs_rpos[k] = d;
             }
@@ -394,18 +422,19 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     std::vector<int32_t> lo_ptr, lo_blk;   // upper blocks (s, r), s < r, of each column r
     {
         std::vector<int32_t> trn(nr, 0);
-        for (int32_t sg = 0; sg < c->n_offseg; ++sg) trn[col_idx[off_blk[sg]]]++;
+        for (int32_t r = 0; r < nr; ++r)
+            for (int64_t kb = row_ptr[r] + 1; kb < row_ptr[r + 1]; ++kb) trn[col_idx[kb]]++;
         for (int32_t r = 0; r < nr; ++r) sf_ptr[r + 1] = sf_ptr[r] + (int32_t)(row_ptr[r + 1] - row_ptr[r]) + trn[r];
         std::vector<int32_t> tr_ptr(nr + 1, 0);
         for (int32_t r = 0; r < nr; ++r) tr_ptr[r + 1] = tr_ptr[r] + trn[r];
         std::vector<int32_t> tr_blk(tr_ptr[nr]), tr_row(tr_ptr[nr]);
         std::vector<int32_t> fill(tr_ptr.begin(), tr_ptr.end() - 1);
-        for (int32_t sg = 0; sg < c->n_offseg; ++sg) {   // segments are in row order
-            const int32_t s = col_idx[off_blk[sg]];
-            const int32_t d = fill[s]++;
-            tr_blk[d] = off_blk[sg];
-            tr_row[d] = seg_row[sg];
-        }
+        for (int32_t r = 0; r < nr; ++r)   // in row order
+            for (int64_t kb = row_ptr[r] + 1; kb < row_ptr[r + 1]; ++kb) {
+                const int32_t d = fill[col_idx[kb]]++;
+                tr_blk[d] = (int32_t)kb;
+                tr_row[d] = r;
+            }
         sf_col.resize(sf_ptr[nr]);
         sf_src.resize(sf_ptr[nr]);
         for (int32_t r = 0; r < nr; ++r) {
@@ -453,17 +482,19 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->sf_src, sf_src);
     upload(c, &c->lo_ptr, lo_ptr);
     upload(c, &c->lo_blk, lo_blk);
+    if (shared) upload(c, &c->img_cam, c->h_img_cam);
     BA_HIP_CHECK(hipStreamSynchronize(c->stream));
     c->h_row_ptr = std::move(row_ptr);
     c->h_col_idx = std::move(col_idx);
     c->h_perm = std::move(perm);
     // workspace
     const size_t es = c->precision == BA_MIXED ? sizeof(float) : sizeof(double);
-    dalloc(c, (char**)&c->R, (size_t)n * kRec * es);
+    dalloc(c, (char**)&c->R, (size_t)n_rec * kRec * es);
     dalloc(c, (char**)&c->Jp, (size_t)n * 6 * es);
     dalloc(c, &c->e, (size_t)n * 2);
     dalloc(c, &c->ptL, (size_t)np * 9);
-    dalloc(c, &c->ebar, (size_t)rowobs_ptr[nr] * 2);
+    // e + K lhat: in row-list order, or (shared intrinsics) by observation
+    dalloc(c, &c->ebar, (size_t)(shared ? n : rowobs_ptr[nr]) * 2);
     dalloc(c, &c->pblk, (size_t)c->n_pblk * 81);
     dalloc(c, &c->blk, (size_t)c->n_blk * 81);
     dalloc(c, &c->Sf, (size_t)c->n_sf * 81);
@@ -542,11 +573,19 @@ ba_status form_rcs_async(ba_ctx* c, double lambda, bool point_done = false) {
         BA_HIP_CHECK(hipMemsetAsync(c->flags + 3, 0, 5 * sizeof(int), c->stream));
     }
     BA_HIP_CHECK(hipEventRecord(c->ev[1], c->stream));
-    if (!point_done) ba::launch_point(c, lambda);
+    if (!point_done) {
+        if (c->shared)   // the point terms need the Jacobians again: one fused pass
+            ba::launch_linpoint_shared(c, c->lin_params, c->lin_pts, lambda);
+        else
+            ba::launch_point(c, lambda);
+    }
     BA_HIP_CHECK(hipEventRecord(c->ev[2], c->stream));
     ba::launch_offdiag(c);
     BA_HIP_CHECK(hipEventRecord(c->ev[3], c->stream));
-    ba::launch_diag(c, lambda);
+    if (c->shared)
+        ba::launch_node_diag(c, lambda);
+    else
+        ba::launch_diag(c, lambda);
     BA_HIP_CHECK(hipEventRecord(c->ev[4], c->stream));
     BA_HIP_CHECK(hipGetLastError());
     c->have_rcs = true;
@@ -559,6 +598,9 @@ ba_status form_rcs_async(ba_ctx* c, double lambda, bool point_done = false) {
     c->lambda = lambda;
     return BA_OK;
 }
+
+// parameters of a shared-intrinsics context: [n_cams][6] then [n_phys][5]
+size_t n_params(const ba_ctx* c) { return 6 * (size_t)c->n_cams + 5 * (size_t)c->n_phys; }
 
 // selects the S copy and the product layout of the next solve (allocating
 // the FP32 copies on first use)
@@ -760,6 +802,7 @@ extern "C" {
 
 ba_status ba_set_preconditioner_net(ba_ctx* c, ba_gnn* net) {
     if (!c) return BA_ERR_INVALID_ARG;
+    if (c->shared && net) { c->err = "the network is trained on 9-parameter camera blocks"; return BA_ERR_INVALID_ARG; }
     return guarded(c, [&]() {
         c->net = net;
         c->learned_ready = net != nullptr;
@@ -855,6 +898,61 @@ ba_status ba_create(const ba_problem_desc* d, ba_ctx** out) {
     return BA_OK;
 }
 
+ba_status ba_create_shared(const ba_shared_desc* d, ba_ctx** out) {
+    if (out) *out = nullptr;
+    g_create_error.clear();
+    if (!d || !out) { g_create_error = "null descriptor or output"; return BA_ERR_INVALID_ARG; }
+    if (d->n_imgs <= 0 || d->n_phys <= 0 || d->n_pts <= 0 || d->n_obs <= 0 || d->n_obs >= INT32_MAX / 2) {
+        g_create_error = "sizes must satisfy n_imgs, n_phys, n_pts > 0 and 0 < n_obs < 2^30";
+        return BA_ERR_INVALID_ARG;
+    }
+    if (!d->obs_img || !d->obs_pt || !d->obs_uv || !d->img_cam) {
+        g_create_error = "null observation or camera arrays";
+        return BA_ERR_INVALID_ARG;
+    }
+    ba_ctx* c = new ba_ctx();
+    c->n_cams = d->n_imgs;
+    c->n_pts = d->n_pts;
+    c->n_obs = d->n_obs;
+    c->precision = BA_FP64;
+    c->stream = (hipStream_t)d->stream;
+    c->cap = d->workspace_cap;
+    c->shared = true;
+    c->n_phys = d->n_phys;
+    ba_status st = guarded(c, [&]() {
+        BA_HIP_CHECK(hipGetDevice(&c->device));
+        const int64_t n = c->n_obs;
+        std::vector<int32_t> cam(n), pt(n);
+        std::vector<double> uv(2 * n);
+        std::vector<uint8_t> fixed;
+        c->h_img_cam.resize(c->n_cams);
+        BA_HIP_CHECK(hipMemcpyAsync(cam.data(), d->obs_img, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(pt.data(), d->obs_pt, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(uv.data(), d->obs_uv, 2 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipMemcpyAsync(c->h_img_cam.data(), d->img_cam, c->n_cams * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, c->stream));
+        if (d->img_fixed) {
+            fixed.resize(c->n_cams);
+            BA_HIP_CHECK(hipMemcpyAsync(fixed.data(), d->img_fixed, c->n_cams, hipMemcpyDeviceToHost, c->stream));
+        }
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        for (int32_t i = 0; i < c->n_cams; ++i)
+            if (c->h_img_cam[i] < 0 || c->h_img_cam[i] >= c->n_phys)
+                throw ba_invalid{"img_cam[" + std::to_string(i) + "] out of range"};
+        build(c, cam, pt, uv, fixed);
+        dalloc(c, &c->lin_params, n_params(c));
+        dalloc(c, &c->lin_pts, (size_t)c->n_pts * 3);
+        return BA_OK;
+    });
+    if (st != BA_OK) {
+        g_create_error = c->err;
+        free_ctx(c);
+        return st;
+    }
+    *out = c;
+    return BA_OK;
+}
+
 void ba_destroy(ba_ctx* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
@@ -878,6 +976,7 @@ ba_status ba_project(const double* cams, const double* pts, const int32_t* obs_c
 ba_status ba_triangulate(ba_ctx* c, const double* cams, double* pts, int32_t linear_init, int32_t n_gn,
                          int64_t* n_failed) {
     if (!c) return BA_ERR_INVALID_ARG;
+    if (c->shared) { c->err = "ba_triangulate takes 9-parameter cameras"; return BA_ERR_INVALID_ARG; }
     if (!cams || !pts) { c->err = "null parameter arrays"; return BA_ERR_INVALID_ARG; }
     if (n_gn < 0 || n_gn > 100) { c->err = "n_gn must be 0..100"; return BA_ERR_INVALID_ARG; }
     return guarded(c, [&]() {
@@ -897,9 +996,19 @@ ba_status ba_linearize(ba_ctx* c, const double* cams, const double* pts, double*
     return guarded(c, [&]() {
         BA_HIP_CHECK(hipEventRecord(c->ev[0], c->stream));
         BA_HIP_CHECK(hipMemsetAsync(c->flags + 2, 0, sizeof(int), c->stream));
-        ba::launch_linearize(c, cams, pts);
-        BA_HIP_CHECK(hipMemcpyAsync(c->lin_cams, cams, (size_t)c->n_cams * 9 * sizeof(double),
-                                    hipMemcpyDeviceToDevice, c->stream));
+        if (c->shared) {
+            // the Jacobians are formed again with the damping by ba_form_rcs
+            // (one fused pass); the parameters are kept for it
+            BA_HIP_CHECK(hipMemcpyAsync(c->lin_params, cams, n_params(c) * sizeof(double), hipMemcpyDeviceToDevice,
+                                        c->stream));
+            BA_HIP_CHECK(hipMemcpyAsync(c->lin_pts, pts, (size_t)c->n_pts * 3 * sizeof(double),
+                                        hipMemcpyDeviceToDevice, c->stream));
+            ba::launch_linpoint_shared(c, c->lin_params, c->lin_pts, 0.0);
+        } else {
+            ba::launch_linearize(c, cams, pts);
+            BA_HIP_CHECK(hipMemcpyAsync(c->lin_cams, cams, (size_t)c->n_cams * 9 * sizeof(double),
+                                        hipMemcpyDeviceToDevice, c->stream));
+        }
         c->defl_ready = false;
         BA_HIP_CHECK(hipEventRecord(c->ev[5], c->stream));
         BA_HIP_CHECK(hipGetLastError());
@@ -962,6 +1071,10 @@ ba_status ba_pcg_solve(ba_ctx* c, const ba_pcg_opts* o, double* dxc, ba_pcg_info
     if (pre != BA_PRECOND_LEARNED && pre != BA_PRECOND_BLOCK_JACOBI && pre != BA_PRECOND_FSAI &&
         pre != BA_PRECOND_LEARNED_FSAI) {
         c->err = "unknown preconditioner";
+        return BA_ERR_INVALID_ARG;
+    }
+    if (c->shared && ((o && o->deflate) || pre == BA_PRECOND_LEARNED || pre == BA_PRECOND_LEARNED_FSAI)) {
+        c->err = "shared-intrinsics contexts take block-Jacobi or FSAI, without deflation";
         return BA_ERR_INVALID_ARG;
     }
     return guarded(c, [&]() {
@@ -1027,7 +1140,10 @@ ba_status ba_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
     if (!c->have_rcs) { c->err = "ba_back_substitute needs a formed RCS"; return BA_ERR_STATE; }
     if (!dxc || !dxp) { c->err = "null dxc or dxp"; return BA_ERR_INVALID_ARG; }
     return guarded(c, [&]() {
-        ba::launch_back_substitute(c, dxc, dxp);
+        if (c->shared)
+            ba::launch_back_substitute_shared(c, dxc, dxp);
+        else
+            ba::launch_back_substitute(c, dxc, dxp);
         BA_HIP_CHECK(hipGetLastError());
         return BA_OK;
     });
@@ -1060,6 +1176,11 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         c->err = "retriangulate must be 0..100 Gauss-Newton steps";
         return BA_ERR_INVALID_ARG;
     }
+    if (c->shared && ((o && (o->deflate || o->retriangulate)) || pre == BA_PRECOND_LEARNED ||
+                      pre == BA_PRECOND_LEARNED_FSAI)) {
+        c->err = "shared-intrinsics contexts take block-Jacobi or FSAI, without deflation or re-triangulation";
+        return BA_ERR_INVALID_ARG;
+    }
     return guarded(c, [&]() {
         ba_lm_info I;
         std::memset(&I, 0, sizeof I);
@@ -1070,9 +1191,17 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         if (relin) {
             // linearization and point stage in one pass (the records are written whole)
             BA_HIP_CHECK(hipMemsetAsync(c->flags, 0, 8 * sizeof(int), c->stream));
-            ba::launch_linearize_point(c, cams, pts, st->lambda);
-            BA_HIP_CHECK(hipMemcpyAsync(c->lin_cams, cams, (size_t)c->n_cams * 9 * sizeof(double),
-                                        hipMemcpyDeviceToDevice, c->stream));
+            if (c->shared) {
+                BA_HIP_CHECK(hipMemcpyAsync(c->lin_params, cams, n_params(c) * sizeof(double),
+                                            hipMemcpyDeviceToDevice, c->stream));
+                BA_HIP_CHECK(hipMemcpyAsync(c->lin_pts, pts, (size_t)c->n_pts * 3 * sizeof(double),
+                                            hipMemcpyDeviceToDevice, c->stream));
+                ba::launch_linpoint_shared(c, c->lin_params, c->lin_pts, st->lambda);
+            } else {
+                ba::launch_linearize_point(c, cams, pts, st->lambda);
+                BA_HIP_CHECK(hipMemcpyAsync(c->lin_cams, cams, (size_t)c->n_cams * 9 * sizeof(double),
+                                            hipMemcpyDeviceToDevice, c->stream));
+            }
             c->defl_ready = false;
         }
         BA_HIP_CHECK(hipEventRecord(ev[5], c->stream));
@@ -1101,7 +1230,10 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         } else
             BA_HIP_CHECK(hipMemsetAsync(c->dxc, 0, sizeof(double), c->stream));
         BA_HIP_CHECK(hipEventRecord(ev[7], c->stream));
-        ba::launch_back_substitute(c, c->dxc, c->dxp);
+        if (c->shared)
+            ba::launch_back_substitute_shared(c, c->dxc, c->dxp);
+        else
+            ba::launch_back_substitute(c, c->dxc, c->dxp);
         const int n_tri = o ? o->retriangulate : 0;
         if (n_tri > 0) {
             // the points re-triangulated with the candidate cameras, starting
@@ -1113,7 +1245,10 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
             c->h_flags[3] = 0;
         }
         BA_HIP_CHECK(hipEventRecord(ev[9], c->stream));
-        ba::launch_evaluate(c, cams, pts, c->dxc, c->dxp);
+        if (c->shared)
+            ba::launch_evaluate_shared(c, cams, pts, c->dxc, c->dxp);
+        else
+            ba::launch_evaluate(c, cams, pts, c->dxc, c->dxp);
         BA_HIP_CHECK(hipEventRecord(ev[10], c->stream));
         BA_HIP_CHECK(hipMemcpyAsync(c->h_scal, c->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         BA_HIP_CHECK(hipMemcpyAsync(c->h_flags, c->flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -1142,7 +1277,10 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
         if (!formed) I.pcg_status = BA_ERR_NOT_SPD;
         const bool ok = formed && (ps == BA_OK || ps == BA_ERR_NOT_CONVERGED) && L > 0.0 && std::isfinite(Fn) && Fn < F;
         if (ok) {
-            ba::launch_update(c, cams, pts, c->dxc, c->dxp);
+            if (c->shared)
+                ba::launch_update_shared(c, cams, pts, c->dxc, c->dxp);
+            else
+                ba::launch_update(c, cams, pts, c->dxc, c->dxp);
             const double t = 2.0 * I.rho - 1.0;
             st->lambda *= std::max(1.0 / 3.0, 1.0 - t * t * t);
             st->nu = 2.0;
@@ -1189,6 +1327,7 @@ ba_status ba_get_rcs(ba_ctx* c, double* blk, double* rhs) {
 
 ba_status ba_get_gauge(ba_ctx* c, double* W) {
     if (!c || !W) return BA_ERR_INVALID_ARG;
+    if (c->shared) { c->err = "no gauge vectors for shared-intrinsics contexts"; return BA_ERR_INVALID_ARG; }
     if (!c->have_rcs) { c->err = "no RCS formed"; return BA_ERR_STATE; }
     return guarded(c, [&]() {
         if (c->n_rows > 0) prepare_defl(c);
@@ -1238,6 +1377,7 @@ ba_status ba_get_store_sizes(const ba_ctx* c, ba_store_sizes* o) {
 
 ba_status ba_get_jacobians(ba_ctx* c, double* J, double* e) {
     if (!c) return BA_ERR_INVALID_ARG;
+    if (c->shared) { c->err = "ba_get_jacobians takes 9-parameter contexts"; return BA_ERR_INVALID_ARG; }
     if (!c->have_lin) { c->err = "no linearization"; return BA_ERR_STATE; }
     return guarded(c, [&]() {
         const int64_t n = c->n_obs;

@@ -357,6 +357,15 @@ struct ba_ctx {
         hipGraphExec_t exec;
     };
     std::vector<PcgGraph> pcg_graphs;
+    // shared intrinsics: images (the n_cams "cameras" above) take the
+    // interior parameters of physical camera img_cam[i]; RCS rows are the
+    // n_free free images (exterior, 6 of 9 slots) then the n_phys cameras
+    // (interior, 5 of 9 slots); parameters [n_cams][6] then [n_phys][5]
+    bool shared = false;
+    int32_t n_phys = 0, n_free = 0;
+    std::vector<int32_t> h_img_cam;
+    int32_t* img_cam = nullptr;
+    double *lin_params = nullptr, *lin_pts = nullptr;   // parameters of the last linearization
     bool have_lin = false, have_rcs = false, learned_ready = false;
     ba_gnn* net = nullptr;             // learned preconditioner (not owned)
     void* lgraph = nullptr;            // its graph of this context's pattern (owned)
@@ -397,6 +406,15 @@ void launch_fsai(ba_ctx* c);
 void build_csr(ba_ctx* c);
 void launch_csr_fill(ba_ctx* c);
 void launch_csr_spmv(ba_ctx* c, const double* x, double* y);
+// shared intrinsics (FP64): fused linearize + point stage over the
+// parameters [n_cams][6] + [n_phys][5] (two records per observation), the
+// diagonal stage (damping, padding, rhs, block-Jacobi factors; the blocks
+// come from the pair stage), back-substitution, evaluation and update
+void launch_linpoint_shared(ba_ctx* c, const double* params, const double* pts, double lambda);
+void launch_node_diag(ba_ctx* c, double lambda);
+void launch_back_substitute_shared(ba_ctx* c, const double* dxc, double* dxp);
+void launch_evaluate_shared(ba_ctx* c, const double* params, const double* pts, const double* dxc, const double* dxp);
+void launch_update_shared(ba_ctx* c, double* params, double* pts, const double* dxc, const double* dxp);
 // re-triangulation of every point with cameras cams (+ dxc by RCS row when
 // not null): start pts (+ out when delta), linear start if `linear`, n_gn
 // Gauss-Newton steps; out = X, or X - pts when delta; failures counted

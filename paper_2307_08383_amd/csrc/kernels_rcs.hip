@@ -301,7 +301,7 @@ struct Chunk<double> { using V = double2; };
 template <>
 struct Chunk<float> { using V = float4; };
 
-template <typename T>
+template <typename T, bool SUB = false>
 __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_offdiag(int n_unit, XcdRanges xr, const int32_t* __restrict__ unit_rng,
                                                    const int32_t* __restrict__ unit_dst,
                                                    const int32_t* __restrict__ trip, const T* __restrict__ R,
@@ -368,10 +368,17 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
                 jb1[q] = (double)me[kRec + 9 + c];
             }
             // M = K_a K_b^T (2x2), P = M J_cb (2 x my columns)
-            const double m00 = ka[0] * kb[0] + ka[1] * kb[1] + ka[2] * kb[2];
+            double m00 = ka[0] * kb[0] + ka[1] * kb[1] + ka[2] * kb[2];
             const double m01 = ka[0] * kb[3] + ka[1] * kb[4] + ka[2] * kb[5];
             const double m10 = ka[3] * kb[0] + ka[4] * kb[1] + ka[5] * kb[2];
-            const double m11 = ka[3] * kb[3] + ka[4] * kb[4] + ka[5] * kb[5];
+            double m11 = ka[3] * kb[3] + ka[4] * kb[4] + ka[5] * kb[5];
+            if (SUB) {
+                // records of one observation (shared intrinsics: its
+                // exterior and interior parts, or one record with itself)
+                // also carry the J_a^T J_b term of U
+                const int2 ab = sT[grp * 4 + slot];
+                if ((ab.x >> 1) == (ab.y >> 1)) { m00 -= 1.0; m11 -= 1.0; }
+            }
             double p0[3], p1[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
@@ -631,7 +638,10 @@ void launch_offdiag(ba_ctx* c) {
     for (int x = 0; x < 9; ++x) xr.wv[x] = c->xcd_wv[x];
     for (int x = 0; x < 8; ++x) most = std::max(most, xr.wv[x + 1] - xr.wv[x]);
     const int grid = 8 * most;
-    if (c->precision == BA_MIXED)
+    if (c->shared)
+        k_offdiag<double, true><<<grid, kWave, 0, c->stream>>>(c->n_unit, xr, c->unit_rng, c->unit_dst, c->trip,
+                                                               (const double*)c->R, c->blk, c->pblk);
+    else if (c->precision == BA_MIXED)
         k_offdiag<float><<<grid, kWave, 0, c->stream>>>(c->n_unit, xr, c->unit_rng, c->unit_dst, c->trip,
                                                         (const float*)c->R, c->blk, c->pblk);
     else

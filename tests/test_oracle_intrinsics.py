@@ -134,3 +134,22 @@ def test_pattern_and_padded_blocks():
         d = blk[rp[u]]
         assert np.array_equal(d[nreal:, nreal:], np.eye(9 - nreal))
         assert not d[nreal:, :nreal].any() and not rhs[u, nreal:].any()
+
+
+def test_dense_step_matches_reduced_system_and_lm_converges():
+    """The step over all unknowns (dense solve of Eq. (1)) has the camera
+    part that solves the reduced system of Eq. (4), and the LM reference
+    with it reaches the noise floor: F close to (2 n_obs - n_unknowns) s^2 / 2."""
+    s = _scene(n_phys=3, n_pts=300)
+    uv = _uv(s)
+    P = I.SharedProblem(s.n_img, s.n_phys, s.img_cam, s.n_pts, s.obs_img, s.obs_pt, uv)
+    S, b, F = P.rcs(s.ext_init, s.intr_init, s.pts_init, 1e-4)
+    dx = np.linalg.solve(S, b)
+    de, dq, dp, F2, pred = P.dense_step(s.ext_init, s.intr_init, s.pts_init, 1e-4)
+    assert F2 == F
+    assert np.abs(dx[:6 * s.n_img].reshape(-1, 6) - de).max() <= 1e-9 * np.abs(de).max()
+    assert np.abs(dx[6 * s.n_img:].reshape(-1, 5) - dq).max() <= 1e-9 * np.abs(dq).max()
+    _, _, _, hist = I.lm_run(P, s.ext_init, s.intr_init, s.pts_init, 8)
+    dof = 2 * s.n_obs - (6 * s.n_img + 5 * s.n_phys + 3 * s.n_pts - 7)
+    F_end = hist[-1]["cost_new"] if hist[-1]["accepted"] else hist[-1]["cost"]
+    assert 0.5 * dof * 0.25 * 0.7 < F_end < 0.5 * dof * 0.25 * 1.3
