@@ -233,6 +233,8 @@ def main():
     log = lambda m: print(m, flush=True)
     t0 = time.time()
     if args.eval_only:
+        import torch
+        torch.zeros(1, device="cuda")   # torch's device context before the library's first call
         wpath = args.weights or (DEFAULT_FSAI_WEIGHTS if args.head == "fsai" else DEFAULT_WEIGHTS)
         net = ba.ba_gnn_create(load_weights(wpath))
         rep = dict(head=args.head, weights=os.path.basename(wpath), eval_seeds=args.eval_seeds,
