@@ -286,6 +286,21 @@ ba_status ba_project(const double* cams, const double* pts, const int32_t* obs_c
                      const int32_t* obs_pt, int64_t n_obs, const double* noise,
                      double* uv, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the cost
+ * F = 1/2 sum |e|^2 that ba_linearize returns, without a context.  All
+ * pointers are device memory: cams [n_cams][9], pts [n_pts][3], obs_cam and
+ * obs_pt [n_obs], uv [2][n_obs]; *cost (one double) receives F.  The work is
+ * enqueued on stream (NULL = default) and nothing is allocated: the partial
+ * sums (one per 1,024 observations) go to a 1 MiB device buffer that the
+ * library holds on each GPU until the process ends and that every call on
+ * that GPU overwrites, so calls that overlap on one GPU race.  Errors:
+ * BA_ERR_INVALID_ARG for n_obs < 0, n_obs > 134,217,728 (the buffer's
+ * limit), a NULL cost or a NULL input with n_obs > 0; BA_ERR_DEVICE if the
+ * buffer's address cannot be taken or the launch fails. */
+ba_status ba_cost_noalloc(const double* cams, const double* pts, const int32_t* obs_cam, const int32_t* obs_pt,
+                          const double* uv, int64_t n_obs, double* cost, void* stream);
+
 typedef struct ba_sizes {
     int32_t n_cams, n_pts, n_rows, precision;
     int64_t n_obs, n_blk, n_pairs;      /* n_pairs: off-diagonal co-observations (triples) */

@@ -92,6 +92,7 @@ SIGNATURES = {
     "ba_lm_step": (C.c_int, [_vp, _vp, _vp, C.POINTER(LMState), C.POINTER(LMOpts), C.POINTER(LMInfo)]),
     "ba_project": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp]),
     "ba_triangulate": (C.c_int, [_vp, _vp, _vp, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
+    "ba_cost_noalloc": (C.c_int, [_vp, _vp, _vp, _vp, _vp, C.c_int64, _vp, _vp]),
     "ba_get_sizes": (C.c_int, [_vp, C.POINTER(Sizes)]),
     "ba_get_pattern": (C.c_int, [_vp, _vp, _vp]),
     "ba_get_rcs": (C.c_int, [_vp, _vp, _vp]),
@@ -247,6 +248,14 @@ def ba_triangulate(ctx, cams, pts, linear_init=True, n_gn=5):
     nf = C.c_int64(0)
     _check(lib().ba_triangulate(ctx, _ptr(cams), _ptr(pts), int(bool(linear_init)), int(n_gn), C.byref(nf)), ctx)
     return nf.value
+
+
+def ba_cost_noalloc(cams, pts, obs_cam, obs_pt, uv, cost, n_obs=None, stream=None):
+    """F = 1/2 sum |e|^2 into the device scalar `cost` (float64 tensor of one
+    element) without allocating; returns the status (BA_OK or an error)."""
+    n = obs_cam.numel() if n_obs is None else n_obs
+    return lib().ba_cost_noalloc(_ptr(cams), _ptr(pts), _ptr(obs_cam), _ptr(obs_pt), _ptr(uv), n, _ptr(cost),
+                                 _stream(stream))
 
 
 def ba_project(cams, pts, obs_cam, obs_pt, noise=None, out=None, stream=None):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libba.so")
-SOURCES = ["api.hip", "kernels_lin.hip", "kernels_rcs.hip", "kernels_pcg.hip", "fsai.hip", "gnn.hip", "csr.hip", "kernels_tri.hip", "kernels_shared.hip"]
+SOURCES = ["api.hip", "kernels_lin.hip", "kernels_rcs.hip", "kernels_pcg.hip", "fsai.hip", "gnn.hip", "csr.hip", "kernels_tri.hip", "noalloc.hip", "kernels_shared.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
