@@ -264,7 +264,7 @@ ba_status ba_lm_step(ba_ctx* ctx, double* cams, double* pts, ba_lm_state* state,
                      const ba_lm_opts* opts, ba_lm_info* info_host);
 
 /* Re-triangulation, the alternative to Eq. (5) of Sec. 3.1 (points
- * "triangulated by camera poses"): every point of the context is
+ * re-estimated from the camera poses): every point of the context is
  * re-estimated from its observations with the cameras cams (device
  * [n_cams][9]) held fixed.  Start: the given pts (device [n_pts][3]), or
  * with linear_init = 1 a linear multi-view solve (each pixel undistorted by

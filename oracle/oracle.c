@@ -289,7 +289,7 @@ void orc_get_cam_row(const orc_problem* P, int32_t* cam_row) {
     memcpy(cam_row, P->cam_row, sizeof(int32_t) * P->n_cams);
 }
 
-/* BSMC "second operation" (Table 1): the block of (r, s) by binary search of
+/* BSMC block lookup (the second operation of Table 1): the block of (r, s) by binary search of
  * s inside row r; -1 if absent. */
 static int64_t find_block(const orc_problem* P, int32_t r, int32_t s) {
     int64_t lo = P->row_ptr[r], hi = P->row_ptr[r + 1] - 1;
@@ -733,14 +733,11 @@ int orc_lm_step(orc_problem* P, double* cams, double* pts, orc_lm_state* st,
     return 0;
 }
 
-/* BSMC memory in bytes from the stored pattern (Eq. (9) counted on the
- * actual blocks: c*c doubles and 3 ints per stored block, plus one int per
- * row). */
 /* ------------------------------------------------------------------------ */
 /* re-triangulation of points with the cameras held fixed                     */
 /* ------------------------------------------------------------------------ */
 /* The paper's alternative to Eq. (5): after the camera step the points are
- * "triangulated by camera poses" (Sec. 3.1, after Eq. (5); Sec. 6 names it
+ * re-estimated from the updated camera poses (Sec. 3.1, after Eq. (5); Sec. 6 names it
  * among the costly steps).  For each point, with every camera fixed:
  *   - linear start (init = 1): each observed pixel is undistorted (the
  *     radius r of the normalised image point solves r (1 + k1 r^2 + k2 r^4)
@@ -847,6 +844,9 @@ int64_t orc_triangulate(const orc_problem* P, const double* cams, const double* 
     return failed;
 }
 
+/* BSMC memory in bytes from the stored pattern (Eq. (9) counted on the
+ * actual blocks: c*c doubles and 3 ints per stored block, plus one int per
+ * row). */
 int64_t orc_bsmc_bytes(const orc_problem* P, int32_t c) {
     return P->n_blk * (int64_t)c * c * 8 + P->n_blk * 3 * 4 + (int64_t)P->n_rows * 4;
 }

@@ -282,39 +282,34 @@ __global__ __launch_bounds__(BS) void k_linpoint_d(int n_chunk, const int32_t* _
 //   S_ij -= J_ca^T (K_a K_b^T) J_cb
 // over the couples of its slot, then the 4 slots are reduced by shuffles.
 // A lane group works on one unit: a whole segment, or a chunk of a long one
-// whose partial block is summed by k_pair_sum.  Each step stages the two records of the wave's 16 couples through LDS
-// with contiguous 16-byte loads spread over the whole wave (every record is
-// fetched once per step instead of once per lane of its couple), so a wave
-// has all of a step's record bytes in flight at once.  Units are stored in
-// windows of rows (longest first inside a window); workgroup b runs on XCD
-// b mod 8, which takes the waves of its own contiguous range of rows (ranges
-// of equal work), keeping the records of neighbouring cameras in its L2.
+// whose partial block is summed by k_pair_sum.  A step covers the wave's 16
+// couples; their two records are copied from global memory straight into LDS
+// (16-byte lane copies that bypass the registers, spread over the whole wave,
+// so every record is fetched once per step instead of once per lane of its
+// couple).  The copies of step s + 1 are issued before step s is computed
+// from the other of two LDS buffers.  A buffer is chunk-major: 16-byte chunk
+// h of couple i sits at slot h * 16 + i, so the 16 couples' copies of one
+// value lie in consecutive banks.  Units are stored in windows of rows
+// (longest first inside a window); workgroup b runs on XCD b mod 8, which
+// takes the waves of its own contiguous range of rows (ranges of equal work),
+// keeping the records of neighbouring cameras in its L2.
 // ---------------------------------------------------------------------------
 constexpr int kPairWave = 4;   // units (camera pairs or chunks) per wave
 
 struct XcdRanges { int wv[9]; };
 
-template <typename T>
-struct Chunk;
-template <>
-struct Chunk<double> { using V = double2; };
-template <>
-struct Chunk<float> { using V = float4; };
-
 template <typename T, bool SUB = false>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_offdiag(int n_unit, XcdRanges xr, const int32_t* __restrict__ unit_rng,
-                                                   const int32_t* __restrict__ unit_dst,
-                                                   const int32_t* __restrict__ trip, const T* __restrict__ R,
-                                                   double* __restrict__ blk, double* __restrict__ pblk) {
-    using V = typename Chunk<T>::V;
-    constexpr int kVal = sizeof(V) / sizeof(T);                      // values per chunk (2 or 4)
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_offdiag(
+    int n_unit, XcdRanges xr, const int32_t* __restrict__ unit_rng, const int32_t* __restrict__ unit_dst,
+    const int32_t* __restrict__ trip, const T* __restrict__ R, double* __restrict__ blk, double* __restrict__ pblk) {
+    constexpr int kVal = 16 / sizeof(T);                             // values per 16-byte chunk
     constexpr int kCh = kRec / kVal;                                 // chunks per record (12 or 6)
     constexpr int kCpl = 4 * kPairWave;                              // couples per step
-    constexpr int kLoads = kCpl * 2 * kCh / kWave;                   // chunk loads per lane per step
-    constexpr int kCS = 2 * kRec + (sizeof(T) == 8 ? 2 : 4);         // couple stride in LDS (padded)
-    static_assert(kLoads * kWave == kCpl * 2 * kCh, "staging must tile the wave");
-    __shared__ __align__(16) T sC[kCpl * kCS];
-    __shared__ int2 sT[kCpl];
+    constexpr int kLoads = kCpl * 2 * kCh / kWave;                   // chunk copies per lane per step
+    constexpr int kRow = kCpl * kVal;                                // values per chunk slot row
+    static_assert(kCpl == 16 && kLoads * kWave == kCpl * 2 * kCh, "staging must tile the wave");
+    __shared__ __align__(16) T sC[2][2 * kCh * kRow];
+    __shared__ int2 sT[2][kCpl];
     const int xcd = blockIdx.x % 8;
     const int wv = xr.wv[xcd] + (int)(blockIdx.x / 8);
     if (wv >= xr.wv[xcd + 1]) return;   // whole workgroup (one wave) leaves
@@ -322,61 +317,66 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
     const int grp = lane / 16, gl = lane % 16;
     const int slot = gl / 4, quarter = gl % 4;
     const int unit = wv * kPairWave + grp;
+    const int cpl = grp * 4 + slot;                      // this lane's couple in a step
     const int c0 = quarter == 0 ? 0 : 2 * quarter + 1;   // 0, 3, 5, 7
     const int nc = quarter == 0 ? 3 : 2;
     const bool live = unit < n_unit;
     int t0 = 0, t1 = 0;
     if (live) { const int2 r = reinterpret_cast<const int2*>(unit_rng)[unit]; t0 = r.x; t1 = r.y; }
-    // wave-uniform step count: the longest of the wave's units
     int steps = (t1 - t0 + 3) / 4;
     steps = max(steps, __shfl_xor(steps, 16, kWave));
     steps = max(steps, __shfl_xor(steps, 32, kWave));
+    // couple (a, b) of step st for this lane's slot; (-1, -1) past the unit's end
+    auto couple = [&](int st) {
+        const int t = t0 + 4 * st + slot;
+        return (st < steps && t < t1) ? reinterpret_cast<const int2*>(trip)[t] : make_int2(-1, -1);
+    };
+    // copy k of the wave fills slots k * 64 .. k * 64 + 63: lane L moves
+    // chunk 4 k + L / 16 of couple L % 16 (chunks past kCh: the b record's)
+    auto issue = [&](int b) {
+        const int2 ab = sT[b][lane % kCpl];
+#pragma unroll
+        for (int k = 0; k < kLoads; ++k) {
+            const int h = 4 * k + lane / kCpl;
+            const int o = h < kCh ? ab.x : ab.y;
+            const T* src = o >= 0 ? R + (int64_t)o * kRec + (h % kCh) * kVal : R;   // unused couple: any valid chunk
+            __builtin_amdgcn_global_load_lds((const void*)src,
+                                             (__attribute__((address_space(3))) void*)(sC[b] + k * kWave * kVal), 16,
+                                             0, 0);
+        }
+    };
     double acc[27];
 #pragma unroll
     for (int m = 0; m < 27; ++m) acc[m] = 0.0;
-    const T* me = sC + (grp * 4 + slot) * kCS;
+    if (quarter == 0) { sT[0][cpl] = couple(0); sT[1][cpl] = couple(1); }
+    __syncthreads();
+    if (steps > 0) issue(0);
     for (int st = 0; st < steps; ++st) {
+        const int b = st & 1;
+        const int2 nxt = quarter == 0 ? couple(st + 2) : make_int2(-1, -1);
+        __builtin_amdgcn_s_waitcnt(0);   // step st's records have landed in sC[b]
+        __syncthreads();
+        if (st + 1 < steps) issue(b ^ 1);
+        // value v of this lane's couple (v < kRec: record a, else record b)
+        const T* me = sC[b] + cpl * kVal;
+        auto at = [&](int v) { return (double)me[(v / kVal) * kRow + v % kVal]; };
         const int t = t0 + 4 * st + slot;
-        const bool ok = t < t1;
-        if (quarter == 0) sT[grp * 4 + slot] = ok ? reinterpret_cast<const int2*>(trip)[t] : make_int2(-1, -1);
-        __syncthreads();
-        V v[kLoads];
-#pragma unroll
-        for (int k = 0; k < kLoads; ++k) {
-            const int ch = k * kWave + lane;
-            const int ci = ch / (2 * kCh), part = ch % (2 * kCh);
-            const int2 ab = sT[ci];
-            const int o = part < kCh ? ab.x : ab.y;
-            if (o >= 0) v[k] = reinterpret_cast<const V*>(R + (int64_t)o * kRec)[part % kCh];
-            else v[k] = V{};
-        }
-#pragma unroll
-        for (int k = 0; k < kLoads; ++k) {
-            const int ch = k * kWave + lane;
-            const int ci = ch / (2 * kCh), part = ch % (2 * kCh);
-            *reinterpret_cast<V*>(sC + ci * kCS + (part / kCh) * kRec + (part % kCh) * kVal) = v[k];
-        }
-        __syncthreads();
-        if (ok) {
+        if (t < t1) {
             double ka[6], kb[6], jb0[3], jb1[3];
 #pragma unroll
-            for (int m = 0; m < 6; ++m) { ka[m] = (double)me[18 + m]; kb[m] = (double)me[kRec + 18 + m]; }
+            for (int m = 0; m < 6; ++m) { ka[m] = at(18 + m); kb[m] = at(kRec + 18 + m); }
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const int c = c0 + (q < nc ? q : 0);
-                jb0[q] = (double)me[kRec + c];
-                jb1[q] = (double)me[kRec + 9 + c];
+                jb0[q] = at(kRec + c);
+                jb1[q] = at(kRec + 9 + c);
             }
-            // M = K_a K_b^T (2x2), P = M J_cb (2 x my columns)
             double m00 = ka[0] * kb[0] + ka[1] * kb[1] + ka[2] * kb[2];
             const double m01 = ka[0] * kb[3] + ka[1] * kb[4] + ka[2] * kb[5];
             const double m10 = ka[3] * kb[0] + ka[4] * kb[1] + ka[5] * kb[2];
             double m11 = ka[3] * kb[3] + ka[4] * kb[4] + ka[5] * kb[5];
             if (SUB) {
-                // records of one observation (shared intrinsics: its
-                // exterior and interior parts, or one record with itself)
-                // also carry the J_a^T J_b term of U
-                const int2 ab = sT[grp * 4 + slot];
+                const int2 ab = sT[b][cpl];
                 if ((ab.x >> 1) == (ab.y >> 1)) { m00 -= 1.0; m11 -= 1.0; }
             }
             double p0[3], p1[3];
@@ -387,12 +387,13 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void
             }
 #pragma unroll
             for (int r = 0; r < 9; ++r) {
-                const double a0 = (double)me[r], a1 = (double)me[9 + r];
+                const double a0 = at(r), a1 = at(9 + r);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) acc[r * 3 + q] += a0 * p0[q] + a1 * p1[q];
             }
         }
-        __syncthreads();
+        __syncthreads();   // every lane is done with sT[b] and sC[b]
+        if (quarter == 0) sT[b][cpl] = nxt;
     }
 #pragma unroll
     for (int m = 0; m < 27; ++m) {

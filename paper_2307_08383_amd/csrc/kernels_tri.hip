@@ -1,6 +1,6 @@
 // Re-triangulation of points with the cameras held fixed: the alternative to
-// the back-substitution of Eq. (5) that Sec. 3.1 names (points "triangulated
-// by camera poses"), and the third costly step Sec. 6 lists.
+// the back-substitution of Eq. (5) that Sec. 3.1 names (points re-estimated
+// from the camera poses), and the third costly step Sec. 6 lists.
 //
 // Per point, over its track:
 //   - optional linear start: each observed pixel is undistorted (the radius

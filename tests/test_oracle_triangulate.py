@@ -1,5 +1,5 @@
 """Pins of the oracle's re-triangulation (the alternative to Eq. (5) that
-Sec. 3.1 names: points "triangulated by camera poses" with the cameras held
+Sec. 3.1 names: points re-estimated from the camera poses, the cameras held
 fixed), independent of how it is computed:
   - exact recovery on noise-free data, from the linear multi-view solve
     alone and after Gauss-Newton (closed form: the rays meet at the point);
