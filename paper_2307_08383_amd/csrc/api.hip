@@ -63,7 +63,7 @@ void free_ctx(ba_ctx* c) {
                     c->pcg.pW, c->pcg.pE, c->lin_cams, c->pcg.state,
                     c->pcg.scal, c->fs.ptr, c->fs.J, c->fs.slot, c->fs.tptr, c->fs.tile, c->fs.brow,
                     c->fs.gu_ptr, c->fs.gu_col, c->fs.gu_pos, c->fs.gu_src, c->fs.gl_self, c->fs.tg, c->pcg.bm, c->fs.Gl, c->fs.Gu, c->fs.An, c->fs.G,
-                    c->tri_failed, c->img_cam, c->lin_params, c->lin_pts, c->csr.bptr, c->csr.slot_src, c->csr.slot_col, c->csr.slot_row, c->csr.rowptr, c->csr.col, c->csr.val};
+                    c->fs.Gh, c->fs.hs, c->fs.Dn, c->tri_failed, c->img_cam, c->lin_params, c->lin_pts, c->csr.bptr, c->csr.slot_src, c->csr.slot_col, c->csr.slot_row, c->csr.rowptr, c->csr.col, c->csr.val};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->h_scal) (void)hipHostFree(c->h_scal);
@@ -628,8 +628,12 @@ void prepare_learned_fsai(ba_ctx* c) {
     if (!c->fs.built) ba::build_fsai(c);
     auto* g = (ba::gnn::Graph*)c->lgraph;
     ba::gnn::compute_features(*g, c->blk, c->stream);
-    ba::gnn::infer_factor(c->net, *g, c->upper ? c->fs.gl_self : c->fs.gu_pos, c->fs.Gl, c->fs.Gu, c->fs.G,
-                          c->stream);
+    // the UPPER apply reads the FP16 copy only; FULL reads Gl and Gu
+    c->fs.half = c->upper;
+    if (c->fs.half) ba::launch_dscale(c);
+    ba::gnn::infer_factor(c->net, *g, c->upper ? c->fs.gl_self : c->fs.gu_pos, c->upper ? nullptr : c->fs.Gl,
+                          c->upper ? nullptr : c->fs.Gu, c->fs.G, c->stream, c->fs.half ? c->fs.Dn : nullptr,
+                          c->fs.half ? c->fs.Gh : nullptr, c->fs.hs);
     c->fs.gu_upper = c->upper;
     c->fs.ready = false;   // the layouts now hold the network's factor
 }
@@ -640,6 +644,11 @@ void prepare_fsai(ba_ctx* c) {
     if (c->fs.ready && c->fs.gu_upper != c->upper) c->fs.ready = false;
     if (!c->fs.ready) {
         ba::launch_fsai(c);
+        c->fs.half = c->upper;
+        if (c->fs.half) {
+            ba::launch_dscale(c);
+            ba::launch_pack_half(c);
+        }
         BA_HIP_CHECK(hipGetLastError());
         c->fs.ready = true;
     }
@@ -737,9 +746,13 @@ void build_fsai(ba_ctx* c) {
     for (size_t p = 0; p < gl_self.size(); ++p) gl_self[p] = (int32_t)p;
     upload(c, &F.gl_self, gl_self);
     F.max_m = max_m;
+    F.n_mem = (int64_t)J.size();
     dalloc(c, &F.Gl, J.size() * 81);
     dalloc(c, &F.Gu, J.size() * 81);
     dalloc(c, &F.tg, J.size() * 9);
+    dalloc(c, &F.Gh, J.size() * 45);
+    dalloc(c, &F.hs, J.size());
+    dalloc(c, &F.Dn, (size_t)nr * 9);
     dalloc(c, &F.An, (size_t)c->n_blk * 81);
     dalloc(c, &F.G, (size_t)c->n_blk * 81);
     BA_HIP_CHECK(hipMemsetAsync(F.G, 0, (size_t)c->n_blk * 81 * sizeof(float), c->stream));

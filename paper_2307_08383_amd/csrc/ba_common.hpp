@@ -243,6 +243,7 @@ struct Fsai {
     int32_t *gu_ptr = nullptr, *gu_col = nullptr;   // rows of G^T: [n_rows+1], column (row i of G)
     int32_t *gu_pos = nullptr;        // per set member (like J): its position in the rows of G^T
     int32_t max_m = 0;
+    int64_t n_mem = 0;                // members of all sets (entries of Gl)
     float *Gl = nullptr, *Gu = nullptr;   // G by rows (like J) and G^T by rows (like gu_col), 9x9 each
     float* An = nullptr;              // [n_blk][81] L_r^-1 S_rc L_c^-T of off-diagonal blocks
     float* G = nullptr;               // [n_blk][81] G in the upper slots
@@ -253,6 +254,14 @@ struct Fsai {
     int32_t* gl_self = nullptr;
     int gu_upper = 0;
     double* tg = nullptr;             // [entries][9] G_ij^T t_i per entry of Gl (UPPER apply of G^T)
+    // half-precision copy for the UPPER apply: member e (G_e = G_{i,j},
+    // j = J[e]) as Gh_e = G_e D_j^-1 / hs[e] in FP16, D_j = diag(S_jj)^-1/2
+    // (Dn [n_rows][9]), hs[e] = max |G_e D_j^-1|; each column of G_e takes
+    // 10 halves (the last one padding): 45 words per member
+    uint32_t* Gh = nullptr;
+    float* hs = nullptr;
+    double* Dn = nullptr;
+    int half = 0;                     // the layouts hold a packed copy of the current factor
 };
 
 // Scalar CSR copy of both triangles of the RCS (the layout BSMC is compared
@@ -352,6 +361,7 @@ struct ba_ctx {
         int defl;
         int s32;
         int upper;
+        int half;
         double tol;
         int max_iter;
         hipGraphExec_t exec;
@@ -401,6 +411,10 @@ void prepare_deflation(ba_ctx* c);
 // current RCS (stream-ordered)
 void build_fsai(ba_ctx* c);
 void launch_fsai(ba_ctx* c);
+// the UPPER apply's FP16 copy of the factor (Fsai::Gh): the Jacobi scaling
+// Dn of the current RCS, and the copy made from Gu
+void launch_dscale(ba_ctx* c);
+void launch_pack_half(ba_ctx* c);
 // CSR copy: index structure (host, once per context), values of the current
 // RCS, and y = S x on it
 void build_csr(ba_ctx* c);

@@ -264,23 +264,25 @@ __global__ __launch_bounds__(64) void k_feat_node(int n, const int32_t* __restri
 }
 
 // Normalised edge blocks A_e = L_i^-1 S_ij L_j^-T (FP32) and their bf16
-// features.  Three edges per workgroup, one thread per block entry: the
+// features.  Three edges per workgroup, one thread per block entry; only
+// the edge that applies its stored upper block as is (etr 0) is computed,
+// and its twin (the reverse edge) takes the transpose, A_twin = A_e^T.  The
 // three blocks of an edge are staged in LDS with contiguous loads, then the
 // two triangular products are formed in two passes (same summation order as
 // a thread-per-edge loop).
 constexpr int kFE = 3;   // edges per workgroup
 __global__ __launch_bounds__(256) void k_feat_edge(int E, const int32_t* __restrict__ esrc, const int32_t* __restrict__ edst,
                                                    const int32_t* __restrict__ eblk, const int32_t* __restrict__ etr,
+                                                   const int32_t* __restrict__ etwin,
                                                    const double* __restrict__ blk, const double* __restrict__ Linv,
                                                    float* __restrict__ A, __bf16* __restrict__ xe) {
     __shared__ double sS[kFE][81], sLi[kFE][81], sLj[kFE][81], sT[kFE][81];
     const int le = threadIdx.x / 81, pq = threadIdx.x % 81;
     const int e = blockIdx.x * kFE + le;
-    const bool act = le < kFE && e < E;
+    const bool act = le < kFE && e < E && etr[e] == 0;
     const int r = pq / 9, c = pq % 9;
     if (act) {
-        const double* S = blk + (int64_t)eblk[e] * 81;
-        sS[le][pq] = etr[e] != 0 ? S[c * 9 + r] : S[pq];   // S_ij as applied
+        sS[le][pq] = blk[(int64_t)eblk[e] * 81 + pq];
         sLi[le][pq] = Linv[(int64_t)esrc[e] * 81 + pq];
         sLj[le][pq] = Linv[(int64_t)edst[e] * 81 + pq];
     }
@@ -294,10 +296,17 @@ __global__ __launch_bounds__(256) void k_feat_edge(int E, const int32_t* __restr
     if (act) {   // A = Li T
         double t = 0.0;
         for (int q = 0; q <= r; ++q) t += sLi[le][r * 9 + q] * sT[le][q * 9 + c];
+        const int64_t tw = etwin[e];
         A[(int64_t)e * 81 + pq] = (float)t;
+        A[tw * 81 + c * 9 + r] = (float)t;
         __bf16* x = xe + (int64_t)e * F_EDGE;
+        __bf16* xt = xe + tw * F_EDGE;
         x[pq] = (__bf16)t;
-        if (pq < F_EDGE - 81) x[81 + pq] = (__bf16)0.0f;
+        xt[c * 9 + r] = (__bf16)t;
+        if (pq < F_EDGE - 81) {
+            x[81 + pq] = (__bf16)0.0f;
+            xt[81 + pq] = (__bf16)0.0f;
+        }
     }
 }
 
@@ -707,36 +716,63 @@ __global__ __launch_bounds__(BS) void k_fscatter_g(int E, const int32_t* __restr
     if (f >= 0) dG[t] += dXf[(int64_t)f * 3 * H + 2 * H + c];
 }
 
-// G of every set member in the original coordinates, G_ij = Ghat_ij L_j^-1
-// (FP64 products), into the layouts given (81 threads per member)
-__global__ __launch_bounds__(128) void k_fassemble(int n, int fm, const int32_t* __restrict__ fptr,
-                                                   const int32_t* __restrict__ fJ, const int32_t* __restrict__ fedge,
-                                                   const int32_t* __restrict__ fslot, const float* __restrict__ O,
-                                                   const float* __restrict__ OE, const float* __restrict__ ao,
-                                                   const float* __restrict__ A, const double* __restrict__ Linv,
-                                                   const int32_t* __restrict__ gu_pos, float* __restrict__ Gl,
-                                                   float* __restrict__ Gu, float* __restrict__ Gs) {
-    __shared__ float gh[81];
-    const int u = blockIdx.x;
-    // row of member u
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) / 2;
-        if (fptr[mid] <= u) lo = mid; else hi = mid;
+// One workgroup per row i: G_ij = Ghat_ij L_j^-1 for the row's members
+// (Ghat from the decoder for the diagonal member, from the head for the
+// others) into the layouts the apply reads: Gl (G by rows), Gu (the
+// transposed block at gu_pos), Gs (the block slots); with Gh, instead of
+// Gu, the UPPER apply's FP16 copy: each transposed block with its rows
+// (the columns of G_ij) divided by Dn of the member's column block, scaled
+// by its largest magnitude (hs), two halves per word, 10 halves per row.
+__global__ __launch_bounds__(BS) void k_fassemble(const int32_t* __restrict__ fptr, const int32_t* __restrict__ fJ,
+                                                  const int32_t* __restrict__ fedge, const int32_t* __restrict__ fslot,
+                                                  const float* __restrict__ O, const float* __restrict__ OE,
+                                                  const float* __restrict__ ao, const float* __restrict__ A,
+                                                  const double* __restrict__ Linv, const int32_t* __restrict__ gu_pos,
+                                                  float* __restrict__ Gl, float* __restrict__ Gu, float* __restrict__ Gs,
+                                                  const double* __restrict__ Dn, uint32_t* __restrict__ Gh,
+                                                  float* __restrict__ hs) {
+    __shared__ float gh[kFsaiM][81];
+    __shared__ float gv[kFsaiM][81];
+    __shared__ float smax[kFsaiM];
+    const int i = blockIdx.x;
+    const int j0 = fptr[i], m = fptr[i + 1] - j0, f0 = j0 - i;
+    for (int e = threadIdx.x; e < m * 81; e += BS) {
+        const int b = e / 81;
+        gh[b][e % 81] = ghat_elem(i, b, m, f0, b < m - 1 ? fedge[j0 + b] : 0, e % 81, O, OE, ao, A);
     }
-    const int i = lo, m = fptr[i + 1] - fptr[i], b = u - fptr[i];
-    const int pq = threadIdx.x;
-    if (pq < 81) gh[pq] = ghat_elem(i, b, m, fptr[i] - i, b < m - 1 ? fedge[u] : 0, pq, O, OE, ao, A);
     __syncthreads();
-    if (pq >= 81) return;
-    const int p = pq / 9, q = pq % 9;
-    const double* Lj = Linv + (int64_t)fJ[u] * 81;
-    double s = 0.0;
-    for (int v = q; v < 9; ++v) s += (double)gh[p * 9 + v] * Lj[v * 9 + q];
-    const float g = (float)s;
-    if (Gl) Gl[(int64_t)u * 81 + pq] = g;
-    if (Gu) Gu[(int64_t)gu_pos[u] * 81 + q * 9 + p] = g;
-    if (Gs) Gs[(int64_t)fslot[u] * 81 + pq] = g;
+    for (int e = threadIdx.x; e < m * 81; e += BS) {
+        const int b = e / 81, pq = e % 81, p = pq / 9, q = pq % 9;
+        const int64_t u = j0 + b;
+        const int j = fJ[u];
+        const double* Lj = Linv + (int64_t)j * 81;
+        double s = 0.0;
+        for (int v = q; v < 9; ++v) s += (double)gh[b][p * 9 + v] * Lj[v * 9 + q];
+        const float g = (float)s;
+        if (Gl) Gl[u * 81 + pq] = g;
+        if (Gs) Gs[(int64_t)fslot[u] * 81 + pq] = g;
+        if (Gh) gv[b][q * 9 + p] = (float)((double)g / Dn[(int64_t)j * 9 + q]);
+        else if (Gu) Gu[(int64_t)gu_pos[u] * 81 + q * 9 + p] = g;
+    }
+    if (!Gh) return;
+    __syncthreads();
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    for (int b = wv; b < m; b += BS / 64) {
+        float mx = fabsf(gv[b][lane]);
+        if (lane + 64 < 81) mx = fmaxf(mx, fabsf(gv[b][lane + 64]));
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0) smax[b] = mx > 0.f && mx <= 3.0e38f ? mx : 1.f;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * 45; e += BS) {
+        const int b = e / 45, w = e % 45, c = w / 5, a = 2 * (w % 5);
+        const float sc = smax[b];
+        const _Float16 lo = (_Float16)(gv[b][c * 9 + a] / sc);
+        const _Float16 hi = (_Float16)(a < 8 ? gv[b][c * 9 + a + 1] / sc : 0.f);
+        Gh[(int64_t)(j0 + b) * 45 + w] =
+            (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+    }
+    for (int b = threadIdx.x; b < m; b += BS) hs[j0 + b] = smax[b];
 }
 
 __global__ __launch_bounds__(BS) void k_add(int64_t n, const float* __restrict__ a, float* __restrict__ b) {
@@ -1059,7 +1095,8 @@ void compute_features(Graph& g, const double* blk, hipStream_t st) {
     BA_HIP_CHECK(hipMemsetAsync(g.flags, 0, 4 * sizeof(int), st));
     if (g.n > 0) k_feat_node<<<nblk(g.n, 64), 64, 0, st>>>(g.n, g.diag_blk, blk, g.Linv, g.xn, g.flags);
     if (g.E > 0)
-        k_feat_edge<<<(g.E + kFE - 1) / kFE, 256, 0, st>>>(g.E, g.esrc, g.edst, g.eblk, g.etr, blk, g.Linv, g.A, g.xe);
+        k_feat_edge<<<(g.E + kFE - 1) / kFE, 256, 0, st>>>(g.E, g.esrc, g.edst, g.eblk, g.etr, g.etwin, blk, g.Linv,
+                                                            g.A, g.xe);
     BA_HIP_CHECK(hipGetLastError());
 }
 
@@ -1070,14 +1107,15 @@ void infer_preconditioner(ba_gnn* net, Graph& g, const double* Minv, double* P, 
     BA_HIP_CHECK(hipGetLastError());
 }
 
-void infer_factor(ba_gnn* net, Graph& g, const int32_t* gu_pos, float* Gl, float* Gu, float* Gslots, hipStream_t st) {
+void infer_factor(ba_gnn* net, Graph& g, const int32_t* gu_pos, float* Gl, float* Gu, float* Gslots, hipStream_t st,
+                  const double* Dn, uint32_t* Gh, float* hs) {
     ensure_work(net->work, g.n, g.E, 1);
     ensure_fwork(net->work, g);
     forward(net, g, st, false);
     head_forward(net, g, st, false);
-    if (g.fm > 0)
-        k_fassemble<<<g.fm, 128, 0, st>>>(g.n, g.fm, g.fptr, g.fJ, g.fedge, g.fslot, net->work.O, net->work.OE,
-                                          net->w + OFF_AO, g.A, g.Linv, gu_pos, Gl, Gu, Gslots);
+    if (g.fm > 0 && g.n > 0)
+        k_fassemble<<<g.n, BS, 0, st>>>(g.fptr, g.fJ, g.fedge, g.fslot, net->work.O, net->work.OE, net->w + OFF_AO,
+                                        g.A, g.Linv, gu_pos, Gl, Gu, Gslots, Dn, Gh, hs);
     BA_HIP_CHECK(hipGetLastError());
 }
 

@@ -154,6 +154,26 @@ __device__ __forceinline__ void load_col9(const TS* __restrict__ b, int c, TS* v
     }
 }
 
+// Half-precision factor blocks (see Fsai::Gh): column c of member e is
+// words e * 45 + 5 c .. + 4, two halves per word, scaled back by hs[e].
+constexpr int kHW = 45;
+__device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)); }
+__device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
+__device__ __forceinline__ void load_colh(const uint32_t* __restrict__ Gh, const float* __restrict__ hs, int64_t e,
+                                          int c, float* v) {
+    const uint32_t* w = Gh + e * kHW + c * 5;
+    const float s = hs[e];
+    uint32_t a[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) a[k] = w[k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[2 * k] = s * half_lo(a[k]);
+        v[2 * k + 1] = s * half_hi(a[k]);
+    }
+    v[8] = s * half_lo(a[4]);
+}
+
 // Row gather by one wave over a block-CSR row (entries start..start+n-1,
 // blocks stored row-major in the orientation they are applied in): y[c] =
 // sum_e B_e v_e, returned in lanes 0..8 (component c = lane).  v_e is
@@ -457,6 +477,48 @@ __device__ __forceinline__ void einv_apply(const double* __restrict__ Einv, cons
     }
 }
 
+// D = diag(S_jj)^-1/2 of every row (the Jacobi scaling of the half copy)
+__global__ __launch_bounds__(BS) void k_dscale(int n_rows, const int32_t* __restrict__ row_ptr,
+                                               const double* __restrict__ blk, double* __restrict__ Dn) {
+    const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (i >= (int64_t)n_rows * 9) return;
+    const int j = (int)(i / 9), b = (int)(i % 9);
+    Dn[i] = 1.0 / sqrt(blk[(int64_t)row_ptr[j] * 81 + b * 10]);
+}
+
+// Half-precision copy of the transposed factor blocks GuT (member e: column
+// block J[e]): row b of the transposed block (column b of G_e) divided by
+// Dn[J[e]][b], the block by its largest magnitude; three members per
+// workgroup
+__global__ __launch_bounds__(BS) void k_pack_half(int64_t n_mem, const int32_t* __restrict__ J,
+                                                  const float* __restrict__ GuT, const double* __restrict__ Dn,
+                                                  uint32_t* __restrict__ Gh, float* __restrict__ hs) {
+    __shared__ float sv[3][81];
+    __shared__ float smax[3];
+    const int t = threadIdx.x, m = t / 81, v = t % 81;
+    const int64_t e = (int64_t)blockIdx.x * 3 + m;
+    const bool act = t < 243 && e < n_mem;
+    if (act) sv[m][v] = (float)((double)GuT[e * 81 + v] / Dn[(int64_t)J[e] * 9 + v / 9]);
+    __syncthreads();
+    if (act && v == 0) {
+        float mx = 0.f;
+        for (int k = 0; k < 81; ++k) mx = fmaxf(mx, fabsf(sv[m][k]));
+        smax[m] = mx > 0.f && mx <= 3.0e38f ? mx : 1.f;
+    }
+    __syncthreads();
+    if (act) {
+        const float s = smax[m];
+        const int b = v / 9, a = v % 9;
+        if (a % 2 == 0) {
+            const _Float16 lo = (_Float16)(sv[m][v] / s);
+            const _Float16 hi = (_Float16)(a < 8 ? sv[m][v + 1] / s : 0.f);
+            Gh[e * kHW + b * 5 + a / 2] = (uint32_t)__builtin_bit_cast(uint16_t, lo) |
+                                          ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+        }
+        if (v == 0) hs[e] = s;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // PCG kernels
 // ---------------------------------------------------------------------------
@@ -554,11 +616,16 @@ __global__ __launch_bounds__(BS) void k_spmv(int n_rows, const int32_t* __restri
 // v_e = v0[col_e] (VM 0) or v0[col_e] - alpha v1[col_e] (VM 1).  Rows of up
 // to 28 entries keep their blocks in registers between the two products;
 // longer rows load them again.  Returns t_row in lanes 0..8.
-template <int VM>
+// H: blocks from the half-precision copy (Gh, hs) in the Jacobi-scaled
+// space, v_e scaled by Dn[col_e] (the products written to tg then lack the
+// factor Dn of their column, which the column sums apply).
+template <int VM, bool H = false>
 __device__ __forceinline__ double row_factor_t(int start, int n, const int32_t* __restrict__ col,
                                                const float* __restrict__ blkT, const double* __restrict__ v0,
                                                const double* __restrict__ v1, double alpha,
-                                               double* __restrict__ tg) {
+                                               double* __restrict__ tg, const uint32_t* __restrict__ Gh = nullptr,
+                                               const float* __restrict__ hs = nullptr,
+                                               const double* __restrict__ Dn = nullptr) {
     constexpr int U = 4;
     const int lane = threadIdx.x % kWave;
     const int grp = lane / 9, comp = lane % 9;
@@ -575,9 +642,11 @@ __device__ __forceinline__ double row_factor_t(int start, int n, const int32_t* 
                 const int e = e0 + u * GRPW;
                 const int ee = start + (e < n ? e : e0);
                 const int cj = col[ee];
-                load_col9<true>(blkT + (int64_t)ee * 81, comp, bv[u]);
+                if (H) load_colh(Gh, hs, ee, comp, bv[u]);
+                else load_col9<true>(blkT + (int64_t)ee * 81, comp, bv[u]);
                 x[u] = v0[(int64_t)cj * 9 + comp];
                 if (VM == 1) x[u] -= alpha * v1[(int64_t)cj * 9 + comp];
+                if (H) x[u] *= Dn[(int64_t)cj * 9 + comp];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -599,7 +668,9 @@ __device__ __forceinline__ double row_factor_t(int start, int n, const int32_t* 
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int e = e0 + u * GRPW;
-                    load_col9<true>(blkT + (int64_t)(start + (e < n ? e : e0)) * 81, comp, bv[u]);
+                    const int64_t ee = start + (e < n ? e : e0);
+                    if (H) load_colh(Gh, hs, ee, comp, bv[u]);
+                    else load_col9<true>(blkT + ee * 81, comp, bv[u]);
                 }
             }
 #pragma unroll
@@ -638,15 +709,17 @@ __device__ __forceinline__ double index_sum(int a0, int n, const int32_t* __rest
 // t = G r (initial step of the factorised preconditioner); UP: from the
 // transposed blocks GlT, with the transposed products G_row,j^T t_row per
 // entry (tg)
-template <bool UP>
+template <bool UP, bool H = false>
 __global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, const int32_t* __restrict__ gl_ptr,
                                                      const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
                                                      const float* __restrict__ GlT, const double* __restrict__ r,
-                                                     double* __restrict__ t, double* __restrict__ tg) {
+                                                     double* __restrict__ t, double* __restrict__ tg,
+                                                     const uint32_t* __restrict__ Gh, const float* __restrict__ hs,
+                                                     const double* __restrict__ Dn) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a = gl_ptr[row], n = gl_ptr[row + 1] - a;
-        const double v = UP ? row_factor_t<0>(a, n, gl_col, GlT, r, nullptr, 0.0, tg)
+        const double v = UP ? row_factor_t<0, H>(a, n, gl_col, GlT, r, nullptr, 0.0, tg, Gh, hs, Dn)
                             : row_gather<float, 0>(a, n, gl_col, Gl, r, nullptr, 0.0);
         if (lane < 9) t[(int64_t)row * 9 + lane] = v;
     }
@@ -958,7 +1031,7 @@ __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restri
 // factorised preconditioner, first half: update and t = G r'; UP: from the
 // transposed blocks GlT, with the transposed products G_row,j^T t_row per
 // entry (tg) for the one-read apply of G^T
-template <bool UP>
+template <bool UP, bool H = false>
 __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __restrict__ gl_ptr,
                                                const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
                                                const float* __restrict__ GlT,
@@ -967,7 +1040,9 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
                                                double* __restrict__ r0buf, double* __restrict__ r1buf,
                                                double* __restrict__ t, double* __restrict__ tg,
                                                const double* __restrict__ pA,
-                                               double* __restrict__ pR, int n_part, int* __restrict__ state) {
+                                               double* __restrict__ pR, int n_part, int* __restrict__ state,
+                                               const uint32_t* __restrict__ Gh, const float* __restrict__ hs,
+                                               const double* __restrict__ Dn) {
     __shared__ double sh[2 * WPB];
     const int done = state[0];
     const int k = state[1];
@@ -987,7 +1062,7 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
     double rr = 0.0;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a0 = gl_ptr[row], n = gl_ptr[row + 1] - a0;
-        const double tv = UP ? row_factor_t<1>(a0, n, gl_col, GlT, rin, q, alpha, tg)
+        const double tv = UP ? row_factor_t<1, H>(a0, n, gl_col, GlT, rin, q, alpha, tg, Gh, hs, Dn)
                              : row_gather<float, 1>(a0, n, gl_col, Gl, rin, q, alpha);
         if (lane < 9) {
             const int64_t o = (int64_t)row * 9 + lane;
@@ -1007,14 +1082,15 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
 // UP: z_j = sum of the transposed products tg of the entries (i, j) of
 // column j of G (ascending i, one lane group per row) instead of a gather
 // over a transposed copy of G.
-template <bool INIT, bool UP>
+template <bool INIT, bool UP, bool H = false>
 __global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, const int32_t* __restrict__ gu_ptr,
                                                const int32_t* __restrict__ gu_col, const float* __restrict__ Gu,
                                                const double* __restrict__ t, const int32_t* __restrict__ gu_src,
                                                const double* __restrict__ tg,
                                                const double* __restrict__ r0buf, const double* __restrict__ r1buf,
                                                double* __restrict__ z, double* __restrict__ pR, int n_part,
-                                               int* __restrict__ state, int defl, const double* __restrict__ SW) {
+                                               int* __restrict__ state, int defl, const double* __restrict__ SW,
+                                               const double* __restrict__ Dn) {
     __shared__ double sh[NP * WPB];
     int k = -1;
     if (!INIT) {
@@ -1044,7 +1120,9 @@ __global__ __launch_bounds__(BS) void k_pcg_Cf(int n_rows, const int32_t* __rest
                 const int row = r0 + grp;
                 if (row >= n_rows) break;
                 const int a0 = gu_ptr[row];
-                finish(row, comp, index_sum(a0, gu_ptr[row + 1] - a0, gu_src, tg, comp, 0.0));
+                double zv = index_sum(a0, gu_ptr[row + 1] - a0, gu_src, tg, comp, 0.0);
+                if (H) zv *= Dn[(int64_t)row * 9 + comp];
+                finish(row, comp, zv);
             }
     } else {
         for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
@@ -1097,16 +1175,21 @@ void launch_factor_step(ba_ctx* c, int g, int defl, hipStream_t st) {
     Fsai& F = c->fs;
     const int nr = c->n_rows;
     if (F.gu_upper != c->upper) throw ba_hip_error(hipErrorInvalidValue, "factor apply (layout of the transposed blocks)", __FILE__, __LINE__);
-    if (c->upper) {
+    if (c->upper && F.half) {
+        k_pcg_Bf<true, true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg,
+                                               P.pA, P.pR, g, P.state, F.Gh, F.hs, F.Dn);
+        k_pcg_Cf<false, true, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
+                                                      P.r[1], P.z, P.pR, g, P.state, defl, P.SW, F.Dn);
+    } else if (c->upper) {
         k_pcg_Bf<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
-                                         P.pR, g, P.state);
+                                         P.pR, g, P.state, nullptr, nullptr, nullptr);
         k_pcg_Cf<false, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0], P.r[1],
-                                                P.z, P.pR, g, P.state, defl, P.SW);
+                                                P.z, P.pR, g, P.state, defl, P.SW, nullptr);
     } else {
         k_pcg_Bf<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
-                                          P.pR, g, P.state);
+                                          P.pR, g, P.state, nullptr, nullptr, nullptr);
         k_pcg_Cf<false, false><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
-                                                 P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
+                                                 P.r[1], P.z, P.pR, g, P.state, defl, P.SW, nullptr);
     }
 }
 
@@ -1116,14 +1199,20 @@ void launch_factor_init(ba_ctx* c, int g, int defl, hipStream_t st) {
     Fsai& F = c->fs;
     const int nr = c->n_rows;
     if (F.gu_upper != c->upper) throw ba_hip_error(hipErrorInvalidValue, "factor apply (layout of the transposed blocks)", __FILE__, __LINE__);
-    if (c->upper) {
-        k_gather_lower<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg);
+    if (c->upper && F.half) {
+        k_gather_lower<true, true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, F.Gh, F.hs, F.Dn);
+        k_pcg_Cf<true, true, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
+                                                     P.r[1], P.z, P.pR, g, P.state, defl, P.SW, F.Dn);
+    } else if (c->upper) {
+        k_gather_lower<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, nullptr, nullptr,
+                                               nullptr);
         k_pcg_Cf<true, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0], P.r[1],
-                                               P.z, P.pR, g, P.state, defl, P.SW);
+                                               P.z, P.pR, g, P.state, defl, P.SW, nullptr);
     } else {
-        k_gather_lower<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg);
+        k_gather_lower<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, nullptr, nullptr,
+                                                nullptr);
         k_pcg_Cf<true, false><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
-                                                P.r[1], P.z, P.pR, g, P.state, defl, P.SW);
+                                                P.r[1], P.z, P.pR, g, P.state, defl, P.SW, nullptr);
     }
 }
 
@@ -1237,7 +1326,7 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
     if (c->use_graphs && n_batches > 0) {
         for (auto& gr : c->pcg_graphs)
             if (gr.M == M && gr.mode == mode && gr.defl == defl && gr.s32 == c->s32 && gr.upper == c->upper &&
-                gr.tol == tol && gr.max_iter == max_iter)
+                gr.half == c->fs.half && gr.tol == tol && gr.max_iter == max_iter)
                 exec = gr.exec;
         if (!exec) {
             hipStream_t cs = c->capture_stream;
@@ -1247,7 +1336,7 @@ ba_status run_pcg(ba_ctx* c, int mode, const double* M, int defl, double tol, in
             BA_HIP_CHECK(hipStreamEndCapture(cs, &graph));
             BA_HIP_CHECK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
             BA_HIP_CHECK(hipGraphDestroy(graph));
-            c->pcg_graphs.push_back({M, mode, defl, c->s32, c->upper, tol, max_iter, exec});
+            c->pcg_graphs.push_back({M, mode, defl, c->s32, c->upper, c->fs.half, tol, max_iter, exec});
         }
     }
     hipEvent_t evb[2] = {c->ev[12], c->ev[13]};
@@ -1288,6 +1377,18 @@ void launch_product(ba_ctx* c, const double* x, double* y) {
     if (c->n_rows == 0) return;
     ensure_sf(c, false);
     product_cur(c, x, y, c->stream);
+}
+
+void launch_dscale(ba_ctx* c) {
+    const int nr = c->n_rows;
+    if (nr > 0)
+        k_dscale<<<(unsigned)(((int64_t)nr * 9 + BS - 1) / BS), BS, 0, c->stream>>>(nr, c->row_ptr, c->blk, c->fs.Dn);
+}
+
+void launch_pack_half(ba_ctx* c) {
+    Fsai& F = c->fs;
+    if (F.n_mem > 0)
+        k_pack_half<<<(unsigned)((F.n_mem + 2) / 3), BS, 0, c->stream>>>(F.n_mem, F.J, F.Gu, F.Dn, F.Gh, F.hs);
 }
 
 }  // namespace ba
