@@ -170,7 +170,12 @@ typedef struct ba_pcg_opts {
  * Both are deterministic; they differ only in the summation order.  AUTO
  * takes UPPER when the copy of both triangles would exceed 256 MiB (about
  * the GPU's last-level cache), FULL otherwise (one kernel less per
- * iteration on small systems). */
+ * iteration on small systems).  A factorised preconditioner (FSAI or the
+ * learned factor, M^-1 = G^T G) is applied with the same layout: FULL reads
+ * G (FP32) by rows and a transposed copy; UPPER reads each block of G once
+ * from an FP16 copy (G D^-1 with D = diag(S)^-1/2, one FP32 scale per
+ * block), so the preconditioner differs from FULL's by that rounding (M
+ * stays SPD; PCG converges to the same solution). */
 enum { BA_PRODUCT_AUTO = 0, BA_PRODUCT_FULL = 1, BA_PRODUCT_UPPER = 2, BA_PRODUCT_CSR = 3 };
 
 typedef struct ba_pcg_info {
