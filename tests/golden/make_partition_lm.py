@@ -29,9 +29,12 @@ from paper_2307_08383_amd import scenegen  # noqa: E402
 OUT = os.path.join(HERE, "partition60000_lm_oracle.json")
 
 
-def main():
+def run(scene, out_path, about):
+    """The oracle's fixed-budget LM run on `scene` (block-Jacobi PCG to the
+    scene's tolerance, cap 1000, lambda0 1e-4), stored with the scene's
+    digest and the digest of the observations it was run on."""
     t0 = time.time()
-    s = scenegen.partition_scene(seed=2, with_stats=False)
+    s = scene
     uv = orc.observations(s)
     uv_sha = hashlib.sha256(np.ascontiguousarray(uv).tobytes()).hexdigest()
     print(f"scene {s.name}: {s.n_obs} observations ({time.time() - t0:.0f} s)", flush=True)
@@ -52,16 +55,19 @@ def main():
         if info["stop"]:
             break
     F_final = P.cost(cams, pts)
-    out = dict(
-        about="Oracle (FP64, CPU) LM run on the 60,000-camera partition scene (seed 2): 10 iterations "
-              "from the perturbed start, lambda0 1e-4, block-Jacobi PCG to rel 1e-6, cap 1000. "
-              "Written by tests/golden/make_partition_lm.py from the oracle only.",
-        scene=s.name, scene_digest=s.digest(), uv_sha256=uv_sha, n_obs=s.n_obs,
-        oracle_threads=orc.default_threads(), iterations=hist, final_cost=F_final,
-        wall_seconds=time.time() - t0)
-    with open(OUT, "w") as f:
+    out = dict(about=about, scene=s.name, scene_digest=s.digest(), uv_sha256=uv_sha, n_obs=s.n_obs,
+               oracle_threads=orc.default_threads(), iterations=hist, final_cost=F_final,
+               wall_seconds=time.time() - t0)
+    with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
-    print(f"final cost {F_final:.12e}; wrote {OUT}", flush=True)
+    print(f"final cost {F_final:.12e}; wrote {out_path}", flush=True)
+
+
+def main():
+    run(scenegen.partition_scene(seed=2, with_stats=False), OUT,
+        "Oracle (FP64, CPU) LM run on the 60,000-camera partition scene (seed 2): 10 iterations "
+        "from the perturbed start, lambda0 1e-4, block-Jacobi PCG to rel 1e-6, cap 1000. "
+        "Written by tests/golden/make_partition_lm.py from the oracle only.")
 
 
 if __name__ == "__main__":
