@@ -29,10 +29,11 @@ from paper_2307_08383_amd import scenegen  # noqa: E402
 OUT = os.path.join(HERE, "partition60000_lm_oracle.json")
 
 
-def run(scene, out_path, about):
-    """The oracle's fixed-budget LM run on `scene` (block-Jacobi PCG to the
-    scene's tolerance, cap 1000, lambda0 1e-4), stored with the scene's
-    digest and the digest of the observations it was run on."""
+def run(scene, out_path, about, pcg_tol=None, pcg_max_iter=1000):
+    """The oracle's fixed-budget LM run on `scene` (block-Jacobi PCG to
+    pcg_tol, by default the scene's tolerance, at most pcg_max_iter
+    iterations; lambda0 1e-4), stored with the scene's digest and the digest
+    of the observations it was run on."""
     t0 = time.time()
     s = scene
     uv = orc.observations(s)
@@ -46,7 +47,7 @@ def run(scene, out_path, about):
     for it in range(s.lm_iterations):
         t1 = time.time()
         lam_before, nu_before = st.lam, st.nu
-        info = P.lm_step(cams, pts, st, s.pcg_tol, 1000)
+        info = P.lm_step(cams, pts, st, s.pcg_tol if pcg_tol is None else pcg_tol, pcg_max_iter)
         info.update(lambda_before=lam_before, nu_before=nu_before, lambda_after=st.lam, nu_after=st.nu,
                     seconds=time.time() - t1)
         hist.append(info)
@@ -56,6 +57,7 @@ def run(scene, out_path, about):
             break
     F_final = P.cost(cams, pts)
     out = dict(about=about, scene=s.name, scene_digest=s.digest(), uv_sha256=uv_sha, n_obs=s.n_obs,
+               pcg_tol=s.pcg_tol if pcg_tol is None else pcg_tol, pcg_max_iter=pcg_max_iter,
                oracle_threads=orc.default_threads(), iterations=hist, final_cost=F_final,
                wall_seconds=time.time() - t0)
     with open(out_path, "w") as f:
