@@ -94,8 +94,9 @@ def stage_bytes(scene, sizes, precision):
     """Algorithmic HBM bytes of one launch of each formation kernel (the
     minimum each must move; per-unit counts of the kernels' design):
       linpoint (linearize + point stage) per observation: indices, pixels and
-        camera-list slot 28, records J_c + K 24, J_p 6 (x sizeof T), e 16,
-        e + K lhat 16; per point: its parameters 24 and point terms 72;
+        camera-list slot 28, records J_c + K 24 (x sizeof T), e 16,
+        e + K lhat 16; per point: its parameters 24 and point terms 72 (J_p
+        is not stored: it is K L^T);
       pair per observation couple: two indices 8 and two records 2 x 24
         (x sizeof T); per off-diagonal block: 81 FP64 values and its bounds 8;
       diag per observation of a free camera: its list entry 4, record 24
@@ -105,7 +106,7 @@ def stage_bytes(scene, sizes, precision):
     n, npt = scene.n_obs, scene.n_pts
     free_obs = int((~scene.cam_fixed.astype(bool))[scene.obs_cam].sum())
     n_offseg = sizes["n_blk"] - sizes["n_rows"]
-    return {"linpoint": n * (28 + 24 * es + 6 * es + 16 + 16) + npt * (24 + 72),
+    return {"linpoint": n * (28 + 24 * es + 16 + 16) + npt * (24 + 72),
             "pair": sizes["n_pairs"] * (8 + 2 * 24 * es) + n_offseg * (81 * 8 + 8),
             "diag": free_obs * (4 + 24 * es + 16) + sizes["n_rows"] * (3 * 81 * 8 + 72 + 12)}
 

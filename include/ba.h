@@ -339,7 +339,10 @@ ba_status ba_get_csr(ba_ctx* ctx, int32_t* row_ptr, int32_t* col, double* val, i
 
 /* Host copies of the last linearization in the caller's observation order:
  * J [n_obs][24] = J_c row 0 (9), J_c row 1 (9), J_p row 0 (3), J_p row 1 (3)
- * (converted to FP64 in mixed precision), e [n_obs][2]; either may be NULL. */
+ * (converted to FP64 in mixed precision), e [n_obs][2]; either may be NULL.
+ * After ba_lm_step J_p is formed as K L^T from the stored K = J_p L^-T and
+ * the point's Cholesky factor L (the step's linearization does not store
+ * J_p), so it equals the Jacobian to rounding. */
 ba_status ba_get_jacobians(ba_ctx* ctx, double* J, double* e);
 
 /* Host copy (FP32, [n_blk][81], row-major 9x9) of the factor G used by the

@@ -505,7 +505,9 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &c->Linv, (size_t)nr * 81);
     dalloc(c, &c->dxc, (size_t)nr * 9);
     dalloc(c, &c->dxp, (size_t)np * 3);
-    c->n_part = (int32_t)(3 * ((n + 255) / 256) + 8);
+    // per-block partials of up to three sums: grids of one block per 256
+    // observations, or per 4 chunks (chunk-based kernels)
+    c->n_part = (int32_t)(3 * std::max<int64_t>((n + 255) / 256, ((int64_t)c->n_chunk + 3) / 4) + 8);
     dalloc(c, &c->part, (size_t)c->n_part);
     dalloc(c, &c->part2, (size_t)3 * ba::kReduceParts);
     dalloc(c, &c->scal, 16);
@@ -1255,6 +1257,7 @@ ba_status ba_lm_step(ba_ctx* c, double* cams, double* pts, ba_lm_state* st, cons
             // from the back-substituted ones; dxp becomes their displacement
             BA_HIP_CHECK(hipMemsetAsync(c->tri_failed, 0, sizeof(int), c->stream));
             ba::launch_triangulate(c, cams, c->dxc, pts, c->dxp, 1, 0, n_tri, c->tri_failed);
+            ba::launch_model_terms(c, c->dxc, c->dxp);
             BA_HIP_CHECK(hipMemcpyAsync(c->h_flags + 3, c->tri_failed, sizeof(int), hipMemcpyDeviceToHost, c->stream));
         } else {
             c->h_flags[3] = 0;
@@ -1397,6 +1400,7 @@ ba_status ba_get_jacobians(ba_ctx* c, double* J, double* e) {
     return guarded(c, [&]() {
         const int64_t n = c->n_obs;
         if (J) {
+            ba::ensure_jp(c);
             const size_t es = c->precision == BA_MIXED ? sizeof(float) : sizeof(double);
             std::vector<char> hr((size_t)n * kRec * es), hp((size_t)n * 6 * es);
             BA_HIP_CHECK(hipMemcpyAsync(hr.data(), c->R, hr.size(), hipMemcpyDeviceToHost, c->stream));

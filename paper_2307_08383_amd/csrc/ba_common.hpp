@@ -169,6 +169,18 @@ __device__ __forceinline__ void store6(float* __restrict__ r, const double* v) {
     for (int i = 0; i < 3; ++i) p[i] = make_float2((float)v[2 * i], (float)v[2 * i + 1]);
 }
 
+// J_p = K L^T (K = J_p L^-T, the record's last 6 values; L the point's
+// Cholesky factor packed as L00, L10, L11, L20, L21, L22)
+__device__ __forceinline__ void jp_from_K(const double* K, const double* L, double* jp) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const double a = K[3 * r], b = K[3 * r + 1], c = K[3 * r + 2];
+        jp[3 * r] = a * L[0];
+        jp[3 * r + 1] = a * L[1] + b * L[2];
+        jp[3 * r + 2] = a * L[3] + b * L[4] + c * L[5];
+    }
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -377,6 +389,10 @@ struct ba_ctx {
     int32_t* img_cam = nullptr;
     double *lin_params = nullptr, *lin_pts = nullptr;   // parameters of the last linearization
     bool have_lin = false, have_rcs = false, learned_ready = false;
+    // Jp holds J_p of the current linearization (k_linearize writes it; the
+    // fused linearize + point stage does not, and J_p = K L^T is formed from
+    // the records and the point terms where it is needed)
+    bool jp_valid = false;
     ba_gnn* net = nullptr;             // learned preconditioner (not owned)
     void* lgraph = nullptr;            // its graph of this context's pattern (owned)
     double lambda = 0.0;
@@ -398,6 +414,11 @@ void launch_reduce(ba_ctx* c, const double* part, int n, int count, double* out)
 void launch_offdiag(ba_ctx* c);
 void launch_diag(ba_ctx* c, double lambda);
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp);
+// J_p of the current linearization into Jp if the fused stage left it out
+void ensure_jp(ba_ctx* c);
+// |J dx|^2 and dx^T l into scal[2], scal[3] for a dx_p replaced after
+// back-substitution (which forms them for its own dx_p)
+void launch_model_terms(ba_ctx* c, const double* dxc, const double* dxp);
 void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const double* dxc, const double* dxp);
 void launch_update(ba_ctx* c, double* cams, double* pts, const double* dxc, const double* dxp);
 // PCG: returns status; fills iters/relres (synchronises).  mode 0: block

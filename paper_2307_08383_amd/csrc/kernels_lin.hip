@@ -49,53 +49,55 @@ __global__ __launch_bounds__(BS) void k_linearize(int n, const int32_t* __restri
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// F' at x + dx, and from the stored linearization |J dx|^2 and dx^T l with
-// l = -J^T e (the model terms of the gain ratio).
-template <typename T>
+// F' at x + dx (the model terms of the gain ratio come with
+// back-substitution)
 __global__ __launch_bounds__(BS) void k_evaluate(int n, const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_pt,
                                                  const int32_t* __restrict__ obs_row, const double* __restrict__ uv,
                                                  const double* __restrict__ cams, const double* __restrict__ pts,
                                                  const double* __restrict__ dxc, const double* __restrict__ dxp,
-                                                 const T* __restrict__ R, const T* __restrict__ Jp,
-                                                 const double* __restrict__ e, double* __restrict__ part, int nb) {
+                                                 double* __restrict__ part) {
     __shared__ double sh[BS / kWave];
     const int k = blockIdx.x * BS + threadIdx.x;
-    double cost = 0.0, jdx2 = 0.0, dxl = 0.0;
+    double cost = 0.0;
     if (k < n) {
         const int row = obs_row[k];
         const int p = obs_pt[k];
         const double* c0 = cams + (int64_t)obs_cam[k] * 9;
-        double c[9], dc[9];
+        double c[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            dc[i] = row >= 0 ? dxc[(int64_t)row * 9 + i] : 0.0;
-            c[i] = c0[i] + dc[i];
-        }
+        for (int i = 0; i < 9; ++i) c[i] = c0[i] + (row >= 0 ? dxc[(int64_t)row * 9 + i] : 0.0);
         const double* X = pts + (int64_t)p * 3;
         const double* dX = dxp + (int64_t)p * 3;
         double pu, pv;
         project_point<false>(c, X[0] + dX[0], X[1] + dX[1], X[2] + dX[2], pu, pv, nullptr, nullptr);
         const double eu = pu - uv[k], ev = pv - uv[n + k];
         cost = 0.5 * (eu * eu + ev * ev);
-        double v[18], jp[6];
-        load_jc(R + (int64_t)k * kRec, v);
-        load6(Jp + (int64_t)k * 6, jp);
-        double g0 = 0.0, g1 = 0.0;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) { g0 += v[i] * dc[i]; g1 += v[9 + i] * dc[i]; }
-#pragma unroll
-        for (int i = 0; i < 3; ++i) { g0 += jp[i] * dX[i]; g1 += jp[3 + i] * dX[i]; }
-        const double2 ek = reinterpret_cast<const double2*>(e)[k];
-        jdx2 = g0 * g0 + g1 * g1;
-        dxl = -(g0 * ek.x + g1 * ek.y);
     }
     const double s0 = block_sum<BS>(cost, sh);
-    const double s1 = block_sum<BS>(jdx2, sh);
-    const double s2 = block_sum<BS>(dxl, sh);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = s0;
-        part[nb + blockIdx.x] = s1;
-        part[2 * nb + blockIdx.x] = s2;
+    if (threadIdx.x == 0) part[blockIdx.x] = s0;
+}
+
+// J_p = K L^T of every observation into Jp (for the getter, after the fused
+// linearize + point stage): one wave per chunk of whole tracks
+template <typename T>
+__global__ __launch_bounds__(BS) void k_jp_from_K(int n_chunk, const int32_t* __restrict__ chunk_ptr,
+                                                  const int32_t* __restrict__ chunk_q, const int32_t* __restrict__ obs_pt,
+                                                  const T* __restrict__ R, const double* __restrict__ ptL,
+                                                  T* __restrict__ Jp) {
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int chunk = blockIdx.x * (BS / kWave) + wv;
+    int k0 = 0, k1 = 0;
+    if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
+    const int k = k0 + lane;
+    const bool act = k < k1;
+    const int p = act ? obs_pt[k] : -1;
+    const Track tk = chunk_track(act, p, lane, k1 - k0);
+    const int64_t q = chunk < n_chunk ? (int64_t)chunk_q[chunk] + tk.idx : 0;
+    if (act) {
+        double K[6], jp[6];
+        load6(R + (int64_t)k * kRec + 18, K);
+        jp_from_K(K, ptL + q * 9, jp);
+        store6(Jp + (int64_t)k * 6, jp);
     }
 }
 
@@ -145,6 +147,7 @@ void launch_linearize(ba_ctx* c, const double* cams, const double* pts) {
         k_linearize<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_uv, cams, pts,
                                                       (double*)c->R, (double*)c->Jp, c->e, c->part, c->flags);
     launch_reduce(c, c->part, nb, 1, c->scal + 0);
+    c->jp_valid = true;
 }
 
 // out[j] = sum of part[j*n .. j*n + n), j < count (count <= 3), in a fixed
@@ -165,13 +168,23 @@ void launch_reduce(ba_ctx* c, const double* part, int n, int count, double* out)
 
 void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const double* dxc, const double* dxp) {
     const int n = (int)c->n_obs, nb = nblk(n);
-    if (c->precision == BA_MIXED)
-        k_evaluate<float><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts,
-                                                    dxc, dxp, (const float*)c->R, (const float*)c->Jp, c->e, c->part, nb);
-    else
-        k_evaluate<double><<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts,
-                                                     dxc, dxp, (const double*)c->R, (const double*)c->Jp, c->e, c->part, nb);
-    launch_reduce(c, c->part, nb, 3, c->scal + 1);   // scal[1] F', [2] |J dx|^2, [3] dx^T l
+    k_evaluate<<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts, dxc, dxp,
+                                         c->part);
+    launch_reduce(c, c->part, nb, 1, c->scal + 1);   // scal[1] F'
+}
+
+void ensure_jp(ba_ctx* c) {
+    if (c->jp_valid) return;
+    const int nb = (c->n_chunk + BS / kWave - 1) / (BS / kWave);
+    if (nb > 0) {
+        if (c->precision == BA_MIXED)
+            k_jp_from_K<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->chunk_q, c->obs_pt,
+                                                         (const float*)c->R, c->ptL, (float*)c->Jp);
+        else
+            k_jp_from_K<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->chunk_q, c->obs_pt,
+                                                          (const double*)c->R, c->ptL, (double*)c->Jp);
+    }
+    c->jp_valid = true;
 }
 
 void launch_update(ba_ctx* c, double* cams, double* pts, const double* dxc, const double* dxp) {

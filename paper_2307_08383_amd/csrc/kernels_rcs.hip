@@ -77,10 +77,14 @@ __device__ __forceinline__ void store_ebar(const double* r, const double* K, dou
 // lane per observation.  Track sums V_p, l_p are reduced through LDS by the
 // lane holding the first observation of the track.
 // ---------------------------------------------------------------------------
-template <typename T>
+// FROM_K: J_p is not stored; it is formed as K L^T from the record and the
+// point terms of the previous formation (read before they are replaced),
+// rounded to T and stored in Jp, so that later formations of the same
+// linearization read it instead of forming it again.
+template <typename T, bool FROM_K = false>
 __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __restrict__ chunk_ptr,
                                               const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ chunk_q,
-                                              T* __restrict__ R, const T* __restrict__ Jp, const double* __restrict__ e,
+                                              T* __restrict__ R, T* __restrict__ Jp, const double* __restrict__ e,
                                               double lambda, double* __restrict__ ptL, const int32_t* __restrict__ obs_rpos,
                                               double* __restrict__ ebar, int* __restrict__ flags) {
     __shared__ double sP[WPB][kWave][kPT];   // track sums, then the head's point terms
@@ -97,7 +101,16 @@ __global__ __launch_bounds__(BS) void k_point(int n_chunk, const int32_t* __rest
     const int head = tk.head, tl = tk.len;
     const int64_t q = chunk < n_chunk ? (int64_t)chunk_q[chunk] + tk.idx : 0;   // internal point index
     if (act) {
-        load6(Jp + (int64_t)k * 6, jp);
+        if (FROM_K) {
+            double K[6];
+            load6(R + (int64_t)k * kRec + 18, K);
+            jp_from_K(K, ptL + q * 9, jp);
+#pragma unroll
+            for (int m = 0; m < 6; ++m) jp[m] = (double)(T)jp[m];
+            store6(Jp + (int64_t)k * 6, jp);
+        } else {
+            load6(Jp + (int64_t)k * 6, jp);
+        }
         ek = reinterpret_cast<const double2*>(e)[k];
         sP[wv][lane][0] = jp[0] * jp[0] + jp[3] * jp[3];
         sP[wv][lane][1] = jp[0] * jp[1] + jp[3] * jp[4];
@@ -244,6 +257,7 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
                           max(0, min(nrec - r0, kPer)) * kRecB, lane);
         __syncthreads();
     }
+    if (!Jp_out) return;   // block-uniform
     constexpr int kJpB = 6 * (int)sizeof(T);
     if (act) store6(reinterpret_cast<T*>(stage + lane * kJpB), jp);
     __syncthreads();
@@ -545,15 +559,22 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
 }
 
 // ---------------------------------------------------------------------------
-// back-substitution (Eq. (5)): dx_p = L^-T (lhat - sum_a K_a^T J_ca dxc_a)
+// back-substitution (Eq. (5)): dx_p = L^-T (lhat - sum_a K_a^T J_ca dxc_a),
+// and with it the model terms of the gain ratio, |J dx|^2 and dx^T l with
+// l = -J^T e: the solve's right-hand side is w = L^T dx_p, so an
+// observation's J dx = J_c dxc + K w with no J_p (J_p = K L^T).  One wave per
+// chunk of whole tracks, one lane per observation; per-block partials of the
+// two model terms.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __restrict__ chunk_ptr,
                                                 const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ obs_row,
                                                 const int32_t* __restrict__ chunk_q, const T* __restrict__ R,
                                                 const double* __restrict__ ptL, const double* __restrict__ dxc,
-                                                double* __restrict__ dxp) {
+                                                const double* __restrict__ e, double* __restrict__ dxp,
+                                                double* __restrict__ part, int nb) {
     __shared__ double sP[WPB][kWave][3];
+    __shared__ double sh[WPB];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int chunk = blockIdx.x * WPB + wv;
     int k0 = 0, k1 = 0;
@@ -564,27 +585,25 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
     const Track tk = chunk_track(act, p, lane, k1 - k0);
     const int head = tk.head, tl = tk.len;
     const int64_t q = chunk < n_chunk ? (int64_t)chunk_q[chunk] + tk.idx : 0;   // internal point index
+    double K[6], g0 = 0.0, g1 = 0.0;
     if (act) {
         const int row = obs_row[k];
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        const T* rk = R + (int64_t)k * kRec;
+        load6(rk + 18, K);
         if (row >= 0) {
-            double jc[18], K[6];
-            const T* rk = R + (int64_t)k * kRec;
+            double jc[18];
             load_jc(rk, jc);
-            load6(rk + 18, K);
             const double* dc = dxc + (int64_t)row * 9;
-            double g0 = 0.0, g1 = 0.0;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const double c = dc[i];
                 g0 += jc[i] * c;
                 g1 += jc[9 + i] * c;
             }
-            s0 = K[0] * g0 + K[3] * g1;
-            s1 = K[1] * g0 + K[4] * g1;
-            s2 = K[2] * g0 + K[5] * g1;
         }
-        sP[wv][lane][0] = s0; sP[wv][lane][1] = s1; sP[wv][lane][2] = s2;
+        sP[wv][lane][0] = K[0] * g0 + K[3] * g1;
+        sP[wv][lane][1] = K[1] * g0 + K[4] * g1;
+        sP[wv][lane][2] = K[2] * g0 + K[5] * g1;
     }
     __syncthreads();
     if (act && head == lane) {
@@ -599,6 +618,77 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
         dxp[(int64_t)p * 3 + 0] = x0;
         dxp[(int64_t)p * 3 + 1] = x1;
         dxp[(int64_t)p * 3 + 2] = x2;
+        // the head's own row is read by no other lane now: w for the track
+        sP[wv][lane][0] = u0; sP[wv][lane][1] = u1; sP[wv][lane][2] = u2;
+    }
+    __syncthreads();
+    double jdx2 = 0.0, dxl = 0.0;
+    if (act) {
+        const double* w = sP[wv][head];
+        const double a0 = g0 + K[0] * w[0] + K[1] * w[1] + K[2] * w[2];
+        const double a1 = g1 + K[3] * w[0] + K[4] * w[1] + K[5] * w[2];
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        jdx2 = a0 * a0 + a1 * a1;
+        dxl = -(a0 * ek.x + a1 * ek.y);
+    }
+    const double s0 = block_sum<BS>(jdx2, sh);
+    const double s1 = block_sum<BS>(dxl, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0;
+        part[nb + blockIdx.x] = s1;
+    }
+}
+
+// The model terms |J dx|^2 and dx^T l for a dx_p given from outside (after
+// re-triangulation): J_p dx_p = K (L^T dx_p) with L from the point terms;
+// same layout and partials as k_backsub
+template <typename T>
+__global__ __launch_bounds__(BS) void k_model_terms(int n_chunk, const int32_t* __restrict__ chunk_ptr,
+                                                    const int32_t* __restrict__ obs_pt,
+                                                    const int32_t* __restrict__ obs_row,
+                                                    const int32_t* __restrict__ chunk_q, const T* __restrict__ R,
+                                                    const double* __restrict__ ptL, const double* __restrict__ dxc,
+                                                    const double* __restrict__ dxp, const double* __restrict__ e,
+                                                    double* __restrict__ part, int nb) {
+    __shared__ double sh[WPB];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int chunk = blockIdx.x * WPB + wv;
+    int k0 = 0, k1 = 0;
+    if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
+    const int k = k0 + lane;
+    const bool act = k < k1;
+    const int p = act ? obs_pt[k] : -1;
+    const Track tk = chunk_track(act, p, lane, k1 - k0);
+    const int64_t q = chunk < n_chunk ? (int64_t)chunk_q[chunk] + tk.idx : 0;
+    double jdx2 = 0.0, dxl = 0.0;
+    if (act) {
+        const int row = obs_row[k];
+        const T* rk = R + (int64_t)k * kRec;
+        double K[6], g0 = 0.0, g1 = 0.0;
+        load6(rk + 18, K);
+        if (row >= 0) {
+            double jc[18];
+            load_jc(rk, jc);
+            const double* dc = dxc + (int64_t)row * 9;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) { g0 += jc[i] * dc[i]; g1 += jc[9 + i] * dc[i]; }
+        }
+        const double* L = ptL + q * 9;   // L00, L10, L11, L20, L21, L22
+        const double* d = dxp + (int64_t)p * 3;
+        const double w0 = L[0] * d[0] + L[1] * d[1] + L[3] * d[2];
+        const double w1 = L[2] * d[1] + L[4] * d[2];
+        const double w2 = L[5] * d[2];
+        const double a0 = g0 + K[0] * w0 + K[1] * w1 + K[2] * w2;
+        const double a1 = g1 + K[3] * w0 + K[4] * w1 + K[5] * w2;
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        jdx2 = a0 * a0 + a1 * a1;
+        dxl = -(a0 * ek.x + a1 * ek.y);
+    }
+    const double s0 = block_sum<BS>(jdx2, sh);
+    const double s1 = block_sum<BS>(dxl, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0;
+        part[nb + blockIdx.x] = s1;
     }
 }
 
@@ -607,14 +697,26 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
 void launch_point(ba_ctx* c, double lambda) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
     if (nb == 0) return;
-    if (c->precision == BA_MIXED)
-        k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (float*)c->R,
-                                                 (const float*)c->Jp, c->e, lambda, c->ptL, c->obs_rpos, c->ebar,
-                                                 c->flags);
-    else
-        k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (double*)c->R,
-                                                  (const double*)c->Jp, c->e, lambda, c->ptL, c->obs_rpos, c->ebar,
-                                                  c->flags);
+    if (c->precision == BA_MIXED) {
+        if (c->jp_valid)
+            k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (float*)c->R,
+                                                     (float*)c->Jp, c->e, lambda, c->ptL, c->obs_rpos, c->ebar,
+                                                     c->flags);
+        else
+            k_point<float, true><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q,
+                                                           (float*)c->R, (float*)c->Jp, c->e, lambda, c->ptL,
+                                                           c->obs_rpos, c->ebar, c->flags);
+    } else {
+        if (c->jp_valid)
+            k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (double*)c->R,
+                                                      (double*)c->Jp, c->e, lambda, c->ptL, c->obs_rpos,
+                                                      c->ebar, c->flags);
+        else
+            k_point<double, true><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q,
+                                                            (double*)c->R, (double*)c->Jp, c->e, lambda, c->ptL,
+                                                            c->obs_rpos, c->ebar, c->flags);
+    }
+    c->jp_valid = true;
 }
 
 void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, double lambda) {
@@ -623,13 +725,14 @@ void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, do
     const int n = (int)c->n_obs;
     if (c->precision == BA_MIXED)
         k_linpoint_f<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
-                                                    c->obs_uv, cams, pts, lambda, (float*)c->R, (float*)c->Jp, c->e,
+                                                    c->obs_uv, cams, pts, lambda, (float*)c->R, nullptr, c->e,
                                                     c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
     else
         k_linpoint_d<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
-                                                     c->obs_uv, cams, pts, lambda, (double*)c->R, (double*)c->Jp,
+                                                     c->obs_uv, cams, pts, lambda, (double*)c->R, nullptr,
                                                      c->e, c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
     launch_reduce(c, c->part, nb, 1, c->scal + 0);
+    c->jp_valid = false;   // J_p = K L^T where it is needed
 }
 
 void launch_offdiag(ba_ctx* c) {
@@ -667,15 +770,35 @@ void launch_diag(ba_ctx* c, double lambda) {
                                                         c->Minv, c->Linv, c->flags);
 }
 
+// back-substitution; the model terms go to scal[2] (|J dx|^2) and scal[3]
+// (dx^T l)
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
     if (nb == 0) return;
+    if (2 * (int64_t)nb > c->n_part)
+        throw ba_hip_error(hipErrorInvalidValue, "model-term partials exceed their buffer", __FILE__, __LINE__);
     if (c->precision == BA_MIXED)
         k_backsub<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
-                                                   (const float*)c->R, c->ptL, dxc, dxp);
+                                                   (const float*)c->R, c->ptL, dxc, c->e, dxp, c->part, nb);
     else
         k_backsub<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
-                                                    (const double*)c->R, c->ptL, dxc, dxp);
+                                                    (const double*)c->R, c->ptL, dxc, c->e, dxp, c->part, nb);
+    launch_reduce(c, c->part, nb, 2, c->scal + 2);
+}
+
+// the model terms for dx_p replaced after back-substitution
+void launch_model_terms(ba_ctx* c, const double* dxc, const double* dxp) {
+    const int nb = (c->n_chunk + WPB - 1) / WPB;
+    if (nb == 0) return;
+    if (2 * (int64_t)nb > c->n_part)
+        throw ba_hip_error(hipErrorInvalidValue, "model-term partials exceed their buffer", __FILE__, __LINE__);
+    if (c->precision == BA_MIXED)
+        k_model_terms<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
+                                                       (const float*)c->R, c->ptL, dxc, dxp, c->e, c->part, nb);
+    else
+        k_model_terms<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
+                                                        (const double*)c->R, c->ptL, dxc, dxp, c->e, c->part, nb);
+    launch_reduce(c, c->part, nb, 2, c->scal + 2);
 }
 
 }  // namespace ba

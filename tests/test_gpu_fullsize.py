@@ -274,13 +274,19 @@ def test_strip_scene_lm_against_oracle_run():
     tests/golden/make_strips_lm.py from the oracle alone).  This start is far
     from the optimum (the first step lowers F about 200-fold, the second
     overshoots and is rejected), so the run is compared where it is
-    reproducible: every step solved to rel 1e-12 as in the stored run.
-    FP64: decisions where the oracle's step is far from a tie, the cost at
-    every iteration and the final cost to rel 1e-6.  Mixed precision: its
-    steps differ from FP64's by the FP32 rounding of the records, which this
-    start amplifies like a loose PCG tolerance, so the first step is held to
-    the bound below and the rest of its run is reported (cost error per
-    iteration and final cost against the oracle's run)."""
+    reproducible: every step solved to rel 1e-12 as in the stored run, with
+    a cap no step reaches.  FP64: every decision, the cost entering each of
+    the 10 iterations (so every accepted step's F' but the last) and the
+    rejected step's F' to rel 1e-6.  The tenth step is not reproducible: from
+    iterates whose costs agree to 5e-7 and with both solves converged to rel
+    1e-12, its F' differed by 3.5e-4 (the step is long and the system
+    ill-conditioned: solutions with equal residuals differ along the
+    smallest eigenvectors, and this start's F' depends on them), so the last
+    F' and the final cost are reported.  Mixed precision: its steps differ
+    from FP64's by the FP32 rounding of the records (block errors up to
+    about 3e-7 here), which the rejected second step amplifies to 1e-2, so
+    its first step is held to rel 1e-6 (measured 1e-7) and the rest of its
+    run is reported against the oracle's."""
     import hashlib
     s = scenegen.strips_scene(seed=1, with_stats=False)
     uv = orc.observations(s)
@@ -302,17 +308,17 @@ def test_strip_scene_lm_against_oracle_run():
         rep[name] = dict(final_cost=F, final_cost_rel_diff=abs(F - F_ref) / F_ref, iterations=per_it)
     _report("fullsize_strips_lm_vs_oracle.json", rep)
     d = rep["fp64_block_jacobi"]
-    assert d["final_cost_rel_diff"] <= 1e-6, d["final_cost_rel_diff"]
+    assert len(d["iterations"]) == len(ref)
     for it, r in zip(d["iterations"], ref):
+        assert it["cost_rel_err"] <= 1e-6, it
+        assert it["pcg_relres"] <= 1e-12, it
         if abs(r["cost"] - r["cost_new"]) > 1e-8 * r["cost"]:
             assert it["accepted"] == r["accepted"]
-            assert it["cost_rel_err"] <= 1e-6, it
+            if not r["accepted"]:
+                assert it["cost_new_rel_err"] <= 1e-6, it
     m = rep["mixed_block_jacobi"]["iterations"][0]
     assert m["cost_rel_err"] <= 1e-12 and m["accepted"] == ref[0]["accepted"]
-    # FP32 records: relative block error of S up to about 3e-7 (the strip
-    # scene's RCS parity), a step of that relative error, and F' error up to
-    # (F / F') times it with F / F' about 220 here
-    assert m["cost_new_rel_err"] <= 1e-4, m
+    assert m["cost_new_rel_err"] <= 1e-6, m
 
 
 @pytest.mark.timeout(1200)
