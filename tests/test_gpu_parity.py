@@ -325,6 +325,28 @@ def test_invalid_inputs():
         ba.ba_destroy(ctx)
 
 
+def test_track_longer_than_a_wave_rejected():
+    """A point seen by more than 64 cameras (one wave holds a track in the
+    point stages) is rejected at creation with BA_ERR_INVALID_ARG; 64 are
+    accepted."""
+    import dataclasses
+    s = scenegen.aerial_grid_scene(seed=3, nx=10, ny=8, n_pts=500, with_stats=False)
+    uv = orc.observations(s)
+    seen = set(s.obs_cam[s.obs_pt == 0].tolist())
+    for n_track, ok in ((64, True), (65, False)):
+        extra = [c for c in range(s.n_cams) if c not in seen][:n_track - len(seen)]
+        oc = np.concatenate([s.obs_cam, np.array(extra, np.int32)])
+        op = np.concatenate([s.obs_pt, np.zeros(len(extra), np.int32)])
+        uv2 = np.concatenate([uv, np.zeros((2, len(extra)))], axis=1)
+        s2 = dataclasses.replace(s, obs_cam=oc, obs_pt=op, n_obs=len(oc))
+        if ok:
+            ba.ba_destroy(create(s2, uv2))
+        else:
+            with pytest.raises(ba.BAError) as ei:
+                create(s2, uv2)
+            assert ei.value.status == ba.BA_ERR_INVALID_ARG
+
+
 def test_workspace_cap_out_of_memory():
     s = small_scene(seed=1)
     uv = orc.observations(s)
