@@ -325,6 +325,90 @@ def test_invalid_inputs():
         ba.ba_destroy(ctx)
 
 
+@pytest.mark.parametrize("scene_kind", ["tiny", "fixed"])
+def test_rcs_parity_undamped(scene_kind):
+    """lambda = 0: the RCS is the Schur complement of J^T J itself (Eq. (4)
+    without damping), positive semidefinite with the similarity gauge in its
+    near-null space, so off-diagonal blocks cancel more than with damping;
+    blocks and rhs against the oracle in the floored metric (the floor is
+    what guards that cancellation)."""
+    if scene_kind == "tiny":
+        s = scenegen.tiny_scene(seed=0, with_stats=False)
+    else:
+        s = _mid_scene()
+        s.cam_fixed[[0, 9, 40, 79]] = 1
+    P, F_ref, ctx, F = _both(s, lam=0.0)
+    try:
+        blk, rhs = ba.ba_get_rcs(ctx)
+        blk_ref, rhs_ref = P.rcs()
+        rp, ci = P.pattern()
+        errs, raw = block_errors(blk, blk_ref, rp, ci)
+        assert errs.max() <= 1e-10, (errs.max(), raw.max())
+        rerr = np.linalg.norm(rhs - rhs_ref, axis=1) / np.maximum(np.linalg.norm(rhs_ref, axis=1), 1e-300)
+        assert rerr.max() <= 1e-9, rerr.max()
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_camera_without_observations():
+    """A free camera that sees no point has a zero row in J: its diagonal
+    RCS block is U* = (1 + lambda) 0 = 0, so formation reports
+    BA_ERR_NOT_SPD (the oracle's block is zero too).  Fixed, the camera has
+    no row, and the RCS equals the oracle's for the same observations."""
+    import dataclasses
+    s = scenegen.tiny_scene(seed=0, with_stats=False)
+    uv = orc.observations(s)
+    extra = s.cams_init[:1].copy()
+    s2 = dataclasses.replace(s, n_cams=s.n_cams + 1, cams_true=np.concatenate([s.cams_true, extra]),
+                             cams_init=np.concatenate([s.cams_init, extra]),
+                             cam_fixed=np.concatenate([s.cam_fixed, np.zeros(1, np.uint8)]))
+    P = orc.Problem.from_scene(s2, uv)
+    P.linearize(s2.cams_init, s2.pts_init)
+    P.form_rcs(1e-3)
+    blk_ref, _ = P.rcs()
+    rp, _ = P.pattern()
+    assert not blk_ref[rp[s.n_cams]].any()
+    ctx = create(s2, uv)
+    try:
+        ba.ba_linearize(ctx, T(s2.cams_init, torch.float64), T(s2.pts_init, torch.float64))
+        with pytest.raises(ba.BAError) as ei:
+            ba.ba_form_rcs(ctx, 1e-3)
+        assert ei.value.status == ba.BA_ERR_NOT_SPD
+    finally:
+        ba.ba_destroy(ctx)
+    s2.cam_fixed[s.n_cams] = 1
+    P2, F_ref, ctx, F = _both(s2, uv=uv, lam=1e-3)
+    try:
+        blk, rhs = ba.ba_get_rcs(ctx)
+        blk_ref, rhs_ref = P2.rcs()
+        rp, ci = P2.pattern()
+        errs, _ = block_errors(blk, blk_ref, rp, ci)
+        assert len(rp) - 1 == s.n_cams and errs.max() <= 1e-10
+        assert abs(F - F_ref) <= 1e-11 * F_ref
+    finally:
+        ba.ba_destroy(ctx)
+
+
+def test_degenerate_observation_sets_rejected():
+    """No observations, and a point seen once (its V_p has rank 2: Eq. (3)
+    needs at least two views), are rejected at creation."""
+    import dataclasses
+    s = scenegen.tiny_scene(seed=0, with_stats=False)
+    uv = orc.observations(s)
+    with pytest.raises(ba.BAError) as ei:
+        ba.ba_create(s.n_cams, s.n_pts, T(np.zeros(0, np.int32), torch.int32), T(np.zeros(0, np.int32), torch.int32),
+                     T(np.zeros((2, 0)), torch.float64))
+    assert ei.value.status == ba.BA_ERR_INVALID_ARG
+    # point 0 keeps one observation
+    first = np.flatnonzero(s.obs_pt == 0)
+    keep = np.ones(s.n_obs, bool)
+    keep[first[1:]] = False
+    s1 = dataclasses.replace(s, obs_cam=s.obs_cam[keep], obs_pt=s.obs_pt[keep], n_obs=int(keep.sum()))
+    with pytest.raises(ba.BAError) as ei:
+        create(s1, uv[:, keep])
+    assert ei.value.status == ba.BA_ERR_INVALID_ARG
+
+
 def test_track_longer_than_a_wave_rejected():
     """A point seen by more than 64 cameras (one wave holds a track in the
     point stages) is rejected at creation with BA_ERR_INVALID_ARG; 64 are
