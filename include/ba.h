@@ -84,8 +84,11 @@ typedef struct ba_problem_desc {
 /* Validates the observations and builds the co-visibility pattern once
  * (Sec. 4: block (i, j) is non-zero iff cameras i and j share a point).
  * Requirements: indices in range, finite pixels, no repeated (camera, point)
- * pair, every point observed 2..64 times.  The context copies the
- * observations (the caller may free them on return) and owns all workspace.
+ * pair, every point observed at least twice (Eq. (3) needs two views).
+ * Tracks of up to 64 observations are handled one wave per chunk of tracks,
+ * longer ones one workgroup per point, with the same results to rounding.
+ * The context copies the observations (the caller may free them on return)
+ * and owns all workspace.
  * Errors: BA_ERR_INVALID_ARG, BA_ERR_OUT_OF_MEMORY, BA_ERR_DEVICE; *out is
  * NULL on error and the message is available from ba_last_error(NULL). */
 ba_status ba_create(const ba_problem_desc* desc, ba_ctx** out);
@@ -107,7 +110,8 @@ ba_status ba_create(const ba_problem_desc* desc, ba_ctx** out);
  * block-Jacobi or FSAI (no deflation, no learned network), no
  * re-triangulation, no ba_get_jacobians or ba_triangulate.  Other fields and
  * errors as in ba_problem_desc / ba_create; img_cam entries outside
- * [0, n_phys) give BA_ERR_INVALID_ARG. */
+ * [0, n_phys) give BA_ERR_INVALID_ARG, and so does a point observed more than
+ * 64 times. */
 typedef struct ba_shared_desc {
     int32_t n_imgs;             /* images, > 0 */
     int32_t n_phys;             /* physical cameras, > 0 */

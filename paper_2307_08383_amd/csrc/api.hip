@@ -55,7 +55,7 @@ void upload(ba_ctx* c, T** p, const std::vector<T>& h) {
 
 void free_ctx(ba_ctx* c) {
     if (!c) return;
-    void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->chunk_q, c->chunk_ptr, c->cam_row,
+    void* ptrs[] = {c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, c->chunk_q, c->chunk_ptr, c->long_ptr, c->cam_row,
                     c->row_ptr, c->col_idx, c->off_blk, c->pair_ptr, c->trip, c->rowobs_ptr, c->rowobs,
                     c->sf_ptr, c->sf_col, c->sf_src, c->Sf, c->Sf32, c->Su32, c->lo_ptr, c->lo_blk, c->unit_rng, c->unit_dst, c->lseg_blk, c->lseg_ptr, c->pblk, c->R, c->Jp, c->e, c->obs_rpos, c->ebar, c->ptL, c->blk, c->rhs, c->Minv,
                     c->Linv, c->Mlearn, c->dxc, c->dxp, c->part, c->part2, c->scal, c->flags, c->pcg.x, c->pcg.r[0],
@@ -100,18 +100,28 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         cnt[pt[k]]++;
         key[pt[k]] = std::min(key[pt[k]], cam[k]);
     }
+    int32_t n_long = 0;
     for (int32_t p = 0; p < np; ++p) {
         const int t = cnt[p];
         if (t < 2) throw ba_invalid{"point " + std::to_string(p) + " has " + std::to_string(t) + " observations (need >= 2)"};
-        if (t > kMaxTrack) throw ba_invalid{"point " + std::to_string(p) + " has more than 64 observations"};
+        if (t > kMaxTrack) {
+            if (c->shared)
+                throw ba_invalid{"point " + std::to_string(p) + " has more than 64 observations (shared intrinsics)"};
+            ++n_long;
+        }
     }
-    std::vector<int32_t> ord(np);   // internal position -> point (counting sort by key, stable)
+    // internal position -> point: counting sort by key (stable), the points
+    // of tracks longer than a wave after all others
+    std::vector<int32_t> ord(np);
     {
-        std::vector<int64_t> kc(nc + 1, 0);
-        for (int32_t p = 0; p < np; ++p) kc[key[p] + 1]++;
-        for (int32_t i = 0; i < nc; ++i) kc[i + 1] += kc[i];
-        for (int32_t p = 0; p < np; ++p) ord[kc[key[p]]++] = p;
+        std::vector<int64_t> kc(2 * (size_t)nc + 1, 0);
+        auto slot = [&](int32_t p) { return (cnt[p] > kMaxTrack ? nc : 0) + key[p]; };
+        for (int32_t p = 0; p < np; ++p) kc[slot(p) + 1]++;
+        for (int32_t i = 0; i < 2 * nc; ++i) kc[i + 1] += kc[i];
+        for (int32_t p = 0; p < np; ++p) ord[kc[slot(p)]++] = p;
     }
+    c->n_long = n_long;
+    c->q_long0 = np - n_long;
     std::vector<int32_t>().swap(key);
     std::vector<int32_t> ptr(np + 1, 0);   // track start by internal position
     std::vector<int32_t> trk(2 * (size_t)np);   // (track start, length) by point, for the permutation
@@ -160,13 +170,15 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     // point-aligned chunks of at most 64 observations, and the internal index
     // of each chunk's first point
     std::vector<int32_t> chunk{0}, chunk_q{0};
-    for (int32_t q = 0; q < np; ++q)
+    const int32_t q_long0 = np - n_long;
+    for (int32_t q = 0; q < q_long0; ++q)
         if (ptr[q + 1] - chunk.back() > kMaxTrack) {
             chunk.push_back(ptr[q]);
             chunk_q.push_back(q);
         }
-    chunk.push_back((int32_t)n);
-    c->n_chunk = (int32_t)chunk.size() - 1;
+    chunk.push_back(ptr[q_long0]);
+    c->n_chunk = q_long0 > 0 ? (int32_t)chunk.size() - 1 : 0;
+    std::vector<int32_t> long_ptr(ptr.begin() + q_long0, ptr.end());   // [n_long + 1]
     // records: one per observation (J_c, K), or with shared intrinsics two
     // (exterior part at the image's row, interior part at its camera's row);
     // rrow is the RCS row of each record (-1: fixed), rptr the tracks
@@ -466,6 +478,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->obs_uv, ouv);
     upload(c, &c->chunk_q, chunk_q);
     upload(c, &c->chunk_ptr, chunk);
+    upload(c, &c->long_ptr, long_ptr);
     upload(c, &c->cam_row, cam_row);
     upload(c, &c->row_ptr, row_ptr32);
     upload(c, &c->col_idx, col_idx);
@@ -507,7 +520,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &c->dxp, (size_t)np * 3);
     // per-block partials of up to three sums: grids of one block per 256
     // observations, or per 4 chunks (chunk-based kernels)
-    c->n_part = (int32_t)(3 * std::max<int64_t>((n + 255) / 256, ((int64_t)c->n_chunk + 3) / 4) + 8);
+    c->n_part = (int32_t)(3 * std::max<int64_t>((n + 255) / 256, ((int64_t)c->n_chunk + 3) / 4 + c->n_long) + 8);
     dalloc(c, &c->part, (size_t)c->n_part);
     dalloc(c, &c->part2, (size_t)3 * ba::kReduceParts);
     dalloc(c, &c->scal, 16);

@@ -13,7 +13,7 @@
 namespace ba {
 
 constexpr int kWave = 64;          // CDNA wavefront width
-constexpr int kMaxTrack = 64;      // observations per point handled by one wave
+constexpr int kMaxTrack = 64;      // observations per point handled by one wave (longer tracks: one workgroup)
 constexpr int kPcgBatch = 16;      // PCG iterations per enqueued batch (one graph)
 constexpr int kRec = 24;           // per-observation record: J_c (18), then K = J_p L^-T (6)
 
@@ -311,6 +311,12 @@ struct ba_ctx {
     double* obs_uv = nullptr;          // [2][n_obs]
     int32_t* chunk_q = nullptr;        // [n_chunk] internal index of each chunk's first point
     int32_t* chunk_ptr = nullptr;      // [n_chunk+1] point-aligned chunks of <= 64 observations
+    // points with more than 64 observations (longer than a wave) come last
+    // in the internal order, after every chunk: n_long of them, internal
+    // indices q_long0 .. q_long0 + n_long - 1, their tracks long_ptr[j] ..
+    // long_ptr[j + 1]; one workgroup works through each
+    int32_t n_long = 0, q_long0 = 0;
+    int32_t* long_ptr = nullptr;       // [n_long+1]
     int32_t* cam_row = nullptr;        // [n_cams] RCS row or -1
     // pattern
     int32_t *row_ptr = nullptr, *col_idx = nullptr;

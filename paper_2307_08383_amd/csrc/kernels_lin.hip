@@ -101,6 +101,21 @@ __global__ __launch_bounds__(BS) void k_jp_from_K(int n_chunk, const int32_t* __
     }
 }
 
+// the same for the tracks longer than a wave: one workgroup per point
+template <typename T>
+__global__ __launch_bounds__(BS) void k_jp_from_K_long(int q0, const int32_t* __restrict__ long_ptr,
+                                                       const T* __restrict__ R, const double* __restrict__ ptL,
+                                                       T* __restrict__ Jp) {
+    const int k0 = long_ptr[blockIdx.x], k1 = long_ptr[blockIdx.x + 1];
+    const double* L = ptL + ((int64_t)q0 + blockIdx.x) * 9;
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        double K[6], jp[6];
+        load6(R + (int64_t)k * kRec + 18, K);
+        jp_from_K(K, L, jp);
+        store6(Jp + (int64_t)k * 6, jp);
+    }
+}
+
 // out[j * ostride + b] = sum of part[j*n + b*chunk .. j*n + min(n, (b+1)*chunk))
 // in a fixed order (block (b, j); b = 0 with chunk >= n sums the whole
 // vector)
@@ -183,6 +198,14 @@ void ensure_jp(ba_ctx* c) {
         else
             k_jp_from_K<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->chunk_q, c->obs_pt,
                                                           (const double*)c->R, c->ptL, (double*)c->Jp);
+    }
+    if (c->n_long > 0) {
+        if (c->precision == BA_MIXED)
+            k_jp_from_K_long<float><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, (const float*)c->R,
+                                                                     c->ptL, (float*)c->Jp);
+        else
+            k_jp_from_K_long<double><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, (const double*)c->R,
+                                                                      c->ptL, (double*)c->Jp);
     }
     c->jp_valid = true;
 }

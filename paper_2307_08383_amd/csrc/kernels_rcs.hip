@@ -161,9 +161,10 @@ __device__ __forceinline__ void wave_copy_out(char* __restrict__ dst, const char
 // linearization fused with the point stage (the LM step after an accepted
 // step): one wave per chunk of whole tracks, one lane per observation.  Each
 // lane forms its residual and Jacobian blocks (Eq. (1)); J_c and J_p are
-// rounded to T first, so the results equal k_linearize followed by k_point.
-// The track sums go through LDS as in k_point, and every record is written
-// whole (J_c, then K) by its lane, with no partial-record writes.
+// rounded to T first, so the records, point terms and e + K lhat equal
+// those of k_linearize followed by k_point.  J_p itself is not stored: it
+// is K L^T wherever it is needed.  The track sums go through LDS as in
+// k_point, and the records are written whole through LDS (below).
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
@@ -171,7 +172,7 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
                                                  const int32_t* __restrict__ obs_pt,
                                                  const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
                                                  const double* __restrict__ cams, const double* __restrict__ pts,
-                                                 double lambda, T* __restrict__ R, T* __restrict__ Jp_out,
+                                                 double lambda, T* __restrict__ R,
                                                  double* __restrict__ e, double* __restrict__ ptL,
                                                  const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
@@ -236,10 +237,10 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
         store_ebar<T>(sP[wv][head], K, eu, ev, obs_rpos[k], ebar);
     }
     __syncthreads();   // every lane has its point terms: sP is free for staging
-    // The wave's records (J_c, K) and J_p rows are contiguous in memory; they
-    // are staged through the wave's 6 KB of sP and written with contiguous
-    // 16-byte (or 8-byte) chunks spread over the lanes, instead of each lane
-    // writing its own record at a 192-byte (96-byte) stride.
+    // The wave's records (J_c, K) are contiguous in memory; they are staged
+    // through the wave's 6 KB of sP and written with contiguous 16-byte
+    // chunks spread over the lanes, instead of each lane writing its own
+    // record at a 192-byte (96-byte) stride.
     char* stage = reinterpret_cast<char*>(&sP[wv][0][0]);
     constexpr int kStageB = kWave * kPT * (int)sizeof(double);
     constexpr int kRecB = kRec * (int)sizeof(T);
@@ -257,11 +258,6 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
                           max(0, min(nrec - r0, kPer)) * kRecB, lane);
         __syncthreads();
     }
-    if (!Jp_out) return;   // block-uniform
-    constexpr int kJpB = 6 * (int)sizeof(T);
-    if (act) store6(reinterpret_cast<T*>(stage + lane * kJpB), jp);
-    __syncthreads();
-    wave_copy_out<kJpB % 16 == 0 ? 16 : 8>(reinterpret_cast<char*>(Jp_out + (int64_t)k0 * 6), stage, nrec * kJpB, lane);
 }
 
 // FP32 records: 96 registers allow five waves per SIMD without spilling;
@@ -271,22 +267,22 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(5))) void k_
                                                  const int32_t* __restrict__ obs_pt,
                                                  const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
                                                  const double* __restrict__ cams, const double* __restrict__ pts,
-                                                 double lambda, float* __restrict__ R, float* __restrict__ Jp_out,
+                                                 double lambda, float* __restrict__ R,
                                                  double* __restrict__ e, double* __restrict__ ptL,
                                                  const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
-    linpoint<float>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, Jp_out, e, ptL, obs_rpos, ebar, part, flags);
+    linpoint<float>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, e, ptL, obs_rpos, ebar, part, flags);
 }
 __global__ __launch_bounds__(BS) void k_linpoint_d(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
                                                  const int32_t* __restrict__ obs_cam,
                                                  const int32_t* __restrict__ obs_pt,
                                                  const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
                                                  const double* __restrict__ cams, const double* __restrict__ pts,
-                                                 double lambda, double* __restrict__ R, double* __restrict__ Jp_out,
+                                                 double lambda, double* __restrict__ R,
                                                  double* __restrict__ e, double* __restrict__ ptL,
                                                  const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
-    linpoint<double>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, Jp_out, e, ptL, obs_rpos, ebar, part, flags);
+    linpoint<double>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, e, ptL, obs_rpos, ebar, part, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -692,46 +688,321 @@ __global__ __launch_bounds__(BS) void k_model_terms(int n_chunk, const int32_t* 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Tracks longer than a wave (more than 64 observations): one workgroup per
+// point, its threads striding over the track; the track sums are reduced in
+// a fixed order (each thread's strided sum, the wave's shuffle tree, then the
+// four waves in order).  The arithmetic per observation is that of the wave
+// kernels above.
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_reduce(double* v, double (*sh)[WPB]) {
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const double w = wave_sum(v[m]);
+        if (lane == 0) sh[m][wv] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < WPB; ++w) t += sh[m][w];
+        v[m] = t;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void add_point_sums(const double* jp, double eu, double ev, double* v) {
+    v[0] += jp[0] * jp[0] + jp[3] * jp[3];
+    v[1] += jp[0] * jp[1] + jp[3] * jp[4];
+    v[2] += jp[0] * jp[2] + jp[3] * jp[5];
+    v[3] += jp[1] * jp[1] + jp[4] * jp[4];
+    v[4] += jp[1] * jp[2] + jp[4] * jp[5];
+    v[5] += jp[2] * jp[2] + jp[5] * jp[5];
+    v[6] -= jp[0] * eu + jp[3] * ev;
+    v[7] -= jp[1] * eu + jp[4] * ev;
+    v[8] -= jp[2] * eu + jp[5] * ev;
+}
+
+// linearization fused with the point stage for point q0 + blockIdx.x (as
+// linpoint: J_p is not stored, the second pass projects again for it);
+// part[blockIdx.x] = the track's cost
+template <typename T>
+__global__ __launch_bounds__(BS) void k_linpoint_long(int q0, const int32_t* __restrict__ long_ptr, int n,
+                                                      const int32_t* __restrict__ obs_cam,
+                                                      const int32_t* __restrict__ obs_pt, const double* __restrict__ uv,
+                                                      const double* __restrict__ cams, const double* __restrict__ pts,
+                                                      double lambda, T* __restrict__ R, double* __restrict__ e,
+                                                      double* __restrict__ ptL, const int32_t* __restrict__ obs_rpos,
+                                                      double* __restrict__ ebar, double* __restrict__ part,
+                                                      int* __restrict__ flags) {
+    __shared__ double sh[10][WPB];
+    __shared__ double sr[kPT];
+    const int k0 = long_ptr[blockIdx.x], k1 = long_ptr[blockIdx.x + 1];
+    const int64_t q = (int64_t)q0 + blockIdx.x;
+    const int p = obs_pt[k0];
+    const double X0 = pts[(int64_t)p * 3], X1 = pts[(int64_t)p * 3 + 1], X2 = pts[(int64_t)p * 3 + 2];
+    double v[10];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) v[m] = 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        double jc[18], jp[6], pu, pv;
+        project_point<true>(cams + (int64_t)obs_cam[k] * 9, X0, X1, X2, pu, pv, jc, jp);
+        const double eu = pu - uv[k], ev = pv - uv[n + k];
+        if (!records_in_range<T>(jc, jp, eu, ev)) flags[2] = 1;
+#pragma unroll
+        for (int m = 0; m < 18; ++m) jc[m] = (double)(T)jc[m];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) jp[m] = (double)(T)jp[m];
+        reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
+        store_jc(R + (int64_t)k * kRec, jc);
+        add_point_sums(jp, eu, ev, v);
+        v[9] += 0.5 * (eu * eu + ev * ev);
+    }
+    block_reduce<10>(v, sh);
+    if (threadIdx.x == 0) {
+        double r[kPT];
+        if (!point_terms(v, lambda, r)) flags[0] = 1;
+#pragma unroll
+        for (int m = 0; m < kPT; ++m) sr[m] = r[m];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
+        part[blockIdx.x] = v[9];
+    }
+    __syncthreads();
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        double jp[6], pu, pv, K[6];
+        project_point<true, false>(cams + (int64_t)obs_cam[k] * 9, X0, X1, X2, pu, pv, nullptr, jp);
+#pragma unroll
+        for (int m = 0; m < 6; ++m) jp[m] = (double)(T)jp[m];
+        point_K(sr, jp, K);
+        store6(R + (int64_t)k * kRec + 18, K);
+        store_ebar<T>(sr, K, pu - uv[k], pv - uv[n + k], obs_rpos[k], ebar);
+    }
+}
+
+// point stage (a new damping) for point q0 + blockIdx.x, as k_point
+template <typename T, bool FROM_K>
+__global__ __launch_bounds__(BS) void k_point_long(int q0, const int32_t* __restrict__ long_ptr, T* __restrict__ R,
+                                                   T* __restrict__ Jp, const double* __restrict__ e, double lambda,
+                                                   double* __restrict__ ptL, const int32_t* __restrict__ obs_rpos,
+                                                   double* __restrict__ ebar, int* __restrict__ flags) {
+    __shared__ double sh[9][WPB];
+    __shared__ double sr[kPT];
+    __shared__ double sL[6];   // the previous formation's factor (FROM_K)
+    const int k0 = long_ptr[blockIdx.x], k1 = long_ptr[blockIdx.x + 1];
+    const int64_t q = (int64_t)q0 + blockIdx.x;
+    if (FROM_K && threadIdx.x < 6) sL[threadIdx.x] = ptL[q * 9 + threadIdx.x];
+    __syncthreads();
+    auto jp_of = [&](int k, double* jp) {
+        if (FROM_K) {
+            double K[6];
+            load6(R + (int64_t)k * kRec + 18, K);
+            jp_from_K(K, sL, jp);
+#pragma unroll
+            for (int m = 0; m < 6; ++m) jp[m] = (double)(T)jp[m];
+        } else {
+            load6(Jp + (int64_t)k * 6, jp);
+        }
+    };
+    double v[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) v[m] = 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        double jp[6];
+        jp_of(k, jp);
+        if (FROM_K) store6(Jp + (int64_t)k * 6, jp);
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        add_point_sums(jp, ek.x, ek.y, v);
+    }
+    block_reduce<9>(v, sh);
+    if (threadIdx.x == 0) {
+        double r[kPT];
+        if (!point_terms(v, lambda, r)) flags[0] = 1;
+#pragma unroll
+        for (int m = 0; m < kPT; ++m) sr[m] = r[m];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
+    }
+    __syncthreads();
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        double jp[6], K[6];
+        jp_of(k, jp);   // FROM_K: from the previous K, which this thread replaces only now
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        point_K(sr, jp, K);
+        store6(R + (int64_t)k * kRec + 18, K);
+        store_ebar<T>(sr, K, ek.x, ek.y, obs_rpos[k], ebar);
+    }
+}
+
+// J_c dxc of observation k (0 for a fixed camera)
+template <typename T>
+__device__ __forceinline__ void jc_dxc(const T* __restrict__ rk, int row, const double* __restrict__ dxc, double& g0,
+                                       double& g1) {
+    g0 = 0.0; g1 = 0.0;
+    if (row < 0) return;
+    double jc[18];
+    load_jc(rk, jc);
+    const double* dc = dxc + (int64_t)row * 9;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { g0 += jc[i] * dc[i]; g1 += jc[9 + i] * dc[i]; }
+}
+
+// back-substitution and the model terms for point q0 + blockIdx.x, as
+// k_backsub; part[blockIdx.x], part[stride + blockIdx.x]
+template <typename T>
+__global__ __launch_bounds__(BS) void k_backsub_long(int q0, const int32_t* __restrict__ long_ptr,
+                                                     const int32_t* __restrict__ obs_pt,
+                                                     const int32_t* __restrict__ obs_row, const T* __restrict__ R,
+                                                     const double* __restrict__ ptL, const double* __restrict__ dxc,
+                                                     const double* __restrict__ e, double* __restrict__ dxp,
+                                                     double* __restrict__ part, int stride) {
+    __shared__ double sh[3][WPB];
+    __shared__ double su[3];
+    const int k0 = long_ptr[blockIdx.x], k1 = long_ptr[blockIdx.x + 1];
+    const int64_t q = (int64_t)q0 + blockIdx.x;
+    const int p = obs_pt[k0];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        const T* rk = R + (int64_t)k * kRec;
+        double K[6], g0, g1;
+        load6(rk + 18, K);
+        jc_dxc(rk, obs_row[k], dxc, g0, g1);
+        v[0] += K[0] * g0 + K[3] * g1;
+        v[1] += K[1] * g0 + K[4] * g1;
+        v[2] += K[2] * g0 + K[5] * g1;
+    }
+    block_reduce<3>(v, sh);
+    if (threadIdx.x == 0) {
+        const double* L = ptL + q * 9;
+        const double u0 = L[6] - v[0], u1 = L[7] - v[1], u2 = L[8] - v[2];
+        const double x2 = u2 / L[5];
+        const double x1 = (u1 - L[4] * x2) / L[2];
+        const double x0 = (u0 - L[1] * x1 - L[3] * x2) / L[0];
+        dxp[(int64_t)p * 3 + 0] = x0;
+        dxp[(int64_t)p * 3 + 1] = x1;
+        dxp[(int64_t)p * 3 + 2] = x2;
+        su[0] = u0; su[1] = u1; su[2] = u2;
+    }
+    __syncthreads();
+    double t[2] = {0.0, 0.0};
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        const T* rk = R + (int64_t)k * kRec;
+        double K[6], g0, g1;
+        load6(rk + 18, K);
+        jc_dxc(rk, obs_row[k], dxc, g0, g1);
+        const double a0 = g0 + K[0] * su[0] + K[1] * su[1] + K[2] * su[2];
+        const double a1 = g1 + K[3] * su[0] + K[4] * su[1] + K[5] * su[2];
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        t[0] += a0 * a0 + a1 * a1;
+        t[1] -= a0 * ek.x + a1 * ek.y;
+    }
+    block_reduce<2>(t, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t[0];
+        part[stride + blockIdx.x] = t[1];
+    }
+}
+
+// the model terms for a given dx_p (after re-triangulation), as k_model_terms
+template <typename T>
+__global__ __launch_bounds__(BS) void k_model_terms_long(int q0, const int32_t* __restrict__ long_ptr,
+                                                         const int32_t* __restrict__ obs_pt,
+                                                         const int32_t* __restrict__ obs_row, const T* __restrict__ R,
+                                                         const double* __restrict__ ptL, const double* __restrict__ dxc,
+                                                         const double* __restrict__ dxp, const double* __restrict__ e,
+                                                         double* __restrict__ part, int stride) {
+    __shared__ double sh[2][WPB];
+    const int k0 = long_ptr[blockIdx.x], k1 = long_ptr[blockIdx.x + 1];
+    const int64_t q = (int64_t)q0 + blockIdx.x;
+    const int p = obs_pt[k0];
+    const double* L = ptL + q * 9;   // L00, L10, L11, L20, L21, L22
+    const double* d = dxp + (int64_t)p * 3;
+    const double w0 = L[0] * d[0] + L[1] * d[1] + L[3] * d[2];
+    const double w1 = L[2] * d[1] + L[4] * d[2];
+    const double w2 = L[5] * d[2];
+    double t[2] = {0.0, 0.0};
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        const T* rk = R + (int64_t)k * kRec;
+        double K[6], g0, g1;
+        load6(rk + 18, K);
+        jc_dxc(rk, obs_row[k], dxc, g0, g1);
+        const double a0 = g0 + K[0] * w0 + K[1] * w1 + K[2] * w2;
+        const double a1 = g1 + K[3] * w0 + K[4] * w1 + K[5] * w2;
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        t[0] += a0 * a0 + a1 * a1;
+        t[1] -= a0 * ek.x + a1 * ek.y;
+    }
+    block_reduce<2>(t, sh);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t[0];
+        part[stride + blockIdx.x] = t[1];
+    }
+}
+
 }  // namespace
 
-void launch_point(ba_ctx* c, double lambda) {
+template <typename T>
+void launch_point_t(ba_ctx* c, double lambda) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
-    if (nb == 0) return;
-    if (c->precision == BA_MIXED) {
+    T* R = (T*)c->R;
+    T* Jp = (T*)c->Jp;
+    if (nb > 0) {
         if (c->jp_valid)
-            k_point<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (float*)c->R,
-                                                     (float*)c->Jp, c->e, lambda, c->ptL, c->obs_rpos, c->ebar,
-                                                     c->flags);
+            k_point<T><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, R, Jp, c->e, lambda,
+                                                 c->ptL, c->obs_rpos, c->ebar, c->flags);
         else
-            k_point<float, true><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q,
-                                                           (float*)c->R, (float*)c->Jp, c->e, lambda, c->ptL,
-                                                           c->obs_rpos, c->ebar, c->flags);
-    } else {
-        if (c->jp_valid)
-            k_point<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, (double*)c->R,
-                                                      (double*)c->Jp, c->e, lambda, c->ptL, c->obs_rpos,
-                                                      c->ebar, c->flags);
-        else
-            k_point<double, true><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q,
-                                                            (double*)c->R, (double*)c->Jp, c->e, lambda, c->ptL,
-                                                            c->obs_rpos, c->ebar, c->flags);
+            k_point<T, true><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->chunk_q, R, Jp, c->e,
+                                                       lambda, c->ptL, c->obs_rpos, c->ebar, c->flags);
     }
+    if (c->n_long > 0) {
+        if (c->jp_valid)
+            k_point_long<T, false><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, R, Jp, c->e, lambda,
+                                                                    c->ptL, c->obs_rpos, c->ebar, c->flags);
+        else
+            k_point_long<T, true><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, R, Jp, c->e, lambda,
+                                                                   c->ptL, c->obs_rpos, c->ebar, c->flags);
+    }
+}
+
+void launch_point(ba_ctx* c, double lambda) {
+    if (c->precision == BA_MIXED)
+        launch_point_t<float>(c, lambda);
+    else
+        launch_point_t<double>(c, lambda);
     c->jp_valid = true;
 }
 
 void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, double lambda) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
-    if (nb == 0) return;
     const int n = (int)c->n_obs;
-    if (c->precision == BA_MIXED)
-        k_linpoint_f<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
-                                                    c->obs_uv, cams, pts, lambda, (float*)c->R, nullptr, c->e,
-                                                    c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
-    else
-        k_linpoint_d<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
-                                                     c->obs_uv, cams, pts, lambda, (double*)c->R, nullptr,
-                                                     c->e, c->ptL, c->obs_rpos, c->ebar, c->part, c->flags);
-    launch_reduce(c, c->part, nb, 1, c->scal + 0);
+    if (nb + (int64_t)c->n_long > c->n_part)
+        throw ba_hip_error(hipErrorInvalidValue, "cost partials exceed their buffer", __FILE__, __LINE__);
+    if (nb > 0) {
+        if (c->precision == BA_MIXED)
+            k_linpoint_f<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
+                                                   c->obs_uv, cams, pts, lambda, (float*)c->R, c->e, c->ptL,
+                                                   c->obs_rpos, c->ebar, c->part, c->flags);
+        else
+            k_linpoint_d<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
+                                                   c->obs_uv, cams, pts, lambda, (double*)c->R, c->e, c->ptL,
+                                                   c->obs_rpos, c->ebar, c->part, c->flags);
+    }
+    if (c->n_long > 0) {
+        if (c->precision == BA_MIXED)
+            k_linpoint_long<float><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, n, c->obs_cam,
+                                                                    c->obs_pt, c->obs_uv, cams, pts, lambda,
+                                                                    (float*)c->R, c->e, c->ptL, c->obs_rpos,
+                                                                    c->ebar, c->part + nb, c->flags);
+        else
+            k_linpoint_long<double><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, n, c->obs_cam,
+                                                                     c->obs_pt, c->obs_uv, cams, pts, lambda,
+                                                                     (double*)c->R, c->e, c->ptL, c->obs_rpos,
+                                                                     c->ebar, c->part + nb, c->flags);
+    }
+    launch_reduce(c, c->part, nb + c->n_long, 1, c->scal + 0);
     c->jp_valid = false;   // J_p = K L^T where it is needed
 }
 
@@ -771,34 +1042,54 @@ void launch_diag(ba_ctx* c, double lambda) {
 }
 
 // back-substitution; the model terms go to scal[2] (|J dx|^2) and scal[3]
-// (dx^T l)
+// (dx^T l): per-block partials of the chunks, then one per long track
+template <typename T>
+void launch_back_substitute_t(ba_ctx* c, const double* dxc, double* dxp, int nb, int stride) {
+    const T* R = (const T*)c->R;
+    if (nb > 0)
+        k_backsub<T><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q, R, c->ptL,
+                                               dxc, c->e, dxp, c->part, stride);
+    if (c->n_long > 0)
+        k_backsub_long<T><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, c->obs_pt, c->obs_row, R, c->ptL,
+                                                           dxc, c->e, dxp, c->part + nb, stride);
+}
+
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
-    if (nb == 0) return;
-    if (2 * (int64_t)nb > c->n_part)
+    const int stride = nb + c->n_long;
+    if (stride == 0) return;
+    if (2 * (int64_t)stride > c->n_part)
         throw ba_hip_error(hipErrorInvalidValue, "model-term partials exceed their buffer", __FILE__, __LINE__);
     if (c->precision == BA_MIXED)
-        k_backsub<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
-                                                   (const float*)c->R, c->ptL, dxc, c->e, dxp, c->part, nb);
+        launch_back_substitute_t<float>(c, dxc, dxp, nb, stride);
     else
-        k_backsub<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
-                                                    (const double*)c->R, c->ptL, dxc, c->e, dxp, c->part, nb);
-    launch_reduce(c, c->part, nb, 2, c->scal + 2);
+        launch_back_substitute_t<double>(c, dxc, dxp, nb, stride);
+    launch_reduce(c, c->part, stride, 2, c->scal + 2);
 }
 
 // the model terms for dx_p replaced after back-substitution
+template <typename T>
+void launch_model_terms_t(ba_ctx* c, const double* dxc, const double* dxp, int nb, int stride) {
+    const T* R = (const T*)c->R;
+    if (nb > 0)
+        k_model_terms<T><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q, R,
+                                                   c->ptL, dxc, dxp, c->e, c->part, stride);
+    if (c->n_long > 0)
+        k_model_terms_long<T><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, c->obs_pt, c->obs_row, R,
+                                                               c->ptL, dxc, dxp, c->e, c->part + nb, stride);
+}
+
 void launch_model_terms(ba_ctx* c, const double* dxc, const double* dxp) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
-    if (nb == 0) return;
-    if (2 * (int64_t)nb > c->n_part)
+    const int stride = nb + c->n_long;
+    if (stride == 0) return;
+    if (2 * (int64_t)stride > c->n_part)
         throw ba_hip_error(hipErrorInvalidValue, "model-term partials exceed their buffer", __FILE__, __LINE__);
     if (c->precision == BA_MIXED)
-        k_model_terms<float><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
-                                                       (const float*)c->R, c->ptL, dxc, dxp, c->e, c->part, nb);
+        launch_model_terms_t<float>(c, dxc, dxp, nb, stride);
     else
-        k_model_terms<double><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q,
-                                                        (const double*)c->R, c->ptL, dxc, dxp, c->e, c->part, nb);
-    launch_reduce(c, c->part, nb, 2, c->scal + 2);
+        launch_model_terms_t<double>(c, dxc, dxp, nb, stride);
+    launch_reduce(c, c->part, stride, 2, c->scal + 2);
 }
 
 }  // namespace ba

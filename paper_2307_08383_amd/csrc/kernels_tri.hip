@@ -56,6 +56,55 @@ __device__ __forceinline__ double undistort_radius(double rho, double k1, double
     return r;
 }
 
+// The terms of observation (camera c, pixel ou, ov) in the normal equations
+// of the linear multi-view solve: A^T A (6 unique) and A^T b of its two rows
+// (x R_3 - R_1) X = t_1 - x t_3, (y R_3 - R_2) X = t_2 - y t_3.
+__device__ __forceinline__ void tri_linear_terms(const double* c, double ou, double ov, double* m) {
+    const double rho = sqrt(ou * ou + ov * ov) / c[6];
+    double x = 0.0, y = 0.0;
+    if (rho > 0.0) {
+        const double r = undistort_radius(rho, c[7], c[8]);
+        x = ou / c[6] * (r / rho);
+        y = ov / c[6] * (r / rho);
+    }
+    const double w0 = c[0], w1 = c[1], w2 = c[2];
+    const double s = w0 * w0 + w1 * w1 + w2 * w2;
+    double a, b, as, bs;
+    rot_coeffs(s, a, b, as, bs);
+    const double R[9] = {1.0 + b * (w0 * w0 - s), -a * w2 + b * w0 * w1, a * w1 + b * w0 * w2,
+                         a * w2 + b * w1 * w0, 1.0 + b * (w1 * w1 - s), -a * w0 + b * w1 * w2,
+                         -a * w1 + b * w2 * w0, a * w0 + b * w2 * w1, 1.0 + b * (w2 * w2 - s)};
+    const double a1[3] = {x * R[6] - R[0], x * R[7] - R[1], x * R[8] - R[2]};
+    const double a2[3] = {y * R[6] - R[3], y * R[7] - R[4], y * R[8] - R[5]};
+    const double b1 = c[3] - x * c[5], b2 = c[4] - y * c[5];
+    m[0] = a1[0] * a1[0] + a2[0] * a2[0];
+    m[1] = a1[0] * a1[1] + a2[0] * a2[1];
+    m[2] = a1[0] * a1[2] + a2[0] * a2[2];
+    m[3] = a1[1] * a1[1] + a2[1] * a2[1];
+    m[4] = a1[1] * a1[2] + a2[1] * a2[2];
+    m[5] = a1[2] * a1[2] + a2[2] * a2[2];
+    m[6] = a1[0] * b1 + a2[0] * b2;
+    m[7] = a1[1] * b1 + a2[1] * b2;
+    m[8] = a1[2] * b1 + a2[2] * b2;
+}
+
+// The terms of the Gauss-Newton step on the point's reprojection error at X:
+// J_p^T J_p (6 unique) and -J_p^T e.
+__device__ __forceinline__ void tri_gn_terms(const double* c, const double* X, double ou, double ov, double* m) {
+    double pu, pv, jp[6];
+    project_point<true, false>(c, X[0], X[1], X[2], pu, pv, nullptr, jp);
+    const double eu = pu - ou, ev = pv - ov;
+    m[0] = jp[0] * jp[0] + jp[3] * jp[3];
+    m[1] = jp[0] * jp[1] + jp[3] * jp[4];
+    m[2] = jp[0] * jp[2] + jp[3] * jp[5];
+    m[3] = jp[1] * jp[1] + jp[4] * jp[4];
+    m[4] = jp[1] * jp[2] + jp[4] * jp[5];
+    m[5] = jp[2] * jp[2] + jp[5] * jp[5];
+    m[6] = -(jp[0] * eu + jp[3] * ev);
+    m[7] = -(jp[1] * eu + jp[4] * ev);
+    m[8] = -(jp[2] * eu + jp[5] * ev);
+}
+
 template <bool LINEAR>
 __global__ __launch_bounds__(BS) void k_triangulate(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
                                                     const int32_t* __restrict__ obs_cam,
@@ -95,33 +144,7 @@ __global__ __launch_bounds__(BS) void k_triangulate(int n_chunk, const int32_t* 
     }
     if (LINEAR) {
         if (act) {
-            const double rho = sqrt(ou * ou + ov * ov) / c[6];
-            double x = 0.0, y = 0.0;
-            if (rho > 0.0) {
-                const double r = undistort_radius(rho, c[7], c[8]);
-                x = ou / c[6] * (r / rho);
-                y = ov / c[6] * (r / rho);
-            }
-            const double w0 = c[0], w1 = c[1], w2 = c[2];
-            const double s = w0 * w0 + w1 * w1 + w2 * w2;
-            double a, b, as, bs;
-            rot_coeffs(s, a, b, as, bs);
-            const double R[9] = {1.0 + b * (w0 * w0 - s), -a * w2 + b * w0 * w1, a * w1 + b * w0 * w2,
-                                 a * w2 + b * w1 * w0, 1.0 + b * (w1 * w1 - s), -a * w0 + b * w1 * w2,
-                                 -a * w1 + b * w2 * w0, a * w0 + b * w2 * w1, 1.0 + b * (w2 * w2 - s)};
-            const double a1[3] = {x * R[6] - R[0], x * R[7] - R[1], x * R[8] - R[2]};
-            const double a2[3] = {y * R[6] - R[3], y * R[7] - R[4], y * R[8] - R[5]};
-            const double b1 = c[3] - x * c[5], b2 = c[4] - y * c[5];
-            double* m = sA[wv][lane];
-            m[0] = a1[0] * a1[0] + a2[0] * a2[0];
-            m[1] = a1[0] * a1[1] + a2[0] * a2[1];
-            m[2] = a1[0] * a1[2] + a2[0] * a2[2];
-            m[3] = a1[1] * a1[1] + a2[1] * a2[1];
-            m[4] = a1[1] * a1[2] + a2[1] * a2[2];
-            m[5] = a1[2] * a1[2] + a2[2] * a2[2];
-            m[6] = a1[0] * b1 + a2[0] * b2;
-            m[7] = a1[1] * b1 + a2[1] * b2;
-            m[8] = a1[2] * b1 + a2[2] * b2;
+            tri_linear_terms(c, ou, ov, sA[wv][lane]);
         }
         __syncthreads();
         if (act && head == lane) {
@@ -141,20 +164,8 @@ __global__ __launch_bounds__(BS) void k_triangulate(int n_chunk, const int32_t* 
     __syncthreads();
     for (int it = 0; it < n_gn; ++it) {
         if (act) {
-            const double X0 = sX[wv][head][0], X1 = sX[wv][head][1], X2 = sX[wv][head][2];
-            double pu, pv, jp[6];
-            project_point<true, false>(c, X0, X1, X2, pu, pv, nullptr, jp);
-            const double eu = pu - ou, ev = pv - ov;
-            double* m = sA[wv][lane];
-            m[0] = jp[0] * jp[0] + jp[3] * jp[3];
-            m[1] = jp[0] * jp[1] + jp[3] * jp[4];
-            m[2] = jp[0] * jp[2] + jp[3] * jp[5];
-            m[3] = jp[1] * jp[1] + jp[4] * jp[4];
-            m[4] = jp[1] * jp[2] + jp[4] * jp[5];
-            m[5] = jp[2] * jp[2] + jp[5] * jp[5];
-            m[6] = -(jp[0] * eu + jp[3] * ev);
-            m[7] = -(jp[1] * eu + jp[4] * ev);
-            m[8] = -(jp[2] * eu + jp[5] * ev);
+            const double X[3] = {sX[wv][head][0], sX[wv][head][1], sX[wv][head][2]};
+            tri_gn_terms(c, X, ou, ov, sA[wv][lane]);
         }
         __syncthreads();
         if (act && head == lane && ok) {
@@ -180,19 +191,106 @@ __global__ __launch_bounds__(BS) void k_triangulate(int n_chunk, const int32_t* 
     }
 }
 
+// The same for a track longer than a wave: one workgroup per point, its
+// threads striding over the track, sums reduced in a fixed order (strided
+// thread sums, the wave's shuffle tree, then the waves in order).
+template <bool LINEAR>
+__global__ __launch_bounds__(BS) void k_triangulate_long(const int32_t* __restrict__ long_ptr, int n,
+                                                         const int32_t* __restrict__ obs_cam,
+                                                         const int32_t* __restrict__ obs_pt,
+                                                         const int32_t* __restrict__ obs_row,
+                                                         const double* __restrict__ uv, const double* __restrict__ cams,
+                                                         const double* __restrict__ dxc, const double* __restrict__ pts,
+                                                         double* __restrict__ out, int delta, int n_gn,
+                                                         int* __restrict__ n_failed) {
+    __shared__ double sh[9][WPB];
+    __shared__ double sX[3];
+    __shared__ int sok;
+    const int k0 = long_ptr[blockIdx.x], k1 = long_ptr[blockIdx.x + 1];
+    const int p = obs_pt[k0];
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 3; ++i) sX[i] = pts[(int64_t)p * 3 + i] + (delta ? out[(int64_t)p * 3 + i] : 0.0);
+        sok = 1;
+    }
+    __syncthreads();
+    auto camera = [&](int k, double* c) {
+        const double* c0 = cams + (int64_t)obs_cam[k] * 9;
+        const int row = obs_row[k];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) c[i] = c0[i] + ((dxc && row >= 0) ? dxc[(int64_t)row * 9 + i] : 0.0);
+    };
+    // sums of the track's terms into sh[m][0] (all threads then read them)
+    auto reduce9 = [&](double* v) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+            const double w = wave_sum(v[m]);
+            if (lane == 0) sh[m][wv] = w;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int m = 0; m < 9; ++m) {
+                double t = 0.0;
+#pragma unroll
+                for (int w = 0; w < WPB; ++w) t += sh[m][w];
+                v[m] = t;
+            }
+    };
+    for (int it = LINEAR ? -1 : 0; it < n_gn; ++it) {
+        double v[9];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) v[m] = 0.0;
+        const double X[3] = {sX[0], sX[1], sX[2]};
+        for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+            double c[9], t[9];
+            camera(k, c);
+            if (it < 0) tri_linear_terms(c, uv[k], uv[n + k], t);
+            else tri_gn_terms(c, X, uv[k], uv[n + k], t);
+#pragma unroll
+            for (int m = 0; m < 9; ++m) v[m] += t[m];
+        }
+        reduce9(v);
+        if (threadIdx.x == 0 && sok) {
+            double d[3];
+            sok = solve3(v, d);
+            if (sok)
+                for (int i = 0; i < 3; ++i) sX[i] = it < 0 ? d[i] : sX[i] + d[i];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (!sok) atomicAdd(n_failed, 1);
+        for (int i = 0; i < 3; ++i) out[(int64_t)p * 3 + i] = sX[i] - (delta ? pts[(int64_t)p * 3 + i] : 0.0);
+    }
+}
+
 }  // namespace
 
 void launch_triangulate(ba_ctx* c, const double* cams, const double* dxc, const double* pts, double* out, int delta,
                         int linear, int n_gn, int* n_failed) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
-    if (nb == 0) return;
     const int n = (int)c->n_obs;
-    if (linear)
-        k_triangulate<true><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->obs_row,
-                                                      c->obs_uv, cams, dxc, pts, out, delta, n_gn, n_failed);
-    else
-        k_triangulate<false><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->obs_row,
-                                                       c->obs_uv, cams, dxc, pts, out, delta, n_gn, n_failed);
+    if (nb > 0) {
+        if (linear)
+            k_triangulate<true><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt,
+                                                          c->obs_row, c->obs_uv, cams, dxc, pts, out, delta, n_gn,
+                                                          n_failed);
+        else
+            k_triangulate<false><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt,
+                                                           c->obs_row, c->obs_uv, cams, dxc, pts, out, delta, n_gn,
+                                                           n_failed);
+    }
+    if (c->n_long > 0) {
+        if (linear)
+            k_triangulate_long<true><<<c->n_long, BS, 0, c->stream>>>(c->long_ptr, n, c->obs_cam, c->obs_pt,
+                                                                      c->obs_row, c->obs_uv, cams, dxc, pts, out,
+                                                                      delta, n_gn, n_failed);
+        else
+            k_triangulate_long<false><<<c->n_long, BS, 0, c->stream>>>(c->long_ptr, n, c->obs_cam, c->obs_pt,
+                                                                       c->obs_row, c->obs_uv, cams, dxc, pts, out,
+                                                                       delta, n_gn, n_failed);
+    }
 }
 
 }  // namespace ba

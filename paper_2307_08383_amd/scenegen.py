@@ -249,6 +249,46 @@ def aerial_grid_scene(seed=0, noise_sigma=0.5, nx=50, ny=40, n_pts=400_000,
                      with_stats=with_stats)
 
 
+def long_track_scene(seed=5, noise_sigma=0.5, nx=20, ny=15, n_pts=6000,
+                     long_tracks=(12, 64, 65, 96, 200, 256, 257, 300), depth=20.0,
+                     altitude=2.5, relief=0.25, with_stats=False):
+    """The aerial grid plus a few distant points (depth units below the
+    ground, near the grid centre, so every camera sees them within
+    normalised radius ~0.65), point j seen by its long_tracks[j] nearest
+    cameras: tracks longer than a 64-wide wave, up to every camera.  The
+    distant points take random positions among the point indices."""
+    rng = np.random.default_rng(seed)
+    xs = np.arange(nx, dtype=np.float64)
+    ys = np.arange(ny, dtype=np.float64)
+    gx, gy = np.meshgrid(xs, ys, indexing="xy")
+    centres = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, altitude)], axis=1)
+    n_c = centres.shape[0]
+    half = 0.5 * altitude
+    near = np.stack([rng.uniform(xs[0] - half, xs[-1] + half, n_pts),
+                     rng.uniform(ys[0] - half, ys[-1] + half, n_pts),
+                     rng.uniform(0.0, relief, n_pts)], axis=1)
+    t, _ = _truncated_geometric(rng, n_pts, 2, 12, 4.0)
+    op_n, oc_n = _nearest_cams(centres[:, :2], near[:, :2], t, 12)
+    lt = np.minimum(np.asarray(long_tracks, np.int64), n_c)
+    n_l = lt.size
+    far = np.stack([rng.uniform(0.4 * xs[-1], 0.6 * xs[-1], n_l),
+                    rng.uniform(0.4 * ys[-1], 0.6 * ys[-1], n_l),
+                    np.full(n_l, -depth)], axis=1)
+    op_f, oc_f = _nearest_cams(centres[:, :2], far[:, :2], lt, int(lt.max()))
+    # point ids: a random permutation of near and far points
+    n_all = n_pts + n_l
+    new_id = rng.permutation(n_all)
+    pts = np.empty((n_all, 3))
+    pts[new_id[:n_pts]] = near
+    pts[new_id[n_pts:]] = far
+    obs_pt = np.concatenate([new_id[op_n], new_id[n_pts + op_f]])
+    obs_cam = np.concatenate([oc_n, oc_f])
+    order = np.lexsort((obs_cam, obs_pt))
+    return _assemble(f"long-tracks-{n_c}cam-{n_all}pt", seed, rng, centres, np.zeros(n_c, np.uint8), pts,
+                     obs_pt[order], obs_cam[order], noise_sigma, lm_iterations=10, pcg_tol=1e-6,
+                     with_stats=with_stats)
+
+
 def strips_scene(seed=1, noise_sigma=0.5, n_strips=5, per_strip=3600, n_cross=2000,
                  n_pts=5_000_000, along=0.5, across=1.0, altitude=2.5, relief=0.25,
                  with_stats=True):

@@ -22,7 +22,7 @@ import pytest
 from oracle import oracle as orc
 from paper_2307_08383_amd import scenegen
 
-from gpu_util import T, block_errors, create
+from gpu_util import T, check_against_oracle, create
 
 pytestmark = pytest.mark.gpu
 
@@ -37,36 +37,6 @@ def _scene(kind):
     if kind == "fixed":
         s.cam_fixed[[0, 9, 40, 79]] = 1
     return s
-
-
-def _check_against_oracle(ctx, P, cams, pts, lam, precision, rng):
-    """J, e, RCS and the point terms (through back-substitution) of ctx
-    against the oracle at (cams, pts, lam)."""
-    F_ref = P.linearize(cams, pts)
-    P.form_rcs(lam)
-    e_ref, Jc, Jp = P.linearization()
-    J, e = ba.ba_get_jacobians(ctx)
-    J_ref = np.concatenate([Jc.reshape(-1, 18), Jp.reshape(-1, 6)], axis=1)
-    scale = np.abs(J_ref).max(axis=1, keepdims=True)
-    jtol = 1e-11 if precision == 0 else 1e-6
-    assert (np.abs(J - J_ref) / scale).max() <= jtol
-    np.testing.assert_allclose(e, e_ref, rtol=0, atol=1e-9)
-    blk, rhs = ba.ba_get_rcs(ctx)
-    blk_ref, rhs_ref = P.rcs()
-    rp, ci = P.pattern()
-    errs, raw = block_errors(blk, blk_ref, rp, ci)
-    assert errs.max() <= (1e-10 if precision == 0 else 1e-4), (errs.max(), raw.max())
-    rerr = np.linalg.norm(rhs - rhs_ref, axis=1) / np.linalg.norm(rhs_ref, axis=1)
-    assert rerr.max() <= (1e-9 if precision == 0 else 1e-4), rerr.max()
-    # back-substitution reads the point terms (Cholesky factor of V*, L^-1 l_p)
-    # that the fused kernel stored
-    dxc = rng.standard_normal((P.n_rows, 9)) * 1e-3
-    dxp = torch.empty((P.n_pts, 3), dtype=torch.float64, device="cuda")
-    ba.ba_back_substitute(ctx, T(dxc, torch.float64), dxp)
-    dxp_ref = P.back_substitute(dxc)
-    btol = 1e-10 if precision == 0 else 1e-4
-    assert np.abs(dxp.cpu().numpy() - dxp_ref).max() <= btol * np.abs(dxp_ref).max()
-    return F_ref, J, e, blk, rhs
 
 
 def _separate(scene, uv, precision, cams, pts, lam):
@@ -101,7 +71,7 @@ def test_fused_path_elementwise(kind, precision):
             info = ba.ba_lm_step(ctx, cams, pts, st)
             if not relin:
                 continue
-            F_ref, J, e, blk, rhs = _check_against_oracle(ctx, P, c0, p0, lam0, precision, rng)
+            F_ref, J, e, blk, rhs = check_against_oracle(ctx, P, c0, p0, lam0, precision, rng)
             assert abs(info["cost"] - F_ref) <= 1e-11 * F_ref
             J2, e2, blk2, rhs2 = _separate(s, uv, precision, c0, p0, lam0)
             assert np.array_equal(J[:, :18], J2[:, :18]) and np.array_equal(e, e2)

@@ -409,25 +409,36 @@ def test_degenerate_observation_sets_rejected():
     assert ei.value.status == ba.BA_ERR_INVALID_ARG
 
 
-def test_track_longer_than_a_wave_rejected():
-    """A point seen by more than 64 cameras (one wave holds a track in the
-    point stages) is rejected at creation with BA_ERR_INVALID_ARG; 64 are
-    accepted."""
+def test_track_length_limits():
+    """A 9-parameter context takes tracks of any length (a point seen by more
+    than 64 cameras, one wave, goes to the workgroup-per-point kernels); a
+    shared-intrinsics context rejects a track longer than 64 at creation
+    with BA_ERR_INVALID_ARG and takes 64."""
     import dataclasses
     s = scenegen.aerial_grid_scene(seed=3, nx=10, ny=8, n_pts=500, with_stats=False)
     uv = orc.observations(s)
     seen = set(s.obs_cam[s.obs_pt == 0].tolist())
+    extra = [c for c in range(s.n_cams) if c not in seen][:65 - len(seen)]
+    oc = np.concatenate([s.obs_cam, np.array(extra, np.int32)])
+    op = np.concatenate([s.obs_pt, np.zeros(len(extra), np.int32)])
+    uv2 = np.concatenate([uv, np.zeros((2, len(extra)))], axis=1)
+    ba.ba_destroy(create(dataclasses.replace(s, obs_cam=oc, obs_pt=op, n_obs=len(oc)), uv2))
+    sh = scenegen.shared_intrinsics_scene(seed=8, nx=10, ny=8, n_pts=500, n_phys=4)
+    seen = set(sh.obs_img[sh.obs_pt == 0].tolist())
     for n_track, ok in ((64, True), (65, False)):
-        extra = [c for c in range(s.n_cams) if c not in seen][:n_track - len(seen)]
-        oc = np.concatenate([s.obs_cam, np.array(extra, np.int32)])
-        op = np.concatenate([s.obs_pt, np.zeros(len(extra), np.int32)])
-        uv2 = np.concatenate([uv, np.zeros((2, len(extra)))], axis=1)
-        s2 = dataclasses.replace(s, obs_cam=oc, obs_pt=op, n_obs=len(oc))
+        extra = [c for c in range(sh.n_img) if c not in seen][:n_track - len(seen)]
+        oi = np.concatenate([sh.obs_img, np.array(extra, np.int32)])
+        op = np.concatenate([sh.obs_pt, np.zeros(len(extra), np.int32)])
+        uv2 = np.zeros((2, len(oi)))
+
+        def make():
+            return ba.ba_create_shared(sh.n_img, sh.n_phys, sh.n_pts, T(oi, torch.int32), T(op, torch.int32),
+                                       T(uv2, torch.float64), T(sh.img_cam, torch.int32), None)
         if ok:
-            ba.ba_destroy(create(s2, uv2))
+            ba.ba_destroy(make())
         else:
             with pytest.raises(ba.BAError) as ei:
-                create(s2, uv2)
+                make()
             assert ei.value.status == ba.BA_ERR_INVALID_ARG
 
 
