@@ -110,8 +110,7 @@ ba_status ba_create(const ba_problem_desc* desc, ba_ctx** out);
  * block-Jacobi or FSAI (no deflation, no learned network), no
  * re-triangulation, no ba_get_jacobians or ba_triangulate.  Other fields and
  * errors as in ba_problem_desc / ba_create; img_cam entries outside
- * [0, n_phys) give BA_ERR_INVALID_ARG, and so does a point observed more than
- * 64 times. */
+ * [0, n_phys) give BA_ERR_INVALID_ARG. */
 typedef struct ba_shared_desc {
     int32_t n_imgs;             /* images, > 0 */
     int32_t n_phys;             /* physical cameras, > 0 */

@@ -104,11 +104,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     for (int32_t p = 0; p < np; ++p) {
         const int t = cnt[p];
         if (t < 2) throw ba_invalid{"point " + std::to_string(p) + " has " + std::to_string(t) + " observations (need >= 2)"};
-        if (t > kMaxTrack) {
-            if (c->shared)
-                throw ba_invalid{"point " + std::to_string(p) + " has more than 64 observations (shared intrinsics)"};
-            ++n_long;
-        }
+        if (t > kMaxTrack) ++n_long;
     }
     // internal position -> point: counting sort by key (stable), the points
     // of tracks longer than a wave after all others

@@ -220,6 +220,28 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return t;
 }
 
+// Deterministic sums of NV values over a workgroup of NW waves: each
+// thread's value, the wave's shuffle tree, then the waves in order.  Every
+// thread receives the totals in v.  Called by every thread of the workgroup.
+template <int NV, int NW>
+__device__ __forceinline__ void block_reduce(double* v, double (*sh)[NW]) {
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        const double w = wave_sum(v[m]);
+        if (lane == 0) sh[m][wv] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NV; ++m) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += sh[m][w];
+        v[m] = t;
+    }
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------

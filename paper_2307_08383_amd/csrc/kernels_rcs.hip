@@ -695,25 +695,6 @@ __global__ __launch_bounds__(BS) void k_model_terms(int n_chunk, const int32_t* 
 // four waves in order).  The arithmetic per observation is that of the wave
 // kernels above.
 // ---------------------------------------------------------------------------
-template <int NV>
-__device__ __forceinline__ void block_reduce(double* v, double (*sh)[WPB]) {
-    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-#pragma unroll
-    for (int m = 0; m < NV; ++m) {
-        const double w = wave_sum(v[m]);
-        if (lane == 0) sh[m][wv] = w;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < NV; ++m) {
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < WPB; ++w) t += sh[m][w];
-        v[m] = t;
-    }
-    __syncthreads();
-}
-
 __device__ __forceinline__ void add_point_sums(const double* jp, double eu, double ev, double* v) {
     v[0] += jp[0] * jp[0] + jp[3] * jp[3];
     v[1] += jp[0] * jp[1] + jp[3] * jp[4];

@@ -163,6 +163,97 @@ __global__ __launch_bounds__(BS) void k_linpoint_s(int n_chunk, const int32_t* _
     }
 }
 
+// Tracks longer than a wave: one workgroup per point (q0 + blockIdx.x), its
+// threads striding over the track, the point's sums reduced in a fixed order
+// (each thread's strided sum, the wave's shuffle tree, the waves in order).
+// The first pass writes J_p, e and the Jacobian parts of both records; the
+// second, with the point terms, K and e + K lhat.  A thread reads back in the
+// second pass only what it wrote in the first.  part[blockIdx.x] = the
+// track's cost.
+__global__ __launch_bounds__(BS) void k_linpoint_s_long(int q0, const int32_t* __restrict__ long_ptr, int n,
+                                                        const int32_t* __restrict__ obs_img,
+                                                        const int32_t* __restrict__ obs_pt,
+                                                        const int32_t* __restrict__ img_cam, int n_img,
+                                                        const double* __restrict__ uv,
+                                                        const double* __restrict__ params,
+                                                        const double* __restrict__ pts, double lambda,
+                                                        double* __restrict__ R, double* __restrict__ Jp_out,
+                                                        double* __restrict__ e, double* __restrict__ ptL,
+                                                        double* __restrict__ ebar, double* __restrict__ part,
+                                                        int* __restrict__ flags) {
+    __shared__ double sh[10][WPB];
+    __shared__ double sr[kPT];
+    const int k0 = long_ptr[blockIdx.x], k1 = long_ptr[blockIdx.x + 1];
+    const int64_t q = (int64_t)q0 + blockIdx.x;
+    const int p = obs_pt[k0];
+    const double X0 = pts[(int64_t)p * 3], X1 = pts[(int64_t)p * 3 + 1], X2 = pts[(int64_t)p * 3 + 2];
+    double v[10];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) v[m] = 0.0;
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        const int img = obs_img[k];
+        const double* intr = params + 6 * (int64_t)n_img + 5 * (int64_t)img_cam[img];
+        double c9[9], jc[18], jp[6], pu, pv;
+        compose(params + 6 * (int64_t)img, intr, c9);
+        project_point<true>(c9, X0, X1, X2, pu, pv, jc, jp);
+        const double eu = pu + intr[1] - uv[k], ev = pv + intr[2] - uv[n + k];
+        if (!records_in_range<double>(jc, jp, eu, ev)) flags[2] = 1;
+#pragma unroll
+        for (int m = 0; m < 6; ++m) Jp_out[(int64_t)k * 6 + m] = jp[m];
+        reinterpret_cast<double2*>(e)[k] = make_double2(eu, ev);
+        // Jacobian parts of the exterior and interior records (layout of
+        // k_linpoint_s)
+        double re[18], ri[18];
+#pragma unroll
+        for (int m = 0; m < 18; ++m) { re[m] = 0.0; ri[m] = 0.0; }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) { re[j] = jc[j]; re[9 + j] = jc[9 + j]; }
+        ri[0] = jc[6]; ri[1] = 1.0; ri[3] = jc[7]; ri[4] = jc[8];
+        ri[9] = jc[15]; ri[11] = 1.0; ri[12] = jc[16]; ri[13] = jc[17];
+        store_jc(R + (int64_t)(2 * k) * kRec, re);
+        store_jc(R + (int64_t)(2 * k + 1) * kRec, ri);
+        v[0] += jp[0] * jp[0] + jp[3] * jp[3];
+        v[1] += jp[0] * jp[1] + jp[3] * jp[4];
+        v[2] += jp[0] * jp[2] + jp[3] * jp[5];
+        v[3] += jp[1] * jp[1] + jp[4] * jp[4];
+        v[4] += jp[1] * jp[2] + jp[4] * jp[5];
+        v[5] += jp[2] * jp[2] + jp[5] * jp[5];
+        v[6] -= jp[0] * eu + jp[3] * ev;
+        v[7] -= jp[1] * eu + jp[4] * ev;
+        v[8] -= jp[2] * eu + jp[5] * ev;
+        v[9] += 0.5 * (eu * eu + ev * ev);
+    }
+    block_reduce<10>(v, sh);
+    if (threadIdx.x == 0) {
+        double r[kPT];
+        if (!point_terms_s(v, lambda, r)) flags[0] = 1;
+#pragma unroll
+        for (int m = 0; m < kPT; ++m) sr[m] = r[m];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) ptL[q * 9 + m] = r[m];
+        part[blockIdx.x] = v[9];
+    }
+    __syncthreads();
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        double jp[6], K[6];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) jp[m] = Jp_out[(int64_t)k * 6 + m];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const double y0 = jp[3 * rr] * sr[9];
+            const double y1 = (jp[3 * rr + 1] - sr[1] * y0) * sr[10];
+            const double y2 = (jp[3 * rr + 2] - sr[3] * y0 - sr[4] * y1) * sr[11];
+            K[3 * rr] = y0; K[3 * rr + 1] = y1; K[3 * rr + 2] = y2;
+        }
+        store6(R + (int64_t)(2 * k) * kRec + 18, K);
+        store6(R + (int64_t)(2 * k + 1) * kRec + 18, K);
+        const double2 ek = reinterpret_cast<const double2*>(e)[k];
+        const double v0 = ek.x + K[0] * sr[6] + K[1] * sr[7] + K[2] * sr[8];
+        const double v1 = ek.y + K[3] * sr[6] + K[4] * sr[7] + K[5] * sr[8];
+        reinterpret_cast<double2*>(ebar)[k] = make_double2(v0, v1);
+    }
+}
+
 // Diagonal stage: one wave per RCS row over its records (the row's list):
 // diag(U) and b_u = -sum J^T (e + K lhat); then the diagonal block that the
 // pair stage formed gets lambda diag(U) and the identity on its padding,
@@ -318,6 +409,41 @@ __global__ __launch_bounds__(BS) void k_backsub_s(int n_chunk, const int32_t* __
     }
 }
 
+// dx_p of a track longer than a wave (point q0 + blockIdx.x), as k_backsub_s
+// with the sums reduced over the workgroup in a fixed order
+__global__ __launch_bounds__(BS) void k_backsub_s_long(int q0, const int32_t* __restrict__ long_ptr,
+                                                       const int32_t* __restrict__ obs_img,
+                                                       const int32_t* __restrict__ obs_pt,
+                                                       const int32_t* __restrict__ obs_row,
+                                                       const int32_t* __restrict__ img_cam, int n_free,
+                                                       const double* __restrict__ R, const double* __restrict__ ptL,
+                                                       const double* __restrict__ dxc, double* __restrict__ dxp) {
+    __shared__ double sh[3][WPB];
+    const int k0 = long_ptr[blockIdx.x], k1 = long_ptr[blockIdx.x + 1];
+    const int64_t q = (int64_t)q0 + blockIdx.x;
+    const int p = obs_pt[k0];
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = k0 + threadIdx.x; k < k1; k += BS) {
+        double g0, g1, K[6];
+        jdx(R, k, obs_row[k], n_free + img_cam[obs_img[k]], dxc, g0, g1);
+        load6(R + (int64_t)(2 * k) * kRec + 18, K);
+        v[0] += K[0] * g0 + K[3] * g1;
+        v[1] += K[1] * g0 + K[4] * g1;
+        v[2] += K[2] * g0 + K[5] * g1;
+    }
+    block_reduce<3>(v, sh);
+    if (threadIdx.x == 0) {
+        const double* L = ptL + q * 9;
+        const double u0 = L[6] - v[0], u1 = L[7] - v[1], u2 = L[8] - v[2];
+        const double x2 = u2 / L[5];
+        const double x1 = (u1 - L[4] * x2) / L[2];
+        const double x0 = (u0 - L[1] * x1 - L[3] * x2) / L[0];
+        dxp[(int64_t)p * 3 + 0] = x0;
+        dxp[(int64_t)p * 3 + 1] = x1;
+        dxp[(int64_t)p * 3 + 2] = x2;
+    }
+}
+
 // F' at the candidate parameters and, from the stored linearization,
 // |J dx|^2 and dx^T l (l = -J^T e)
 __global__ __launch_bounds__(BS) void k_evaluate_s(int n, const int32_t* __restrict__ obs_img,
@@ -391,11 +517,20 @@ inline int nblk(int64_t n) { return (int)((n + BS - 1) / BS); }
 
 void launch_linpoint_shared(ba_ctx* c, const double* params, const double* pts, double lambda) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
-    if (nb == 0) return;
-    k_linpoint_s<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, (int)c->n_obs, c->obs_cam, c->obs_pt, c->chunk_q,
-                                           c->img_cam, c->n_cams, c->obs_uv, params, pts, lambda, (double*)c->R,
-                                           (double*)c->Jp, c->e, c->ptL, c->ebar, c->part, c->flags);
-    launch_reduce(c, c->part, nb, 1, c->scal + 0);
+    if (nb + c->n_long == 0) return;
+    if (nb + (int64_t)c->n_long > c->n_part)
+        throw ba_hip_error(hipErrorInvalidValue, "cost partials exceed their buffer", __FILE__, __LINE__);
+    if (nb > 0)
+        k_linpoint_s<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, (int)c->n_obs, c->obs_cam, c->obs_pt,
+                                               c->chunk_q, c->img_cam, c->n_cams, c->obs_uv, params, pts, lambda,
+                                               (double*)c->R, (double*)c->Jp, c->e, c->ptL, c->ebar, c->part,
+                                               c->flags);
+    if (c->n_long > 0)
+        k_linpoint_s_long<<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, (int)c->n_obs, c->obs_cam,
+                                                           c->obs_pt, c->img_cam, c->n_cams, c->obs_uv, params, pts,
+                                                           lambda, (double*)c->R, (double*)c->Jp, c->e, c->ptL,
+                                                           c->ebar, c->part + nb, c->flags);
+    launch_reduce(c, c->part, nb + c->n_long, 1, c->scal + 0);
 }
 
 void launch_node_diag(ba_ctx* c, double lambda) {
@@ -407,9 +542,14 @@ void launch_node_diag(ba_ctx* c, double lambda) {
 
 void launch_back_substitute_shared(ba_ctx* c, const double* dxc, double* dxp) {
     const int nb = (c->n_chunk + WPB - 1) / WPB;
-    if (nb == 0) return;
-    k_backsub_s<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_cam, c->obs_pt, c->obs_row, c->chunk_q,
-                                          c->img_cam, c->n_free, (const double*)c->R, c->ptL, dxc, dxp);
+    if (nb > 0)
+        k_backsub_s<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_cam, c->obs_pt, c->obs_row,
+                                              c->chunk_q, c->img_cam, c->n_free, (const double*)c->R, c->ptL, dxc,
+                                              dxp);
+    if (c->n_long > 0)
+        k_backsub_s_long<<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, c->obs_cam, c->obs_pt,
+                                                          c->obs_row, c->img_cam, c->n_free, (const double*)c->R,
+                                                          c->ptL, dxc, dxp);
 }
 
 void launch_evaluate_shared(ba_ctx* c, const double* params, const double* pts, const double* dxc, const double* dxp) {

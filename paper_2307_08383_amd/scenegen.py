@@ -375,14 +375,18 @@ class SharedScene:
 
 
 def shared_intrinsics_scene(seed=0, nx=10, ny=8, n_pts=20_000, n_phys=4, noise_sigma=0.5, altitude=2.5,
-                            relief=0.25, intr_sigma=0.0):
+                            relief=0.25, intr_sigma=0.0, long_tracks=(), depth=20.0):
     """The aerial grid (nadir images on an nx x ny grid, 60% overlap, tracks
     truncated-geometric on [2, 12] with mean 4, each point seen by its t
     nearest images) flown with n_phys physical cameras: image i is taken by
     camera i mod n_phys.  Interior: f ~ U(950, 1050) px, principal point
     (cx, cy) ~ U(-5, 5) px, k1 ~ U(-0.05, 0.05), k2 ~ U(-0.01, 0.01).  Start:
     poses perturbed as in the other scenes, interior parameters moved by
-    N(0, intr_sigma) relative (0: at their true values)."""
+    N(0, intr_sigma) relative (0: at their true values).  long_tracks adds
+    distant points as in long_track_scene (depth units below the ground near
+    the grid centre, point j seen by its long_tracks[j] nearest images), at
+    random point indices, drawn from a second generator so that the rest of
+    the scene is that of the same seed without them."""
     rng = np.random.default_rng(seed)
     xs = np.arange(nx, dtype=np.float64)
     ys = np.arange(ny, dtype=np.float64)
@@ -407,6 +411,26 @@ def shared_intrinsics_scene(seed=0, nx=10, ny=8, n_pts=20_000, n_phys=4, noise_s
     ext_init = np.concatenate([rot_init.as_rotvec(), _translations(rot_init, centres_init)], axis=1)
     intr_init = intr * (1.0 + rng.normal(0.0, 1.0, size=intr.shape) * intr_sigma)
     pts_init = pts + rng.normal(0.0, 0.05, size=pts.shape)
+    if len(long_tracks):
+        r2 = np.random.default_rng(seed + 7919)
+        lt = np.minimum(np.asarray(long_tracks, np.int64), n_img)
+        far = np.stack([r2.uniform(0.4 * xs[-1], 0.6 * xs[-1], lt.size),
+                        r2.uniform(0.4 * ys[-1], 0.6 * ys[-1], lt.size),
+                        np.full(lt.size, -depth)], axis=1)
+        op_f, oi_f = _nearest_cams(centres[:, :2], far[:, :2], lt, int(lt.max()))
+        n_all = n_pts + lt.size
+        new_id = r2.permutation(n_all)
+        pts_all = np.empty((n_all, 3))
+        init_all = np.empty((n_all, 3))
+        pts_all[new_id[:n_pts]], pts_all[new_id[n_pts:]] = pts, far
+        init_all[new_id[:n_pts]] = pts_init
+        init_all[new_id[n_pts:]] = far + r2.normal(0.0, 0.05, size=far.shape)
+        op = np.concatenate([new_id[obs_pt], new_id[n_pts + op_f]])
+        oi = np.concatenate([obs_img, oi_f])
+        nz = np.concatenate([noise, r2.normal(0.0, 1.0, size=(2, op_f.size)) * noise_sigma], axis=1)
+        order = np.lexsort((oi, op))
+        obs_pt, obs_img, noise = op[order], oi[order], nz[:, order]
+        pts, pts_init, n_pts = pts_all, init_all, n_all
     return SharedScene(name=f"shared-{n_img}img-{n_phys}cam-{n_pts}pt", seed=seed, n_img=n_img, n_phys=n_phys,
                        n_pts=n_pts, n_obs=int(obs_pt.size), img_cam=(np.arange(n_img) % n_phys).astype(np.int32),
                        ext_true=ext, intr_true=intr, pts_true=pts, ext_init=ext_init, intr_init=intr_init,

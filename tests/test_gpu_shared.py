@@ -10,7 +10,10 @@ camera (Sec. 4.1's c = 11; Table 2's fewer cameras than images).
   - PCG on it against the dense solution, its unused slots exactly 0;
   - LM: the step (PCG to rel 1e-12) against the reference's dense step of
     Eq. (1), and the trajectory of 8 iterations against the reference's LM
-    (same damping schedule), final cost to rel 1e-6."""
+    (same damping schedule), final cost to rel 1e-6;
+  - the same with points seen by more than 64 images (tracks longer than a
+    wave, which the fused stage and back-substitution take one workgroup
+    per point), up to every image of a 272-image block."""
 import numpy as np
 import pytest
 
@@ -33,6 +36,14 @@ def _case(kind):
     elif kind == "fixed":
         s = scenegen.shared_intrinsics_scene(seed=7, nx=5, ny=4, n_pts=600, n_phys=3)
         s.img_fixed[[0, 7, 19]] = 1
+    elif kind == "long":
+        # points seen by 65 .. all 272 images (more than a 64-wide wave, up
+        # to two passes of a 256-thread workgroup), three images fixed
+        s = scenegen.shared_intrinsics_scene(seed=9, nx=17, ny=16, n_pts=800, n_phys=3,
+                                             long_tracks=(65, 100, 200, 256, 257, 272))
+        s.img_fixed[[0, 100, 271]] = 1
+    elif kind == "long_small":
+        s = scenegen.shared_intrinsics_scene(seed=10, nx=10, ny=8, n_pts=400, n_phys=2, long_tracks=(65, 72, 80))
     else:   # mid: 80 images, 4 cameras, several tiles of every kernel
         s = scenegen.shared_intrinsics_scene(seed=8, nx=10, ny=8, n_pts=4000, n_phys=4)
     pu, pv = I.project(s.ext_true, s.intr_true, s.img_cam, s.pts_true, s.obs_img, s.obs_pt)
@@ -51,7 +62,7 @@ def _params(ext, intr):
     return T(np.concatenate([ext.ravel(), intr.ravel()]), torch.float64)
 
 
-@pytest.mark.parametrize("kind", ["small", "one_camera", "fixed", "mid"])
+@pytest.mark.parametrize("kind", ["small", "one_camera", "fixed", "mid", "long"])
 def test_shared_rcs_parity(kind):
     s, uv, P = _case(kind)
     lam = 1e-3
@@ -104,8 +115,9 @@ def test_shared_pcg_solution():
         ba.ba_destroy(ctx)
 
 
-def test_shared_lm_step_and_trajectory():
-    s, uv, P = _case("small")
+@pytest.mark.parametrize("kind", ["small", "long_small"])
+def test_shared_lm_step_and_trajectory(kind):
+    s, uv, P = _case(kind)
     ctx = _ctx(s, uv)
     try:
         # one step with the RCS solved tightly: the dense step of Eq. (1)
