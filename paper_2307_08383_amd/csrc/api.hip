@@ -4,10 +4,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <cstdlib>
 
 #include "ba_common.hpp"
+#include "host_par.hpp"
 #include "gnn.hpp"
 
 namespace ba {
@@ -17,6 +19,9 @@ void launch_product(ba_ctx* c, const double* x, double* y);
 namespace {
 
 using ba::kMaxTrack;
+using ba::counting_sort;
+using ba::host_threads;
+using ba::parallel_for;
 using ba::kRec;
 using ba::Pcg;
 
@@ -79,68 +84,143 @@ void free_ctx(ba_ctx* c) {
     delete c;
 }
 
+// The first index in [0, n) where bad(k) holds, or n (threads in parallel).
+template <typename F>
+int64_t first_where(int64_t n, F&& bad) {
+    std::atomic<int64_t> first{n};
+    parallel_for(n, 1 << 18, [&](int64_t k0, int64_t k1, int) {
+        for (int64_t k = k0; k < k1 && k < first.load(std::memory_order_relaxed); ++k)
+            if (bad(k)) {
+                int64_t cur = first.load();
+                while (k < cur && !first.compare_exchange_weak(cur, k)) {}
+                break;
+            }
+    });
+    return first.load();
+}
+
 // Builds the internal observation order, the pattern and every index
-// structure on the host, then uploads them.
-void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t>& pt, const std::vector<double>& uv,
-           const std::vector<uint8_t>& fixed) {
+// structure on the host, then uploads them; the caller's point ids and
+// pixels (device arrays d_pt, d_uv) are put in the internal order on the
+// device, where the pixels are also checked.
+void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t>& pt, const int32_t* d_pt,
+           const double* d_uv, const std::vector<uint8_t>& fixed) {
+    ba::Phases ph("ba_create");
     const int64_t n = c->n_obs;
     const int32_t nc = c->n_cams, np = c->n_pts;
-    for (int64_t k = 0; k < n; ++k) {
-        if (cam[k] < 0 || cam[k] >= nc) throw ba_invalid{"obs_cam[" + std::to_string(k) + "] out of range"};
-        if (pt[k] < 0 || pt[k] >= np) throw ba_invalid{"obs_pt[" + std::to_string(k) + "] out of range"};
-        if (!std::isfinite(uv[k]) || !std::isfinite(uv[n + k]))
-            throw ba_invalid{"obs_uv of observation " + std::to_string(k) + " is not finite"};
+    {
+        const int64_t k = first_where(n, [&](int64_t i) { return cam[i] < 0 || cam[i] >= nc || pt[i] < 0 || pt[i] >= np; });
+        if (k < n) {
+            if (cam[k] < 0 || cam[k] >= nc) throw ba_invalid{"obs_cam[" + std::to_string(k) + "] out of range"};
+            throw ba_invalid{"obs_pt[" + std::to_string(k) + "] out of range"};
+        }
     }
+    ph.mark("validate");
     // internal order: whole tracks, points by the lowest camera that sees
     // them (ties by point), observations of a track by camera.  Points seen by
     // one neighbourhood of cameras end up close together, so the records that
     // a camera pair (or a camera) reads lie in a narrow window of memory.
-    std::vector<int32_t> cnt(np, 0), key(np, nc);
-    for (int64_t k = 0; k < n; ++k) {
-        cnt[pt[k]]++;
-        key[pt[k]] = std::min(key[pt[k]], cam[k]);
+    // track lengths and lowest cameras (order-free sums and minima, all
+    // threads at once)
+    std::vector<int32_t> cnt(np), key(np);
+    {
+        std::unique_ptr<std::atomic<int32_t>[]> acnt(new std::atomic<int32_t>[np]), akey(new std::atomic<int32_t>[np]);
+        parallel_for(np, 1 << 16, [&](int64_t p0, int64_t p1, int) {
+            for (int64_t p = p0; p < p1; ++p) {
+                acnt[p].store(0, std::memory_order_relaxed);
+                akey[p].store(nc, std::memory_order_relaxed);
+            }
+        });
+        parallel_for(n, 1 << 18, [&](int64_t k0, int64_t k1, int) {
+            for (int64_t k = k0; k < k1; ++k) {
+                const int32_t p = pt[k], cm = cam[k];
+                acnt[p].fetch_add(1, std::memory_order_relaxed);
+                int32_t cur = akey[p].load(std::memory_order_relaxed);
+                while (cm < cur && !akey[p].compare_exchange_weak(cur, cm, std::memory_order_relaxed)) {}
+            }
+        });
+        parallel_for(np, 1 << 16, [&](int64_t p0, int64_t p1, int) {
+            for (int64_t p = p0; p < p1; ++p) {
+                cnt[p] = acnt[p].load(std::memory_order_relaxed);
+                key[p] = akey[p].load(std::memory_order_relaxed);
+            }
+        });
     }
-    int32_t n_long = 0;
-    for (int32_t p = 0; p < np; ++p) {
-        const int t = cnt[p];
-        if (t < 2) throw ba_invalid{"point " + std::to_string(p) + " has " + std::to_string(t) + " observations (need >= 2)"};
-        if (t > kMaxTrack) ++n_long;
+    {
+        const int64_t p = first_where(np, [&](int64_t i) { return cnt[i] < 2; });
+        if (p < np)
+            throw ba_invalid{"point " + std::to_string(p) + " has " + std::to_string(cnt[p]) +
+                             " observations (need >= 2)"};
     }
+    const int32_t n_long = (int32_t)std::count_if(cnt.begin(), cnt.end(), [](int32_t t) { return t > kMaxTrack; });
+    ph.mark("track counts");
     // internal position -> point: counting sort by key (stable), the points
     // of tracks longer than a wave after all others
-    std::vector<int32_t> ord(np);
+    std::vector<int32_t> ord;
     {
-        std::vector<int64_t> kc(2 * (size_t)nc + 1, 0);
-        auto slot = [&](int32_t p) { return (cnt[p] > kMaxTrack ? nc : 0) + key[p]; };
-        for (int32_t p = 0; p < np; ++p) kc[slot(p) + 1]++;
-        for (int32_t i = 0; i < 2 * nc; ++i) kc[i + 1] += kc[i];
-        for (int32_t p = 0; p < np; ++p) ord[kc[slot(p)]++] = p;
+        std::vector<int64_t> kc;
+        counting_sort(np, 2 * nc, [&](int64_t p) { return (cnt[p] > kMaxTrack ? nc : 0) + key[p]; }, kc, ord);
     }
     c->n_long = n_long;
     c->q_long0 = np - n_long;
     std::vector<int32_t>().swap(key);
     std::vector<int32_t> ptr(np + 1, 0);   // track start by internal position
     std::vector<int32_t> trk(2 * (size_t)np);   // (track start, length) by point, for the permutation
-    for (int32_t q = 0; q < np; ++q) {
-        const int32_t p = ord[q];
-        ptr[q + 1] = ptr[q] + cnt[p];
-        trk[2 * (size_t)p] = ptr[q];
-        trk[2 * (size_t)p + 1] = cnt[p];
-    }
+    parallel_for(np, 1 << 16, [&](int64_t q0, int64_t q1, int) {
+        for (int64_t q = q0; q < q1; ++q) ptr[q + 1] = cnt[ord[q]];
+    });
+    for (int32_t q = 0; q < np; ++q) ptr[q + 1] += ptr[q];
+    parallel_for(np, 1 << 16, [&](int64_t q0, int64_t q1, int) {
+        for (int64_t q = q0; q < q1; ++q) {
+            const int32_t p = ord[q];
+            trk[2 * (size_t)p] = ptr[q];
+            trk[2 * (size_t)p + 1] = cnt[p];
+        }
+    });
+    ph.mark("point order");
+    // observations of each track, then sorted by camera: placed by all
+    // threads at once (the order inside a track is set by its sort), each
+    // track sorted on its own; a camera repeated in a track is an error,
+    // reported for the first such track in internal order
     std::vector<int64_t> perm(n);
     {
-        std::vector<int32_t> fill(np);
-        for (int32_t p = 0; p < np; ++p) fill[p] = trk[2 * (size_t)p];
-        for (int64_t k = 0; k < n; ++k) perm[fill[pt[k]]++] = k;
+        std::unique_ptr<std::atomic<int32_t>[]> fill(new std::atomic<int32_t>[np]);
+        parallel_for(np, 1 << 16, [&](int64_t p0, int64_t p1, int) {
+            for (int64_t p = p0; p < p1; ++p) fill[p].store(trk[2 * (size_t)p], std::memory_order_relaxed);
+        });
+        parallel_for(n, 1 << 18, [&](int64_t k0, int64_t k1, int) {
+            for (int64_t k = k0; k < k1; ++k) perm[fill[pt[k]].fetch_add(1, std::memory_order_relaxed)] = k;
+        });
     }
-    for (int32_t q = 0; q < np; ++q) {
-        auto b = perm.begin() + ptr[q], e = perm.begin() + ptr[q + 1];
-        std::sort(b, e, [&](int64_t x, int64_t y) { return cam[x] < cam[y]; });
-        for (auto it = b + 1; it < e; ++it)
-            if (cam[*it] == cam[*(it - 1)])
-                throw ba_invalid{"duplicate observation of point " + std::to_string(ord[q]) + " by camera " +
-                                 std::to_string(cam[*it])};
+    {
+        std::atomic<int32_t> bad{np};   // internal index of the first track with a repeated camera
+        parallel_for(np, 1 << 14, [&](int64_t q0, int64_t q1, int) {
+            auto less = [&](int64_t x, int64_t y) { return cam[x] < cam[y]; };
+            for (int64_t q = q0; q < q1; ++q) {
+                int64_t* b = perm.data() + ptr[q];
+                int64_t* e = perm.data() + ptr[q + 1];
+                if (e - b > 32) {
+                    std::sort(b, e, less);
+                } else {
+                    for (int64_t* i = b + 1; i < e; ++i)
+                        for (int64_t* j = i; j > b && less(*j, *(j - 1)); --j) std::swap(*j, *(j - 1));
+                }
+                for (int64_t* i = b + 1; i < e; ++i)
+                    if (cam[*i] == cam[*(i - 1)]) {
+                        int32_t cur = bad.load();
+                        while ((int32_t)q < cur && !bad.compare_exchange_weak(cur, (int32_t)q)) {}
+                        break;
+                    }
+            }
+        });
+        const int32_t q = bad.load();
+        if (q < np)
+            for (int32_t i = ptr[q] + 1; i < ptr[q + 1]; ++i)
+                if (cam[perm[i]] == cam[perm[i - 1]])
+                    throw ba_invalid{"duplicate observation of point " + std::to_string(ord[q]) + " by camera " +
+                                     std::to_string(cam[perm[i]])};
     }
+    ph.mark("track sort");
     std::vector<int32_t>().swap(ord);
     std::vector<int32_t>().swap(cnt);
     std::vector<int32_t>().swap(trk);
@@ -153,16 +233,15 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     c->n_free = nr;
     if (shared) nr += c->n_phys;
     c->n_rows = nr;
-    std::vector<int32_t> ocam(n), opt(n), orow(n);
-    std::vector<double> ouv(2 * n);
-    for (int64_t k = 0; k < n; ++k) {
-        const int64_t s = perm[k];
-        ocam[k] = cam[s];
-        opt[k] = pt[s];
-        orow[k] = cam_row[cam[s]];
-        ouv[k] = uv[s];
-        ouv[n + k] = uv[n + s];
-    }
+    std::vector<int32_t> ocam(n), orow(n);
+    parallel_for(n, 1 << 18, [&](int64_t k0, int64_t k1, int) {
+        for (int64_t k = k0; k < k1; ++k) {
+            const int32_t cs = cam[perm[k]];
+            ocam[k] = cs;
+            orow[k] = cam_row[cs];
+        }
+    });
+    ph.mark("permute");
     // point-aligned chunks of at most 64 observations, and the internal index
     // of each chunk's first point
     std::vector<int32_t> chunk{0}, chunk_q{0};
@@ -180,122 +259,142 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     // rrow is the RCS row of each record (-1: fixed), rptr the tracks
     const int64_t n_rec = shared ? 2 * n : n;
     std::vector<int32_t> rrow(n_rec), rptr(np + 1);
-    for (int64_t k = 0; k < n; ++k) {
-        if (shared) {
-            rrow[2 * k] = orow[k];
-            rrow[2 * k + 1] = c->n_free + c->h_img_cam[ocam[k]];
-        } else {
-            rrow[k] = orow[k];
+    parallel_for(n, 1 << 18, [&](int64_t k0, int64_t k1, int) {
+        for (int64_t k = k0; k < k1; ++k) {
+            if (shared) {
+                rrow[2 * k] = orow[k];
+                rrow[2 * k + 1] = c->n_free + c->h_img_cam[ocam[k]];
+            } else {
+                rrow[k] = orow[k];
+            }
         }
-    }
+    });
     for (int32_t q = 0; q <= np; ++q) rptr[q] = shared ? 2 * ptr[q] : ptr[q];
+    ph.mark("records");
+    // records of each RCS row, in record order, and each record's position
+    // in its row's list
+    std::vector<int32_t> rowobs_ptr(nr + 1, 0), rowobs;
+    std::vector<int32_t> obs_rpos(n_rec, -1);
+    {
+        std::vector<int64_t> rp64;
+        counting_sort(n_rec, nr, [&](int64_t k) { return rrow[k]; }, rp64, rowobs);
+        for (int32_t r = 0; r <= nr; ++r) rowobs_ptr[r] = (int32_t)rp64[r];
+        parallel_for(nr, 64, [&](int64_t r0, int64_t r1, int) {
+            for (int64_t r = r0; r < r1; ++r)
+                for (int32_t d = rowobs_ptr[r]; d < rowobs_ptr[r + 1]; ++d) obs_rpos[rowobs[d]] = d;
+        });
+    }
+    ph.mark("row lists");
     // couples of records of a track whose rows differ (each unordered pair
     // once, oriented from the lower row); with shared intrinsics also every
     // ordered pair of records on the same row, itself included: those sum
     // into the diagonal block (a camera's images seeing one point)
-    auto take = [&](int32_t a, int32_t b) {
-        const int32_t ra = rrow[a], rb = rrow[b];
-        if (ra < 0 || rb < 0) return false;
-        return shared ? ra <= rb : a < b;
-    };
-    int64_t ntr = 0;
-    for (int32_t p = 0; p < np; ++p)
-        for (int32_t a = rptr[p]; a < rptr[p + 1]; ++a)
-            for (int32_t b = shared ? rptr[p] : a + 1; b < rptr[p + 1]; ++b)
-                if (take(a, b)) ntr += 1;
-    if (ntr > INT32_MAX) throw ba_invalid{"too many camera-pair couples for 32-bit indices"};
-    std::vector<int32_t> ta(ntr), tb(ntr);
-    {
-        int64_t m = 0;
-        for (int32_t p = 0; p < np; ++p)
-            for (int32_t a = rptr[p]; a < rptr[p + 1]; ++a)
-                for (int32_t b = shared ? rptr[p] : a + 1; b < rptr[p + 1]; ++b)
-                    if (take(a, b)) { ta[m] = a; tb[m] = b; ++m; }
-    }
-    // stable two-pass counting sort by (row(a), row(b)); row(a) <= row(b)
-    std::vector<int32_t> ta2(ntr), tb2(ntr);
-    {
-        std::vector<int64_t> cnt(nr + 1, 0);
-        for (int64_t m = 0; m < ntr; ++m) cnt[rrow[tb[m]] + 1]++;
-        for (int32_t r = 0; r < nr; ++r) cnt[r + 1] += cnt[r];
-        for (int64_t m = 0; m < ntr; ++m) {
-            const int64_t d = cnt[rrow[tb[m]]]++;
-            ta2[d] = ta[m]; tb2[d] = tb[m];
-        }
-        std::fill(cnt.begin(), cnt.end(), 0);
-        for (int64_t m = 0; m < ntr; ++m) cnt[rrow[ta2[m]] + 1]++;
-        for (int32_t r = 0; r < nr; ++r) cnt[r + 1] += cnt[r];
-        for (int64_t m = 0; m < ntr; ++m) {
-            const int64_t d = cnt[rrow[ta2[m]]]++;
-            ta[d] = ta2[m]; tb[d] = tb2[m];
-        }
-    }
-    std::vector<int32_t>().swap(ta2);
-    std::vector<int32_t>().swap(tb2);
-    // blocks: per row the diagonal first, then the off-diagonal segments
-    std::vector<int64_t> row_ptr(nr + 1, 0);
-    std::vector<int32_t> col_idx;
-    std::vector<int32_t> off_blk, pair_ptr, seg_row;
-    col_idx.reserve(nr * 8);
-    {
-        int64_t m = 0;
-        int64_t blk_id = 0;
-        for (int32_t r = 0; r < nr; ++r) {
-            row_ptr[r] = blk_id;
-            col_idx.push_back(r);
-            ++blk_id;
-            while (m < ntr && rrow[ta[m]] == r) {
-                const int32_t s = rrow[tb[m]];
-                pair_ptr.push_back((int32_t)m);
-                seg_row.push_back(r);
-                if (s == r) {
-                    off_blk.push_back((int32_t)row_ptr[r]);   // same-row couples: the diagonal block
-                } else {
-                    off_blk.push_back((int32_t)blk_id);
-                    col_idx.push_back(s);
-                    ++blk_id;
-                }
-                while (m < ntr && rrow[ta[m]] == r && rrow[tb[m]] == s) ++m;
+    // Built row by row (rows in parallel): the couples (a, b) with a on row
+    // r, in record order of a, then b; grouped by the row s of b into
+    // segments, one per block (r, s) (s = r: the diagonal block); inside the
+    // row the segments are ordered longest first (ties by column), so that
+    // lanes sharing a wavefront get similar amounts of work.  Blocks of a
+    // row: the diagonal, then the columns s > r in ascending order.
+    std::vector<int32_t> rq(n_rec);   // internal point of each record
+    parallel_for(np, 1 << 14, [&](int64_t q0, int64_t q1, int) {
+        for (int64_t q = q0; q < q1; ++q)
+            for (int32_t a = rptr[q]; a < rptr[q + 1]; ++a) rq[a] = (int32_t)q;
+    });
+    auto scan_row = [&](int32_t r, auto&& visit) {
+        for (int32_t i = rowobs_ptr[r]; i < rowobs_ptr[r + 1]; ++i) {
+            const int32_t a = rowobs[i], q = rq[a];
+            for (int32_t b = shared ? rptr[q] : a + 1; b < rptr[q + 1]; ++b) {
+                const int32_t rb = rrow[b];
+                if (rb < 0 || (shared && rb < r)) continue;
+                visit(a, b, rb);
             }
         }
-        row_ptr[nr] = blk_id;
-        pair_ptr.push_back((int32_t)ntr);
-    }
-    c->n_blk = (int64_t)col_idx.size();
-    c->n_offseg = (int32_t)off_blk.size();
-    c->n_pairs = ntr;
-    // inside each row, order the pair segments longest first so that lanes
-    // sharing a wavefront get similar amounts of work (the block each segment
-    // writes is unchanged)
-    {
-        const int32_t ns = c->n_offseg;
-        std::vector<int32_t> order(ns);
-        std::iota(order.begin(), order.end(), 0);
-        int32_t s0 = 0;
-        while (s0 < ns) {
-            int32_t s1 = s0;
-            while (s1 < ns && seg_row[s1] == seg_row[s0]) ++s1;
-            std::stable_sort(order.begin() + s0, order.begin() + s1, [&](int32_t x, int32_t y) {
-                return pair_ptr[x + 1] - pair_ptr[x] > pair_ptr[y + 1] - pair_ptr[y];
-            });
-            s0 = s1;
-        }
-        std::vector<int32_t> off2(ns), ptr2(ns + 1), row2(ns), ta2(ntr), tb2(ntr);
+    };
+    const int nth = host_threads();
+    std::vector<std::vector<int32_t>> t_cnt(nth, std::vector<int32_t>(nr, 0)), t_blk(nth, std::vector<int32_t>(nr));
+    std::vector<std::vector<int64_t>> t_pos(nth, std::vector<int64_t>(nr));
+    std::vector<std::vector<int32_t>> t_touch(nth);
+    // the row's columns with their couple counts (t_cnt, t_touch)
+    auto count_row = [&](int32_t r, int t) {
+        std::vector<int32_t>& cnt_s = t_cnt[t];
+        std::vector<int32_t>& touch = t_touch[t];
         int64_t m = 0;
-        for (int32_t i = 0; i < ns; ++i) {
-            const int32_t sg = order[i];
-            off2[i] = off_blk[sg];
-            row2[i] = seg_row[sg];
-            ptr2[i] = (int32_t)m;
-            for (int32_t t = pair_ptr[sg]; t < pair_ptr[sg + 1]; ++t, ++m) { ta2[m] = ta[t]; tb2[m] = tb[t]; }
+        scan_row(r, [&](int32_t, int32_t, int32_t s) {
+            if (cnt_s[s]++ == 0) touch.push_back(s);
+            ++m;
+        });
+        return m;
+    };
+    std::vector<int64_t> ctr(nr + 1, 0), row_ptr(nr + 1, 0);
+    std::vector<int32_t> sptr(nr + 1, 0);
+    parallel_for(nr, 16, [&](int64_t r0, int64_t r1, int t) {
+        for (int64_t r = r0; r < r1; ++r) {
+            ctr[r + 1] = count_row((int32_t)r, t);
+            int32_t nb = 1;
+            for (int32_t s2 : t_touch[t]) {
+                if (s2 != r) ++nb;
+                t_cnt[t][s2] = 0;
+            }
+            sptr[r + 1] = (int32_t)t_touch[t].size();
+            row_ptr[r + 1] = nb;
+            t_touch[t].clear();
         }
-        ptr2[ns] = (int32_t)m;
-        off_blk.swap(off2);
-        pair_ptr.swap(ptr2);
-        seg_row.swap(row2);
-        ta.swap(ta2);
-        tb.swap(tb2);
+    });
+    for (int32_t r = 0; r < nr; ++r) {
+        ctr[r + 1] += ctr[r];
+        sptr[r + 1] += sptr[r];
+        row_ptr[r + 1] += row_ptr[r];
     }
+    const int64_t ntr = ctr[nr];
+    if (ntr > INT32_MAX) throw ba_invalid{"too many camera-pair couples for 32-bit indices"};
+    if (row_ptr[nr] > INT32_MAX) throw ba_invalid{"too many RCS blocks for 32-bit indices"};
+    const int32_t nseg = sptr[nr];
+    std::vector<int32_t> trip(2 * (size_t)ntr), col_idx(row_ptr[nr]);
+    std::vector<int32_t> off_blk(nseg), pair_ptr(nseg + 1), seg_row(nseg);
+    parallel_for(nr, 16, [&](int64_t r0, int64_t r1, int t) {
+        std::vector<int32_t>& cnt_s = t_cnt[t];
+        std::vector<int32_t>& blk_s = t_blk[t];
+        std::vector<int64_t>& pos_s = t_pos[t];
+        std::vector<int32_t>& touch = t_touch[t];
+        for (int64_t r = r0; r < r1; ++r) {
+            count_row((int32_t)r, t);
+            std::sort(touch.begin(), touch.end());
+            int64_t kb = row_ptr[r];
+            col_idx[kb++] = (int32_t)r;
+            for (int32_t s2 : touch) {
+                if (s2 == r) {
+                    blk_s[s2] = (int32_t)row_ptr[r];
+                } else {
+                    blk_s[s2] = (int32_t)kb;
+                    col_idx[kb++] = s2;
+                }
+            }
+            std::stable_sort(touch.begin(), touch.end(), [&](int32_t x, int32_t y) { return cnt_s[x] > cnt_s[y]; });
+            int64_t m = ctr[r];
+            int32_t sg = sptr[r];
+            for (int32_t s2 : touch) {
+                off_blk[sg] = blk_s[s2];
+                seg_row[sg] = (int32_t)r;
+                pair_ptr[sg] = (int32_t)m;
+                pos_s[s2] = m;
+                m += cnt_s[s2];
+                ++sg;
+            }
+            scan_row((int32_t)r, [&](int32_t a, int32_t b, int32_t s2) {
+                const int64_t d = pos_s[s2]++;
+                trip[2 * d] = a;
+                trip[2 * d + 1] = b;
+            });
+            for (int32_t s2 : touch) cnt_s[s2] = 0;
+            touch.clear();
+        }
+    });
+    pair_ptr[nseg] = (int32_t)ntr;
+    std::vector<int32_t>().swap(rq);
+    c->n_blk = row_ptr[nr];
+    c->n_offseg = nseg;
+    c->n_pairs = ntr;
+    ph.mark("couples");
     // pair-stage work units.  One lane group works through a unit's couples
     // one after another, so a long segment would set the stage's duration on
     // small problems: segments longer than the cap are cut into chunks that
@@ -357,6 +456,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
             ++n_cl;
         }
     }
+    ph.mark("clusters");
     std::vector<int32_t> unit_rng, unit_dst, lseg_blk, lseg_ptr{0};
     {
         struct Unit { int32_t win, t0, t1, dst; };
@@ -407,25 +507,10 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         c->n_lseg = (int32_t)lseg_blk.size();
         c->n_pblk = n_p;
     }
+    ph.mark("units");
     c->h_blk_pairs.assign(c->n_blk, 0);
     for (int32_t sg = 0; sg < c->n_offseg; ++sg)
         if (off_blk[sg] != row_ptr[seg_row[sg]]) c->h_blk_pairs[off_blk[sg]] = pair_ptr[sg + 1] - pair_ptr[sg];
-    // records of each RCS row
-    std::vector<int32_t> rowobs_ptr(nr + 1, 0), rowobs;
-    for (int64_t k = 0; k < n_rec; ++k)
-        if (rrow[k] >= 0) rowobs_ptr[rrow[k] + 1]++;
-    for (int32_t r = 0; r < nr; ++r) rowobs_ptr[r + 1] += rowobs_ptr[r];
-    rowobs.resize(rowobs_ptr[nr]);
-    std::vector<int32_t> obs_rpos(n_rec, -1);   // position of each record in its row's list
-    {
-        std::vector<int32_t> fill(rowobs_ptr.begin(), rowobs_ptr.end() - 1);
-        for (int64_t k = 0; k < n_rec; ++k)
-            if (rrow[k] >= 0) {
-                const int32_t d = fill[rrow[k]]++;
-                rowobs[d] = (int32_t)k;
-                obs_rpos[k] = d;
-            }
-    }
     // both triangles by rows: the row's upper blocks S_rs (column s), then the
     // blocks (s, r), s < r, of its column, transposed (column s)
     std::vector<int32_t> sf_ptr(nr + 1, 0), sf_col, sf_src;
@@ -462,16 +547,11 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
         lo_ptr = std::move(tr_ptr);
         lo_blk = std::move(tr_blk);
     }
-    std::vector<int32_t> trip(2 * (size_t)ntr);
-    for (int64_t m = 0; m < ntr; ++m) { trip[2 * m] = ta[m]; trip[2 * m + 1] = tb[m]; }
-    std::vector<int32_t>().swap(ta);
-    std::vector<int32_t>().swap(tb);
+    ph.mark("sf/lo lists");
     std::vector<int32_t> row_ptr32(row_ptr.begin(), row_ptr.end());
     // device copies
     upload(c, &c->obs_cam, ocam);
-    upload(c, &c->obs_pt, opt);
     upload(c, &c->obs_row, orow);
-    upload(c, &c->obs_uv, ouv);
     upload(c, &c->chunk_q, chunk_q);
     upload(c, &c->chunk_ptr, chunk);
     upload(c, &c->long_ptr, long_ptr);
@@ -495,6 +575,7 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     upload(c, &c->lo_blk, lo_blk);
     if (shared) upload(c, &c->img_cam, c->h_img_cam);
     BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    ph.mark("uploads");
     c->h_row_ptr = std::move(row_ptr);
     c->h_col_idx = std::move(col_idx);
     c->h_perm = std::move(perm);
@@ -548,6 +629,29 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     for (auto& e : c->ev) BA_HIP_CHECK(hipEventCreate(&e));
     BA_HIP_CHECK(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
     if (const char* g = std::getenv("BA_PCG_GRAPHS")) c->use_graphs = std::atoi(g) != 0;
+    ph.mark("workspace");
+    // point ids and pixels in the internal order, gathered on the device
+    // (the permutation travels in the record buffer, written only later)
+    {
+        dalloc(c, &c->obs_pt, (size_t)n);
+        dalloc(c, &c->obs_uv, (size_t)n * 2);
+        std::vector<int32_t> perm32(n);
+        parallel_for(n, 1 << 18, [&](int64_t k0, int64_t k1, int) {
+            for (int64_t k = k0; k < k1; ++k) perm32[k] = (int32_t)c->h_perm[k];
+        });
+        int32_t* d_perm = (int32_t*)c->R;
+        BA_HIP_CHECK(hipMemcpyAsync(d_perm, perm32.data(), (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice,
+                                    c->stream));
+        unsigned long long* d_bad = reinterpret_cast<unsigned long long*>(c->part);
+        BA_HIP_CHECK(hipMemsetAsync(d_bad, 0xff, sizeof(unsigned long long), c->stream));
+        ba::launch_gather_obs(c, d_perm, d_pt, d_uv, d_bad);
+        unsigned long long bad = 0;
+        BA_HIP_CHECK(hipMemcpyAsync(&bad, d_bad, sizeof(bad), hipMemcpyDeviceToHost, c->stream));
+        BA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        if (bad < (unsigned long long)n)
+            throw ba_invalid{"obs_uv of observation " + std::to_string(bad) + " is not finite"};
+    }
+    ph.mark("gather");
 }
 
 template <typename F>
@@ -699,6 +803,7 @@ namespace ba {
 // then ascending, then i), the G slot of each member, the local tiles and
 // the gather lists of G (lower, per row) and G^T (upper, per row).
 void build_fsai(ba_ctx* c) {
+    Phases ph("build_fsai");
     const int32_t nr = c->n_rows;
     const std::vector<int64_t>& rp = c->h_row_ptr;
     const std::vector<int32_t>& ci = c->h_col_idx;
@@ -707,39 +812,53 @@ void build_fsai(ba_ctx* c) {
     for (int32_t r = 0; r < nr; ++r)
         for (int64_t kb = rp[r]; kb < rp[r + 1]; ++kb) brow[kb] = r;
     std::vector<int32_t> ptr, J, slot, tile;
+    ph.mark("rows");
     ba::gnn::fsai_sets(nr, rp.data(), ci.data(), cnt.data(), ptr, J, slot);
+    ph.mark("sets");
+    // local tiles of each set (rows in parallel): for members a >= b of
+    // J_i the block (J_b, J_a) (-2 on the diagonal, -1 if not stored)
     std::vector<int64_t> tptr(nr + 1, 0);
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> gu(nr);
     int32_t max_m = 1;
     for (int32_t i = 0; i < nr; ++i) {
         const int32_t m = ptr[i + 1] - ptr[i];
-        const int32_t* Jm = J.data() + ptr[i];
         max_m = std::max(max_m, m);
-        for (int32_t a = 0; a < m; ++a)
-            for (int32_t b = 0; b <= a; ++b) {
-                if (a == b) {
-                    tile.push_back(-2);
-                    continue;
-                }
-                const int32_t jb = Jm[b], ja = Jm[a];   // jb < ja: upper block (jb, ja)
-                auto first = ci.begin() + rp[jb] + 1, last = ci.begin() + rp[jb + 1];
-                auto it = std::lower_bound(first, last, ja);
-                tile.push_back(it != last && *it == ja ? (int32_t)(it - ci.begin()) : -1);
-            }
         tptr[i + 1] = tptr[i] + (int64_t)m * (m + 1) / 2;
-        for (int32_t b = 0; b < m; ++b) gu[Jm[b]].push_back({i, ptr[i] + b});
     }
-    // rows of G^T: row j lists (i, member b) for every set J_i containing j,
-    // in i order
-    std::vector<int32_t> gu_ptr(nr + 1, 0), gu_col, gu_pos(J.size());
-    for (int32_t j = 0; j < nr; ++j) gu_ptr[j + 1] = gu_ptr[j] + (int32_t)gu[j].size();
-    gu_col.resize(gu_ptr[nr]);
-    for (int32_t j = 0; j < nr; ++j)
-        for (size_t e = 0; e < gu[j].size(); ++e) {
-            const int32_t d = gu_ptr[j] + (int32_t)e;
-            gu_col[d] = gu[j][e].first;
-            gu_pos[gu[j][e].second] = d;
+    tile.resize(tptr[nr]);
+    ba::parallel_for(nr, 256, [&](int64_t i0, int64_t i1, int) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const int32_t m = ptr[i + 1] - ptr[i];
+            const int32_t* Jm = J.data() + ptr[i];
+            int64_t d = tptr[i];
+            for (int32_t a = 0; a < m; ++a)
+                for (int32_t b = 0; b <= a; ++b, ++d) {
+                    if (a == b) {
+                        tile[d] = -2;
+                        continue;
+                    }
+                    const int32_t jb = Jm[b], ja = Jm[a];   // jb < ja: upper block (jb, ja)
+                    auto first = ci.begin() + rp[jb] + 1, last = ci.begin() + rp[jb + 1];
+                    auto it = std::lower_bound(first, last, ja);
+                    tile[d] = it != last && *it == ja ? (int32_t)(it - ci.begin()) : -1;
+                }
         }
+    });
+    ph.mark("tiles");
+    // rows of G^T: row j lists (i, member) for every set J_i containing j, in
+    // i order (a stable counting sort of the members by J)
+    std::vector<int32_t> mem_row(J.size());
+    for (int32_t i = 0; i < nr; ++i)
+        for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e) mem_row[e] = i;
+    std::vector<int64_t> gp64;
+    std::vector<int32_t> gu_list;
+    ba::counting_sort((int64_t)J.size(), nr, [&](int64_t e) { return J[e]; }, gp64, gu_list);
+    std::vector<int32_t> gu_ptr(nr + 1, 0), gu_col(gu_list.size()), gu_pos(J.size());
+    for (int32_t j = 0; j <= nr; ++j) gu_ptr[j] = (int32_t)gp64[j];
+    for (size_t d = 0; d < gu_list.size(); ++d) {
+        gu_col[d] = mem_row[gu_list[d]];
+        gu_pos[gu_list[d]] = (int32_t)d;
+    }
+    ph.mark("transpose");
     Fsai& F = c->fs;
     upload(c, &F.ptr, ptr);
     upload(c, &F.J, J);
@@ -767,6 +886,7 @@ void build_fsai(ba_ctx* c) {
     dalloc(c, &F.An, (size_t)c->n_blk * 81);
     dalloc(c, &F.G, (size_t)c->n_blk * 81);
     BA_HIP_CHECK(hipMemsetAsync(F.G, 0, (size_t)c->n_blk * 81 * sizeof(float), c->stream));
+    ph.mark("upload+alloc");
     F.built = true;
 }
 
@@ -902,17 +1022,15 @@ ba_status ba_create(const ba_problem_desc* d, ba_ctx** out) {
         BA_HIP_CHECK(hipGetDevice(&c->device));
         const int64_t n = c->n_obs;
         std::vector<int32_t> cam(n), pt(n);
-        std::vector<double> uv(2 * n);
         std::vector<uint8_t> fixed;
         BA_HIP_CHECK(hipMemcpyAsync(cam.data(), d->obs_cam, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
         BA_HIP_CHECK(hipMemcpyAsync(pt.data(), d->obs_pt, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-        BA_HIP_CHECK(hipMemcpyAsync(uv.data(), d->obs_uv, 2 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         if (d->cam_fixed) {
             fixed.resize(c->n_cams);
             BA_HIP_CHECK(hipMemcpyAsync(fixed.data(), d->cam_fixed, c->n_cams, hipMemcpyDeviceToHost, c->stream));
         }
         BA_HIP_CHECK(hipStreamSynchronize(c->stream));
-        build(c, cam, pt, uv, fixed);
+        build(c, cam, pt, d->obs_pt, d->obs_uv, fixed);
         return BA_OK;
     });
     if (st != BA_OK) {
@@ -949,12 +1067,10 @@ ba_status ba_create_shared(const ba_shared_desc* d, ba_ctx** out) {
         BA_HIP_CHECK(hipGetDevice(&c->device));
         const int64_t n = c->n_obs;
         std::vector<int32_t> cam(n), pt(n);
-        std::vector<double> uv(2 * n);
         std::vector<uint8_t> fixed;
         c->h_img_cam.resize(c->n_cams);
         BA_HIP_CHECK(hipMemcpyAsync(cam.data(), d->obs_img, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
         BA_HIP_CHECK(hipMemcpyAsync(pt.data(), d->obs_pt, n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
-        BA_HIP_CHECK(hipMemcpyAsync(uv.data(), d->obs_uv, 2 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         BA_HIP_CHECK(hipMemcpyAsync(c->h_img_cam.data(), d->img_cam, c->n_cams * sizeof(int32_t),
                                     hipMemcpyDeviceToHost, c->stream));
         if (d->img_fixed) {
@@ -965,7 +1081,7 @@ ba_status ba_create_shared(const ba_shared_desc* d, ba_ctx** out) {
         for (int32_t i = 0; i < c->n_cams; ++i)
             if (c->h_img_cam[i] < 0 || c->h_img_cam[i] >= c->n_phys)
                 throw ba_invalid{"img_cam[" + std::to_string(i) + "] out of range"};
-        build(c, cam, pt, uv, fixed);
+        build(c, cam, pt, d->obs_pt, d->obs_uv, fixed);
         dalloc(c, &c->lin_params, n_params(c));
         dalloc(c, &c->lin_pts, (size_t)c->n_pts * 3);
         return BA_OK;

@@ -4,7 +4,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -16,6 +19,22 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kMaxTrack = 64;      // observations per point handled by one wave (longer tracks: one workgroup)
 constexpr int kPcgBatch = 16;      // PCG iterations per enqueued batch (one graph)
 constexpr int kRec = 24;           // per-observation record: J_c (18), then K = J_p L^-T (6)
+
+// Durations of the phases of a host build (ba_create, the FSAI index
+// structure) on stderr when BA_TIMING is set in the environment.
+struct Phases {
+    const char* label;
+    bool on = std::getenv("BA_TIMING") != nullptr;
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    explicit Phases(const char* l) : label(l) {}
+    void mark(const char* what) {
+        if (!on) return;
+        const auto now = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "%s %-14s %9.1f ms\n", label, what,
+                     std::chrono::duration<double, std::milli>(now - t).count());
+        t = now;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // device math
@@ -444,6 +463,8 @@ void launch_diag(ba_ctx* c, double lambda);
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp);
 // J_p of the current linearization into Jp if the fused stage left it out
 void ensure_jp(ba_ctx* c);
+void launch_gather_obs(ba_ctx* c, const int32_t* perm, const int32_t* pt_in, const double* uv_in,
+                       unsigned long long* bad);
 // |J dx|^2 and dx^T l into scal[2], scal[3] for a dx_p replaced after
 // back-substitution (which forms them for its own dx_p)
 void launch_model_terms(ba_ctx* c, const double* dxc, const double* dxp);

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "gnn.hpp"
+#include "host_par.hpp"
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -995,31 +996,44 @@ void backward(ba_gnn* net, Graph& g, float* grad, hipStream_t st, bool head = fa
 
 void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* blk_pairs,
                  hipStream_t st) {
-    struct Ed { int32_t s, d, b, t; };
-    std::vector<Ed> ed;
-    std::vector<int32_t> diag(n);
+    Phases ph("build_graph");
+    // directed edges by source, destinations ascending: for source r the
+    // blocks (s, r), s < r (t = 1: the block transposed), in ascending s,
+    // then the row's own upper blocks (r, s) (t = 0); the twin of an edge is
+    // the other direction through the same block
+    const int64_t nb = row_ptr[n];
+    std::vector<int32_t> diag(n), brow(nb);
     for (int r = 0; r < n; ++r) {
         diag[r] = (int32_t)row_ptr[r];
-        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
-            const int32_t s = col_idx[k];
-            if (s == r) continue;
-            ed.push_back({r, s, (int32_t)k, 0});
-            ed.push_back({s, r, (int32_t)k, 1});
+        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) brow[k] = r;
+    }
+    std::vector<int64_t> lptr;
+    std::vector<int32_t> lblk;   // blocks (s, r), s < r, of each column r, ascending s
+    counting_sort(nb, n, [&](int64_t k) { return k == row_ptr[brow[k]] ? -1 : col_idx[k]; }, lptr, lblk);
+    std::vector<int32_t> eptr(n + 1, 0);
+    for (int r = 0; r < n; ++r)
+        eptr[r + 1] = eptr[r] + (int32_t)(lptr[r + 1] - lptr[r]) + (int32_t)(row_ptr[r + 1] - row_ptr[r] - 1);
+    const int E = eptr[n];
+    std::vector<int32_t> src(E), dst(E), eb(E), et(E), twin(E), e_up(nb, -1), e_lo(nb, -1);
+    parallel_for(n, 256, [&](int64_t r0, int64_t r1, int) {
+        for (int64_t r = r0; r < r1; ++r) {
+            int32_t e = eptr[r];
+            for (int64_t i = lptr[r]; i < lptr[r + 1]; ++i, ++e) {
+                const int32_t k = lblk[i];
+                src[e] = (int32_t)r; dst[e] = brow[k]; eb[e] = k; et[e] = 1;
+                e_lo[k] = e;
+            }
+            for (int64_t k = row_ptr[r] + 1; k < row_ptr[r + 1]; ++k, ++e) {
+                src[e] = (int32_t)r; dst[e] = col_idx[k]; eb[e] = (int32_t)k; et[e] = 0;
+                e_up[k] = e;
+            }
         }
-    }
-    std::sort(ed.begin(), ed.end(), [](const Ed& a, const Ed& b) { return a.s != b.s ? a.s < b.s : a.d < b.d; });
-    const int E = (int)ed.size();
-    std::vector<int32_t> eptr(n + 1, 0), src(E), dst(E), eb(E), et(E), twin(E);
-    for (int e = 0; e < E; ++e) {
-        src[e] = ed[e].s; dst[e] = ed[e].d; eb[e] = ed[e].b; et[e] = ed[e].t;
-        eptr[ed[e].s + 1]++;
-    }
-    for (int r = 0; r < n; ++r) eptr[r + 1] += eptr[r];
-    for (int e = 0; e < E; ++e) {   // twin: the edge dst -> src, found in dst's sorted list
-        const int32_t a = dst[e], b = src[e];
-        const auto first = dst.begin() + eptr[a], last = dst.begin() + eptr[a + 1];
-        twin[e] = (int32_t)(std::lower_bound(first, last, b) - dst.begin());
-    }
+    });
+    ph.mark("edges");
+    parallel_for(E, 1 << 16, [&](int64_t e0, int64_t e1, int) {
+        for (int64_t e = e0; e < e1; ++e) twin[e] = et[e] ? e_up[eb[e]] : e_lo[eb[e]];
+    });
+    ph.mark("twins");
     g.n = n;
     g.E = E;
     auto up = [&](int32_t** p, const std::vector<int32_t>& h) {
@@ -1036,6 +1050,7 @@ void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx
     BA_HIP_CHECK(hipMalloc((void**)&g.flags, 4 * sizeof(int)));
     g.bytes += (size_t)n * (F_NODE * 2 + 81 * 8) + (size_t)E * (F_EDGE * 2 + 81 * 4);
     g.n_blk = (int)row_ptr[n];
+    ph.mark("upload+alloc");
     if (blk_pairs) {
         std::vector<int32_t> fptr, fJ, fslot;
         fsai_sets(n, row_ptr, col_idx, blk_pairs, fptr, fJ, fslot);
@@ -1045,23 +1060,37 @@ void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx
             return (it != last && *it == b) ? (int32_t)(it - dst.begin()) : -1;
         };
         const int fm = (int)fJ.size();
-        std::vector<int32_t> fedge(fm, -1), ftile, fsrc, fdst, fe, e2f(E, -1);
+        // per set J_i: its members' edges i -> j (all but i itself) and the
+        // local tile of edges (J_a -> J_b), filled rows in parallel at
+        // offsets fixed by the set sizes
         std::vector<int64_t> ftptr(n + 1, 0);
+        std::vector<int32_t> fsp(n + 1, 0);
         int max_m = 1;
         for (int i = 0; i < n; ++i) {
-            const int j0 = fptr[i], m = fptr[i + 1] - j0;
+            const int m = fptr[i + 1] - fptr[i];
             max_m = std::max(max_m, m);
-            for (int b = 0; b < m - 1; ++b) {
-                fedge[j0 + b] = edge(i, fJ[j0 + b]);
-                e2f[fedge[j0 + b]] = (int32_t)fsrc.size();
-                fsrc.push_back(i);
-                fdst.push_back(fJ[j0 + b]);
-                fe.push_back(fedge[j0 + b]);
-            }
-            for (int a = 0; a < m; ++a)
-                for (int b = 0; b <= a; ++b) ftile.push_back(a == b ? -2 : edge(fJ[j0 + a], fJ[j0 + b]));
+            fsp[i + 1] = fsp[i] + (m - 1);
             ftptr[i + 1] = ftptr[i] + (int64_t)m * (m + 1) / 2;
         }
+        const int fE0 = fsp[n];
+        std::vector<int32_t> fedge(fm, -1), ftile(ftptr[n]), fsrc(fE0), fdst(fE0), fe(fE0), e2f(E, -1);
+        parallel_for(n, 256, [&](int64_t i0, int64_t i1, int) {
+            for (int64_t i = i0; i < i1; ++i) {
+                const int j0 = fptr[i], m = fptr[i + 1] - j0;
+                for (int b = 0; b < m - 1; ++b) {
+                    const int32_t f = fsp[i] + b;
+                    fedge[j0 + b] = edge((int32_t)i, fJ[j0 + b]);
+                    e2f[fedge[j0 + b]] = f;
+                    fsrc[f] = (int32_t)i;
+                    fdst[f] = fJ[j0 + b];
+                    fe[f] = fedge[j0 + b];
+                }
+                int64_t d = ftptr[i];
+                for (int a = 0; a < m; ++a)
+                    for (int b = 0; b <= a; ++b, ++d) ftile[d] = a == b ? -2 : edge(fJ[j0 + a], fJ[j0 + b]);
+            }
+        });
+        ph.mark("fsai tiles");
         const int fE = (int)fsrc.size();
         std::vector<int32_t> fd_ptr(n + 1, 0), fd_list(fE);
         for (int f = 0; f < fE; ++f) fd_ptr[fdst[f] + 1]++;
@@ -1081,6 +1110,7 @@ void build_graph(Graph& g, int n, const int64_t* row_ptr, const int32_t* col_idx
         g.has_fsai = true;
     }
     BA_HIP_CHECK(hipStreamSynchronize(st));
+    ph.mark("fsai upload");
 }
 
 void free_graph(Graph& g) {

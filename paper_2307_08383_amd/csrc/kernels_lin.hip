@@ -101,6 +101,23 @@ __global__ __launch_bounds__(BS) void k_jp_from_K(int n_chunk, const int32_t* __
     }
 }
 
+// point ids and pixels of the caller's observations in the internal order
+// (perm: internal position -> caller's index); *bad = the lowest caller's
+// index whose pixel is not finite (unchanged if none)
+__global__ __launch_bounds__(BS) void k_gather_obs(int64_t n, const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ pt_in,
+                                                   const double* __restrict__ uv_in, int32_t* __restrict__ pt,
+                                                   double* __restrict__ uv, unsigned long long* __restrict__ bad) {
+    const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+    if (k >= n) return;
+    const int64_t s = perm[k];
+    const double u = uv_in[s], v = uv_in[n + s];
+    pt[k] = pt_in[s];
+    uv[k] = u;
+    uv[n + k] = v;
+    if (!isfinite(u) || !isfinite(v)) atomicMin(bad, (unsigned long long)s);
+}
+
 // the same for the tracks longer than a wave: one workgroup per point
 template <typename T>
 __global__ __launch_bounds__(BS) void k_jp_from_K_long(int q0, const int32_t* __restrict__ long_ptr,
@@ -186,6 +203,13 @@ void launch_evaluate(ba_ctx* c, const double* cams, const double* pts, const dou
     k_evaluate<<<nb, BS, 0, c->stream>>>(n, c->obs_cam, c->obs_pt, c->obs_row, c->obs_uv, cams, pts, dxc, dxp,
                                          c->part);
     launch_reduce(c, c->part, nb, 1, c->scal + 1);   // scal[1] F'
+}
+
+void launch_gather_obs(ba_ctx* c, const int32_t* perm, const int32_t* pt_in, const double* uv_in,
+                       unsigned long long* bad) {
+    const int64_t n = c->n_obs;
+    k_gather_obs<<<(unsigned)((n + BS - 1) / BS), BS, 0, c->stream>>>(n, perm, pt_in, uv_in, c->obs_pt, c->obs_uv, bad);
+    BA_HIP_CHECK(hipGetLastError());
 }
 
 void ensure_jp(ba_ctx* c) {
