@@ -1151,29 +1151,45 @@ void infer_factor(ba_gnn* net, Graph& g, const int32_t* gu_pos, float* Gl, float
 
 void fsai_sets(int n, const int64_t* row_ptr, const int32_t* col_idx, const int32_t* blk_pairs,
                std::vector<int32_t>& ptr, std::vector<int32_t>& J, std::vector<int32_t>& slot) {
-    std::vector<std::vector<std::pair<int32_t, int64_t>>> low(n);
-    for (int32_t r = 0; r < n; ++r)
-        for (int64_t kb = row_ptr[r] + 1; kb < row_ptr[r + 1]; ++kb) low[col_idx[kb]].push_back({r, kb});
+    // blocks (r, i), r < i, of each column i in ascending r
+    const int64_t nb = row_ptr[n];
+    std::vector<int32_t> brow(nb);
+    parallel_for(n, 256, [&](int64_t r0, int64_t r1, int) {
+        for (int64_t r = r0; r < r1; ++r)
+            for (int64_t kb = row_ptr[r]; kb < row_ptr[r + 1]; ++kb) brow[kb] = (int32_t)r;
+    });
+    std::vector<int64_t> lptr;
+    std::vector<int32_t> lblk;
+    counting_sort(nb, n, [&](int64_t kb) { return kb == row_ptr[brow[kb]] ? -1 : col_idx[kb]; }, lptr, lblk);
     ptr.assign(n + 1, 0);
-    J.clear();
-    slot.clear();
-    for (int32_t i = 0; i < n; ++i) {
-        auto& L = low[i];
-        std::sort(L.begin(), L.end(), [&](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) {
-            const int32_t cx = blk_pairs[x.second], cy = blk_pairs[y.second];
-            return cx != cy ? cx > cy : x.first < y.first;
-        });
-        if ((int)L.size() > kFsaiM - 1) L.resize(kFsaiM - 1);
-        std::sort(L.begin(), L.end());
-        for (auto& e : L) {
-            J.push_back(e.first);
-            slot.push_back((int32_t)e.second);
+    for (int i = 0; i < n; ++i)
+        ptr[i + 1] = ptr[i] + (int32_t)std::min<int64_t>(lptr[i + 1] - lptr[i], kFsaiM - 1) + 1;
+    J.resize(ptr[n]);
+    slot.resize(ptr[n]);
+    // per row (in parallel): the kFsaiM - 1 lower neighbours with the most
+    // common points (ties to the lower row), in ascending order, then i
+    parallel_for(n, 256, [&](int64_t i0, int64_t i1, int) {
+        std::vector<std::pair<int32_t, int64_t>> L;
+        for (int64_t i = i0; i < i1; ++i) {
+            L.clear();
+            for (int64_t t = lptr[i]; t < lptr[i + 1]; ++t) L.push_back({brow[lblk[t]], lblk[t]});
+            std::sort(L.begin(), L.end(), [&](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) {
+                const int32_t cx = blk_pairs[x.second], cy = blk_pairs[y.second];
+                return cx != cy ? cx > cy : x.first < y.first;
+            });
+            if ((int)L.size() > kFsaiM - 1) L.resize(kFsaiM - 1);
+            std::sort(L.begin(), L.end());
+            int32_t d = ptr[i];
+            for (auto& e : L) {
+                J[d] = e.first;
+                slot[d++] = (int32_t)e.second;
+            }
+            J[d] = (int32_t)i;
+            slot[d] = (int32_t)row_ptr[i];
         }
-        J.push_back(i);
-        slot.push_back((int32_t)row_ptr[i]);
-        ptr[i + 1] = (int32_t)J.size();
-    }
+    });
 }
+
 
 void free_work(Work& W) {
     void* p[] = {W.H0, W.Hf, W.G, W.O, W.Z, W.Y, W.Hb, W.Gb, W.Xm, W.Xu, W.Mm, W.T, W.dO, W.dH, W.dT, W.dXu,

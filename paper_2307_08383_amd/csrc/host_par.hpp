@@ -62,9 +62,11 @@ void parallel_for(int64_t n, int64_t grain, F&& f) {
     if (err) std::rethrow_exception(err);
 }
 
-// Stable counting sort of [0, n) by key(i) in [0, n_keys): out[ptr[key] ..]
-// lists the i of each key in ascending order; ptr has n_keys + 1 entries.
-// Threads take contiguous ranges of i and count per key first.
+// Stable counting sort of [0, n) by key(i) in [0, n_keys) (a negative key
+// drops i): out[ptr[key] ..] lists the i of each key in ascending order; ptr
+// has n_keys + 1 entries.  Threads take contiguous ranges of i and count per
+// key first, with n_keys counters each (meant for key ranges up to a few
+// million).
 template <typename K, typename O>
 void counting_sort(int64_t n, int32_t n_keys, K&& key, std::vector<int64_t>& ptr, std::vector<O>& out) {
     const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(host_threads(), n / (1 << 16)));
