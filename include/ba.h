@@ -88,7 +88,9 @@ typedef struct ba_problem_desc {
  * Tracks of up to 64 observations are handled one wave per chunk of tracks,
  * longer ones one workgroup per point, with the same results to rounding.
  * The context copies the observations (the caller may free them on return)
- * and owns all workspace.
+ * and owns all workspace.  The host part of the build runs on up to 16
+ * threads (BA_THREADS in the environment sets the count; the result does not
+ * depend on it); BA_TIMING=1 prints the duration of each phase to stderr.
  * Errors: BA_ERR_INVALID_ARG, BA_ERR_OUT_OF_MEMORY, BA_ERR_DEVICE; *out is
  * NULL on error and the message is available from ba_last_error(NULL). */
 ba_status ba_create(const ba_problem_desc* desc, ba_ctx** out);
