@@ -596,8 +596,9 @@ void build(ba_ctx* c, const std::vector<int32_t>& cam, const std::vector<int32_t
     dalloc(c, &c->dxc, (size_t)nr * 9);
     dalloc(c, &c->dxp, (size_t)np * 3);
     // per-block partials of up to three sums: grids of one block per 256
-    // observations, or per 4 chunks (chunk-based kernels)
-    c->n_part = (int32_t)(3 * std::max<int64_t>((n + 255) / 256, ((int64_t)c->n_chunk + 3) / 4 + c->n_long) + 8);
+    // observations, or per chunk at most (chunk-based kernels), plus one per
+    // long track
+    c->n_part = (int32_t)(3 * std::max<int64_t>((n + 255) / 256, (int64_t)c->n_chunk + c->n_long) + 8);
     dalloc(c, &c->part, (size_t)c->n_part);
     dalloc(c, &c->part2, (size_t)3 * ba::kReduceParts);
     dalloc(c, &c->scal, 16);

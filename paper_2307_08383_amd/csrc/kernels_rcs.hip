@@ -166,7 +166,13 @@ __device__ __forceinline__ void wave_copy_out(char* __restrict__ dst, const char
 // is K L^T wherever it is needed.  The track sums go through LDS as in
 // k_point, and the records are written whole through LDS (below).
 // ---------------------------------------------------------------------------
-template <typename T>
+// Waves per workgroup of the fused stage: one, so that its barriers hold a
+// single wave (on the 60,000-camera partition, FP64, measured against four
+// waves on the same GPU: 7.01 against 7.29 ms, and 7.82 against 7.97 ms on
+// another; two waves 7.09 ms).
+constexpr int kLinNW = 1;
+
+template <typename T, int NW>
 __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
                                                  const int32_t* __restrict__ obs_cam,
                                                  const int32_t* __restrict__ obs_pt,
@@ -176,10 +182,10 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
                                                  double* __restrict__ e, double* __restrict__ ptL,
                                                  const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
-    __shared__ __align__(16) double sP[WPB][kWave][kPT];   // track sums, the head's point terms, then staging
-    __shared__ double sh[WPB];
+    __shared__ __align__(16) double sP[NW][kWave][kPT];   // track sums, the head's point terms, then staging
+    __shared__ double sh[NW];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int chunk = blockIdx.x * WPB + wv;
+    const int chunk = blockIdx.x * NW + wv;
     int k0 = 0, k1 = 0;
     if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
     const int k = k0 + lane;
@@ -213,7 +219,7 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
         sP[wv][lane][7] = -(jp[1] * eu + jp[4] * ev);
         sP[wv][lane][8] = -(jp[2] * eu + jp[5] * ev);
     }
-    const double csum = block_sum<BS>(cost, sh);   // contains the barrier for sP
+    const double csum = block_sum<NW * kWave>(cost, sh);   // contains the barrier for sP
     if (threadIdx.x == 0) part[blockIdx.x] = csum;
     if (act && head == lane) {
         double s[9];
@@ -262,7 +268,7 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
 
 // FP32 records: 96 registers allow five waves per SIMD without spilling;
 // the FP64 build keeps the default (it would spill).
-__global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(5))) void k_linpoint_f(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
+__global__ __launch_bounds__(kLinNW * kWave) __attribute__((amdgpu_waves_per_eu(5))) void k_linpoint_f(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
                                                  const int32_t* __restrict__ obs_cam,
                                                  const int32_t* __restrict__ obs_pt,
                                                  const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
@@ -271,9 +277,9 @@ __global__ __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(5))) void k_
                                                  double* __restrict__ e, double* __restrict__ ptL,
                                                  const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
-    linpoint<float>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, e, ptL, obs_rpos, ebar, part, flags);
+    linpoint<float, kLinNW>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, e, ptL, obs_rpos, ebar, part, flags);
 }
-__global__ __launch_bounds__(BS) void k_linpoint_d(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
+__global__ __launch_bounds__(kLinNW * kWave) void k_linpoint_d(int n_chunk, const int32_t* __restrict__ chunk_ptr, int n,
                                                  const int32_t* __restrict__ obs_cam,
                                                  const int32_t* __restrict__ obs_pt,
                                                  const int32_t* __restrict__ chunk_q, const double* __restrict__ uv,
@@ -282,7 +288,7 @@ __global__ __launch_bounds__(BS) void k_linpoint_d(int n_chunk, const int32_t* _
                                                  double* __restrict__ e, double* __restrict__ ptL,
                                                  const int32_t* __restrict__ obs_rpos, double* __restrict__ ebar,
                                                  double* __restrict__ part, int* __restrict__ flags) {
-    linpoint<double>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, e, ptL, obs_rpos, ebar, part, flags);
+    linpoint<double, kLinNW>(n_chunk, chunk_ptr, n, obs_cam, obs_pt, chunk_q, uv, cams, pts, lambda, R, e, ptL, obs_rpos, ebar, part, flags);
 }
 
 // ---------------------------------------------------------------------------
@@ -562,17 +568,21 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
 // chunk of whole tracks, one lane per observation; per-block partials of the
 // two model terms.
 // ---------------------------------------------------------------------------
+// four waves per workgroup (on the 60,000-camera partition, FP64: 6.40 ms
+// against 6.46 with two and 6.50 with one)
+constexpr int kBackNW = 4;
+
 template <typename T>
-__global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __restrict__ chunk_ptr,
+__global__ __launch_bounds__(kBackNW * kWave) void k_backsub(int n_chunk, const int32_t* __restrict__ chunk_ptr,
                                                 const int32_t* __restrict__ obs_pt, const int32_t* __restrict__ obs_row,
                                                 const int32_t* __restrict__ chunk_q, const T* __restrict__ R,
                                                 const double* __restrict__ ptL, const double* __restrict__ dxc,
                                                 const double* __restrict__ e, double* __restrict__ dxp,
                                                 double* __restrict__ part, int nb) {
-    __shared__ double sP[WPB][kWave][3];
-    __shared__ double sh[WPB];
+    __shared__ double sP[kBackNW][kWave][3];
+    __shared__ double sh[kBackNW];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int chunk = blockIdx.x * WPB + wv;
+    const int chunk = blockIdx.x * kBackNW + wv;
     int k0 = 0, k1 = 0;
     if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
     const int k = k0 + lane;
@@ -627,8 +637,8 @@ __global__ __launch_bounds__(BS) void k_backsub(int n_chunk, const int32_t* __re
         jdx2 = a0 * a0 + a1 * a1;
         dxl = -(a0 * ek.x + a1 * ek.y);
     }
-    const double s0 = block_sum<BS>(jdx2, sh);
-    const double s1 = block_sum<BS>(dxl, sh);
+    const double s0 = block_sum<kBackNW * kWave>(jdx2, sh);
+    const double s1 = block_sum<kBackNW * kWave>(dxl, sh);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = s0;
         part[nb + blockIdx.x] = s1;
@@ -957,17 +967,17 @@ void launch_point(ba_ctx* c, double lambda) {
 }
 
 void launch_linearize_point(ba_ctx* c, const double* cams, const double* pts, double lambda) {
-    const int nb = (c->n_chunk + WPB - 1) / WPB;
+    const int nb = (c->n_chunk + kLinNW - 1) / kLinNW;
     const int n = (int)c->n_obs;
     if (nb + (int64_t)c->n_long > c->n_part)
         throw ba_hip_error(hipErrorInvalidValue, "cost partials exceed their buffer", __FILE__, __LINE__);
     if (nb > 0) {
         if (c->precision == BA_MIXED)
-            k_linpoint_f<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
+            k_linpoint_f<<<nb, kLinNW * kWave, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
                                                    c->obs_uv, cams, pts, lambda, (float*)c->R, c->e, c->ptL,
                                                    c->obs_rpos, c->ebar, c->part, c->flags);
         else
-            k_linpoint_d<<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
+            k_linpoint_d<<<nb, kLinNW * kWave, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, n, c->obs_cam, c->obs_pt, c->chunk_q,
                                                    c->obs_uv, cams, pts, lambda, (double*)c->R, c->e, c->ptL,
                                                    c->obs_rpos, c->ebar, c->part, c->flags);
     }
@@ -1028,7 +1038,7 @@ template <typename T>
 void launch_back_substitute_t(ba_ctx* c, const double* dxc, double* dxp, int nb, int stride) {
     const T* R = (const T*)c->R;
     if (nb > 0)
-        k_backsub<T><<<nb, BS, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q, R, c->ptL,
+        k_backsub<T><<<nb, kBackNW * kWave, 0, c->stream>>>(c->n_chunk, c->chunk_ptr, c->obs_pt, c->obs_row, c->chunk_q, R, c->ptL,
                                                dxc, c->e, dxp, c->part, stride);
     if (c->n_long > 0)
         k_backsub_long<T><<<c->n_long, BS, 0, c->stream>>>(c->q_long0, c->long_ptr, c->obs_pt, c->obs_row, R, c->ptL,
@@ -1036,7 +1046,7 @@ void launch_back_substitute_t(ba_ctx* c, const double* dxc, double* dxp, int nb,
 }
 
 void launch_back_substitute(ba_ctx* c, const double* dxc, double* dxp) {
-    const int nb = (c->n_chunk + WPB - 1) / WPB;
+    const int nb = (c->n_chunk + kBackNW - 1) / kBackNW;
     const int stride = nb + c->n_long;
     if (stride == 0) return;
     if (2 * (int64_t)stride > c->n_part)
