@@ -830,7 +830,7 @@ template <bool TR, typename TS>
 __device__ __forceinline__ double row_upper(int row, int start, int n, const int32_t* __restrict__ col,
                                             const TS* __restrict__ blk, const double* __restrict__ z,
                                             double* __restrict__ tb) {
-    constexpr int U = sizeof(TS) == 8 ? 2 : 4;   // blocks in flight per group (144 bytes per lane)
+    constexpr int U = sizeof(TS) == 8 ? 1 : 4;   // blocks in flight per group (72 or 144 bytes per lane)
     const int lane = threadIdx.x % kWave;
     const int grp = lane / 9, comp = lane % 9;
     double zr[9], acc[9];
