@@ -224,6 +224,14 @@ __device__ __forceinline__ Track chunk_track(bool act, int p, int lane, int len)
     return t;
 }
 
+// Block index in XCD-contiguous order: the blocks that run on one XCD
+// (hardware block id mod 8) take one contiguous range of indices, so the
+// lines that neighbouring blocks share stay in that XCD's L2.
+__device__ __forceinline__ int xcd_block() {
+    const int nb = gridDim.x, x = blockIdx.x % 8, per = nb / 8, extra = nb % 8;
+    return x * per + min(x, extra) + blockIdx.x / 8;
+}
+
 // Deterministic block sum (fixed shuffle tree, then fixed LDS order); the
 // result is valid in thread 0.
 template <int BS>

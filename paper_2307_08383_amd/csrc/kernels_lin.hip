@@ -57,7 +57,7 @@ __global__ __launch_bounds__(BS) void k_evaluate(int n, const int32_t* __restric
                                                  const double* __restrict__ dxc, const double* __restrict__ dxp,
                                                  double* __restrict__ part) {
     __shared__ double sh[BS / kWave];
-    const int k = blockIdx.x * BS + threadIdx.x;
+    const int k = xcd_block() * BS + threadIdx.x;
     double cost = 0.0;
     if (k < n) {
         const int row = obs_row[k];

@@ -169,7 +169,9 @@ __device__ __forceinline__ void wave_copy_out(char* __restrict__ dst, const char
 // Waves per workgroup of the fused stage: one, so that its barriers hold a
 // single wave (on the 60,000-camera partition, FP64, measured against four
 // waves on the same GPU: 7.01 against 7.29 ms, and 7.82 against 7.97 ms on
-// another; two waves 7.09 ms).
+// another; two waves 7.09 ms).  Its chunks go to the XCDs in contiguous
+// ranges (7.56 against 7.80 ms): a chunk boundary splits lines of the
+// observation arrays, which the neighbouring chunk then finds in L2.
 constexpr int kLinNW = 1;
 
 template <typename T, int NW>
@@ -185,7 +187,7 @@ __device__ __forceinline__ void linpoint(int n_chunk, const int32_t* __restrict_
     __shared__ __align__(16) double sP[NW][kWave][kPT];   // track sums, the head's point terms, then staging
     __shared__ double sh[NW];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int chunk = blockIdx.x * NW + wv;
+    const int chunk = xcd_block() * NW + wv;   // neighbouring chunks on one XCD
     int k0 = 0, k1 = 0;
     if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
     const int k = k0 + lane;
@@ -569,7 +571,8 @@ __global__ __launch_bounds__(BS) void k_diag(int n_rows, const int32_t* __restri
 // two model terms.
 // ---------------------------------------------------------------------------
 // four waves per workgroup (on the 60,000-camera partition, FP64: 6.40 ms
-// against 6.46 with two and 6.50 with one)
+// against 6.46 with two and 6.50 with one), blocks in XCD-contiguous order
+// (6.31 against 6.39 ms)
 constexpr int kBackNW = 4;
 
 template <typename T>
@@ -582,7 +585,7 @@ __global__ __launch_bounds__(kBackNW * kWave) void k_backsub(int n_chunk, const 
     __shared__ double sP[kBackNW][kWave][3];
     __shared__ double sh[kBackNW];
     const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int chunk = blockIdx.x * kBackNW + wv;
+    const int chunk = xcd_block() * kBackNW + wv;
     int k0 = 0, k1 = 0;
     if (chunk < n_chunk) { k0 = chunk_ptr[chunk]; k1 = chunk_ptr[chunk + 1]; }
     const int k = k0 + lane;
