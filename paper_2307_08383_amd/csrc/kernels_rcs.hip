@@ -316,8 +316,11 @@ constexpr int kPairWave = 4;   // units (camera pairs or chunks) per wave
 
 struct XcdRanges { int wv[9]; };
 
+// Three waves per SIMD: the FP64 instance's two 6 KB LDS buffers allow no
+// more (12 per CU), and asking for four made the compiler spill to fit 128
+// registers (12.26 against 12.14 ms on the 60,000-camera partition).
 template <typename T, bool SUB = false>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_offdiag(
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(3))) void k_offdiag(
     int n_unit, XcdRanges xr, const int32_t* __restrict__ unit_rng, const int32_t* __restrict__ unit_dst,
     const int32_t* __restrict__ trip, const T* __restrict__ R, double* __restrict__ blk, double* __restrict__ pblk) {
     constexpr int kVal = 16 / sizeof(T);                             // values per 16-byte chunk
