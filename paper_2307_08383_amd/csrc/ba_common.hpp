@@ -200,9 +200,32 @@ __device__ __forceinline__ void jp_from_K(const double* K, const double* L, doub
     }
 }
 
+// v from another lane by a DPP lane pattern (CTRL), both halves of the double
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// v from lane ^ 16 (swizzle, bit mode, inside each 32 lanes)
+__device__ __forceinline__ double swz_xor16(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)b, 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(b >> 32), 0x401F);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// Sum over the wave, the same value in every lane: each step adds the value
+// of a partner lane (the pairing is symmetric, so both partners form the same
+// sum): lane ^ 1 and lane ^ 2 (quad permutes), the mirrored lane within 8 and
+// within 16 (DPP), lane ^ 16 (swizzle), lane ^ 32.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    v += dpp_mov<0xB1>(v);
+    v += dpp_mov<0x4E>(v);
+    v += dpp_mov<0x141>(v);
+    v += dpp_mov<0x140>(v);
+    v += swz_xor16(v);
+    v += __shfl_xor(v, 32, kWave);
     return v;
 }
 
