@@ -749,7 +749,7 @@ void prepare_learned_fsai(ba_ctx* c) {
     if (c->fs.half) ba::launch_dscale(c);
     ba::gnn::infer_factor(c->net, *g, c->upper ? c->fs.gl_self : c->fs.gu_pos, c->upper ? nullptr : c->fs.Gl,
                           c->upper ? nullptr : c->fs.Gu, c->fs.G, c->stream, c->fs.half ? c->fs.Dn : nullptr,
-                          c->fs.half ? c->fs.Gh : nullptr, c->fs.hs);
+                          c->fs.half ? c->fs.Gh : nullptr, c->fs.half ? c->fs.Gh8 : nullptr, c->fs.hs);
     c->fs.gu_upper = c->upper;
     c->fs.ready = false;   // the layouts now hold the network's factor
 }
@@ -881,7 +881,9 @@ void build_fsai(ba_ctx* c) {
     dalloc(c, &F.Gl, J.size() * 81);
     dalloc(c, &F.Gu, J.size() * 81);
     dalloc(c, &F.tg, J.size() * 9);
-    dalloc(c, &F.Gh, J.size() * 45);
+    // 36 words of groups per member, then the row-8 halves (9 per member)
+    dalloc(c, &F.Gh, J.size() * 36 + (J.size() * 9 + 1) / 2);
+    F.Gh8 = reinterpret_cast<uint16_t*>(F.Gh + J.size() * 36);
     dalloc(c, &F.hs, J.size());
     dalloc(c, &F.Dn, (size_t)nr * 9);
     dalloc(c, &F.An, (size_t)c->n_blk * 81);

@@ -340,9 +340,12 @@ struct Fsai {
     double* tg = nullptr;             // [entries][9] G_ij^T t_i per entry of Gl (UPPER apply of G^T)
     // half-precision copy for the UPPER apply: member e (G_e = G_{i,j},
     // j = J[e]) as Gh_e = G_e D_j^-1 / hs[e] in FP16, D_j = diag(S_jj)^-1/2
-    // (Dn [n_rows][9]), hs[e] = max |G_e D_j^-1|; each column of G_e takes
-    // 10 halves (the last one padding): 45 words per member
+    // (Dn [n_rows][9]), hs[e] = max |G_e D_j^-1|; rows 0..7 of column c of
+    // G_e as eight halves in one 16-byte group (Gh[e * 36 + 4 c ..], 144
+    // bytes per member), row 8 in Gh8[e * 9 + c] (the array after the groups
+    // of all members)
     uint32_t* Gh = nullptr;
+    uint16_t* Gh8 = nullptr;
     float* hs = nullptr;
     double* Dn = nullptr;
     int half = 0;                     // the layouts hold a packed copy of the current factor

@@ -723,7 +723,8 @@ __global__ __launch_bounds__(BS) void k_fscatter_g(int E, const int32_t* __restr
 // transposed block at gu_pos), Gs (the block slots); with Gh, instead of
 // Gu, the UPPER apply's FP16 copy: each transposed block with its rows
 // (the columns of G_ij) divided by Dn of the member's column block, scaled
-// by its largest magnitude (hs), two halves per word, 10 halves per row.
+// by its largest magnitude (hs); elements 0..7 of a row as halves in one
+// 16-byte group (Gh, 36 words per member), element 8 in Gh8.
 __global__ __launch_bounds__(BS) void k_fassemble(const int32_t* __restrict__ fptr, const int32_t* __restrict__ fJ,
                                                   const int32_t* __restrict__ fedge, const int32_t* __restrict__ fslot,
                                                   const float* __restrict__ O, const float* __restrict__ OE,
@@ -731,7 +732,7 @@ __global__ __launch_bounds__(BS) void k_fassemble(const int32_t* __restrict__ fp
                                                   const double* __restrict__ Linv, const int32_t* __restrict__ gu_pos,
                                                   float* __restrict__ Gl, float* __restrict__ Gu, float* __restrict__ Gs,
                                                   const double* __restrict__ Dn, uint32_t* __restrict__ Gh,
-                                                  float* __restrict__ hs) {
+                                                  uint16_t* __restrict__ Gh8, float* __restrict__ hs) {
     __shared__ float gh[kFsaiM][81];
     __shared__ float gv[kFsaiM][81];
     __shared__ float smax[kFsaiM];
@@ -765,13 +766,17 @@ __global__ __launch_bounds__(BS) void k_fassemble(const int32_t* __restrict__ fp
         if (lane == 0) smax[b] = mx > 0.f && mx <= 3.0e38f ? mx : 1.f;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < m * 45; e += BS) {
-        const int b = e / 45, w = e % 45, c = w / 5, a = 2 * (w % 5);
+    for (int e = threadIdx.x; e < m * 36; e += BS) {
+        const int b = e / 36, w = e % 36, c = w / 4, a = 2 * (w % 4);
         const float sc = smax[b];
         const _Float16 lo = (_Float16)(gv[b][c * 9 + a] / sc);
-        const _Float16 hi = (_Float16)(a < 8 ? gv[b][c * 9 + a + 1] / sc : 0.f);
-        Gh[(int64_t)(j0 + b) * 45 + w] =
+        const _Float16 hi = (_Float16)(gv[b][c * 9 + a + 1] / sc);
+        Gh[(int64_t)(j0 + b) * 36 + w] =
             (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+    }
+    for (int e = threadIdx.x; e < m * 9; e += BS) {
+        const int b = e / 9, c = e % 9;
+        Gh8[(int64_t)(j0 + b) * 9 + c] = __builtin_bit_cast(uint16_t, (_Float16)(gv[b][c * 9 + 8] / smax[b]));
     }
     for (int b = threadIdx.x; b < m; b += BS) hs[j0 + b] = smax[b];
 }
@@ -1138,14 +1143,14 @@ void infer_preconditioner(ba_gnn* net, Graph& g, const double* Minv, double* P, 
 }
 
 void infer_factor(ba_gnn* net, Graph& g, const int32_t* gu_pos, float* Gl, float* Gu, float* Gslots, hipStream_t st,
-                  const double* Dn, uint32_t* Gh, float* hs) {
+                  const double* Dn, uint32_t* Gh, uint16_t* Gh8, float* hs) {
     ensure_work(net->work, g.n, g.E, 1);
     ensure_fwork(net->work, g);
     forward(net, g, st, false);
     head_forward(net, g, st, false);
     if (g.fm > 0 && g.n > 0)
         k_fassemble<<<g.n, BS, 0, st>>>(g.fptr, g.fJ, g.fedge, g.fslot, net->work.O, net->work.OE, net->w + OFF_AO,
-                                        g.A, g.Linv, gu_pos, Gl, Gu, Gslots, Dn, Gh, hs);
+                                        g.A, g.Linv, gu_pos, Gl, Gu, Gslots, Dn, Gh, Gh8, hs);
     BA_HIP_CHECK(hipGetLastError());
 }
 

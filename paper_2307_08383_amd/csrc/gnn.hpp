@@ -105,9 +105,10 @@ void infer_preconditioner(ba_gnn* net, Graph& g, const double* Minv, double* P, 
 // factorised head: G of the graph's FSAI sets into the layouts of the
 // library's FSAI (Gl by member, Gu at gu_pos, G at the block slots; any may
 // be null)
-// with Gh (and hs, Dn): the FP16 copy of the UPPER apply instead of Gu
+// with Gh (and Gh8, hs, Dn): the FP16 copy of the UPPER apply instead of Gu
 void infer_factor(ba_gnn* net, Graph& g, const int32_t* gu_pos, float* Gl, float* Gu, float* Gslots, hipStream_t st,
-                  const double* Dn = nullptr, uint32_t* Gh = nullptr, float* hs = nullptr);
+                  const double* Dn = nullptr, uint32_t* Gh = nullptr, uint16_t* Gh8 = nullptr,
+                  float* hs = nullptr);
 // the FSAI sets of a pattern (shared with the library's FSAI): per row, its
 // lower neighbours with the most common points (at most kFsaiM - 1, ties to
 // the lower index), ascending, then the row

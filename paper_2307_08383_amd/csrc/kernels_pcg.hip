@@ -154,24 +154,24 @@ __device__ __forceinline__ void load_col9(const TS* __restrict__ b, int c, TS* v
     }
 }
 
-// Half-precision factor blocks (see Fsai::Gh): column c of member e is
-// words e * 45 + 5 c .. + 4, two halves per word, scaled back by hs[e].
-constexpr int kHW = 45;
+// Half-precision factor blocks (see Fsai::Gh): rows 0..7 of column c of
+// member e are the 16 bytes at word e * 36 + 4 c (two halves per word), row 8
+// is Gh8[e * 9 + c]; all scaled back by hs[e].
+constexpr int kHW = 36;
 __device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)); }
 __device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
-__device__ __forceinline__ void load_colh(const uint32_t* __restrict__ Gh, const float* __restrict__ hs, int64_t e,
-                                          int c, float* v) {
-    const uint32_t* w = Gh + e * kHW + c * 5;
+__device__ __forceinline__ void load_colh(const uint32_t* __restrict__ Gh, const uint16_t* __restrict__ Gh8,
+                                          const float* __restrict__ hs, int64_t e, int c, float* v) {
+    const uint4 a = *reinterpret_cast<const uint4*>(Gh + e * kHW + c * 4);
+    const uint16_t r8 = Gh8[e * 9 + c];
     const float s = hs[e];
-    uint32_t a[5];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) a[k] = w[k];
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        v[2 * k] = s * half_lo(a[k]);
-        v[2 * k + 1] = s * half_hi(a[k]);
+        v[2 * k] = s * half_lo(w[k]);
+        v[2 * k + 1] = s * half_hi(w[k]);
     }
-    v[8] = s * half_lo(a[4]);
+    v[8] = s * (float)__builtin_bit_cast(_Float16, r8);
 }
 
 // Row gather by one wave over a block-CSR row (entries start..start+n-1,
@@ -492,7 +492,8 @@ __global__ __launch_bounds__(BS) void k_dscale(int n_rows, const int32_t* __rest
 // workgroup
 __global__ __launch_bounds__(BS) void k_pack_half(int64_t n_mem, const int32_t* __restrict__ J,
                                                   const float* __restrict__ GuT, const double* __restrict__ Dn,
-                                                  uint32_t* __restrict__ Gh, float* __restrict__ hs) {
+                                                  uint32_t* __restrict__ Gh, uint16_t* __restrict__ Gh8,
+                                                  float* __restrict__ hs) {
     __shared__ float sv[3][81];
     __shared__ float smax[3];
     const int t = threadIdx.x, m = t / 81, v = t % 81;
@@ -509,12 +510,13 @@ __global__ __launch_bounds__(BS) void k_pack_half(int64_t n_mem, const int32_t* 
     if (act) {
         const float s = smax[m];
         const int b = v / 9, a = v % 9;
-        if (a % 2 == 0) {
+        if (a < 8 && a % 2 == 0) {
             const _Float16 lo = (_Float16)(sv[m][v] / s);
-            const _Float16 hi = (_Float16)(a < 8 ? sv[m][v + 1] / s : 0.f);
-            Gh[e * kHW + b * 5 + a / 2] = (uint32_t)__builtin_bit_cast(uint16_t, lo) |
+            const _Float16 hi = (_Float16)(sv[m][v + 1] / s);
+            Gh[e * kHW + b * 4 + a / 2] = (uint32_t)__builtin_bit_cast(uint16_t, lo) |
                                           ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
         }
+        if (a == 8) Gh8[e * 9 + b] = __builtin_bit_cast(uint16_t, (_Float16)(sv[m][v] / s));
         if (v == 0) hs[e] = s;
     }
 }
@@ -624,6 +626,7 @@ __device__ __forceinline__ double row_factor_t(int start, int n, const int32_t* 
                                                const float* __restrict__ blkT, const double* __restrict__ v0,
                                                const double* __restrict__ v1, double alpha,
                                                double* __restrict__ tg, const uint32_t* __restrict__ Gh = nullptr,
+                                               const uint16_t* __restrict__ Gh8 = nullptr,
                                                const float* __restrict__ hs = nullptr,
                                                const double* __restrict__ Dn = nullptr) {
     constexpr int U = 4;
@@ -642,7 +645,7 @@ __device__ __forceinline__ double row_factor_t(int start, int n, const int32_t* 
                 const int e = e0 + u * GRPW;
                 const int ee = start + (e < n ? e : e0);
                 const int cj = col[ee];
-                if (H) load_colh(Gh, hs, ee, comp, bv[u]);
+                if (H) load_colh(Gh, Gh8, hs, ee, comp, bv[u]);
                 else load_col9<true>(blkT + (int64_t)ee * 81, comp, bv[u]);
                 x[u] = v0[(int64_t)cj * 9 + comp];
                 if (VM == 1) x[u] -= alpha * v1[(int64_t)cj * 9 + comp];
@@ -669,7 +672,7 @@ __device__ __forceinline__ double row_factor_t(int start, int n, const int32_t* 
                 for (int u = 0; u < U; ++u) {
                     const int e = e0 + u * GRPW;
                     const int64_t ee = start + (e < n ? e : e0);
-                    if (H) load_colh(Gh, hs, ee, comp, bv[u]);
+                    if (H) load_colh(Gh, Gh8, hs, ee, comp, bv[u]);
                     else load_col9<true>(blkT + ee * 81, comp, bv[u]);
                 }
             }
@@ -714,12 +717,13 @@ __global__ __launch_bounds__(BS) void k_gather_lower(int n_rows, const int32_t* 
                                                      const int32_t* __restrict__ gl_col, const float* __restrict__ Gl,
                                                      const float* __restrict__ GlT, const double* __restrict__ r,
                                                      double* __restrict__ t, double* __restrict__ tg,
-                                                     const uint32_t* __restrict__ Gh, const float* __restrict__ hs,
+                                                     const uint32_t* __restrict__ Gh, const uint16_t* __restrict__ Gh8,
+                                                     const float* __restrict__ hs,
                                                      const double* __restrict__ Dn) {
     const int lane = threadIdx.x % kWave;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a = gl_ptr[row], n = gl_ptr[row + 1] - a;
-        const double v = UP ? row_factor_t<0, H>(a, n, gl_col, GlT, r, nullptr, 0.0, tg, Gh, hs, Dn)
+        const double v = UP ? row_factor_t<0, H>(a, n, gl_col, GlT, r, nullptr, 0.0, tg, Gh, Gh8, hs, Dn)
                             : row_gather<float, 0>(a, n, gl_col, Gl, r, nullptr, 0.0);
         if (lane < 9) t[(int64_t)row * 9 + lane] = v;
     }
@@ -1041,7 +1045,8 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
                                                double* __restrict__ t, double* __restrict__ tg,
                                                const double* __restrict__ pA,
                                                double* __restrict__ pR, int n_part, int* __restrict__ state,
-                                               const uint32_t* __restrict__ Gh, const float* __restrict__ hs,
+                                               const uint32_t* __restrict__ Gh, const uint16_t* __restrict__ Gh8,
+                                               const float* __restrict__ hs,
                                                const double* __restrict__ Dn) {
     __shared__ double sh[2 * WPB];
     const int done = state[0];
@@ -1062,7 +1067,7 @@ __global__ __launch_bounds__(BS) void k_pcg_Bf(int n_rows, const int32_t* __rest
     double rr = 0.0;
     for (int row = blockIdx.x * WPB + threadIdx.x / kWave; row < n_rows; row += gridDim.x * WPB) {
         const int a0 = gl_ptr[row], n = gl_ptr[row + 1] - a0;
-        const double tv = UP ? row_factor_t<1, H>(a0, n, gl_col, GlT, rin, q, alpha, tg, Gh, hs, Dn)
+        const double tv = UP ? row_factor_t<1, H>(a0, n, gl_col, GlT, rin, q, alpha, tg, Gh, Gh8, hs, Dn)
                              : row_gather<float, 1>(a0, n, gl_col, Gl, rin, q, alpha);
         if (lane < 9) {
             const int64_t o = (int64_t)row * 9 + lane;
@@ -1177,17 +1182,17 @@ void launch_factor_step(ba_ctx* c, int g, int defl, hipStream_t st) {
     if (F.gu_upper != c->upper) throw ba_hip_error(hipErrorInvalidValue, "factor apply (layout of the transposed blocks)", __FILE__, __LINE__);
     if (c->upper && F.half) {
         k_pcg_Bf<true, true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg,
-                                               P.pA, P.pR, g, P.state, F.Gh, F.hs, F.Dn);
+                                               P.pA, P.pR, g, P.state, F.Gh, F.Gh8, F.hs, F.Dn);
         k_pcg_Cf<false, true, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
                                                       P.r[1], P.z, P.pR, g, P.state, defl, P.SW, F.Dn);
     } else if (c->upper) {
         k_pcg_Bf<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
-                                         P.pR, g, P.state, nullptr, nullptr, nullptr);
+                                         P.pR, g, P.state, nullptr, nullptr, nullptr, nullptr);
         k_pcg_Cf<false, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0], P.r[1],
                                                 P.z, P.pR, g, P.state, defl, P.SW, nullptr);
     } else {
         k_pcg_Bf<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.d, P.q, P.x, P.r[0], P.r[1], P.t, F.tg, P.pA,
-                                          P.pR, g, P.state, nullptr, nullptr, nullptr);
+                                          P.pR, g, P.state, nullptr, nullptr, nullptr, nullptr);
         k_pcg_Cf<false, false><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
                                                  P.r[1], P.z, P.pR, g, P.state, defl, P.SW, nullptr);
     }
@@ -1200,16 +1205,16 @@ void launch_factor_init(ba_ctx* c, int g, int defl, hipStream_t st) {
     const int nr = c->n_rows;
     if (F.gu_upper != c->upper) throw ba_hip_error(hipErrorInvalidValue, "factor apply (layout of the transposed blocks)", __FILE__, __LINE__);
     if (c->upper && F.half) {
-        k_gather_lower<true, true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, F.Gh, F.hs, F.Dn);
+        k_gather_lower<true, true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, F.Gh, F.Gh8, F.hs, F.Dn);
         k_pcg_Cf<true, true, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
                                                      P.r[1], P.z, P.pR, g, P.state, defl, P.SW, F.Dn);
     } else if (c->upper) {
-        k_gather_lower<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, nullptr, nullptr,
+        k_gather_lower<true><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, nullptr, nullptr, nullptr,
                                                nullptr);
         k_pcg_Cf<true, true><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0], P.r[1],
                                                P.z, P.pR, g, P.state, defl, P.SW, nullptr);
     } else {
-        k_gather_lower<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, nullptr, nullptr,
+        k_gather_lower<false><<<g, BS, 0, st>>>(nr, F.ptr, F.J, F.Gl, F.Gu, P.r[0], P.t, F.tg, nullptr, nullptr, nullptr,
                                                 nullptr);
         k_pcg_Cf<true, false><<<g, BS, 0, st>>>(nr, F.gu_ptr, F.gu_col, F.Gu, P.t, F.gu_src, F.tg, P.r[0],
                                                 P.r[1], P.z, P.pR, g, P.state, defl, P.SW, nullptr);
@@ -1388,7 +1393,7 @@ void launch_dscale(ba_ctx* c) {
 void launch_pack_half(ba_ctx* c) {
     Fsai& F = c->fs;
     if (F.n_mem > 0)
-        k_pack_half<<<(unsigned)((F.n_mem + 2) / 3), BS, 0, c->stream>>>(F.n_mem, F.J, F.Gu, F.Dn, F.Gh, F.hs);
+        k_pack_half<<<(unsigned)((F.n_mem + 2) / 3), BS, 0, c->stream>>>(F.n_mem, F.J, F.Gu, F.Dn, F.Gh, F.Gh8, F.hs);
 }
 
 }  // namespace ba
