@@ -6,8 +6,9 @@ on the same inputs; on the two large scenes also the PCG product S x in
 both layouts.  LM runs: 20 iterations on the aerial scene against the
 oracle's run (both precisions, with the per-iteration cost error and the
 error of the first step's dx reported), 10 iterations on the strip scene
-(both precisions) and on the partition against the oracle's stored runs.  Reports are written to gpurun_out/ when
-that directory exists."""
+(both precisions) and on the partition against the oracle's stored runs.
+Each report is printed, and also saved as JSON in the repository's output
+folder when that folder exists."""
 import json
 import os
 
