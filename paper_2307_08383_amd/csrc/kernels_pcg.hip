@@ -980,6 +980,19 @@ __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restri
                                               int* __restrict__ state, int defl, const double* __restrict__ SW) {
     __shared__ double sh[NP * WPB];
     __shared__ double sr[RPB][9];
+    const int lr = threadIdx.x / 9, i = threadIdx.x % 9;
+    // row i of the thread's block of M, requested a pass ahead (the first
+    // one before the partial sums): M does not depend on the step
+    double mr[9];
+    auto load_m = [&](int base) {
+        const int row = base + lr;
+        if (threadIdx.x < RPB * 9 && row < n_rows) {
+            const double* Mr = M + (int64_t)row * 81 + i * 9;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) mr[c] = Mr[c];
+        }
+    };
+    load_m(blockIdx.x * RPB);
     const int done = state[0];
     const int k = state[1];
     double s[2];
@@ -992,7 +1005,6 @@ __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restri
         return;
     }
     const double alpha = rz / dq;
-    const int lr = threadIdx.x / 9, i = threadIdx.x % 9;
     double acc[NP];
 #pragma unroll
     for (int j = 0; j < NP; ++j) acc[j] = 0.0;
@@ -1009,10 +1021,9 @@ __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restri
         }
         __syncthreads();
         if (act) {
-            const double* Mr = M + (int64_t)row * 81 + i * 9;
             double zv = 0.0;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) zv += Mr[c] * sr[lr][c];
+            for (int c = 0; c < 9; ++c) zv += mr[c] * sr[lr][c];
             z[o] = zv;
             acc[0] += rv * zv;
             acc[1] += rv * rv;
@@ -1022,6 +1033,7 @@ __global__ __launch_bounds__(BS) void k_pcg_B(int n_rows, const double* __restri
                 for (int v = 0; v < kW; ++v) acc[2 + v] += Sr[v * 9] * zv;
             }
         }
+        load_m(base + gridDim.x * RPB);
         __syncthreads();
     }
     double t[NP];
