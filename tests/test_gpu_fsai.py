@@ -96,6 +96,35 @@ def test_fsai_pcg_parity():
     assert info6["iters"] < bj6["iters"]
 
 
+@pytest.mark.parametrize("kind", ["grid", "dense"])
+def test_fsai_in_both_product_layouts(kind):
+    """Exact FSAI applied with the FULL layout (FP32 blocks of G and G^T by
+    rows) and with the UPPER layout (the FP16 copy of the Jacobi-scaled
+    factor, one 16-byte group plus one half per column): iteration counts
+    equal up to the FP16 rounding of the factor, and both solutions within
+    1e-7 of the oracle's solve."""
+    s = (scenegen.aerial_grid_scene(seed=7, nx=10, ny=8, n_pts=12000, with_stats=False)
+         if kind == "grid" else _dense_scene())
+    P, ctx = _case(s)
+    try:
+        dxc = torch.empty((P.n_rows, 9), dtype=torch.float64, device="cuda")
+        out = {}
+        for prod in (ba.BA_PRODUCT_FULL, ba.BA_PRODUCT_UPPER, ba.BA_PRODUCT_UPPER):
+            info = ba.ba_pcg_solve(ctx, dxc, tol=1e-10, max_iter=5000, precond=ba.BA_PRECOND_FSAI, product=prod)
+            assert info["status"] == 0
+            out.setdefault(prod, []).append((info["iters"], dxc.cpu().numpy().copy()))
+    finally:
+        ba.ba_destroy(ctx)
+    (i_f, x_f), = out[ba.BA_PRODUCT_FULL]
+    (i_u, x_u), (i_u2, x_u2) = out[ba.BA_PRODUCT_UPPER]
+    # the FP16 copy is made once per RCS: a second solve repeats the first
+    assert i_u2 == i_u and np.array_equal(x_u2, x_u)
+    assert abs(i_u - i_f) <= max(2, 0.05 * i_f)
+    x_ref, _ = P.pcg(tol=1e-12, max_iter=5000)
+    for xv in (x_f, x_u):
+        assert np.linalg.norm(xv - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
+
+
 def test_fsai_initial_guess_and_reuse():
     s = scenegen.aerial_grid_scene(seed=6, nx=8, ny=6, n_pts=6000, with_stats=False)
     P, ctx = _case(s)
